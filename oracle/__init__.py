@@ -1,0 +1,235 @@
+"""FP64 CPU oracle for differential walk on spheres -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product library never loads it and
+shares no code with it.
+
+The numerics live in ``dwos_oracle.cpp`` (plain C++17, FP64, brute-force
+closest points, its own Philox4x32-10, Bessel functions from libstdc++'s
+``std::cyl_bessel_i/k``).  This module compiles it with g++ and marshals
+``scenes.Scene`` objects into its C struct with ctypes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dwos_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle shared library with g++ (host only)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread",
+                               "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        dp = C.POINTER(C.c_double)
+        ip = C.POINTER(C.c_int32)
+        lp = C.POINTER(C.c_int64)
+        up = C.POINTER(C.c_uint32)
+        sp = C.POINTER(OracleScene)
+        L.oracle_threads.restype = C.c_int
+        L.oracle_philox.argtypes = [up, up, up]
+        L.oracle_green.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double]
+        L.oracle_green.restype = C.c_double
+        L.oracle_poisson_scale.argtypes = [C.c_int, C.c_double, C.c_double]
+        L.oracle_poisson_scale.restype = C.c_double
+        L.oracle_closest.argtypes = [sp, dp, dp]
+        L.oracle_walk_records.argtypes = [sp, dp, C.c_int64, C.c_int32, C.c_uint64, C.c_int32,
+                                          C.c_int32, dp, dp, lp, ip, dp, lp, C.c_int]
+        L.oracle_solve.argtypes = [sp, dp, C.c_int64, C.c_int32, C.c_uint64, C.c_int32, dp, dp,
+                                   lp, C.c_int]
+        L.oracle_jvp.argtypes = [sp, dp, C.c_int64, C.c_int32, C.c_uint64, C.c_int32, dp, dp, dp,
+                                 lp, C.c_int]
+        L.oracle_grad.argtypes = [sp, dp, C.c_int64, dp, C.c_int32, C.c_uint64, C.c_int32, dp, dp,
+                                  lp, C.c_int]
+        L.oracle_grad_sqloss.argtypes = [sp, dp, C.c_int64, dp, C.c_int32, C.c_int32, C.c_uint64,
+                                         C.c_int32, dp, dp, dp, lp, C.c_int]
+        _lib = L
+    return _lib
+
+
+class OracleScene(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("nv", C.c_int32), ("V", C.POINTER(C.c_double)),
+        ("np", C.c_int32), ("prims", C.POINTER(C.c_int32)), ("label", C.POINTER(C.c_int32)),
+        ("sigma", C.c_double), ("eps", C.c_double), ("delta", C.c_double),
+        ("K", C.c_int32), ("kmax", C.c_int32), ("rr", C.c_int32),
+        ("src_c0", C.c_double), ("n_gauss", C.c_int32), ("gauss", C.POINTER(C.c_double)),
+        ("n_labels", C.c_int32), ("bc_kind", C.POINTER(C.c_int32)),
+        ("bc_quad", C.POINTER(C.c_double)), ("gvert", C.POINTER(C.c_double)),
+        ("N", C.c_int32), ("rowptr", C.POINTER(C.c_int64)), ("pid", C.POINTER(C.c_int32)),
+        ("vel", C.POINTER(C.c_double)), ("bc_pid", C.POINTER(C.c_int32)),
+    ]
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct)) if a is not None else None
+
+
+class Oracle:
+    """Oracle bound to one scene (keeps the marshalled arrays alive)."""
+
+    def __init__(self, scene, V: Optional[np.ndarray] = None, threads: int = 0):
+        self.scene = scene
+        self.threads = int(threads)
+        D = scene.dim
+        self._V = np.ascontiguousarray(scene.V if V is None else V, dtype=np.float64)
+        self._prims = np.ascontiguousarray(scene.prims, dtype=np.int32)
+        self._label = np.ascontiguousarray(scene.label, dtype=np.int32)
+        self._gauss = np.ascontiguousarray(np.asarray(scene.gauss, float).reshape(-1, D + 2))
+        kinds, quads = [], []
+        for b in scene.bc:
+            if b["kind"] == "mapped":
+                kinds.append(1)
+                quads.append(np.zeros(1 + D + D * D))
+            else:
+                kinds.append(0)
+                quads.append(np.concatenate([[b["c"]], np.asarray(b["b"], float).ravel(),
+                                             np.asarray(b["A"], float).ravel()]))
+        self._kind = np.ascontiguousarray(kinds, dtype=np.int32)
+        self._quad = np.ascontiguousarray(np.concatenate(quads), dtype=np.float64)
+        self._gvert = np.ascontiguousarray(scene.gvert, dtype=np.float64)
+        nv = self._V.shape[0]
+        if scene.rowptr is not None:
+            self._rowptr = np.ascontiguousarray(scene.rowptr, dtype=np.int64)
+            self._pid = np.ascontiguousarray(scene.pid, dtype=np.int32)
+            self._vel = np.ascontiguousarray(scene.vel, dtype=np.float64).reshape(-1)
+        else:
+            self._rowptr = np.zeros(nv + 1, np.int64)
+            self._pid = np.zeros(1, np.int32)
+            self._vel = np.zeros(D, np.float64)
+        self._bcpid = (np.ascontiguousarray(scene.bc_pid, dtype=np.int32)
+                       if scene.bc_pid is not None else None)
+        s = OracleScene()
+        s.dim = D
+        s.nv = nv
+        s.V = _ptr(self._V, C.c_double)
+        s.np = self._prims.shape[0]
+        s.prims = _ptr(self._prims, C.c_int32)
+        s.label = _ptr(self._label, C.c_int32)
+        s.sigma, s.eps, s.delta = float(scene.sigma), float(scene.eps), float(scene.delta)
+        s.K, s.kmax, s.rr = int(scene.K), int(scene.kmax), int(scene.rr)
+        s.src_c0 = float(scene.src_c0)
+        s.n_gauss = self._gauss.shape[0]
+        s.gauss = _ptr(self._gauss, C.c_double)
+        s.n_labels = len(kinds)
+        s.bc_kind = _ptr(self._kind, C.c_int32)
+        s.bc_quad = _ptr(self._quad, C.c_double)
+        s.gvert = _ptr(self._gvert, C.c_double)
+        s.N = int(scene.N)
+        s.rowptr = _ptr(self._rowptr, C.c_int64)
+        s.pid = _ptr(self._pid, C.c_int32)
+        s.vel = _ptr(self._vel, C.c_double)
+        s.bc_pid = _ptr(self._bcpid, C.c_int32)
+        self._s = s
+
+    @staticmethod
+    def _X(X):
+        return np.ascontiguousarray(X, dtype=np.float64)
+
+    def closest(self, x):
+        out = np.zeros(8)
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        rc = lib().oracle_closest(C.byref(self._s), _ptr(x, C.c_double), _ptr(out, C.c_double))
+        assert rc == 0
+        return dict(d=out[0], prim=int(out[1]), bary=out[2:5].copy(), xbar=out[5:8].copy())
+
+    def walk_records(self, X, W, seed, mode=0, instance=0, want_udot=True):
+        X = self._X(X)
+        P = X.shape[0]
+        N = self.scene.N
+        u = np.zeros(P * W)
+        udot = np.zeros(P * W * N) if (mode == 1 and want_udot and N > 0) else None
+        steps = np.zeros(P * W, np.int64)
+        prim = np.zeros(P * W, np.int32)
+        uoff = np.zeros(P * W)
+        tr = np.zeros(1, np.int64)
+        rc = lib().oracle_walk_records(C.byref(self._s), _ptr(X, C.c_double), P, W, seed, mode,
+                                       instance, _ptr(u, C.c_double), _ptr(udot, C.c_double),
+                                       _ptr(steps, C.c_int64), _ptr(prim, C.c_int32),
+                                       _ptr(uoff, C.c_double), _ptr(tr, C.c_int64), self.threads)
+        assert rc == 0
+        out = dict(u=u.reshape(P, W), steps=steps.reshape(P, W), prim=prim.reshape(P, W),
+                   uoff=uoff.reshape(P, W), truncated=int(tr[0]))
+        if udot is not None:
+            out["udot"] = udot.reshape(P, W, N)
+        return out
+
+    def solve(self, X, W, seed, instance=0):
+        X = self._X(X)
+        P = X.shape[0]
+        m, v, st = np.zeros(P), np.zeros(P), np.zeros(1, np.int64)
+        rc = lib().oracle_solve(C.byref(self._s), _ptr(X, C.c_double), P, W, seed, instance,
+                                _ptr(m, C.c_double), _ptr(v, C.c_double), _ptr(st, C.c_int64),
+                                self.threads)
+        assert rc == 0
+        return m, v, int(st[0])
+
+    def jvp(self, X, W, seed, instance=0):
+        X = self._X(X)
+        P = X.shape[0]
+        N = self.scene.N
+        m, v, um, st = np.zeros(P * N), np.zeros(P * N), np.zeros(P), np.zeros(1, np.int64)
+        rc = lib().oracle_jvp(C.byref(self._s), _ptr(X, C.c_double), P, W, seed, instance,
+                              _ptr(m, C.c_double), _ptr(v, C.c_double), _ptr(um, C.c_double),
+                              _ptr(st, C.c_int64), self.threads)
+        assert rc == 0
+        return m.reshape(P, N), v.reshape(P, N), um, int(st[0])
+
+    def grad(self, X, w, W, seed, instance=0):
+        X = self._X(X)
+        P = X.shape[0]
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        g, um, st = np.zeros(self.scene.N), np.zeros(P), np.zeros(1, np.int64)
+        rc = lib().oracle_grad(C.byref(self._s), _ptr(X, C.c_double), P, _ptr(w, C.c_double), W,
+                               seed, instance, _ptr(g, C.c_double), _ptr(um, C.c_double),
+                               _ptr(st, C.c_int64), self.threads)
+        assert rc == 0
+        return g, um, int(st[0])
+
+    def grad_sqloss(self, X, uref, W, B, seed, instance=0):
+        X = self._X(X)
+        P = X.shape[0]
+        uref = np.ascontiguousarray(uref, dtype=np.float64)
+        g, um, st, L = np.zeros(self.scene.N), np.zeros(P), np.zeros(1, np.int64), np.zeros(1)
+        rc = lib().oracle_grad_sqloss(C.byref(self._s), _ptr(X, C.c_double), P,
+                                      _ptr(uref, C.c_double), W, B, seed, instance,
+                                      _ptr(L, C.c_double), _ptr(g, C.c_double),
+                                      _ptr(um, C.c_double), _ptr(st, C.c_int64), self.threads)
+        if rc != 0:
+            raise ValueError("oracle_grad_sqloss: invalid arguments")
+        return float(L[0]), g, um, int(st[0])
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    o = np.zeros(4, np.uint32)
+    lib().oracle_philox(_ptr(c, C.c_uint32), _ptr(k, C.c_uint32), _ptr(o, C.c_uint32))
+    return o
+
+
+def green(dim, sigma, r, R):
+    return lib().oracle_green(dim, sigma, r, R)
+
+
+def poisson_scale(dim, sigma, R):
+    return lib().oracle_poisson_scale(dim, sigma, R)

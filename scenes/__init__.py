@@ -1,0 +1,454 @@
+"""Seeded synthetic scenes and query points for differential walk on spheres.
+
+This module builds inputs only: boundary geometry, boundary-data and source
+specifications, the parameter Jacobian dv/dpi of the boundary vertices, and
+query points.  It holds none of the estimator's arithmetic, so both the FP64
+oracle and the GPU library can consume the same inputs.
+
+The paper's own scenes (bunny, pose mesh, toaster, heightfields, images) are
+not available; these generators stand in for them with the shapes and sizes of
+the paper's workloads (Sec. 6-7, Table 1):
+
+* ``c1_polygon``   2D Laplace on a regular n-gon inscribed in a disk, parameter
+                   = radius (Sec. 6.3 ablation-style 2D scene).
+* ``c2_star``      2D screened Poisson on a Fourier star polygon with a Gaussian
+                   source; 64 shape coefficients (Sec. 7 polyline examples).
+* ``c3_icosphere`` 3D shape from diffusion: displaced icosphere inside a box,
+                   radial-basis vertex displacement parameters (Sec. 7.2).
+* ``c4_batch``     many C3-like instances of uneven size.
+
+Every array is float64 / int32 / int64 numpy.  Vertex positions are linear in
+the parameters: ``V(pi) = V_base + sum_j pi_j * J_j`` with the Jacobian stored
+as CSR by vertex (``rowptr``, ``pid``, ``vel``).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+__all__ = [
+    "Scene", "c1_polygon", "c2_star", "c3_icosphere", "c4_batch",
+    "disk_polygon", "icosphere", "box_triangles", "sphere_scene",
+    "shell_scene", "annulus_scene", "points_in_disk", "points_on_box_faces",
+    "points_in_ball", "vertices_at",
+]
+
+
+@dataclass
+class Scene:
+    """A Dirichlet screened-Poisson problem on an explicit boundary.
+
+    Boundary data per label is either a restricted quadratic field
+    ``g(x) = c + b.x + x^T A x`` (``kind='restricted'``) or values mapped from
+    the reference surface, given per vertex and interpolated linearly over a
+    primitive (``kind='mapped'``, values in ``gvert``).
+
+    The source is ``f(x) = c0 + sum_i a_i exp(-|x - m_i|^2 / (2 s_i^2))`` with
+    rows ``(a_i, m_i[dim], s_i)`` in ``gauss``.
+    """
+    dim: int
+    V: np.ndarray                 # (nv, dim) float64 vertex positions
+    prims: np.ndarray             # (np, dim) int32 vertex indices
+    label: np.ndarray             # (np,) int32 boundary-data label
+    bc: list                      # per label: dict(kind=..., c=, b=, A=)
+    gvert: np.ndarray             # (nv,) float64 values for mapped labels
+    sigma: float = 0.0
+    eps: float = 1e-3
+    delta: float = 1e-2
+    K: int = 1
+    kmax: int = 65536
+    rr: int = 1
+    src_c0: float = 0.0
+    gauss: np.ndarray = field(default_factory=lambda: np.zeros((0, 4)))
+    # parameters: dv_i/dpi_j as CSR by vertex
+    N: int = 0
+    rowptr: Optional[np.ndarray] = None   # (nv+1,) int64
+    pid: Optional[np.ndarray] = None      # (nnz,) int32
+    vel: Optional[np.ndarray] = None      # (nnz, dim) float64
+    bc_pid: Optional[np.ndarray] = None   # (nv,) int32, -1 = none
+    V_base: Optional[np.ndarray] = None   # V(pi) = V_base + J pi
+    pi0: Optional[np.ndarray] = None      # parameter values giving V
+    name: str = ""
+
+    @property
+    def nv(self) -> int:
+        return int(self.V.shape[0])
+
+    @property
+    def np_(self) -> int:
+        return int(self.prims.shape[0])
+
+    def with_(self, **kw) -> "Scene":
+        d = dict(self.__dict__)
+        d.update(kw)
+        return Scene(**d)
+
+
+def vertices_at(scene: Scene, pi: np.ndarray) -> np.ndarray:
+    """Vertex positions for parameter vector ``pi`` (vertices are linear in pi)."""
+    pi = np.asarray(pi, dtype=np.float64)
+    nv = scene.nv
+    rows = np.repeat(np.arange(nv), np.diff(scene.rowptr))
+    V = scene.V_base.copy()
+    np.add.at(V, rows, scene.vel * pi[scene.pid][:, None])
+    return V
+
+
+def _restricted(c=0.0, b=None, A=None, dim=2):
+    b = np.zeros(dim) if b is None else np.asarray(b, float)
+    A = np.zeros((dim, dim)) if A is None else np.asarray(A, float)
+    return dict(kind="restricted", c=float(c), b=b, A=A)
+
+
+def _mapped():
+    return dict(kind="mapped")
+
+
+def _dense_csr(J: np.ndarray):
+    """CSR of a dense Jacobian J[nv, N, dim]."""
+    nv, N, dim = J.shape
+    rowptr = (np.arange(nv + 1, dtype=np.int64) * N)
+    pid = np.tile(np.arange(N, dtype=np.int32), nv)
+    vel = J.reshape(nv * N, dim).astype(np.float64)
+    return rowptr, pid, vel
+
+
+# --------------------------------------------------------------------------
+# 2D geometry
+# --------------------------------------------------------------------------
+
+def disk_polygon(n: int, R: float = 1.0):
+    """Regular n-gon with vertices R(cos 2 pi i/n, sin 2 pi i/n), CCW."""
+    th = 2.0 * np.pi * np.arange(n) / n
+    U = np.stack([np.cos(th), np.sin(th)], axis=1)
+    prims = np.stack([np.arange(n), (np.arange(n) + 1) % n], axis=1).astype(np.int32)
+    return R * U, U, prims
+
+
+def c1_polygon(n: int = 128, R: float = 1.0, mapped: bool = False,
+               eps: float = 1e-4, delta: float = 1e-3, sigma: float = 0.0,
+               g: str = "x2-y2", K: int = 1) -> Scene:
+    """Regular n-gon, one parameter pi = R with dv_i/dR = v_i / R.
+
+    ``g='x2-y2'`` gives the harmonic field x^2 - y^2; ``g='one'`` gives g = 1.
+    With ``mapped=True`` the field is sampled at the vertices and interpolated
+    along edges instead of being restricted.
+    """
+    V, U, prims = disk_polygon(n, R)
+    if g == "x2-y2":
+        fld = _restricted(0.0, None, [[1.0, 0.0], [0.0, -1.0]], 2)
+        gv = V[:, 0] ** 2 - V[:, 1] ** 2
+    elif g == "one":
+        fld = _restricted(1.0, None, None, 2)
+        gv = np.ones(n)
+    else:
+        raise ValueError(g)
+    bc = [_mapped() if mapped else fld]
+    rowptr = np.arange(n + 1, dtype=np.int64)
+    pid = np.zeros(n, dtype=np.int32)
+    return Scene(dim=2, V=V, prims=prims, label=np.zeros(n, np.int32), bc=bc,
+                 gvert=gv, sigma=sigma, eps=eps, delta=delta, K=K,
+                 N=1, rowptr=rowptr, pid=pid, vel=U.copy(),
+                 V_base=np.zeros_like(V), pi0=np.array([R]),
+                 name=f"c1_polygon{n}{'_mapped' if mapped else ''}")
+
+
+def points_in_disk(P: int, rmax: float, seed: int, centre=(0.0, 0.0)) -> np.ndarray:
+    """P points area-uniform in the disk r < rmax."""
+    rng = np.random.default_rng(seed)
+    r = rmax * np.sqrt(rng.random(P))
+    th = 2 * np.pi * rng.random(P)
+    return np.stack([centre[0] + r * np.cos(th), centre[1] + r * np.sin(th)], axis=1)
+
+
+def star_coefficients(seed: int, kmax: int = 32, scale: float = 0.02):
+    """a_k, b_k ~ N(0, (scale/k)^2), k = 1..kmax; returned as [a_1..a_K, b_1..b_K]."""
+    rng = np.random.default_rng(seed)
+    k = np.arange(1, kmax + 1)
+    a = rng.normal(0.0, scale / k)
+    b = rng.normal(0.0, scale / k)
+    return np.concatenate([a, b])
+
+
+def c2_star(n: int = 4096, coef: Optional[np.ndarray] = None, coef_seed: int = 0,
+            kmax: int = 32, sigma: float = 10.0, eps: float = 1e-3,
+            delta: float = 1e-2, K: int = 1, source: bool = True) -> Scene:
+    """Star polygon r(th) = 1 + sum_k a_k cos k th + b_k sin k th, n vertices.
+
+    Parameters are the 2*kmax Fourier coefficients; dv_i/da_k = cos(k th_i) u_i,
+    dv_i/db_k = sin(k th_i) u_i with u_i the radial unit vector (dense rows).
+    """
+    if coef is None:
+        coef = star_coefficients(coef_seed, kmax)
+    coef = np.asarray(coef, float)
+    th = 2.0 * np.pi * np.arange(n) / n
+    U = np.stack([np.cos(th), np.sin(th)], axis=1)
+    k = np.arange(1, kmax + 1)
+    C = np.cos(np.outer(th, k))
+    S = np.sin(np.outer(th, k))
+    basis = np.concatenate([C, S], axis=1)            # (n, 2kmax)
+    J = basis[:, :, None] * U[:, None, :]              # (n, N, 2)
+    V = U * (1.0 + basis @ coef)[:, None]
+    prims = np.stack([np.arange(n), (np.arange(n) + 1) % n], axis=1).astype(np.int32)
+    rowptr, pid, vel = _dense_csr(J)
+    gauss = np.array([[100.0, 0.25, 0.1, 0.15]]) if source else np.zeros((0, 4))
+    return Scene(dim=2, V=V, prims=prims, label=np.zeros(n, np.int32),
+                 bc=[_restricted(0.0, None, [[1.0, 0.0], [0.0, -1.0]], 2)],
+                 gvert=V[:, 0] ** 2 - V[:, 1] ** 2, sigma=sigma, eps=eps,
+                 delta=delta, K=K, src_c0=0.0, gauss=gauss,
+                 N=2 * kmax, rowptr=rowptr, pid=pid, vel=vel,
+                 V_base=U.copy(), pi0=coef.copy(), name=f"c2_star{n}")
+
+
+def star_points(P: int, seed: int, rmax: float = 0.8) -> np.ndarray:
+    return points_in_disk(P, rmax, seed)
+
+
+def annulus_scene(a: float, b: float, n: int = 1024, sigma: float = 0.0,
+                  eps: float = 1e-4, delta: float = 1e-3) -> Scene:
+    """Two concentric n-gons: u = 1 on r = a (label 1), 0 on r = b (label 0).
+
+    One parameter: the inner radius a (dv/da = v/a on the inner polygon).
+    Inner polygon is listed clockwise so that, like the outer one, the domain
+    lies on the left of each directed edge.
+    """
+    Vo, Uo, po = disk_polygon(n, b)
+    Vi, Ui, pi_ = disk_polygon(n, a)
+    pi_ = pi_[:, ::-1].copy() + n
+    V = np.concatenate([Vo, Vi])
+    prims = np.concatenate([po, pi_]).astype(np.int32)
+    label = np.concatenate([np.zeros(n, np.int32), np.ones(n, np.int32)])
+    rowptr = np.concatenate([np.zeros(n, np.int64), np.arange(n + 1, dtype=np.int64)])
+    pid = np.zeros(n, np.int32)
+    vel = Ui.copy()
+    Vb = np.concatenate([Vo, np.zeros_like(Vi)])
+    return Scene(dim=2, V=V, prims=prims, label=label,
+                 bc=[_restricted(0.0, dim=2), _restricted(1.0, dim=2)],
+                 gvert=np.zeros(2 * n), sigma=sigma, eps=eps, delta=delta,
+                 N=1, rowptr=rowptr, pid=pid, vel=vel, V_base=Vb,
+                 pi0=np.array([a]), name=f"annulus{n}")
+
+
+# --------------------------------------------------------------------------
+# 3D geometry
+# --------------------------------------------------------------------------
+
+def _icosahedron():
+    t = (1.0 + 5 ** 0.5) / 2.0
+    v = np.array([[-1, t, 0], [1, t, 0], [-1, -t, 0], [1, -t, 0],
+                  [0, -1, t], [0, 1, t], [0, -1, -t], [0, 1, -t],
+                  [t, 0, -1], [t, 0, 1], [-t, 0, -1], [-t, 0, 1]], float)
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    f = np.array([[0, 11, 5], [0, 5, 1], [0, 1, 7], [0, 7, 10], [0, 10, 11],
+                  [1, 5, 9], [5, 11, 4], [11, 10, 2], [10, 7, 6], [7, 1, 8],
+                  [3, 9, 4], [3, 4, 2], [3, 2, 6], [3, 6, 8], [3, 8, 9],
+                  [4, 9, 5], [2, 4, 11], [6, 2, 10], [8, 6, 7], [9, 8, 1]])
+    return v, f
+
+
+def icosphere(nu: int):
+    """Class-I geodesic icosphere of frequency nu: 20 nu^2 triangles,
+    10 nu^2 + 2 unit-length vertices, outward (CCW seen from outside) winding."""
+    v0, f0 = _icosahedron()
+    pts = []
+    tris = []
+    # barycentric lattice on each face
+    idx = {}
+    for (i, j) in [(i, j) for i in range(nu + 1) for j in range(nu + 1 - i)]:
+        idx[(i, j)] = len(idx)
+    lat = np.array(list(idx.keys()), float) / nu            # (m, 2): (i/nu, j/nu)
+    loc_tris = []
+    for i in range(nu):
+        for j in range(nu - i):
+            a, b, c = idx[(i, j)], idx[(i + 1, j)], idx[(i, j + 1)]
+            loc_tris.append((a, b, c))
+            if j + i + 1 < nu:
+                d = idx[(i + 1, j + 1)]
+                loc_tris.append((b, d, c))
+    loc_tris = np.array(loc_tris)
+    m = lat.shape[0]
+    for fi, (A, B, C) in enumerate(f0):
+        P = (v0[A][None, :] * (1 - lat[:, :1] - lat[:, 1:]) + v0[B][None, :] * lat[:, :1]
+             + v0[C][None, :] * lat[:, 1:])
+        pts.append(P)
+        tris.append(loc_tris + fi * m)
+    P = np.concatenate(pts)
+    T = np.concatenate(tris)
+    P /= np.linalg.norm(P, axis=1, keepdims=True)
+    key = np.round(P * 1e9).astype(np.int64)
+    _, first, inv = np.unique(key, axis=0, return_index=True, return_inverse=True)
+    inv = inv.reshape(-1)
+    Vu = P[first]
+    T = inv[T]
+    # orient outward
+    a, b, c = Vu[T[:, 0]], Vu[T[:, 1]], Vu[T[:, 2]]
+    nrm = np.cross(b - a, c - a)
+    flip = np.einsum("ij,ij->i", nrm, a + b + c) < 0
+    T[flip] = T[flip][:, [0, 2, 1]]
+    return Vu, T.astype(np.int32)
+
+
+def box_triangles(h: float = 2.0):
+    """Axis-aligned cube [-h, h]^3 as 12 triangles with outward winding."""
+    V = np.array([[x, y, z] for x in (-h, h) for y in (-h, h) for z in (-h, h)], float)
+    quads = [(0, 1, 3, 2), (4, 6, 7, 5), (0, 4, 5, 1), (2, 3, 7, 6), (0, 2, 6, 4), (1, 5, 7, 3)]
+    T = []
+    for q in quads:
+        T.append((q[0], q[1], q[2]))
+        T.append((q[0], q[2], q[3]))
+    T = np.array(T, np.int32)
+    a, b, c = V[T[:, 0]], V[T[:, 1]], V[T[:, 2]]
+    nrm = np.cross(b - a, c - a)
+    flip = np.einsum("ij,ij->i", nrm, a + b + c) < 0
+    T[flip] = T[flip][:, [0, 2, 1]]
+    return V, T
+
+
+def fibonacci_sphere(n: int):
+    i = np.arange(n) + 0.5
+    z = 1.0 - 2.0 * i / n
+    phi = np.pi * (1.0 + 5 ** 0.5) * i
+    r = np.sqrt(1 - z * z)
+    return np.stack([r * np.cos(phi), r * np.sin(phi), z], axis=1)
+
+
+def radial_basis(Vu: np.ndarray, centres: np.ndarray, h: float, cut: float = 3.0):
+    """Angular Gaussian bumps exp(-theta^2/(2h^2)), truncated at theta > cut*h.
+
+    Returns CSR (rowptr, cols, vals) of phi_j(v_i)."""
+    rows, cols, vals = [], [], []
+    cosc = math.cos(cut * h)
+    for s in range(0, Vu.shape[0], 8192):
+        blk = Vu[s:s + 8192]
+        dots = blk @ centres.T
+        ii, jj = np.nonzero(dots >= cosc)
+        th = np.arccos(np.clip(dots[ii, jj], -1.0, 1.0))
+        rows.append(ii + s)
+        cols.append(jj)
+        vals.append(np.exp(-th ** 2 / (2 * h * h)))
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    vals = np.concatenate(vals)
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    rowptr = np.zeros(Vu.shape[0] + 1, np.int64)
+    np.add.at(rowptr, rows + 1, 1)
+    rowptr = np.cumsum(rowptr)
+    return rowptr, cols.astype(np.int32), vals
+
+
+def c3_icosphere(nu: int = 100, n_basis: int = 1024, h: float = 0.1,
+                 coef: Optional[np.ndarray] = None, coef_seed: int = 0,
+                 coef_std: float = 0.05, R0: float = 1.0, box: float = 2.0,
+                 sigma: float = 4.0, eps: float = 4e-3, delta: float = 4e-2,
+                 K: int = 1) -> Scene:
+    """Displaced icosphere (label 1, g = 1) inside the box [-box, box]^3
+    (label 0, g = 0).  v_i = u_i (R0 + sum_j c_j phi_j(u_i)); parameters c_j."""
+    Vu, T = icosphere(nu)
+    centres = fibonacci_sphere(n_basis)
+    rp, cols, vals = radial_basis(Vu, centres, h)
+    if coef is None:
+        coef = np.random.default_rng(coef_seed).normal(0.0, coef_std, n_basis)
+    coef = np.asarray(coef, float)
+    rows = np.repeat(np.arange(Vu.shape[0]), np.diff(rp))
+    disp = np.zeros(Vu.shape[0])
+    np.add.at(disp, rows, vals * coef[cols])
+    Vobj = Vu * (R0 + disp)[:, None]
+    Vb, Tb = box_triangles(box)
+    nb = Vb.shape[0]
+    V = np.concatenate([Vb, Vobj])
+    # object winding flipped: its stored normal points into the object,
+    # i.e. out of the domain between object and box
+    prims = np.concatenate([Tb, T[:, [0, 2, 1]] + nb]).astype(np.int32)
+    label = np.concatenate([np.zeros(len(Tb), np.int32), np.ones(len(T), np.int32)])
+    rowptr = np.concatenate([np.zeros(nb, np.int64), rp])
+    vel = Vu[rows] * vals[:, None]
+    Vbase = np.concatenate([Vb, Vu * R0])
+    return Scene(dim=3, V=V, prims=prims, label=label,
+                 bc=[_restricted(0.0, dim=3), _restricted(1.0, dim=3)],
+                 gvert=np.zeros(V.shape[0]), sigma=sigma, eps=eps, delta=delta,
+                 K=K, N=n_basis, rowptr=rowptr, pid=cols, vel=vel,
+                 V_base=Vbase, pi0=coef.copy(), name=f"c3_icosphere{nu}")
+
+
+def points_on_box_faces(P: int, seed: int, inset: float = 1.9) -> np.ndarray:
+    """P points uniform on the six faces |coord| = inset of a cube (face uniform)."""
+    rng = np.random.default_rng(seed)
+    face = rng.integers(0, 6, P)
+    uv = rng.uniform(-inset, inset, (P, 2))
+    X = np.zeros((P, 3))
+    ax = face // 2
+    sgn = np.where(face % 2 == 0, -1.0, 1.0)
+    for a in range(3):
+        m = ax == a
+        others = [o for o in range(3) if o != a]
+        X[m, a] = sgn[m] * inset
+        X[m, others[0]] = uv[m, 0]
+        X[m, others[1]] = uv[m, 1]
+    return X
+
+
+def points_in_ball(P: int, rmin: float, rmax: float, seed: int) -> np.ndarray:
+    """P points volume-uniform in the spherical shell rmin < r < rmax."""
+    rng = np.random.default_rng(seed)
+    r = (rmin ** 3 + (rmax ** 3 - rmin ** 3) * rng.random(P)) ** (1.0 / 3.0)
+    d = rng.normal(size=(P, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return d * r[:, None]
+
+
+def sphere_scene(nu: int, R: float = 1.0, g: str = "one", sigma: float = 0.0,
+                 eps: float = 1e-3, delta: float = 1e-2, source_c0: float = 0.0) -> Scene:
+    """Ball of radius R as an icosphere mesh (domain inside), parameter pi = R.
+
+    The stored triangle normal points away from the centre, i.e. out of the
+    domain."""
+    Vu, T = icosphere(nu)
+    fld = _restricted(1.0, dim=3) if g == "one" else _restricted(0.0, dim=3)
+    n = Vu.shape[0]
+    return Scene(dim=3, V=R * Vu, prims=T, label=np.zeros(len(T), np.int32), bc=[fld],
+                 gvert=np.zeros(n), sigma=sigma, eps=eps, delta=delta,
+                 src_c0=source_c0, N=1, rowptr=np.arange(n + 1, dtype=np.int64),
+                 pid=np.zeros(n, np.int32), vel=Vu.copy(), V_base=np.zeros_like(Vu),
+                 pi0=np.array([R]), name=f"sphere{nu}")
+
+
+def shell_scene(nu_in: int, nu_out: int, a: float, b: float, sigma: float,
+                eps: float = 1e-3, delta: float = 1e-2) -> Scene:
+    """Spherical shell a < r < b: g = 1 on the inner icosphere (label 1,
+    parameter pi = a), g = 0 on the outer icosphere (label 0)."""
+    Vo, To = icosphere(nu_out)
+    Vi, Ti = icosphere(nu_in)
+    no = Vo.shape[0]
+    V = np.concatenate([b * Vo, a * Vi])
+    prims = np.concatenate([To, Ti[:, [0, 2, 1]] + no]).astype(np.int32)
+    label = np.concatenate([np.zeros(len(To), np.int32), np.ones(len(Ti), np.int32)])
+    rowptr = np.concatenate([np.zeros(no, np.int64), np.arange(Vi.shape[0] + 1, dtype=np.int64)])
+    return Scene(dim=3, V=V, prims=prims, label=label,
+                 bc=[_restricted(0.0, dim=3), _restricted(1.0, dim=3)],
+                 gvert=np.zeros(V.shape[0]), sigma=sigma, eps=eps, delta=delta,
+                 N=1, rowptr=rowptr, pid=np.zeros(Vi.shape[0], np.int32),
+                 vel=Vi.copy(), V_base=np.concatenate([b * Vo, np.zeros_like(Vi)]),
+                 pi0=np.array([a]), name=f"shell{nu_in}_{nu_out}")
+
+
+def c4_batch(n_inst: int = 256, seed0: int = 100, tri_lo: float = 1e3,
+             tri_hi: float = 1e5, p_lo: float = 512, p_hi: float = 16384,
+             n_basis: int = 256, sigma_hi: float = 20.0):
+    """Instances of the C3 generator with log-uniform triangle and point counts.
+
+    Returns a list of (Scene, X) pairs; instance i draws from seed seed0 + i."""
+    out = []
+    for i in range(n_inst):
+        rng = np.random.default_rng(seed0 + i)
+        T = math.exp(rng.uniform(math.log(tri_lo), math.log(tri_hi)))
+        nu = max(1, int(round(math.sqrt(T / 20.0))))
+        P = int(round(math.exp(rng.uniform(math.log(p_lo), math.log(p_hi)))))
+        sigma = float(rng.uniform(0.0, sigma_hi))
+        sc = c3_icosphere(nu=nu, n_basis=n_basis, coef_seed=seed0 + i, sigma=sigma)
+        X = points_on_box_faces(P, seed0 + i)
+        out.append((sc, X))
+    return out
