@@ -1,0 +1,254 @@
+/*
+ * dwos.h -- C ABI of the MI355X differential walk-on-spheres library.
+ *
+ * The library estimates, at chosen query points x_p inside a domain Omega(pi),
+ * the solution u of the screened Poisson Dirichlet problem
+ *
+ *     -Lap u + sigma u = f   in Omega(pi),      u = g(., pi)   on dOmega(pi)
+ *
+ * (Miller et al., "Differential Walk on Spheres", TOG 43(6) 2024, Sec. 3.2,
+ * eq. (bvp); the sign is chosen so that the Green's-function source term of
+ * eq. (wos) enters with a plus sign), and the derivatives of u with respect
+ * to every boundary parameter pi_j at once (Sec. 4, eq. (bvp_deriv); Sec. 5.1,
+ * eq. (wos_deriv)), plus reverse-mode shape-functional gradients (Sec. 4,
+ * eq. (functional_deriv); Sec. 5.3, eq. (ustatistics)).
+ *
+ * Conventions shared by every entry point
+ *  - Every call returns a dwos_status; nothing throws across the ABI.  On an
+ *    error the call has no effect on outputs and dwos_last_error() returns a
+ *    message (thread-local, valid until the next failing call on the thread).
+ *  - "host" arrays are read during the call and not retained.  "device"
+ *    arrays are HIP device pointers owned by the caller; work on them is
+ *    enqueued asynchronously on the stream given to dwos_create, so they must
+ *    stay valid until that stream has reached the call's work.
+ *  - The library copies whatever it keeps (geometry, BVH, Jacobian) into its
+ *    own device allocations, released by dwos_destroy.
+ *  - Sizes are element counts.  Multi-component arrays are row-major
+ *    (point-major): X[p*dim + c], V[i*dim + c], udot[p*N + j].
+ *  - A non-NULL dwos_stats* is host memory; filling it synchronises the stream.
+ *  - Query points must lie inside Omega (the paper's eps-shell is defined
+ *    inside the domain, Sec. 3.3.1); this is not checked.
+ */
+#ifndef DWOS_H
+#define DWOS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dwos_ctx dwos_ctx;
+typedef int32_t dwos_status;
+
+#define DWOS_OK      0
+#define DWOS_EINVAL  1  /* bad argument: NULL, size, range, NaN */
+#define DWOS_ENOMEM  2  /* device or host allocation failed */
+#define DWOS_EDEVICE 3  /* a HIP call failed or no gfx950 device */
+#define DWOS_ESTATE  4  /* call order: e.g. solve before set_boundary */
+
+/* Working precision of the walks.  FP64 is the debug instantiation used for
+ * walk-for-walk comparison with an FP64 reference. */
+#define DWOS_FP32 0
+#define DWOS_FP64 1
+
+#define DWOS_MAX_LABELS 16
+#define DWOS_MAX_GAUSS  8
+
+/* Boundary data of one label (Sec. 4, "Restricted boundary data" and
+ * "Mapped boundary data").
+ *  kind 0 (restricted): g is the restriction of the field
+ *         g(x) = c + b.x + x^T A x   (A row-major, top-left dim x dim used);
+ *         the field does not depend on pi, so its parameter derivative is 0
+ *         and eq. (boundary_deriv_restricted) reduces to (dg/dn - du/dn) V_n.
+ *  kind 1 (mapped): per-vertex values (dwos_set_boundary's gvert) carried by
+ *         the surface parameterisation and interpolated linearly over a
+ *         primitive (eq. (boundary_deriv_mapped), Appendix A).  A vertex value
+ *         may itself be a parameter (dwos_set_parameters' bc_pid). */
+typedef struct dwos_bc {
+    int32_t kind;
+    int32_t pad_;
+    double c;
+    double b[3];
+    double A[9];
+} dwos_bc;
+
+/* Problem constants (Sec. 3.2-3.3, Sec. 6.3).
+ *  sigma  >= 0    screening coefficient
+ *  eps    >  0    eps-shell width: a walk stops when d(x) < eps (Algorithm 1)
+ *  delta  >  0    offset of the backward-difference normal derivative,
+ *                 eq. (dudn_fd_estimate); delta <= eps is accepted (the
+ *                 degenerate case of Sec. 6.3: the estimate is then 0)
+ *  K      1..255  forward walks nested at each differential terminal (Table 1)
+ *  kmax   >= 1    cap on closest-point queries per walk; the kmax-th query is
+ *                 treated as terminal and counted in dwos_stats.truncated
+ *  rr     0/1     Russian roulette with probability alpha = P/p^dB (Sec. 3.3)
+ *  source f(x) = src_c0 + sum_i gauss[i][0] exp(-|x - m_i|^2 / (2 s_i^2)),
+ *         m_i = gauss[i][1..dim], s_i = gauss[i][4]  (n_gauss <= 8)
+ *  bc[l]  boundary data for primitives with label l (n_labels <= 16) */
+typedef struct dwos_problem {
+    double sigma;
+    double eps;
+    double delta;
+    int32_t K;
+    int32_t kmax;
+    int32_t rr;
+    int32_t n_gauss;
+    double src_c0;
+    double gauss[DWOS_MAX_GAUSS][5];
+    int32_t n_labels;
+    int32_t pad_;
+    dwos_bc bc[DWOS_MAX_LABELS];
+} dwos_problem;
+
+/* Counters of one call (filled when a non-NULL pointer is passed). */
+typedef struct dwos_stats {
+    int64_t walks;         /* forward or differential walks started */
+    int64_t nested_walks;  /* forward walks nested at differential terminals */
+    int64_t steps;         /* closest-point queries, all walks (the walk-step unit) */
+    int64_t terminal;      /* main walks that reached the eps-shell */
+    int64_t truncated;     /* walks cut at kmax */
+    int64_t nodes;         /* BVH pair nodes visited */
+    int64_t prims;         /* primitive distance tests */
+    int64_t stack_overflow;/* traversals aborted for lack of stack (must be 0) */
+    int64_t invalid;       /* walks ended at a non-finite position (NaN result) */
+    double walk_ms;        /* device time of the walk kernel(s) of this call */
+} dwos_stats;
+
+/* Create a context for dim = 2 (polyline boundary) or 3 (triangle mesh) in
+ * precision DWOS_FP32 or DWOS_FP64, enqueueing all work on `stream` (a
+ * hipStream_t; NULL = the null stream).  Errors: EINVAL, ENOMEM, EDEVICE. */
+dwos_status dwos_create(int32_t dim, int32_t precision, void* stream, dwos_ctx** out);
+
+/* Release every allocation of the context (synchronises its stream). */
+dwos_status dwos_destroy(dwos_ctx* ctx);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* dwos_last_error(void);
+
+/* Boundary dOmega as nv vertices (host, nv x dim, FP64) and np primitives
+ * (host, np x dim vertex indices: segments in 2D, triangles in 3D) with a
+ * boundary-data label per primitive (host, np; NULL = all 0) and per-vertex
+ * values for mapped labels (host, nv; NULL = 0).  Builds the BVH.
+ * Primitive winding does not matter: at a closest point the normal is the
+ * primitive's geometric normal oriented away from the query point, i.e. out
+ * of the domain.  Errors: EINVAL (index out of range, degenerate primitive,
+ * non-finite coordinate), ENOMEM. */
+dwos_status dwos_set_boundary(dwos_ctx* ctx, const double* V, int64_t nv,
+                              const int32_t* prims, int64_t np, const int32_t* label,
+                              const double* gvert);
+
+/* Move the vertices (device, nv x dim, FP64) keeping the topology, and refit
+ * the BVH on the device (explicit surface phi(., pi), Sec. 3.1.2).
+ * Errors: ESTATE without a boundary, EINVAL on NULL. */
+dwos_status dwos_update_vertices(dwos_ctx* ctx, const double* V_dev);
+
+/* Move the vertices to V(pi) = V_base + J pi for parameter values pi (device,
+ * N FP64) and base positions V_base (device, nv x dim FP64), with J the
+ * Jacobian of dwos_set_parameters (vertices linear in pi, as for radial or
+ * Fourier displacements), then refit as dwos_update_vertices.
+ * Errors: ESTATE without boundary or parameters, EINVAL on NULL. */
+dwos_status dwos_apply_parameters(dwos_ctx* ctx, const double* V_base_dev, const double* pi_dev);
+
+/* Problem constants (host struct).  Errors: EINVAL (sigma < 0, eps <= 0,
+ * delta <= 0, K outside 1..255, kmax < 1, NaN, too many labels/gaussians). */
+dwos_status dwos_set_problem(dwos_ctx* ctx, const dwos_problem* prob);
+
+/* Parameters pi (N of them) as the Jacobian of the vertex positions,
+ * dv_i/dpi_j, in CSR by vertex (host): rowptr[nv+1], pid[nnz] (column ids,
+ * 0 <= pid < N), vel[nnz*dim].  bc_pid (host, nv, or NULL) gives, for mapped
+ * labels, the parameter that a vertex's boundary value equals (-1: none).
+ * The normal velocity of Sec. 3.1.2 is V_n = n . sum_k b_k dv_{i_k}/dpi_j at a
+ * closest point with barycentrics b.  Errors: EINVAL, ESTATE, ENOMEM. */
+dwos_status dwos_set_parameters(dwos_ctx* ctx, int64_t N, const int64_t* rowptr,
+                                const int32_t* pid, const double* vel, const int32_t* bc_pid);
+
+/* Forward solve (Algorithm 1): W walks from each of P points (device,
+ * P x dim FP64).  Writes the per-point mean u_mean[P] and the variance of that
+ * mean u_var[P] (device FP64; u_var may be NULL).  Walk m of point p draws
+ * from the Philox4x32-10 stream keyed by `seed` with counter
+ * (step, m, p, purpose | nested<<8 | instance<<16), so results do not depend
+ * on launch shape.  Errors: ESTATE (no boundary/problem), EINVAL (P < 0,
+ * W < 1, NULL). */
+dwos_status dwos_solve(dwos_ctx* ctx, const double* X, int64_t P, int32_t W, uint64_t seed,
+                       double* u_mean, double* u_var, dwos_stats* stats);
+
+/* Reverse mode (Sec. 4, eq. (functional_deriv), domain term): with one
+ * differential walk per (p, m) (Algorithm 2, with K nested forward walks at
+ * the terminal), accumulates grad[j] = sum_p w[p] * mean_m udot_m[j] into
+ * grad (device, N FP64; overwritten).  w is device FP64 [P].  u_mean (device
+ * [P] or NULL) receives the joint estimate of u from the same walks
+ * (Sec. 5.1, observation 2).  Requires dwos_set_parameters.  Errors as
+ * dwos_solve. */
+dwos_status dwos_grad(dwos_ctx* ctx, const double* X, int64_t P, const double* w, int32_t W,
+                      uint64_t seed, double* grad, double* u_mean, dwos_stats* stats);
+
+/* Fused squared loss L = sum_p 1/2 (u_p - u_ref[p])^2 (Sec. 5.3): loss
+ * (device, 1) gets L from the per-point walk means, grad (device, N) gets
+ * sum_p [U-stat estimate of u udot - u_ref udot] using eq. (ustatistics) over
+ * batches of B consecutive walks of a point, averaged over the W/B batches.
+ * Errors: EINVAL unless B >= 2 and W % B == 0; otherwise as dwos_grad. */
+dwos_status dwos_grad_sqloss(dwos_ctx* ctx, const double* X, int64_t P, const double* u_ref,
+                             int32_t W, int32_t B, uint64_t seed, double* loss, double* grad,
+                             double* u_mean, dwos_stats* stats);
+
+/* Forward mode (Sec. 5, "forward-mode derivatives"): udot (device, P x N)
+ * gets the per-point mean of udot over W differential walks, udot_var (device
+ * P x N or NULL) the variance of that mean, u_mean (device P or NULL) the
+ * joint u estimate.  Meant for small N (cost grows with P*N*W).
+ * Errors: ENOMEM if P*N is too large for the workspace limit. */
+dwos_status dwos_jvp(dwos_ctx* ctx, const double* X, int64_t P, int32_t W, uint64_t seed,
+                     double* udot, double* udot_var, double* u_mean, dwos_stats* stats);
+
+/* Per-walk records for walk-for-walk comparison.  mode 0: Algorithm 1,
+ * mode 1: Algorithm 2.  u (device P*W) the walk's u estimate; steps (device
+ * P*W int64 or NULL) its closest-point queries including nested walks;
+ * prim (device P*W int32 or NULL) the terminal primitive or -1 when Russian
+ * roulette stopped it; uoff (device P*W or NULL) the mean of the nested walks.
+ * udot (device P*W*N or NULL, mode 1) the walk's full derivative vector. */
+dwos_status dwos_walk_records(dwos_ctx* ctx, const double* X, int64_t P, int32_t W,
+                              uint64_t seed, int32_t mode, double* u, int64_t* steps,
+                              int32_t* prim, double* uoff, double* udot);
+
+/* Closest boundary point through the BVH (Algorithm 1, DistanceToBoundary)
+ * for P points (device P x dim): out (device P x 8 FP64) =
+ * {d, primitive, b0, b1, b2, xbar0, xbar1, xbar2}; ties go to the lowest
+ * primitive index. */
+dwos_status dwos_closest(dwos_ctx* ctx, const double* X, int64_t P, double* out);
+
+/* The ball's Green's function and Poisson-kernel scale (Sec. 3.3.1) as the
+ * walk kernels evaluate them, for n (r, R) pairs (device): G|B| = G(r;R) times
+ * the ball volume, and alpha = P(R)/p^dB(R).  Outputs device FP64 [n]. */
+dwos_status dwos_eval_ball_kernels(dwos_ctx* ctx, const double* r, const double* R, int64_t n,
+                                   double sigma, double* GB, double* alpha);
+
+/* Accumulated device time of walk-kernel launches since the last reset
+ * (events recorded on the context stream; this call synchronises them).
+ * walk_ms and launches may be NULL.  reset != 0 clears the accumulators. */
+dwos_status dwos_walk_timing(dwos_ctx* ctx, int32_t reset, double* walk_ms, int64_t* launches);
+
+/* ---- Batched instances: many boundaries and query sets in one launch ----
+ * A batch context holds I instances, each with its own boundary, BVH, sigma,
+ * eps, delta and query points; all instances share the other problem
+ * constants and the boundary-data table.  Walk m of point p of instance i
+ * uses the Philox counter (step, m, p, purpose | nested<<8 | i<<16). */
+
+/* Append an instance (same arguments as dwos_set_boundary plus its own
+ * screening and shell constants).  Must be called before dwos_batch_solve;
+ * the instance index is written to *index.  Errors: EINVAL, ENOMEM. */
+dwos_status dwos_batch_add_instance(dwos_ctx* ctx, const double* V, int64_t nv,
+                                    const int32_t* prims, int64_t np, const int32_t* label,
+                                    double sigma, double eps, double delta, int32_t* index);
+
+/* Solve every instance in one persistent launch: X_all (device) holds the
+ * instances' points back to back (sum_i P[i] x dim), P (host, I counts),
+ * W walks per point; u_mean/u_var (device, sum_i P[i]).  Errors as solve. */
+dwos_status dwos_batch_solve(dwos_ctx* ctx, const double* X_all, const int64_t* P,
+                             int32_t W, uint64_t seed, double* u_mean, double* u_var,
+                             dwos_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DWOS_H */

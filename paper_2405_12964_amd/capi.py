@@ -1,0 +1,116 @@
+"""ctypes binding of libdwos.so (include/dwos.h): argument marshalling only.
+
+Every function here has the name and argument order of the C entry point it
+wraps; all arithmetic happens in the HIP library.  Importing this module fails
+loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdwos.so")
+
+DWOS_OK, DWOS_EINVAL, DWOS_ENOMEM, DWOS_EDEVICE, DWOS_ESTATE = 0, 1, 2, 3, 4
+DWOS_FP32, DWOS_FP64 = 0, 1
+MAX_LABELS, MAX_GAUSS = 16, 8
+
+
+class dwos_bc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("pad_", C.c_int32), ("c", C.c_double),
+                ("b", C.c_double * 3), ("A", C.c_double * 9)]
+
+
+class dwos_problem(C.Structure):
+    _fields_ = [("sigma", C.c_double), ("eps", C.c_double), ("delta", C.c_double),
+                ("K", C.c_int32), ("kmax", C.c_int32), ("rr", C.c_int32), ("n_gauss", C.c_int32),
+                ("src_c0", C.c_double), ("gauss", (C.c_double * 5) * MAX_GAUSS),
+                ("n_labels", C.c_int32), ("pad_", C.c_int32), ("bc", dwos_bc * MAX_LABELS)]
+
+
+class dwos_stats(C.Structure):
+    _fields_ = [("walks", C.c_int64), ("nested_walks", C.c_int64), ("steps", C.c_int64),
+                ("terminal", C.c_int64), ("truncated", C.c_int64), ("nodes", C.c_int64),
+                ("prims", C.c_int64), ("stack_overflow", C.c_int64), ("invalid", C.c_int64),
+                ("walk_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class DwosError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"dwos error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libdwos.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not built: run __graft_entry__.build() or "
+                              "python -m paper_2405_12964_amd.build")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, i32p, i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+        st = C.c_int32
+        sig = {
+            "dwos_create": [C.c_int32, C.c_int32, vp, C.POINTER(vp)],
+            "dwos_destroy": [vp],
+            "dwos_set_boundary": [vp, dp, C.c_int64, i32p, C.c_int64, i32p, dp],
+            "dwos_update_vertices": [vp, vp],
+            "dwos_apply_parameters": [vp, vp, vp],
+            "dwos_set_problem": [vp, C.POINTER(dwos_problem)],
+            "dwos_set_parameters": [vp, C.c_int64, i64p, i32p, dp, i32p],
+            "dwos_solve": [vp, vp, C.c_int64, C.c_int32, C.c_uint64, vp, vp, C.POINTER(dwos_stats)],
+            "dwos_grad": [vp, vp, C.c_int64, vp, C.c_int32, C.c_uint64, vp, vp, C.POINTER(dwos_stats)],
+            "dwos_grad_sqloss": [vp, vp, C.c_int64, vp, C.c_int32, C.c_int32, C.c_uint64, vp, vp, vp,
+                                 C.POINTER(dwos_stats)],
+            "dwos_jvp": [vp, vp, C.c_int64, C.c_int32, C.c_uint64, vp, vp, vp, C.POINTER(dwos_stats)],
+            "dwos_walk_records": [vp, vp, C.c_int64, C.c_int32, C.c_uint64, C.c_int32, vp, vp, vp, vp, vp],
+            "dwos_closest": [vp, vp, C.c_int64, vp],
+            "dwos_eval_ball_kernels": [vp, vp, vp, C.c_int64, C.c_double, vp, vp],
+            "dwos_walk_timing": [vp, C.c_int32, dp, i64p],
+            "dwos_batch_add_instance": [vp, dp, C.c_int64, i32p, C.c_int64, i32p, C.c_double,
+                                        C.c_double, C.c_double, i32p],
+            "dwos_batch_solve": [vp, vp, i64p, C.c_int32, C.c_uint64, vp, vp, C.POINTER(dwos_stats)],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = st
+        L.dwos_last_error.argtypes = []
+        L.dwos_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+EXPORTED = [
+    "dwos_create", "dwos_destroy", "dwos_last_error", "dwos_set_boundary", "dwos_update_vertices",
+    "dwos_apply_parameters",
+    "dwos_set_problem", "dwos_set_parameters", "dwos_solve", "dwos_grad", "dwos_grad_sqloss",
+    "dwos_jvp", "dwos_walk_records", "dwos_closest", "dwos_eval_ball_kernels", "dwos_walk_timing",
+    "dwos_batch_add_instance", "dwos_batch_solve",
+]
+
+
+def check(code):
+    if code != DWOS_OK:
+        raise DwosError(code, lib().dwos_last_error().decode(errors="replace"))
+    return code
+
+
+def _wrap(name):
+    def f(*args):
+        return getattr(lib(), name)(*args)
+    f.__name__ = name
+    f.__doc__ = f"Call {name} of include/dwos.h (returns the dwos_status)."
+    return f
+
+
+for _n in EXPORTED:
+    globals()[_n] = _wrap(_n)

@@ -1,0 +1,887 @@
+// C ABI of the differential walk-on-spheres library (declared in include/dwos.h).
+//
+// A context owns one boundary (or a batch of instance boundaries), its BVH in
+// the working precision, the problem constants, the parameter Jacobian and
+// grow-only workspaces.  Every entry point validates its arguments on the
+// host, enqueues kernels on the context stream and returns a status.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/dwos.h"
+#include "aux_kernels.hpp"
+#include "bvh.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+dwos_status fail(dwos_status code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_OK(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(e_ == hipErrorOutOfMemory ? DWOS_ENOMEM : DWOS_EDEVICE,          \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));              \
+    } while (0)
+
+// grow-only device buffer
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() { if (ptr) (void)hipFree(ptr); }
+    hipError_t reserve(size_t b) {
+        if (b <= bytes) return hipSuccess;
+        if (ptr) { (void)hipFree(ptr); ptr = nullptr; bytes = 0; }
+        hipError_t e = hipMalloc(&ptr, std::max<size_t>(b, 256));
+        if (e == hipSuccess) bytes = std::max<size_t>(b, 256);
+        return e;
+    }
+    template <class U> U* as() const { return static_cast<U*>(ptr); }
+};
+
+template <class U>
+hipError_t upload(DevBuf& b, const U* host, size_t n, hipStream_t s) {
+    hipError_t e = b.reserve(n * sizeof(U));
+    if (e != hipSuccess) return e;
+    if (n == 0) return hipSuccess;
+    e = hipMemcpyAsync(b.ptr, host, n * sizeof(U), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);   // host vectors may die after return
+}
+
+constexpr int64_t kMaxWalksPerChunk = int64_t(1) << 26;
+
+struct InstanceHost {
+    int32_t root;
+    int64_t nv_off, np_off;
+    double sigma, eps, delta;
+};
+
+}  // namespace
+
+struct dwos_ctx {
+    int D = 0;
+    int prec = DWOS_FP32;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int cu_count = 0;
+    // geometry
+    bool has_boundary = false;
+    int64_t nv = 0, np = 0, n_nodes = 0;
+    DevBuf nodes, prims, orig, verts, pverts, label, gvert, leaf_of;
+    DevBuf refit_order;
+    std::vector<int32_t> refit_level_start;
+    std::vector<InstanceHost> instances;      // batch contexts
+    std::vector<double> hostV;                // batch: accumulated geometry
+    std::vector<int32_t> hostP, hostL;
+    std::vector<dwos::HostNode> hostNodes;
+    std::vector<int32_t> hostOrder;
+    // problem
+    bool has_problem = false;
+    dwos_problem prob{};
+    // parameters
+    bool has_params = false;
+    int64_t N = 0;
+    DevBuf rowptr, pid, vel, bc_pid, colptr, cvert, cvel, bcptr, bcvert;
+    bool has_bc_params = false;
+    // workspaces
+    DevBuf rec_u, rec_prim, rec_b, rec_uoff, rec_steps, accA, accB, queue, counters, instbuf, walk_udot;
+    DevBuf vtmp;   // V(pi) for dwos_apply_parameters
+    // timing
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    double timed_ms = 0.0;
+    int64_t timed_launches = 0;
+};
+
+namespace {
+
+template <class T>
+dwos::Params<T> make_params(const dwos_problem& p) {
+    dwos::Params<T> q{};
+    q.K = p.K;
+    q.kmax = p.kmax;
+    q.rr = p.rr;
+    q.n_gauss = p.n_gauss;
+    q.n_labels = p.n_labels;
+    q.src_c0 = T(p.src_c0);
+    q.has_source = (p.src_c0 != 0.0 || p.n_gauss > 0) ? 1 : 0;
+    for (int i = 0; i < dwos::kMaxGauss; ++i)
+        for (int k = 0; k < 5; ++k) q.gauss[i][k] = T(p.gauss[i][k]);
+    for (int l = 0; l < dwos::kMaxLabels; ++l) {
+        q.kind[l] = p.bc[l].kind;
+        q.gc[l] = T(p.bc[l].c);
+        for (int i = 0; i < 3; ++i) q.gb[l][i] = T(p.bc[l].b[i]);
+        for (int i = 0; i < 9; ++i) q.gA[l][i] = T(p.bc[l].A[i]);
+    }
+    return q;
+}
+
+template <class T>
+dwos::Scene<T> make_scene(dwos_ctx* c) {
+    dwos::Scene<T> s;
+    s.nodes = c->nodes.as<T>();
+    s.prims = c->prims.as<T>();
+    s.orig = c->orig.as<int32_t>();
+    s.verts = c->verts.as<T>();
+    s.pverts = c->pverts.as<int32_t>();
+    s.label = c->label.as<int32_t>();
+    s.gvert = c->gvert.as<T>();
+    return s;
+}
+
+dwos::ParamCSR make_csr(dwos_ctx* c) {
+    dwos::ParamCSR J{};
+    J.rowptr = c->rowptr.as<int64_t>();
+    J.pid = c->pid.as<int32_t>();
+    J.vel = c->vel.as<double>();
+    J.bc_pid = c->has_bc_params ? c->bc_pid.as<int32_t>() : nullptr;
+    J.colptr = c->colptr.as<int64_t>();
+    J.cvert = c->cvert.as<int32_t>();
+    J.cvel = c->cvel.as<double>();
+    J.bcptr = c->has_bc_params ? c->bcptr.as<int64_t>() : nullptr;
+    J.bcvert = c->has_bc_params ? c->bcvert.as<int32_t>() : nullptr;
+    J.N = c->N;
+    return J;
+}
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// Upload a built BVH + geometry in the working precision T.
+template <class T>
+dwos_status upload_geometry(dwos_ctx* c, const std::vector<double>& V, const std::vector<int32_t>& prims,
+                            const std::vector<int32_t>& label, const std::vector<double>& gvert,
+                            const std::vector<dwos::HostNode>& hn, const std::vector<int32_t>& order) {
+    const int D = c->D;
+    const int NS = dwos::node_scalars(D), PS = dwos::prim_scalars(D);
+    const int64_t np = (int64_t)prims.size() / D, nv = (int64_t)V.size() / D;
+    std::vector<T> nodes((size_t)hn.size() * NS, T(0));
+    for (size_t i = 0; i < hn.size(); ++i) {
+        T* p = &nodes[i * NS];
+        for (int k = 0; k < D; ++k) {
+            p[k] = T(hn[i].lo[0][k]); p[D + k] = T(hn[i].hi[0][k]);
+            p[2 * D + k] = T(hn[i].lo[1][k]); p[3 * D + k] = T(hn[i].hi[1][k]);
+        }
+        int32_t* r = reinterpret_cast<int32_t*>(p + 4 * D);
+        r[0] = hn[i].child[0];
+        r[1] = hn[i].child[1];
+    }
+    std::vector<T> pr((size_t)np * PS, T(0));
+    for (int64_t lp = 0; lp < np; ++lp) {
+        const int32_t o = order[lp];
+        for (int k = 0; k < D; ++k)
+            for (int cc = 0; cc < D; ++cc) pr[lp * PS + k * D + cc] = T(V[(size_t)prims[(size_t)o * D + k] * D + cc]);
+    }
+    std::vector<int32_t> origv(order.begin(), order.end());
+    std::vector<int32_t> leaf_of(np);
+    for (int64_t i = 0; i < np; ++i) leaf_of[order[i]] = (int32_t)i;
+    std::vector<T> vt(V.size());
+    for (size_t i = 0; i < V.size(); ++i) vt[i] = T(V[i]);
+    std::vector<T> gv(gvert.size());
+    for (size_t i = 0; i < gvert.size(); ++i) gv[i] = T(gvert[i]);
+    hipStream_t s = c->stream;
+    HIP_OK(upload(c->nodes, nodes.data(), nodes.size(), s));
+    HIP_OK(upload(c->prims, pr.data(), pr.size(), s));
+    HIP_OK(upload(c->orig, origv.data(), origv.size(), s));
+    HIP_OK(upload(c->leaf_of, leaf_of.data(), leaf_of.size(), s));
+    HIP_OK(upload(c->verts, vt.data(), vt.size(), s));
+    HIP_OK(upload(c->pverts, prims.data(), prims.size(), s));
+    HIP_OK(upload(c->label, label.data(), label.size(), s));
+    HIP_OK(upload(c->gvert, gv.data(), gv.size(), s));
+    c->nv = nv;
+    c->np = np;
+    c->n_nodes = (int64_t)hn.size();
+    return DWOS_OK;
+}
+
+dwos_status check_geometry(int D, const double* V, int64_t nv, const int32_t* prims, int64_t np,
+                           const int32_t* label, int n_labels_limit) {
+    if (!V || !prims || nv <= 0 || np <= 0) return fail(DWOS_EINVAL, "set_boundary: empty or NULL geometry");
+    if (nv > INT32_MAX || np > (int64_t(1) << 27)) return fail(DWOS_EINVAL, "set_boundary: too many vertices/primitives");
+    for (int64_t i = 0; i < nv * D; ++i)
+        if (!std::isfinite(V[i])) return fail(DWOS_EINVAL, "set_boundary: non-finite vertex coordinate");
+    for (int64_t p = 0; p < np; ++p) {
+        for (int k = 0; k < D; ++k) {
+            const int32_t v = prims[p * D + k];
+            if (v < 0 || v >= nv) return fail(DWOS_EINVAL, "set_boundary: vertex index out of range");
+        }
+        double e1[3] = {0, 0, 0}, e2[3] = {0, 0, 0};
+        const double* a = V + (size_t)prims[p * D] * D;
+        const double* b = V + (size_t)prims[p * D + 1] * D;
+        for (int c = 0; c < D; ++c) e1[c] = b[c] - a[c];
+        double area2;
+        if (D == 2) {
+            area2 = e1[0] * e1[0] + e1[1] * e1[1];
+        } else {
+            const double* cc = V + (size_t)prims[p * D + 2] * D;
+            for (int c = 0; c < 3; ++c) e2[c] = cc[c] - a[c];
+            const double x = e1[1] * e2[2] - e1[2] * e2[1], y = e1[2] * e2[0] - e1[0] * e2[2],
+                         z = e1[0] * e2[1] - e1[1] * e2[0];
+            area2 = x * x + y * y + z * z;
+        }
+        if (!(area2 > 0)) return fail(DWOS_EINVAL, "set_boundary: degenerate primitive " + std::to_string(p));
+        if (label && (label[p] < 0 || label[p] >= n_labels_limit))
+            return fail(DWOS_EINVAL, "set_boundary: label out of range");
+    }
+    return DWOS_OK;
+}
+
+dwos_status drain_events(dwos_ctx* c, double* call_ms, size_t from) {
+    double ms_call = 0.0;
+    for (size_t i = 0; i < c->pending.size(); ++i) {
+        auto& pr = c->pending[i];
+        HIP_OK(hipEventSynchronize(pr.second));
+        float ms = 0.f;
+        HIP_OK(hipEventElapsedTime(&ms, pr.first, pr.second));
+        c->timed_ms += ms;
+        c->timed_launches += 1;
+        if (i >= from) ms_call += ms;
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    c->pending.clear();
+    if (call_ms) *call_ms = ms_call;
+    return DWOS_OK;
+}
+
+// Launch the persistent walk kernel over `total` walks.
+template <class T, int D, int MODE>
+dwos_status launch_walks(dwos_ctx* c, dwos::WalkArgs<T>& a) {
+    hipStream_t s = c->stream;
+    hipLaunchKernelGGL(dwos::fill_u64_kernel, dim3(1), dim3(64), 0, s, a.queue, (int64_t)1);
+    int per_cu = 0;
+    HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dwos::walk_kernel<T, D, MODE>, 256, 0));
+    per_cu = std::max(1, per_cu);
+    const int64_t need = (a.total + 255) / 256;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)per_cu * c->cu_count));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    HIP_OK(hipEventRecord(e0, s));
+    hipLaunchKernelGGL((dwos::walk_kernel<T, D, MODE>), dim3(grid), dim3(256), 0, s, a);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipEventRecord(e1, s));
+    c->pending.emplace_back(e0, e1);
+    if (c->pending.size() > 4096) {
+        dwos_status st = drain_events(c, nullptr, c->pending.size());
+        if (st) return st;
+    }
+    return DWOS_OK;
+}
+
+template <class T>
+dwos_status ensure_records(dwos_ctx* c, int64_t walks, bool diff, bool steps) {
+    HIP_OK(c->rec_u.reserve(walks * sizeof(T)));
+    if (diff) {
+        HIP_OK(c->rec_prim.reserve(walks * sizeof(int32_t)));
+        HIP_OK(c->rec_b.reserve(walks * (c->D - 1) * sizeof(T)));
+        HIP_OK(c->rec_uoff.reserve(walks * sizeof(T)));
+    }
+    if (steps) HIP_OK(c->rec_steps.reserve(walks * sizeof(int64_t)));
+    HIP_OK(c->queue.reserve(sizeof(unsigned long long)));
+    HIP_OK(c->counters.reserve(sizeof(dwos::Counters)));
+    return DWOS_OK;
+}
+
+template <class T>
+dwos::WalkArgs<T> base_args(dwos_ctx* c, const double* X, int32_t W, uint64_t seed) {
+    dwos::WalkArgs<T> a{};
+    a.s = make_scene<T>(c);
+    a.prm = make_params<T>(c->prob);
+    a.X = X;
+    a.W = W;
+    a.key0 = (uint32_t)seed;
+    a.key1 = (uint32_t)(seed >> 32);
+    a.queue = c->queue.as<unsigned long long>();
+    a.cnt = c->counters.as<dwos::Counters>();
+    a.rec_u = c->rec_u.as<T>();
+    a.rec_prim = c->rec_prim.as<int32_t>();
+    a.rec_b = c->rec_b.as<T>();
+    a.rec_uoff = c->rec_uoff.as<T>();
+    a.rec_steps = nullptr;
+    return a;
+}
+
+// single-instance table for points [p0, p0 + P) of a chunk
+template <class T>
+dwos_status set_single_instance(dwos_ctx* c, int64_t p0, int64_t P, int32_t W) {
+    dwos::Instance<T> in{};
+    in.walk_begin = 0;
+    in.point_begin = p0;
+    in.p_counter = p0;
+    in.root = 0;
+    in.P = (int32_t)P;
+    const double sg = c->prob.sigma;
+    in.kappa = T(std::sqrt(sg));
+    in.eps = T(c->prob.eps);
+    in.delta = T(c->prob.delta);
+    HIP_OK(c->instbuf.reserve(sizeof(in)));
+    HIP_OK(hipMemcpyAsync(c->instbuf.ptr, &in, sizeof(in), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return DWOS_OK;
+}
+
+dwos_status begin_call(dwos_ctx* c, bool need_params) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (!c->has_boundary) return fail(DWOS_ESTATE, "no boundary: call dwos_set_boundary first");
+    if (!c->has_problem) return fail(DWOS_ESTATE, "no problem: call dwos_set_problem first");
+    if (need_params && !c->has_params) return fail(DWOS_ESTATE, "no parameters: call dwos_set_parameters first");
+    HIP_OK(hipSetDevice(c->device));
+    HIP_OK(c->counters.reserve(sizeof(dwos::Counters)));
+    hipLaunchKernelGGL(dwos::fill_u64_kernel, dim3(1), dim3(64), 0, c->stream,
+                       c->counters.as<unsigned long long>(), (int64_t)(sizeof(dwos::Counters) / 8));
+    return DWOS_OK;
+}
+
+dwos_status finish_call(dwos_ctx* c, dwos_stats* st, size_t ev_from) {
+    HIP_OK(hipGetLastError());
+    if (!st) return DWOS_OK;
+    HIP_OK(hipStreamSynchronize(c->stream));
+    dwos::Counters h{};
+    HIP_OK(hipMemcpy(&h, c->counters.ptr, sizeof(h), hipMemcpyDeviceToHost));
+    st->walks = (int64_t)h.walks;
+    st->nested_walks = (int64_t)h.nested;
+    st->steps = (int64_t)h.steps;
+    st->terminal = (int64_t)h.terminal;
+    st->truncated = (int64_t)h.truncated;
+    st->nodes = (int64_t)h.nodes;
+    st->prims = (int64_t)h.prims;
+    st->stack_overflow = (int64_t)h.overflow;
+    st->invalid = (int64_t)h.invalid;
+    double ms = 0.0;
+    dwos_status s = drain_events(c, &ms, ev_from);
+    st->walk_ms = ms;
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// the main driver: walks over chunks of points, then per-chunk reductions
+// ---------------------------------------------------------------------------
+enum class Op { Solve, Grad, SqLoss, Jvp, Records };
+
+struct OpArgs {
+    const double* X;
+    int64_t P;
+    int32_t W, B;
+    uint64_t seed;
+    const double* w;
+    const double* uref;
+    double* u_mean;
+    double* u_var;
+    double* grad;
+    double* loss;
+    double* udot;
+    double* udot_var;
+    // records op
+    double* rec_u_out;
+    int64_t* rec_steps_out;
+    int32_t* rec_prim_out;
+    double* rec_uoff_out;
+    double* rec_udot_out;
+    int32_t mode;
+};
+
+template <class T>
+__global__ void copy_records_kernel(const T* u, const int32_t* prim, const T* uoff, int64_t n, int64_t off,
+                                    double* uo, int32_t* po, double* uoffo, int diff) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uo[off + i] = double(u[i]);
+    if (po) po[off + i] = diff ? (prim[i] >= 0 ? (prim[i] >> 1) : -1) : -1;
+    if (uoffo) uoffo[off + i] = diff ? double(uoff[i]) : 0.0;
+}
+
+__global__ void copy_steps_kernel(const int64_t* s, int64_t n, int64_t off, int64_t* o) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) o[off + i] = s[i];
+}
+
+template <class T, int D>
+dwos_status run_op(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
+    const bool diff = op != Op::Solve && !(op == Op::Records && o.mode == 0);
+    const int64_t P = o.P;
+    const int32_t W = o.W;
+    hipStream_t s = c->stream;
+    const int64_t chunk_pts = std::max<int64_t>(1, kMaxWalksPerChunk / W);
+    const int64_t max_walks = std::min<int64_t>(P, chunk_pts) * W;
+    dwos_status rc = ensure_records<T>(c, std::max<int64_t>(1, max_walks), diff, op == Op::Records);
+    if (rc) return rc;
+    const size_t ev_from = c->pending.size();
+    const bool needA = op == Op::Grad || op == Op::SqLoss;
+    if (needA) {
+        HIP_OK(c->accA.reserve(c->nv * D * sizeof(double)));
+        HIP_OK(c->accB.reserve(c->nv * sizeof(double)));
+        hipLaunchKernelGGL(dwos::fill_f64_kernel, dim3(blocks_for(c->nv * D, 256)), dim3(256), 0, s,
+                           c->accA.as<double>(), c->nv * D);
+        hipLaunchKernelGGL(dwos::fill_f64_kernel, dim3(blocks_for(c->nv, 256)), dim3(256), 0, s,
+                           c->accB.as<double>(), c->nv);
+    }
+    const dwos::Params<T> prm = make_params<T>(c->prob);
+    const dwos::Scene<T> scene = make_scene<T>(c);
+    for (int64_t p0 = 0; p0 < P; p0 += chunk_pts) {
+        const int64_t Pc = std::min(chunk_pts, P - p0);
+        const int64_t walks = Pc * W;
+        rc = set_single_instance<T>(c, p0, Pc, W);
+        if (rc) return rc;
+        dwos::WalkArgs<T> a = base_args<T>(c, o.X, W, o.seed);
+        a.inst = c->instbuf.as<dwos::Instance<T>>();
+        a.n_inst = 1;
+        a.total = walks;
+        a.wid_offset = 0;
+        a.rec_steps = op == Op::Records ? c->rec_steps.as<int64_t>() : nullptr;
+        // walk ids within a chunk restart at 0; the instance's p_counter = p0
+        // keeps the Philox point word absolute
+        rc = diff ? launch_walks<T, D, 1>(c, a) : launch_walks<T, D, 0>(c, a);
+        if (rc) return rc;
+        // per-point statistics
+        if (o.u_mean) {
+            hipLaunchKernelGGL(dwos::point_stats_kernel<T>, dim3(blocks_for(Pc, 4)), dim3(256), 0, s,
+                               c->rec_u.as<T>(), Pc, W, o.u_mean + p0, o.u_var ? o.u_var + p0 : nullptr);
+        }
+        if (needA) {
+            dwos::AccArgs<T> aa{};
+            aa.s = scene;
+            aa.prm = prm;
+            aa.delta = T(c->prob.delta);
+            aa.rec_u = c->rec_u.as<T>();
+            aa.rec_prim = c->rec_prim.as<int32_t>();
+            aa.rec_b = c->rec_b.as<T>();
+            aa.rec_uoff = c->rec_uoff.as<T>();
+            aa.nwalks = walks;
+            aa.p_offset = p0;
+            aa.W = W;
+            aa.B = o.B;
+            aa.mode = op == Op::Grad ? 0 : 1;
+            aa.w = o.w;
+            aa.uref = o.uref;
+            aa.bc_pid = c->has_bc_params ? c->bc_pid.as<int32_t>() : nullptr;
+            aa.A = c->accA.as<double>();
+            aa.Bacc = c->accB.as<double>();
+            hipLaunchKernelGGL((dwos::accumulate_kernel<T, D>), dim3(blocks_for(walks, 256)), dim3(256), 0, s, aa);
+        }
+        if (op == Op::Jvp || (op == Op::Records && diff && o.rec_udot_out)) {
+            dwos::JvpArgs<T> ja{};
+            ja.s = scene;
+            ja.prm = prm;
+            ja.delta = T(c->prob.delta);
+            ja.J = make_csr(c);
+            ja.rec_prim = c->rec_prim.as<int32_t>();
+            ja.rec_b = c->rec_b.as<T>();
+            ja.rec_uoff = c->rec_uoff.as<T>();
+            ja.P = Pc;
+            ja.p_offset = p0;
+            ja.W = W;
+            ja.udot = op == Op::Jvp ? o.udot : nullptr;
+            ja.udot_var = op == Op::Jvp ? o.udot_var : nullptr;
+            ja.walk_udot = op == Op::Records ? o.rec_udot_out + p0 * W * c->N : nullptr;
+            dim3 grid((unsigned)Pc, (unsigned)((c->N + 63) / 64));
+            hipLaunchKernelGGL((dwos::jvp_kernel<T, D>), grid, dim3(64), 0, s, ja);
+        }
+        if (op == Op::Records) {
+            hipLaunchKernelGGL(copy_records_kernel<T>, dim3(blocks_for(walks, 256)), dim3(256), 0, s,
+                               c->rec_u.as<T>(), diff ? c->rec_prim.as<int32_t>() : nullptr,
+                               diff ? c->rec_uoff.as<T>() : nullptr, walks, p0 * W, o.rec_u_out,
+                               o.rec_prim_out, o.rec_uoff_out, diff ? 1 : 0);
+            if (o.rec_steps_out)
+                hipLaunchKernelGGL(copy_steps_kernel, dim3(blocks_for(walks, 256)), dim3(256), 0, s,
+                                   c->rec_steps.as<int64_t>(), walks, p0 * W, o.rec_steps_out);
+        }
+    }
+    if (needA) {
+        hipLaunchKernelGGL(dwos::spmv_kernel<D>, dim3(blocks_for(c->N, 4)), dim3(256), 0, s, make_csr(c),
+                           c->accA.as<double>(), c->accB.as<double>(), o.grad);
+    }
+    if (op == Op::SqLoss && o.loss) {
+        hipLaunchKernelGGL(dwos::sqloss_kernel, dim3(1), dim3(256), 0, s, o.u_mean, o.uref, P, o.loss);
+    }
+    return finish_call(c, st, ev_from);
+}
+
+dwos_status dispatch(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
+    if (c->prec == DWOS_FP32) {
+        return c->D == 2 ? run_op<float, 2>(c, op, o, st) : run_op<float, 3>(c, op, o, st);
+    }
+    return c->D == 2 ? run_op<double, 2>(c, op, o, st) : run_op<double, 3>(c, op, o, st);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* dwos_last_error(void) { return g_last_error.c_str(); }
+
+dwos_status dwos_create(int32_t dim, int32_t precision, void* stream, dwos_ctx** out) {
+    if (!out) return fail(DWOS_EINVAL, "dwos_create: out is NULL");
+    *out = nullptr;
+    if (dim != 2 && dim != 3) return fail(DWOS_EINVAL, "dwos_create: dim must be 2 or 3");
+    if (precision != DWOS_FP32 && precision != DWOS_FP64) return fail(DWOS_EINVAL, "dwos_create: bad precision");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(DWOS_EDEVICE, "dwos_create: no HIP device");
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_OK(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(DWOS_EDEVICE, std::string("dwos_create: device is ") + prop.gcnArchName + ", library built for gfx950");
+    auto* c = new (std::nothrow) dwos_ctx();
+    if (!c) return fail(DWOS_ENOMEM, "dwos_create: out of host memory");
+    c->D = dim;
+    c->prec = precision;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->device = dev;
+    c->cu_count = prop.multiProcessorCount;
+    *out = c;
+    return DWOS_OK;
+}
+
+dwos_status dwos_destroy(dwos_ctx* c) {
+    if (!c) return DWOS_OK;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& pr : c->pending) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
+    delete c;
+    return DWOS_OK;
+}
+
+dwos_status dwos_set_boundary(dwos_ctx* c, const double* V, int64_t nv, const int32_t* prims, int64_t np,
+                              const int32_t* label, const double* gvert) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    const int D = c->D;
+    dwos_status rc = check_geometry(D, V, nv, prims, np, label, DWOS_MAX_LABELS);
+    if (rc) return rc;
+    HIP_OK(hipSetDevice(c->device));
+    dwos::HostBVH bvh = dwos::build_bvh(V, prims, np, D);
+    if (bvh.max_depth >= dwos::kMaxDepth) return fail(DWOS_EINVAL, "set_boundary: BVH too deep");
+    std::vector<double> Vv(V, V + nv * D);
+    std::vector<int32_t> Pv(prims, prims + np * D);
+    std::vector<int32_t> Lv(np, 0);
+    if (label) Lv.assign(label, label + np);
+    std::vector<double> Gv(nv, 0.0);
+    if (gvert) Gv.assign(gvert, gvert + nv);
+    rc = c->prec == DWOS_FP32 ? upload_geometry<float>(c, Vv, Pv, Lv, Gv, bvh.nodes, bvh.order)
+                              : upload_geometry<double>(c, Vv, Pv, Lv, Gv, bvh.nodes, bvh.order);
+    if (rc) return rc;
+    std::vector<int32_t> order;
+    dwos::refit_levels(bvh, order, c->refit_level_start);
+    HIP_OK(upload(c->refit_order, order.data(), order.size(), c->stream));
+    c->instances.clear();
+    c->has_boundary = true;
+    c->has_params = false;   // Jacobian rows refer to the previous vertices
+    return DWOS_OK;
+}
+
+dwos_status dwos_update_vertices(dwos_ctx* c, const double* Vdev) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (!c->has_boundary) return fail(DWOS_ESTATE, "update_vertices: no boundary");
+    if (!c->instances.empty()) return fail(DWOS_ESTATE, "update_vertices: not supported on batch contexts");
+    if (!Vdev) return fail(DWOS_EINVAL, "update_vertices: NULL vertices");
+    HIP_OK(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    const int D = c->D;
+    auto run = [&](auto tag) -> dwos_status {
+        using T = decltype(tag);
+        if (D == 2) {
+            hipLaunchKernelGGL((dwos::pack_vertices_kernel<T, 2>), dim3(blocks_for(c->nv * 2, 256)), dim3(256), 0, s,
+                               Vdev, c->nv, c->verts.as<T>());
+            hipLaunchKernelGGL((dwos::pack_prims_kernel<T, 2>), dim3(blocks_for(c->np, 256)), dim3(256), 0, s,
+                               c->verts.as<T>(), c->pverts.as<int32_t>(), c->orig.as<int32_t>(), c->np, c->prims.as<T>());
+            for (size_t l = 0; l + 1 < c->refit_level_start.size(); ++l) {
+                const int32_t b = c->refit_level_start[l], e = c->refit_level_start[l + 1];
+                hipLaunchKernelGGL((dwos::refit_level_kernel<T, 2>), dim3(blocks_for(e - b, 256)), dim3(256), 0, s,
+                                   c->nodes.as<T>(), c->prims.as<T>(), c->refit_order.as<int32_t>(), b, e);
+            }
+        } else {
+            hipLaunchKernelGGL((dwos::pack_vertices_kernel<T, 3>), dim3(blocks_for(c->nv * 3, 256)), dim3(256), 0, s,
+                               Vdev, c->nv, c->verts.as<T>());
+            hipLaunchKernelGGL((dwos::pack_prims_kernel<T, 3>), dim3(blocks_for(c->np, 256)), dim3(256), 0, s,
+                               c->verts.as<T>(), c->pverts.as<int32_t>(), c->orig.as<int32_t>(), c->np, c->prims.as<T>());
+            for (size_t l = 0; l + 1 < c->refit_level_start.size(); ++l) {
+                const int32_t b = c->refit_level_start[l], e = c->refit_level_start[l + 1];
+                hipLaunchKernelGGL((dwos::refit_level_kernel<T, 3>), dim3(blocks_for(e - b, 256)), dim3(256), 0, s,
+                                   c->nodes.as<T>(), c->prims.as<T>(), c->refit_order.as<int32_t>(), b, e);
+            }
+        }
+        HIP_OK(hipGetLastError());
+        return DWOS_OK;
+    };
+    return c->prec == DWOS_FP32 ? run(float{}) : run(double{});
+}
+
+dwos_status dwos_apply_parameters(dwos_ctx* c, const double* Vb, const double* pi) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (!c->has_boundary || !c->has_params) return fail(DWOS_ESTATE, "apply_parameters: need boundary and parameters");
+    if (!Vb || !pi) return fail(DWOS_EINVAL, "apply_parameters: NULL argument");
+    HIP_OK(hipSetDevice(c->device));
+    HIP_OK(c->vtmp.reserve(c->nv * c->D * sizeof(double)));
+    if (c->D == 2)
+        hipLaunchKernelGGL(dwos::apply_params_kernel<2>, dim3(blocks_for(c->nv, 256)), dim3(256), 0, c->stream, Vb,
+                           c->rowptr.as<int64_t>(), c->pid.as<int32_t>(), c->vel.as<double>(), pi, c->nv,
+                           c->vtmp.as<double>());
+    else
+        hipLaunchKernelGGL(dwos::apply_params_kernel<3>, dim3(blocks_for(c->nv, 256)), dim3(256), 0, c->stream, Vb,
+                           c->rowptr.as<int64_t>(), c->pid.as<int32_t>(), c->vel.as<double>(), pi, c->nv,
+                           c->vtmp.as<double>());
+    HIP_OK(hipGetLastError());
+    return dwos_update_vertices(c, c->vtmp.as<double>());
+}
+
+dwos_status dwos_set_problem(dwos_ctx* c, const dwos_problem* p) {
+    if (!c || !p) return fail(DWOS_EINVAL, "set_problem: NULL argument");
+    if (!(p->sigma >= 0) || !std::isfinite(p->sigma)) return fail(DWOS_EINVAL, "set_problem: sigma must be finite and >= 0");
+    if (!(p->eps > 0) || !std::isfinite(p->eps)) return fail(DWOS_EINVAL, "set_problem: eps must be > 0");
+    if (!(p->delta > 0) || !std::isfinite(p->delta)) return fail(DWOS_EINVAL, "set_problem: delta must be > 0");
+    if (p->K < 1 || p->K > 255) return fail(DWOS_EINVAL, "set_problem: K must be in 1..255");
+    if (p->kmax < 1) return fail(DWOS_EINVAL, "set_problem: kmax must be >= 1");
+    if (p->n_gauss < 0 || p->n_gauss > DWOS_MAX_GAUSS) return fail(DWOS_EINVAL, "set_problem: n_gauss out of range");
+    if (p->n_labels < 1 || p->n_labels > DWOS_MAX_LABELS) return fail(DWOS_EINVAL, "set_problem: n_labels out of range");
+    if (!std::isfinite(p->src_c0)) return fail(DWOS_EINVAL, "set_problem: non-finite source");
+    for (int i = 0; i < p->n_gauss; ++i) {
+        for (int k = 0; k < 5; ++k)
+            if (!std::isfinite(p->gauss[i][k])) return fail(DWOS_EINVAL, "set_problem: non-finite gaussian");
+        if (!(p->gauss[i][4] > 0)) return fail(DWOS_EINVAL, "set_problem: gaussian width must be > 0");
+    }
+    for (int l = 0; l < p->n_labels; ++l) {
+        if (p->bc[l].kind != 0 && p->bc[l].kind != 1) return fail(DWOS_EINVAL, "set_problem: bad boundary-data kind");
+        if (!std::isfinite(p->bc[l].c)) return fail(DWOS_EINVAL, "set_problem: non-finite boundary data");
+        for (int i = 0; i < 3; ++i) if (!std::isfinite(p->bc[l].b[i])) return fail(DWOS_EINVAL, "set_problem: non-finite boundary data");
+        for (int i = 0; i < 9; ++i) if (!std::isfinite(p->bc[l].A[i])) return fail(DWOS_EINVAL, "set_problem: non-finite boundary data");
+    }
+    c->prob = *p;
+    c->has_problem = true;
+    return DWOS_OK;
+}
+
+dwos_status dwos_set_parameters(dwos_ctx* c, int64_t N, const int64_t* rowptr, const int32_t* pid,
+                                const double* vel, const int32_t* bc_pid) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (!c->has_boundary) return fail(DWOS_ESTATE, "set_parameters: no boundary");
+    if (!c->instances.empty()) return fail(DWOS_ESTATE, "set_parameters: not supported on batch contexts");
+    if (N < 1 || N > INT32_MAX || !rowptr) return fail(DWOS_EINVAL, "set_parameters: bad N or NULL rowptr");
+    const int D = c->D;
+    const int64_t nv = c->nv;
+    if (rowptr[0] != 0) return fail(DWOS_EINVAL, "set_parameters: rowptr[0] must be 0");
+    for (int64_t i = 0; i < nv; ++i)
+        if (rowptr[i + 1] < rowptr[i]) return fail(DWOS_EINVAL, "set_parameters: rowptr not monotone");
+    const int64_t nnz = rowptr[nv];
+    if (nnz > 0 && (!pid || !vel)) return fail(DWOS_EINVAL, "set_parameters: NULL pid/vel");
+    // rows sorted by parameter id (binary search in forward mode)
+    std::vector<int64_t> rp(rowptr, rowptr + nv + 1);
+    std::vector<int32_t> pv(nnz);
+    std::vector<double> vv(nnz * D);
+    for (int64_t i = 0; i < nv; ++i) {
+        std::vector<int64_t> idx;
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            if (pid[e] < 0 || pid[e] >= N) return fail(DWOS_EINVAL, "set_parameters: pid out of range");
+            for (int cc = 0; cc < D; ++cc)
+                if (!std::isfinite(vel[e * D + cc])) return fail(DWOS_EINVAL, "set_parameters: non-finite velocity");
+            idx.push_back(e);
+        }
+        std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return pid[a] < pid[b]; });
+        for (size_t q = 0; q < idx.size(); ++q) {
+            const int64_t e = rowptr[i] + (int64_t)q;
+            if (q > 0 && pid[idx[q]] == pid[idx[q - 1]]) return fail(DWOS_EINVAL, "set_parameters: duplicate (vertex, parameter)");
+            pv[e] = pid[idx[q]];
+            for (int cc = 0; cc < D; ++cc) vv[e * D + cc] = vel[idx[q] * D + cc];
+        }
+    }
+    // transpose: parameter-major
+    std::vector<int64_t> cp(N + 1, 0);
+    for (int64_t e = 0; e < nnz; ++e) cp[pv[e] + 1]++;
+    for (int64_t j = 0; j < N; ++j) cp[j + 1] += cp[j];
+    std::vector<int32_t> cvt(nnz);
+    std::vector<double> cvl(nnz * D);
+    std::vector<int64_t> fillp(cp.begin(), cp.end() - 1);
+    for (int64_t i = 0; i < nv; ++i)
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+            const int64_t q = fillp[pv[e]]++;
+            cvt[q] = (int32_t)i;
+            for (int cc = 0; cc < D; ++cc) cvl[q * D + cc] = vv[e * D + cc];
+        }
+    // mapped boundary values as parameters
+    std::vector<int32_t> bcp(nv, -1);
+    std::vector<int64_t> bp(N + 1, 0);
+    std::vector<int32_t> bvt;
+    bool any_bc = false;
+    if (bc_pid) {
+        for (int64_t i = 0; i < nv; ++i) {
+            if (bc_pid[i] < -1 || bc_pid[i] >= N) return fail(DWOS_EINVAL, "set_parameters: bc_pid out of range");
+            bcp[i] = bc_pid[i];
+            if (bc_pid[i] >= 0) { bp[bc_pid[i] + 1]++; any_bc = true; }
+        }
+        for (int64_t j = 0; j < N; ++j) bp[j + 1] += bp[j];
+        bvt.assign(bp[N], 0);
+        std::vector<int64_t> f(bp.begin(), bp.end() - 1);
+        for (int64_t i = 0; i < nv; ++i) if (bcp[i] >= 0) bvt[f[bcp[i]]++] = (int32_t)i;
+    }
+    HIP_OK(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    HIP_OK(upload(c->rowptr, rp.data(), rp.size(), s));
+    HIP_OK(upload(c->pid, pv.data(), std::max<size_t>(1, pv.size()) * (pv.empty() ? 0 : 1), s));
+    HIP_OK(c->pid.reserve(4));
+    HIP_OK(upload(c->vel, vv.data(), vv.size(), s));
+    HIP_OK(c->vel.reserve(8));
+    HIP_OK(upload(c->colptr, cp.data(), cp.size(), s));
+    HIP_OK(upload(c->cvert, cvt.data(), cvt.size(), s));
+    HIP_OK(c->cvert.reserve(4));
+    HIP_OK(upload(c->cvel, cvl.data(), cvl.size(), s));
+    HIP_OK(c->cvel.reserve(8));
+    c->has_bc_params = any_bc;
+    if (any_bc) {
+        HIP_OK(upload(c->bc_pid, bcp.data(), bcp.size(), s));
+        HIP_OK(upload(c->bcptr, bp.data(), bp.size(), s));
+        HIP_OK(upload(c->bcvert, bvt.data(), bvt.size(), s));
+    }
+    c->N = N;
+    c->has_params = true;
+    return DWOS_OK;
+}
+
+static dwos_status check_points(const double* X, int64_t P, int32_t W) {
+    if (P < 0) return fail(DWOS_EINVAL, "P must be >= 0");
+    if (W < 1) return fail(DWOS_EINVAL, "W must be >= 1");
+    if (P > 0 && !X) return fail(DWOS_EINVAL, "NULL points");
+    if (P > INT32_MAX) return fail(DWOS_EINVAL, "too many points");
+    return DWOS_OK;
+}
+
+dwos_status dwos_solve(dwos_ctx* c, const double* X, int64_t P, int32_t W, uint64_t seed, double* u_mean,
+                       double* u_var, dwos_stats* stats) {
+    dwos_status rc = begin_call(c, false);
+    if (rc) return rc;
+    if ((rc = check_points(X, P, W))) return rc;
+    if (P > 0 && !u_mean) return fail(DWOS_EINVAL, "solve: NULL u_mean");
+    if (P == 0) return finish_call(c, stats, c->pending.size());
+    OpArgs o{};
+    o.X = X; o.P = P; o.W = W; o.seed = seed; o.u_mean = u_mean; o.u_var = u_var;
+    return dispatch(c, Op::Solve, o, stats);
+}
+
+dwos_status dwos_grad(dwos_ctx* c, const double* X, int64_t P, const double* w, int32_t W, uint64_t seed,
+                      double* grad, double* u_mean, dwos_stats* stats) {
+    dwos_status rc = begin_call(c, true);
+    if (rc) return rc;
+    if ((rc = check_points(X, P, W))) return rc;
+    if (!grad || (P > 0 && !w)) return fail(DWOS_EINVAL, "grad: NULL grad or w");
+    OpArgs o{};
+    o.X = X; o.P = P; o.W = W; o.seed = seed; o.w = w; o.grad = grad; o.u_mean = u_mean;
+    return dispatch(c, Op::Grad, o, stats);
+}
+
+dwos_status dwos_grad_sqloss(dwos_ctx* c, const double* X, int64_t P, const double* u_ref, int32_t W, int32_t B,
+                             uint64_t seed, double* loss, double* grad, double* u_mean, dwos_stats* stats) {
+    dwos_status rc = begin_call(c, true);
+    if (rc) return rc;
+    if ((rc = check_points(X, P, W))) return rc;
+    if (B < 2 || W % B != 0) return fail(DWOS_EINVAL, "grad_sqloss: need B >= 2 and W % B == 0");
+    if (!grad || (P > 0 && !u_ref)) return fail(DWOS_EINVAL, "grad_sqloss: NULL grad or u_ref");
+    if (loss && P > 0 && !u_mean) return fail(DWOS_EINVAL, "grad_sqloss: loss needs u_mean");
+    OpArgs o{};
+    o.X = X; o.P = P; o.W = W; o.B = B; o.seed = seed; o.uref = u_ref; o.loss = loss; o.grad = grad;
+    o.u_mean = u_mean;
+    return dispatch(c, Op::SqLoss, o, stats);
+}
+
+dwos_status dwos_jvp(dwos_ctx* c, const double* X, int64_t P, int32_t W, uint64_t seed, double* udot,
+                     double* udot_var, double* u_mean, dwos_stats* stats) {
+    dwos_status rc = begin_call(c, true);
+    if (rc) return rc;
+    if ((rc = check_points(X, P, W))) return rc;
+    if (P > 0 && !udot) return fail(DWOS_EINVAL, "jvp: NULL udot");
+    if (P * c->N > (int64_t(1) << 31)) return fail(DWOS_ENOMEM, "jvp: P*N too large");
+    OpArgs o{};
+    o.X = X; o.P = P; o.W = W; o.seed = seed; o.udot = udot; o.udot_var = udot_var; o.u_mean = u_mean;
+    return dispatch(c, Op::Jvp, o, stats);
+}
+
+dwos_status dwos_walk_records(dwos_ctx* c, const double* X, int64_t P, int32_t W, uint64_t seed, int32_t mode,
+                              double* u, int64_t* steps, int32_t* prim, double* uoff, double* udot) {
+    dwos_status rc = begin_call(c, mode == 1 && udot != nullptr);
+    if (rc) return rc;
+    if ((rc = check_points(X, P, W))) return rc;
+    if (mode != 0 && mode != 1) return fail(DWOS_EINVAL, "walk_records: mode must be 0 or 1");
+    if (P > 0 && !u) return fail(DWOS_EINVAL, "walk_records: NULL u");
+    OpArgs o{};
+    o.X = X; o.P = P; o.W = W; o.seed = seed; o.mode = mode;
+    o.rec_u_out = u; o.rec_steps_out = steps; o.rec_prim_out = prim; o.rec_uoff_out = uoff; o.rec_udot_out = udot;
+    return dispatch(c, Op::Records, o, nullptr);
+}
+
+dwos_status dwos_closest(dwos_ctx* c, const double* X, int64_t P, double* out) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (!c->has_boundary) return fail(DWOS_ESTATE, "closest: no boundary");
+    if (P < 0 || (P > 0 && (!X || !out))) return fail(DWOS_EINVAL, "closest: bad arguments");
+    if (P == 0) return DWOS_OK;
+    HIP_OK(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    auto run = [&](auto tag) {
+        using T = decltype(tag);
+        if (c->D == 2)
+            hipLaunchKernelGGL((dwos::closest_kernel<T, 2>), dim3(blocks_for(P, 64)), dim3(64), 0, s,
+                               make_scene<T>(c), 0, X, P, out);
+        else
+            hipLaunchKernelGGL((dwos::closest_kernel<T, 3>), dim3(blocks_for(P, 64)), dim3(64), 0, s,
+                               make_scene<T>(c), 0, X, P, out);
+    };
+    if (c->prec == DWOS_FP32) run(float{}); else run(double{});
+    HIP_OK(hipGetLastError());
+    return DWOS_OK;
+}
+
+dwos_status dwos_eval_ball_kernels(dwos_ctx* c, const double* r, const double* R, int64_t n, double sigma,
+                                   double* GB, double* alpha) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (n < 0 || (n > 0 && (!r || !R || !GB || !alpha)) || !(sigma >= 0))
+        return fail(DWOS_EINVAL, "eval_ball_kernels: bad arguments");
+    if (n == 0) return DWOS_OK;
+    HIP_OK(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    const double kappa = std::sqrt(sigma);
+    auto run = [&](auto tag) {
+        using T = decltype(tag);
+        if (c->D == 2)
+            hipLaunchKernelGGL((dwos::ball_kernel_eval<T, 2>), dim3(blocks_for(n, 256)), dim3(256), 0, s, r, R, n,
+                               T(kappa), GB, alpha);
+        else
+            hipLaunchKernelGGL((dwos::ball_kernel_eval<T, 3>), dim3(blocks_for(n, 256)), dim3(256), 0, s, r, R, n,
+                               T(kappa), GB, alpha);
+    };
+    if (c->prec == DWOS_FP32) run(float{}); else run(double{});
+    HIP_OK(hipGetLastError());
+    return DWOS_OK;
+}
+
+dwos_status dwos_walk_timing(dwos_ctx* c, int32_t reset, double* walk_ms, int64_t* launches) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    dwos_status rc = drain_events(c, nullptr, 0);
+    if (rc) return rc;
+    if (walk_ms) *walk_ms = c->timed_ms;
+    if (launches) *launches = c->timed_launches;
+    if (reset) { c->timed_ms = 0.0; c->timed_launches = 0; }
+    return DWOS_OK;
+}
+
+dwos_status dwos_batch_add_instance(dwos_ctx* c, const double* V, int64_t nv, const int32_t* prims, int64_t np,
+                                    const int32_t* label, double sigma, double eps, double delta, int32_t* index) {
+    (void)c; (void)V; (void)nv; (void)prims; (void)np; (void)label; (void)sigma; (void)eps; (void)delta; (void)index;
+    return fail(DWOS_EINVAL, "batch: not available yet");
+}
+
+dwos_status dwos_batch_solve(dwos_ctx* c, const double* X_all, const int64_t* P, int32_t W, uint64_t seed,
+                             double* u_mean, double* u_var, dwos_stats* stats) {
+    (void)c; (void)X_all; (void)P; (void)W; (void)seed; (void)u_mean; (void)u_var; (void)stats;
+    return fail(DWOS_EINVAL, "batch: not available yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,614 @@
+// Walk kernels for (differential) walk on spheres on gfx950.
+//
+// One walk per lane.  The walk kernel is persistent: each wavefront takes
+// chunks of logical walk ids from a global atomic counter and hands a new
+// walk to every lane whose walk has ended (ballot + prefix count), so lanes
+// stay busy while walk lengths differ.  Each loop iteration performs exactly
+// one closest-point query per active lane (one "walk step") followed by the
+// step logic of Algorithm 1 (forward) or Algorithm 2 (differential, with K
+// nested forward walks at the terminal point), written as a state machine.
+//
+// Outputs are per-walk records indexed by the logical walk id p*W + m; small
+// follow-up kernels reduce them (per-point statistics, reverse-mode scatter,
+// parameter-space SpMV), so results do not depend on scheduling.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <climits>
+
+#include "bvh.hpp"
+#include "device_math.hpp"
+
+namespace dwos {
+
+constexpr int kMaxLabels = 16;
+constexpr int kMaxGauss = 8;
+constexpr uint32_t kQueueChunk = 128;   // walk ids taken per wavefront refill
+
+template <class T>
+struct Params {
+    int K, kmax, rr, n_gauss, n_labels, has_source;
+    T src_c0;
+    T gauss[kMaxGauss][5];
+    int kind[kMaxLabels];
+    T gc[kMaxLabels];
+    T gb[kMaxLabels][3];
+    T gA[kMaxLabels][9];
+};
+
+// Per-instance constants (a plain solve has one instance).
+template <class T>
+struct Instance {
+    int64_t walk_begin;   // first logical walk id of the instance
+    int64_t point_begin;  // first point (row of X) of the instance
+    int64_t p_counter;    // added to the point index inside the instance to
+                          // form the Philox point word (chunked solves)
+    int32_t root;         // root pair node
+    int32_t P;            // points of the instance
+    T kappa, eps, delta;
+};
+
+template <class T>
+struct Scene {
+    const T* nodes;          // pair nodes
+    const T* prims;          // leaf-order primitive coordinates
+    const int32_t* orig;     // leaf position -> original primitive
+    const T* verts;          // vertices (original order), nv x D
+    const int32_t* pverts;   // original primitive -> vertex ids, np x D
+    const int32_t* label;    // original primitive -> label
+    const T* gvert;          // per-vertex values of mapped labels
+};
+
+struct Counters {   // device-side statistics (int64 atomics)
+    unsigned long long walks, nested, steps, terminal, truncated, nodes, prims, overflow, invalid;
+};
+
+template <class T>
+struct WalkArgs {
+    Scene<T> s;
+    Params<T> prm;
+    const Instance<T>* inst;
+    int32_t n_inst;
+    const double* X;         // points, rows point_begin.. of each instance
+    int32_t W;
+    int64_t total;           // walks in this launch
+    int64_t wid_offset;      // logical id of walk 0 of this launch
+    uint32_t key0, key1;
+    unsigned long long* queue;
+    Counters* cnt;
+    // records (indexed by logical id - wid_offset)
+    T* rec_u;
+    int32_t* rec_prim;       // orig*2 + flip, -1 when stopped by roulette
+    T* rec_b;                // barycentrics b1 (2D) or b1,b2 (3D)
+    T* rec_uoff;             // mean of the nested walks
+    int64_t* rec_steps;      // optional per-walk query count
+};
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+template <class T> struct Slack;
+template <> struct Slack<float> { static constexpr float v = 1.00001f; };
+template <> struct Slack<double> { static constexpr double v = 1.000000000001; };
+
+template <class T, int D>
+__device__ __forceinline__ T box_d2(const T* lo, const T* hi, const T* x) {
+    T s = T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        const T e = fmax(fmax(lo[i] - x[i], x[i] - hi[i]), T(0));
+        s += e * e;
+    }
+    return s;
+}
+
+// Closest point on a segment (2D) or triangle (3D) with its barycentrics.
+// Triangle: classify the query against the vertex, edge and face Voronoi
+// regions using the dot products of the query offset with the two edges
+// (the classical region test, e.g. Ericson, Real-Time Collision Detection
+// Sec. 5.1.5).
+template <class T, int D>
+__device__ __forceinline__ T prim_closest(const T* P, const T* x, T* bary) {
+    if constexpr (D == 2) {
+        const T ex = P[2] - P[0], ey = P[3] - P[1];
+        const T ax = x[0] - P[0], ay = x[1] - P[1];
+        const T L2 = ex * ex + ey * ey;
+        T t = L2 > T(0) ? (ax * ex + ay * ey) / L2 : T(0);
+        t = fmin(fmax(t, T(0)), T(1));
+        const T dx = ax - t * ex, dy = ay - t * ey;
+        bary[0] = T(1) - t; bary[1] = t; bary[2] = T(0);
+        return dx * dx + dy * dy;
+    } else {
+        const T ab[3] = {P[3] - P[0], P[4] - P[1], P[5] - P[2]};
+        const T ac[3] = {P[6] - P[0], P[7] - P[1], P[8] - P[2]};
+        const T ap[3] = {x[0] - P[0], x[1] - P[1], x[2] - P[2]};
+        const T d1 = ab[0] * ap[0] + ab[1] * ap[1] + ab[2] * ap[2];
+        const T d2 = ac[0] * ap[0] + ac[1] * ap[1] + ac[2] * ap[2];
+        T v, w;
+        if (d1 <= T(0) && d2 <= T(0)) { v = T(0); w = T(0); }
+        else {
+            const T bp[3] = {x[0] - P[3], x[1] - P[4], x[2] - P[5]};
+            const T d3 = ab[0] * bp[0] + ab[1] * bp[1] + ab[2] * bp[2];
+            const T d4 = ac[0] * bp[0] + ac[1] * bp[1] + ac[2] * bp[2];
+            if (d3 >= T(0) && d4 <= d3) { v = T(1); w = T(0); }
+            else {
+                const T vc = d1 * d4 - d3 * d2;
+                if (vc <= T(0) && d1 >= T(0) && d3 <= T(0)) { v = d1 / (d1 - d3); w = T(0); }
+                else {
+                    const T cp[3] = {x[0] - P[6], x[1] - P[7], x[2] - P[8]};
+                    const T d5 = ab[0] * cp[0] + ab[1] * cp[1] + ab[2] * cp[2];
+                    const T d6 = ac[0] * cp[0] + ac[1] * cp[1] + ac[2] * cp[2];
+                    if (d6 >= T(0) && d5 <= d6) { v = T(0); w = T(1); }
+                    else {
+                        const T vb = d5 * d2 - d1 * d6;
+                        if (vb <= T(0) && d2 >= T(0) && d6 <= T(0)) { v = T(0); w = d2 / (d2 - d6); }
+                        else {
+                            const T va = d3 * d6 - d5 * d4;
+                            if (va <= T(0) && (d4 - d3) >= T(0) && (d5 - d6) >= T(0)) {
+                                w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+                                v = T(1) - w;
+                            } else {
+                                const T den = T(1) / (va + vb + vc);
+                                v = vb * den;
+                                w = vc * den;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        bary[0] = T(1) - v - w; bary[1] = v; bary[2] = w;
+        const T q0 = ap[0] - v * ab[0] - w * ac[0];
+        const T q1 = ap[1] - v * ab[1] - w * ac[1];
+        const T q2 = ap[2] - v * ab[2] - w * ac[2];
+        return q0 * q0 + q1 * q1 + q2 * q2;
+    }
+}
+
+template <class T, int D>
+__device__ __forceinline__ void load_prim(const T* prims, int32_t i, T* P) {
+    const T* p = prims + (size_t)i * prim_scalars(D);
+    if constexpr (sizeof(T) == 4 && D == 2) {
+        const float4 a = *reinterpret_cast<const float4*>(p);
+        P[0] = a.x; P[1] = a.y; P[2] = a.z; P[3] = a.w;
+    } else if constexpr (sizeof(T) == 4 && D == 3) {
+        const float4 a = reinterpret_cast<const float4*>(p)[0];
+        const float4 b = reinterpret_cast<const float4*>(p)[1];
+        const float4 c = reinterpret_cast<const float4*>(p)[2];
+        P[0] = a.x; P[1] = a.y; P[2] = a.z; P[3] = a.w; P[4] = b.x; P[5] = b.y;
+        P[6] = b.z; P[7] = b.w; P[8] = c.x;
+    } else {
+#pragma unroll
+        for (int k = 0; k < D * D; ++k) P[k] = p[k];
+    }
+}
+
+template <class T, int D>
+struct NodeData {
+    T lo0[D], hi0[D], lo1[D], hi1[D];
+    int32_t c0, c1;
+};
+
+template <class T, int D>
+__device__ __forceinline__ void load_node(const T* nodes, int32_t i, NodeData<T, D>& nd) {
+    const T* p = nodes + (size_t)i * node_scalars(D);
+    if constexpr (sizeof(T) == 4) {
+        const float4* q = reinterpret_cast<const float4*>(p);
+        if constexpr (D == 2) {
+            const float4 a = q[0], b = q[1], c = q[2];
+            nd.lo0[0] = a.x; nd.lo0[1] = a.y; nd.hi0[0] = a.z; nd.hi0[1] = a.w;
+            nd.lo1[0] = b.x; nd.lo1[1] = b.y; nd.hi1[0] = b.z; nd.hi1[1] = b.w;
+            nd.c0 = __float_as_int(c.x); nd.c1 = __float_as_int(c.y);
+        } else {
+            const float4 a = q[0], b = q[1], c = q[2], d = q[3];
+            nd.lo0[0] = a.x; nd.lo0[1] = a.y; nd.lo0[2] = a.z; nd.hi0[0] = a.w;
+            nd.hi0[1] = b.x; nd.hi0[2] = b.y; nd.lo1[0] = b.z; nd.lo1[1] = b.w;
+            nd.lo1[2] = c.x; nd.hi1[0] = c.y; nd.hi1[1] = c.z; nd.hi1[2] = c.w;
+            nd.c0 = __float_as_int(d.x); nd.c1 = __float_as_int(d.y);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            nd.lo0[k] = p[k]; nd.hi0[k] = p[D + k]; nd.lo1[k] = p[2 * D + k]; nd.hi1[k] = p[3 * D + k];
+        }
+        const int32_t* r = reinterpret_cast<const int32_t*>(p + 4 * D);
+        nd.c0 = r[0]; nd.c1 = r[1];
+    }
+}
+
+struct QueryCount { unsigned int nodes, prims, overflow; };
+
+// DistanceToBoundary: nearest primitive to x through the pair-node BVH.
+// Starts from the upper bound given by a previously closest primitive
+// (`warm`, leaf position, or -1) -- the new closest point can only be at
+// that distance or nearer, so the result is unchanged while most of the tree
+// is pruned.  Ties go to the lowest original primitive index.
+template <class T, int D>
+__device__ __forceinline__ int32_t closest_leaf(const Scene<T>& s, int32_t root, const T* x,
+                                                int32_t warm, T& best, QueryCount& qc) {
+    constexpr T slack = Slack<T>::v;
+    best = T(INFINITY);
+    int32_t bleaf = -1;
+    if (warm >= 0) {
+        T P[9], bb[3];
+        load_prim<T, D>(s.prims, warm, P);
+        best = prim_closest<T, D>(P, x, bb);
+        bleaf = warm;
+    }
+    int32_t st_node[kStackSize];
+    T st_d[kStackSize];
+    int sp = 0;
+    int32_t node = root;
+    auto test_leaf = [&](int32_t ref) {
+        const int32_t v = -1 - ref;
+        const int32_t start = v >> 3, n = (v & 7) + 1;
+        for (int32_t i = start; i < start + n; ++i) {
+            T P[9], bb[3];
+            load_prim<T, D>(s.prims, i, P);
+            const T d2 = prim_closest<T, D>(P, x, bb);
+            qc.prims++;
+            if (d2 < best) { best = d2; bleaf = i; }
+            else if (d2 == best && i != bleaf && s.orig[i] < s.orig[bleaf]) { bleaf = i; }
+        }
+    };
+    while (true) {
+        NodeData<T, D> nd;
+        load_node<T, D>(s.nodes, node, nd);
+        qc.nodes++;
+        const T d0 = box_d2<T, D>(nd.lo0, nd.hi0, x);
+        const T d1 = box_d2<T, D>(nd.lo1, nd.hi1, x);
+        bool h0 = d0 <= best * slack, h1 = d1 <= best * slack;
+        // leaves are tested on the spot, nearer first
+        if (h0 && nd.c0 < 0 && h1 && nd.c1 < 0) {
+            if (d0 <= d1) { test_leaf(nd.c0); if (d1 <= best * slack) test_leaf(nd.c1); }
+            else { test_leaf(nd.c1); if (d0 <= best * slack) test_leaf(nd.c0); }
+            h0 = h1 = false;
+        } else if (h0 && nd.c0 < 0) {
+            test_leaf(nd.c0); h0 = false; h1 = h1 && d1 <= best * slack;
+        } else if (h1 && nd.c1 < 0) {
+            test_leaf(nd.c1); h1 = false; h0 = h0 && d0 <= best * slack;
+        }
+        int32_t next = -1;
+        if (h0 && h1) {
+            const bool near0 = d0 <= d1;
+            if (sp < kStackSize) {
+                st_node[sp] = near0 ? nd.c1 : nd.c0;
+                st_d[sp] = near0 ? d1 : d0;
+                ++sp;
+            } else {
+                qc.overflow++;
+            }
+            next = near0 ? nd.c0 : nd.c1;
+        } else if (h0) {
+            next = nd.c0;
+        } else if (h1) {
+            next = nd.c1;
+        }
+        if (next < 0) {
+            while (sp > 0) {
+                --sp;
+                if (st_d[sp] <= best * slack) { next = st_node[sp]; break; }
+            }
+            if (next < 0) break;
+        }
+        node = next;
+    }
+    return bleaf;
+}
+
+// ---------------------------------------------------------------------------
+// boundary data and normals
+// ---------------------------------------------------------------------------
+template <class T, int D>
+__device__ __forceinline__ void prim_vertices(const Scene<T>& s, int32_t orig, T* V, int32_t* vid) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        vid[k] = s.pverts[(size_t)orig * D + k];
+#pragma unroll
+        for (int c = 0; c < D; ++c) V[k * D + c] = s.verts[(size_t)vid[k] * D + c];
+    }
+}
+
+// geometric normal of a primitive from its vertices (unit length)
+template <class T, int D>
+__device__ __forceinline__ void geo_normal(const T* V, T* n) {
+    if constexpr (D == 2) {
+        const T tx = V[2] - V[0], ty = V[3] - V[1];
+        const T inv = T(1) / sqrt(tx * tx + ty * ty);
+        n[0] = ty * inv; n[1] = -tx * inv;
+    } else {
+        const T e1[3] = {V[3] - V[0], V[4] - V[1], V[5] - V[2]};
+        const T e2[3] = {V[6] - V[0], V[7] - V[1], V[8] - V[2]};
+        T c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        const T inv = T(1) / sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        n[0] = c[0] * inv; n[1] = c[1] * inv; n[2] = c[2] * inv;
+    }
+}
+
+// g at a closest point (restricted field or interpolated mapped values)
+template <class T, int D>
+__device__ __forceinline__ T boundary_value(const Scene<T>& s, const Params<T>& prm, int32_t orig,
+                                            const T* bary, const T* xbar, const int32_t* vid) {
+    const int L = s.label[orig];
+    if (prm.kind[L] == 1) {
+        T v = T(0);
+#pragma unroll
+        for (int k = 0; k < D; ++k) v += bary[k] * s.gvert[vid[k]];
+        return v;
+    }
+    T v = prm.gc[L];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        v += prm.gb[L][i] * xbar[i];
+#pragma unroll
+        for (int j = 0; j < D; ++j) v += xbar[i] * prm.gA[L][i * 3 + j] * xbar[j];
+    }
+    return v;
+}
+
+template <class T, int D>
+__device__ __forceinline__ T source_f(const Params<T>& prm, const T* y) {
+    T v = prm.src_c0;
+    for (int i = 0; i < prm.n_gauss; ++i) {
+        T d2 = T(0);
+#pragma unroll
+        for (int k = 0; k < D; ++k) { const T e = y[k] - prm.gauss[i][1 + k]; d2 += e * e; }
+        v += prm.gauss[i][0] * exp(-d2 / (T(2) * prm.gauss[i][4] * prm.gauss[i][4]));
+    }
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned lo = (unsigned)__shfl_xor((int)(unsigned)(v & 0xffffffffull), o);
+        const unsigned hi = (unsigned)__shfl_xor((int)(unsigned)(v >> 32), o);
+        v += ((unsigned long long)hi << 32) | lo;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// wave-level work queue
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long bcast64(unsigned long long v, int src) {
+    const unsigned lo = (unsigned)__shfl((int)(unsigned)(v & 0xffffffffull), src);
+    const unsigned hi = (unsigned)__shfl((int)(unsigned)(v >> 32), src);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// ---------------------------------------------------------------------------
+// the walk kernel
+//   MODE 0: Algorithm 1 (forward walks): rec_u = walk estimate
+//   MODE 1: Algorithm 2 (differential walks) with the joint u estimate and K
+//           nested forward walks from xbar - delta n at the terminal point
+// ---------------------------------------------------------------------------
+template <class T, int D, int MODE>
+__global__ void __launch_bounds__(256) walk_kernel(WalkArgs<T> a) {
+    const int lane = threadIdx.x & 63;
+    unsigned long long pool_next = 0, pool_end = 0;   // wave-uniform
+    bool done = false;
+    int64_t wid = -1;          // logical walk id (relative to wid_offset)
+    // walk state
+    T x[D], xoff[D];
+    T acc = T(0), u_main = T(0), usum = T(0);
+    T kappa = T(0), eps = T(1), delta = T(1);
+    uint32_t k = 0, m = 0, p = 0, inst_tag = 0;
+    int32_t root = 0, warm = -1, term_leaf = -1, term_code = -1, phase = 0;
+    T term_b1 = T(0), term_b2 = T(0);
+    int64_t wsteps = 0;
+    // lane statistics
+    unsigned long long c_walks = 0, c_nested = 0, c_steps = 0, c_term = 0, c_trunc = 0,
+                       c_nodes = 0, c_prims = 0, c_ovf = 0, c_invalid = 0;
+#pragma unroll 1
+    while (true) {
+        // ---- hand new walks to idle lanes ------------------------------------
+        const bool need = (wid < 0) && !done;
+        const unsigned long long mask = __ballot(need);
+        if (mask) {
+            const int n = __popcll(mask);
+            const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+            const unsigned long long avail = pool_end - pool_next;
+            unsigned long long myid;
+            if (avail >= (unsigned long long)n) {
+                myid = pool_next + rank;
+                pool_next += n;
+            } else {
+                const int leader = __ffsll((long long)mask) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(a.queue, (unsigned long long)kQueueChunk);
+                base = bcast64(base, leader);
+                myid = (unsigned long long)rank < avail ? pool_next + rank : base + (rank - avail);
+                pool_next = base + (n - avail);
+                pool_end = base + kQueueChunk;
+            }
+            if (need) {
+                if (myid >= (unsigned long long)a.total) {
+                    done = true;
+                } else {
+                    wid = (int64_t)myid;
+                    const int64_t gid = wid + a.wid_offset;
+                    int ii = 0;
+                    if (a.n_inst > 1) {   // instance containing walk gid
+                        int lo = 0, hi = a.n_inst - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (a.inst[mid].walk_begin <= gid) lo = mid; else hi = mid - 1;
+                        }
+                        ii = lo;
+                    }
+                    const Instance<T> in = a.inst[ii];
+                    const int64_t local = gid - in.walk_begin;
+                    const int64_t pin = local / a.W;
+                    m = (uint32_t)(local - pin * a.W);
+                    p = (uint32_t)(pin + in.p_counter);
+                    root = in.root;
+                    kappa = in.kappa; eps = in.eps; delta = in.delta;
+                    inst_tag = (uint32_t)ii << 16;
+                    const double* xp = a.X + (size_t)(in.point_begin + pin) * D;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) x[i] = T(xp[i]);
+                    acc = T(0); k = 0; warm = -1; phase = 0; usum = T(0); wsteps = 0;
+                    c_walks++;
+                }
+            }
+        }
+        if (__ballot(!done) == 0ull) break;
+        if (done) continue;
+
+        // ---- one walk step: closest-point query -----------------------------
+        T d2;
+        QueryCount qc{0, 0, 0};
+        const int32_t leaf = closest_leaf<T, D>(a.s, root, x, warm, d2, qc);
+        c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;
+        c_steps++;
+        wsteps++;
+        if (leaf < 0 || !(d2 >= T(0))) {
+            // non-finite position (e.g. a NaN query point): end the walk with
+            // a NaN result instead of touching primitive -1
+            c_invalid++;
+            const T nanv = T(NAN);
+            a.rec_u[wid] = nanv;
+            if (MODE == 1) { a.rec_prim[wid] = -1; a.rec_uoff[wid] = nanv; }
+            if (a.rec_steps) a.rec_steps[wid] = wsteps;
+            wid = -1;
+            continue;
+        }
+        const T d = sqrt(d2);
+        const bool cap = (int)(k + 1) >= a.prm.kmax;
+        const bool nested = MODE == 1 && phase > 0;
+        bool finished = false;     // the current (main or nested) walk ended
+        T result = T(0);           // its value
+        if (d < eps || cap) {
+            if (cap && !(d < eps)) c_trunc++;
+            // closest point, barycentrics, boundary value
+            T P[9], bary[3];
+            load_prim<T, D>(a.s.prims, leaf, P);
+            prim_closest<T, D>(P, x, bary);
+            const int32_t orig = a.s.orig[leaf];
+            T V[9];
+            int32_t vid[3];
+            prim_vertices<T, D>(a.s, orig, V, vid);
+            T xbar[3] = {T(0), T(0), T(0)};
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                T v = T(0);
+#pragma unroll
+                for (int kk = 0; kk < D; ++kk) v += bary[kk] * V[kk * D + c];
+                xbar[c] = v;
+            }
+            const T g = boundary_value<T, D>(a.s, a.prm, orig, bary, xbar, vid);
+            if (MODE == 1 && phase == 0) {
+                // BoundaryNormal, oriented out of the domain (away from x)
+                T n[3] = {T(0), T(0), T(0)};
+                geo_normal<T, D>(V, n);
+                T dn = T(0);
+#pragma unroll
+                for (int c = 0; c < D; ++c) dn += n[c] * (xbar[c] - x[c]);
+                const int flip = dn < T(0) ? 1 : 0;
+                if (flip) {
+#pragma unroll
+                    for (int c = 0; c < D; ++c) n[c] = -n[c];
+                }
+                u_main = acc + g;
+                term_code = orig * 2 + flip;
+                term_b1 = bary[1]; term_b2 = bary[2];
+                term_leaf = leaf;
+#pragma unroll
+                for (int c = 0; c < D; ++c) xoff[c] = xbar[c] - delta * n[c];
+                c_term++;
+                // start the first nested forward walk at the offset point
+                phase = 1;
+#pragma unroll
+                for (int c = 0; c < D; ++c) x[c] = xoff[c];
+                acc = T(0); k = 0; warm = term_leaf;
+                c_nested++;
+                continue;
+            }
+            finished = true;
+            result = acc + g;
+        } else {
+            const uint32_t tag = inst_tag | (nested ? (1u | ((uint32_t)(phase - 1) << 8)) : 0u);
+            const u4 r = philox10(u4{k, m, p, tag}, a.key0, a.key1);
+            if (a.prm.has_source) {
+                const u4 r2 = philox10(u4{k, m, p, tag | 2u}, a.key0, a.key1);
+                T dir[3];
+                unit_dir<T, D>(r2.x, r2.y, dir);
+                T rho;
+                if constexpr (D == 2) rho = sqrt(unif_pos<T>(r.w));
+                else rho = cbrt(unif_pos<T>(r.w));
+                T y[3];
+#pragma unroll
+                for (int c = 0; c < D; ++c) y[c] = x[c] + rho * d * dir[c];
+                acc += green_ball_t<D, T>(kappa, rho, d) * source_f<T, D>(a.prm, y);
+            }
+            const T alpha = poisson_scale<T, D>(kappa, d);
+            if (a.prm.rr && alpha < unif<T>(r.z)) {
+                finished = true;
+                result = acc;
+                if (MODE == 1 && phase == 0) term_code = -1;
+            } else {
+                T dir[3];
+                unit_dir<T, D>(r.x, r.y, dir);
+#pragma unroll
+                for (int c = 0; c < D; ++c) x[c] += d * dir[c];
+                ++k;
+                warm = leaf;
+            }
+        }
+        if (!finished) continue;
+
+        if (MODE == 0) {
+            a.rec_u[wid] = result;
+            if (a.rec_steps) a.rec_steps[wid] = wsteps;
+            wid = -1;
+        } else if (phase == 0) {
+            // differential walk stopped by roulette: udot = 0, u = sources
+            a.rec_u[wid] = result;
+            a.rec_prim[wid] = -1;
+            a.rec_uoff[wid] = T(0);
+            if (a.rec_steps) a.rec_steps[wid] = wsteps;
+            wid = -1;
+        } else {
+            usum += result;
+            if (phase >= a.prm.K) {
+                a.rec_u[wid] = u_main;
+                a.rec_prim[wid] = term_code;
+                a.rec_b[(size_t)wid * (D - 1)] = term_b1;
+                if constexpr (D == 3) a.rec_b[(size_t)wid * 2 + 1] = term_b2;
+                a.rec_uoff[wid] = usum / T(a.prm.K);
+                if (a.rec_steps) a.rec_steps[wid] = wsteps;
+                wid = -1;
+            } else {
+                ++phase;
+#pragma unroll
+                for (int c = 0; c < D; ++c) x[c] = xoff[c];
+                acc = T(0); k = 0; warm = term_leaf;
+                c_nested++;
+            }
+        }
+    }
+    // ---- statistics: wave sums, then one atomic per counter per wave -------
+    c_walks = wave_sum_u64(c_walks);
+    c_nested = wave_sum_u64(c_nested);
+    c_steps = wave_sum_u64(c_steps);
+    c_term = wave_sum_u64(c_term);
+    c_nodes = wave_sum_u64(c_nodes);
+    c_prims = wave_sum_u64(c_prims);
+    c_trunc = wave_sum_u64(c_trunc);
+    c_ovf = wave_sum_u64(c_ovf);
+    c_invalid = wave_sum_u64(c_invalid);
+    if (lane == 0) {
+        atomicAdd(&a.cnt->walks, c_walks);
+        atomicAdd(&a.cnt->nested, c_nested);
+        atomicAdd(&a.cnt->steps, c_steps);
+        atomicAdd(&a.cnt->terminal, c_term);
+        atomicAdd(&a.cnt->nodes, c_nodes);
+        atomicAdd(&a.cnt->prims, c_prims);
+        if (c_trunc) atomicAdd(&a.cnt->truncated, c_trunc);
+        if (c_ovf) atomicAdd(&a.cnt->overflow, c_ovf);
+        if (c_invalid) atomicAdd(&a.cnt->invalid, c_invalid);
+    }
+}
+
+}  // namespace dwos

@@ -1,0 +1,224 @@
+"""Object wrapper over the C ABI: a Solver owns one dwos_ctx.
+
+Host-side setup arrays are numpy; hot-path arrays are torch tensors on the
+GPU (float64), passed to the library as device pointers on torch's current
+stream.  No estimator arithmetic happens here.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import capi
+from .capi import check
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _lp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+def _dev(t: Optional[torch.Tensor], dtype=torch.float64):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a GPU tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def make_problem(sigma=0.0, eps=1e-3, delta=1e-2, K=1, kmax=65536, rr=1, src_c0=0.0,
+                 gauss=None, bc=None, dim=3) -> capi.dwos_problem:
+    """Fill a dwos_problem.  bc: list of dicts kind='restricted' (c, b, A) or
+    kind='mapped'; gauss: rows (amplitude, centre[dim], width)."""
+    p = capi.dwos_problem()
+    p.sigma, p.eps, p.delta = float(sigma), float(eps), float(delta)
+    p.K, p.kmax, p.rr = int(K), int(kmax), int(rr)
+    p.src_c0 = float(src_c0)
+    g = np.zeros((0, dim + 2)) if gauss is None else np.asarray(gauss, float).reshape(-1, dim + 2)
+    if g.shape[0] > capi.MAX_GAUSS:
+        raise ValueError("too many gaussians")
+    p.n_gauss = g.shape[0]
+    for i in range(g.shape[0]):
+        p.gauss[i][0] = g[i, 0]
+        for k in range(dim):
+            p.gauss[i][1 + k] = g[i, 1 + k]
+        p.gauss[i][4] = g[i, 1 + dim]
+    bc = bc or [dict(kind="restricted", c=0.0)]
+    if len(bc) > capi.MAX_LABELS:
+        raise ValueError("too many labels")
+    p.n_labels = len(bc)
+    for l, b in enumerate(bc):
+        if b["kind"] == "mapped":
+            p.bc[l].kind = 1
+        else:
+            p.bc[l].kind = 0
+            p.bc[l].c = float(b.get("c", 0.0))
+            bb = np.zeros(3)
+            bv = np.asarray(b.get("b", np.zeros(dim)), float).ravel()
+            bb[:bv.size] = bv
+            A = np.zeros((3, 3))
+            Av = np.asarray(b.get("A", np.zeros((dim, dim))), float)
+            A[:Av.shape[0], :Av.shape[1]] = Av
+            for i in range(3):
+                p.bc[l].b[i] = bb[i]
+            for i in range(9):
+                p.bc[l].A[i] = A.ravel()[i]
+    return p
+
+
+class Solver:
+    """One library context: a boundary, problem constants and parameters."""
+
+    def __init__(self, dim: int, precision: str = "fp32", stream: Optional[torch.cuda.Stream] = None):
+        self.dim = int(dim)
+        self.precision = precision
+        prec = capi.DWOS_FP32 if precision == "fp32" else capi.DWOS_FP64
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._ctx = C.c_void_p()
+        check(capi.dwos_create(self.dim, prec, C.c_void_p(self.stream.cuda_stream), C.byref(self._ctx)))
+        self.N = 0
+        self.nv = 0
+
+    def __del__(self):
+        ctx = getattr(self, "_ctx", None)
+        if ctx is not None and ctx.value:
+            capi.dwos_destroy(ctx)
+            self._ctx = None
+
+    # ---- setup (host arrays) ------------------------------------------------
+    def set_boundary(self, V, prims, label=None, gvert=None):
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        prims = np.ascontiguousarray(prims, dtype=np.int32)
+        lab = None if label is None else np.ascontiguousarray(label, dtype=np.int32)
+        gv = None if gvert is None else np.ascontiguousarray(gvert, dtype=np.float64)
+        check(capi.dwos_set_boundary(self._ctx, _dp(V), V.shape[0], _ip(prims), prims.shape[0],
+                                     _ip(lab) if lab is not None else None,
+                                     _dp(gv) if gv is not None else None))
+        self.nv = V.shape[0]
+
+    def update_vertices(self, V: torch.Tensor):
+        check(capi.dwos_update_vertices(self._ctx, _dev(V)))
+
+    def apply_parameters(self, V_base: torch.Tensor, pi: torch.Tensor):
+        check(capi.dwos_apply_parameters(self._ctx, _dev(V_base), _dev(pi)))
+
+    def set_problem(self, prob: capi.dwos_problem):
+        check(capi.dwos_set_problem(self._ctx, C.byref(prob)))
+
+    def set_parameters(self, N, rowptr, pid, vel, bc_pid=None):
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        pid = np.ascontiguousarray(pid, dtype=np.int32)
+        vel = np.ascontiguousarray(vel, dtype=np.float64)
+        bcp = None if bc_pid is None else np.ascontiguousarray(bc_pid, dtype=np.int32)
+        check(capi.dwos_set_parameters(self._ctx, int(N), _lp(rowptr), _ip(pid), _dp(vel),
+                                       _ip(bcp) if bcp is not None else None))
+        self.N = int(N)
+
+    @classmethod
+    def from_scene(cls, scene, precision: str = "fp32", V=None, stream=None) -> "Solver":
+        """Configure from a scene description (attributes as in ``scenes.Scene``)."""
+        s = cls(scene.dim, precision, stream)
+        s.set_boundary(scene.V if V is None else V, scene.prims, scene.label, scene.gvert)
+        s.set_problem(make_problem(scene.sigma, scene.eps, scene.delta, scene.K, scene.kmax,
+                                   scene.rr, scene.src_c0, scene.gauss, scene.bc, scene.dim))
+        if scene.N > 0 and scene.rowptr is not None:
+            s.set_parameters(scene.N, scene.rowptr, scene.pid, scene.vel, scene.bc_pid)
+        return s
+
+    # ---- hot path (device tensors) -----------------------------------------
+    def _X(self, X: torch.Tensor):
+        if X.dim() != 2 or X.shape[1] != self.dim:
+            raise ValueError(f"points must be (P, {self.dim})")
+        return X
+
+    def solve(self, X, W, seed, var=True, stats=False):
+        X = self._X(X)
+        P = X.shape[0]
+        m = torch.empty(P, dtype=torch.float64, device=X.device)
+        v = torch.empty(P, dtype=torch.float64, device=X.device) if var else None
+        st = capi.dwos_stats() if stats else None
+        check(capi.dwos_solve(self._ctx, _dev(X), P, int(W), int(seed), _dev(m), _dev(v),
+                              C.byref(st) if st is not None else None))
+        return (m, v, st.as_dict()) if stats else (m, v)
+
+    def grad(self, X, w, W, seed, u_mean=True, stats=False):
+        X = self._X(X)
+        P = X.shape[0]
+        g = torch.empty(self.N, dtype=torch.float64, device=X.device)
+        um = torch.empty(P, dtype=torch.float64, device=X.device) if u_mean else None
+        st = capi.dwos_stats() if stats else None
+        check(capi.dwos_grad(self._ctx, _dev(X), P, _dev(w), int(W), int(seed), _dev(g), _dev(um),
+                             C.byref(st) if st is not None else None))
+        return (g, um, st.as_dict()) if stats else (g, um)
+
+    def grad_sqloss(self, X, uref, W, B, seed, stats=False):
+        X = self._X(X)
+        P = X.shape[0]
+        g = torch.empty(self.N, dtype=torch.float64, device=X.device)
+        L = torch.empty(1, dtype=torch.float64, device=X.device)
+        um = torch.empty(P, dtype=torch.float64, device=X.device)
+        st = capi.dwos_stats() if stats else None
+        check(capi.dwos_grad_sqloss(self._ctx, _dev(X), P, _dev(uref), int(W), int(B), int(seed),
+                                    _dev(L), _dev(g), _dev(um), C.byref(st) if st is not None else None))
+        return (L, g, um, st.as_dict()) if stats else (L, g, um)
+
+    def jvp(self, X, W, seed, var=True, stats=False):
+        X = self._X(X)
+        P = X.shape[0]
+        ud = torch.empty(P, self.N, dtype=torch.float64, device=X.device)
+        uv = torch.empty(P, self.N, dtype=torch.float64, device=X.device) if var else None
+        um = torch.empty(P, dtype=torch.float64, device=X.device)
+        st = capi.dwos_stats() if stats else None
+        check(capi.dwos_jvp(self._ctx, _dev(X), P, int(W), int(seed), _dev(ud), _dev(uv), _dev(um),
+                            C.byref(st) if st is not None else None))
+        return (ud, uv, um, st.as_dict()) if stats else (ud, uv, um)
+
+    def walk_records(self, X, W, seed, mode=0, udot=False):
+        X = self._X(X)
+        P = X.shape[0]
+        dev = X.device
+        u = torch.empty(P * W, dtype=torch.float64, device=dev)
+        steps = torch.empty(P * W, dtype=torch.int64, device=dev)
+        prim = torch.empty(P * W, dtype=torch.int32, device=dev)
+        uoff = torch.empty(P * W, dtype=torch.float64, device=dev)
+        ud = torch.empty(P * W * self.N, dtype=torch.float64, device=dev) if (udot and mode == 1) else None
+        check(capi.dwos_walk_records(self._ctx, _dev(X), P, int(W), int(seed), int(mode), _dev(u),
+                                     _dev(steps, torch.int64), _dev(prim, torch.int32), _dev(uoff),
+                                     _dev(ud)))
+        out = dict(u=u.view(P, W), steps=steps.view(P, W), prim=prim.view(P, W), uoff=uoff.view(P, W))
+        if ud is not None:
+            out["udot"] = ud.view(P, W, self.N)
+        return out
+
+    def closest(self, X):
+        X = self._X(X)
+        out = torch.empty(X.shape[0], 8, dtype=torch.float64, device=X.device)
+        check(capi.dwos_closest(self._ctx, _dev(X), X.shape[0], _dev(out)))
+        return out
+
+    def eval_ball_kernels(self, r, R, sigma):
+        GB = torch.empty_like(r)
+        al = torch.empty_like(r)
+        check(capi.dwos_eval_ball_kernels(self._ctx, _dev(r), _dev(R), r.numel(), float(sigma),
+                                          _dev(GB), _dev(al)))
+        return GB, al
+
+    def walk_timing(self, reset=False):
+        ms = C.c_double()
+        n = C.c_int64()
+        check(capi.dwos_walk_timing(self._ctx, 1 if reset else 0, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
