@@ -1,0 +1,179 @@
+#!/usr/bin/env python
+"""Benchmark: one shape-optimisation step of differential walk on spheres.
+
+Workload (N = 1): the 2D screened-Poisson star polygon -- 4096 boundary
+segments, r(th) = 1 + sum_{k<=32} a_k cos k th + b_k sin k th with
+a_k, b_k ~ N(0, (0.02/k)^2), sigma = 10, Gaussian source, restricted data
+g = x^2 - y^2, eps = 1e-3, delta = 1e-2 -- with 4096 query points x 4096
+walks, FP32 walks, gradients with respect to the 64 Fourier coefficients
+through DWoSFunction.  One step = move the boundary to the current
+coefficients (device V(pi) + BVH refit), forward walks (u), squared loss
+against a reference solution, backward (differential walks with nested
+forward walks, reverse-mode scatter, SpMV) and an Adam update of the
+coefficients.
+
+value = walk steps (closest-point queries of every forward, differential and
+nested walk) per second over the timed steps.  The roofline object reports
+the differential walk kernel against the FP32 vector-ALU peak; see the
+design notes for the per-unit operation counts.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "walk-steps/s and shape-gradient evals/s at fixed RMSE; surrogate vs plain WoS"
+
+# Algorithmic FP32 operations per counted unit (2D), from the arithmetic of
+# the kernels: a pair-node visit evaluates two point-box squared distances
+# (2 dims x [2 sub, 2 max, 1 fma] = 12 each); a segment test is ~22
+# (edge/offset differences, projection, clamp, residual, squared norm); a
+# walk step adds ~40 (roulette scale 1/I0 series, direction, position
+# update); a source sample adds ~200 (FP64 Green's function series and the
+# Gaussian source) -- counted for non-terminal steps only.
+OPS_NODE_2D = 24
+OPS_PRIM_2D = 22
+OPS_STEP_2D = 40
+OPS_SOURCE_2D = 200
+PEAK_FP32_VALU = 157.3e12     # MI355X FP32 vector, FLOP/s
+PEAK_HBM = 8.0e12             # bytes/s
+
+
+def kernel_ops(tot, has_source=True):
+    nonterm = max(0, tot["steps"] - tot["walks"] - tot["nested_walks"])
+    return (tot["nodes"] * OPS_NODE_2D + tot["prims"] * OPS_PRIM_2D + tot["steps"] * OPS_STEP_2D
+            + (nonterm * OPS_SOURCE_2D if has_source else 0))
+
+
+def cpu_baseline(sc, X, uref_np, seed, threads, npts=256, W=64):
+    """The FP64 oracle on a bounded sample of the same workload (forward and
+    differential walks of npts points x W walks each)."""
+    import numpy as np
+    import oracle
+    o = oracle.Oracle(sc, threads=threads)
+    Xs = X[:npts]
+    t0 = time.perf_counter()
+    _, _, s1 = o.solve(Xs, W, seed)
+    w = np.ones(len(Xs))
+    _, _, s2 = o.grad(Xs, w, W, seed + 1)
+    dt = time.perf_counter() - t0
+    return {"value": (s1 + s2) / dt, "unit": "walk-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{npts} points x {W} forward walks + {npts} x {W} differential walks "
+                      f"(K=1 nested) of the same scene, brute-force FP64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--points", type=int, default=4096)
+    ap.add_argument("--walks", type=int, default=4096)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="run a plain device copy of this size first (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; the walks shard across GPUs "
+                                   "by (point, walk) ranges but no multi-GPU path is built",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import scenes
+    import paper_2405_12964_amd as dw
+
+    dev = torch.device("cuda:0")
+    P, W = args.points, args.walks
+    sc = scenes.c2_star(n=4096, coef_seed=0)
+    X = scenes.star_points(P, 1)
+    Xt = torch.tensor(X, dtype=torch.float64, device=dev)
+
+    if args.calib_copy_mb:
+        a = torch.empty(args.calib_copy_mb * (1 << 20) // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        b = a.clone()
+        torch.cuda.synchronize()
+        del a, b
+
+    # reference solution at the target coefficients (setup, untimed)
+    coef_t = scenes.star_coefficients(3)
+    ref = dw.Solver.from_scene(sc, "fp32", V=scenes.vertices_at(sc, coef_t))
+    uref, _ = ref.solve(Xt, W, 99)
+    torch.cuda.synchronize()
+    del ref
+
+    model = dw.ShapeModel(sc, "fp32")
+    pi = torch.tensor(sc.pi0, dtype=torch.float64, device=dev, requires_grad=True)
+    opt = torch.optim.Adam([pi], lr=1e-3)
+
+    def step(i):
+        opt.zero_grad(set_to_none=True)
+        u = dw.DWoSFunction.apply(pi, Xt, model, W, 1000 + 2 * i, W, 1001 + 2 * i)
+        loss = 0.5 * ((u - uref) ** 2).sum()
+        loss.backward()
+        opt.step()
+        return loss
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    for kind in (0, 1):
+        model.solver.walk_timing(kind, reset=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        loss = step(args.warmup + i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+
+    ms0, n0, tot0 = model.solver.walk_timing(0)
+    ms1, n1, tot1 = model.solver.walk_timing(1)
+    steps_total = tot0["steps"] + tot1["steps"]
+    value = steps_total / elapsed
+    # dominant kernel: the differential walk kernel (or whichever took longer)
+    kind, ms, n, tot = (1, ms1, n1, tot1) if ms1 >= ms0 else (0, ms0, n0, tot0)
+    avg_s = ms / max(1, n) / 1e3
+    ops = kernel_ops(tot) / max(1, n)
+    achieved = ops / avg_s
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None,
+            "kernel": f"walk_kernel<float,2,{kind}>", "avg_launch_ms": ms / max(1, n),
+            "launches": n, "ops_per_launch": ops,
+            "steps_per_launch": tot["steps"] / max(1, n),
+            "nodes_per_step": tot["nodes"] / max(1, tot["steps"]),
+            "prims_per_step": tot["prims"] / max(1, tot["steps"])}
+    assert tot0["stack_overflow"] == 0 and tot1["stack_overflow"] == 0
+    assert tot0["invalid"] == 0 and tot1["invalid"] == 0
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "walk-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2D screened Poisson star polygon, 4096 segments, sigma=10, "
+                               f"Gaussian source, {P} points x {W} walks, grads wrt 64 coeffs "
+                               "via autograd (forward walks + differential walks, K=1)",
+                   "points": P, "walks_per_point": W, "segments": 4096, "params": 64},
+        "grad_evals_per_s": args.steps / elapsed,
+        "walk_steps": {"forward": tot0["steps"], "differential": tot1["steps"],
+                       "forward_ms": ms0, "differential_ms": ms1},
+        "loss": float(loss.item()),
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        threads = min(16, len(os.sched_getaffinity(0)))
+        out["cpu_baseline"] = cpu_baseline(sc, X, uref.cpu().numpy(), 7, threads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -222,10 +222,15 @@ dwos_status dwos_closest(dwos_ctx* ctx, const double* X, int64_t P, double* out)
 dwos_status dwos_eval_ball_kernels(dwos_ctx* ctx, const double* r, const double* R, int64_t n,
                                    double sigma, double* GB, double* alpha);
 
-/* Accumulated device time of walk-kernel launches since the last reset
- * (events recorded on the context stream; this call synchronises them).
- * walk_ms and launches may be NULL.  reset != 0 clears the accumulators. */
-dwos_status dwos_walk_timing(dwos_ctx* ctx, int32_t reset, double* walk_ms, int64_t* launches);
+/* Accumulated device time and counters of the walk-kernel launches of one
+ * kind (kind 0: forward walks, Algorithm 1; kind 1: differential walks with
+ * their nested forward walks, Algorithm 2) since the last reset.  Time comes
+ * from events recorded on the context stream around each launch; this call
+ * synchronises them.  walk_ms, launches and totals may be NULL; totals gets
+ * the summed counters (walk_ms field = the same total time).
+ * reset != 0 clears the accumulators of that kind after reading. */
+dwos_status dwos_walk_timing(dwos_ctx* ctx, int32_t kind, int32_t reset, double* walk_ms,
+                             int64_t* launches, dwos_stats* totals);
 
 /* ---- Batched instances: many boundaries and query sets in one launch ----
  * A batch context holds I instances, each with its own boundary, BVH, sigma,

@@ -31,7 +31,9 @@
 //              sinh(k(R-r))/(4 pi r sinh(kR)) (3D); k = sqrt(sigma).
 //   * Shell test d < eps; Russian roulette stops iff alpha < U, U in [0,1).
 //   * Normal at the closest point: geometric normal of the closest primitive,
-//     flipped so that n.(xbar - x) >= 0 (points out of the domain).
+//     flipped so that n.(xbar - x) >= 0 (points out of the domain).  The
+//     closest primitive is the lowest-index one among those whose squared
+//     distance is within a relative 1e-12 of the minimum.
 //   * Walk-length cap kmax: the kmax-th query is treated as terminal.
 //   * Mapped data: udot = gdot_ref - grad_G g . V - V_n du/dn (Appendix A
 //     with tangential components of the velocity kept explicitly).
@@ -193,7 +195,10 @@ struct Scene {
             }
             double d2 = 0;
             for (int i = 0; i < D; ++i) d2 += (x[i] - q[i]) * (x[i] - q[i]);
-            if (d2 < h.d2) {   // strict: ties keep the lowest index
+            // distances within a relative 1e-12 of each other are ties (two
+            // primitives sharing an edge or vertex compute the same distance
+            // with different rounding); a tie keeps the lowest index
+            if (d2 < h.d2 * (1.0 - 1e-12)) {
                 h.d2 = d2; h.prim = p;
                 for (int i = 0; i < 3; ++i) { h.bary[i] = bary[i]; h.xbar[i] = q[i]; }
             }

@@ -74,7 +74,7 @@ def lib():
             "dwos_walk_records": [vp, vp, C.c_int64, C.c_int32, C.c_uint64, C.c_int32, vp, vp, vp, vp, vp],
             "dwos_closest": [vp, vp, C.c_int64, vp],
             "dwos_eval_ball_kernels": [vp, vp, vp, C.c_int64, C.c_double, vp, vp],
-            "dwos_walk_timing": [vp, C.c_int32, dp, i64p],
+            "dwos_walk_timing": [vp, C.c_int32, C.c_int32, dp, i64p, C.POINTER(dwos_stats)],
             "dwos_batch_add_instance": [vp, dp, C.c_int64, i32p, C.c_int64, i32p, C.c_double,
                                         C.c_double, C.c_double, i32p],
             "dwos_batch_solve": [vp, vp, i64p, C.c_int32, C.c_uint64, vp, vp, C.POINTER(dwos_stats)],

@@ -59,10 +59,10 @@ __device__ __forceinline__ void unit_dir(uint32_t w0, uint32_t w1, T* s) {
 // Modified Bessel functions for the 2D kernels.
 //   I0(z) = sum_k t_k,  t_k = (z^2/4)^k / (k!)^2
 //   F(z)  = K0(z) + (ln(z/2) + gamma) I0(z) = sum_{k>=1} H_k t_k
-// Both series have positive terms (no cancellation).  K0 for z > 2 uses the
-// trapezoidal rule on K0(z) = int_0^inf exp(-z cosh t) dt, whose integrand is
-// analytic in the strip |Im t| < pi/2, so the rule converges like
-// exp(-pi^2/h); h = 1/4 gives ~1e-17 relative error.
+// Both series have positive terms (no cancellation).  K0 for 2 < z <= 20
+// uses the trapezoidal rule on K0(z) = int_0^inf exp(-z cosh t) dt, whose
+// integrand is analytic in the strip |Im t| < pi/2 (geometric convergence in
+// 1/h); for z > 20 its asymptotic expansion.
 // ---------------------------------------------------------------------------
 template <class T> struct SeriesTol;
 template <> struct SeriesTol<float> { static constexpr float v = 3e-8f; };
@@ -102,12 +102,24 @@ __device__ inline double bessel_k0(double z) {
         bessel_i0_f(z, &i0, &f);
         return f - (log(0.5 * z) + euler_gamma) * i0;
     }
-    // scaled: e^z K0(z) = h [1/2 + sum_j exp(-z (cosh(jh) - 1))]
-    const double h = 0.25;
+    if (z > 20.0) {
+        // asymptotic series sqrt(pi/(2z)) e^-z sum_k a_k, a_k = -a_{k-1} (2k-1)^2/(8kz);
+        // its smallest term is ~e^{-2z}, below 1e-17 here
+        double a = 1.0, s = 1.0;
+        for (int k = 1; k < 40; ++k) {
+            a *= -double((2 * k - 1) * (2 * k - 1)) / (8.0 * k * z);
+            s += a;
+            if (fabs(a) < 1e-18 * s) break;
+        }
+        return sqrt(1.5707963267948966 / z) * exp(-z) * s;
+    }
+    // trapezoid on e^z K0(z) = int_0^inf exp(-z (cosh t - 1)) dt; the error of
+    // step h behaves like exp(z - pi^2/h), so h = 1/8 keeps it below 1e-25
+    // for z <= 20
+    const double h = 0.125;
     double s = 0.5;
-    for (int j = 1; j < 64; ++j) {
-        const double c1 = cosh(j * h) - 1.0;
-        const double e = exp(-z * c1);
+    for (int j = 1; j < 128; ++j) {
+        const double e = exp(-z * (cosh(j * h) - 1.0));
         s += e;
         if (e < 1e-18 * s) break;
     }

@@ -98,10 +98,12 @@ struct dwos_ctx {
     // workspaces
     DevBuf rec_u, rec_prim, rec_b, rec_uoff, rec_steps, accA, accB, queue, counters, instbuf, walk_udot;
     DevBuf vtmp;   // V(pi) for dwos_apply_parameters
-    // timing
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
-    double timed_ms = 0.0;
-    int64_t timed_launches = 0;
+    // timing and cumulative counters per walk kind (0 forward, 1 differential)
+    struct Pending { hipEvent_t e0, e1; int kind; };
+    std::vector<Pending> pending;
+    double timed_ms[2] = {0.0, 0.0};
+    int64_t timed_launches[2] = {0, 0};
+    DevBuf totals;   // 2 x Counters
 };
 
 namespace {
@@ -240,17 +242,25 @@ dwos_status drain_events(dwos_ctx* c, double* call_ms, size_t from) {
     double ms_call = 0.0;
     for (size_t i = 0; i < c->pending.size(); ++i) {
         auto& pr = c->pending[i];
-        HIP_OK(hipEventSynchronize(pr.second));
+        HIP_OK(hipEventSynchronize(pr.e1));
         float ms = 0.f;
-        HIP_OK(hipEventElapsedTime(&ms, pr.first, pr.second));
-        c->timed_ms += ms;
-        c->timed_launches += 1;
+        HIP_OK(hipEventElapsedTime(&ms, pr.e0, pr.e1));
+        c->timed_ms[pr.kind] += ms;
+        c->timed_launches[pr.kind] += 1;
         if (i >= from) ms_call += ms;
-        (void)hipEventDestroy(pr.first);
-        (void)hipEventDestroy(pr.second);
+        (void)hipEventDestroy(pr.e0);
+        (void)hipEventDestroy(pr.e1);
     }
     c->pending.clear();
     if (call_ms) *call_ms = ms_call;
+    return DWOS_OK;
+}
+
+dwos_status ensure_totals(dwos_ctx* c) {
+    if (c->totals.bytes >= 2 * sizeof(dwos::Counters)) return DWOS_OK;
+    HIP_OK(c->totals.reserve(2 * sizeof(dwos::Counters)));
+    hipLaunchKernelGGL(dwos::fill_u64_kernel, dim3(1), dim3(64), 0, c->stream,
+                       c->totals.as<unsigned long long>(), (int64_t)(2 * sizeof(dwos::Counters) / 8));
     return DWOS_OK;
 }
 
@@ -258,6 +268,7 @@ dwos_status drain_events(dwos_ctx* c, double* call_ms, size_t from) {
 template <class T, int D, int MODE>
 dwos_status launch_walks(dwos_ctx* c, dwos::WalkArgs<T>& a) {
     hipStream_t s = c->stream;
+    a.tot = c->totals.as<dwos::Counters>() + MODE;
     hipLaunchKernelGGL(dwos::fill_u64_kernel, dim3(1), dim3(64), 0, s, a.queue, (int64_t)1);
     int per_cu = 0;
     HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dwos::walk_kernel<T, D, MODE>, 256, 0));
@@ -271,7 +282,7 @@ dwos_status launch_walks(dwos_ctx* c, dwos::WalkArgs<T>& a) {
     hipLaunchKernelGGL((dwos::walk_kernel<T, D, MODE>), dim3(grid), dim3(256), 0, s, a);
     HIP_OK(hipGetLastError());
     HIP_OK(hipEventRecord(e1, s));
-    c->pending.emplace_back(e0, e1);
+    c->pending.push_back({e0, e1, MODE});
     if (c->pending.size() > 4096) {
         dwos_status st = drain_events(c, nullptr, c->pending.size());
         if (st) return st;
@@ -304,6 +315,7 @@ dwos::WalkArgs<T> base_args(dwos_ctx* c, const double* X, int32_t W, uint64_t se
     a.key1 = (uint32_t)(seed >> 32);
     a.queue = c->queue.as<unsigned long long>();
     a.cnt = c->counters.as<dwos::Counters>();
+    a.tot = c->totals.as<dwos::Counters>();
     a.rec_u = c->rec_u.as<T>();
     a.rec_prim = c->rec_prim.as<int32_t>();
     a.rec_b = c->rec_b.as<T>();
@@ -340,7 +352,7 @@ dwos_status begin_call(dwos_ctx* c, bool need_params) {
     HIP_OK(c->counters.reserve(sizeof(dwos::Counters)));
     hipLaunchKernelGGL(dwos::fill_u64_kernel, dim3(1), dim3(64), 0, c->stream,
                        c->counters.as<unsigned long long>(), (int64_t)(sizeof(dwos::Counters) / 8));
-    return DWOS_OK;
+    return ensure_totals(c);
 }
 
 dwos_status finish_call(dwos_ctx* c, dwos_stats* st, size_t ev_from) {
@@ -550,7 +562,7 @@ dwos_status dwos_create(int32_t dim, int32_t precision, void* stream, dwos_ctx**
 dwos_status dwos_destroy(dwos_ctx* c) {
     if (!c) return DWOS_OK;
     (void)hipStreamSynchronize(c->stream);
-    for (auto& pr : c->pending) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
+    for (auto& pr : c->pending) { (void)hipEventDestroy(pr.e0); (void)hipEventDestroy(pr.e1); }
     delete c;
     return DWOS_OK;
 }
@@ -862,13 +874,39 @@ dwos_status dwos_eval_ball_kernels(dwos_ctx* c, const double* r, const double* R
     return DWOS_OK;
 }
 
-dwos_status dwos_walk_timing(dwos_ctx* c, int32_t reset, double* walk_ms, int64_t* launches) {
+dwos_status dwos_walk_timing(dwos_ctx* c, int32_t kind, int32_t reset, double* walk_ms, int64_t* launches,
+                             dwos_stats* totals) {
     if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (kind != 0 && kind != 1) return fail(DWOS_EINVAL, "walk_timing: kind must be 0 or 1");
+    HIP_OK(hipSetDevice(c->device));
     dwos_status rc = drain_events(c, nullptr, 0);
     if (rc) return rc;
-    if (walk_ms) *walk_ms = c->timed_ms;
-    if (launches) *launches = c->timed_launches;
-    if (reset) { c->timed_ms = 0.0; c->timed_launches = 0; }
+    if (walk_ms) *walk_ms = c->timed_ms[kind];
+    if (launches) *launches = c->timed_launches[kind];
+    if ((rc = ensure_totals(c))) return rc;
+    HIP_OK(hipStreamSynchronize(c->stream));
+    dwos::Counters h{};
+    HIP_OK(hipMemcpy(&h, c->totals.as<dwos::Counters>() + kind, sizeof(h), hipMemcpyDeviceToHost));
+    if (totals) {
+        totals->walks = (int64_t)h.walks;
+        totals->nested_walks = (int64_t)h.nested;
+        totals->steps = (int64_t)h.steps;
+        totals->terminal = (int64_t)h.terminal;
+        totals->truncated = (int64_t)h.truncated;
+        totals->nodes = (int64_t)h.nodes;
+        totals->prims = (int64_t)h.prims;
+        totals->stack_overflow = (int64_t)h.overflow;
+        totals->invalid = (int64_t)h.invalid;
+        totals->walk_ms = c->timed_ms[kind];
+    }
+    if (reset) {
+        c->timed_ms[kind] = 0.0;
+        c->timed_launches[kind] = 0;
+        hipLaunchKernelGGL(dwos::fill_u64_kernel, dim3(1), dim3(64), 0, c->stream,
+                           reinterpret_cast<unsigned long long*>(c->totals.as<dwos::Counters>() + kind),
+                           (int64_t)(sizeof(dwos::Counters) / 8));
+        HIP_OK(hipStreamSynchronize(c->stream));
+    }
     return DWOS_OK;
 }
 

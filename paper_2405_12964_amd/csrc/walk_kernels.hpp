@@ -75,7 +75,8 @@ struct WalkArgs {
     int64_t wid_offset;      // logical id of walk 0 of this launch
     uint32_t key0, key1;
     unsigned long long* queue;
-    Counters* cnt;
+    Counters* cnt;           // this call
+    Counters* tot;           // cumulative for this walk kind
     // records (indexed by logical id - wid_offset)
     T* rec_u;
     int32_t* rec_prim;       // orig*2 + flip, -1 when stopped by roulette
@@ -90,6 +91,11 @@ struct WalkArgs {
 template <class T> struct Slack;
 template <> struct Slack<float> { static constexpr float v = 1.00001f; };
 template <> struct Slack<double> { static constexpr double v = 1.000000000001; };
+// Relative band within which two squared distances count as a tie (shared
+// edges and vertices); ties keep the lowest original primitive index.
+template <class T> struct TieBand;
+template <> struct TieBand<float> { static constexpr float v = 0.0f; };
+template <> struct TieBand<double> { static constexpr double v = 1e-12; };
 
 template <class T, int D>
 __device__ __forceinline__ T box_d2(const T* lo, const T* hi, const T* x) {
@@ -247,8 +253,11 @@ __device__ __forceinline__ int32_t closest_leaf(const Scene<T>& s, int32_t root,
             load_prim<T, D>(s.prims, i, P);
             const T d2 = prim_closest<T, D>(P, x, bb);
             qc.prims++;
-            if (d2 < best) { best = d2; bleaf = i; }
-            else if (d2 == best && i != bleaf && s.orig[i] < s.orig[bleaf]) { bleaf = i; }
+            if (d2 < best * (T(1) - TieBand<T>::v)) { best = d2; bleaf = i; }
+            else if (d2 <= best * (T(1) + TieBand<T>::v) && i != bleaf && s.orig[i] < s.orig[bleaf]) {
+                best = d2;
+                bleaf = i;
+            }
         }
     };
     while (true) {
@@ -599,15 +608,19 @@ __global__ void __launch_bounds__(256) walk_kernel(WalkArgs<T> a) {
     c_ovf = wave_sum_u64(c_ovf);
     c_invalid = wave_sum_u64(c_invalid);
     if (lane == 0) {
-        atomicAdd(&a.cnt->walks, c_walks);
-        atomicAdd(&a.cnt->nested, c_nested);
-        atomicAdd(&a.cnt->steps, c_steps);
-        atomicAdd(&a.cnt->terminal, c_term);
-        atomicAdd(&a.cnt->nodes, c_nodes);
-        atomicAdd(&a.cnt->prims, c_prims);
-        if (c_trunc) atomicAdd(&a.cnt->truncated, c_trunc);
-        if (c_ovf) atomicAdd(&a.cnt->overflow, c_ovf);
-        if (c_invalid) atomicAdd(&a.cnt->invalid, c_invalid);
+        Counters* dst[2] = {a.cnt, a.tot};
+        for (int q = 0; q < 2; ++q) {
+            Counters* c = dst[q];
+            atomicAdd(&c->walks, c_walks);
+            atomicAdd(&c->nested, c_nested);
+            atomicAdd(&c->steps, c_steps);
+            atomicAdd(&c->terminal, c_term);
+            atomicAdd(&c->nodes, c_nodes);
+            atomicAdd(&c->prims, c_prims);
+            if (c_trunc) atomicAdd(&c->truncated, c_trunc);
+            if (c_ovf) atomicAdd(&c->overflow, c_ovf);
+            if (c_invalid) atomicAdd(&c->invalid, c_invalid);
+        }
     }
 }
 

@@ -217,8 +217,12 @@ class Solver:
                                           _dev(GB), _dev(al)))
         return GB, al
 
-    def walk_timing(self, reset=False):
+    def walk_timing(self, kind: int, reset=False):
+        """(ms, launches, totals dict) of the walk kernels of one kind
+        (0 forward, 1 differential) since the last reset."""
         ms = C.c_double()
         n = C.c_int64()
-        check(capi.dwos_walk_timing(self._ctx, 1 if reset else 0, C.byref(ms), C.byref(n)))
-        return ms.value, n.value
+        st = capi.dwos_stats()
+        check(capi.dwos_walk_timing(self._ctx, int(kind), 1 if reset else 0, C.byref(ms), C.byref(n),
+                                    C.byref(st)))
+        return ms.value, n.value, st.as_dict()
