@@ -31,13 +31,15 @@ if ROOT not in sys.path:
 METRIC = "walk-steps/s and shape-gradient evals/s at fixed RMSE; surrogate vs plain WoS"
 
 # Algorithmic FP32 operations per counted unit (2D), from the arithmetic of
-# the kernels: a pair-node visit evaluates two point-box squared distances
-# (2 dims x [2 sub, 2 max, 1 fma] = 12 each); a segment test is ~22
-# (edge/offset differences, projection, clamp, residual, squared norm); a
-# walk step adds ~40 (roulette scale 1/I0 series, direction, position
-# update); a source sample adds ~200 (FP64 Green's function series and the
-# Gaussian source) -- counted for non-terminal steps only.
-OPS_NODE_2D = 24
+# the kernels: a pair-node visit evaluates, for both children, a point-box
+# squared distance (2 dims x [2 sub, 2 max, 1 fma] = 12) and a point-slab
+# squared distance (2 fma, abs-sub, max, mul = 6) plus the max of the two
+# (2 x 19 + 2 = 40); a segment test is ~22 (edge/offset differences,
+# projection, clamp, residual, squared norm); a walk step adds ~40 (roulette
+# scale 1/I0 series, direction, position update); a source sample adds ~200
+# (FP64 Green's function series and the Gaussian source) -- counted for
+# non-terminal steps only.
+OPS_NODE_2D = 40
 OPS_PRIM_2D = 22
 OPS_STEP_2D = 40
 OPS_SOURCE_2D = 200

@@ -16,18 +16,20 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = LIB, csrc: str = CSRC, defines=()) -> str:
+    """Compile libdwos.so.  `defines` are extra -D knobs (e.g. DWOS_LEAF_MAX=2)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+    tmp = out + ".tmp"
+    cmd = [hipcc, *HIPCC_FLAGS, *[f"-D{d}" for d in defines], "-o", tmp] + \
+        [os.path.join(csrc, s) for s in SOURCES]
     if verbose:
         print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, cwd=CSRC, capture_output=True, text=True)
+    r = subprocess.run(cmd, cwd=csrc, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed building libdwos.so")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -314,19 +314,21 @@ template <class T, int D>
 __global__ void closest_kernel(Scene<T> s, int32_t root, const double* X, int64_t P, double* out) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
+    const StageView sv{0, -1};
     T x[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) x[c] = T(X[p * D + c]);
     T d2;
     QueryCount qc{0, 0, 0};
-    const int32_t leaf = closest_leaf<T, D>(s, root, x, -1, d2, qc);
+    TravStack<T, false> stack;
+    const int32_t leaf = closest_leaf<T, D>(s, sv, root, x, -1, d2, qc, stack);
     double* o = out + p * 8;
     if (leaf < 0) {
         for (int k = 0; k < 8; ++k) o[k] = NAN;
         return;
     }
     T P9[9], bary[3];
-    load_prim<T, D>(s.prims, leaf, P9);
+    scene_prim<T, D>(s, sv, leaf, P9);
     prim_closest<T, D>(P9, x, bary);
     const int32_t orig = s.orig[leaf];
     T V[9];
@@ -341,6 +343,23 @@ __global__ void closest_kernel(Scene<T> s, int32_t root, const double* X, int64_
             for (int k = 0; k < D; ++k) v += double(bary[k]) * double(V[k * D + c]);
         o[5 + c] = v;
     }
+}
+
+// closest primitive of each start point (shared first query of its walks)
+template <class T, int D>
+__global__ void first_query_kernel(Scene<T> s, int32_t root, const double* X, int64_t P, int32_t* leaf_out,
+                                   T* d2_out) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const StageView sv{0, -1};
+    T x[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) x[c] = T(X[p * D + c]);
+    T d2;
+    QueryCount qc{0, 0, 0};
+    TravStack<T, false> stack;
+    leaf_out[p] = closest_leaf<T, D>(s, sv, root, x, -1, d2, qc, stack);
+    d2_out[p] = d2;
 }
 
 template <class T, int D>
@@ -380,41 +399,71 @@ __global__ void pack_prims_kernel(const T* verts, const int32_t* pverts, const i
     }
 }
 
-template <class T, int D>
-__device__ __forceinline__ void child_bounds(const T* nodes, const T* prims, int32_t ref, T* lo, T* hi) {
-    if (ref < 0) {
-        const int32_t v = -1 - ref;
-        const int32_t start = v >> 3, n = (v & 7) + 1;
-        for (int c = 0; c < D; ++c) { lo[c] = T(INFINITY); hi[c] = T(-INFINITY); }
-        for (int32_t i = start; i < start + n; ++i) {
-            const T* P = prims + (size_t)i * prim_scalars(D);
-            for (int k = 0; k < D; ++k)
-                for (int c = 0; c < D; ++c) { lo[c] = fmin(lo[c], P[k * D + c]); hi[c] = fmax(hi[c], P[k * D + c]); }
-        }
-    } else {
-        NodeData<T, D> nd;
-        load_node<T, D>(nodes, ref, nd);
-        for (int c = 0; c < D; ++c) {
-            lo[c] = fmin(nd.lo0[c], nd.lo1[c]);
-            hi[c] = fmax(nd.hi0[c], nd.hi1[c]);
-        }
-    }
+// Refit one pair node per wavefront: recompute both children's boxes and
+// slab offsets/thicknesses (normals kept) from the primitives in their
+// leaf-order ranges.  Every node is independent, so one launch refits the tree.
+template <class T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+template <class T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
 }
 
 template <class T, int D>
-__global__ void refit_level_kernel(T* nodes, const T* prims, const int32_t* order, int32_t begin,
-                                   int32_t end) {
-    const int32_t t = begin + (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (t >= end) return;
-    const int32_t ni = order[t];
-    T* p = nodes + (size_t)ni * node_scalars(D);
-    const int32_t* refs = reinterpret_cast<const int32_t*>(p + 4 * D);
-    const int32_t r0 = refs[0], r1 = refs[1];
-    T lo[D], hi[D];
-    child_bounds<T, D>(nodes, prims, r0, lo, hi);
-    for (int c = 0; c < D; ++c) { p[c] = lo[c]; p[D + c] = hi[c]; }
-    child_bounds<T, D>(nodes, prims, r1, lo, hi);
-    for (int c = 0; c < D; ++c) { p[2 * D + c] = lo[c]; p[3 * D + c] = hi[c]; }
+__global__ void __launch_bounds__(256) refit_nodes_kernel(T* nodes, const T* prims, const int32_t* ranges,
+                                                          int64_t n_nodes) {
+    const int64_t ni = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (ni >= n_nodes) return;
+    T* p = nodes + ni * node_scalars(D);
+    for (int c = 0; c < 2; ++c) {
+        const int32_t b = ranges[ni * 4 + 2 * c], e = ranges[ni * 4 + 2 * c + 1];
+        if (e <= b) continue;   // empty child keeps its sentinel bounds
+        T* lo = p + 2 * c * D;
+        T* hi = p + (2 * c + 1) * D;
+        T* slab = p + slab_offset(D) + c * (D + 2);
+        T n[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) n[k] = slab[k];
+        T mn[D], mx[D], smin = T(INFINITY), smax = T(-INFINITY);
+#pragma unroll
+        for (int k = 0; k < D; ++k) { mn[k] = T(INFINITY); mx[k] = T(-INFINITY); }
+        for (int32_t i = b + lane; i < e; i += 64) {
+            const T* P = prims + (size_t)i * prim_scalars(D);
+#pragma unroll
+            for (int v = 0; v < D; ++v) {
+                T pr = T(0);
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const T x = P[v * D + k];
+                    mn[k] = fmin(mn[k], x);
+                    mx[k] = fmax(mx[k], x);
+                    pr += n[k] * x;
+                }
+                smin = fmin(smin, pr);
+                smax = fmax(smax, pr);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) { mn[k] = wave_min(mn[k]); mx[k] = wave_max(mx[k]); }
+        smin = wave_min(smin);
+        smax = wave_max(smax);
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) { lo[k] = mn[k]; hi[k] = mx[k]; }
+            T scale = fmax(fabs(smin), fabs(smax));
+#pragma unroll
+            for (int k = 0; k < D; ++k) scale += fmax(fabs(mn[k]), fabs(mx[k]));
+            slab[D] = T(0.5) * (smin + smax);
+            slab[D + 1] = T(0.5) * (smax - smin) + slab_pad<T>(scale);
+        }
+    }
 }
 
 // V_i = V_base_i + sum_{e in row i} vel_e pi_{pid_e}

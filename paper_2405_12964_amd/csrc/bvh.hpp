@@ -1,13 +1,19 @@
 // Bounding volume hierarchy for closest-point queries (Algorithm 1,
 // DistanceToBoundary).  Host builder and the device layout it produces.
 //
-// Layout (one "pair node" per internal node): a node stores the bounding
-// boxes of BOTH of its children and the two child references, so one node
-// fetch decides which children to enter.  A node is NODE_T(D) scalars:
-//   [ lo0[D] hi0[D] lo1[D] hi1[D] | refs ]   (3D FP32: 64 B, 2D FP32: 48 B)
+// Layout (one "pair node" per internal node): a node stores, for BOTH of its
+// children, an axis-aligned box and an oriented slab {y : |n.y - o| <= t},
+// plus the two child references, so one node fetch decides which children to
+// enter.  The distance lower bound of a child is the larger of the point-box
+// and point-slab distances; for a smooth boundary the slab thickness t is
+// the sagitta of the child's patch, so the bound is nearly exact in the
+// direction of the normal, where axis-aligned boxes are loosest.
+// A node is node_scalars(D) scalars:
+//   [ lo0[D] hi0[D] lo1[D] hi1[D] | n0[D] o0 t0 | n1[D] o1 t1 | refs ]
+//   (2D: 20 scalars, 3D: 24; FP32 nodes are 80 B / 96 B)
 // A child reference r >= 0 is another pair node; r < 0 encodes a leaf,
 // v = -1 - r: primitives [v >> 3, (v >> 3) + (v & 7) + 1) in leaf order.
-// Primitives are stored in leaf order (PRIM_T(D) scalars each: 2D a,b;
+// Primitives are stored in leaf order (prim_scalars(D) scalars each: 2D a,b;
 // 3D a,b,c padded to 12) with their original indices alongside.
 #pragma once
 #include <cstdint>
@@ -15,19 +21,37 @@
 
 namespace dwos {
 
-constexpr int kLeafMax = 4;     // primitives per leaf (fits the 3-bit count)
-constexpr int kMaxDepth = 40;   // builder guarantee; traversal stack size
-constexpr int kStackSize = 48;
+#ifndef DWOS_LEAF_MAX
+#define DWOS_LEAF_MAX 4
+#endif
+#ifndef DWOS_STACK_SIZE
+#define DWOS_STACK_SIZE 48
+#endif
+constexpr int kLeafMax = DWOS_LEAF_MAX;     // primitives per leaf (<= 8: 3-bit count)
+constexpr int kStackSize = DWOS_STACK_SIZE; // traversal stack entries
+constexpr int kMaxDepth = kStackSize - 2;   // builder guarantee (stack never overflows)
+static_assert(kLeafMax >= 1 && kLeafMax <= 8, "leaf size must fit the 3-bit count");
 
-constexpr int node_scalars(int D) { return 4 * D + 4; }   // 16 (3D) or 12 (2D)
+constexpr int node_scalars(int D) { return D == 2 ? 20 : 24; }
+constexpr int slab_offset(int D) { return 4 * D; }                  // n0[D] o0 t0 n1[D] o1 t1
+constexpr int ref_offset(int D) { return 4 * D + 2 * (D + 2); }     // two int32 child refs
 constexpr int prim_scalars(int D) { return D == 2 ? 4 : 12; }
+
+// Padding added to a slab half-thickness so that the rounding of the
+// working-precision projection n.x - o can never make the slab bound exceed
+// the true distance: 16 units of roundoff of the projected magnitudes.
+template <class T>
+inline T slab_pad_host(T scale) { return T(16) * (sizeof(T) == 4 ? T(5.9604644775390625e-08) : T(1.1102230246251565e-16)) * scale; }
 
 inline int32_t leaf_ref(int32_t start, int32_t count) { return -1 - ((start << 3) | (count - 1)); }
 
 struct HostNode {
     double lo[2][3];
     double hi[2][3];
+    double n[2][3];          // slab normals
+    double o[2], t[2];       // slab offsets and half-thicknesses
     int32_t child[2];
+    int32_t range[2][2];     // leaf-order primitive range under each child
     int32_t depth;
 };
 
@@ -43,7 +67,10 @@ struct HostBVH {
 // median splits when a subtree would otherwise get too deep.
 HostBVH build_bvh(const double* V, const int32_t* prims, int64_t np, int D);
 
-// Refit order: node indices grouped by depth (deepest level first).
-void refit_levels(const HostBVH& bvh, std::vector<int32_t>& order, std::vector<int32_t>& level_start);
+// Renumber the pair nodes in breadth-first order (root first, then each
+// level), so that the top levels of the tree form a prefix of the node array
+// that can be staged in LDS.
+void reorder_bfs(HostBVH& bvh);
+
 
 }  // namespace dwos

@@ -28,8 +28,60 @@ struct Box {
     }
 };
 
+// Best-fit normal of a point set: the eigenvector of the smallest eigenvalue
+// of its covariance (2D in closed form, 3D by cyclic Jacobi rotations).
+void fit_normal(const std::vector<double>& pts, int D, double n[3]) {
+    const size_t m = pts.size() / 3;
+    double c[3] = {0, 0, 0};
+    for (size_t i = 0; i < m; ++i) for (int k = 0; k < 3; ++k) c[k] += pts[3 * i + k];
+    for (int k = 0; k < 3; ++k) c[k] /= std::max<size_t>(1, m);
+    double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (size_t i = 0; i < m; ++i)
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) A[a][b] += (pts[3 * i + a] - c[a]) * (pts[3 * i + b] - c[b]);
+    n[0] = n[1] = n[2] = 0;
+    if (D == 2) {
+        const double th = 0.5 * std::atan2(2 * A[0][1], A[0][0] - A[1][1]);  // major axis
+        n[0] = -std::sin(th);
+        n[1] = std::cos(th);
+        return;
+    }
+    double V[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        double off = std::fabs(A[0][1]) + std::fabs(A[0][2]) + std::fabs(A[1][2]);
+        if (off < 1e-300) break;
+        for (int p = 0; p < 2; ++p)
+            for (int q = p + 1; q < 3; ++q) {
+                if (std::fabs(A[p][q]) < 1e-300) continue;
+                const double th = 0.5 * std::atan2(2 * A[p][q], A[q][q] - A[p][p]);
+                const double cs = std::cos(th), sn = std::sin(th);
+                for (int k = 0; k < 3; ++k) {   // A <- A J
+                    const double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = cs * akp - sn * akq;
+                    A[k][q] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < 3; ++k) {   // A <- J^T A
+                    const double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = cs * apk - sn * aqk;
+                    A[q][k] = sn * apk + cs * aqk;
+                }
+                for (int k = 0; k < 3; ++k) {
+                    const double vkp = V[k][p], vkq = V[k][q];
+                    V[k][p] = cs * vkp - sn * vkq;
+                    V[k][q] = sn * vkp + cs * vkq;
+                }
+            }
+    }
+    int j = 0;
+    for (int k = 1; k < 3; ++k) if (A[k][k] < A[j][j]) j = k;
+    const double L = std::sqrt(V[0][j] * V[0][j] + V[1][j] * V[1][j] + V[2][j] * V[2][j]);
+    for (int k = 0; k < 3; ++k) n[k] = V[k][j] / (L > 0 ? L : 1.0);
+}
+
 struct Builder {
     int D;
+    const double* V = nullptr;
+    const int32_t* P = nullptr;
     std::vector<Box> pbox;
     std::vector<double> cen;     // np x 3 centroids
     std::vector<int32_t> idx;    // permutation being partitioned
@@ -118,7 +170,32 @@ struct Builder {
         }
         nd.child[0] = c0;
         nd.child[1] = c1;
+        set_slab(nd, 0, b, mid);
+        set_slab(nd, 1, mid, e);
         return me;
+    }
+
+    // slab of the primitives idx[b, e): fitted normal, exact enclosure
+    void set_slab(HostNode& nd, int c, int b, int e) {
+        nd.range[c][0] = b;
+        nd.range[c][1] = e;
+        std::vector<double> pts;
+        pts.reserve(3 * D * (size_t)(e - b));
+        for (int i = b; i < e; ++i)
+            for (int k = 0; k < D; ++k) {
+                const double* v = V + (size_t)P[(size_t)idx[i] * D + k] * D;
+                pts.push_back(v[0]); pts.push_back(v[1]); pts.push_back(D == 3 ? v[2] : 0.0);
+            }
+        double n[3];
+        fit_normal(pts, D, n);
+        double lo = std::numeric_limits<double>::infinity(), hi = -lo;
+        for (size_t i = 0; i < pts.size() / 3; ++i) {
+            const double pr = n[0] * pts[3 * i] + n[1] * pts[3 * i + 1] + n[2] * pts[3 * i + 2];
+            lo = std::min(lo, pr); hi = std::max(hi, pr);
+        }
+        for (int k = 0; k < 3; ++k) nd.n[c][k] = n[k];
+        nd.o[c] = 0.5 * (lo + hi);
+        nd.t[c] = 0.5 * (hi - lo);
     }
 };
 
@@ -127,6 +204,8 @@ struct Builder {
 HostBVH build_bvh(const double* V, const int32_t* prims, int64_t np, int D) {
     Builder B;
     B.D = D;
+    B.V = V;
+    B.P = prims;
     B.pbox.resize(np);
     B.cen.assign(3 * (size_t)np, 0.0);
     B.idx.resize(np);
@@ -149,6 +228,11 @@ HostBVH build_bvh(const double* V, const int32_t* prims, int64_t np, int D) {
         nd.child[0] = leaf_ref(0, (int)np);
         nd.child[1] = leaf_ref(0, 1);
         nd.depth = 0;
+        B.set_slab(nd, 0, 0, (int)np);
+        // the second child is empty: an inverted box and a slab nothing is near
+        nd.n[1][0] = 1; nd.n[1][1] = 0; nd.n[1][2] = 0;
+        nd.o[1] = 0; nd.t[1] = -1e300;
+        nd.range[1][0] = 0; nd.range[1][1] = 0;
         B.out.nodes.push_back(nd);
     } else {
         B.build(0, (int)np, 0);
@@ -159,17 +243,23 @@ HostBVH build_bvh(const double* V, const int32_t* prims, int64_t np, int D) {
     return std::move(B.out);
 }
 
-void refit_levels(const HostBVH& bvh, std::vector<int32_t>& order, std::vector<int32_t>& level_start) {
-    const int L = bvh.max_depth + 1;
-    std::vector<std::vector<int32_t>> by(L);
-    for (int32_t i = 0; i < (int32_t)bvh.nodes.size(); ++i) by[bvh.nodes[i].depth].push_back(i);
-    order.clear();
-    level_start.clear();
-    for (int d = L - 1; d >= 0; --d) {
-        level_start.push_back((int32_t)order.size());
-        order.insert(order.end(), by[d].begin(), by[d].end());
+void reorder_bfs(HostBVH& bvh) {
+    const size_t n = bvh.nodes.size();
+    std::vector<int32_t> order;
+    order.reserve(n);
+    order.push_back(0);
+    for (size_t h = 0; h < order.size(); ++h)
+        for (int c = 0; c < 2; ++c)
+            if (bvh.nodes[order[h]].child[c] >= 0) order.push_back(bvh.nodes[order[h]].child[c]);
+    std::vector<int32_t> newid(n, -1);
+    for (size_t i = 0; i < order.size(); ++i) newid[order[i]] = (int32_t)i;
+    std::vector<HostNode> out(order.size());
+    for (size_t i = 0; i < order.size(); ++i) {
+        out[i] = bvh.nodes[order[i]];
+        for (int c = 0; c < 2; ++c)
+            if (out[i].child[c] >= 0) out[i].child[c] = newid[out[i].child[c]];
     }
-    level_start.push_back((int32_t)order.size());
+    bvh.nodes.swap(out);
 }
 
 }  // namespace dwos

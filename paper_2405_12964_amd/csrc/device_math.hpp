@@ -59,71 +59,112 @@ __device__ __forceinline__ void unit_dir(uint32_t w0, uint32_t w1, T* s) {
 // Modified Bessel functions for the 2D kernels.
 //   I0(z) = sum_k t_k,  t_k = (z^2/4)^k / (k!)^2
 //   F(z)  = K0(z) + (ln(z/2) + gamma) I0(z) = sum_{k>=1} H_k t_k
-// Both series have positive terms (no cancellation).  K0 for 2 < z <= 20
-// uses the trapezoidal rule on K0(z) = int_0^inf exp(-z cosh t) dt, whose
-// integrand is analytic in the strip |Im t| < pi/2 (geometric convergence in
-// 1/h); for z > 20 its asymptotic expansion.
+// (H_k harmonic numbers).  Both series have positive terms.  For z > 2 the
+// kernels use exponentially scaled forms I0s(z) = e^-z I0(z) and
+// K0s(z) = e^z K0(z) so that nothing overflows:
+//   I0s: the series times e^-z for z <= 20, else the asymptotic series
+//        (2 pi z)^-1/2 sum_k ((2k-1)!!)^2 / (k! (8z)^k)
+//   K0s: the trapezoidal rule on e^z K0(z) = int_0^inf exp(-z (cosh t - 1)) dt
+//        for z <= 20 (integrand analytic in |Im t| < pi/2, so the error
+//        falls geometrically in 1/h), else the asymptotic series
+//        (pi/(2z))^1/2 sum_k (-1)^k ((2k-1)!!)^2 / (k! (8z)^k).
 // ---------------------------------------------------------------------------
-template <class T> struct SeriesTol;
-template <> struct SeriesTol<float> { static constexpr float v = 3e-8f; };
-template <> struct SeriesTol<double> { static constexpr double v = 1e-17; };
+template <class T> struct BesselCfg;
+template <> struct BesselCfg<float> {
+    static constexpr float tol = 3e-8f;
+    static constexpr float h = 0.25f;   // trapezoid step: error ~e^{0.46 z - 25}
+};
+template <> struct BesselCfg<double> {
+    static constexpr double tol = 1e-17;
+    static constexpr double h = 0.125;  // error ~e^{z - 79}
+};
 
+// 1/k^2 and H_k for k = 0..63 (index 0 unused)
+struct SeriesTables {
+    double inv_k2[64];
+    double harm[64];
+    constexpr SeriesTables() : inv_k2(), harm() {
+        double h = 0.0;
+        for (int k = 1; k < 64; ++k) {
+            inv_k2[k] = 1.0 / (double(k) * double(k));
+            h += 1.0 / double(k);
+            harm[k] = h;
+        }
+    }
+};
+__constant__ constexpr SeriesTables kSeries{};
+
+// I0 by its series (z up to ~20)
 template <class T>
-__device__ inline T bessel_i0(T z) {
+__device__ inline T i0_series(T z) {
     const T q = T(0.25) * z * z;
     T t = T(1), s = T(1);
-    for (int k = 1; k < 200; ++k) {
-        t *= q / T(k * k);
+    for (int k = 1; k < 64; ++k) {
+        t *= q * T(kSeries.inv_k2[k]);
         s += t;
-        if (t < SeriesTol<T>::v * s) break;
+        if (t < BesselCfg<T>::tol * s) break;
     }
     return s;
 }
 
-// I0(z) and F(z) together.
-__device__ inline void bessel_i0_f(double z, double* i0, double* f) {
+// I0 and F by their series, fixed 13 terms: exact to double rounding for z <= 2
+__device__ __forceinline__ void i0_f_small(double z, double& i0, double& f) {
     const double q = 0.25 * z * z;
-    double t = 1.0, s = 1.0, sf = 0.0, H = 0.0;
-    for (int k = 1; k < 200; ++k) {
-        t *= q / double(k * k);
-        H += 1.0 / double(k);
+    double t = 1.0, s = 1.0, sf = 0.0;
+#pragma unroll
+    for (int k = 1; k <= 13; ++k) {
+        t *= q * kSeries.inv_k2[k];
         s += t;
-        sf += H * t;
-        if (t * H < 1e-17 * sf && t < 1e-17 * s) break;
+        sf += kSeries.harm[k] * t;
     }
-    *i0 = s;
-    *f = sf;
+    i0 = s;
+    f = sf;
 }
 
-__device__ inline double bessel_k0(double z) {
-    const double euler_gamma = 0.57721566490153286061;
-    if (z <= 2.0) {
-        double i0, f;
-        bessel_i0_f(z, &i0, &f);
-        return f - (log(0.5 * z) + euler_gamma) * i0;
+template <class T>
+__device__ inline T i0_scaled(T z) {   // e^-z I0(z), z >= 0
+    if (z <= T(20)) return i0_series<T>(z) * exp(-z);
+    T a = T(1), s = T(1);
+    for (int k = 1; k < 30; ++k) {
+        a *= T((2 * k - 1) * (2 * k - 1)) / (T(8) * T(k) * z);
+        s += a;
+        if (a < BesselCfg<T>::tol * s) break;
     }
-    if (z > 20.0) {
-        // asymptotic series sqrt(pi/(2z)) e^-z sum_k a_k, a_k = -a_{k-1} (2k-1)^2/(8kz);
-        // its smallest term is ~e^{-2z}, below 1e-17 here
-        double a = 1.0, s = 1.0;
-        for (int k = 1; k < 40; ++k) {
-            a *= -double((2 * k - 1) * (2 * k - 1)) / (8.0 * k * z);
+    return s / sqrt(T(6.283185307179586) * z);
+}
+
+template <class T>
+__device__ inline T k0_scaled(T z) {   // e^z K0(z), z > 2
+    if (z > T(20)) {
+        T a = T(1), s = T(1);
+        for (int k = 1; k < 30; ++k) {
+            a *= -T((2 * k - 1) * (2 * k - 1)) / (T(8) * T(k) * z);
             s += a;
-            if (fabs(a) < 1e-18 * s) break;
+            if (fabs(a) < BesselCfg<T>::tol * s) break;
         }
-        return sqrt(1.5707963267948966 / z) * exp(-z) * s;
+        return sqrt(T(1.5707963267948966) / z) * s;
     }
-    // trapezoid on e^z K0(z) = int_0^inf exp(-z (cosh t - 1)) dt; the error of
-    // step h behaves like exp(z - pi^2/h), so h = 1/8 keeps it below 1e-25
-    // for z <= 20
-    const double h = 0.125;
-    double s = 0.5;
+    const T h = BesselCfg<T>::h;
+    T s = T(0.5);
     for (int j = 1; j < 128; ++j) {
-        const double e = exp(-z * (cosh(j * h) - 1.0));
+        const T e = exp(-z * (cosh(T(j) * h) - T(1)));
         s += e;
-        if (e < 1e-18 * s) break;
+        if (e < BesselCfg<T>::tol * s) break;
     }
-    return h * s * exp(-z);
+    return h * s;
+}
+
+template <class T>
+__device__ inline T k0_small(T z) {    // K0(z) for 0 < z <= 2 from F - (ln(z/2) + gamma) I0
+    const T q = T(0.25) * z * z;
+    T t = T(1), s = T(1), sf = T(0);
+    for (int k = 1; k < 64; ++k) {
+        t *= q * T(kSeries.inv_k2[k]);
+        s += t;
+        sf += T(kSeries.harm[k]) * t;
+        if (t < BesselCfg<T>::tol * s) break;
+    }
+    return sf - (log(T(0.5) * z) + T(0.57721566490153286061)) * s;
 }
 
 // ---------------------------------------------------------------------------
@@ -132,10 +173,11 @@ __device__ inline double bessel_k0(double z) {
 //   G(r;R)|B_R| with r = rho R, rho in (0, 1]:
 //     2D: pi R^2 [K0(kr) - K0(kR) I0(kr)/I0(kR)] / (2 pi)
 //     3D: (4/3) pi R^3 sinh(k(R-r)) / (4 pi r sinh(kR))
-// 2D is evaluated in FP64.  For kR <= 2 it uses the log-factored form
+// 2D at small radius (kR <= 2) is evaluated in FP64 with the log-factored form
 //   2 pi G = I0(kr) ln(R/r) + [F(kr) I0(kR) - F(kR) I0(kr)] / I0(kR),
-// which removes the cancellation of the two logarithmic singular parts of
-// K0(kr) - K0(kR) at small radius.  3D uses expm1 so that the sinh ratio
+// which removes the cancellation between the logarithmic singular parts of
+// K0(kr) and K0(kR); at kR > 2 the direct form is evaluated with scaled
+// functions in the working precision.  3D uses expm1 so that the sinh ratio
 // e^{-kr} (1 - e^{-2k(R-r)}) / (1 - e^{-2kR}) has no cancellation.
 // ---------------------------------------------------------------------------
 template <class T, int D>
@@ -143,51 +185,36 @@ __device__ __forceinline__ T poisson_scale(T kappa, T R) {
     if (kappa == T(0)) return T(1);
     const T a = kappa * R;
     if constexpr (D == 2) {
-        return T(1) / bessel_i0<T>(a);
+        if (a <= T(20)) return T(1) / i0_series<T>(a);
+        return exp(-a) / i0_scaled<T>(a);
     } else {
         return T(2) * a * exp(-a) / (-expm1(T(-2) * a));
     }
 }
 
-template <int D>
-__device__ inline double green_ball(double kappa, double rho, double R) {
-    if constexpr (D == 2) {
-        const double area = 3.14159265358979323846 * R * R;
-        const double lnR_r = -log(rho);
-        if (kappa == 0.0) return area * lnR_r / (2.0 * 3.14159265358979323846);
-        const double b = kappa * R, a = rho * b;
-        double g2pi;
-        if (b <= 2.0) {
-            double i0a, fa, i0b, fb;
-            bessel_i0_f(a, &i0a, &fa);
-            bessel_i0_f(b, &i0b, &fb);
-            g2pi = i0a * lnR_r + (fa * i0b - fb * i0a) / i0b;
-        } else {
-            const double i0a = bessel_i0<double>(a), i0b = bessel_i0<double>(b);
-            g2pi = bessel_k0(a) - bessel_k0(b) * (i0a / i0b);
-        }
-        return area * g2pi / (2.0 * 3.14159265358979323846);
-    } else {
-        const double r = rho * R;
-        if (kappa == 0.0) return R * R * (R - r) / (3.0 * r);
-        const double ratio = exp(-kappa * r) * (expm1(-2.0 * kappa * (R - r)) / expm1(-2.0 * kappa * R));
-        return R * R * R * ratio / (3.0 * r);
-    }
-}
-
 template <int D, class T>
-__device__ __forceinline__ T green_ball_t(T kappa, T rho, T R) {
+__device__ inline T green_ball_t(T kappa, T rho, T R) {
     if constexpr (D == 2) {
-        return T(green_ball<2>(double(kappa), double(rho), double(R)));
-    } else {
-        if constexpr (sizeof(T) == 8) {
-            return green_ball<3>(kappa, rho, R);
-        } else {
-            const T r = rho * R;
-            if (kappa == T(0)) return R * R * (R - r) / (T(3) * r);
-            const T ratio = exp(-kappa * r) * (expm1(T(-2) * kappa * (R - r)) / expm1(T(-2) * kappa * R));
-            return R * R * R * ratio / (T(3) * r);
+        const T lnR_r = -log(rho);
+        if (kappa == T(0)) return T(0.5) * R * R * lnR_r;
+        const T b = kappa * R, a = rho * b;
+        if (b <= T(2)) {
+            double i0a, fa, i0b, fb;
+            i0_f_small(double(a), i0a, fa);
+            i0_f_small(double(b), i0b, fb);
+            const double g2pi = i0a * double(lnR_r) + (fa * i0b - fb * i0a) / i0b;
+            return T(0.5 * double(R) * double(R) * g2pi);
         }
+        // 2 pi G = K0(a) - K0(b) I0(a)/I0(b)
+        //        = K0(a) - K0s(b) I0s(a)/I0s(b) e^{a - 2b}
+        const T ka = a <= T(2) ? k0_small<T>(a) : k0_scaled<T>(a) * exp(-a);
+        const T g2pi = ka - k0_scaled<T>(b) * (i0_scaled<T>(a) / i0_scaled<T>(b)) * exp(a - T(2) * b);
+        return T(0.5) * R * R * g2pi;
+    } else {
+        const T r = rho * R;
+        if (kappa == T(0)) return R * R * (R - r) / (T(3) * r);
+        const T ratio = exp(-kappa * r) * (expm1(T(-2) * kappa * (R - r)) / expm1(T(-2) * kappa * R));
+        return R * R * R * ratio / (T(3) * r);
     }
 }
 

@@ -76,12 +76,12 @@ struct dwos_ctx {
     hipStream_t stream = nullptr;
     int device = 0;
     int cu_count = 0;
+    size_t max_smem = 0;      // LDS bytes a block may use
     // geometry
     bool has_boundary = false;
     int64_t nv = 0, np = 0, n_nodes = 0;
     DevBuf nodes, prims, orig, verts, pverts, label, gvert, leaf_of;
-    DevBuf refit_order;
-    std::vector<int32_t> refit_level_start;
+    DevBuf node_ranges;   // leaf-order primitive range of each node's two children
     std::vector<InstanceHost> instances;      // batch contexts
     std::vector<double> hostV;                // batch: accumulated geometry
     std::vector<int32_t> hostP, hostL;
@@ -98,6 +98,7 @@ struct dwos_ctx {
     // workspaces
     DevBuf rec_u, rec_prim, rec_b, rec_uoff, rec_steps, accA, accB, queue, counters, instbuf, walk_udot;
     DevBuf vtmp;   // V(pi) for dwos_apply_parameters
+    DevBuf first_leaf, first_d2;   // shared first query of each start point
     // timing and cumulative counters per walk kind (0 forward, 1 differential)
     struct Pending { hipEvent_t e0, e1; int kind; };
     std::vector<Pending> pending;
@@ -139,7 +140,27 @@ dwos::Scene<T> make_scene(dwos_ctx* c) {
     s.pverts = c->pverts.as<int32_t>();
     s.label = c->label.as<int32_t>();
     s.gvert = c->gvert.as<T>();
+    s.n_prims = c->np;
+    // LDS staging plan: the whole BVH and all primitives if they fit, else a
+    // prefix of the (breadth-first ordered) nodes
+    const size_t budget = c->max_smem >= 1024 ? c->max_smem - 512 : 0;
+    const size_t nb = (size_t)dwos::node_scalars(c->D) * sizeof(T);
+    const size_t pb = (size_t)dwos::prim_scalars(c->D) * sizeof(T);
+    const size_t all_nodes = (size_t)c->n_nodes * nb, all_prims = (size_t)c->np * pb;
+    if (all_nodes + all_prims <= budget) {
+        s.n_stage_nodes = (int32_t)c->n_nodes;
+        s.stage_prims = 1;
+    } else {
+        s.n_stage_nodes = (int32_t)std::min<size_t>((size_t)c->n_nodes, budget / nb);
+        s.stage_prims = 0;
+    }
     return s;
+}
+
+template <class T>
+size_t stage_bytes(const dwos::Scene<T>& s, int D) {
+    return (size_t)s.n_stage_nodes * dwos::node_scalars(D) * sizeof(T) +
+           (s.stage_prims ? (size_t)s.n_prims * dwos::prim_scalars(D) * sizeof(T) : 0);
 }
 
 dwos::ParamCSR make_csr(dwos_ctx* c) {
@@ -168,13 +189,26 @@ dwos_status upload_geometry(dwos_ctx* c, const std::vector<double>& V, const std
     const int NS = dwos::node_scalars(D), PS = dwos::prim_scalars(D);
     const int64_t np = (int64_t)prims.size() / D, nv = (int64_t)V.size() / D;
     std::vector<T> nodes((size_t)hn.size() * NS, T(0));
+    std::vector<int32_t> ranges((size_t)hn.size() * 4);
     for (size_t i = 0; i < hn.size(); ++i) {
         T* p = &nodes[i * NS];
         for (int k = 0; k < D; ++k) {
             p[k] = T(hn[i].lo[0][k]); p[D + k] = T(hn[i].hi[0][k]);
             p[2 * D + k] = T(hn[i].lo[1][k]); p[3 * D + k] = T(hn[i].hi[1][k]);
         }
-        int32_t* r = reinterpret_cast<int32_t*>(p + 4 * D);
+        for (int c = 0; c < 2; ++c) {
+            T* sl = p + dwos::slab_offset(D) + c * (D + 2);
+            double scale = std::fabs(hn[i].o[c]);
+            for (int k = 0; k < D; ++k) {
+                sl[k] = T(hn[i].n[c][k]);
+                scale += std::max(std::fabs(hn[i].lo[c][k]), std::fabs(hn[i].hi[c][k]));
+            }
+            sl[D] = T(hn[i].o[c]);
+            sl[D + 1] = hn[i].t[c] < 0 ? T(hn[i].t[c]) : T(hn[i].t[c]) + dwos::slab_pad_host<T>(T(scale));
+            ranges[i * 4 + 2 * c] = hn[i].range[c][0];
+            ranges[i * 4 + 2 * c + 1] = hn[i].range[c][1];
+        }
+        int32_t* r = reinterpret_cast<int32_t*>(p + dwos::ref_offset(D));
         r[0] = hn[i].child[0];
         r[1] = hn[i].child[1];
     }
@@ -193,6 +227,7 @@ dwos_status upload_geometry(dwos_ctx* c, const std::vector<double>& V, const std
     for (size_t i = 0; i < gvert.size(); ++i) gv[i] = T(gvert[i]);
     hipStream_t s = c->stream;
     HIP_OK(upload(c->nodes, nodes.data(), nodes.size(), s));
+    HIP_OK(upload(c->node_ranges, ranges.data(), ranges.size(), s));
     HIP_OK(upload(c->prims, pr.data(), pr.size(), s));
     HIP_OK(upload(c->orig, origv.data(), origv.size(), s));
     HIP_OK(upload(c->leaf_of, leaf_of.data(), leaf_of.size(), s));
@@ -264,22 +299,31 @@ dwos_status ensure_totals(dwos_ctx* c) {
     return DWOS_OK;
 }
 
-// Launch the persistent walk kernel over `total` walks.
+// Launch the persistent walk kernel over `total` walks.  FP32 uses the
+// LDS-staged kernel (one large block per CU); the FP64 debug build keeps
+// everything in global memory.
 template <class T, int D, int MODE>
 dwos_status launch_walks(dwos_ctx* c, dwos::WalkArgs<T>& a) {
     hipStream_t s = c->stream;
     a.tot = c->totals.as<dwos::Counters>() + MODE;
     hipLaunchKernelGGL(dwos::fill_u64_kernel, dim3(1), dim3(64), 0, s, a.queue, (int64_t)1);
+    constexpr bool staged = sizeof(T) == 4;
+    constexpr int block = staged ? dwos::kBlockStaged : dwos::kBlock;
+    const size_t smem = staged ? stage_bytes<T>(a.s, D) : 0;
+    auto kern = dwos::walk_kernel<T, D, MODE, staged>;
+    if (smem > 0)
+        HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
     int per_cu = 0;
-    HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dwos::walk_kernel<T, D, MODE>, 256, 0));
+    HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, smem));
     per_cu = std::max(1, per_cu);
-    const int64_t need = (a.total + 255) / 256;
+    const int64_t need = (a.total + block - 1) / block;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)per_cu * c->cu_count));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_OK(hipEventCreate(&e0));
     HIP_OK(hipEventCreate(&e1));
     HIP_OK(hipEventRecord(e0, s));
-    hipLaunchKernelGGL((dwos::walk_kernel<T, D, MODE>), dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), smem, s, a);
     HIP_OK(hipGetLastError());
     HIP_OK(hipEventRecord(e1, s));
     c->pending.push_back({e0, e1, MODE});
@@ -450,6 +494,14 @@ dwos_status run_op(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
         a.n_inst = 1;
         a.total = walks;
         a.wid_offset = 0;
+        // every walk of a point starts with the same closest-point query
+        HIP_OK(c->first_leaf.reserve(Pc * sizeof(int32_t)));
+        HIP_OK(c->first_d2.reserve(Pc * sizeof(T)));
+        hipLaunchKernelGGL((dwos::first_query_kernel<T, D>), dim3(blocks_for(Pc, 64)), dim3(64), 0, s, scene, 0,
+                           o.X + p0 * D, Pc, c->first_leaf.as<int32_t>(), c->first_d2.as<T>());
+        a.first_leaf = c->first_leaf.as<int32_t>();
+        a.first_d2 = c->first_d2.as<T>();
+        a.x_base = p0;
         a.rec_steps = op == Op::Records ? c->rec_steps.as<int64_t>() : nullptr;
         // walk ids within a chunk restart at 0; the instance's p_counter = p0
         // keeps the Philox point word absolute
@@ -555,6 +607,9 @@ dwos_status dwos_create(int32_t dim, int32_t precision, void* stream, dwos_ctx**
     c->stream = static_cast<hipStream_t>(stream);
     c->device = dev;
     c->cu_count = prop.multiProcessorCount;
+    int smem = 0;
+    if (hipDeviceGetAttribute(&smem, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) smem = 65536;
+    c->max_smem = (size_t)smem;
     *out = c;
     return DWOS_OK;
 }
@@ -576,6 +631,7 @@ dwos_status dwos_set_boundary(dwos_ctx* c, const double* V, int64_t nv, const in
     HIP_OK(hipSetDevice(c->device));
     dwos::HostBVH bvh = dwos::build_bvh(V, prims, np, D);
     if (bvh.max_depth >= dwos::kMaxDepth) return fail(DWOS_EINVAL, "set_boundary: BVH too deep");
+    dwos::reorder_bfs(bvh);
     std::vector<double> Vv(V, V + nv * D);
     std::vector<int32_t> Pv(prims, prims + np * D);
     std::vector<int32_t> Lv(np, 0);
@@ -585,9 +641,6 @@ dwos_status dwos_set_boundary(dwos_ctx* c, const double* V, int64_t nv, const in
     rc = c->prec == DWOS_FP32 ? upload_geometry<float>(c, Vv, Pv, Lv, Gv, bvh.nodes, bvh.order)
                               : upload_geometry<double>(c, Vv, Pv, Lv, Gv, bvh.nodes, bvh.order);
     if (rc) return rc;
-    std::vector<int32_t> order;
-    dwos::refit_levels(bvh, order, c->refit_level_start);
-    HIP_OK(upload(c->refit_order, order.data(), order.size(), c->stream));
     c->instances.clear();
     c->has_boundary = true;
     c->has_params = false;   // Jacobian rows refer to the previous vertices
@@ -609,21 +662,15 @@ dwos_status dwos_update_vertices(dwos_ctx* c, const double* Vdev) {
                                Vdev, c->nv, c->verts.as<T>());
             hipLaunchKernelGGL((dwos::pack_prims_kernel<T, 2>), dim3(blocks_for(c->np, 256)), dim3(256), 0, s,
                                c->verts.as<T>(), c->pverts.as<int32_t>(), c->orig.as<int32_t>(), c->np, c->prims.as<T>());
-            for (size_t l = 0; l + 1 < c->refit_level_start.size(); ++l) {
-                const int32_t b = c->refit_level_start[l], e = c->refit_level_start[l + 1];
-                hipLaunchKernelGGL((dwos::refit_level_kernel<T, 2>), dim3(blocks_for(e - b, 256)), dim3(256), 0, s,
-                                   c->nodes.as<T>(), c->prims.as<T>(), c->refit_order.as<int32_t>(), b, e);
-            }
+            hipLaunchKernelGGL((dwos::refit_nodes_kernel<T, 2>), dim3(blocks_for(c->n_nodes, 4)), dim3(256), 0, s,
+                               c->nodes.as<T>(), c->prims.as<T>(), c->node_ranges.as<int32_t>(), c->n_nodes);
         } else {
             hipLaunchKernelGGL((dwos::pack_vertices_kernel<T, 3>), dim3(blocks_for(c->nv * 3, 256)), dim3(256), 0, s,
                                Vdev, c->nv, c->verts.as<T>());
             hipLaunchKernelGGL((dwos::pack_prims_kernel<T, 3>), dim3(blocks_for(c->np, 256)), dim3(256), 0, s,
                                c->verts.as<T>(), c->pverts.as<int32_t>(), c->orig.as<int32_t>(), c->np, c->prims.as<T>());
-            for (size_t l = 0; l + 1 < c->refit_level_start.size(); ++l) {
-                const int32_t b = c->refit_level_start[l], e = c->refit_level_start[l + 1];
-                hipLaunchKernelGGL((dwos::refit_level_kernel<T, 3>), dim3(blocks_for(e - b, 256)), dim3(256), 0, s,
-                                   c->nodes.as<T>(), c->prims.as<T>(), c->refit_order.as<int32_t>(), b, e);
-            }
+            hipLaunchKernelGGL((dwos::refit_nodes_kernel<T, 3>), dim3(blocks_for(c->n_nodes, 4)), dim3(256), 0, s,
+                               c->nodes.as<T>(), c->prims.as<T>(), c->node_ranges.as<int32_t>(), c->n_nodes);
         }
         HIP_OK(hipGetLastError());
         return DWOS_OK;

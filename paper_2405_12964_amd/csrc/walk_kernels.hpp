@@ -21,6 +21,18 @@
 
 namespace dwos {
 
+#ifndef DWOS_BLOCK
+#define DWOS_BLOCK 256
+#endif
+#ifndef DWOS_LDS_STACK
+#define DWOS_LDS_STACK 0
+#endif
+constexpr int kBlock = DWOS_BLOCK;          // threads per walk-kernel block
+#ifndef DWOS_BLOCK_STAGED
+#define DWOS_BLOCK_STAGED 1024
+#endif
+constexpr int kBlockStaged = DWOS_BLOCK_STAGED;  // block of the LDS-staged walk kernel
+constexpr bool kLdsStack = DWOS_LDS_STACK;  // traversal stack in LDS (else private memory)
 constexpr int kMaxLabels = 16;
 constexpr int kMaxGauss = 8;
 constexpr uint32_t kQueueChunk = 128;   // walk ids taken per wavefront refill
@@ -57,6 +69,9 @@ struct Scene {
     const int32_t* pverts;   // original primitive -> vertex ids, np x D
     const int32_t* label;    // original primitive -> label
     const T* gvert;          // per-vertex values of mapped labels
+    int32_t n_stage_nodes;   // nodes to stage in LDS (staged kernels)
+    int32_t stage_prims;     // 1: stage every primitive as well
+    int64_t n_prims;
 };
 
 struct Counters {   // device-side statistics (int64 atomics)
@@ -83,6 +98,11 @@ struct WalkArgs {
     T* rec_b;                // barycentrics b1 (2D) or b1,b2 (3D)
     T* rec_uoff;             // mean of the nested walks
     int64_t* rec_steps;      // optional per-walk query count
+    // closest primitive of every start point (all walks of a point share
+    // their first query), indexed by X row - x_base; null: query per walk
+    const int32_t* first_leaf;
+    const T* first_d2;
+    int64_t x_base;
 };
 
 // ---------------------------------------------------------------------------
@@ -192,82 +212,182 @@ __device__ __forceinline__ void load_prim(const T* prims, int32_t i, T* P) {
 template <class T, int D>
 struct NodeData {
     T lo0[D], hi0[D], lo1[D], hi1[D];
+    T n0[D], n1[D];
+    T o0, t0, o1, t1;
     int32_t c0, c1;
 };
+
+// decode a node from 16-byte words (FP32 layout of bvh.hpp)
+template <int D>
+__device__ __forceinline__ void decode_node_f32(const float4* q, NodeData<float, D>& nd) {
+    if constexpr (D == 2) {
+        const float4 a = q[0], b = q[1], c = q[2], d = q[3], e = q[4];
+        nd.lo0[0] = a.x; nd.lo0[1] = a.y; nd.hi0[0] = a.z; nd.hi0[1] = a.w;
+        nd.lo1[0] = b.x; nd.lo1[1] = b.y; nd.hi1[0] = b.z; nd.hi1[1] = b.w;
+        nd.n0[0] = c.x; nd.n0[1] = c.y; nd.o0 = c.z; nd.t0 = c.w;
+        nd.n1[0] = d.x; nd.n1[1] = d.y; nd.o1 = d.z; nd.t1 = d.w;
+        nd.c0 = __float_as_int(e.x); nd.c1 = __float_as_int(e.y);
+    } else {
+        const float4 a = q[0], b = q[1], c = q[2], d = q[3], e = q[4], f = q[5];
+        nd.lo0[0] = a.x; nd.lo0[1] = a.y; nd.lo0[2] = a.z; nd.hi0[0] = a.w;
+        nd.hi0[1] = b.x; nd.hi0[2] = b.y; nd.lo1[0] = b.z; nd.lo1[1] = b.w;
+        nd.lo1[2] = c.x; nd.hi1[0] = c.y; nd.hi1[1] = c.z; nd.hi1[2] = c.w;
+        nd.n0[0] = d.x; nd.n0[1] = d.y; nd.n0[2] = d.z; nd.o0 = d.w;
+        nd.t0 = e.x; nd.n1[0] = e.y; nd.n1[1] = e.z; nd.n1[2] = e.w;
+        nd.o1 = f.x; nd.t1 = f.y; nd.c0 = __float_as_int(f.z); nd.c1 = __float_as_int(f.w);
+    }
+}
 
 template <class T, int D>
 __device__ __forceinline__ void load_node(const T* nodes, int32_t i, NodeData<T, D>& nd) {
     const T* p = nodes + (size_t)i * node_scalars(D);
     if constexpr (sizeof(T) == 4) {
-        const float4* q = reinterpret_cast<const float4*>(p);
-        if constexpr (D == 2) {
-            const float4 a = q[0], b = q[1], c = q[2];
-            nd.lo0[0] = a.x; nd.lo0[1] = a.y; nd.hi0[0] = a.z; nd.hi0[1] = a.w;
-            nd.lo1[0] = b.x; nd.lo1[1] = b.y; nd.hi1[0] = b.z; nd.hi1[1] = b.w;
-            nd.c0 = __float_as_int(c.x); nd.c1 = __float_as_int(c.y);
-        } else {
-            const float4 a = q[0], b = q[1], c = q[2], d = q[3];
-            nd.lo0[0] = a.x; nd.lo0[1] = a.y; nd.lo0[2] = a.z; nd.hi0[0] = a.w;
-            nd.hi0[1] = b.x; nd.hi0[2] = b.y; nd.lo1[0] = b.z; nd.lo1[1] = b.w;
-            nd.lo1[2] = c.x; nd.hi1[0] = c.y; nd.hi1[1] = c.z; nd.hi1[2] = c.w;
-            nd.c0 = __float_as_int(d.x); nd.c1 = __float_as_int(d.y);
-        }
+        decode_node_f32<D>(reinterpret_cast<const float4*>(p), nd);
     } else {
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             nd.lo0[k] = p[k]; nd.hi0[k] = p[D + k]; nd.lo1[k] = p[2 * D + k]; nd.hi1[k] = p[3 * D + k];
+            nd.n0[k] = p[4 * D + k]; nd.n1[k] = p[5 * D + 2 + k];
         }
-        const int32_t* r = reinterpret_cast<const int32_t*>(p + 4 * D);
+        nd.o0 = p[5 * D]; nd.t0 = p[5 * D + 1]; nd.o1 = p[6 * D + 2]; nd.t1 = p[6 * D + 3];
+        const int32_t* r = reinterpret_cast<const int32_t*>(p + ref_offset(D));
         nd.c0 = r[0]; nd.c1 = r[1];
     }
 }
 
+template <class T>
+__device__ __forceinline__ T slab_pad(T scale) {
+    return T(16) * (sizeof(T) == 4 ? T(5.9604644775390625e-08) : T(1.1102230246251565e-16)) * scale;
+}
+
+// squared distance from x to the slab {y : |n.y - o| <= t}
+template <class T, int D>
+__device__ __forceinline__ T slab_d2(const T* n, T o, T t, const T* x) {
+    T pr = -o;
+#pragma unroll
+    for (int i = 0; i < D; ++i) pr += n[i] * x[i];
+    const T e = fmax(fabs(pr) - t, T(0));
+    return e * e;
+}
+
+// Dynamic LDS of the staged walk kernel: the first n_lnodes pair nodes, then
+// (optionally) every primitive, as 16-byte words.
+extern __shared__ float4 g_stage[];
+
+// Where a traversal reads nodes and primitives: LDS below the staged prefix,
+// global memory otherwise.  prim_off4 < 0: primitives stay in global memory.
+struct StageView {
+    int32_t n_lnodes;
+    int64_t prim_off4;
+};
+
+template <class T, int D>
+__device__ __forceinline__ void scene_node(const Scene<T>& s, const StageView& v, int32_t i,
+                                           NodeData<T, D>& nd) {
+    if constexpr (sizeof(T) == 4) {
+        if (i < v.n_lnodes) {
+            decode_node_f32<D>(g_stage + (int64_t)i * (node_scalars(D) / 4), nd);
+            return;
+        }
+    }
+    load_node<T, D>(s.nodes, i, nd);
+}
+
+template <class T, int D>
+__device__ __forceinline__ void scene_prim(const Scene<T>& s, const StageView& v, int32_t i, T* P) {
+    if constexpr (sizeof(T) == 4) {
+        if (v.prim_off4 >= 0) {
+            const float4* q = g_stage + v.prim_off4 + (int64_t)i * (prim_scalars(D) / 4);
+            if constexpr (D == 2) {
+                const float4 a = q[0];
+                P[0] = a.x; P[1] = a.y; P[2] = a.z; P[3] = a.w;
+            } else {
+                const float4 a = q[0], b = q[1], c = q[2];
+                P[0] = a.x; P[1] = a.y; P[2] = a.z; P[3] = a.w; P[4] = b.x; P[5] = b.y;
+                P[6] = b.z; P[7] = b.w; P[8] = c.x;
+            }
+            return;
+        }
+    }
+    load_prim<T, D>(s.prims, i, P);
+}
+
 struct QueryCount { unsigned int nodes, prims, overflow; };
+
+// Traversal stack of (node, squared box distance) entries: per-lane private
+// arrays, or a slice of LDS interleaved across the block's lanes.
+template <class T, bool LDS> struct TravStack;
+template <class T> struct TravStack<T, false> {
+    int32_t node[kStackSize];
+    T d[kStackSize];
+    __device__ __forceinline__ void put(int i, int32_t n, T v) { node[i] = n; d[i] = v; }
+    __device__ __forceinline__ int32_t get_node(int i) const { return node[i]; }
+    __device__ __forceinline__ T get_d(int i) const { return d[i]; }
+};
+template <class T> struct TravStack<T, true> {
+    int32_t* node;   // node[i * kBlock]
+    T* d;
+    __device__ __forceinline__ void put(int i, int32_t n, T v) { node[i * kBlock] = n; d[i * kBlock] = v; }
+    __device__ __forceinline__ int32_t get_node(int i) const { return node[i * kBlock]; }
+    __device__ __forceinline__ T get_d(int i) const { return d[i * kBlock]; }
+};
+
+#ifndef DWOS_TRAV
+#define DWOS_TRAV 2
+#endif
 
 // DistanceToBoundary: nearest primitive to x through the pair-node BVH.
 // Starts from the upper bound given by a previously closest primitive
 // (`warm`, leaf position, or -1) -- the new closest point can only be at
 // that distance or nearer, so the result is unchanged while most of the tree
 // is pruned.  Ties go to the lowest original primitive index.
-template <class T, int D>
-__device__ __forceinline__ int32_t closest_leaf(const Scene<T>& s, int32_t root, const T* x,
-                                                int32_t warm, T& best, QueryCount& qc) {
+//
+// Loop structure (the lanes of a wavefront run different queries):
+//   DWOS_TRAV 0: expand one node per iteration, testing hit leaves on the spot
+//   DWOS_TRAV 1: one unit per iteration (a primitive, a node, or a pop)
+//   DWOS_TRAV 2: alternate phases -- expand nodes until every lane holds a
+//                leaf or has finished, then test the held leaves together --
+//                so that node and primitive work are not interleaved within
+//                one iteration of the wavefront.
+template <class T, int D, class Stack>
+__device__ __forceinline__ int32_t closest_leaf(const Scene<T>& s, const StageView& sv, int32_t root,
+                                                const T* x, int32_t warm, T& best, QueryCount& qc,
+                                                Stack& st) {
     constexpr T slack = Slack<T>::v;
     best = T(INFINITY);
     int32_t bleaf = -1;
     if (warm >= 0) {
         T P[9], bb[3];
-        load_prim<T, D>(s.prims, warm, P);
+        scene_prim<T, D>(s, sv, warm, P);
         best = prim_closest<T, D>(P, x, bb);
         bleaf = warm;
     }
-    int32_t st_node[kStackSize];
-    T st_d[kStackSize];
-    int sp = 0;
-    int32_t node = root;
+    auto test_prim = [&](int32_t i) {
+        T P[9], bb[3];
+        scene_prim<T, D>(s, sv, i, P);
+        const T d2 = prim_closest<T, D>(P, x, bb);
+        qc.prims++;
+        if (d2 < best * (T(1) - TieBand<T>::v)) { best = d2; bleaf = i; }
+        else if (d2 <= best * (T(1) + TieBand<T>::v) && i != bleaf && s.orig[i] < s.orig[bleaf]) {
+            best = d2;
+            bleaf = i;
+        }
+    };
     auto test_leaf = [&](int32_t ref) {
         const int32_t v = -1 - ref;
         const int32_t start = v >> 3, n = (v & 7) + 1;
-        for (int32_t i = start; i < start + n; ++i) {
-            T P[9], bb[3];
-            load_prim<T, D>(s.prims, i, P);
-            const T d2 = prim_closest<T, D>(P, x, bb);
-            qc.prims++;
-            if (d2 < best * (T(1) - TieBand<T>::v)) { best = d2; bleaf = i; }
-            else if (d2 <= best * (T(1) + TieBand<T>::v) && i != bleaf && s.orig[i] < s.orig[bleaf]) {
-                best = d2;
-                bleaf = i;
-            }
-        }
+        for (int32_t i = start; i < start + n; ++i) test_prim(i);
     };
+    int sp = 0;
+#if DWOS_TRAV == 0
+    int32_t node = root;
     while (true) {
         NodeData<T, D> nd;
-        load_node<T, D>(s.nodes, node, nd);
+        scene_node<T, D>(s, sv, node, nd);
         qc.nodes++;
-        const T d0 = box_d2<T, D>(nd.lo0, nd.hi0, x);
-        const T d1 = box_d2<T, D>(nd.lo1, nd.hi1, x);
+        const T d0 = fmax(box_d2<T, D>(nd.lo0, nd.hi0, x), slab_d2<T, D>(nd.n0, nd.o0, nd.t0, x));
+        const T d1 = fmax(box_d2<T, D>(nd.lo1, nd.hi1, x), slab_d2<T, D>(nd.n1, nd.o1, nd.t1, x));
         bool h0 = d0 <= best * slack, h1 = d1 <= best * slack;
-        // leaves are tested on the spot, nearer first
         if (h0 && nd.c0 < 0 && h1 && nd.c1 < 0) {
             if (d0 <= d1) { test_leaf(nd.c0); if (d1 <= best * slack) test_leaf(nd.c1); }
             else { test_leaf(nd.c1); if (d0 <= best * slack) test_leaf(nd.c0); }
@@ -280,13 +400,8 @@ __device__ __forceinline__ int32_t closest_leaf(const Scene<T>& s, int32_t root,
         int32_t next = -1;
         if (h0 && h1) {
             const bool near0 = d0 <= d1;
-            if (sp < kStackSize) {
-                st_node[sp] = near0 ? nd.c1 : nd.c0;
-                st_d[sp] = near0 ? d1 : d0;
-                ++sp;
-            } else {
-                qc.overflow++;
-            }
+            if (sp < kStackSize) { st.put(sp, near0 ? nd.c1 : nd.c0, near0 ? d1 : d0); ++sp; }
+            else qc.overflow++;
             next = near0 ? nd.c0 : nd.c1;
         } else if (h0) {
             next = nd.c0;
@@ -296,12 +411,72 @@ __device__ __forceinline__ int32_t closest_leaf(const Scene<T>& s, int32_t root,
         if (next < 0) {
             while (sp > 0) {
                 --sp;
-                if (st_d[sp] <= best * slack) { next = st_node[sp]; break; }
+                if (st.get_d(sp) <= best * slack) { next = st.get_node(sp); break; }
             }
             if (next < 0) break;
         }
         node = next;
     }
+#else
+    int32_t node = root;         // internal node to expand next, or -1
+    int32_t leaf = 0;            // held leaf reference
+    bool has_leaf = false;
+    bool done = false;
+#pragma unroll 1
+    while (true) {
+#if DWOS_TRAV == 2
+        // phase 1: expand nodes until this lane holds a leaf or is finished
+#pragma unroll 1
+        while (!has_leaf && !done) {
+#else
+        if (has_leaf) {
+            test_leaf(leaf);
+            has_leaf = false;
+            continue;
+        }
+        if (done) break;
+        {
+#endif
+            int32_t cur = node;
+            if (cur < 0) {
+                if (sp == 0) { done = true; continue; }
+                --sp;
+                if (st.get_d(sp) > best * slack) continue;
+                cur = st.get_node(sp);
+                if (cur < 0) { leaf = cur; has_leaf = true; continue; }   // a postponed leaf
+            }
+            NodeData<T, D> nd;
+            scene_node<T, D>(s, sv, cur, nd);
+            qc.nodes++;
+            const T d0 = fmax(box_d2<T, D>(nd.lo0, nd.hi0, x), slab_d2<T, D>(nd.n0, nd.o0, nd.t0, x));
+            const T d1 = fmax(box_d2<T, D>(nd.lo1, nd.hi1, x), slab_d2<T, D>(nd.n1, nd.o1, nd.t1, x));
+            const T lim = best * slack;
+            const bool h0 = d0 <= lim, h1 = d1 <= lim;
+            const bool near0 = d0 <= d1;
+            int32_t next = -1;
+            if (h0 && h1) {
+                if (sp < kStackSize) { st.put(sp, near0 ? nd.c1 : nd.c0, near0 ? d1 : d0); ++sp; }
+                else qc.overflow++;
+                next = near0 ? nd.c0 : nd.c1;
+            } else if (h0) {
+                next = nd.c0;
+            } else if (h1) {
+                next = nd.c1;
+            }
+            node = -1;
+            if (next >= 0) node = next;
+            else if (h0 || h1) { leaf = next; has_leaf = true; }   // -1 is the leaf {0}
+        }
+#if DWOS_TRAV == 2
+        // phase 2: every lane holding a leaf tests it
+        if (has_leaf) {
+            test_leaf(leaf);
+            has_leaf = false;
+        }
+        if (done) break;
+#endif
+    }
+#endif
     return bleaf;
 }
 
@@ -392,9 +567,33 @@ __device__ __forceinline__ unsigned long long bcast64(unsigned long long v, int 
 //   MODE 1: Algorithm 2 (differential walks) with the joint u estimate and K
 //           nested forward walks from xbar - delta n at the terminal point
 // ---------------------------------------------------------------------------
-template <class T, int D, int MODE>
-__global__ void __launch_bounds__(256) walk_kernel(WalkArgs<T> a) {
+template <class T, int D, int MODE, bool STAGED>
+__global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(WalkArgs<T> a) {
     const int lane = threadIdx.x & 63;
+    TravStack<T, kLdsStack && !STAGED> stack;
+    if constexpr (kLdsStack && !STAGED) {
+        __shared__ int32_t s_node[kStackSize * kBlock];
+        __shared__ T s_d[kStackSize * kBlock];
+        stack.node = s_node + threadIdx.x;
+        stack.d = s_d + threadIdx.x;
+    }
+    StageView sv{0, -1};
+    if constexpr (STAGED) {
+        // copy the top BVH levels (and, if they fit, all primitives) into LDS
+        // once per persistent block; every later node or primitive fetch
+        // below the staged prefix is an LDS read
+        const int64_t nn4 = (int64_t)a.s.n_stage_nodes * node_scalars(D) * (int64_t)sizeof(T) / 16;
+        const float4* gn = reinterpret_cast<const float4*>(a.s.nodes);
+        for (int64_t i = threadIdx.x; i < nn4; i += blockDim.x) g_stage[i] = gn[i];
+        if (a.s.stage_prims) {
+            const int64_t np4 = a.s.n_prims * prim_scalars(D) * (int64_t)sizeof(T) / 16;
+            const float4* gp = reinterpret_cast<const float4*>(a.s.prims);
+            for (int64_t i = threadIdx.x; i < np4; i += blockDim.x) g_stage[nn4 + i] = gp[i];
+        }
+        __syncthreads();
+        sv.n_lnodes = a.s.n_stage_nodes;
+        sv.prim_off4 = a.s.stage_prims ? nn4 : -1;
+    }
     unsigned long long pool_next = 0, pool_end = 0;   // wave-uniform
     bool done = false;
     int64_t wid = -1;          // logical walk id (relative to wid_offset)
@@ -403,6 +602,7 @@ __global__ void __launch_bounds__(256) walk_kernel(WalkArgs<T> a) {
     T acc = T(0), u_main = T(0), usum = T(0);
     T kappa = T(0), eps = T(1), delta = T(1);
     uint32_t k = 0, m = 0, p = 0, inst_tag = 0;
+    int64_t first_row = 0;
     int32_t root = 0, warm = -1, term_leaf = -1, term_code = -1, phase = 0;
     T term_b1 = T(0), term_b2 = T(0);
     int64_t wsteps = 0;
@@ -455,6 +655,7 @@ __global__ void __launch_bounds__(256) walk_kernel(WalkArgs<T> a) {
                     kappa = in.kappa; eps = in.eps; delta = in.delta;
                     inst_tag = (uint32_t)ii << 16;
                     const double* xp = a.X + (size_t)(in.point_begin + pin) * D;
+                    first_row = in.point_begin + pin - a.x_base;
 #pragma unroll
                     for (int i = 0; i < D; ++i) x[i] = T(xp[i]);
                     acc = T(0); k = 0; warm = -1; phase = 0; usum = T(0); wsteps = 0;
@@ -467,9 +668,15 @@ __global__ void __launch_bounds__(256) walk_kernel(WalkArgs<T> a) {
 
         // ---- one walk step: closest-point query -----------------------------
         T d2;
-        QueryCount qc{0, 0, 0};
-        const int32_t leaf = closest_leaf<T, D>(a.s, root, x, warm, d2, qc);
-        c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;
+        int32_t leaf;
+        if (a.first_leaf && phase == 0 && k == 0) {
+            leaf = a.first_leaf[first_row];
+            d2 = a.first_d2[first_row];
+        } else {
+            QueryCount qc{0, 0, 0};
+            leaf = closest_leaf<T, D>(a.s, sv, root, x, warm, d2, qc, stack);
+            c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;
+        }
         c_steps++;
         wsteps++;
         if (leaf < 0 || !(d2 >= T(0))) {
@@ -492,7 +699,7 @@ __global__ void __launch_bounds__(256) walk_kernel(WalkArgs<T> a) {
             if (cap && !(d < eps)) c_trunc++;
             // closest point, barycentrics, boundary value
             T P[9], bary[3];
-            load_prim<T, D>(a.s.prims, leaf, P);
+            scene_prim<T, D>(a.s, sv, leaf, P);
             prim_closest<T, D>(P, x, bary);
             const int32_t orig = a.s.orig[leaf];
             T V[9];
