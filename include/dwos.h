@@ -200,6 +200,18 @@ dwos_status dwos_grad_sqloss(dwos_ctx* ctx, const double* X, int64_t P, const do
 dwos_status dwos_jvp(dwos_ctx* ctx, const double* X, int64_t P, int32_t W, uint64_t seed,
                      double* udot, double* udot_var, double* u_mean, dwos_stats* stats);
 
+/* Graph capture.  Every hot-path call (dwos_solve, dwos_grad,
+ * dwos_grad_sqloss, dwos_jvp, dwos_batch_solve, dwos_apply_parameters,
+ * dwos_update_vertices) enqueues only kernels when (a) an identical call has
+ * run before on the context, so workspaces and tables are in place, and (b)
+ * stats is NULL; it may then be captured into a hipGraph on the context
+ * stream.  Walk-kernel timing is skipped while the stream is capturing.
+ * seed_dev (device, one uint64, or NULL to disable) makes every later call
+ * use seed + *seed_dev, read on the device when the kernels run, so a
+ * captured graph replays with fresh random streams after the caller updates
+ * *seed_dev.  Errors: EINVAL on a NULL context. */
+dwos_status dwos_set_seed_buffer(dwos_ctx* ctx, const uint64_t* seed_dev);
+
 /* Per-walk records for walk-for-walk comparison.  mode 0: Algorithm 1,
  * mode 1: Algorithm 2.  u (device P*W) the walk's u estimate; steps (device
  * P*W int64 or NULL) its closest-point queries including nested walks;

@@ -53,7 +53,7 @@ def lib():
         L.oracle_poisson_scale.restype = C.c_double
         L.oracle_closest.argtypes = [sp, dp, dp]
         L.oracle_walk_records.argtypes = [sp, dp, C.c_int64, C.c_int32, C.c_uint64, C.c_int32,
-                                          C.c_int32, dp, dp, lp, ip, dp, lp, C.c_int]
+                                          C.c_int32, dp, dp, lp, ip, dp, lp, dp, C.c_int]
         L.oracle_solve.argtypes = [sp, dp, C.c_int64, C.c_int32, C.c_uint64, C.c_int32, dp, dp,
                                    lp, C.c_int]
         L.oracle_jvp.argtypes = [sp, dp, C.c_int64, C.c_int32, C.c_uint64, C.c_int32, dp, dp, dp,
@@ -161,14 +161,16 @@ class Oracle:
         steps = np.zeros(P * W, np.int64)
         prim = np.zeros(P * W, np.int32)
         uoff = np.zeros(P * W)
+        xbar = np.zeros(P * W * 3)
         tr = np.zeros(1, np.int64)
         rc = lib().oracle_walk_records(C.byref(self._s), _ptr(X, C.c_double), P, W, seed, mode,
                                        instance, _ptr(u, C.c_double), _ptr(udot, C.c_double),
                                        _ptr(steps, C.c_int64), _ptr(prim, C.c_int32),
-                                       _ptr(uoff, C.c_double), _ptr(tr, C.c_int64), self.threads)
+                                       _ptr(uoff, C.c_double), _ptr(tr, C.c_int64),
+                                       _ptr(xbar, C.c_double), self.threads)
         assert rc == 0
         out = dict(u=u.reshape(P, W), steps=steps.reshape(P, W), prim=prim.reshape(P, W),
-                   uoff=uoff.reshape(P, W), truncated=int(tr[0]))
+                   uoff=uoff.reshape(P, W), truncated=int(tr[0]), xbar=xbar.reshape(P, W, 3))
         if udot is not None:
             out["udot"] = udot.reshape(P, W, N)
         return out

@@ -389,6 +389,7 @@ struct DiffOut {
     double u = 0;          // joint estimate of u (sources + g at the terminal)
     bool terminal = false; // reached the shell (false: stopped by roulette)
     int prim = -1;
+    double xbar[3] = {0, 0, 0};   // terminal closest point
     double uoff = 0;       // mean of the K nested walks at the offset point
     int64_t nested_steps = 0;
     std::vector<double> udot;  // dense N-vector
@@ -433,6 +434,7 @@ DiffOut diff_walk_on_spheres(const Scene& sc, const double* x0, const Stream& st
             out.u = acc + gx;
             out.terminal = true;
             out.prim = h.prim;
+            for (int i = 0; i < 3; ++i) out.xbar[i] = h.xbar[i];
             out.uoff = uhat;
             if (want_udot) {
                 // velocity field at xbar for each parameter: V_j = sum_k b_k dv_{i_k}/dpi_j
@@ -544,10 +546,12 @@ int oracle_closest(const oracle_scene* s, const double* x, double* out) {
 // Per-walk records.  mode 0: Algorithm 1 from each point; mode 1: Algorithm 2.
 // u[P*W]; udot[P*W*N] (mode 1, may be NULL); steps[P*W] total closest-point
 // queries including nested walks (may be NULL); prim[P*W] terminal primitive or
-// -1 (may be NULL); uoff[P*W] nested mean (may be NULL).
+// -1 (may be NULL); uoff[P*W] nested mean (may be NULL); xbar[P*W*3] the
+// terminal closest point of a differential walk (may be NULL).
 int oracle_walk_records(const oracle_scene* s, const double* X, int64_t P, int32_t W,
                         uint64_t seed, int32_t mode, int32_t instance, double* u, double* udot,
-                        int64_t* steps, int32_t* prim, double* uoff, int64_t* truncated, int threads) {
+                        int64_t* steps, int32_t* prim, double* uoff, int64_t* truncated,
+                        double* xbar, int threads) {
     if (check_scene(s) || W < 1 || P < 0) return 1;
     Scene sc(*s);
     const int D = s->dim;
@@ -568,6 +572,7 @@ int oracle_walk_records(const oracle_scene* s, const double* X, int64_t P, int32
                 if (udot) std::memcpy(udot + id * s->N, o.udot.data(), sizeof(double) * s->N);
                 if (prim) prim[id] = o.terminal ? o.prim : -1;
                 if (uoff) uoff[id] = o.uoff;
+                if (xbar) for (int i = 0; i < 3; ++i) xbar[id * 3 + i] = o.xbar[i];
             }
             if (steps) steps[id] = c.steps;
             trunc[t] += c.truncated;

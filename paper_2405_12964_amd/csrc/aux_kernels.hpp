@@ -345,21 +345,29 @@ __global__ void closest_kernel(Scene<T> s, int32_t root, const double* X, int64_
     }
 }
 
-// closest primitive of each start point (shared first query of its walks)
+// closest primitive of each start point (shared first query of its walks);
+// row r of X is global point x_base + r, which lies in the instance whose
+// point range contains it
 template <class T, int D>
-__global__ void first_query_kernel(Scene<T> s, int32_t root, const double* X, int64_t P, int32_t* leaf_out,
-                                   T* d2_out) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
+__global__ void first_query_kernel(Scene<T> s, const Instance<T>* inst, int32_t n_inst, const double* X,
+                                   int64_t x_base, int64_t P, int32_t* leaf_out, T* d2_out) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= P) return;
+    const int64_t g = x_base + r;
+    int lo = 0, hi = n_inst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (inst[mid].point_begin <= g) lo = mid; else hi = mid - 1;
+    }
     const StageView sv{0, -1};
     T x[D];
 #pragma unroll
-    for (int c = 0; c < D; ++c) x[c] = T(X[p * D + c]);
+    for (int c = 0; c < D; ++c) x[c] = T(X[r * D + c]);
     T d2;
     QueryCount qc{0, 0, 0};
     TravStack<T, false> stack;
-    leaf_out[p] = closest_leaf<T, D>(s, sv, root, x, -1, d2, qc, stack);
-    d2_out[p] = d2;
+    leaf_out[r] = closest_leaf<T, D>(s, sv, inst[lo].root, x, -1, d2, qc, stack);
+    d2_out[r] = d2;
 }
 
 template <class T, int D>

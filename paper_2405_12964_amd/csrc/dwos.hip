@@ -63,8 +63,8 @@ hipError_t upload(DevBuf& b, const U* host, size_t n, hipStream_t s) {
 constexpr int64_t kMaxWalksPerChunk = int64_t(1) << 26;
 
 struct InstanceHost {
-    int32_t root;
-    int64_t nv_off, np_off;
+    int32_t root;            // root pair node in the combined node array
+    int64_t nv_off, np_off;  // first vertex / primitive of the instance
     double sigma, eps, delta;
 };
 
@@ -82,11 +82,14 @@ struct dwos_ctx {
     int64_t nv = 0, np = 0, n_nodes = 0;
     DevBuf nodes, prims, orig, verts, pverts, label, gvert, leaf_of;
     DevBuf node_ranges;   // leaf-order primitive range of each node's two children
-    std::vector<InstanceHost> instances;      // batch contexts
-    std::vector<double> hostV;                // batch: accumulated geometry
+    // batch contexts: instances accumulated on the host, uploaded together
+    std::vector<InstanceHost> instances;
+    std::vector<double> hostV, hostG;
     std::vector<int32_t> hostP, hostL;
     std::vector<dwos::HostNode> hostNodes;
     std::vector<int32_t> hostOrder;
+    bool batch_dirty = false;
+    std::vector<unsigned char> inst_host;     // last uploaded instance table
     // problem
     bool has_problem = false;
     dwos_problem prob{};
@@ -99,6 +102,7 @@ struct dwos_ctx {
     DevBuf rec_u, rec_prim, rec_b, rec_uoff, rec_steps, accA, accB, queue, counters, instbuf, walk_udot;
     DevBuf vtmp;   // V(pi) for dwos_apply_parameters
     DevBuf first_leaf, first_d2;   // shared first query of each start point
+    const uint64_t* seed_dev = nullptr;   // optional device seed offset
     // timing and cumulative counters per walk kind (0 forward, 1 differential)
     struct Pending { hipEvent_t e0, e1; int kind; };
     std::vector<Pending> pending;
@@ -147,7 +151,11 @@ dwos::Scene<T> make_scene(dwos_ctx* c) {
     const size_t nb = (size_t)dwos::node_scalars(c->D) * sizeof(T);
     const size_t pb = (size_t)dwos::prim_scalars(c->D) * sizeof(T);
     const size_t all_nodes = (size_t)c->n_nodes * nb, all_prims = (size_t)c->np * pb;
-    if (all_nodes + all_prims <= budget) {
+    if (!c->instances.empty()) {
+        // batches: every instance has its own tree, so no common prefix
+        s.n_stage_nodes = 0;
+        s.stage_prims = 0;
+    } else if (all_nodes + all_prims <= budget) {
         s.n_stage_nodes = (int32_t)c->n_nodes;
         s.stage_prims = 1;
     } else {
@@ -311,14 +319,32 @@ dwos_status launch_walks(dwos_ctx* c, dwos::WalkArgs<T>& a) {
     constexpr int block = staged ? dwos::kBlockStaged : dwos::kBlock;
     const size_t smem = staged ? stage_bytes<T>(a.s, D) : 0;
     auto kern = dwos::walk_kernel<T, D, MODE, staged>;
-    if (smem > 0)
+    // launch attributes and occupancy are computed once per kernel and LDS
+    // size (no runtime queries on later, possibly captured, calls)
+    static size_t attr_smem = 0;
+    static size_t occ_smem = ~size_t(0);
+    static int occ_per_cu = 1;
+    if (smem > attr_smem) {
         HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-    int per_cu = 0;
-    HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, smem));
-    per_cu = std::max(1, per_cu);
+        attr_smem = smem;
+    }
+    if (occ_smem != smem) {
+        int per = 0;
+        HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, block, smem));
+        occ_per_cu = std::max(1, per);
+        occ_smem = smem;
+    }
+    const int per_cu = occ_per_cu;
     const int64_t need = (a.total + block - 1) / block;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)per_cu * c->cu_count));
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_OK(hipStreamIsCapturing(s, &cap));
+    if (cap != hipStreamCaptureStatusNone) {   // captured launches are not timed
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), smem, s, a);
+        HIP_OK(hipGetLastError());
+        return DWOS_OK;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_OK(hipEventCreate(&e0));
     HIP_OK(hipEventCreate(&e1));
@@ -357,6 +383,7 @@ dwos::WalkArgs<T> base_args(dwos_ctx* c, const double* X, int32_t W, uint64_t se
     a.W = W;
     a.key0 = (uint32_t)seed;
     a.key1 = (uint32_t)(seed >> 32);
+    a.seed_ptr = reinterpret_cast<const unsigned long long*>(c->seed_dev);
     a.queue = c->queue.as<unsigned long long>();
     a.cnt = c->counters.as<dwos::Counters>();
     a.tot = c->totals.as<dwos::Counters>();
@@ -366,6 +393,26 @@ dwos::WalkArgs<T> base_args(dwos_ctx* c, const double* X, int32_t W, uint64_t se
     a.rec_uoff = c->rec_uoff.as<T>();
     a.rec_steps = nullptr;
     return a;
+}
+
+// Upload an instance table (skipped when identical to the last one).  The
+// host copy lives in the context, so the asynchronous copy needs no sync.
+template <class T>
+dwos_status upload_instances(dwos_ctx* c, const dwos::Instance<T>* in, size_t n) {
+    const size_t bytes = n * sizeof(dwos::Instance<T>);
+    const unsigned char* src = reinterpret_cast<const unsigned char*>(in);
+    if (c->inst_host.size() == bytes && std::memcmp(c->inst_host.data(), src, bytes) == 0 &&
+        c->instbuf.bytes >= bytes)
+        return DWOS_OK;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_OK(hipStreamIsCapturing(c->stream, &cap));
+    if (cap != hipStreamCaptureStatusNone)
+        return fail(DWOS_ESTATE, "instance table changed during graph capture: run the call once before capturing");
+    HIP_OK(hipStreamSynchronize(c->stream));   // the previous table may still be in use
+    c->inst_host.assign(src, src + bytes);
+    HIP_OK(c->instbuf.reserve(bytes));
+    HIP_OK(hipMemcpyAsync(c->instbuf.ptr, c->inst_host.data(), bytes, hipMemcpyHostToDevice, c->stream));
+    return DWOS_OK;
 }
 
 // single-instance table for points [p0, p0 + P) of a chunk
@@ -381,10 +428,7 @@ dwos_status set_single_instance(dwos_ctx* c, int64_t p0, int64_t P, int32_t W) {
     in.kappa = T(std::sqrt(sg));
     in.eps = T(c->prob.eps);
     in.delta = T(c->prob.delta);
-    HIP_OK(c->instbuf.reserve(sizeof(in)));
-    HIP_OK(hipMemcpyAsync(c->instbuf.ptr, &in, sizeof(in), hipMemcpyHostToDevice, c->stream));
-    HIP_OK(hipStreamSynchronize(c->stream));
-    return DWOS_OK;
+    return upload_instances(c, &in, 1);
 }
 
 dwos_status begin_call(dwos_ctx* c, bool need_params) {
@@ -497,8 +541,9 @@ dwos_status run_op(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
         // every walk of a point starts with the same closest-point query
         HIP_OK(c->first_leaf.reserve(Pc * sizeof(int32_t)));
         HIP_OK(c->first_d2.reserve(Pc * sizeof(T)));
-        hipLaunchKernelGGL((dwos::first_query_kernel<T, D>), dim3(blocks_for(Pc, 64)), dim3(64), 0, s, scene, 0,
-                           o.X + p0 * D, Pc, c->first_leaf.as<int32_t>(), c->first_d2.as<T>());
+        hipLaunchKernelGGL((dwos::first_query_kernel<T, D>), dim3(blocks_for(Pc, 64)), dim3(64), 0, s, scene,
+                           c->instbuf.as<dwos::Instance<T>>(), 1, o.X + p0 * D, p0, Pc,
+                           c->first_leaf.as<int32_t>(), c->first_d2.as<T>());
         a.first_leaf = c->first_leaf.as<int32_t>();
         a.first_d2 = c->first_d2.as<T>();
         a.x_base = p0;
@@ -626,6 +671,7 @@ dwos_status dwos_set_boundary(dwos_ctx* c, const double* V, int64_t nv, const in
                               const int32_t* label, const double* gvert) {
     if (!c) return fail(DWOS_EINVAL, "NULL context");
     const int D = c->D;
+    if (!c->instances.empty()) return fail(DWOS_ESTATE, "set_boundary: context is a batch context");
     dwos_status rc = check_geometry(D, V, nv, prims, np, label, DWOS_MAX_LABELS);
     if (rc) return rc;
     HIP_OK(hipSetDevice(c->device));
@@ -641,7 +687,6 @@ dwos_status dwos_set_boundary(dwos_ctx* c, const double* V, int64_t nv, const in
     rc = c->prec == DWOS_FP32 ? upload_geometry<float>(c, Vv, Pv, Lv, Gv, bvh.nodes, bvh.order)
                               : upload_geometry<double>(c, Vv, Pv, Lv, Gv, bvh.nodes, bvh.order);
     if (rc) return rc;
-    c->instances.clear();
     c->has_boundary = true;
     c->has_params = false;   // Jacobian rows refer to the previous vertices
     return DWOS_OK;
@@ -921,6 +966,12 @@ dwos_status dwos_eval_ball_kernels(dwos_ctx* c, const double* r, const double* R
     return DWOS_OK;
 }
 
+dwos_status dwos_set_seed_buffer(dwos_ctx* c, const uint64_t* seed_dev) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    c->seed_dev = seed_dev;
+    return DWOS_OK;
+}
+
 dwos_status dwos_walk_timing(dwos_ctx* c, int32_t kind, int32_t reset, double* walk_ms, int64_t* launches,
                              dwos_stats* totals) {
     if (!c) return fail(DWOS_EINVAL, "NULL context");
@@ -959,14 +1010,131 @@ dwos_status dwos_walk_timing(dwos_ctx* c, int32_t kind, int32_t reset, double* w
 
 dwos_status dwos_batch_add_instance(dwos_ctx* c, const double* V, int64_t nv, const int32_t* prims, int64_t np,
                                     const int32_t* label, double sigma, double eps, double delta, int32_t* index) {
-    (void)c; (void)V; (void)nv; (void)prims; (void)np; (void)label; (void)sigma; (void)eps; (void)delta; (void)index;
-    return fail(DWOS_EINVAL, "batch: not available yet");
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    const int D = c->D;
+    dwos_status rc = check_geometry(D, V, nv, prims, np, label, DWOS_MAX_LABELS);
+    if (rc) return rc;
+    if (!(sigma >= 0) || !std::isfinite(sigma) || !(eps > 0) || !(delta > 0) || !std::isfinite(eps) ||
+        !std::isfinite(delta))
+        return fail(DWOS_EINVAL, "batch_add_instance: need sigma >= 0, eps > 0, delta > 0");
+    if (c->has_boundary && c->instances.empty())
+        return fail(DWOS_ESTATE, "batch_add_instance: context already holds a single boundary");
+    if (c->instances.size() >= 65535) return fail(DWOS_EINVAL, "batch_add_instance: too many instances");
+    const int64_t nv_off = (int64_t)c->hostV.size() / D, np_off = (int64_t)c->hostOrder.size();
+    if (nv_off + nv > INT32_MAX || (np_off + np) > (int64_t(1) << 27))
+        return fail(DWOS_EINVAL, "batch_add_instance: batch too large");
+    dwos::HostBVH bvh = dwos::build_bvh(V, prims, np, D);
+    if (bvh.max_depth >= dwos::kMaxDepth) return fail(DWOS_EINVAL, "batch_add_instance: BVH too deep");
+    dwos::reorder_bfs(bvh);
+    const int32_t node_off = (int32_t)c->hostNodes.size();
+    for (auto nd : bvh.nodes) {
+        for (int k = 0; k < 2; ++k) {
+            if (nd.child[k] >= 0) {
+                nd.child[k] += node_off;
+            } else {
+                const int32_t v = -1 - nd.child[k];
+                nd.child[k] = dwos::leaf_ref((v >> 3) + (int32_t)np_off, (v & 7) + 1);
+            }
+            nd.range[k][0] += (int32_t)np_off;
+            nd.range[k][1] += (int32_t)np_off;
+        }
+        c->hostNodes.push_back(nd);
+    }
+    for (int64_t i = 0; i < np; ++i) c->hostOrder.push_back(bvh.order[i] + (int32_t)np_off);
+    for (int64_t i = 0; i < np * D; ++i) c->hostP.push_back(prims[i] + (int32_t)nv_off);
+    for (int64_t i = 0; i < np; ++i) c->hostL.push_back(label ? label[i] : 0);
+    c->hostV.insert(c->hostV.end(), V, V + nv * D);
+    c->hostG.resize(c->hostV.size() / D, 0.0);
+    c->instances.push_back({node_off, nv_off, np_off, sigma, eps, delta});
+    c->batch_dirty = true;
+    c->has_params = false;
+    if (index) *index = (int32_t)c->instances.size() - 1;
+    return DWOS_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+template <class T, int D>
+dwos_status run_batch(dwos_ctx* c, const double* X, const int64_t* P, int32_t W, uint64_t seed, double* u_mean,
+                      double* u_var, dwos_stats* st) {
+    hipStream_t s = c->stream;
+    const int n = (int)c->instances.size();
+    std::vector<dwos::Instance<T>> tab(n);
+    int64_t walks = 0, pts = 0;
+    for (int i = 0; i < n; ++i) {
+        tab[i].walk_begin = walks;
+        tab[i].point_begin = pts;
+        tab[i].p_counter = 0;
+        tab[i].root = c->instances[i].root;
+        tab[i].P = (int32_t)P[i];
+        tab[i].kappa = T(std::sqrt(c->instances[i].sigma));
+        tab[i].eps = T(c->instances[i].eps);
+        tab[i].delta = T(c->instances[i].delta);
+        walks += P[i] * W;
+        pts += P[i];
+    }
+    if (walks > (int64_t(1) << 28)) return fail(DWOS_ENOMEM, "batch_solve: more than 2^28 walks in one batch");
+    dwos_status rc = ensure_records<T>(c, std::max<int64_t>(1, walks), false, false);
+    if (rc) return rc;
+    rc = upload_instances<T>(c, tab.data(), tab.size());
+    if (rc) return rc;
+    const size_t ev_from = c->pending.size();
+    const dwos::Scene<T> scene = make_scene<T>(c);
+    HIP_OK(c->first_leaf.reserve(std::max<int64_t>(1, pts) * sizeof(int32_t)));
+    HIP_OK(c->first_d2.reserve(std::max<int64_t>(1, pts) * sizeof(T)));
+    hipLaunchKernelGGL((dwos::first_query_kernel<T, D>), dim3(blocks_for(pts, 64)), dim3(64), 0, s, scene,
+                       c->instbuf.as<dwos::Instance<T>>(), n, X, (int64_t)0, pts, c->first_leaf.as<int32_t>(),
+                       c->first_d2.as<T>());
+    dwos::WalkArgs<T> a = base_args<T>(c, X, W, seed);
+    a.inst = c->instbuf.as<dwos::Instance<T>>();
+    a.n_inst = n;
+    a.total = walks;
+    a.wid_offset = 0;
+    a.first_leaf = c->first_leaf.as<int32_t>();
+    a.first_d2 = c->first_d2.as<T>();
+    a.x_base = 0;
+    rc = launch_walks<T, D, 0>(c, a);
+    if (rc) return rc;
+    hipLaunchKernelGGL(dwos::point_stats_kernel<T>, dim3(blocks_for(pts, 4)), dim3(256), 0, s, c->rec_u.as<T>(),
+                       pts, W, u_mean, u_var);
+    return finish_call(c, st, ev_from);
+}
+
+}  // namespace
+
+extern "C" {
 
 dwos_status dwos_batch_solve(dwos_ctx* c, const double* X_all, const int64_t* P, int32_t W, uint64_t seed,
                              double* u_mean, double* u_var, dwos_stats* stats) {
-    (void)c; (void)X_all; (void)P; (void)W; (void)seed; (void)u_mean; (void)u_var; (void)stats;
-    return fail(DWOS_EINVAL, "batch: not available yet");
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (c->instances.empty()) return fail(DWOS_ESTATE, "batch_solve: no instances");
+    if (!c->has_problem) return fail(DWOS_ESTATE, "batch_solve: no problem: call dwos_set_problem first");
+    if (!P || W < 1) return fail(DWOS_EINVAL, "batch_solve: bad P or W");
+    int64_t pts = 0;
+    for (size_t i = 0; i < c->instances.size(); ++i) {
+        if (P[i] < 0 || P[i] > INT32_MAX) return fail(DWOS_EINVAL, "batch_solve: bad point count");
+        pts += P[i];
+    }
+    if (pts > 0 && (!X_all || !u_mean)) return fail(DWOS_EINVAL, "batch_solve: NULL points or output");
+    HIP_OK(hipSetDevice(c->device));
+    if (c->batch_dirty) {
+        dwos_status rc = c->prec == DWOS_FP32
+            ? upload_geometry<float>(c, c->hostV, c->hostP, c->hostL, c->hostG, c->hostNodes, c->hostOrder)
+            : upload_geometry<double>(c, c->hostV, c->hostP, c->hostL, c->hostG, c->hostNodes, c->hostOrder);
+        if (rc) return rc;
+        c->batch_dirty = false;
+        c->has_boundary = true;
+    }
+    dwos_status rc = begin_call(c, false);
+    if (rc) return rc;
+    if (pts == 0) return finish_call(c, stats, c->pending.size());
+    if (c->prec == DWOS_FP32)
+        return c->D == 2 ? run_batch<float, 2>(c, X_all, P, W, seed, u_mean, u_var, stats)
+                         : run_batch<float, 3>(c, X_all, P, W, seed, u_mean, u_var, stats);
+    return c->D == 2 ? run_batch<double, 2>(c, X_all, P, W, seed, u_mean, u_var, stats)
+                     : run_batch<double, 3>(c, X_all, P, W, seed, u_mean, u_var, stats);
 }
 
 }  // extern "C"

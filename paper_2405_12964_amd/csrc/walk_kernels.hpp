@@ -89,6 +89,7 @@ struct WalkArgs {
     int64_t total;           // walks in this launch
     int64_t wid_offset;      // logical id of walk 0 of this launch
     uint32_t key0, key1;
+    const unsigned long long* seed_ptr;   // if set, the key is seed + *seed_ptr
     unsigned long long* queue;
     Counters* cnt;           // this call
     Counters* tot;           // cumulative for this walk kind
@@ -594,6 +595,12 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
         sv.n_lnodes = a.s.n_stage_nodes;
         sv.prim_off4 = a.s.stage_prims ? nn4 : -1;
     }
+    uint32_t key0 = a.key0, key1 = a.key1;
+    if (a.seed_ptr) {
+        const unsigned long long sd = *a.seed_ptr + (((unsigned long long)a.key1 << 32) | a.key0);
+        key0 = (uint32_t)sd;
+        key1 = (uint32_t)(sd >> 32);
+    }
     unsigned long long pool_next = 0, pool_end = 0;   // wave-uniform
     bool done = false;
     int64_t wid = -1;          // logical walk id (relative to wid_offset)
@@ -745,9 +752,9 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
             result = acc + g;
         } else {
             const uint32_t tag = inst_tag | (nested ? (1u | ((uint32_t)(phase - 1) << 8)) : 0u);
-            const u4 r = philox10(u4{k, m, p, tag}, a.key0, a.key1);
+            const u4 r = philox10(u4{k, m, p, tag}, key0, key1);
             if (a.prm.has_source) {
-                const u4 r2 = philox10(u4{k, m, p, tag | 2u}, a.key0, a.key1);
+                const u4 r2 = philox10(u4{k, m, p, tag | 2u}, key0, key1);
                 T dir[3];
                 unit_dir<T, D>(r2.x, r2.y, dir);
                 T rho;

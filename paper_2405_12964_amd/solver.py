@@ -217,6 +217,36 @@ class Solver:
                                           _dev(GB), _dev(al)))
         return GB, al
 
+    # ---- batched instances ------------------------------------------------
+    def batch_add_instance(self, V, prims, label, sigma, eps, delta) -> int:
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        prims = np.ascontiguousarray(prims, dtype=np.int32)
+        lab = None if label is None else np.ascontiguousarray(label, dtype=np.int32)
+        idx = C.c_int32()
+        check(capi.dwos_batch_add_instance(self._ctx, _dp(V), V.shape[0], _ip(prims), prims.shape[0],
+                                           _ip(lab) if lab is not None else None, float(sigma),
+                                           float(eps), float(delta), C.byref(idx)))
+        return idx.value
+
+    def batch_solve(self, X_all, P, W, seed, var=True, stats=False):
+        X_all = self._X(X_all)
+        Pn = np.ascontiguousarray(P, dtype=np.int64)
+        tot = int(Pn.sum())
+        if tot != X_all.shape[0]:
+            raise ValueError("sum of P must equal the number of points")
+        m = torch.empty(tot, dtype=torch.float64, device=X_all.device)
+        v = torch.empty(tot, dtype=torch.float64, device=X_all.device) if var else None
+        st = capi.dwos_stats() if stats else None
+        check(capi.dwos_batch_solve(self._ctx, _dev(X_all), _lp(Pn), int(W), int(seed), _dev(m), _dev(v),
+                                    C.byref(st) if st is not None else None))
+        return (m, v, st.as_dict()) if stats else (m, v)
+
+    def set_seed_buffer(self, seed_dev: Optional[torch.Tensor]):
+        """Use seed + seed_dev[0] (a 1-element int64 GPU tensor) in every later
+        call, so that a captured graph replays with fresh streams."""
+        self._seed_buf = seed_dev
+        check(capi.dwos_set_seed_buffer(self._ctx, _dev(seed_dev, torch.int64) if seed_dev is not None else None))
+
     def walk_timing(self, kind: int, reset=False):
         """(ms, launches, totals dict) of the walk kernels of one kind
         (0 forward, 1 differential) since the last reset."""

@@ -266,3 +266,89 @@ def test_autograd_function_matches_oracle_gradient(dev, dwos, oracle_mod):
     w = om - uref.cpu().numpy()
     og, _, _ = o.grad(X, w, 64, 42)
     assert np.allclose(pi.grad.cpu().numpy(), og, atol=1e-9)
+
+
+# ------------------------------------------------------- batched instances --
+
+def _batch(dwos, prec, insts, K=1):
+    s = dwos.Solver(3, prec)
+    sc0 = insts[0][0]
+    s.set_problem(dwos.make_problem(0.0, 1e-3, 1e-2, K, sc0.kmax, 1, 0.0, None, sc0.bc, 3))
+    for sc, _ in insts:
+        s.batch_add_instance(sc.V, sc.prims, sc.label, sc.sigma, sc.eps, sc.delta)
+    return s
+
+
+def test_batch_walk_for_walk_fp64(dev, dwos, oracle_mod):
+    """Instances of different size and screening in one launch: every walk of
+    instance i equals the oracle's walk with the instance index in its stream."""
+    insts = []
+    for i, (nu, sigma) in enumerate([(3, 0.0), (5, 7.0), (2, 19.0), (4, 3.0)]):
+        sc = scenes.c3_icosphere(nu=nu, n_basis=32, h=0.5, coef_seed=10 + i, sigma=sigma)
+        insts.append((sc, scenes.points_on_box_faces(5 + 3 * i, 20 + i)))
+    s = _batch(dwos, "fp64", insts)
+    X = np.concatenate([x for _, x in insts])
+    P = [len(x) for _, x in insts]
+    W = 8
+    m, v = s.batch_solve(T(X, dev), P, W, 77)
+    m = m.cpu().numpy()
+    off = 0
+    for i, (sc, x) in enumerate(insts):
+        rec = oracle_mod.Oracle(sc).walk_records(x, W, 77, mode=0, instance=i)
+        assert np.allclose(m[off:off + len(x)], rec["u"].mean(1), atol=1e-10), i
+        off += len(x)
+
+
+def test_batch_fp32_parity(dev, dwos, oracle_mod):
+    insts = []
+    for i, (nu, sigma) in enumerate([(6, 2.0), (10, 12.0), (4, 0.5)]):
+        sc = scenes.c3_icosphere(nu=nu, n_basis=64, h=0.4, coef_seed=30 + i, sigma=sigma)
+        insts.append((sc, scenes.points_on_box_faces(24, 40 + i)))
+    s = _batch(dwos, "fp32", insts)
+    X = np.concatenate([x for _, x in insts])
+    m, v = s.batch_solve(T(X, dev), [len(x) for _, x in insts], 512, 5)
+    m, v = m.cpu().numpy(), v.cpu().numpy()
+    om = np.concatenate([oracle_mod.Oracle(sc).solve(x, 512, 900 + i, instance=i)[0] for i, (sc, x) in enumerate(insts)])
+    ov = np.concatenate([oracle_mod.Oracle(sc).solve(x, 512, 900 + i, instance=i)[1] for i, (sc, x) in enumerate(insts)])
+    parity(m, _se(v), om, _se(ov), name="batch solve")
+
+
+# ------------------------------------------------------------ graph capture --
+
+def test_graph_capture_replays_match_eager(dev, dwos):
+    """Forward and reverse-mode calls captured in one hipGraph (through torch's
+    graph capture on the context stream) and replayed with a new device seed
+    each time: every replay equals the eager call with the same seed (the
+    gradient to FP64 atomic-summation order), with eager work and
+    synchronisations between replays."""
+    sc = star_small(512)
+    X = scenes.star_points(64, 11)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        s = dwos.Solver.from_scene(sc, "fp32", stream=stream)
+        Xt = T(X, dev)
+        w = torch.linspace(-1, 1, 64, dtype=torch.float64, device=dev)
+        seed_buf = torch.zeros(1, dtype=torch.int64, device=dev)
+        s.set_seed_buffer(seed_buf)
+        s.solve(Xt, 256, 5)
+        s.grad(Xt, w, 256, 6)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        mg, vg = s.solve(Xt, 256, 5)
+        gg, ug = s.grad(Xt, w, 256, 6)
+    outs = []
+    for r in range(4):
+        with torch.cuda.stream(stream):
+            seed_buf.fill_(1000 + r)
+            g.replay()
+            me, ve = s.solve(Xt, 256, 5)
+            ge, ue = s.grad(Xt, w, 256, 6)
+        torch.cuda.synchronize()
+        assert torch.equal(mg, me) and torch.equal(vg, ve), r
+        # the reverse-mode scatter sums with FP64 atomics, whose order varies
+        assert torch.allclose(gg, ge, rtol=1e-12, atol=1e-14) and torch.equal(ug, ue), r
+        outs.append(mg.clone())
+        _ = torch.randn(1000, device=dev).sum().item()   # unrelated eager work between replays
+    assert not torch.equal(outs[0], outs[1])                # new streams per replay
+    s.set_seed_buffer(None)

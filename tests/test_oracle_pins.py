@@ -217,11 +217,68 @@ def test_shape_derivative_ball(oracle_mod):
 
 def test_restricted_harmonic_field_has_zero_shape_derivative(oracle_mod):
     """Restricted harmonic data: u = g everywhere, so du/dR = 0; the estimator's
-    dg/dn - du/dn cancels up to the offset bias (delta/2) d2g/dn2."""
-    sc = scenes.c1_polygon(128, eps=1e-4, delta=1e-3)
+    dg/dn - du/dn cancels up to the offset bias (delta/2) d2g/dn2 V_n.  A
+    missing or halved dg/dn term leaves -dg/dn V_n ~ O(1) instead."""
+    sc = scenes.c1_polygon(128, eps=1e-3, delta=1e-2)
     X = scenes.points_in_disk(32, 0.9, 41)
-    jm, jv, _, _ = oracle_mod.Oracle(sc).jvp(X, 2048, 12)
-    check_vs_exact(jm[:, 0], _se(jv[:, 0]), np.zeros(len(X)), 2e-3, "P6 restricted")
+    jm, jv, _, _ = oracle_mod.Oracle(sc).jvp(X, 4096, 12)
+    check_vs_exact(jm[:, 0], _se(jv[:, 0]), np.zeros(len(X)), 0.015, "P6 restricted")
+
+
+def _rotation_params(sc):
+    """Replace the parameter by a rigid rotation angle: dv_i/dphi = (-y_i, x_i)."""
+    V = sc.V
+    return sc.with_(N=1, rowptr=np.arange(sc.nv + 1, dtype=np.int64),
+                    pid=np.zeros(sc.nv, np.int32), vel=np.stack([-V[:, 1], V[:, 0]], 1))
+
+
+def test_rotation_derivative_mapped_and_restricted(oracle_mod):
+    """Rotating the boundary by phi: with mapped data the values ride along, so
+    u(x; phi) = U(R(-phi) x) and du/dphi = grad u . (y, -x) = 4xy for
+    u ~ x^2 - y^2; the velocity is tangential, which exercises the surface
+    gradient term of the mapped boundary derivative.  With restricted data
+    the field stays put and the (circular) domain does not change: du/dphi = 0."""
+    X = scenes.points_in_disk(32, 0.8, 43)
+    sc = _rotation_params(scenes.c1_polygon(128, mapped=True, eps=1e-3, delta=1e-2))
+    jm, jv, _, _ = oracle_mod.Oracle(sc).jvp(X, 2048, 14)
+    check_vs_exact(jm[:, 0], _se(jv[:, 0]), 4 * X[:, 0] * X[:, 1], 4e-3, "rotation mapped")
+    sc = _rotation_params(scenes.c1_polygon(128, eps=1e-3, delta=1e-2))
+    jm, jv, _, _ = oracle_mod.Oracle(sc).jvp(X, 2048, 15)
+    check_vs_exact(jm[:, 0], _se(jv[:, 0]), np.zeros(len(X)), 0.015, "rotation restricted")
+
+
+def test_derivative_splits_by_barycentrics(oracle_mod):
+    """Explicit surface (Sec. 3.1.2): the velocity at a terminal point is the
+    barycentric blend of its primitive's vertex velocities, so with one radial
+    parameter per vertex the two vertices of the terminal edge receive udot in
+    the ratio b0 (n.u0) : b1 (n.u1), with b the position of the terminal point
+    along the edge (computed here from the geometry)."""
+    sc = scenes.c1_polygon(12, g="one", eps=1e-3, delta=1e-2, sigma=2.0)
+    n = sc.nv
+    U = sc.V / np.linalg.norm(sc.V, axis=1, keepdims=True)
+    sc = sc.with_(N=n, rowptr=np.arange(n + 1, dtype=np.int64), pid=np.arange(n, dtype=np.int32), vel=U)
+    X = scenes.points_in_disk(8, 0.7, 44)
+    rec = oracle_mod.Oracle(sc).walk_records(X, 64, 16, mode=1)
+    checked = 0
+    for p in range(len(X)):
+        for m in range(64):
+            pr = rec["prim"][p, m]
+            if pr < 0:
+                continue
+            i0, i1 = sc.prims[pr]
+            a, b = sc.V[i0], sc.V[i1]
+            xb = rec["xbar"][p, m, :2]
+            b1 = np.dot(xb - a, b - a) / np.dot(b - a, b - a)
+            t = (b - a) / np.linalg.norm(b - a)
+            nrm = np.array([t[1], -t[0]])
+            ud = rec["udot"][p, m]
+            others = np.delete(ud, [i0, i1])
+            assert np.all(others == 0.0)
+            w0, w1 = (1 - b1) * np.dot(nrm, U[i0]), b1 * np.dot(nrm, U[i1])
+            # ud[i0] * w1 == ud[i1] * w0, in a form that is safe near the vertices
+            assert abs(ud[i0] * w1 - ud[i1] * w0) <= 1e-9 * (abs(ud[i0]) + abs(ud[i1]) + 1e-300)
+            checked += 1
+    assert checked > 100
 
 
 def test_mapped_data_shape_derivative(oracle_mod):
