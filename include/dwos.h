@@ -200,6 +200,19 @@ dwos_status dwos_grad_sqloss(dwos_ctx* ctx, const double* X, int64_t P, const do
 dwos_status dwos_jvp(dwos_ctx* ctx, const double* X, int64_t P, int32_t W, uint64_t seed,
                      double* udot, double* udot_var, double* u_mean, dwos_stats* stats);
 
+/* Launch-shape autotuner.  Times a forward solve of the first min(P, 512)
+ * points with W walks under each walk-kernel launch shape and keeps the
+ * fastest for the context (FP32 only):
+ *   variant 0: one 1024-thread block per CU with the top BVH levels (and, if
+ *              they fit, all primitives) staged in LDS;
+ *   variant 1: 256-thread blocks, several per CU, BVH read through the caches.
+ * chosen (host, may be NULL) gets the variant, ms (host, 2 entries, may be
+ * NULL) the timed milliseconds.  dwos_set_variant forces a variant.
+ * Errors: as dwos_solve; EINVAL for a bad variant. */
+dwos_status dwos_autotune(dwos_ctx* ctx, const double* X, int64_t P, int32_t W, uint64_t seed,
+                          int32_t* chosen, double* ms);
+dwos_status dwos_set_variant(dwos_ctx* ctx, int32_t variant);
+
 /* Graph capture.  Every hot-path call (dwos_solve, dwos_grad,
  * dwos_grad_sqloss, dwos_jvp, dwos_batch_solve, dwos_apply_parameters,
  * dwos_update_vertices) enqueues only kernels when (a) an identical call has

@@ -76,6 +76,8 @@ def lib():
             "dwos_eval_ball_kernels": [vp, vp, vp, C.c_int64, C.c_double, vp, vp],
             "dwos_walk_timing": [vp, C.c_int32, C.c_int32, dp, i64p, C.POINTER(dwos_stats)],
             "dwos_set_seed_buffer": [vp, vp],
+            "dwos_autotune": [vp, vp, C.c_int64, C.c_int32, C.c_uint64, i32p, dp],
+            "dwos_set_variant": [vp, C.c_int32],
             "dwos_batch_add_instance": [vp, dp, C.c_int64, i32p, C.c_int64, i32p, C.c_double,
                                         C.c_double, C.c_double, i32p],
             "dwos_batch_solve": [vp, vp, i64p, C.c_int32, C.c_uint64, vp, vp, C.POINTER(dwos_stats)],
@@ -95,7 +97,8 @@ EXPORTED = [
     "dwos_apply_parameters",
     "dwos_set_problem", "dwos_set_parameters", "dwos_solve", "dwos_grad", "dwos_grad_sqloss",
     "dwos_jvp", "dwos_walk_records", "dwos_closest", "dwos_eval_ball_kernels", "dwos_walk_timing",
-    "dwos_batch_add_instance", "dwos_batch_solve", "dwos_set_seed_buffer",
+    "dwos_batch_add_instance", "dwos_batch_solve", "dwos_set_seed_buffer", "dwos_autotune",
+    "dwos_set_variant",
 ]
 
 

@@ -103,6 +103,7 @@ struct dwos_ctx {
     DevBuf vtmp;   // V(pi) for dwos_apply_parameters
     DevBuf first_leaf, first_d2;   // shared first query of each start point
     const uint64_t* seed_dev = nullptr;   // optional device seed offset
+    int variant = 0;                      // walk-kernel launch shape (FP32)
     // timing and cumulative counters per walk kind (0 forward, 1 differential)
     struct Pending { hipEvent_t e0, e1; int kind; };
     std::vector<Pending> pending;
@@ -307,6 +308,9 @@ dwos_status ensure_totals(dwos_ctx* c) {
     return DWOS_OK;
 }
 
+template <class T, int D, int MODE, bool staged>
+dwos_status launch_shape(dwos_ctx* c, dwos::WalkArgs<T>& a);
+
 // Launch the persistent walk kernel over `total` walks.  FP32 uses the
 // LDS-staged kernel (one large block per CU); the FP64 debug build keeps
 // everything in global memory.
@@ -315,7 +319,17 @@ dwos_status launch_walks(dwos_ctx* c, dwos::WalkArgs<T>& a) {
     hipStream_t s = c->stream;
     a.tot = c->totals.as<dwos::Counters>() + MODE;
     hipLaunchKernelGGL(dwos::fill_u64_kernel, dim3(1), dim3(64), 0, s, a.queue, (int64_t)1);
-    constexpr bool staged = sizeof(T) == 4;
+    if constexpr (sizeof(T) == 4) {
+        if (c->variant == 1) return launch_shape<T, D, MODE, false>(c, a);
+        return launch_shape<T, D, MODE, true>(c, a);
+    } else {
+        return launch_shape<T, D, MODE, false>(c, a);
+    }
+}
+
+template <class T, int D, int MODE, bool staged>
+dwos_status launch_shape(dwos_ctx* c, dwos::WalkArgs<T>& a) {
+    hipStream_t s = c->stream;
     constexpr int block = staged ? dwos::kBlockStaged : dwos::kBlock;
     const size_t smem = staged ? stage_bytes<T>(a.s, D) : 0;
     auto kern = dwos::walk_kernel<T, D, MODE, staged>;
@@ -963,6 +977,38 @@ dwos_status dwos_eval_ball_kernels(dwos_ctx* c, const double* r, const double* R
     };
     if (c->prec == DWOS_FP32) run(float{}); else run(double{});
     HIP_OK(hipGetLastError());
+    return DWOS_OK;
+}
+
+dwos_status dwos_set_variant(dwos_ctx* c, int32_t variant) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (variant != 0 && variant != 1) return fail(DWOS_EINVAL, "set_variant: variant must be 0 or 1");
+    c->variant = variant;
+    return DWOS_OK;
+}
+
+dwos_status dwos_autotune(dwos_ctx* c, const double* X, int64_t P, int32_t W, uint64_t seed, int32_t* chosen,
+                          double* ms) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (P <= 0 || W < 1 || !X) return fail(DWOS_EINVAL, "autotune: need points and W >= 1");
+    const int64_t Ps = std::min<int64_t>(P, 512);
+    DevBuf mean;
+    HIP_OK(mean.reserve(Ps * sizeof(double)));
+    double t[2] = {0.0, 0.0};
+    const int keep = c->variant;
+    for (int v = 0; v < 2; ++v) {
+        c->variant = v;
+        dwos_status rc = dwos_solve(c, X, Ps, W, seed, mean.as<double>(), nullptr, nullptr);   // warm-up
+        if (rc) { c->variant = keep; return rc; }
+        dwos_stats st{};
+        rc = dwos_solve(c, X, Ps, W, seed + 1, mean.as<double>(), nullptr, &st);
+        if (rc) { c->variant = keep; return rc; }
+        t[v] = st.walk_ms;
+    }
+    c->variant = (c->prec == DWOS_FP32 && t[1] < t[0]) ? 1 : 0;
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (chosen) *chosen = c->variant;
+    if (ms) { ms[0] = t[0]; ms[1] = t[1]; }
     return DWOS_OK;
 }
 

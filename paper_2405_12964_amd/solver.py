@@ -241,6 +241,18 @@ class Solver:
                                     C.byref(st) if st is not None else None))
         return (m, v, st.as_dict()) if stats else (m, v)
 
+    def autotune(self, X, W, seed=0):
+        """Pick the faster walk-kernel launch shape on a sample of X; returns
+        (variant, [ms variant 0, ms variant 1])."""
+        X = self._X(X)
+        ch = C.c_int32()
+        ms = (C.c_double * 2)()
+        check(capi.dwos_autotune(self._ctx, _dev(X), X.shape[0], int(W), int(seed), C.byref(ch), ms))
+        return ch.value, [ms[0], ms[1]]
+
+    def set_variant(self, v: int):
+        check(capi.dwos_set_variant(self._ctx, int(v)))
+
     def set_seed_buffer(self, seed_dev: Optional[torch.Tensor]):
         """Use seed + seed_dev[0] (a 1-element int64 GPU tensor) in every later
         call, so that a captured graph replays with fresh streams."""

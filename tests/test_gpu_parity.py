@@ -352,3 +352,29 @@ def test_graph_capture_replays_match_eager(dev, dwos):
         _ = torch.randn(1000, device=dev).sum().item()   # unrelated eager work between replays
     assert not torch.equal(outs[0], outs[1])                # new streams per replay
     s.set_seed_buffer(None)
+
+
+# ---------------------------------------------------------------- autotuner --
+
+@pytest.mark.parametrize("which", ["star", "c3"])
+def test_launch_variants_identical_and_autotune(dev, dwos, which):
+    """Walk results depend only on (seed, point, walk), so both launch shapes
+    of the walk kernel give bit-identical estimates; the autotuner then picks
+    one of them."""
+    if which == "star":
+        sc, X = star_small(2048), scenes.star_points(128, 12)
+    else:
+        sc, X = small_c3(nu=16), scenes.points_on_box_faces(128, 13)
+    s = dwos.Solver.from_scene(sc, "fp32")
+    Xt = T(X, dev)
+    w = torch.ones(len(X), dtype=torch.float64, device=dev)
+    res = []
+    for v in (0, 1):
+        s.set_variant(v)
+        m, var = s.solve(Xt, 256, 21)
+        g, _ = s.grad(Xt, w, 256, 22)
+        res.append((m, var, g))
+    assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
+    assert torch.allclose(res[0][2], res[1][2], rtol=1e-12, atol=1e-14)
+    v, ms = s.autotune(Xt, 256)
+    assert v in (0, 1) and all(t > 0 for t in ms)
