@@ -21,6 +21,7 @@ import argparse
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -45,6 +46,35 @@ OPS_STEP_2D = 40
 OPS_SOURCE_2D = 200
 PEAK_FP32_VALU = 157.3e12     # MI355X FP32 vector, FLOP/s
 PEAK_HBM = 8.0e12             # bytes/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_kernel_c2_star4096_hbm.txt")
+
+
+def sources_sha256():
+    """Hash of the kernel sources; HBM counters taken on other sources are stale."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2405_12964_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".hpp", ".cpp", ".h")):
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """Scaled FETCH_SIZE + WRITE_SIZE bytes per launch of `kernel` from the
+    committed counter summary, or None when it is missing or was taken on
+    different kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    kv = dict(re.findall(r"^# (\w+): (\S+)$", text, re.M))
+    if kv.get("sources_sha256") != sources_sha256():
+        return None
+    m = re.search(r"^traffic_bytes_per_launch +" + re.escape(kernel) + r" +(\S+)$", text, re.M)
+    return float(m.group(1)) if m else None
 
 
 def kernel_ops(tot, has_source=True):
@@ -53,7 +83,7 @@ def kernel_ops(tot, has_source=True):
             + (nonterm * OPS_SOURCE_2D if has_source else 0))
 
 
-def cpu_baseline(sc, X, uref_np, seed, threads, npts=256, W=64):
+def cpu_baseline(sc, X, uref_np, seed, threads, npts=1024, W=1024):
     """The FP64 oracle on a bounded sample of the same workload (forward and
     differential walks of npts points x W walks each)."""
     import numpy as np
@@ -146,9 +176,11 @@ def main():
     avg_s = ms / max(1, n) / 1e3
     ops = kernel_ops(tot) / max(1, n)
     achieved = ops / avg_s
+    # the default launch shape: the LDS-staged 1024-thread walk kernel
+    kname = f"walk_kernel<float,2,{kind},true>"
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None,
-            "kernel": f"walk_kernel<float,2,{kind}>", "avg_launch_ms": ms / max(1, n),
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": measured_traffic(kname),
+            "kernel": kname, "avg_launch_ms": ms / max(1, n),
             "launches": n, "ops_per_launch": ops,
             "steps_per_launch": tot["steps"] / max(1, n),
             "nodes_per_step": tot["nodes"] / max(1, tot["steps"]),
