@@ -56,12 +56,21 @@ def lib():
                                           C.c_int32, dp, dp, lp, ip, dp, lp, dp, C.c_int]
         L.oracle_solve.argtypes = [sp, dp, C.c_int64, C.c_int32, C.c_uint64, C.c_int32, dp, dp,
                                    lp, C.c_int]
+        cvp = C.POINTER(OracleCV)
         L.oracle_jvp.argtypes = [sp, dp, C.c_int64, C.c_int32, C.c_uint64, C.c_int32, dp, dp, dp,
-                                 lp, C.c_int]
+                                 lp, C.c_int, cvp]
         L.oracle_grad.argtypes = [sp, dp, C.c_int64, dp, C.c_int32, C.c_uint64, C.c_int32, dp, dp,
-                                  lp, C.c_int]
+                                  lp, C.c_int, cvp]
         L.oracle_grad_sqloss.argtypes = [sp, dp, C.c_int64, dp, C.c_int32, C.c_int32, C.c_uint64,
-                                         C.c_int32, dp, dp, dp, lp, C.c_int]
+                                         C.c_int32, dp, dp, dp, lp, C.c_int, cvp]
+        L.oracle_mlp_eval.argtypes = [C.c_int32, C.c_int32, dp, dp, dp, C.c_int64, dp, dp, dp]
+        L.oracle_mlp_theta_size.restype = C.c_int32
+        L.oracle_mlp_loss_grad.argtypes = [C.c_int32, C.c_int32, dp, dp, dp, dp, dp, C.c_int64,
+                                           dp, dp]
+        L.oracle_adam.argtypes = [C.c_int64, dp, dp, dp, dp, C.c_double, C.c_double, C.c_double,
+                                  C.c_double, C.c_int64]
+        L.oracle_walk_records_cv.argtypes = [sp, cvp, dp, C.c_int64, C.c_int32, C.c_uint64,
+                                             C.c_int32, dp, dp, C.c_int]
         _lib = L
     return _lib
 
@@ -78,6 +87,11 @@ class OracleScene(C.Structure):
         ("N", C.c_int32), ("rowptr", C.POINTER(C.c_int64)), ("pid", C.POINTER(C.c_int32)),
         ("vel", C.POINTER(C.c_double)), ("bc_pid", C.POINTER(C.c_int32)),
     ]
+
+
+class OracleCV(C.Structure):
+    _fields_ = [("F", C.c_int32), ("B", C.POINTER(C.c_double)), ("theta", C.POINTER(C.c_double)),
+                ("q", C.c_double)]
 
 
 def _ptr(a, ct):
@@ -185,29 +199,29 @@ class Oracle:
         assert rc == 0
         return m, v, int(st[0])
 
-    def jvp(self, X, W, seed, instance=0):
+    def jvp(self, X, W, seed, instance=0, cv=None):
         X = self._X(X)
         P = X.shape[0]
         N = self.scene.N
         m, v, um, st = np.zeros(P * N), np.zeros(P * N), np.zeros(P), np.zeros(1, np.int64)
         rc = lib().oracle_jvp(C.byref(self._s), _ptr(X, C.c_double), P, W, seed, instance,
                               _ptr(m, C.c_double), _ptr(v, C.c_double), _ptr(um, C.c_double),
-                              _ptr(st, C.c_int64), self.threads)
+                              _ptr(st, C.c_int64), self.threads, _cvref(cv))
         assert rc == 0
         return m.reshape(P, N), v.reshape(P, N), um, int(st[0])
 
-    def grad(self, X, w, W, seed, instance=0):
+    def grad(self, X, w, W, seed, instance=0, cv=None):
         X = self._X(X)
         P = X.shape[0]
         w = np.ascontiguousarray(w, dtype=np.float64)
         g, um, st = np.zeros(self.scene.N), np.zeros(P), np.zeros(1, np.int64)
         rc = lib().oracle_grad(C.byref(self._s), _ptr(X, C.c_double), P, _ptr(w, C.c_double), W,
                                seed, instance, _ptr(g, C.c_double), _ptr(um, C.c_double),
-                               _ptr(st, C.c_int64), self.threads)
+                               _ptr(st, C.c_int64), self.threads, _cvref(cv))
         assert rc == 0
         return g, um, int(st[0])
 
-    def grad_sqloss(self, X, uref, W, B, seed, instance=0):
+    def grad_sqloss(self, X, uref, W, B, seed, instance=0, cv=None):
         X = self._X(X)
         P = X.shape[0]
         uref = np.ascontiguousarray(uref, dtype=np.float64)
@@ -215,10 +229,89 @@ class Oracle:
         rc = lib().oracle_grad_sqloss(C.byref(self._s), _ptr(X, C.c_double), P,
                                       _ptr(uref, C.c_double), W, B, seed, instance,
                                       _ptr(L, C.c_double), _ptr(g, C.c_double),
-                                      _ptr(um, C.c_double), _ptr(st, C.c_int64), self.threads)
+                                      _ptr(um, C.c_double), _ptr(st, C.c_int64), self.threads,
+                                      _cvref(cv))
         if rc != 0:
             raise ValueError("oracle_grad_sqloss: invalid arguments")
         return float(L[0]), g, um, int(st[0])
+
+    def walk_records_cv(self, X, W, seed, cv, instance=0):
+        """Differential walks with the control variate: per-walk records
+        (run, xoff, uoff plain, uoff_cv, target, u, prim) and per nested walk
+        (L, alive, xstop, y, rho, d)."""
+        X = self._X(X)
+        P = X.shape[0]
+        K = int(self.scene.K)
+        walk = np.zeros(P * W * 9)
+        nested = np.zeros(P * W * K * 10)
+        rc = lib().oracle_walk_records_cv(C.byref(self._s), _cvref(cv), _ptr(X, C.c_double), P, W,
+                                          seed, instance, _ptr(walk, C.c_double),
+                                          _ptr(nested, C.c_double), self.threads)
+        assert rc == 0
+        w = walk.reshape(P, W, 9)
+        n = nested.reshape(P, W, K, 10)
+        return dict(run=w[..., 0].astype(np.int32), xoff=w[..., 1:4], uoff=w[..., 4],
+                    uoff_cv=w[..., 5], target=w[..., 6], u=w[..., 7], prim=w[..., 8].astype(np.int32),
+                    L=n[..., 0].astype(np.int64), alive=n[..., 1].astype(np.int32),
+                    xstop=n[..., 2:5], y=n[..., 5:8], rho=n[..., 8], d=n[..., 9])
+
+
+class Net:
+    """The control-variate network of the oracle: frequencies B (F x dim) and
+    parameters theta (THETA_SIZE); q is the probability of running the nested
+    walks.  Arrays are kept alive for the C structure."""
+
+    def __init__(self, dim, B, theta, q=1.0):
+        self.dim = int(dim)
+        self.B = np.ascontiguousarray(B, dtype=np.float64).reshape(-1, self.dim)
+        self.theta = np.ascontiguousarray(theta, dtype=np.float64)
+        assert self.theta.size == theta_size()
+        self.q = float(q)
+        self._c = OracleCV()
+        self._c.F = self.B.shape[0]
+        self._c.B = _ptr(self.B, C.c_double)
+        self._c.theta = _ptr(self.theta, C.c_double)
+        self._c.q = self.q
+
+    def eval(self, X):
+        X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, self.dim)
+        n = X.shape[0]
+        N, G, Lp = np.zeros(n), np.zeros(n * self.dim), np.zeros(n)
+        rc = lib().oracle_mlp_eval(self.dim, self.B.shape[0], _ptr(self.B, C.c_double),
+                                   _ptr(self.theta, C.c_double), _ptr(X, C.c_double), n,
+                                   _ptr(N, C.c_double), _ptr(G, C.c_double), _ptr(Lp, C.c_double))
+        assert rc == 0
+        return N, G.reshape(n, self.dim), Lp
+
+    def loss_grad(self, X, T, w=None):
+        X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, self.dim)
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        w = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+        g = np.zeros(theta_size())
+        L = np.zeros(1)
+        rc = lib().oracle_mlp_loss_grad(self.dim, self.B.shape[0], _ptr(self.B, C.c_double),
+                                        _ptr(self.theta, C.c_double), _ptr(X, C.c_double),
+                                        _ptr(T, C.c_double), _ptr(w, C.c_double), X.shape[0],
+                                        _ptr(L, C.c_double), _ptr(g, C.c_double))
+        assert rc == 0
+        return float(L[0]), g
+
+
+def _cvref(cv):
+    return C.byref(cv._c) if cv is not None else None
+
+
+def theta_size():
+    return int(lib().oracle_mlp_theta_size())
+
+
+def adam(theta, m, v, g, lr, beta1, beta2, eps, step):
+    """One Adam step in place on float64 arrays."""
+    for a in (theta, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    lib().oracle_adam(theta.size, _ptr(theta, C.c_double), _ptr(m, C.c_double),
+                      _ptr(v, C.c_double), _ptr(g, C.c_double), lr, beta1, beta2, eps, step)
 
 
 def philox(ctr, key):

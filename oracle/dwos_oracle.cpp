@@ -37,6 +37,10 @@
 //   * Walk-length cap kmax: the kmax-th query is treated as terminal.
 //   * Mapped data: udot = gdot_ref - grad_G g . V - V_n du/dn (Appendix A
 //     with tangential components of the velocity kept explicitly).
+//
+// Extension (not in the paper, which lists variance reduction and caches that
+// estimate u without a walk as future work in Sec. 8 and Appendix B): a
+// learned control variate for the nested walks, see "Control variate" below.
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -67,6 +71,16 @@ struct oracle_scene {
     const int32_t* pid;      // nnz parameter ids
     const double* vel;       // nnz*dim velocities dv_i/dpi_j
     const int32_t* bc_pid;   // nv parameter id of the mapped value, -1 none (NULL: none)
+};
+
+// Learned control variate of the nested walks: network N(x) (frequencies B,
+// F x dim, and parameters theta, see mlp_eval) and the probability q in (0, 1]
+// of running the nested walks at a differential terminal.
+struct oracle_cv {
+    int32_t F;
+    const double* B;
+    const double* theta;
+    double q;
 };
 
 }  // extern "C"
@@ -341,6 +355,169 @@ void sphere_dir(int D, uint32_t w0, uint32_t w1, double s[3]) {
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// The control-variate network (an extension; see the file header).
+//   gamma(x) = [sin(2 pi B x) (F), cos(2 pi B x) (F), x (dim), 0 ...]  (64)
+//   a_1 = tanh(W_1 gamma + b_1), a_l = tanh(W_l a_{l-1} + b_l), l = 2..4 (64)
+//   N(x) = w_5 . a_4 + b_5
+// theta holds, for l = 1..4, W_l (64 x 64, row = output unit) then b_l (64),
+// followed by w_5 (64) and b_5: 16705 values.
+// ---------------------------------------------------------------------------
+constexpr int kWidth = 64;
+constexpr int kLayers = 4;
+constexpr int kLayerSize = kWidth * kWidth + kWidth;
+constexpr int kThetaSize = kLayers * kLayerSize + kWidth + 1;
+
+struct MlpOut {
+    double N = 0;
+    double grad[3] = {0, 0, 0};
+    double lap = 0;
+};
+
+// Input features with their spatial gradients and Laplacians.
+void mlp_features(int D, int F, const double* B, const double* x, double v[kWidth],
+                  double g[kWidth][3], double L[kWidth]) {
+    for (int f = 0; f < kWidth; ++f) {
+        v[f] = 0; L[f] = 0;
+        for (int c = 0; c < 3; ++c) g[f][c] = 0;
+    }
+    for (int i = 0; i < F; ++i) {
+        const double* b = B + (size_t)i * D;
+        double th = 0, bb = 0;
+        for (int c = 0; c < D; ++c) { th += 2 * M_PI * b[c] * x[c]; bb += b[c] * b[c]; }
+        double sn = std::sin(th), cs = std::cos(th);
+        double w2 = 4 * M_PI * M_PI * bb;
+        v[i] = sn; v[F + i] = cs;
+        for (int c = 0; c < D; ++c) {
+            g[i][c] = 2 * M_PI * b[c] * cs;
+            g[F + i][c] = -2 * M_PI * b[c] * sn;
+        }
+        L[i] = -w2 * sn; L[F + i] = -w2 * cs;
+    }
+    for (int c = 0; c < D; ++c) { v[2 * F + c] = x[c]; g[2 * F + c][c] = 1; }
+}
+
+// N, grad N and Lap N at x: the value, the dim first derivatives and the
+// Laplacian are carried through every layer (chain rule; for h = tanh z,
+// h' = 1 - h^2 and h'' = -2 h (1 - h^2)).
+MlpOut mlp_eval(int D, int F, const double* B, const double* theta, const double* x) {
+    double v[kWidth], g[kWidth][3], L[kWidth];
+    mlp_features(D, F, B, x, v, g, L);
+    for (int l = 0; l < kLayers; ++l) {
+        const double* W = theta + (size_t)l * kLayerSize;
+        const double* b = W + kWidth * kWidth;
+        double nv[kWidth], ng[kWidth][3], nL[kWidth];
+        for (int o = 0; o < kWidth; ++o) {
+            double z = b[o], zL = 0, zg[3] = {0, 0, 0};
+            for (int i = 0; i < kWidth; ++i) {
+                double w = W[o * kWidth + i];
+                z += w * v[i];
+                zL += w * L[i];
+                for (int c = 0; c < D; ++c) zg[c] += w * g[i][c];
+            }
+            double h = std::tanh(z), s = 1 - h * h, zz = 0;
+            for (int c = 0; c < D; ++c) zz += zg[c] * zg[c];
+            nv[o] = h;
+            for (int c = 0; c < 3; ++c) ng[o][c] = c < D ? s * zg[c] : 0;
+            nL[o] = s * zL - 2 * h * s * zz;
+        }
+        std::memcpy(v, nv, sizeof v); std::memcpy(g, ng, sizeof g); std::memcpy(L, nL, sizeof L);
+    }
+    const double* w5 = theta + (size_t)kLayers * kLayerSize;
+    MlpOut out;
+    out.N = w5[kWidth];
+    for (int i = 0; i < kWidth; ++i) {
+        out.N += w5[i] * v[i];
+        out.lap += w5[i] * L[i];
+        for (int c = 0; c < D; ++c) out.grad[c] += w5[i] * g[i][c];
+    }
+    return out;
+}
+
+// Squared-error training loss sum_i 1/2 w_i (N(x_i) - t_i)^2 and its gradient
+// with respect to theta (reverse mode through the layers above).
+double mlp_loss_grad(int D, int F, const double* B, const double* theta, const double* X,
+                     const double* T, const double* Wt, int64_t n, double* grad) {
+    double loss = 0;
+    for (int64_t s = 0; s < n; ++s) {
+        double a[kLayers + 1][kWidth], gdum[kWidth][3], Ldum[kWidth];
+        mlp_features(D, F, B, X + s * D, a[0], gdum, Ldum);
+        for (int l = 0; l < kLayers; ++l) {
+            const double* W = theta + (size_t)l * kLayerSize;
+            const double* b = W + kWidth * kWidth;
+            for (int o = 0; o < kWidth; ++o) {
+                double z = b[o];
+                for (int i = 0; i < kWidth; ++i) z += W[o * kWidth + i] * a[l][i];
+                a[l + 1][o] = std::tanh(z);
+            }
+        }
+        const double* w5 = theta + (size_t)kLayers * kLayerSize;
+        double N = w5[kWidth];
+        for (int i = 0; i < kWidth; ++i) N += w5[i] * a[kLayers][i];
+        double w = Wt ? Wt[s] : 1.0;
+        double r = w * (N - T[s]);
+        loss += 0.5 * w * (N - T[s]) * (N - T[s]);
+        double* gw5 = grad + (size_t)kLayers * kLayerSize;
+        double delta[kWidth];
+        for (int i = 0; i < kWidth; ++i) {
+            gw5[i] += r * a[kLayers][i];
+            delta[i] = r * w5[i] * (1 - a[kLayers][i] * a[kLayers][i]);
+        }
+        gw5[kWidth] += r;
+        for (int l = kLayers - 1; l >= 0; --l) {
+            const double* W = theta + (size_t)l * kLayerSize;
+            double* gW = grad + (size_t)l * kLayerSize;
+            double* gb = gW + kWidth * kWidth;
+            for (int o = 0; o < kWidth; ++o) {
+                gb[o] += delta[o];
+                for (int i = 0; i < kWidth; ++i) gW[o * kWidth + i] += delta[o] * a[l][i];
+            }
+            if (l == 0) break;
+            double prev[kWidth];
+            for (int i = 0; i < kWidth; ++i) {
+                double acc = 0;
+                for (int o = 0; o < kWidth; ++o) acc += W[o * kWidth + i] * delta[o];
+                prev[i] = acc * (1 - a[l][i] * a[l][i]);
+            }
+            std::memcpy(delta, prev, sizeof delta);
+        }
+    }
+    return loss;
+}
+
+// ---------------------------------------------------------------------------
+// Control variate of a nested walk.  For any twice differentiable N, applying
+// the ball's mean-value identity for the screened operator (Sec. 3.3: the
+// Poisson-kernel average of N on the sphere plus the Green's-function integral
+// of -Lap N + sigma N over the ball) at every step of Algorithm 1 gives
+//   N(x_0) = E[ sum over source steps j of  int_{B_j} G_j (-Lap N + sigma N)
+//               + [the walk ended in the shell or at the cap] N(x_stop) ],
+// with the same stopping rules (shell, roulette, cap) as the walk.  So
+//   C = N(x_0) - sum_j int_{B_j} G_j (-Lap N + sigma N) - [alive] N(x_stop)
+// has mean zero, and uhat + C is an estimate of u(x_0) with the same mean as
+// uhat; its variance vanishes as N approaches u.  The sum over the L source
+// steps is estimated by one step J chosen uniformly (reservoir sampling as the
+// walk proceeds) weighted by L, with one uniform ball point y_J of B_J:
+//   sum_j ~ L |B_J| G_J(|y_J - x_J|) (-Lap N + sigma N)(y_J).
+// ---------------------------------------------------------------------------
+struct CvTrace {
+    int64_t L = 0;         // source (non-terminal) steps
+    bool alive = false;    // ended in the shell or at the cap (not by roulette)
+    double xstop[3] = {0, 0, 0};
+    double y[3] = {0, 0, 0};
+    double rho = 0, d = 0; // y = x_J + rho d dir, rho in (0, 1], d = radius of B_J
+};
+
+// 24-bit threshold of the probability q: the nested walks run iff the top 24
+// bits of a uniform word are below it.
+uint32_t cv_threshold(double q) {
+    double t = std::round(q * 16777216.0);
+    if (t < 1) t = 1;
+    if (t > 16777216.0) t = 16777216.0;
+    return (uint32_t)t;
+}
+
 struct WalkCount { int64_t steps = 0; int64_t truncated = 0; };
 
 // ---------------------------------------------------------------------------
@@ -350,7 +527,7 @@ struct WalkCount { int64_t steps = 0; int64_t truncated = 0; };
 // carries the running sum of source contributions.
 // ---------------------------------------------------------------------------
 double walk_on_spheres(const Scene& sc, const double* x0, const Stream& st, uint32_t extra,
-                       WalkCount& cnt) {
+                       WalkCount& cnt, CvTrace* tr = nullptr) {
     const int D = sc.D;
     double x[3] = {0, 0, 0};
     for (int i = 0; i < D; ++i) x[i] = x0[i];
@@ -362,10 +539,26 @@ double walk_on_spheres(const Scene& sc, const double* x0, const Stream& st, uint
         bool cap = (int64_t)k + 1 >= sc.s.kmax;
         if (d < sc.s.eps || cap) {                      // in the eps-shell
             if (cap && !(d < sc.s.eps)) cnt.truncated++;
+            if (tr) {
+                tr->alive = true;
+                for (int i = 0; i < D; ++i) tr->xstop[i] = x[i];
+            }
             return acc + sc.g(h);
         }
         uint32_t w[4];
         st.draw(k, extra, w);
+        if (tr) {   // reservoir choice of the source step for the control variate
+            tr->L++;
+            uint32_t wr[4];
+            st.draw(k, extra | 4u, wr);
+            if ((uint64_t)(wr[0] >> 8) * (uint64_t)tr->L < (1ull << 24)) {
+                double dir[3];
+                sphere_dir(D, wr[1], wr[2], dir);
+                tr->rho = std::pow(u24pos(wr[3]), 1.0 / D);
+                tr->d = d;
+                for (int i = 0; i < D; ++i) tr->y[i] = x[i] + tr->rho * d * dir[i];
+            }
+        }
         if (sc.has_source()) {                          // source contribution
             uint32_t wb[4];
             st.draw(k, extra | 2u, wb);
@@ -393,7 +586,35 @@ struct DiffOut {
     double uoff = 0;       // mean of the K nested walks at the offset point
     int64_t nested_steps = 0;
     std::vector<double> udot;  // dense N-vector
+    // with the control variate:
+    int run = -1;          // -1 no terminal, 0 nested walks skipped, 1 run
+    double xoff[3] = {0, 0, 0};
+    double uoff_cv = 0;    // estimate of u(xoff) used in du/dn
+    double target = 0;     // N(xoff) + (mean of uhat + C), run == 1 only
+    std::vector<CvTrace> traces;
 };
+
+// The control-variate estimate of u(xoff) from the nested walks' traces:
+//   N(xoff) + [run] (uhat - mean_i corr_i) / q,
+//   corr_i = L_i |B| G (-Lap N + sigma N)(y_i) + [alive_i] N(xstop_i).
+void cv_combine(const Scene& sc, const oracle_cv& cv, DiffOut& o) {
+    const int D = sc.D;
+    double Noff = mlp_eval(D, cv.F, cv.B, cv.theta, o.xoff).N;
+    if (o.run == 0) { o.uoff_cv = Noff; return; }
+    double corr = 0;
+    for (const CvTrace& t : o.traces) {
+        if (t.L > 0) {
+            MlpOut e = mlp_eval(D, cv.F, cv.B, cv.theta, t.y);
+            double fN = -e.lap + sc.s.sigma * e.N;
+            corr += (double)t.L * green(D, sc.s.sigma, t.rho * t.d, t.d) * ball_volume(D, t.d) * fN;
+        }
+        if (t.alive) corr += mlp_eval(D, cv.F, cv.B, cv.theta, t.xstop).N;
+    }
+    corr /= (double)o.traces.size();
+    double q = (double)cv_threshold(cv.q) * 0x1p-24;
+    o.target = Noff + o.uoff - corr;
+    o.uoff_cv = Noff + (o.uoff - corr) / q;
+}
 
 // ---------------------------------------------------------------------------
 // Algorithm 2: DiffWalkOnSpheres(x, eps, delta).  The walk follows the same
@@ -402,7 +623,7 @@ struct DiffOut {
 // point xbar - delta n and forms the differential boundary value.
 // ---------------------------------------------------------------------------
 DiffOut diff_walk_on_spheres(const Scene& sc, const double* x0, const Stream& st,
-                             WalkCount& cnt, bool want_udot) {
+                             WalkCount& cnt, bool want_udot, const oracle_cv* cv = nullptr) {
     const int D = sc.D;
     const int N = sc.s.N;
     DiffOut out;
@@ -422,20 +643,33 @@ DiffOut diff_walk_on_spheres(const Scene& sc, const double* x0, const Stream& st
             double xoff[3] = {0, 0, 0};
             for (int i = 0; i < D; ++i) xoff[i] = h.xbar[i] - sc.s.delta * n[i];
             double usum = 0;
-            for (int i = 0; i < sc.s.K; ++i) {                 // nested forward walks
+            out.run = 1;
+            if (cv && cv_threshold(cv->q) < (1u << 24)) {      // run the nested walks w.p. q
+                uint32_t wq[4];
+                st.draw(k, 4u, wq);
+                out.run = (wq[0] >> 8) < cv_threshold(cv->q) ? 1 : 0;
+            }
+            if (cv) out.traces.assign(out.run ? sc.s.K : 0, CvTrace());
+            for (int i = 0; out.run && i < sc.s.K; ++i) {      // nested forward walks
                 WalkCount c2;
-                usum += walk_on_spheres(sc, xoff, st, 1u | ((uint32_t)i << 8), c2);
+                usum += walk_on_spheres(sc, xoff, st, 1u | ((uint32_t)i << 8), c2,
+                                        cv ? &out.traces[i] : nullptr);
                 out.nested_steps += c2.steps;
                 cnt.truncated += c2.truncated;
             }
             double uhat = usum / sc.s.K;
+            for (int i = 0; i < 3; ++i) out.xoff[i] = xoff[i];
+            out.uoff = uhat;
+            if (cv) {
+                cv_combine(sc, *cv, out);
+                uhat = out.uoff_cv;
+            }
             double gx = sc.g(h);
             double dudn = (gx - uhat) / sc.s.delta;            // eq. (dudn_fd_estimate)
             out.u = acc + gx;
             out.terminal = true;
             out.prim = h.prim;
             for (int i = 0; i < 3; ++i) out.xbar[i] = h.xbar[i];
-            out.uoff = uhat;
             if (want_udot) {
                 // velocity field at xbar for each parameter: V_j = sum_k b_k dv_{i_k}/dpi_j
                 std::vector<double> Vj((size_t)N * 3, 0.0);
@@ -611,7 +845,7 @@ int oracle_solve(const oracle_scene* s, const double* X, int64_t P, int32_t W, u
 // Forward mode: per point mean of the N-vector udot and the variance of that mean.
 int oracle_jvp(const oracle_scene* s, const double* X, int64_t P, int32_t W, uint64_t seed,
                int32_t instance, double* udot_mean, double* udot_var, double* u_mean,
-               int64_t* steps_total, int threads) {
+               int64_t* steps_total, int threads, const oracle_cv* cv) {
     if (check_scene(s) || W < 1 || P < 0) return 1;
     Scene sc(*s);
     const int D = s->dim, N = s->N;
@@ -624,7 +858,7 @@ int oracle_jvp(const oracle_scene* s, const double* X, int64_t P, int32_t W, uin
         for (int m = 0; m < W; ++m) {
             Stream st = make_stream(seed, (uint32_t)p, (uint32_t)m, (uint32_t)instance);
             WalkCount c;
-            DiffOut o = diff_walk_on_spheres(sc, X + p * D, st, c, true);
+            DiffOut o = diff_walk_on_spheres(sc, X + p * D, st, c, true, cv);
             for (int j = 0; j < N; ++j) { s1[j] += o.udot[j]; s2[j] += o.udot[j] * o.udot[j]; }
             us += o.u;
             st_steps[t] += c.steps + o.nested_steps;
@@ -643,7 +877,7 @@ int oracle_jvp(const oracle_scene* s, const double* X, int64_t P, int32_t W, uin
 // Reverse mode: grad_j = sum_p w_p * mean_m udot_m[j]; also the joint u mean.
 int oracle_grad(const oracle_scene* s, const double* X, int64_t P, const double* w, int32_t W,
                 uint64_t seed, int32_t instance, double* grad, double* u_mean,
-                int64_t* steps_total, int threads) {
+                int64_t* steps_total, int threads, const oracle_cv* cv) {
     if (check_scene(s) || W < 1 || P < 0) return 1;
     Scene sc(*s);
     const int D = s->dim, N = s->N;
@@ -657,7 +891,7 @@ int oracle_grad(const oracle_scene* s, const double* X, int64_t P, const double*
         for (int m = 0; m < W; ++m) {
             Stream st = make_stream(seed, (uint32_t)p, (uint32_t)m, (uint32_t)instance);
             WalkCount c;
-            DiffOut o = diff_walk_on_spheres(sc, X + p * D, st, c, true);
+            DiffOut o = diff_walk_on_spheres(sc, X + p * D, st, c, true, cv);
             for (int j = 0; j < N; ++j) s1[j] += o.udot[j];
             us += o.u;
             st_steps[t] += c.steps + o.nested_steps;
@@ -677,7 +911,8 @@ int oracle_grad(const oracle_scene* s, const double* X, int64_t P, const double*
 // per-point walk mean.
 int oracle_grad_sqloss(const oracle_scene* s, const double* X, int64_t P, const double* uref,
                        int32_t W, int32_t B, uint64_t seed, int32_t instance, double* loss,
-                       double* grad, double* u_mean, int64_t* steps_total, int threads) {
+                       double* grad, double* u_mean, int64_t* steps_total, int threads,
+                       const oracle_cv* cv) {
     if (check_scene(s) || W < 1 || P < 0 || B < 2 || W % B != 0) return 1;
     Scene sc(*s);
     const int D = s->dim, N = s->N;
@@ -697,7 +932,7 @@ int oracle_grad_sqloss(const oracle_scene* s, const double* X, int64_t P, const 
                 int m = b * B + q;
                 Stream st = make_stream(seed, (uint32_t)p, (uint32_t)m, (uint32_t)instance);
                 WalkCount c;
-                DiffOut o = diff_walk_on_spheres(sc, X + p * D, st, c, true);
+                DiffOut o = diff_walk_on_spheres(sc, X + p * D, st, c, true, cv);
                 ud[q] = o.udot; uh[q] = o.u; us += o.u;
                 st_steps[t] += c.steps + o.nested_steps;
             }
@@ -719,6 +954,80 @@ int oracle_grad_sqloss(const oracle_scene* s, const double* X, int64_t P, const 
     if (loss) *loss = L;
     for (int j = 0; j < N; ++j) { double a = 0; for (int t = 0; t < T; ++t) a += part[t][j]; grad[j] = a; }
     if (steps_total) { int64_t a = 0; for (auto v : st_steps) a += v; *steps_total = a; }
+    return 0;
+}
+
+// ----- control variate --------------------------------------------------
+// N, grad N (n x dim) and Lap N at n points (grad and lap may be NULL).
+int oracle_mlp_eval(int32_t dim, int32_t F, const double* B, const double* theta,
+                    const double* X, int64_t n, double* N, double* grad, double* lap) {
+    if ((dim != 2 && dim != 3) || F < 0 || 2 * F + dim > kWidth || n < 0) return 1;
+    for (int64_t i = 0; i < n; ++i) {
+        MlpOut o = mlp_eval(dim, F, B, theta, X + i * dim);
+        N[i] = o.N;
+        if (grad) for (int c = 0; c < dim; ++c) grad[i * dim + c] = o.grad[c];
+        if (lap) lap[i] = o.lap;
+    }
+    return 0;
+}
+
+int32_t oracle_mlp_theta_size(void) { return kThetaSize; }
+
+// loss = sum_i 1/2 w_i (N(x_i) - t_i)^2 (w may be NULL: all 1); grad
+// (kThetaSize) is overwritten with d loss / d theta.
+int oracle_mlp_loss_grad(int32_t dim, int32_t F, const double* B, const double* theta,
+                         const double* X, const double* T, const double* w, int64_t n,
+                         double* loss, double* grad) {
+    if ((dim != 2 && dim != 3) || F < 0 || 2 * F + dim > kWidth || n < 0) return 1;
+    std::fill(grad, grad + kThetaSize, 0.0);
+    double L = mlp_loss_grad(dim, F, B, theta, X, T, w, n, grad);
+    if (loss) *loss = L;
+    return 0;
+}
+
+// One Adam step (Kingma and Ba, ICLR 2015, Algorithm 1) on n parameters;
+// step is the 1-based step count used in the bias corrections.
+void oracle_adam(int64_t n, double* theta, double* m, double* v, const double* g, double lr,
+                 double beta1, double beta2, double eps, int64_t step) {
+    double c1 = 1 - std::pow(beta1, (double)step), c2 = 1 - std::pow(beta2, (double)step);
+    for (int64_t i = 0; i < n; ++i) {
+        m[i] = beta1 * m[i] + (1 - beta1) * g[i];
+        v[i] = beta2 * v[i] + (1 - beta2) * g[i] * g[i];
+        theta[i] -= lr * (m[i] / c1) / (std::sqrt(v[i] / c2) + eps);
+    }
+}
+
+// Differential-walk records with the control variate.
+// walk (P*W*9): run, xoff[3], uoff (plain nested mean), uoff_cv, target, u, prim
+// nested (P*W*K*10): L, alive, xstop[3], y[3], rho, d  (zeros when not run)
+int oracle_walk_records_cv(const oracle_scene* s, const oracle_cv* cv, const double* X,
+                           int64_t P, int32_t W, uint64_t seed, int32_t instance,
+                           double* walk, double* nested, int threads) {
+    if (check_scene(s) || !cv || W < 1 || P < 0) return 1;
+    Scene sc(*s);
+    const int D = s->dim, K = s->K;
+    parallel_points(P, threads, [&](int, int64_t p) {
+        for (int m = 0; m < W; ++m) {
+            size_t id = (size_t)p * W + m;
+            Stream st = make_stream(seed, (uint32_t)p, (uint32_t)m, (uint32_t)instance);
+            WalkCount c;
+            DiffOut o = diff_walk_on_spheres(sc, X + p * D, st, c, false, cv);
+            double* r = walk + id * 9;
+            r[0] = o.run;
+            for (int i = 0; i < 3; ++i) r[1 + i] = o.xoff[i];
+            r[4] = o.uoff; r[5] = o.uoff_cv; r[6] = o.target; r[7] = o.u;
+            r[8] = o.terminal ? o.prim : -1;
+            for (int i = 0; i < K; ++i) {
+                double* q = nested + (id * K + i) * 10;
+                std::fill(q, q + 10, 0.0);
+                if (i >= (int)o.traces.size()) continue;
+                const CvTrace& t = o.traces[i];
+                q[0] = (double)t.L; q[1] = t.alive ? 1 : 0;
+                for (int c2 = 0; c2 < 3; ++c2) { q[2 + c2] = t.xstop[c2]; q[5 + c2] = t.y[c2]; }
+                q[8] = t.rho; q[9] = t.d;
+            }
+        }
+    });
     return 0;
 }
 

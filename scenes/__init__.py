@@ -452,3 +452,35 @@ def c4_batch(n_inst: int = 256, seed0: int = 100, tri_lo: float = 1e3,
         X = points_on_box_faces(P, seed0 + i)
         out.append((sc, X))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Initial parameters of the control-variate network (inputs, not arithmetic):
+# F random Fourier frequencies B ~ N(0, freq_scale^2) and Glorot-uniform
+# weights for four 64-wide layers and the scalar output, zero biases.  The
+# flat layout is, for each layer, W (64 x 64, row = output unit) then b (64),
+# followed by the output weights (64) and output bias.
+# ---------------------------------------------------------------------------
+MLP_WIDTH = 64
+MLP_LAYERS = 4
+MLP_FREQS = 16
+MLP_THETA_SIZE = MLP_LAYERS * (MLP_WIDTH * MLP_WIDTH + MLP_WIDTH) + MLP_WIDTH + 1
+
+
+def mlp_init(dim: int, seed: int, freq_scale: float = 1.0, F: int = MLP_FREQS):
+    """(B [F x dim], theta [MLP_THETA_SIZE]) as float64."""
+    assert 2 * F + dim <= MLP_WIDTH
+    rng = np.random.default_rng(seed)
+    B = rng.normal(0.0, freq_scale, size=(F, dim))
+    theta = np.zeros(MLP_THETA_SIZE)
+    H = MLP_WIDTH
+    lim = math.sqrt(6.0 / (H + H))
+    for l in range(MLP_LAYERS):
+        off = l * (H * H + H)
+        W = rng.uniform(-lim, lim, size=(H, H))
+        if l == 0:
+            W[:, 2 * F + dim:] = 0.0          # padding inputs
+        theta[off:off + H * H] = W.ravel()
+    off = MLP_LAYERS * (H * H + H)
+    theta[off:off + H] = rng.uniform(-math.sqrt(6.0 / (H + 1)), math.sqrt(6.0 / (H + 1)), size=H)
+    return B, theta
