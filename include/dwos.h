@@ -277,6 +277,86 @@ dwos_status dwos_batch_solve(dwos_ctx* ctx, const double* X_all, const int64_t* 
                              int32_t W, uint64_t seed, double* u_mean, double* u_var,
                              dwos_stats* stats);
 
+/* ---- Learned control variate of the nested walks ----
+ * An extension of the method: the paper lists variance reduction and caches
+ * that estimate u without a walk as future work (Sec. 8; Appendix B).
+ *
+ * A network N(x): features [sin 2 pi B x, cos 2 pi B x, x, 0...] (64 inputs;
+ * B is F x dim, 2F + dim <= 64), four tanh layers of width 64 and a linear
+ * scalar output; parameters theta (dwos_mlp_theta_size() FP32 values, for
+ * l = 1..4: W_l 64 x 64 row-major with row = output unit, then b_l; then
+ * w_5[64], b_5).  The products run on the matrix cores with split-BF16
+ * operands (hi + lo, about 16 mantissa bits) and FP32 accumulation.
+ *
+ * For any smooth N, the ball's mean-value identity of the screened operator
+ * (Sec. 3.3) applied at each step of a nested walk (Algorithm 1) makes
+ *   C = N(x_0) - sum_j |B_j| G_j (-Lap N + sigma N)(y_j) - [alive] N(x_stop)
+ * a zero-mean quantity ("alive": the walk ended in the eps-shell or at the
+ * cap, not by roulette).  With a network attached, each differential
+ * terminal (Algorithm 2) estimates u(xoff) by
+ *   N(xoff) + [run] (uhat + C_mean) / q
+ * where the K nested walks run with probability q (a Philox draw of the
+ * terminal step, counter purpose 4), the source-step sum is estimated by one
+ * step chosen uniformly along the walk (reservoir sampling, counter purpose
+ * 4 of each nested step) weighted by the number of source steps, and C_mean
+ * averages C over the K nested walks.  The mean is that of the plain
+ * estimator for any N and q; the variance vanishes as N approaches u.  The
+ * walks themselves (and their random numbers) are unchanged. */
+typedef struct dwos_mlp dwos_mlp;
+
+int32_t dwos_mlp_theta_size(void);
+
+/* Create a network with frequencies B (host, F x dim FP32) on the current
+ * device, work enqueued on `stream` (hipStream_t, NULL = null stream).
+ * theta starts at zero (N = 0); the Adam moments at zero.
+ * Errors: EINVAL (dim, F, NULL or non-finite B), ENOMEM, EDEVICE. */
+dwos_status dwos_mlp_create(int32_t dim, int32_t F, const float* B, void* stream, dwos_mlp** out);
+void dwos_mlp_destroy(dwos_mlp* m);
+
+/* Copy theta in (device, FP32) and reset the Adam state / out (device). */
+dwos_status dwos_mlp_set_params(dwos_mlp* m, const float* theta);
+dwos_status dwos_mlp_get_params(dwos_mlp* m, float* theta);
+
+/* N at n points X (device, n x dim FP32) into N (device n); if grad (device
+ * n x dim) or lap (device n) is non-NULL, also grad N and Lap N (value,
+ * gradient and Laplacian channels carried through every layer). */
+dwos_status dwos_mlp_eval(dwos_mlp* m, const float* X, int64_t n, float* N, float* grad, float* lap);
+
+/* Gradient of the training loss sum_i 1/2 w_i (N(x_i) - t_i)^2 (w device or
+ * NULL for all 1) into the network's gradient buffer; loss (device, one
+ * float, may be NULL) gets the loss and grad (device, theta size, may be
+ * NULL) a copy of the gradient. */
+dwos_status dwos_mlp_loss_grad(dwos_mlp* m, const float* X, const float* T, const float* w, int64_t n,
+                               float* loss, float* grad);
+
+/* One Adam step (Kingma and Ba 2015) with the last computed gradient. */
+dwos_status dwos_mlp_adam_step(dwos_mlp* m, float lr, float beta1, float beta2, float eps);
+
+/* Attach a network (not owned; NULL detaches) with nested-walk probability
+ * q in (0, 1] to a context: every later differential call (dwos_grad,
+ * dwos_grad_sqloss, dwos_jvp, dwos_walk_records mode 1) uses the control
+ * variate.  Errors: EINVAL (q, dimension or device mismatch). */
+dwos_status dwos_cv_attach(dwos_ctx* ctx, dwos_mlp* m, double q);
+
+/* Train the attached network for `steps` Adam steps (lr; beta 0.9, 0.999;
+ * eps 1e-8) on the records of the last differential chunk: each step draws
+ * `batch` walks (Philox key seed) and fits N(xoff) to the walk's
+ * N(xoff) + uhat + C_mean (nested walks that ran) and N(xbar) to g(xbar)
+ * (walks that reached the boundary), weight 1/batch each.  loss (device, one
+ * float, may be NULL) gets the last step's loss.  Records are consumed
+ * after they were used, so a network never sees the walks it corrects.
+ * Errors: ESTATE (no network or no records), EINVAL. */
+dwos_status dwos_cv_train(dwos_ctx* ctx, int32_t steps, int32_t batch, float lr, uint64_t seed,
+                          float* loss);
+
+/* Differential walks with the control variate, exported per walk (device
+ * P*W*9 FP64: run (-1 no terminal, 0 skipped, 1 run), xoff[3], plain nested
+ * mean, control-variate estimate, training target, u, terminal primitive)
+ * and per nested walk (device P*W*K*10: L, alive, xstop[3], y[3], rho, d).
+ * Errors: as dwos_walk_records; ESTATE without an attached network. */
+dwos_status dwos_cv_walk_records(dwos_ctx* ctx, const double* X, int64_t P, int32_t W, uint64_t seed,
+                                 double* walk, double* nested);
+
 #ifdef __cplusplus
 }
 #endif

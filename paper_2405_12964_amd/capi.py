@@ -81,6 +81,15 @@ def lib():
             "dwos_batch_add_instance": [vp, dp, C.c_int64, i32p, C.c_int64, i32p, C.c_double,
                                         C.c_double, C.c_double, i32p],
             "dwos_batch_solve": [vp, vp, i64p, C.c_int32, C.c_uint64, vp, vp, C.POINTER(dwos_stats)],
+            "dwos_mlp_create": [C.c_int32, C.c_int32, C.POINTER(C.c_float), vp, C.POINTER(vp)],
+            "dwos_mlp_set_params": [vp, vp],
+            "dwos_mlp_get_params": [vp, vp],
+            "dwos_mlp_eval": [vp, vp, C.c_int64, vp, vp, vp],
+            "dwos_mlp_loss_grad": [vp, vp, vp, vp, C.c_int64, vp, vp],
+            "dwos_mlp_adam_step": [vp, C.c_float, C.c_float, C.c_float, C.c_float],
+            "dwos_cv_attach": [vp, vp, C.c_double],
+            "dwos_cv_train": [vp, C.c_int32, C.c_int32, C.c_float, C.c_uint64, vp],
+            "dwos_cv_walk_records": [vp, vp, C.c_int64, C.c_int32, C.c_uint64, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -88,6 +97,10 @@ def lib():
             f.restype = st
         L.dwos_last_error.argtypes = []
         L.dwos_last_error.restype = C.c_char_p
+        L.dwos_mlp_theta_size.argtypes = []
+        L.dwos_mlp_theta_size.restype = C.c_int32
+        L.dwos_mlp_destroy.argtypes = [vp]
+        L.dwos_mlp_destroy.restype = None
         _lib = L
     return _lib
 
@@ -98,7 +111,9 @@ EXPORTED = [
     "dwos_set_problem", "dwos_set_parameters", "dwos_solve", "dwos_grad", "dwos_grad_sqloss",
     "dwos_jvp", "dwos_walk_records", "dwos_closest", "dwos_eval_ball_kernels", "dwos_walk_timing",
     "dwos_batch_add_instance", "dwos_batch_solve", "dwos_set_seed_buffer", "dwos_autotune",
-    "dwos_set_variant",
+    "dwos_set_variant", "dwos_mlp_theta_size", "dwos_mlp_create", "dwos_mlp_destroy",
+    "dwos_mlp_set_params", "dwos_mlp_get_params", "dwos_mlp_eval", "dwos_mlp_loss_grad",
+    "dwos_mlp_adam_step", "dwos_cv_attach", "dwos_cv_train", "dwos_cv_walk_records",
 ]
 
 

@@ -16,49 +16,17 @@
 
 #include "../../include/dwos.h"
 #include "aux_kernels.hpp"
+#include "cv_kernels.hpp"
+#include "host_common.hpp"
+#include "mlp.hpp"
 #include "bvh.hpp"
 
 namespace {
 
-thread_local std::string g_last_error;
-
-dwos_status fail(dwos_status code, const std::string& msg) {
-    g_last_error = msg;
-    return code;
-}
-
-#define HIP_OK(expr)                                                                     \
-    do {                                                                                 \
-        hipError_t e_ = (expr);                                                          \
-        if (e_ != hipSuccess)                                                            \
-            return fail(e_ == hipErrorOutOfMemory ? DWOS_ENOMEM : DWOS_EDEVICE,          \
-                        std::string(#expr) + ": " + hipGetErrorString(e_));              \
-    } while (0)
-
-// grow-only device buffer
-struct DevBuf {
-    void* ptr = nullptr;
-    size_t bytes = 0;
-    ~DevBuf() { if (ptr) (void)hipFree(ptr); }
-    hipError_t reserve(size_t b) {
-        if (b <= bytes) return hipSuccess;
-        if (ptr) { (void)hipFree(ptr); ptr = nullptr; bytes = 0; }
-        hipError_t e = hipMalloc(&ptr, std::max<size_t>(b, 256));
-        if (e == hipSuccess) bytes = std::max<size_t>(b, 256);
-        return e;
-    }
-    template <class U> U* as() const { return static_cast<U*>(ptr); }
-};
-
-template <class U>
-hipError_t upload(DevBuf& b, const U* host, size_t n, hipStream_t s) {
-    hipError_t e = b.reserve(n * sizeof(U));
-    if (e != hipSuccess) return e;
-    if (n == 0) return hipSuccess;
-    e = hipMemcpyAsync(b.ptr, host, n * sizeof(U), hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return e;
-    return hipStreamSynchronize(s);   // host vectors may die after return
-}
+using dwos_host::fail;
+using dwos_host::DevBuf;
+using dwos_host::upload;
+using dwos_host::blocks_for;
 
 constexpr int64_t kMaxWalksPerChunk = int64_t(1) << 26;
 
@@ -99,7 +67,7 @@ struct dwos_ctx {
     DevBuf rowptr, pid, vel, bc_pid, colptr, cvert, cvel, bcptr, bcvert;
     bool has_bc_params = false;
     // workspaces
-    DevBuf rec_u, rec_prim, rec_b, rec_uoff, rec_steps, accA, accB, queue, counters, instbuf, walk_udot;
+    DevBuf rec_u, rec_prim, rec_b, rec_uoff, rec_steps, accA, accB, queue, counters, instbuf, export_u;
     DevBuf vtmp;   // V(pi) for dwos_apply_parameters
     DevBuf first_leaf, first_d2;   // shared first query of each start point
     const uint64_t* seed_dev = nullptr;   // optional device seed offset
@@ -110,6 +78,13 @@ struct dwos_ctx {
     double timed_ms[2] = {0.0, 0.0};
     int64_t timed_launches[2] = {0, 0};
     DevBuf totals;   // 2 x Counters
+    // learned control variate of the nested walks (not owned)
+    dwos_mlp* cv = nullptr;
+    uint32_t cv_qthresh = 1u << 24;
+    DevBuf cv_run, cv_xoff, cv_xbar, cv_g, cv_stop, cv_y, cv_rho, cv_d, cv_La;
+    DevBuf cv_Noff, cv_Nstop, cv_Ny, cv_Ly, cv_target, cv_uplain;
+    DevBuf cv_bx, cv_bt, cv_bw;   // training batch
+    int64_t cv_nrec = 0;          // walks recorded by the last differential chunk
 };
 
 namespace {
@@ -187,7 +162,6 @@ dwos::ParamCSR make_csr(dwos_ctx* c) {
     return J;
 }
 
-inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 // Upload a built BVH + geometry in the working precision T.
 template <class T>
@@ -383,6 +357,24 @@ dwos_status ensure_records(dwos_ctx* c, int64_t walks, bool diff, bool steps) {
         HIP_OK(c->rec_uoff.reserve(walks * sizeof(T)));
     }
     if (steps) HIP_OK(c->rec_steps.reserve(walks * sizeof(int64_t)));
+    if (diff && c->cv) {
+        const int64_t nk = walks * c->prob.K;
+        HIP_OK(c->cv_run.reserve(walks * sizeof(int32_t)));
+        HIP_OK(c->cv_xoff.reserve(walks * c->D * sizeof(T)));
+        HIP_OK(c->cv_xbar.reserve(walks * c->D * sizeof(T)));
+        HIP_OK(c->cv_g.reserve(walks * sizeof(T)));
+        HIP_OK(c->cv_target.reserve(walks * sizeof(T)));
+        HIP_OK(c->cv_uplain.reserve(walks * sizeof(T)));
+        HIP_OK(c->cv_Noff.reserve(walks * sizeof(float)));
+        HIP_OK(c->cv_stop.reserve(nk * c->D * sizeof(T)));
+        HIP_OK(c->cv_y.reserve(nk * c->D * sizeof(T)));
+        HIP_OK(c->cv_rho.reserve(nk * sizeof(T)));
+        HIP_OK(c->cv_d.reserve(nk * sizeof(T)));
+        HIP_OK(c->cv_La.reserve(nk * sizeof(int32_t)));
+        HIP_OK(c->cv_Nstop.reserve(nk * sizeof(float)));
+        HIP_OK(c->cv_Ny.reserve(nk * sizeof(float)));
+        HIP_OK(c->cv_Ly.reserve(nk * sizeof(float)));
+    }
     HIP_OK(c->queue.reserve(sizeof(unsigned long long)));
     HIP_OK(c->counters.reserve(sizeof(dwos::Counters)));
     return DWOS_OK;
@@ -406,7 +398,59 @@ dwos::WalkArgs<T> base_args(dwos_ctx* c, const double* X, int32_t W, uint64_t se
     a.rec_b = c->rec_b.as<T>();
     a.rec_uoff = c->rec_uoff.as<T>();
     a.rec_steps = nullptr;
+    a.cv_run = nullptr;
+    a.cv_qthresh = 1u << 24;
     return a;
+}
+
+// Attach the control-variate records to a differential launch.
+template <class T>
+void cv_args(dwos_ctx* c, dwos::WalkArgs<T>& a) {
+    a.cv_run = c->cv_run.as<int32_t>();
+    a.cv_xoff = c->cv_xoff.as<T>();
+    a.cv_xbar = c->cv_xbar.as<T>();
+    a.cv_g = c->cv_g.as<T>();
+    a.cv_stop = c->cv_stop.as<T>();
+    a.cv_y = c->cv_y.as<T>();
+    a.cv_rho = c->cv_rho.as<T>();
+    a.cv_d = c->cv_d.as<T>();
+    a.cv_La = c->cv_La.as<int32_t>();
+    a.cv_qthresh = c->cv_qthresh;
+}
+
+// Network values at the recorded points, then the control-variate estimate
+// of every nested mean (in place in rec_uoff).
+template <class T, int D>
+dwos_status cv_apply(dwos_ctx* c, int64_t walks, bool keep_plain) {
+    hipStream_t s = c->stream;
+    const int K = c->prob.K;
+    const int32_t* run = c->cv_run.as<int32_t>();
+    HIP_OK(dwos_host::mlp_eval_launch<T>(c->cv, s, c->cv_xoff.as<T>(), walks, run, 1, 0,
+                                         c->cv_Noff.as<float>(), nullptr, nullptr));
+    HIP_OK(dwos_host::mlp_eval_launch<T>(c->cv, s, c->cv_stop.as<T>(), walks * K, run, K, 1,
+                                         c->cv_Nstop.as<float>(), nullptr, nullptr));
+    HIP_OK(dwos_host::mlp_eval_launch<T>(c->cv, s, c->cv_y.as<T>(), walks * K, run, K, 1,
+                                         c->cv_Ny.as<float>(), nullptr, c->cv_Ly.as<float>()));
+    dwos::CvCombineArgs<T> ca{};
+    ca.run = run;
+    ca.La = c->cv_La.as<int32_t>();
+    ca.rho = c->cv_rho.as<T>();
+    ca.d = c->cv_d.as<T>();
+    ca.Noff = c->cv_Noff.as<float>();
+    ca.Nstop = c->cv_Nstop.as<float>();
+    ca.Ny = c->cv_Ny.as<float>();
+    ca.Ly = c->cv_Ly.as<float>();
+    ca.uoff = c->rec_uoff.as<T>();
+    ca.target = c->cv_target.as<T>();
+    ca.uoff_plain = keep_plain ? c->cv_uplain.as<T>() : nullptr;
+    ca.nwalks = walks;
+    ca.K = K;
+    ca.sigma = T(c->prob.sigma);
+    ca.kappa = T(std::sqrt(c->prob.sigma));
+    ca.inv_q = T(16777216.0 / (double)c->cv_qthresh);
+    hipLaunchKernelGGL((dwos::cv_combine_kernel<T, D>), dim3(blocks_for(walks, 256)), dim3(256), 0, s, ca);
+    c->cv_nrec = walks;
+    return DWOS_OK;
 }
 
 // Upload an instance table (skipped when identical to the last one).  The
@@ -503,6 +547,9 @@ struct OpArgs {
     double* rec_uoff_out;
     double* rec_udot_out;
     int32_t mode;
+    // control-variate record export (oracle layout)
+    double* cv_walk_out;
+    double* cv_nested_out;
 };
 
 template <class T>
@@ -562,10 +609,23 @@ dwos_status run_op(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
         a.first_d2 = c->first_d2.as<T>();
         a.x_base = p0;
         a.rec_steps = op == Op::Records ? c->rec_steps.as<int64_t>() : nullptr;
+        const bool use_cv = diff && c->cv != nullptr;
+        if (use_cv) cv_args<T>(c, a);
         // walk ids within a chunk restart at 0; the instance's p_counter = p0
         // keeps the Philox point word absolute
         rc = diff ? launch_walks<T, D, 1>(c, a) : launch_walks<T, D, 0>(c, a);
         if (rc) return rc;
+        if (use_cv) {
+            rc = cv_apply<T, D>(c, walks, o.cv_walk_out != nullptr);
+            if (rc) return rc;
+            if (o.cv_walk_out)
+                hipLaunchKernelGGL((dwos::cv_export_kernel<T, D>), dim3(blocks_for(walks, 256)), dim3(256), 0, s,
+                                   c->cv_run.as<int32_t>(), c->cv_xoff.as<T>(), c->cv_uplain.as<T>(),
+                                   c->rec_uoff.as<T>(), c->cv_target.as<T>(), c->rec_u.as<T>(),
+                                   c->rec_prim.as<int32_t>(), c->cv_La.as<int32_t>(), c->cv_stop.as<T>(),
+                                   c->cv_y.as<T>(), c->cv_rho.as<T>(), c->cv_d.as<T>(), walks, c->prob.K,
+                                   p0 * W, o.cv_walk_out, o.cv_nested_out);
+        }
         // per-point statistics
         if (o.u_mean) {
             hipLaunchKernelGGL(dwos::point_stats_kernel<T>, dim3(blocks_for(Pc, 4)), dim3(256), 0, s,
@@ -644,7 +704,7 @@ dwos_status dispatch(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
 // ===========================================================================
 extern "C" {
 
-const char* dwos_last_error(void) { return g_last_error.c_str(); }
+const char* dwos_last_error(void) { return dwos_host::g_last_error.c_str(); }
 
 dwos_status dwos_create(int32_t dim, int32_t precision, void* stream, dwos_ctx** out) {
     if (!out) return fail(DWOS_EINVAL, "dwos_create: out is NULL");
@@ -933,6 +993,78 @@ dwos_status dwos_walk_records(dwos_ctx* c, const double* X, int64_t P, int32_t W
     OpArgs o{};
     o.X = X; o.P = P; o.W = W; o.seed = seed; o.mode = mode;
     o.rec_u_out = u; o.rec_steps_out = steps; o.rec_prim_out = prim; o.rec_uoff_out = uoff; o.rec_udot_out = udot;
+    return dispatch(c, Op::Records, o, nullptr);
+}
+
+dwos_status dwos_cv_attach(dwos_ctx* c, dwos_mlp* m, double q) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (m) {
+        if (!(q > 0.0 && q <= 1.0)) return fail(DWOS_EINVAL, "cv_attach: q must lie in (0, 1]");
+        if (m->dim != c->D) return fail(DWOS_EINVAL, "cv_attach: network dimension differs from the context");
+        if (m->device != c->device) return fail(DWOS_EINVAL, "cv_attach: network on another device");
+        double t = std::round(q * 16777216.0);
+        if (t < 1.0) t = 1.0;
+        c->cv_qthresh = (uint32_t)t;
+    } else {
+        c->cv_qthresh = 1u << 24;
+    }
+    c->cv = m;
+    c->cv_nrec = 0;
+    return DWOS_OK;
+}
+
+dwos_status dwos_cv_train(dwos_ctx* c, int32_t steps, int32_t batch, float lr, uint64_t seed, float* loss) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (!c->cv) return fail(DWOS_ESTATE, "cv_train: no network attached");
+    if (c->cv_nrec <= 0) return fail(DWOS_ESTATE, "cv_train: no differential walks recorded since attaching");
+    if (steps < 0 || batch < 1 || !(lr > 0.f)) return fail(DWOS_EINVAL, "cv_train: bad steps, batch or lr");
+    HIP_OK(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    const int D = c->D;
+    HIP_OK(c->cv_bx.reserve((size_t)2 * batch * D * sizeof(float)));
+    HIP_OK(c->cv_bt.reserve((size_t)2 * batch * sizeof(float)));
+    HIP_OK(c->cv_bw.reserve((size_t)2 * batch * sizeof(float)));
+    for (int32_t it = 0; it < steps; ++it) {
+        auto gather = [&](auto tag) {
+            using T = decltype(tag);
+            if (D == 2)
+                hipLaunchKernelGGL((dwos::cv_gather_kernel<T, 2>), dim3(blocks_for(batch, 256)), dim3(256), 0, s,
+                                   c->cv_run.as<int32_t>(), c->cv_xoff.as<T>(), c->cv_xbar.as<T>(), c->cv_g.as<T>(),
+                                   c->cv_target.as<T>(), c->cv_nrec, batch, (uint32_t)it, (uint32_t)seed,
+                                   (uint32_t)(seed >> 32), c->cv_bx.as<float>(), c->cv_bt.as<float>(),
+                                   c->cv_bw.as<float>());
+            else
+                hipLaunchKernelGGL((dwos::cv_gather_kernel<T, 3>), dim3(blocks_for(batch, 256)), dim3(256), 0, s,
+                                   c->cv_run.as<int32_t>(), c->cv_xoff.as<T>(), c->cv_xbar.as<T>(), c->cv_g.as<T>(),
+                                   c->cv_target.as<T>(), c->cv_nrec, batch, (uint32_t)it, (uint32_t)seed,
+                                   (uint32_t)(seed >> 32), c->cv_bx.as<float>(), c->cv_bt.as<float>(),
+                                   c->cv_bw.as<float>());
+        };
+        if (c->prec == DWOS_FP32) gather(float{}); else gather(double{});
+        HIP_OK(hipGetLastError());
+        HIP_OK(dwos_host::mlp_loss_grad_launch(c->cv, s, c->cv_bx.as<float>(), c->cv_bt.as<float>(),
+                                               c->cv_bw.as<float>(), 2 * (int64_t)batch,
+                                               it + 1 == steps ? loss : nullptr));
+        HIP_OK(dwos_host::mlp_adam_launch(c->cv, s, lr, 0.9f, 0.999f, 1e-8f));
+    }
+    return DWOS_OK;
+}
+
+dwos_status dwos_cv_walk_records(dwos_ctx* c, const double* X, int64_t P, int32_t W, uint64_t seed,
+                                 double* walk, double* nested) {
+    dwos_status rc = begin_call(c, false);
+    if (rc) return rc;
+    if ((rc = check_points(X, P, W))) return rc;
+    if (!c->cv) return fail(DWOS_ESTATE, "cv_walk_records: no network attached");
+    if (P > 0 && (!walk || !nested)) return fail(DWOS_EINVAL, "cv_walk_records: NULL output");
+    HIP_OK(c->rec_u.reserve(1));
+    OpArgs o{};
+    o.X = X; o.P = P; o.W = W; o.seed = seed; o.mode = 1;
+    o.cv_walk_out = walk;
+    o.cv_nested_out = nested;
+    // the plain per-walk arrays are not exported: keep them in the context
+    HIP_OK(c->export_u.reserve(std::max<int64_t>(1, P * W) * sizeof(double)));
+    o.rec_u_out = c->export_u.as<double>();
     return dispatch(c, Op::Records, o, nullptr);
 }
 

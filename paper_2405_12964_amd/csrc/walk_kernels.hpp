@@ -104,6 +104,22 @@ struct WalkArgs {
     const int32_t* first_leaf;
     const T* first_d2;
     int64_t x_base;
+    // control variate of the nested walks (MODE 1; cv_run == nullptr: off).
+    // Per walk: cv_run (-1 no terminal, 0 nested walks skipped, 1 run),
+    // the offset point, the terminal point and g there.  Per nested walk
+    // (walk-major, K per walk): the stop point, the reservoir-chosen ball
+    // sample y = x_J + rho d_J dir, and 2 L + alive (L source steps; alive:
+    // ended in the shell or at the cap rather than by roulette).
+    int32_t* cv_run;
+    T* cv_xoff;
+    T* cv_xbar;
+    T* cv_g;
+    T* cv_stop;
+    T* cv_y;
+    T* cv_rho;
+    T* cv_d;
+    int32_t* cv_La;
+    uint32_t cv_qthresh;     // nested walks run iff (u32 >> 8) < cv_qthresh; 1 << 24: always
 };
 
 // ---------------------------------------------------------------------------
@@ -613,6 +629,11 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
     int32_t root = 0, warm = -1, term_leaf = -1, term_code = -1, phase = 0;
     T term_b1 = T(0), term_b2 = T(0);
     int64_t wsteps = 0;
+    // control-variate trace of the current nested walk
+    int32_t cv_L = 0;
+    T ysel[D], rho_sel = T(0), d_sel = T(0);
+#pragma unroll
+    for (int c = 0; c < D; ++c) ysel[c] = T(0);
     // lane statistics
     unsigned long long c_walks = 0, c_nested = 0, c_steps = 0, c_term = 0, c_trunc = 0,
                        c_nodes = 0, c_prims = 0, c_ovf = 0, c_invalid = 0;
@@ -692,7 +713,11 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
             c_invalid++;
             const T nanv = T(NAN);
             a.rec_u[wid] = nanv;
-            if (MODE == 1) { a.rec_prim[wid] = -1; a.rec_uoff[wid] = nanv; }
+            if (MODE == 1) {
+                a.rec_prim[wid] = -1;
+                a.rec_uoff[wid] = nanv;
+                if (a.cv_run) a.cv_run[wid] = -1;
+            }
             if (a.rec_steps) a.rec_steps[wid] = wsteps;
             wid = -1;
             continue;
@@ -701,6 +726,7 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
         const bool cap = (int)(k + 1) >= a.prm.kmax;
         const bool nested = MODE == 1 && phase > 0;
         bool finished = false;     // the current (main or nested) walk ended
+        bool alive = false;        // ... in the shell or at the cap (not by roulette)
         T result = T(0);           // its value
         if (d < eps || cap) {
             if (cap && !(d < eps)) c_trunc++;
@@ -740,8 +766,34 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
 #pragma unroll
                 for (int c = 0; c < D; ++c) xoff[c] = xbar[c] - delta * n[c];
                 c_term++;
+                if (a.cv_run) {
+#pragma unroll
+                    for (int c = 0; c < D; ++c) {
+                        a.cv_xoff[(size_t)wid * D + c] = xoff[c];
+                        a.cv_xbar[(size_t)wid * D + c] = xbar[c];
+                    }
+                    a.cv_g[wid] = g;
+                    int run = 1;
+                    if (a.cv_qthresh < (1u << 24)) {
+                        // run the nested walks with probability q
+                        const u4 rq = philox10(u4{k, m, p, inst_tag | 4u}, key0, key1);
+                        run = (rq.x >> 8) < a.cv_qthresh ? 1 : 0;
+                    }
+                    a.cv_run[wid] = run;
+                    if (!run) {
+                        a.rec_u[wid] = u_main;
+                        a.rec_prim[wid] = term_code;
+                        a.rec_b[(size_t)wid * (D - 1)] = term_b1;
+                        if constexpr (D == 3) a.rec_b[(size_t)wid * 2 + 1] = term_b2;
+                        a.rec_uoff[wid] = T(0);
+                        if (a.rec_steps) a.rec_steps[wid] = wsteps;
+                        wid = -1;
+                        continue;
+                    }
+                }
                 // start the first nested forward walk at the offset point
                 phase = 1;
+                cv_L = 0; rho_sel = T(0); d_sel = T(0);
 #pragma unroll
                 for (int c = 0; c < D; ++c) x[c] = xoff[c];
                 acc = T(0); k = 0; warm = term_leaf;
@@ -749,10 +801,28 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
                 continue;
             }
             finished = true;
+            alive = true;
             result = acc + g;
         } else {
             const uint32_t tag = inst_tag | (nested ? (1u | ((uint32_t)(phase - 1) << 8)) : 0u);
             const u4 r = philox10(u4{k, m, p, tag}, key0, key1);
+            if (MODE == 1 && nested && a.cv_run) {
+                // reservoir choice of one source step, uniform over the walk's
+                // source steps, with one uniform point of its ball
+                ++cv_L;
+                const u4 r3 = philox10(u4{k, m, p, tag | 4u}, key0, key1);
+                if ((unsigned long long)(r3.x >> 8) * (unsigned long long)cv_L < (1ull << 24)) {
+                    T dir[3];
+                    unit_dir<T, D>(r3.y, r3.z, dir);
+                    T rho;
+                    if constexpr (D == 2) rho = sqrt(unif_pos<T>(r3.w));
+                    else rho = cbrt(unif_pos<T>(r3.w));
+#pragma unroll
+                    for (int c = 0; c < D; ++c) ysel[c] = x[c] + rho * d * dir[c];
+                    rho_sel = rho;
+                    d_sel = d;
+                }
+            }
             if (a.prm.has_source) {
                 const u4 r2 = philox10(u4{k, m, p, tag | 2u}, key0, key1);
                 T dir[3];
@@ -790,10 +860,22 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
             a.rec_u[wid] = result;
             a.rec_prim[wid] = -1;
             a.rec_uoff[wid] = T(0);
+            if (a.cv_run) a.cv_run[wid] = -1;
             if (a.rec_steps) a.rec_steps[wid] = wsteps;
             wid = -1;
         } else {
             usum += result;
+            if (a.cv_run) {
+                const size_t q = (size_t)wid * a.prm.K + (phase - 1);
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    a.cv_stop[q * D + c] = x[c];
+                    a.cv_y[q * D + c] = ysel[c];
+                }
+                a.cv_rho[q] = rho_sel;
+                a.cv_d[q] = d_sel;
+                a.cv_La[q] = 2 * cv_L + (alive ? 1 : 0);
+            }
             if (phase >= a.prm.K) {
                 a.rec_u[wid] = u_main;
                 a.rec_prim[wid] = term_code;
@@ -807,6 +889,7 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
 #pragma unroll
                 for (int c = 0; c < D; ++c) x[c] = xoff[c];
                 acc = T(0); k = 0; warm = term_leaf;
+                cv_L = 0; rho_sel = T(0); d_sel = T(0);
                 c_nested++;
             }
         }

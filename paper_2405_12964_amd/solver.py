@@ -118,6 +118,7 @@ class Solver:
 
     def set_problem(self, prob: capi.dwos_problem):
         check(capi.dwos_set_problem(self._ctx, C.byref(prob)))
+        self._K = int(prob.K)
 
     def set_parameters(self, N, rowptr, pid, vel, bc_pid=None):
         rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
@@ -258,6 +259,35 @@ class Solver:
         call, so that a captured graph replays with fresh streams."""
         self._seed_buf = seed_dev
         check(capi.dwos_set_seed_buffer(self._ctx, _dev(seed_dev, torch.int64) if seed_dev is not None else None))
+
+    # ---- learned control variate of the nested walks ----------------------
+    def attach_cv(self, net, q: float = 1.0):
+        """Use net (a cv.Network, or None to detach) as the control variate of
+        every later differential call; nested walks run with probability q."""
+        self._cv = net
+        check(capi.dwos_cv_attach(self._ctx, net.handle if net is not None else None, float(q)))
+
+    def cv_train(self, steps: int, batch: int, lr: float, seed: int):
+        """Adam steps of the attached network on the last differential walks'
+        records; returns the last step's loss (device float32 tensor)."""
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        check(capi.dwos_cv_train(self._ctx, int(steps), int(batch), float(lr), int(seed),
+                                 C.c_void_p(loss.data_ptr())))
+        return loss
+
+    def cv_walk_records(self, X, W, seed):
+        X = self._X(X)
+        P = X.shape[0]
+        K = self._K
+        walk = torch.empty(P * W * 9, dtype=torch.float64, device=X.device)
+        nested = torch.empty(P * W * K * 10, dtype=torch.float64, device=X.device)
+        check(capi.dwos_cv_walk_records(self._ctx, _dev(X), P, int(W), int(seed), _dev(walk), _dev(nested)))
+        w = walk.view(P, W, 9)
+        n = nested.view(P, W, K, 10)
+        return dict(run=w[..., 0].to(torch.int32), xoff=w[..., 1:4], uoff=w[..., 4], uoff_cv=w[..., 5],
+                    target=w[..., 6], u=w[..., 7], prim=w[..., 8].to(torch.int32),
+                    L=n[..., 0].to(torch.int64), alive=n[..., 1].to(torch.int32), xstop=n[..., 2:5],
+                    y=n[..., 5:8], rho=n[..., 8], d=n[..., 9])
 
     def walk_timing(self, kind: int, reset=False):
         """(ms, launches, totals dict) of the walk kernels of one kind

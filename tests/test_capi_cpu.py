@@ -19,7 +19,7 @@ HEADER = os.path.join(ROOT, "include", "dwos.h")
 
 def declared():
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"^(?:dwos_status|const char\*)\s+(dwos_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^(?:dwos_status|const char\*|int32_t|void)\s+(dwos_\w+)\s*\(", txt, re.M)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -67,3 +67,11 @@ def test_create_without_gpu_reports_device_error():
     assert capi.dwos_last_error()  # message set
     assert capi.dwos_create(4, capi.DWOS_FP32, None, C.byref(ctx)) == capi.DWOS_EINVAL
     assert capi.dwos_destroy(None) == capi.DWOS_OK
+    # the control-variate network needs a device too
+    m = C.c_void_p()
+    B = (C.c_float * 32)()
+    assert capi.dwos_mlp_create(2, 16, B, None, C.byref(m)) == capi.DWOS_EDEVICE
+    assert m.value is None
+    assert capi.dwos_mlp_create(2, 40, B, None, C.byref(m)) == capi.DWOS_EINVAL
+    assert capi.dwos_mlp_theta_size() == 4 * (64 * 64 + 64) + 65
+    assert capi.dwos_cv_attach(None, None, 1.0) == capi.DWOS_EINVAL
