@@ -301,7 +301,11 @@ dwos_status dwos_batch_solve(dwos_ctx* ctx, const double* X_all, const int64_t* 
  * 4 of each nested step) weighted by the number of source steps, and C_mean
  * averages C over the K nested walks.  The mean is that of the plain
  * estimator for any N and q; the variance vanishes as N approaches u.  The
- * walks themselves (and their random numbers) are unchanged. */
+ * walks themselves (and their random numbers) are unchanged.
+ * C enters with a coefficient beta (N(xoff) and C_mean scaled by beta):
+ * 1 on the first call after attaching, then the variance-minimising
+ * -E[uhat C] / E[C^2] estimated on the device from the previous call's walks
+ * and clamped to [0, 1], so it never depends on the walks it weights. */
 typedef struct dwos_mlp dwos_mlp;
 
 int32_t dwos_mlp_theta_size(void);
@@ -329,6 +333,14 @@ dwos_status dwos_mlp_eval(dwos_mlp* m, const float* X, int64_t n, float* N, floa
 dwos_status dwos_mlp_loss_grad(dwos_mlp* m, const float* X, const float* T, const float* w, int64_t n,
                                float* loss, float* grad);
 
+/* Gradient of sum_i (Nbar_i N(x_i) + Lbar_i Lap N(x_i)) (Nbar, Lbar device
+ * n floats; Lbar may be NULL) into the network's gradient buffer; grad
+ * (device, may be NULL) gets a copy.  The Laplacian's parameter derivative is
+ * carried by reverse mode through the value, gradient and Laplacian
+ * channels of every layer. */
+dwos_status dwos_mlp_vjp(dwos_mlp* m, const float* X, const float* Nbar, const float* Lbar, int64_t n,
+                         float* grad);
+
 /* One Adam step (Kingma and Ba 2015) with the last computed gradient. */
 dwos_status dwos_mlp_adam_step(dwos_mlp* m, float lr, float beta1, float beta2, float eps);
 
@@ -338,14 +350,21 @@ dwos_status dwos_mlp_adam_step(dwos_mlp* m, float lr, float beta1, float beta2, 
  * variate.  Errors: EINVAL (q, dimension or device mismatch). */
 dwos_status dwos_cv_attach(dwos_ctx* ctx, dwos_mlp* m, double q);
 
+/* The coefficient beta the next differential call will use (host output;
+ * synchronises the context stream).  Errors: EINVAL, ESTATE (no network). */
+dwos_status dwos_cv_beta(dwos_ctx* ctx, double* beta);
+
 /* Train the attached network for `steps` Adam steps (lr; beta 0.9, 0.999;
- * eps 1e-8) on the records of the last differential chunk: each step draws
- * `batch` walks (Philox key seed) and fits N(xoff) to the walk's
- * N(xoff) + uhat + C_mean (nested walks that ran) and N(xbar) to g(xbar)
- * (walks that reached the boundary), weight 1/batch each.  loss (device, one
- * float, may be NULL) gets the last step's loss.  Records are consumed
- * after they were used, so a network never sees the walks it corrects.
- * Errors: ESTATE (no network or no records), EINVAL. */
+ * eps 1e-8) on the records of the last differential chunk.  The objective is
+ * the sample variance of the control-variate estimate: since E[C] = 0,
+ * E[(uhat + C)^2] = Var(uhat + C) + u^2, so each step draws `batch` walks
+ * (Philox key seed) and minimises the mean of (uhat + C)^2/2 (through N at
+ * the offset and stop points and N, Lap N at the ball samples) plus
+ * (N(xbar) - g(xbar))^2/2 at their terminal points (N(xoff) serves as a
+ * baseline held fixed in the differentiation).  loss (device, one
+ * float, may be NULL) gets the last step's objective.  Records are consumed
+ * after they were used, so a network never corrects the walks it was
+ * trained on.  Errors: ESTATE (no network or no records), EINVAL. */
 dwos_status dwos_cv_train(dwos_ctx* ctx, int32_t steps, int32_t batch, float lr, uint64_t seed,
                           float* loss);
 

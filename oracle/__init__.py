@@ -51,6 +51,8 @@ def lib():
         L.oracle_green.restype = C.c_double
         L.oracle_poisson_scale.argtypes = [C.c_int, C.c_double, C.c_double]
         L.oracle_poisson_scale.restype = C.c_double
+        L.oracle_green_mass.argtypes = [C.c_int, C.c_double, C.c_double]
+        L.oracle_green_mass.restype = C.c_double
         L.oracle_closest.argtypes = [sp, dp, dp]
         L.oracle_walk_records.argtypes = [sp, dp, C.c_int64, C.c_int32, C.c_uint64, C.c_int32,
                                           C.c_int32, dp, dp, lp, ip, dp, lp, dp, C.c_int]
@@ -67,6 +69,7 @@ def lib():
         L.oracle_mlp_theta_size.restype = C.c_int32
         L.oracle_mlp_loss_grad.argtypes = [C.c_int32, C.c_int32, dp, dp, dp, dp, dp, C.c_int64,
                                            dp, dp]
+        L.oracle_mlp_vjp.argtypes = [C.c_int32, C.c_int32, dp, dp, dp, dp, dp, C.c_int64, dp]
         L.oracle_adam.argtypes = [C.c_int64, dp, dp, dp, dp, C.c_double, C.c_double, C.c_double,
                                   C.c_double, C.c_int64]
         L.oracle_walk_records_cv.argtypes = [sp, cvp, dp, C.c_int64, C.c_int32, C.c_uint64,
@@ -238,7 +241,7 @@ class Oracle:
     def walk_records_cv(self, X, W, seed, cv, instance=0):
         """Differential walks with the control variate: per-walk records
         (run, xoff, uoff plain, uoff_cv, target, u, prim) and per nested walk
-        (L, alive, xstop, y, rho, d)."""
+        (S, alive, xstop, y, rho, d)."""
         X = self._X(X)
         P = X.shape[0]
         K = int(self.scene.K)
@@ -252,7 +255,7 @@ class Oracle:
         n = nested.reshape(P, W, K, 10)
         return dict(run=w[..., 0].astype(np.int32), xoff=w[..., 1:4], uoff=w[..., 4],
                     uoff_cv=w[..., 5], target=w[..., 6], u=w[..., 7], prim=w[..., 8].astype(np.int32),
-                    L=n[..., 0].astype(np.int64), alive=n[..., 1].astype(np.int32),
+                    S=n[..., 0], alive=n[..., 1].astype(np.int32),
                     xstop=n[..., 2:5], y=n[..., 5:8], rho=n[..., 8], d=n[..., 9])
 
 
@@ -297,6 +300,22 @@ class Net:
         return float(L[0]), g
 
 
+def _vjp(self, X, Nbar, Lbar=None):
+    """d/dtheta sum_i (Nbar_i N(x_i) + Lbar_i Lap N(x_i))."""
+    X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, self.dim)
+    Nb = np.ascontiguousarray(Nbar, dtype=np.float64)
+    Lb = None if Lbar is None else np.ascontiguousarray(Lbar, dtype=np.float64)
+    g = np.zeros(theta_size())
+    rc = lib().oracle_mlp_vjp(self.dim, self.B.shape[0], _ptr(self.B, C.c_double),
+                              _ptr(self.theta, C.c_double), _ptr(X, C.c_double), _ptr(Nb, C.c_double),
+                              _ptr(Lb, C.c_double), X.shape[0], _ptr(g, C.c_double))
+    assert rc == 0
+    return g
+
+
+Net.vjp = _vjp
+
+
 def _cvref(cv):
     return C.byref(cv._c) if cv is not None else None
 
@@ -328,3 +347,7 @@ def green(dim, sigma, r, R):
 
 def poisson_scale(dim, sigma, R):
     return lib().oracle_poisson_scale(dim, sigma, R)
+
+
+def green_mass(dim, sigma, R):
+    return lib().oracle_green_mass(dim, sigma, R)

@@ -248,6 +248,19 @@ struct Scene {
     // ----- boundary data g, its spatial gradient, and its surface gradient --
     bool mapped(int prim) const { return s.bc_kind[lab(prim)] == 1; }
 
+    // Does the boundary at this primitive depend on a parameter (a vertex with
+    // a velocity row or a parameterised value)?  Scenes without parameters
+    // count as dependent everywhere.
+    bool depends(int prim) const {
+        if (s.N <= 0 || !s.rowptr) return true;
+        for (int k = 0; k < D; ++k) {
+            const int vi = pv(prim, k);
+            if (s.rowptr[vi + 1] > s.rowptr[vi]) return true;
+            if (s.bc_pid && s.bc_pid[vi] >= 0) return true;
+        }
+        return false;
+    }
+
     double g(const Hit& h) const {
         int L = lab(h.prim);
         if (s.bc_kind[L] == 1) {
@@ -340,6 +353,30 @@ double green(int D, double sigma, double r, double R) {
     if (sigma == 0.0) return (1.0 / r - 1.0 / R) / (4 * M_PI);
     double k = std::sqrt(sigma);
     return std::sinh(k * (R - r)) / (4 * M_PI * r * std::sinh(k * R));
+}
+
+// Mass of the Green's function over the ball, int_B G dy = (1 - Q(R))/sigma
+// (R^2/(2D) at sigma = 0): the expected source integral of one step for a
+// unit source.  1 - Q is summed from its power series where Q is close to 1:
+//   2D: 1 - 1/I0(x) = (I0(x) - 1)/I0(x),  I0(x) - 1 = sum_{k>=1} (x^2/4)^k/(k!)^2
+//   3D: 1 - x/sinh x = (sinh x - x)/sinh x,  sinh x - x = sum_{k>=1} x^(2k+1)/(2k+1)!
+double green_mass(int D, double sigma, double R) {
+    if (sigma == 0.0) return R * R / (2 * D);
+    const double x = std::sqrt(sigma) * R;
+    if (D == 2) {
+        if (x < 2.0) {
+            double t = 1, s = 0;
+            for (int k = 1; k <= 40; ++k) { t *= (x * x / 4) / ((double)k * k); s += t; }
+            return s / ((1 + s) * sigma);
+        }
+        return (1 - 1 / std::cyl_bessel_i(0.0, x)) / sigma;
+    }
+    if (x < 1.0) {
+        double t = x, s = 0;
+        for (int k = 1; k <= 20; ++k) { t *= x * x / ((2.0 * k) * (2.0 * k + 1)); s += t; }
+        return s / (std::sinh(x) * sigma);
+    }
+    return (1 - x / std::sinh(x)) / sigma;
 }
 
 // Uniform directions and ball points from 24-bit uniforms.
@@ -486,6 +523,83 @@ double mlp_loss_grad(int D, int F, const double* B, const double* theta, const d
     return loss;
 }
 
+// Vector-Jacobian product through the value and Laplacian of the network:
+// grad += d/dtheta sum_i (Nbar_i N(x_i) + Lbar_i Lap N(x_i)).  The forward
+// pass keeps, per layer, the pre-activation value z, its spatial gradient
+// z_c and Laplacian z_L; with h = tanh z, s = 1 - h^2, Q = sum_c z_c^2 the
+// layer outputs are (h, s z_c, s z_L - 2 h s Q), whose adjoints give
+//   zbar_L = s abar_L
+//   zbar_c = s abar_c - 4 h s z_c abar_L
+//   zbar   = s abar - 2 h s sum_c z_c abar_c - (2 h s z_L + 2 s (s - 2 h^2) Q) abar_L
+// and every channel goes back through W^T.
+void mlp_vjp(int D, int F, const double* B, const double* theta, const double* x, double Nbar,
+             double Lbar, double* grad) {
+    constexpr int NC = 5;   // value, 3 gradient components, Laplacian
+    double a[kLayers + 1][NC][kWidth] = {};
+    double z[kLayers][NC][kWidth] = {};
+    {
+        double v[kWidth], g[kWidth][3], L[kWidth];
+        mlp_features(D, F, B, x, v, g, L);
+        for (int i = 0; i < kWidth; ++i) {
+            a[0][0][i] = v[i];
+            for (int c = 0; c < 3; ++c) a[0][1 + c][i] = g[i][c];
+            a[0][4][i] = L[i];
+        }
+    }
+    for (int l = 0; l < kLayers; ++l) {
+        const double* W = theta + (size_t)l * kLayerSize;
+        const double* b = W + kWidth * kWidth;
+        for (int o = 0; o < kWidth; ++o) {
+            for (int ch = 0; ch < NC; ++ch) {
+                double acc = ch == 0 ? b[o] : 0.0;
+                for (int i = 0; i < kWidth; ++i) acc += W[o * kWidth + i] * a[l][ch][i];
+                z[l][ch][o] = acc;
+            }
+            double h = std::tanh(z[l][0][o]), s = 1 - h * h, Q = 0;
+            for (int c = 0; c < D; ++c) Q += z[l][1 + c][o] * z[l][1 + c][o];
+            a[l + 1][0][o] = h;
+            for (int c = 0; c < 3; ++c) a[l + 1][1 + c][o] = c < D ? s * z[l][1 + c][o] : 0.0;
+            a[l + 1][4][o] = s * z[l][4][o] - 2 * h * s * Q;
+        }
+    }
+    const double* w5 = theta + (size_t)kLayers * kLayerSize;
+    double* gw5 = grad + (size_t)kLayers * kLayerSize;
+    double abar[NC][kWidth] = {};
+    for (int i = 0; i < kWidth; ++i) {
+        gw5[i] += Nbar * a[kLayers][0][i] + Lbar * a[kLayers][4][i];
+        abar[0][i] = Nbar * w5[i];
+        abar[4][i] = Lbar * w5[i];
+    }
+    gw5[kWidth] += Nbar;
+    for (int l = kLayers - 1; l >= 0; --l) {
+        const double* W = theta + (size_t)l * kLayerSize;
+        double* gW = grad + (size_t)l * kLayerSize;
+        double* gb = gW + kWidth * kWidth;
+        double zbar[NC][kWidth] = {};
+        for (int o = 0; o < kWidth; ++o) {
+            double h = std::tanh(z[l][0][o]), s = 1 - h * h, Q = 0, za = 0;
+            for (int c = 0; c < D; ++c) {
+                Q += z[l][1 + c][o] * z[l][1 + c][o];
+                za += z[l][1 + c][o] * abar[1 + c][o];
+            }
+            zbar[4][o] = s * abar[4][o];
+            for (int c = 0; c < D; ++c) zbar[1 + c][o] = s * abar[1 + c][o] - 4 * h * s * z[l][1 + c][o] * abar[4][o];
+            zbar[0][o] = s * abar[0][o] - 2 * h * s * za -
+                         (2 * h * s * z[l][4][o] + 2 * s * (s - 2 * h * h) * Q) * abar[4][o];
+            gb[o] += zbar[0][o];
+            for (int ch = 0; ch < NC; ++ch)
+                for (int i = 0; i < kWidth; ++i) gW[o * kWidth + i] += zbar[ch][o] * a[l][ch][i];
+        }
+        if (l == 0) break;
+        for (int ch = 0; ch < NC; ++ch)
+            for (int i = 0; i < kWidth; ++i) {
+                double acc = 0;
+                for (int o = 0; o < kWidth; ++o) acc += W[o * kWidth + i] * zbar[ch][o];
+                abar[ch][i] = acc;
+            }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Control variate of a nested walk.  For any twice differentiable N, applying
 // the ball's mean-value identity for the screened operator (Sec. 3.3: the
@@ -496,17 +610,23 @@ double mlp_loss_grad(int D, int F, const double* B, const double* theta, const d
 // with the same stopping rules (shell, roulette, cap) as the walk.  So
 //   C = N(x_0) - sum_j int_{B_j} G_j (-Lap N + sigma N) - [alive] N(x_stop)
 // has mean zero, and uhat + C is an estimate of u(x_0) with the same mean as
-// uhat; its variance vanishes as N approaches u.  The sum over the L source
-// steps is estimated by one step J chosen uniformly (reservoir sampling as the
-// walk proceeds) weighted by L, with one uniform ball point y_J of B_J:
-//   sum_j ~ L |B_J| G_J(|y_J - x_J|) (-Lap N + sigma N)(y_J).
+// uhat; its variance vanishes as N approaches u.  The sum over the source
+// steps is estimated by one step J chosen with probability m_J / S, where
+// m_j = int_{B_j} G_j is the Green's-function mass of step j's ball and S the
+// walk's total (weighted reservoir sampling as the walk proceeds: step j
+// replaces the choice iff U S_j < m_j with S_j the running total), and one
+// uniform point y_J of B_J:
+//   sum_j ~ S |B_J| G_J(|y_J - x_J|) (-Lap N + sigma N)(y_J) / m_J.
+// For a residual -Lap N + sigma N that is constant along the walk the
+// estimate is exact up to the ball-point weight.
 // ---------------------------------------------------------------------------
 struct CvTrace {
-    int64_t L = 0;         // source (non-terminal) steps
+    double S = 0;          // total Green's-function mass of the source steps
     bool alive = false;    // ended in the shell or at the cap (not by roulette)
     double xstop[3] = {0, 0, 0};
     double y[3] = {0, 0, 0};
     double rho = 0, d = 0; // y = x_J + rho d dir, rho in (0, 1], d = radius of B_J
+    bool any = false;      // at least one source step
 };
 
 // 24-bit threshold of the probability q: the nested walks run iff the top 24
@@ -548,10 +668,12 @@ double walk_on_spheres(const Scene& sc, const double* x0, const Stream& st, uint
         uint32_t w[4];
         st.draw(k, extra, w);
         if (tr) {   // reservoir choice of the source step for the control variate
-            tr->L++;
+            const double mj = green_mass(D, sc.s.sigma, d);
+            tr->S += mj;
+            tr->any = true;
             uint32_t wr[4];
             st.draw(k, extra | 4u, wr);
-            if ((uint64_t)(wr[0] >> 8) * (uint64_t)tr->L < (1ull << 24)) {
+            if (u24(wr[0]) * tr->S < mj) {
                 double dir[3];
                 sphere_dir(D, wr[1], wr[2], dir);
                 tr->rho = std::pow(u24pos(wr[3]), 1.0 / D);
@@ -596,17 +718,18 @@ struct DiffOut {
 
 // The control-variate estimate of u(xoff) from the nested walks' traces:
 //   N(xoff) + [run] (uhat - mean_i corr_i) / q,
-//   corr_i = L_i |B| G (-Lap N + sigma N)(y_i) + [alive_i] N(xstop_i).
+//   corr_i = S_i |B| G (-Lap N + sigma N)(y_i) / m(d_i) + [alive_i] N(xstop_i).
 void cv_combine(const Scene& sc, const oracle_cv& cv, DiffOut& o) {
     const int D = sc.D;
     double Noff = mlp_eval(D, cv.F, cv.B, cv.theta, o.xoff).N;
     if (o.run == 0) { o.uoff_cv = Noff; return; }
     double corr = 0;
     for (const CvTrace& t : o.traces) {
-        if (t.L > 0) {
+        if (t.any) {
             MlpOut e = mlp_eval(D, cv.F, cv.B, cv.theta, t.y);
             double fN = -e.lap + sc.s.sigma * e.N;
-            corr += (double)t.L * green(D, sc.s.sigma, t.rho * t.d, t.d) * ball_volume(D, t.d) * fN;
+            corr += t.S * green(D, sc.s.sigma, t.rho * t.d, t.d) * ball_volume(D, t.d) /
+                    green_mass(D, sc.s.sigma, t.d) * fN;
         }
         if (t.alive) corr += mlp_eval(D, cv.F, cv.B, cv.theta, t.xstop).N;
     }
@@ -644,27 +767,32 @@ DiffOut diff_walk_on_spheres(const Scene& sc, const double* x0, const Stream& st
             for (int i = 0; i < D; ++i) xoff[i] = h.xbar[i] - sc.s.delta * n[i];
             double usum = 0;
             out.run = 1;
-            if (cv && cv_threshold(cv->q) < (1u << 24)) {      // run the nested walks w.p. q
+            // At a primitive that depends on no parameter the nested estimate is
+            // multiplied by V_n = 0 and gdot = 0 in every derivative, so the
+            // nested walks are not run (their mean is reported as g).
+            const bool dep = sc.depends(h.prim);
+            if (!dep) out.run = -1;
+            if (dep && cv && cv_threshold(cv->q) < (1u << 24)) {   // run the nested walks w.p. q
                 uint32_t wq[4];
                 st.draw(k, 4u, wq);
                 out.run = (wq[0] >> 8) < cv_threshold(cv->q) ? 1 : 0;
             }
-            if (cv) out.traces.assign(out.run ? sc.s.K : 0, CvTrace());
-            for (int i = 0; out.run && i < sc.s.K; ++i) {      // nested forward walks
+            if (cv) out.traces.assign(out.run == 1 ? sc.s.K : 0, CvTrace());
+            for (int i = 0; out.run == 1 && i < sc.s.K; ++i) {  // nested forward walks
                 WalkCount c2;
                 usum += walk_on_spheres(sc, xoff, st, 1u | ((uint32_t)i << 8), c2,
                                         cv ? &out.traces[i] : nullptr);
                 out.nested_steps += c2.steps;
                 cnt.truncated += c2.truncated;
             }
-            double uhat = usum / sc.s.K;
+            double gx = sc.g(h);
+            double uhat = dep ? usum / sc.s.K : gx;
             for (int i = 0; i < 3; ++i) out.xoff[i] = xoff[i];
             out.uoff = uhat;
-            if (cv) {
+            if (cv && dep) {
                 cv_combine(sc, *cv, out);
                 uhat = out.uoff_cv;
             }
-            double gx = sc.g(h);
             double dudn = (gx - uhat) / sc.s.delta;            // eq. (dudn_fd_estimate)
             out.u = acc + gx;
             out.terminal = true;
@@ -766,6 +894,7 @@ void oracle_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
 
 double oracle_green(int dim, double sigma, double r, double R) { return green(dim, sigma, r, R); }
 double oracle_poisson_scale(int dim, double sigma, double R) { return poisson_scale(dim, sigma, R); }
+double oracle_green_mass(int dim, double sigma, double R) { return green_mass(dim, sigma, R); }
 
 // closest point: out = {d, prim, bary0, bary1, bary2, xbar0, xbar1, xbar2}
 int oracle_closest(const oracle_scene* s, const double* x, double* out) {
@@ -985,6 +1114,16 @@ int oracle_mlp_loss_grad(int32_t dim, int32_t F, const double* B, const double* 
     return 0;
 }
 
+// grad (kThetaSize) := d/dtheta sum_i (Nbar_i N(x_i) + Lbar_i Lap N(x_i)).
+int oracle_mlp_vjp(int32_t dim, int32_t F, const double* B, const double* theta, const double* X,
+                   const double* Nbar, const double* Lbar, int64_t n, double* grad) {
+    if ((dim != 2 && dim != 3) || F < 0 || 2 * F + dim > kWidth || n < 0) return 1;
+    std::fill(grad, grad + kThetaSize, 0.0);
+    for (int64_t i = 0; i < n; ++i)
+        mlp_vjp(dim, F, B, theta, X + i * dim, Nbar[i], Lbar ? Lbar[i] : 0.0, grad);
+    return 0;
+}
+
 // One Adam step (Kingma and Ba, ICLR 2015, Algorithm 1) on n parameters;
 // step is the 1-based step count used in the bias corrections.
 void oracle_adam(int64_t n, double* theta, double* m, double* v, const double* g, double lr,
@@ -999,7 +1138,7 @@ void oracle_adam(int64_t n, double* theta, double* m, double* v, const double* g
 
 // Differential-walk records with the control variate.
 // walk (P*W*9): run, xoff[3], uoff (plain nested mean), uoff_cv, target, u, prim
-// nested (P*W*K*10): L, alive, xstop[3], y[3], rho, d  (zeros when not run)
+// nested (P*W*K*10): S, alive, xstop[3], y[3], rho, d  (zeros when not run)
 int oracle_walk_records_cv(const oracle_scene* s, const oracle_cv* cv, const double* X,
                            int64_t P, int32_t W, uint64_t seed, int32_t instance,
                            double* walk, double* nested, int threads) {
@@ -1015,14 +1154,16 @@ int oracle_walk_records_cv(const oracle_scene* s, const oracle_cv* cv, const dou
             double* r = walk + id * 9;
             r[0] = o.run;
             for (int i = 0; i < 3; ++i) r[1 + i] = o.xoff[i];
-            r[4] = o.uoff; r[5] = o.uoff_cv; r[6] = o.target; r[7] = o.u;
+            r[4] = o.run >= 0 ? o.uoff : 0.0;
+            r[5] = o.run >= 0 ? o.uoff_cv : 0.0;
+            r[6] = o.target; r[7] = o.u;
             r[8] = o.terminal ? o.prim : -1;
             for (int i = 0; i < K; ++i) {
                 double* q = nested + (id * K + i) * 10;
                 std::fill(q, q + 10, 0.0);
                 if (i >= (int)o.traces.size()) continue;
                 const CvTrace& t = o.traces[i];
-                q[0] = (double)t.L; q[1] = t.alive ? 1 : 0;
+                q[0] = t.S; q[1] = t.alive ? 1 : 0;
                 for (int c2 = 0; c2 < 3; ++c2) { q[2 + c2] = t.xstop[c2]; q[5 + c2] = t.y[c2]; }
                 q[8] = t.rho; q[9] = t.d;
             }

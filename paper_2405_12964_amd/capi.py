@@ -86,8 +86,10 @@ def lib():
             "dwos_mlp_get_params": [vp, vp],
             "dwos_mlp_eval": [vp, vp, C.c_int64, vp, vp, vp],
             "dwos_mlp_loss_grad": [vp, vp, vp, vp, C.c_int64, vp, vp],
+            "dwos_mlp_vjp": [vp, vp, vp, vp, C.c_int64, vp],
             "dwos_mlp_adam_step": [vp, C.c_float, C.c_float, C.c_float, C.c_float],
             "dwos_cv_attach": [vp, vp, C.c_double],
+            "dwos_cv_beta": [vp, dp],
             "dwos_cv_train": [vp, C.c_int32, C.c_int32, C.c_float, C.c_uint64, vp],
             "dwos_cv_walk_records": [vp, vp, C.c_int64, C.c_int32, C.c_uint64, vp, vp],
         }
@@ -113,7 +115,7 @@ EXPORTED = [
     "dwos_batch_add_instance", "dwos_batch_solve", "dwos_set_seed_buffer", "dwos_autotune",
     "dwos_set_variant", "dwos_mlp_theta_size", "dwos_mlp_create", "dwos_mlp_destroy",
     "dwos_mlp_set_params", "dwos_mlp_get_params", "dwos_mlp_eval", "dwos_mlp_loss_grad",
-    "dwos_mlp_adam_step", "dwos_cv_attach", "dwos_cv_train", "dwos_cv_walk_records",
+    "dwos_mlp_vjp", "dwos_mlp_adam_step", "dwos_cv_attach", "dwos_cv_beta", "dwos_cv_train", "dwos_cv_walk_records",
 ]
 
 

@@ -497,6 +497,21 @@ __global__ void fill_u64_kernel(unsigned long long* p, int64_t n) {
     if (i < n) p[i] = 0ull;
 }
 
+// per primitive: does any of its vertices move or carry a value parameter?
+__global__ void prim_dep_kernel(const int32_t* pverts, const int32_t* vparam, int64_t np, int D,
+                                int32_t* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    int dep = 0;
+    for (int k = 0; k < D; ++k) dep |= vparam[pverts[i * D + k]] != 0;
+    out[i] = dep;
+}
+
+__global__ void fill_f32_kernel(float* p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
 __global__ void fill_f64_kernel(double* p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0.0;

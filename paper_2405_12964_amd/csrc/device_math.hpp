@@ -192,6 +192,40 @@ __device__ __forceinline__ T poisson_scale(T kappa, T R) {
     }
 }
 
+// Green's-function mass of the ball, int_B G dy = (1 - alpha(R))/sigma
+// (R^2/(2D) at sigma = 0), with 1 - alpha from its power series where alpha
+// is close to 1: 2D (I0(x) - 1)/I0(x), 3D (sinh x - x)/sinh x, x = kR.
+template <int D, class T>
+__device__ inline T green_mass(T kappa, T R) {
+    if (kappa == T(0)) return R * R / T(2 * D);
+    const T x = kappa * R, k2 = kappa * kappa;
+    if constexpr (D == 2) {
+        if (x < T(2)) {
+            const T q = T(0.25) * x * x;
+            T t = T(1), s = T(0);
+            for (int k = 1; k < 40; ++k) {
+                t *= q * T(kSeries.inv_k2[k]);
+                s += t;
+                if (t < BesselCfg<T>::tol * s) break;
+            }
+            return s / ((T(1) + s) * k2);
+        }
+        return (T(1) - poisson_scale<T, 2>(kappa, R)) / k2;
+    } else {
+        if (x < T(1)) {
+            const T x2 = x * x;
+            T t = x, s = T(0);
+            for (int k = 1; k < 20; ++k) {
+                t *= x2 / (T(2 * k) * T(2 * k + 1));
+                s += t;
+                if (t < BesselCfg<T>::tol * s) break;
+            }
+            return s / (sinh(x) * k2);
+        }
+        return (T(1) - poisson_scale<T, 3>(kappa, R)) / k2;
+    }
+}
+
 template <int D, class T>
 __device__ inline T green_ball_t(T kappa, T rho, T R) {
     if constexpr (D == 2) {

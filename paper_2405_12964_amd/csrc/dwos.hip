@@ -81,9 +81,13 @@ struct dwos_ctx {
     // learned control variate of the nested walks (not owned)
     dwos_mlp* cv = nullptr;
     uint32_t cv_qthresh = 1u << 24;
-    DevBuf cv_run, cv_xoff, cv_xbar, cv_g, cv_stop, cv_y, cv_rho, cv_d, cv_La;
+    DevBuf cv_run, cv_xoff, cv_xbar, cv_g, cv_stop, cv_y, cv_rho, cv_d, cv_S, cv_alive;
     DevBuf cv_Noff, cv_Nstop, cv_Ny, cv_Ly, cv_target, cv_uplain;
-    DevBuf cv_bx, cv_bt, cv_bw;   // training batch
+    DevBuf cv_bx, cv_bN, cv_bL, cv_bNbar, cv_bLbar, cv_bs, cv_bvalid;   // training batch
+    DevBuf cv_beta, cv_stats;     // control-variate coefficient; sums for the next one
+    DevBuf vparam;                // per vertex: 1 if it moves or carries a parameter value
+    DevBuf prim_dep;              // per primitive: 1 if a vertex of it does
+    bool cv_fresh = true;         // beta must be reset to 1 before the next use
     int64_t cv_nrec = 0;          // walks recorded by the last differential chunk
 };
 
@@ -370,7 +374,8 @@ dwos_status ensure_records(dwos_ctx* c, int64_t walks, bool diff, bool steps) {
         HIP_OK(c->cv_y.reserve(nk * c->D * sizeof(T)));
         HIP_OK(c->cv_rho.reserve(nk * sizeof(T)));
         HIP_OK(c->cv_d.reserve(nk * sizeof(T)));
-        HIP_OK(c->cv_La.reserve(nk * sizeof(int32_t)));
+        HIP_OK(c->cv_S.reserve(nk * sizeof(T)));
+        HIP_OK(c->cv_alive.reserve(nk * sizeof(int32_t)));
         HIP_OK(c->cv_Nstop.reserve(nk * sizeof(float)));
         HIP_OK(c->cv_Ny.reserve(nk * sizeof(float)));
         HIP_OK(c->cv_Ly.reserve(nk * sizeof(float)));
@@ -400,6 +405,7 @@ dwos::WalkArgs<T> base_args(dwos_ctx* c, const double* X, int32_t W, uint64_t se
     a.rec_steps = nullptr;
     a.cv_run = nullptr;
     a.cv_qthresh = 1u << 24;
+    a.prim_dep = c->has_params ? c->prim_dep.as<int32_t>() : nullptr;
     return a;
 }
 
@@ -414,14 +420,26 @@ void cv_args(dwos_ctx* c, dwos::WalkArgs<T>& a) {
     a.cv_y = c->cv_y.as<T>();
     a.cv_rho = c->cv_rho.as<T>();
     a.cv_d = c->cv_d.as<T>();
-    a.cv_La = c->cv_La.as<int32_t>();
+    a.cv_S = c->cv_S.as<T>();
+    a.cv_alive = c->cv_alive.as<int32_t>();
     a.cv_qthresh = c->cv_qthresh;
 }
 
 // Network values at the recorded points, then the control-variate estimate
 // of every nested mean (in place in rec_uoff).
+// Once per differential call: beta from the previous call's sums (or 1 after
+// attaching), sums cleared.
+dwos_status cv_begin(dwos_ctx* c) {
+    HIP_OK(c->cv_beta.reserve(sizeof(double)));
+    HIP_OK(c->cv_stats.reserve(3 * sizeof(double)));
+    hipLaunchKernelGGL(dwos::cv_beta_kernel, dim3(1), dim3(64), 0, c->stream, c->cv_beta.as<double>(),
+                       c->cv_stats.as<double>(), c->cv_fresh ? 1 : 0);
+    c->cv_fresh = false;
+    return DWOS_OK;
+}
+
 template <class T, int D>
-dwos_status cv_apply(dwos_ctx* c, int64_t walks, bool keep_plain) {
+dwos_status cv_apply(dwos_ctx* c, int64_t walks) {
     hipStream_t s = c->stream;
     const int K = c->prob.K;
     const int32_t* run = c->cv_run.as<int32_t>();
@@ -433,7 +451,11 @@ dwos_status cv_apply(dwos_ctx* c, int64_t walks, bool keep_plain) {
                                          c->cv_Ny.as<float>(), nullptr, c->cv_Ly.as<float>()));
     dwos::CvCombineArgs<T> ca{};
     ca.run = run;
-    ca.La = c->cv_La.as<int32_t>();
+    ca.prim = c->rec_prim.as<int32_t>();
+    ca.pverts = c->pverts.as<int32_t>();
+    ca.vparam = c->has_params ? c->vparam.as<int32_t>() : nullptr;
+    ca.S = c->cv_S.as<T>();
+    ca.alive = c->cv_alive.as<int32_t>();
     ca.rho = c->cv_rho.as<T>();
     ca.d = c->cv_d.as<T>();
     ca.Noff = c->cv_Noff.as<float>();
@@ -442,7 +464,9 @@ dwos_status cv_apply(dwos_ctx* c, int64_t walks, bool keep_plain) {
     ca.Ly = c->cv_Ly.as<float>();
     ca.uoff = c->rec_uoff.as<T>();
     ca.target = c->cv_target.as<T>();
-    ca.uoff_plain = keep_plain ? c->cv_uplain.as<T>() : nullptr;
+    ca.uoff_plain = c->cv_uplain.as<T>();
+    ca.beta = c->cv_beta.as<double>();
+    ca.stats = c->cv_stats.as<double>();
     ca.nwalks = walks;
     ca.K = K;
     ca.sigma = T(c->prob.sigma);
@@ -589,6 +613,10 @@ dwos_status run_op(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
     }
     const dwos::Params<T> prm = make_params<T>(c->prob);
     const dwos::Scene<T> scene = make_scene<T>(c);
+    if (diff && c->cv) {
+        rc = cv_begin(c);
+        if (rc) return rc;
+    }
     for (int64_t p0 = 0; p0 < P; p0 += chunk_pts) {
         const int64_t Pc = std::min(chunk_pts, P - p0);
         const int64_t walks = Pc * W;
@@ -616,13 +644,14 @@ dwos_status run_op(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
         rc = diff ? launch_walks<T, D, 1>(c, a) : launch_walks<T, D, 0>(c, a);
         if (rc) return rc;
         if (use_cv) {
-            rc = cv_apply<T, D>(c, walks, o.cv_walk_out != nullptr);
+            rc = cv_apply<T, D>(c, walks);
             if (rc) return rc;
             if (o.cv_walk_out)
                 hipLaunchKernelGGL((dwos::cv_export_kernel<T, D>), dim3(blocks_for(walks, 256)), dim3(256), 0, s,
                                    c->cv_run.as<int32_t>(), c->cv_xoff.as<T>(), c->cv_uplain.as<T>(),
                                    c->rec_uoff.as<T>(), c->cv_target.as<T>(), c->rec_u.as<T>(),
-                                   c->rec_prim.as<int32_t>(), c->cv_La.as<int32_t>(), c->cv_stop.as<T>(),
+                                   c->rec_prim.as<int32_t>(), c->cv_S.as<T>(), c->cv_alive.as<int32_t>(),
+                                   c->cv_stop.as<T>(),
                                    c->cv_y.as<T>(), c->cv_rho.as<T>(), c->cv_d.as<T>(), walks, c->prob.K,
                                    p0 * W, o.cv_walk_out, o.cv_nested_out);
         }
@@ -921,6 +950,15 @@ dwos_status dwos_set_parameters(dwos_ctx* c, int64_t N, const int64_t* rowptr, c
         HIP_OK(upload(c->bcptr, bp.data(), bp.size(), s));
         HIP_OK(upload(c->bcvert, bvt.data(), bvt.size(), s));
     }
+    // vertices that move or carry a parameter value: terminal points on
+    // their primitives are the ones whose nested walks enter the gradient
+    std::vector<int32_t> vpar(nv, 0);
+    for (int64_t i = 0; i < nv; ++i) vpar[i] = (rp[i + 1] > rp[i] || bcp[i] >= 0) ? 1 : 0;
+    HIP_OK(upload(c->vparam, vpar.data(), vpar.size(), s));
+    HIP_OK(c->prim_dep.reserve(c->np * sizeof(int32_t)));
+    hipLaunchKernelGGL(dwos::prim_dep_kernel, dim3(blocks_for(c->np, 256)), dim3(256), 0, s,
+                       c->pverts.as<int32_t>(), c->vparam.as<int32_t>(), c->np, D, c->prim_dep.as<int32_t>());
+    HIP_OK(hipGetLastError());
     c->N = N;
     c->has_params = true;
     return DWOS_OK;
@@ -1010,6 +1048,17 @@ dwos_status dwos_cv_attach(dwos_ctx* c, dwos_mlp* m, double q) {
     }
     c->cv = m;
     c->cv_nrec = 0;
+    c->cv_fresh = true;
+    return DWOS_OK;
+}
+
+dwos_status dwos_cv_beta(dwos_ctx* c, double* beta) {
+    if (!c || !beta) return fail(DWOS_EINVAL, "cv_beta: NULL argument");
+    if (!c->cv) return fail(DWOS_ESTATE, "cv_beta: no network attached");
+    if (c->cv_fresh || !c->cv_beta.ptr) { *beta = 1.0; return DWOS_OK; }
+    HIP_OK(hipSetDevice(c->device));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    HIP_OK(hipMemcpy(beta, c->cv_beta.ptr, sizeof(double), hipMemcpyDeviceToHost));
     return DWOS_OK;
 }
 
@@ -1020,31 +1069,46 @@ dwos_status dwos_cv_train(dwos_ctx* c, int32_t steps, int32_t batch, float lr, u
     if (steps < 0 || batch < 1 || !(lr > 0.f)) return fail(DWOS_EINVAL, "cv_train: bad steps, batch or lr");
     HIP_OK(hipSetDevice(c->device));
     hipStream_t s = c->stream;
-    const int D = c->D;
-    HIP_OK(c->cv_bx.reserve((size_t)2 * batch * D * sizeof(float)));
-    HIP_OK(c->cv_bt.reserve((size_t)2 * batch * sizeof(float)));
-    HIP_OK(c->cv_bw.reserve((size_t)2 * batch * sizeof(float)));
+    const int D = c->D, K = c->prob.K;
+    const int64_t b = batch, rows = 2 * b + 2 * b * K, nval = 2 * b + b * K;
+    HIP_OK(c->cv_bx.reserve((size_t)rows * D * sizeof(float)));
+    HIP_OK(c->cv_bN.reserve((size_t)rows * sizeof(float)));
+    HIP_OK(c->cv_bL.reserve((size_t)b * K * sizeof(float)));
+    HIP_OK(c->cv_bNbar.reserve((size_t)rows * sizeof(float)));
+    HIP_OK(c->cv_bLbar.reserve((size_t)rows * sizeof(float)));
+    HIP_OK(c->cv_bs.reserve((size_t)(2 * b + 2 * b * K) * sizeof(float)));
+    HIP_OK(c->cv_bvalid.reserve((size_t)b * sizeof(int32_t)));
+    float* su = c->cv_bs.as<float>();
+    float* sg = su + b;
+    float* sw = sg + b;
+    float* salive = sw + b * K;
+    float* X = c->cv_bx.as<float>();
+    float* N = c->cv_bN.as<float>();
     for (int32_t it = 0; it < steps; ++it) {
-        auto gather = [&](auto tag) {
+        auto sample = [&](auto tag) {
             using T = decltype(tag);
-            if (D == 2)
-                hipLaunchKernelGGL((dwos::cv_gather_kernel<T, 2>), dim3(blocks_for(batch, 256)), dim3(256), 0, s,
-                                   c->cv_run.as<int32_t>(), c->cv_xoff.as<T>(), c->cv_xbar.as<T>(), c->cv_g.as<T>(),
-                                   c->cv_target.as<T>(), c->cv_nrec, batch, (uint32_t)it, (uint32_t)seed,
-                                   (uint32_t)(seed >> 32), c->cv_bx.as<float>(), c->cv_bt.as<float>(),
-                                   c->cv_bw.as<float>());
-            else
-                hipLaunchKernelGGL((dwos::cv_gather_kernel<T, 3>), dim3(blocks_for(batch, 256)), dim3(256), 0, s,
-                                   c->cv_run.as<int32_t>(), c->cv_xoff.as<T>(), c->cv_xbar.as<T>(), c->cv_g.as<T>(),
-                                   c->cv_target.as<T>(), c->cv_nrec, batch, (uint32_t)it, (uint32_t)seed,
-                                   (uint32_t)(seed >> 32), c->cv_bx.as<float>(), c->cv_bt.as<float>(),
-                                   c->cv_bw.as<float>());
+            auto kern = D == 2 ? dwos::cv_sample_kernel<T, 2> : dwos::cv_sample_kernel<T, 3>;
+            hipLaunchKernelGGL(kern, dim3(blocks_for(b, 256)), dim3(256), 0, s, c->cv_run.as<int32_t>(),
+                               c->rec_prim.as<int32_t>(), c->pverts.as<int32_t>(),
+                               c->has_params ? c->vparam.as<int32_t>() : nullptr, c->cv_xoff.as<T>(), c->cv_xbar.as<T>(), c->cv_g.as<T>(), c->cv_uplain.as<T>(),
+                               c->cv_S.as<T>(), c->cv_alive.as<int32_t>(), c->cv_stop.as<T>(), c->cv_y.as<T>(),
+                               c->cv_rho.as<T>(),
+                               c->cv_d.as<T>(), c->cv_nrec, batch, K, (uint32_t)it, (uint32_t)seed,
+                               (uint32_t)(seed >> 32), T(std::sqrt(c->prob.sigma)), X, su, sg, sw, salive,
+                               c->cv_bvalid.as<int32_t>());
         };
-        if (c->prec == DWOS_FP32) gather(float{}); else gather(double{});
+        if (c->prec == DWOS_FP32) sample(float{}); else sample(double{});
         HIP_OK(hipGetLastError());
-        HIP_OK(dwos_host::mlp_loss_grad_launch(c->cv, s, c->cv_bx.as<float>(), c->cv_bt.as<float>(),
-                                               c->cv_bw.as<float>(), 2 * (int64_t)batch,
-                                               it + 1 == steps ? loss : nullptr));
+        HIP_OK(dwos_host::mlp_eval_launch<float>(c->cv, s, X, nval, nullptr, 1, 0, N, nullptr, nullptr));
+        HIP_OK(dwos_host::mlp_eval_launch<float>(c->cv, s, X + nval * D, b * K, nullptr, 1, 0, N + nval,
+                                                 nullptr, c->cv_bL.as<float>()));
+        float* lo = (it + 1 == steps) ? loss : nullptr;
+        if (lo) hipLaunchKernelGGL(dwos::fill_f32_kernel, dim3(1), dim3(64), 0, s, lo, (int64_t)1);
+        hipLaunchKernelGGL(dwos::cv_adjoint_kernel, dim3(blocks_for(b, 256)), dim3(256), 0, s, N,
+                           c->cv_bL.as<float>(), su, sg, sw, salive, c->cv_bvalid.as<int32_t>(), batch, K,
+                           (float)c->prob.sigma, 1.0f, c->cv_bNbar.as<float>(), c->cv_bLbar.as<float>(), lo);
+        HIP_OK(hipGetLastError());
+        HIP_OK(dwos_host::mlp_vjp_launch(c->cv, s, X, c->cv_bNbar.as<float>(), c->cv_bLbar.as<float>(), rows));
         HIP_OK(dwos_host::mlp_adam_launch(c->cv, s, lr, 0.9f, 0.999f, 1e-8f));
     }
     return DWOS_OK;

@@ -417,6 +417,163 @@ __global__ void __launch_bounds__(64) wgrad_kernel(const __bf16* __restrict__ ws
         atomicAdd(&grad[(size_t)l * kLayerSize + (16 * mo + 4 * g + r) * kWidth + 16 * mi + i], acc[r]);
 }
 
+struct VjpArgs {
+    const u32x4* packed;
+    const float* theta;
+    const float* B;
+    int F;
+    const float* X;
+    const float* Nbar;
+    const float* Lbar;
+    int64_t n;
+    int64_t pad;
+    float* grad;
+    __bf16* ws;       // [layer][virtual tile = tile * NC + channel][zh, zl, ah, al][64][16]
+    float* zs;        // [layer][tile][channel][64][16] pre-activations
+};
+
+// ---------------------------------------------------------------------------
+// grad += d/dtheta sum_i (Nbar_i N(x_i) + Lbar_i Lap N(x_i)), part 1.  The
+// forward pass carries the value, gradient and Laplacian channels (as in
+// eval_kernel) and keeps each layer's pre-activations; the backward pass
+// turns the output adjoints into pre-activation adjoints per layer
+// (h = tanh z, s = 1 - h^2, Q = sum_c z_c^2):
+//   zbar_L = s abar_L,  zbar_c = s abar_c - 4 h s z_c abar_L,
+//   zbar = s abar - 2 h s sum_c z_c abar_c - (2 h s z_L + 2 s (s - 2 h^2) Q) abar_L
+// and sends every channel back through W^T on the matrix cores.  Each
+// layer's channel inputs and pre-activation adjoints go to the workspace for
+// the weight-gradient products, which contract over points and channels.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(256) vjp_kernel(VjpArgs a) {
+    constexpr int NC = D + 2;
+    const int lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    const int waves = blockDim.x >> 6;
+    const float* w5 = a.theta + (size_t)kLayers * kLayerSize;
+    const u32x4* fwd = a.packed;
+    const u32x4* bwd = a.packed + kPackDirU4;
+    const int64_t ntiles = a.pad / 16;
+    const int lane_off = (4 * g) * 16 + col;
+    for (int64_t tile = (int64_t)blockIdx.x * waves + (threadIdx.x >> 6); tile < ntiles;
+         tile += (int64_t)gridDim.x * waves) {
+        const int64_t p = tile * 16 + col;
+        const bool valid = p < a.n;
+        float x[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) x[c] = valid ? a.X[p * D + c] : 0.f;
+        const float nb = valid ? a.Nbar[p] : 0.f;
+        const float lb = (valid && a.Lbar) ? a.Lbar[p] : 0.f;
+        float act[NC][4][4];
+        features<D, NC>(a.B, a.F, x, g, act);
+        bf16x8 bh[NC][2], bl[NC][2];
+        f32x4 acc[NC][4];
+#pragma unroll 1
+        for (int l = 0; l < kLayers; ++l) {
+            __bf16* wsl = a.ws + ((size_t)l * ntiles + tile) * NC * 4 * kWidth * 16 + lane_off;
+            float* zsl = a.zs + (((size_t)l * ntiles + tile) * NC) * kWidth * 16 + lane_off;
+#pragma unroll
+            for (int ch = 0; ch < NC; ++ch)
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        __bf16 h, lo;
+                        split(act[ch][t][r], h, lo);
+                        const int uo = ch * 4 * kWidth * 16 + (16 * t + r) * 16;
+                        wsl[2 * kWidth * 16 + uo] = h;
+                        wsl[3 * kWidth * 16 + uo] = lo;
+                    }
+            to_operands<NC>(act, bh, bl);
+            layer_product<NC>(fwd + (size_t)l * kPackLayerU4, lane, bh, bl, acc);
+            const float* bias = a.theta + (size_t)l * kLayerSize + kWidth * kWidth;
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float z = acc[0][mt][r] + bias[16 * mt + 4 * g + r];
+                    const int uo = (16 * mt + r) * 16;
+                    zsl[uo] = z;
+#pragma unroll
+                    for (int ch = 1; ch < NC; ++ch) zsl[ch * kWidth * 16 + uo] = acc[ch][mt][r];
+                    const float h = tanhf(z), s = 1.f - h * h;
+                    float zz = 0.f;
+#pragma unroll
+                    for (int c = 0; c < D; ++c) {
+                        const float zg = acc[1 + c][mt][r];
+                        zz += zg * zg;
+                        act[1 + c][mt][r] = s * zg;
+                    }
+                    act[0][mt][r] = h;
+                    act[D + 1][mt][r] = s * acc[D + 1][mt][r] - 2.f * h * s * zz;
+                }
+        }
+        // output layer: N = w5 . a_v + b5, Lap N = w5 . a_L
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int u = 16 * t + 4 * g + r;
+                const float gw = col_sum(nb * act[0][t][r] + lb * act[D + 1][t][r]);
+                if (col == 0) atomicAdd(&a.grad[(size_t)kLayers * kLayerSize + u], gw);
+#pragma unroll
+                for (int ch = 0; ch < NC; ++ch) act[ch][t][r] = 0.f;   // becomes abar
+                act[0][t][r] = nb * w5[u];
+                act[D + 1][t][r] = lb * w5[u];
+            }
+        {
+            const float gb = col_sum(g == 0 ? nb : 0.f);
+            if (lane == 0) atomicAdd(&a.grad[(size_t)kLayers * kLayerSize + kWidth], gb);
+        }
+        // act now holds the adjoints abar of the current layer's outputs
+#pragma unroll 1
+        for (int l = kLayers - 1; l >= 0; --l) {
+            __bf16* wsl = a.ws + ((size_t)l * ntiles + tile) * NC * 4 * kWidth * 16 + lane_off;
+            const float* zsl = a.zs + (((size_t)l * ntiles + tile) * NC) * kWidth * 16 + lane_off;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int uo = (16 * t + r) * 16;
+                    const float z = zsl[uo];
+                    const float zL = zsl[(D + 1) * kWidth * 16 + uo];
+                    const float h = tanhf(z), s = 1.f - h * h;
+                    const float aL = act[D + 1][t][r];
+                    float Q = 0.f, za = 0.f;
+#pragma unroll
+                    for (int c = 0; c < D; ++c) {
+                        const float zc = zsl[(1 + c) * kWidth * 16 + uo];
+                        Q += zc * zc;
+                        za += zc * act[1 + c][t][r];
+                        act[1 + c][t][r] = s * act[1 + c][t][r] - 4.f * h * s * zc * aL;
+                    }
+                    act[0][t][r] = s * act[0][t][r] - 2.f * h * s * za -
+                                   (2.f * h * s * zL + 2.f * s * (s - 2.f * h * h) * Q) * aL;
+                    act[D + 1][t][r] = s * aL;
+                    const int u = 16 * t + 4 * g + r;
+                    const float gb = col_sum(act[0][t][r]);
+                    if (col == 0) atomicAdd(&a.grad[(size_t)l * kLayerSize + kWidth * kWidth + u], gb);
+#pragma unroll
+                    for (int ch = 0; ch < NC; ++ch) {
+                        __bf16 hh, lo;
+                        split(act[ch][t][r], hh, lo);
+                        const int o = ch * 4 * kWidth * 16 + uo;
+                        wsl[o] = hh;
+                        wsl[kWidth * 16 + o] = lo;
+                    }
+                }
+            if (l == 0) break;
+            to_operands<NC>(act, bh, bl);
+            layer_product<NC>(bwd + (size_t)l * kPackLayerU4, lane, bh, bl, acc);
+#pragma unroll
+            for (int ch = 0; ch < NC; ++ch)
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) act[ch][mt][r] = acc[ch][mt][r];
+        }
+    }
+}
+
 __global__ void zero_kernel(float* __restrict__ p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0.f;
@@ -508,6 +665,32 @@ hipError_t mlp_loss_grad_launch(dwos_mlp* m, hipStream_t s, const float* X, cons
     splits = (chunks + per - 1) / per;
     hipLaunchKernelGGL(wgrad_kernel, dim3(kLayers * 16, (unsigned)splits), dim3(64), 0, s,
                        m->ws.as<__bf16>(), pad, per, m->grad.as<float>());
+    return hipGetLastError();
+}
+
+hipError_t mlp_vjp_launch(dwos_mlp* m, hipStream_t s, const float* X, const float* Nbar,
+                          const float* Lbar, int64_t n) {
+    hipError_t e;
+    if ((e = zero(m->grad.as<float>(), kThetaSize, s)) != hipSuccess) return e;
+    if (n <= 0) return hipSuccess;
+    const int NC = m->dim + 2;
+    const int64_t pad = (n + 31) / 32 * 32;
+    if ((e = m->ws.reserve((size_t)kLayers * NC * 4 * kWidth * pad * sizeof(__bf16))) != hipSuccess) return e;
+    if ((e = m->zs.reserve((size_t)kLayers * NC * kWidth * pad * sizeof(float))) != hipSuccess) return e;
+    VjpArgs a{m->packed.as<u32x4>(), m->theta.as<float>(), m->B.as<float>(), m->F, X, Nbar, Lbar, n, pad,
+              m->grad.as<float>(), m->ws.as<__bf16>(), m->zs.as<float>()};
+    const dim3 grid(grid_for_tiles(pad, 1024)), block(256);
+    if (m->dim == 2) hipLaunchKernelGGL(vjp_kernel<2>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(vjp_kernel<3>, grid, block, 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // weight gradients: contraction over the pad * NC (point, channel) pairs
+    const int64_t padv = pad * NC;
+    const int64_t chunks = padv / 32;
+    int64_t splits = chunks < 128 ? chunks : 128;
+    const int64_t per = (chunks + splits - 1) / splits;
+    splits = (chunks + per - 1) / per;
+    hipLaunchKernelGGL(wgrad_kernel, dim3(kLayers * 16, (unsigned)splits), dim3(64), 0, s,
+                       m->ws.as<__bf16>(), padv, per, m->grad.as<float>());
     return hipGetLastError();
 }
 
@@ -612,6 +795,18 @@ dwos_status dwos_mlp_loss_grad(dwos_mlp* m, const float* X, const float* T, cons
     if (n < 0 || (n > 0 && (!X || !T))) return fail(DWOS_EINVAL, "mlp_loss_grad: bad arguments");
     HIP_OK(hipSetDevice(m->device));
     HIP_OK(dwos_host::mlp_loss_grad_launch(m, m->stream, X, T, w, n, loss));
+    if (grad)
+        HIP_OK(hipMemcpyAsync(grad, m->grad.ptr, (size_t)dwos_mlp_k::kThetaSize * sizeof(float),
+                              hipMemcpyDeviceToDevice, m->stream));
+    return DWOS_OK;
+}
+
+dwos_status dwos_mlp_vjp(dwos_mlp* m, const float* X, const float* Nbar, const float* Lbar, int64_t n,
+                         float* grad) {
+    if (!m) return fail(DWOS_EINVAL, "mlp_vjp: NULL network");
+    if (n < 0 || (n > 0 && (!X || !Nbar))) return fail(DWOS_EINVAL, "mlp_vjp: bad arguments");
+    HIP_OK(hipSetDevice(m->device));
+    HIP_OK(dwos_host::mlp_vjp_launch(m, m->stream, X, Nbar, Lbar, n));
     if (grad)
         HIP_OK(hipMemcpyAsync(grad, m->grad.ptr, (size_t)dwos_mlp_k::kThetaSize * sizeof(float),
                               hipMemcpyDeviceToDevice, m->stream));

@@ -41,6 +41,7 @@ struct dwos_mlp {
     // unit-major with the batch padded to a multiple of 32
     dwos_host::DevBuf ws;
     int64_t ws_pad = 0;
+    dwos_host::DevBuf zs;   // pre-activations of every layer and channel (vjp)
 };
 
 namespace dwos_host {
@@ -57,6 +58,10 @@ hipError_t mlp_eval_launch(const dwos_mlp* m, hipStream_t s, const TX* X, int64_
 // (device, may be NULL) := the loss.
 hipError_t mlp_loss_grad_launch(dwos_mlp* m, hipStream_t s, const float* X, const float* T,
                                 const float* w, int64_t n, float* loss);
+
+// grad := d/dtheta sum_i (Nbar_i N(x_i) + Lbar_i Lap N(x_i)) (Lbar may be NULL).
+hipError_t mlp_vjp_launch(dwos_mlp* m, hipStream_t s, const float* X, const float* Nbar,
+                          const float* Lbar, int64_t n);
 
 // One Adam step on theta with the current grad, then repack the BF16 weights.
 hipError_t mlp_adam_launch(dwos_mlp* m, hipStream_t s, float lr, float beta1, float beta2,

@@ -108,9 +108,16 @@ struct WalkArgs {
     // Per walk: cv_run (-1 no terminal, 0 nested walks skipped, 1 run),
     // the offset point, the terminal point and g there.  Per nested walk
     // (walk-major, K per walk): the stop point, the reservoir-chosen ball
-    // sample y = x_J + rho d_J dir, and 2 L + alive (L source steps; alive:
+    // sample y = x_J + rho d_J dir, S and alive (alive:
     // ended in the shell or at the cap rather than by roulette).
+    // S: the walk's total Green's-function mass over its source steps; the
+    // ball sample is taken in the step chosen with probability m_j / S.
     int32_t* cv_run;
+    // per original primitive: 1 if a vertex moves or carries a value
+    // parameter; the nested walks of a terminal on any other primitive are
+    // skipped (their mean enters every derivative times V_n = 0 and
+    // gdot = 0) and reported as g.  NULL: run everywhere.
+    const int32_t* prim_dep;
     T* cv_xoff;
     T* cv_xbar;
     T* cv_g;
@@ -118,7 +125,8 @@ struct WalkArgs {
     T* cv_y;
     T* cv_rho;
     T* cv_d;
-    int32_t* cv_La;
+    T* cv_S;
+    int32_t* cv_alive;
     uint32_t cv_qthresh;     // nested walks run iff (u32 >> 8) < cv_qthresh; 1 << 24: always
 };
 
@@ -630,7 +638,7 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
     T term_b1 = T(0), term_b2 = T(0);
     int64_t wsteps = 0;
     // control-variate trace of the current nested walk
-    int32_t cv_L = 0;
+    T cv_S = T(0);
     T ysel[D], rho_sel = T(0), d_sel = T(0);
 #pragma unroll
     for (int c = 0; c < D; ++c) ysel[c] = T(0);
@@ -766,6 +774,17 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
 #pragma unroll
                 for (int c = 0; c < D; ++c) xoff[c] = xbar[c] - delta * n[c];
                 c_term++;
+                if (a.prim_dep && !a.prim_dep[orig]) {
+                    a.rec_u[wid] = u_main;
+                    a.rec_prim[wid] = term_code;
+                    a.rec_b[(size_t)wid * (D - 1)] = term_b1;
+                    if constexpr (D == 3) a.rec_b[(size_t)wid * 2 + 1] = term_b2;
+                    a.rec_uoff[wid] = g;
+                    if (a.cv_run) a.cv_run[wid] = -1;
+                    if (a.rec_steps) a.rec_steps[wid] = wsteps;
+                    wid = -1;
+                    continue;
+                }
                 if (a.cv_run) {
 #pragma unroll
                     for (int c = 0; c < D; ++c) {
@@ -793,7 +812,7 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
                 }
                 // start the first nested forward walk at the offset point
                 phase = 1;
-                cv_L = 0; rho_sel = T(0); d_sel = T(0);
+                cv_S = T(0); rho_sel = T(0); d_sel = T(0);
 #pragma unroll
                 for (int c = 0; c < D; ++c) x[c] = xoff[c];
                 acc = T(0); k = 0; warm = term_leaf;
@@ -807,11 +826,13 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
             const uint32_t tag = inst_tag | (nested ? (1u | ((uint32_t)(phase - 1) << 8)) : 0u);
             const u4 r = philox10(u4{k, m, p, tag}, key0, key1);
             if (MODE == 1 && nested && a.cv_run) {
-                // reservoir choice of one source step, uniform over the walk's
-                // source steps, with one uniform point of its ball
-                ++cv_L;
+                // weighted reservoir choice of one source step (probability
+                // proportional to its ball's Green's-function mass) with one
+                // uniform point of its ball
+                const T mj = green_mass<D, T>(kappa, d);
+                cv_S += mj;
                 const u4 r3 = philox10(u4{k, m, p, tag | 4u}, key0, key1);
-                if ((unsigned long long)(r3.x >> 8) * (unsigned long long)cv_L < (1ull << 24)) {
+                if (unif<T>(r3.x) * cv_S < mj) {
                     T dir[3];
                     unit_dir<T, D>(r3.y, r3.z, dir);
                     T rho;
@@ -874,7 +895,8 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
                 }
                 a.cv_rho[q] = rho_sel;
                 a.cv_d[q] = d_sel;
-                a.cv_La[q] = 2 * cv_L + (alive ? 1 : 0);
+                a.cv_S[q] = cv_S;
+                a.cv_alive[q] = alive ? 1 : 0;
             }
             if (phase >= a.prm.K) {
                 a.rec_u[wid] = u_main;
@@ -889,7 +911,7 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
 #pragma unroll
                 for (int c = 0; c < D; ++c) x[c] = xoff[c];
                 acc = T(0); k = 0; warm = term_leaf;
-                cv_L = 0; rho_sel = T(0); d_sel = T(0);
+                cv_S = T(0); rho_sel = T(0); d_sel = T(0);
                 c_nested++;
             }
         }

@@ -85,5 +85,14 @@ class Network:
         check(capi.dwos_mlp_loss_grad(self._m, _dev(X), _dev(T), _dev(w), X.shape[0], _dev(loss), _dev(g)))
         return loss, g
 
+    def vjp(self, X, Nbar, Lbar=None):
+        """d/dtheta sum_i (Nbar_i N(x_i) + Lbar_i Lap N(x_i))."""
+        X = X.to(torch.float32).contiguous()
+        Nbar = Nbar.to(torch.float32).contiguous()
+        Lbar = None if Lbar is None else Lbar.to(torch.float32).contiguous()
+        g = torch.empty(theta_size(), dtype=torch.float32, device=X.device)
+        check(capi.dwos_mlp_vjp(self._m, _dev(X), _dev(Nbar), _dev(Lbar), X.shape[0], _dev(g)))
+        return g
+
     def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         check(capi.dwos_mlp_adam_step(self._m, float(lr), float(beta1), float(beta2), float(eps)))

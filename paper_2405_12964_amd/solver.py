@@ -267,6 +267,12 @@ class Solver:
         self._cv = net
         check(capi.dwos_cv_attach(self._ctx, net.handle if net is not None else None, float(q)))
 
+    def cv_beta(self) -> float:
+        """Coefficient of the control variate in the next differential call."""
+        b = C.c_double()
+        check(capi.dwos_cv_beta(self._ctx, C.byref(b)))
+        return b.value
+
     def cv_train(self, steps: int, batch: int, lr: float, seed: int):
         """Adam steps of the attached network on the last differential walks'
         records; returns the last step's loss (device float32 tensor)."""
@@ -286,7 +292,7 @@ class Solver:
         n = nested.view(P, W, K, 10)
         return dict(run=w[..., 0].to(torch.int32), xoff=w[..., 1:4], uoff=w[..., 4], uoff_cv=w[..., 5],
                     target=w[..., 6], u=w[..., 7], prim=w[..., 8].to(torch.int32),
-                    L=n[..., 0].to(torch.int64), alive=n[..., 1].to(torch.int32), xstop=n[..., 2:5],
+                    S=n[..., 0], alive=n[..., 1].to(torch.int32), xstop=n[..., 2:5],
                     y=n[..., 5:8], rho=n[..., 8], d=n[..., 9])
 
     def walk_timing(self, kind: int, reset=False):

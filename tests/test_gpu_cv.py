@@ -7,8 +7,8 @@
   with random-sign rounding over 64 inputs and four layers the absolute error
   of a channel stays within 1e-4 of that channel's scale (the largest
   magnitude it takes over the sample); measured: ~1.2e-5.
-* Walk-for-walk (FP64 walks): run flags, reservoir counts, alive flags, stop
-  points, ball samples and the plain nested means equal the oracle's; the
+* Walk-for-walk (FP64 walks): run flags, alive flags, Green's-function masses,
+  stop points, ball samples and the plain nested means equal the oracle's; the
   control-variate estimates differ only through the network's error.
 * Statistical (FP32 walks): the differential estimate with the control
   variate agrees with the oracle's and with the closed-form shape derivative.
@@ -98,6 +98,27 @@ def test_network_loss_gradient_and_adam_match_oracle(dev, dwos, oracle_mod):
     assert np.abs(th1 - tho).max() <= 2 * lr + 1e-6
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_network_vjp_matches_oracle(dev, dwos, oracle_mod, dim):
+    """Reverse mode through the value and Laplacian channels:
+    d/dtheta sum_i (Nbar_i N + Lbar_i Lap N) against the oracle (FP64)."""
+    B, th = scenes.mlp_init(dim, 51 + dim, 1.0)
+    B = B.astype(np.float32).astype(np.float64)
+    th = th.astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(52)
+    n = 333
+    X = rng.uniform(-1.5, 1.5, (n, dim)).astype(np.float32)
+    Nb = (rng.normal(size=n) / n).astype(np.float32)
+    Lb = (rng.normal(size=n) / n * 0.05).astype(np.float32)
+    net = dwos.Network(dim, B, th)
+    g = net.vjp(T(X, dev, torch.float32), T(Nb, dev, torch.float32), T(Lb, dev, torch.float32))
+    go = oracle_mod.Net(dim, B, th).vjp(X.astype(np.float64), Nb.astype(np.float64), Lb.astype(np.float64))
+    g = g.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(g - go) / np.linalg.norm(go)
+    print(f"vjp dim {dim}: rel err {rel:.2e}")
+    assert rel < 2e-3
+
+
 def _disk_scene(sigma=10.0, delta=0.25, src=3.0):
     sc = scenes.c1_polygon(256, g="one", eps=1e-3, delta=delta, sigma=sigma)
     return sc.with_(src_c0=src, gauss=np.array([[5.0, 0.2, -0.1, 0.3]]))
@@ -121,7 +142,7 @@ def test_cv_walk_records_walk_for_walk(dev, dwos, oracle_mod, case):
     net = dwos.Network(sc.dim, B, th)
     s.attach_cv(net, q)
     rg = {k: v.cpu().numpy() for k, v in s.cv_walk_records(T(X, dev), W, 74).items()}
-    for k in ("run", "prim", "L", "alive"):
+    for k in ("run", "prim", "alive"):
         assert np.array_equal(rg[k], ro[k]), k
     run = ro["run"] == 1
     assert run.sum() > (0.3 if q == 1 else 0.1) * run.size
@@ -129,22 +150,23 @@ def test_cv_walk_records_walk_for_walk(dev, dwos, oracle_mod, case):
         assert (ro["run"] == 0).sum() > 0.1 * run.size
     for k in ("xoff", "uoff", "u"):
         np.testing.assert_allclose(rg[k], ro[k], rtol=1e-9, atol=1e-9, err_msg=k)
-    for k in ("y", "rho", "d"):
+    for k in ("y", "rho", "d", "S"):
         np.testing.assert_allclose(rg[k][run], ro[k][run], rtol=1e-9, atol=1e-9, err_msg=k)
     alive = (ro["alive"] == 1) & run[..., None]
     np.testing.assert_allclose(rg["xstop"][alive], ro["xstop"][alive], rtol=1e-9, atol=1e-9)
     # the control-variate estimates: network error only.  Bound per walk:
-    # |dN| (1 + 1/q) + L |B| G (|dLap| + sigma |dN|) with the network's error
+    # |dN| (1 + 1/q) + (S |B| G / m) (|dLap| + sigma |dN|) with the network's error
     # levels eN, eL from its own parity bound (1e-4 of the channel scale)
     onet = oracle_mod.Net(sc.dim, B, th, q)
     pts = np.concatenate([ro["xoff"][..., :sc.dim].reshape(-1, sc.dim), ro["y"][..., :sc.dim].reshape(-1, sc.dim)])
     No, _, Lo = onet.eval(pts)
     eN, eL = 1e-4 * _scale(No), 1e-4 * _scale(Lo)
-    L = ro["L"][..., 0].astype(float)
+    Sm = ro["S"][..., 0]
     GB = np.vectorize(lambda r, R: oracle_mod.green(sc.dim, sc.sigma, r * R, R) *
-                      (math.pi * R * R if sc.dim == 2 else 4 / 3 * math.pi * R ** 3) if R > 0 else 0.0)(
+                      (math.pi * R * R if sc.dim == 2 else 4 / 3 * math.pi * R ** 3) /
+                      oracle_mod.green_mass(sc.dim, sc.sigma, R) if R > 0 else 0.0)(
         ro["rho"][..., 0], ro["d"][..., 0])
-    bound = eN * (1 + 1 / q) + (L * GB * (eL + sc.sigma * eN) + eN) / q
+    bound = eN * (1 + 1 / q) + (Sm * GB * (eL + sc.sigma * eN) + eN) / q
     for k in ("uoff_cv", "target"):
         d = np.abs(rg[k] - ro[k])
         sel = ro["run"] >= 0 if k == "uoff_cv" else run

@@ -212,8 +212,8 @@ def _disk(oracle_mod, sigma=10.0, src=0.0, n=256, delta=1e-2):
 def test_cv_leaves_the_walks_unchanged(oracle_mod):
     """The control variate draws from its own counter purpose: the main and
     nested walks, their terminal points and plain nested means are those of
-    the plain estimator; the reservoir count L equals the nested walk's
-    source steps (>= 1 since delta > eps)."""
+    the plain estimator; every nested walk has source steps (delta > eps), so
+    its Green's-function mass S is positive."""
     sc = _disk(oracle_mod, src=3.0)
     X = scenes.points_in_disk(8, 0.8, 51)
     o = oracle_mod.Oracle(sc)
@@ -225,8 +225,11 @@ def test_cv_leaves_the_walks_unchanged(oracle_mod):
     term = rc["prim"] >= 0
     assert np.array_equal(rc["run"], np.where(term, 1, -1))
     assert np.array_equal(rp["uoff"][term], rc["uoff"][term])
-    assert np.all(rc["L"][term] >= 1)
-    assert np.all(rc["L"][~term] == 0)
+    assert np.all(rc["S"][term] > 0)
+    assert np.all(rc["S"][~term] == 0)
+    # S is at least the mass of the selected ball
+    m = np.vectorize(lambda d: oracle_mod.green_mass(2, sc.sigma, d))(rc["d"][term])
+    assert np.all(rc["S"][term] >= m * (1 - 1e-12))
     # reservoir point lies in its ball; xoff is the offset of the terminal point
     dy = rc["y"][term, 0, :2] - 0  # y lies within d of the selected centre: |y| < 1
     assert np.all(np.linalg.norm(dy, axis=1) < 1.0)
@@ -256,7 +259,7 @@ def test_cv_constant_network_identity(oracle_mod):
     """N = 1: -Lap N + sigma N = sigma, so the zero-mean identity reads
     P(alive) + E[L |B| G sigma] = 1 -- the walk's killing probability equals its
     expected Green's-function integral of sigma.  A wrong Green's weight, a
-    dropped L or a wrong alive flag breaks it.  The nested walks start a
+    wrong reservoir weight or a wrong alive flag breaks it.  The nested walks start a
     quarter of the radius inside (delta = 0.25) so that they take many steps
     in large balls."""
     sc = _disk(oracle_mod, sigma=30.0, delta=0.25)
@@ -296,6 +299,28 @@ def test_cv_has_zero_mean_for_any_network(oracle_mod, case):
     m, se = _mean_se(C)
     assert abs(m) < 4 * se, (m, se)
     assert np.std(C) > 0.05     # the control variate is far from zero walk by walk
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_green_mass_series(oracle_mod, D):
+    """The Green's-function mass int_B G: equal to (1 - Q)/sigma where that
+    has no cancellation, to the quadrature of G for tiny balls (where 1 - Q
+    cancels), and to R^2/(2D) at sigma = 0."""
+    from scipy import integrate
+    for sigma in (0.0, 0.3, 4.0, 10.0):
+        for R in (1e-4, 1e-2, 0.3, 0.9, 2.5):
+            m = oracle_mod.green_mass(D, sigma, R)
+            if D == 2:
+                f = lambda r: oracle_mod.green(2, sigma, r, R) * 2 * math.pi * r
+            else:
+                f = lambda r: oracle_mod.green(3, sigma, r, R) * 4 * math.pi * r * r
+            val, _ = integrate.quad(f, 0.0, R, limit=200, epsabs=0, epsrel=1e-11)
+            assert m == pytest.approx(val, rel=1e-8), (D, sigma, R)
+            if sigma > 0 and math.sqrt(sigma) * R > 1:
+                Q = oracle_mod.poisson_scale(D, sigma, R)
+                assert m == pytest.approx((1 - Q) / sigma, rel=1e-12)
+            if sigma == 0:
+                assert m == pytest.approx(R * R / (2 * D), rel=1e-14)
 
 
 def _bowl_net(oracle_mod, dim, q=1.0):
@@ -373,3 +398,41 @@ def test_cv_shape_derivative_disk(oracle_mod):
     jm, jv, _, _ = oracle_mod.Oracle(sc).jvp(X, 2048, 61, cv=_net(oracle_mod, 2, seed=24, q=0.5))
     exact = -k * special.i0(k * r) * special.i1(k) / special.i0(k) ** 2
     check_vs_exact(jm[:, 0], np.sqrt(jv[:, 0]), exact, 0.045 * np.abs(exact).max(), "P6 disk CV")
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_value_laplacian_vjp_matches_autograd(oracle_mod, dim):
+    """d/dtheta sum_i (Nbar_i N + Lbar_i Lap N) against torch's double
+    backward (float64) and a directional finite difference of the oracle's
+    own forward channels."""
+    B, th = scenes.mlp_init(dim, 13 + dim, 1.0)
+    th[np.arange(4) * (H * H + H) + H * H] = 0.1   # some nonzero biases
+    net = oracle_mod.Net(dim, B, th)
+    rng = np.random.default_rng(20 + dim)
+    n = 9
+    X = rng.uniform(-1.2, 1.2, (n, dim))
+    Nb, Lb = rng.normal(size=n), rng.normal(size=n) * 0.1
+    g = net.vjp(X, Nb, Lb)
+    # autograd: rebuild the network from a leaf theta
+    tt = torch.tensor(th, requires_grad=True)
+    F = B.shape[0]
+    x = torch.tensor(X, requires_grad=True)
+    ang = 2 * math.pi * x @ torch.tensor(B).T
+    a = torch.cat([torch.sin(ang), torch.cos(ang), x, torch.zeros(n, H - 2 * F - dim, dtype=x.dtype)], 1)
+    for l in range(4):
+        off = l * (H * H + H)
+        a = torch.tanh(a @ tt[off:off + H * H].reshape(H, H).T + tt[off + H * H:off + H * H + H])
+    y = a @ tt[4 * (H * H + H):4 * (H * H + H) + H] + tt[-1]
+    gx = torch.autograd.grad(y.sum(), x, create_graph=True)[0]
+    lap = sum(torch.autograd.grad(gx[:, c].sum(), x, create_graph=True)[0][:, c] for c in range(dim))
+    obj = (torch.tensor(Nb) * y).sum() + (torch.tensor(Lb) * lap).sum()
+    gt = torch.autograd.grad(obj, tt)[0].numpy()
+    np.testing.assert_allclose(g, gt, rtol=1e-8, atol=1e-10)
+    d = rng.normal(size=th.size)
+    h = 1e-6
+
+    def f(t):
+        N, _, L = oracle_mod.Net(dim, B, t).eval(X)
+        return float(Nb @ N + Lb @ L)
+    fd = (f(th + h * d) - f(th - h * d)) / (2 * h)
+    assert abs(fd - g @ d) < 1e-5 * (1 + abs(fd))

@@ -445,3 +445,24 @@ def test_central_difference_with_common_random_numbers(oracle_mod):
         z = (fm - jm[:, j]) / np.sqrt(fse ** 2 + jv[:, j])
         assert np.all(np.abs(z) < 4.0), (j, z, fm, jm[:, j])
         assert abs(np.mean(z)) < 4.0 / math.sqrt(len(z)) + 0.5, (j, z)
+
+
+def test_nested_walks_skipped_where_boundary_is_static(oracle_mod):
+    """Shell a < r < b with only the inner sphere moving: walks that end on
+    the static outer sphere run no nested walks (their mean enters every
+    derivative times V_n = 0), report the boundary value as the nested mean
+    and give a zero derivative; walks ending on the inner sphere do run them."""
+    sc = scenes.shell_scene(8, 8, 0.5, 1.0, 4.0, eps=1e-3, delta=1e-2)
+    X = scenes.points_in_ball(16, 0.6, 0.9, 91)
+    r = oracle_mod.Oracle(sc).walk_records(X, 64, 92, mode=1)
+    term = r["prim"] >= 0
+    outer = term & (sc.label[np.maximum(r["prim"], 0)] == 0)
+    inner = term & (sc.label[np.maximum(r["prim"], 0)] == 1)
+    assert outer.sum() > 50 and inner.sum() > 50
+    assert np.all(r["uoff"][outer] == 0.0)        # g = 0 on the outer sphere
+    assert np.all(r["udot"][outer] == 0.0)
+    # no nested walks: a main walk alone rarely takes fewer queries than
+    # main + nested; compare with the forward walk of the same stream
+    rf = oracle_mod.Oracle(sc).walk_records(X, 64, 92, mode=0)
+    assert np.array_equal(r["steps"][outer], rf["steps"][outer])
+    assert np.all(r["steps"][inner] > rf["steps"][inner])
