@@ -100,14 +100,139 @@ def cpu_baseline(sc, X, uref_np, seed, threads, npts=1024, W=1024):
                       f"(K=1 nested) of the same scene, brute-force FP64, {dt:.1f} s"}
 
 
+def run_c5(args):
+    """Shape from diffusion on the displaced icosphere (200,000 object
+    triangles + box) with the learned control variate, trained online.
+
+    65536 points on the box faces, W = 64 forward and 64 differential walks
+    per iteration, squared loss against a reference solution of the target
+    coefficients (seed 3), Adam on the 1024 coefficients from c = 0, and after
+    each backward 16 Adam steps of the control-variate network (30 Fourier
+    frequencies of scale 0.125, lr 1e-3) on that iteration's walk records.  After the timed iterations the gradient at the
+    final coefficients is re-estimated with independent seeds, plain and with
+    the control variate at q = 1, 0.5, 0.25, to compare variance x time."""
+    import numpy as np
+    import torch
+    import scenes
+    import paper_2405_12964_amd as dw
+
+    dev = torch.device("cuda:0")
+    P, W = args.points or 65536, args.walks or 64
+    nb = 1024
+    sc = scenes.c3_icosphere(nu=100, n_basis=nb, coef=np.zeros(nb))
+    X = scenes.points_on_box_faces(P, 1)
+    Xt = torch.tensor(X, dtype=torch.float64, device=dev)
+    coef_t = np.random.default_rng(3).normal(0.0, 0.05, nb)
+    ref = dw.Solver.from_scene(sc, "fp32", V=scenes.vertices_at(sc, coef_t))
+    uref, _ = ref.solve(Xt, 1024, 99)
+    torch.cuda.synchronize()
+    del ref
+
+    model = dw.ShapeModel(sc, "fp32")
+    B, th = scenes.mlp_init(3, args.cv_seed, args.cv_freq, args.cv_features)
+    th[-(scenes.MLP_WIDTH + 1):] = 0.0        # N = 0: the first calls are plain
+    net = dw.Network(3, B, th)
+    model.solver.attach_cv(net, 1.0)
+    pi = torch.zeros(nb, dtype=torch.float64, device=dev, requires_grad=True)
+    opt = torch.optim.Adam([pi], lr=1e-3)
+
+    def step(i):
+        opt.zero_grad(set_to_none=True)
+        u = dw.DWoSFunction.apply(pi, Xt, model, W, 1000 + 2 * i, W, 1001 + 2 * i)
+        loss = 0.5 * ((u - uref) ** 2).sum()
+        loss.backward()
+        opt.step()
+        model.solver.cv_train(args.cv_steps, args.cv_batch, args.cv_lr, 50000 + i)
+        return loss
+
+    coef_t_dev = torch.tensor(coef_t, device=dev)
+    err0 = float(torch.linalg.norm(pi.detach() - coef_t_dev).item())
+    loss0 = float(step(0).item())
+    for i in range(1, args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    for kind in (0, 1):
+        model.solver.walk_timing(kind, reset=True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        loss = step(args.warmup + i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms0, n0, tot0 = model.solver.walk_timing(0)
+    ms1, n1, tot1 = model.solver.walk_timing(1)
+
+    # gradient variance at the final coefficients: plain vs control variate
+    with torch.no_grad():
+        model.apply(pi)
+        u, _ = model.solver.solve(Xt, W, 777)
+        w = (u - uref).contiguous()
+
+    def grads(q, reps=6):
+        if q is None:
+            model.solver.attach_cv(None)
+        else:
+            model.solver.attach_cv(net, q)
+            model.solver.grad(Xt, w, W, 900)          # sets beta for this q
+        gs, ts = [], []
+        for r in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            g, _ = model.solver.grad(Xt, w, W, 901 + r, u_mean=False)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+            gs.append(g.cpu().numpy())
+        gs = np.array(gs)
+        beta = model.solver.cv_beta() if q is not None else None
+        return float(gs.var(axis=0, ddof=1).sum()), float(np.mean(ts)), gs.mean(axis=0), beta
+
+    v_plain, t_plain, g_mean, _ = grads(None)
+    cv = {"plain": {"grad_var": v_plain, "ms": 1e3 * t_plain}}
+    for q in (1.0, 0.5, 0.25):
+        v, t, _, beta = grads(q)
+        cv[f"q={q}"] = {"grad_var": v, "ms": 1e3 * t, "beta": beta, "var_ratio": v / v_plain,
+                        "efficiency": (v_plain * t_plain) / (v * t)}
+    steps_total = tot0["steps"] + tot1["steps"]
+    return {
+        "metric": METRIC, "value": steps_total / elapsed, "unit": "walk-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "3D shape from diffusion: displaced icosphere (200,000 triangles) in a "
+                               f"box, sigma=4, {P} points x {W} walks per iteration, 1024 coefficients, "
+                               "learned control variate trained online", "points": P,
+                   "walks_per_point": W, "triangles": int(sc.prims.shape[0]), "params": nb},
+        "grad_evals_per_s": args.steps / elapsed,
+        "walk_steps": {"forward": tot0["steps"], "differential": tot1["steps"],
+                       "forward_ms": ms0, "differential_ms": ms1},
+        "loss_first": loss0, "loss": float(loss.item()),
+        "coef_error_first": err0, "coef_error": float(torch.linalg.norm(pi.detach() - coef_t_dev).item()),
+        "grad_norm": float(np.linalg.norm(g_mean)),
+        # cosine between the descent direction and the way to the target
+        "grad_alignment": float(-g_mean @ (coef_t - pi.detach().cpu().numpy()) /
+                                (np.linalg.norm(g_mean) * np.linalg.norm(coef_t - pi.detach().cpu().numpy()))),
+        "cv_training": {"freq_scale": args.cv_freq, "features": args.cv_features, "init_seed": args.cv_seed,
+                        "adam_steps_per_iteration": args.cv_steps, "batch": args.cv_batch, "lr": args.cv_lr},
+        "control_variate": cv,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--points", type=int, default=4096)
-    ap.add_argument("--walks", type=int, default=4096)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", choices=["c2", "c5"], default="c2",
+                    help="c2: 2D star (the reported configuration); c5: 3D shape from diffusion "
+                         "with the learned control variate")
+    ap.add_argument("--points", type=int, default=0)
+    ap.add_argument("--walks", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cv-freq", type=float, default=0.125, help="c5: Fourier frequency scale")
+    ap.add_argument("--cv-features", type=int, default=30, help="c5: Fourier frequencies (2F + 3 <= 64)")
+    ap.add_argument("--cv-steps", type=int, default=16, help="c5: network Adam steps per iteration")
+    ap.add_argument("--cv-batch", type=int, default=8192, help="c5: walks per network Adam step")
+    ap.add_argument("--cv-lr", type=float, default=1e-3, help="c5: network learning rate")
+    ap.add_argument("--cv-seed", type=int, default=4, help="c5: network initialisation seed")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -117,13 +242,21 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
+    if args.workload == "c5":
+        args.steps = 50 if args.steps is None else args.steps
+        args.warmup = 150 if args.warmup is None else args.warmup
+        print(json.dumps(run_c5(args)), flush=True)
+        return
+    args.steps = 5 if args.steps is None else args.steps
+    args.warmup = 2 if args.warmup is None else args.warmup
+
     import numpy as np
     import torch
     import scenes
     import paper_2405_12964_amd as dw
 
     dev = torch.device("cuda:0")
-    P, W = args.points, args.walks
+    P, W = args.points or 4096, args.walks or 4096
     sc = scenes.c2_star(n=4096, coef_seed=0)
     X = scenes.star_points(P, 1)
     Xt = torch.tensor(X, dtype=torch.float64, device=dev)

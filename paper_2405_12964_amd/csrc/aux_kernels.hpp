@@ -204,6 +204,11 @@ struct AccArgs {
     const double* w;         // mode 0
     const double* uref;      // mode 1
     const int32_t* bc_pid;
+    // skip lists (NULL: none): terminals on primitives that depend on no
+    // parameter, and vertices without a Jacobian row or value parameter --
+    // their accumulators are multiplied by zero in the SpMV
+    const int32_t* prim_dep;
+    const int32_t* vparam;
     double* A;               // nv x D
     double* Bacc;            // nv
 };
@@ -214,6 +219,7 @@ __global__ void __launch_bounds__(256) accumulate_kernel(AccArgs<T> a) {
     if (i >= a.nwalks) return;
     const int32_t code = a.rec_prim[i];
     if (code < 0) return;
+    if (a.prim_dep && !a.prim_dep[code >> 1]) return;
     const int64_t pl = i / a.W;
     const int32_t m = (int32_t)(i - pl * a.W);
     const int64_t p = pl + a.p_offset;
@@ -232,6 +238,7 @@ __global__ void __launch_bounds__(256) accumulate_kernel(AccArgs<T> a) {
     terminal_term<T, D>(a.s, a.prm, a.delta, code, a.rec_b + i * (D - 1), a.rec_uoff[i], t);
 #pragma unroll
     for (int k = 0; k < D; ++k) {
+        if (a.vparam && !a.vparam[t.vid[k]]) continue;
         const double wb = omega * double(t.bary[k]);
 #pragma unroll
         for (int c = 0; c < D; ++c) unsafeAtomicAdd(&a.A[(size_t)t.vid[k] * D + c], wb * double(t.Tvec[c]));

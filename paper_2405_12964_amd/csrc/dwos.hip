@@ -677,6 +677,8 @@ dwos_status run_op(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
             aa.w = o.w;
             aa.uref = o.uref;
             aa.bc_pid = c->has_bc_params ? c->bc_pid.as<int32_t>() : nullptr;
+            aa.prim_dep = c->prim_dep.as<int32_t>();
+            aa.vparam = c->vparam.as<int32_t>();
             aa.A = c->accA.as<double>();
             aa.Bacc = c->accB.as<double>();
             hipLaunchKernelGGL((dwos::accumulate_kernel<T, D>), dim3(blocks_for(walks, 256)), dim3(256), 0, s, aa);
