@@ -45,7 +45,10 @@ class Network:
     def __del__(self):
         m = getattr(self, "_m", None)
         if m is not None and m.value:
-            capi.lib().dwos_mlp_destroy(m)
+            try:
+                capi.lib().dwos_mlp_destroy(m)
+            except Exception:   # interpreter shutdown: module globals already gone
+                pass
             self._m = None
 
     @property
