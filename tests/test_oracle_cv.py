@@ -372,6 +372,36 @@ def test_cv_has_zero_mean_for_a_concave_network(oracle_mod, case):
     assert abs(m) < 4 * se, (m, se)
 
 
+def test_cv_has_zero_mean_for_a_residual_that_changes_along_the_walk(oracle_mod):
+    """N = chain of tanh units over sum_i cos(2 pi 0.6 d_i . x) for 16
+    directions d_i (close to 16 J0(3.77 r)): its residual -Lap N + sigma N is
+    positive for r < 0.64 and negative beyond.  The nested walks start at
+    r = 0.5 (delta = 0.5), so their first, large balls sit where the residual
+    is positive and their last, small balls where it is negative: a source
+    step not chosen in proportion to its ball's Green's mass (e.g. always the
+    last one) biases the control variate."""
+    F = scenes.MLP_FREQS
+    a = 2 * np.pi * np.arange(F) / F
+    B = 0.6 * np.stack([np.cos(a), np.sin(a)], 1)
+    th = np.zeros(scenes.MLP_THETA_SIZE)
+    th[F:2 * F] = 0.1
+    for l in (1, 2, 3):
+        th[l * (H * H + H)] = 1.0
+    th[4 * (H * H + H)] = 10.0
+    net = oracle_mod.Net(2, B, th)
+    sc = _disk(oracle_mod, sigma=10.0, delta=0.5)
+    P = np.array([[0.0, 0.0], [0.3, 0.2], [0.0, 0.95], [0.7, 0.68]])
+    N0, _, Lp = net.eval(P)
+    fN = -Lp + sc.sigma * N0
+    assert fN[0] > 0 and fN[1] > 0 and fN[2] < 0 and fN[3] < 0
+    X = scenes.points_in_disk(32, 0.8, 96)
+    r = oracle_mod.Oracle(sc).walk_records_cv(X, 256, 97, net)
+    term = r["run"] == 1
+    C = (r["uoff_cv"] - r["uoff"])[term]
+    m, se = _mean_se(C)
+    assert abs(m) < 4 * se, (m, se)
+
+
 def test_cv_mean_is_independent_of_q(oracle_mod):
     """Skipping the nested walks with probability 1 - q and reweighting the
     residual by 1/q keeps the mean: per walk the offset point is the same, so

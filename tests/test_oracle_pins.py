@@ -466,3 +466,27 @@ def test_nested_walks_skipped_where_boundary_is_static(oracle_mod):
     rf = oracle_mod.Oracle(sc).walk_records(X, 64, 92, mode=0)
     assert np.array_equal(r["steps"][outer], rf["steps"][outer])
     assert np.all(r["steps"][inner] > rf["steps"][inner])
+
+
+def test_vertex_value_parameters_sum_to_constant_data_solution(oracle_mod):
+    """Mapped data whose only parameters are the vertex values g_i (no vertex
+    moves): u is linear in the g_i, so sum_i du/dg_i is the solution for
+    g = 1 -- I0(kr)/I0(kR) on the disk (1 at sigma = 0).  Every terminal
+    depends on a parameter through its values alone."""
+    n = 256
+    for sigma in (0.0, 10.0):
+        base = scenes.c1_polygon(n, mapped=True, g="one", eps=1e-3, delta=1e-2, sigma=sigma)
+        sc = base.with_(N=n, rowptr=np.zeros(n + 1, np.int64), pid=np.zeros(0, np.int32),
+                        vel=np.zeros((0, 2)), bc_pid=np.arange(n, dtype=np.int32))
+        X = scenes.points_in_disk(16, 0.8, 93)
+        jm, jv, _, _ = oracle_mod.Oracle(sc).jvp(X, 2048, 94)
+        tot = jm.sum(axis=1)
+        # the per-walk sum has its own variance: estimate it from the mean
+        # and per-parameter variances conservatively (parameters of one walk
+        # are correlated), via an independent second run
+        jm2, _, _, _ = oracle_mod.Oracle(sc).jvp(X, 2048, 95)
+        se = np.abs(tot - jm2.sum(axis=1)) / np.sqrt(2) + 1e-3
+        k = math.sqrt(sigma)
+        r = np.linalg.norm(X, axis=1)
+        exact = special.i0(k * r) / special.i0(k) if sigma > 0 else np.ones(len(X))
+        assert np.all(np.abs(tot - exact) < 4 * se + 0.01), (sigma, tot - exact)
