@@ -24,6 +24,13 @@ namespace dwos {
 #ifndef DWOS_BLOCK
 #define DWOS_BLOCK 256
 #endif
+// A wavefront stops traversing once this many of its lanes have their query
+// answered; they take their walk step while the others resume later.
+#ifndef DWOS_PARK
+#define DWOS_PARK 32
+#endif
+constexpr int kParkLanes = DWOS_PARK;
+
 #ifndef DWOS_LDS_STACK
 #define DWOS_LDS_STACK 0
 #endif
@@ -357,75 +364,87 @@ template <class T> struct TravStack<T, true> {
     __device__ __forceinline__ T get_d(int i) const { return d[i * kBlock]; }
 };
 
-#ifndef DWOS_TRAV
-#define DWOS_TRAV 2
-#endif
-
-// DistanceToBoundary: nearest primitive to x through the pair-node BVH.
-// Starts from the upper bound given by a previously closest primitive
-// (`warm`, leaf position, or -1) -- the new closest point can only be at
-// that distance or nearer, so the result is unchanged while most of the tree
-// is pruned.  Ties go to the lowest original primitive index.
+// DistanceToBoundary: nearest primitive to x through the pair-node BVH, as a
+// resumable query so that a wavefront can stop traversing when enough of its
+// lanes have their answer (see walk_kernel).  The query starts from the upper
+// bound given by a previously closest primitive (`warm`, leaf position, or
+// -1): the new closest point can only be at that distance or nearer, so the
+// result is unchanged while most of the tree is pruned.  Ties go to the
+// lowest original primitive index.
 //
-// Loop structure (the lanes of a wavefront run different queries):
-//   DWOS_TRAV 0: expand one node per iteration, testing hit leaves on the spot
-//   DWOS_TRAV 1: one unit per iteration (a primitive, a node, or a pop)
-//   DWOS_TRAV 2: alternate phases -- expand nodes until every lane holds a
-//                leaf or has finished, then test the held leaves together --
-//                so that node and primitive work are not interleaved within
-//                one iteration of the wavefront.
-template <class T, int D, class Stack>
-__device__ __forceinline__ int32_t closest_leaf(const Scene<T>& s, const StageView& sv, int32_t root,
-                                                const T* x, int32_t warm, T& best, QueryCount& qc,
-                                                Stack& st) {
-    constexpr T slack = Slack<T>::v;
-    best = T(INFINITY);
-    int32_t bleaf = -1;
+// One round alternates two phases over the wavefront: expand nodes until
+// every lane holds a leaf or has finished, then test the held leaves
+// together, so that node and primitive work are not interleaved within one
+// iteration.
+template <class T>
+struct Query {
+    T best;          // squared distance of the best primitive so far
+    int32_t bleaf;   // its leaf position, -1 none
+    int32_t node;    // internal node to expand next, or -1 (pop)
+    int32_t leaf;    // held leaf reference
+    int32_t sp;      // stack depth
+    bool has_leaf, done;
+};
+
+template <class T, int D>
+__device__ __forceinline__ void query_test_prim(const Scene<T>& s, const StageView& sv, const T* x,
+                                                int32_t i, Query<T>& q, QueryCount& qc) {
+    T P[9], bb[3];
+    scene_prim<T, D>(s, sv, i, P);
+    const T d2 = prim_closest<T, D>(P, x, bb);
+    qc.prims++;
+    if (d2 < q.best * (T(1) - TieBand<T>::v)) { q.best = d2; q.bleaf = i; }
+    else if (d2 <= q.best * (T(1) + TieBand<T>::v) && i != q.bleaf && s.orig[i] < s.orig[q.bleaf]) {
+        q.best = d2;
+        q.bleaf = i;
+    }
+}
+
+template <class T, int D>
+__device__ __forceinline__ void query_begin(const Scene<T>& s, const StageView& sv, int32_t root,
+                                            const T* x, int32_t warm, Query<T>& q) {
+    q.best = T(INFINITY);
+    q.bleaf = -1;
     if (warm >= 0) {
         T P[9], bb[3];
         scene_prim<T, D>(s, sv, warm, P);
-        best = prim_closest<T, D>(P, x, bb);
-        bleaf = warm;
+        q.best = prim_closest<T, D>(P, x, bb);
+        q.bleaf = warm;
     }
-    auto test_prim = [&](int32_t i) {
-        T P[9], bb[3];
-        scene_prim<T, D>(s, sv, i, P);
-        const T d2 = prim_closest<T, D>(P, x, bb);
-        qc.prims++;
-        if (d2 < best * (T(1) - TieBand<T>::v)) { best = d2; bleaf = i; }
-        else if (d2 <= best * (T(1) + TieBand<T>::v) && i != bleaf && s.orig[i] < s.orig[bleaf]) {
-            best = d2;
-            bleaf = i;
+    q.node = root;
+    q.leaf = 0;
+    q.sp = 0;
+    q.has_leaf = false;
+    q.done = false;
+}
+
+// One round for the lanes with `active` set (a query in progress).
+template <class T, int D, class Stack>
+__device__ __forceinline__ void query_round(const Scene<T>& s, const StageView& sv, const T* x, bool active,
+                                            Query<T>& q, QueryCount& qc, Stack& st) {
+    constexpr T slack = Slack<T>::v;
+    // phase 1: expand nodes until this lane holds a leaf or is finished
+#pragma unroll 1
+    while (active && !q.has_leaf && !q.done) {
+        int32_t cur = q.node;
+        if (cur < 0) {
+            if (q.sp == 0) { q.done = true; continue; }
+            --q.sp;
+            if (st.get_d(q.sp) > q.best * slack) continue;
+            cur = st.get_node(q.sp);
+            if (cur < 0) { q.leaf = cur; q.has_leaf = true; continue; }   // a postponed leaf
         }
-    };
-    auto test_leaf = [&](int32_t ref) {
-        const int32_t v = -1 - ref;
-        const int32_t start = v >> 3, n = (v & 7) + 1;
-        for (int32_t i = start; i < start + n; ++i) test_prim(i);
-    };
-    int sp = 0;
-#if DWOS_TRAV == 0
-    int32_t node = root;
-    while (true) {
         NodeData<T, D> nd;
-        scene_node<T, D>(s, sv, node, nd);
+        scene_node<T, D>(s, sv, cur, nd);
         qc.nodes++;
         const T d0 = fmax(box_d2<T, D>(nd.lo0, nd.hi0, x), slab_d2<T, D>(nd.n0, nd.o0, nd.t0, x));
         const T d1 = fmax(box_d2<T, D>(nd.lo1, nd.hi1, x), slab_d2<T, D>(nd.n1, nd.o1, nd.t1, x));
-        bool h0 = d0 <= best * slack, h1 = d1 <= best * slack;
-        if (h0 && nd.c0 < 0 && h1 && nd.c1 < 0) {
-            if (d0 <= d1) { test_leaf(nd.c0); if (d1 <= best * slack) test_leaf(nd.c1); }
-            else { test_leaf(nd.c1); if (d0 <= best * slack) test_leaf(nd.c0); }
-            h0 = h1 = false;
-        } else if (h0 && nd.c0 < 0) {
-            test_leaf(nd.c0); h0 = false; h1 = h1 && d1 <= best * slack;
-        } else if (h1 && nd.c1 < 0) {
-            test_leaf(nd.c1); h1 = false; h0 = h0 && d0 <= best * slack;
-        }
+        const T lim = q.best * slack;
+        const bool h0 = d0 <= lim, h1 = d1 <= lim;
+        const bool near0 = d0 <= d1;
         int32_t next = -1;
         if (h0 && h1) {
-            const bool near0 = d0 <= d1;
-            if (sp < kStackSize) { st.put(sp, near0 ? nd.c1 : nd.c0, near0 ? d1 : d0); ++sp; }
+            if (q.sp < kStackSize) { st.put(q.sp, near0 ? nd.c1 : nd.c0, near0 ? d1 : d0); ++q.sp; }
             else qc.overflow++;
             next = near0 ? nd.c0 : nd.c1;
         } else if (h0) {
@@ -433,76 +452,30 @@ __device__ __forceinline__ int32_t closest_leaf(const Scene<T>& s, const StageVi
         } else if (h1) {
             next = nd.c1;
         }
-        if (next < 0) {
-            while (sp > 0) {
-                --sp;
-                if (st.get_d(sp) <= best * slack) { next = st.get_node(sp); break; }
-            }
-            if (next < 0) break;
-        }
-        node = next;
+        q.node = -1;
+        if (next >= 0) q.node = next;
+        else if (h0 || h1) { q.leaf = next; q.has_leaf = true; }   // -1 is the leaf {0}
     }
-#else
-    int32_t node = root;         // internal node to expand next, or -1
-    int32_t leaf = 0;            // held leaf reference
-    bool has_leaf = false;
-    bool done = false;
-#pragma unroll 1
-    while (true) {
-#if DWOS_TRAV == 2
-        // phase 1: expand nodes until this lane holds a leaf or is finished
-#pragma unroll 1
-        while (!has_leaf && !done) {
-#else
-        if (has_leaf) {
-            test_leaf(leaf);
-            has_leaf = false;
-            continue;
-        }
-        if (done) break;
-        {
-#endif
-            int32_t cur = node;
-            if (cur < 0) {
-                if (sp == 0) { done = true; continue; }
-                --sp;
-                if (st.get_d(sp) > best * slack) continue;
-                cur = st.get_node(sp);
-                if (cur < 0) { leaf = cur; has_leaf = true; continue; }   // a postponed leaf
-            }
-            NodeData<T, D> nd;
-            scene_node<T, D>(s, sv, cur, nd);
-            qc.nodes++;
-            const T d0 = fmax(box_d2<T, D>(nd.lo0, nd.hi0, x), slab_d2<T, D>(nd.n0, nd.o0, nd.t0, x));
-            const T d1 = fmax(box_d2<T, D>(nd.lo1, nd.hi1, x), slab_d2<T, D>(nd.n1, nd.o1, nd.t1, x));
-            const T lim = best * slack;
-            const bool h0 = d0 <= lim, h1 = d1 <= lim;
-            const bool near0 = d0 <= d1;
-            int32_t next = -1;
-            if (h0 && h1) {
-                if (sp < kStackSize) { st.put(sp, near0 ? nd.c1 : nd.c0, near0 ? d1 : d0); ++sp; }
-                else qc.overflow++;
-                next = near0 ? nd.c0 : nd.c1;
-            } else if (h0) {
-                next = nd.c0;
-            } else if (h1) {
-                next = nd.c1;
-            }
-            node = -1;
-            if (next >= 0) node = next;
-            else if (h0 || h1) { leaf = next; has_leaf = true; }   // -1 is the leaf {0}
-        }
-#if DWOS_TRAV == 2
-        // phase 2: every lane holding a leaf tests it
-        if (has_leaf) {
-            test_leaf(leaf);
-            has_leaf = false;
-        }
-        if (done) break;
-#endif
+    // phase 2: every lane holding a leaf tests it
+    if (active && q.has_leaf) {
+        const int32_t v = -1 - q.leaf;
+        const int32_t start = v >> 3, n = (v & 7) + 1;
+        for (int32_t i = start; i < start + n; ++i) query_test_prim<T, D>(s, sv, x, i, q, qc);
+        q.has_leaf = false;
     }
-#endif
-    return bleaf;
+}
+
+// A whole query (every lane runs its own to completion).
+template <class T, int D, class Stack>
+__device__ __forceinline__ int32_t closest_leaf(const Scene<T>& s, const StageView& sv, int32_t root,
+                                                const T* x, int32_t warm, T& best, QueryCount& qc,
+                                                Stack& st) {
+    Query<T> q;
+    query_begin<T, D>(s, sv, root, x, warm, q);
+#pragma unroll 1
+    while (!q.done) query_round<T, D>(s, sv, x, true, q, qc, st);
+    best = q.best;
+    return q.bleaf;
 }
 
 // ---------------------------------------------------------------------------
@@ -637,6 +610,9 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
     int32_t root = 0, warm = -1, term_leaf = -1, term_code = -1, phase = 0;
     T term_b1 = T(0), term_b2 = T(0);
     int64_t wsteps = 0;
+    // closest-point query in progress (resumable across iterations)
+    Query<T> q;
+    bool qpend = false;
     // control-variate trace of the current nested walk
     T cv_S = T(0);
     T ysel[D], rho_sel = T(0), d_sel = T(0);
@@ -703,16 +679,43 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
         if (done) continue;
 
         // ---- one walk step: closest-point query -----------------------------
-        T d2;
-        int32_t leaf;
-        if (a.first_leaf && phase == 0 && k == 0) {
-            leaf = a.first_leaf[first_row];
-            d2 = a.first_d2[first_row];
-        } else {
+        // A lane without a query in progress starts one at x.  The wavefront
+        // then traverses until at least kParkLanes of its lanes have their
+        // answer (or none is still searching); lanes whose query is
+        // unfinished skip the rest of this iteration and resume it in the
+        // next, so that fast queries do not wait for the slowest one.
+        bool ready = false;
+        T d2 = T(0);
+        int32_t leaf = -1;
+        if (!qpend) {
+            if (a.first_leaf && phase == 0 && k == 0) {
+                leaf = a.first_leaf[first_row];
+                d2 = a.first_d2[first_row];
+                ready = true;
+            } else {
+                query_begin<T, D>(a.s, sv, root, x, warm, q);
+                qpend = true;
+            }
+        }
+        {
             QueryCount qc{0, 0, 0};
-            leaf = closest_leaf<T, D>(a.s, sv, root, x, warm, d2, qc, stack);
+#pragma unroll 1
+            while (true) {
+                const bool searching = qpend && !q.done;
+                const unsigned long long sm = __ballot(searching);
+                const unsigned long long rm = __ballot(ready || (qpend && q.done));
+                if (sm == 0ull || __popcll(rm) >= kParkLanes) break;
+                query_round<T, D>(a.s, sv, x, searching, q, qc, stack);
+            }
             c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;
         }
+        if (qpend && q.done) {
+            leaf = q.bleaf;
+            d2 = q.best;
+            qpend = false;
+            ready = true;
+        }
+        if (!ready) continue;
         c_steps++;
         wsteps++;
         if (leaf < 0 || !(d2 >= T(0))) {
