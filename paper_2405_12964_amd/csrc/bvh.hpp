@@ -22,7 +22,7 @@
 namespace dwos {
 
 #ifndef DWOS_LEAF_MAX
-#define DWOS_LEAF_MAX 4
+#define DWOS_LEAF_MAX 8
 #endif
 #ifndef DWOS_STACK_SIZE
 #define DWOS_STACK_SIZE 48
