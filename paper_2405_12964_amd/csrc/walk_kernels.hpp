@@ -27,7 +27,7 @@ namespace dwos {
 // A wavefront stops traversing once this many of its lanes have their query
 // answered; they take their walk step while the others resume later.
 #ifndef DWOS_PARK
-#define DWOS_PARK 32
+#define DWOS_PARK 24
 #endif
 constexpr int kParkLanes = DWOS_PARK;
 
@@ -165,13 +165,21 @@ __device__ __forceinline__ T box_d2(const T* lo, const T* hi, const T* x) {
 // regions using the dot products of the query offset with the two edges
 // (the classical region test, e.g. Ericson, Real-Time Collision Detection
 // Sec. 5.1.5).
+// a / b in the walk precision: FP32 uses the hardware reciprocal (1 ulp),
+// FP64 (the walk-for-walk reference build) the correctly rounded division
+template <class T>
+__device__ __forceinline__ T quot(T a, T b) {
+    if constexpr (sizeof(T) == 4) return a * __builtin_amdgcn_rcpf(b);
+    else return a / b;
+}
+
 template <class T, int D>
 __device__ __forceinline__ T prim_closest(const T* P, const T* x, T* bary) {
     if constexpr (D == 2) {
         const T ex = P[2] - P[0], ey = P[3] - P[1];
         const T ax = x[0] - P[0], ay = x[1] - P[1];
         const T L2 = ex * ex + ey * ey;
-        T t = L2 > T(0) ? (ax * ex + ay * ey) / L2 : T(0);
+        T t = L2 > T(0) ? quot<T>(ax * ex + ay * ey, L2) : T(0);
         t = fmin(fmax(t, T(0)), T(1));
         const T dx = ax - t * ex, dy = ay - t * ey;
         bary[0] = T(1) - t; bary[1] = t; bary[2] = T(0);
@@ -191,7 +199,7 @@ __device__ __forceinline__ T prim_closest(const T* P, const T* x, T* bary) {
             if (d3 >= T(0) && d4 <= d3) { v = T(1); w = T(0); }
             else {
                 const T vc = d1 * d4 - d3 * d2;
-                if (vc <= T(0) && d1 >= T(0) && d3 <= T(0)) { v = d1 / (d1 - d3); w = T(0); }
+                if (vc <= T(0) && d1 >= T(0) && d3 <= T(0)) { v = quot<T>(d1, d1 - d3); w = T(0); }
                 else {
                     const T cp[3] = {x[0] - P[6], x[1] - P[7], x[2] - P[8]};
                     const T d5 = ab[0] * cp[0] + ab[1] * cp[1] + ab[2] * cp[2];
@@ -199,14 +207,14 @@ __device__ __forceinline__ T prim_closest(const T* P, const T* x, T* bary) {
                     if (d6 >= T(0) && d5 <= d6) { v = T(0); w = T(1); }
                     else {
                         const T vb = d5 * d2 - d1 * d6;
-                        if (vb <= T(0) && d2 >= T(0) && d6 <= T(0)) { v = T(0); w = d2 / (d2 - d6); }
+                        if (vb <= T(0) && d2 >= T(0) && d6 <= T(0)) { v = T(0); w = quot<T>(d2, d2 - d6); }
                         else {
                             const T va = d3 * d6 - d5 * d4;
                             if (va <= T(0) && (d4 - d3) >= T(0) && (d5 - d6) >= T(0)) {
-                                w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+                                w = quot<T>(d4 - d3, (d4 - d3) + (d5 - d6));
                                 v = T(1) - w;
                             } else {
-                                const T den = T(1) / (va + vb + vc);
+                                const T den = quot<T>(T(1), va + vb + vc);
                                 v = vb * den;
                                 w = vc * den;
                             }
