@@ -216,12 +216,74 @@ def run_c5(args):
     }
 
 
+def run_c4(args):
+    """Many instances of uneven size in one persistent launch: 256 displaced
+    icospheres in boxes (980 - 100,820 triangles, log-uniform), 512 - 16384
+    points each (log-uniform), screening sigma_i ~ U(0, 20), W walks per
+    point; against the same work as one launch per instance (one context
+    each)."""
+    import numpy as np
+    import torch
+    import scenes
+    import paper_2405_12964_amd as dw
+
+    dev = torch.device("cuda:0")
+    W = args.walks or 64
+    insts = scenes.c4_batch()
+    s = dw.Solver(3, "fp32")
+    sc0 = insts[0][0]
+    s.set_problem(dw.make_problem(0.0, sc0.eps, sc0.delta, 1, sc0.kmax, 1, 0.0, None, sc0.bc, 3))
+    for sc, _ in insts:
+        s.batch_add_instance(sc.V, sc.prims, sc.label, sc.sigma, sc.eps, sc.delta)
+    X = torch.tensor(np.concatenate([x for _, x in insts]), dtype=torch.float64, device=dev)
+    P = [len(x) for _, x in insts]
+    s.batch_solve(X, P, W, 1)
+    torch.cuda.synchronize()
+    s.walk_timing(0, reset=True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        s.batch_solve(X, P, W, 10 + i, var=False)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms, n, tot = s.walk_timing(0)
+    # the same work, one context and one launch per instance
+    solvers = []
+    for (sc, x) in insts:
+        si = dw.Solver(3, "fp32")
+        si.set_boundary(sc.V, sc.prims, sc.label, sc.gvert)
+        si.set_problem(dw.make_problem(sc.sigma, sc.eps, sc.delta, 1, sc.kmax, 1, 0.0, None, sc.bc, 3))
+        solvers.append((si, torch.tensor(x, dtype=torch.float64, device=dev)))
+    for si, xi in solvers:
+        si.solve(xi, W, 1, var=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i in range(args.steps):
+        for si, xi in solvers:
+            si.solve(xi, W, 10 + i, var=False)
+    torch.cuda.synchronize()
+    elapsed_seq = time.perf_counter() - t1
+    steps_total = tot["steps"]
+    return {
+        "metric": METRIC, "value": steps_total / elapsed, "unit": "walk-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"256 instances (C3 generator, 980-100,820 triangles, 512-16384 points, "
+                               f"sigma ~ U(0,20)) in one persistent launch, W = {W}",
+                   "instances": len(insts), "triangles": int(sum(sc.prims.shape[0] for sc, _ in insts)),
+                   "points": int(sum(P)), "walks_per_point": W},
+        "walk_kernel_ms": ms / max(1, n),
+        "per_instance_launches": {"ms_per_step": 1e3 * elapsed_seq / args.steps,
+                                  "speedup_of_one_launch": elapsed_seq / elapsed},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", choices=["c2", "c5"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c4", "c5"], default="c2",
                     help="c2: 2D star (the reported configuration); c5: 3D shape from diffusion "
                          "with the learned control variate")
     ap.add_argument("--points", type=int, default=0)
@@ -242,6 +304,10 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
+    if args.workload == "c4":
+        args.steps = 3 if args.steps is None else args.steps
+        print(json.dumps(run_c4(args)), flush=True)
+        return
     if args.workload == "c5":
         args.steps = 50 if args.steps is None else args.steps
         args.warmup = 150 if args.warmup is None else args.warmup
