@@ -384,14 +384,20 @@ template <class T> struct TravStack<T, true> {
 // every lane holds a leaf or has finished, then test the held leaves
 // together, so that node and primitive work are not interleaved within one
 // iteration.
+// The traversal stack's most recent entry is kept in registers (tnode,
+// tdist); a push moves the previous one to the stack memory only when it is
+// still there, and a pop reads memory only when it is not.  Depth-first
+// descent alternates pushes and pops, so most entries never reach memory.
 template <class T>
 struct Query {
     T best;          // squared distance of the best primitive so far
+    T tdist;         // register-held top entry: squared bound distance
     int32_t bleaf;   // its leaf position, -1 none
     int32_t node;    // internal node to expand next, or -1 (pop)
     int32_t leaf;    // held leaf reference
-    int32_t sp;      // stack depth
-    bool has_leaf, done;
+    int32_t sp;      // entries in stack memory
+    int32_t tnode;   // register-held top entry: node reference
+    bool has_leaf, done, top;
 };
 
 template <class T, int D>
@@ -424,6 +430,7 @@ __device__ __forceinline__ void query_begin(const Scene<T>& s, const StageView& 
     q.sp = 0;
     q.has_leaf = false;
     q.done = false;
+    q.top = false;
 }
 
 // One round for the lanes with `active` set (a query in progress).
@@ -436,10 +443,18 @@ __device__ __forceinline__ void query_round(const Scene<T>& s, const StageView& 
     while (active && !q.has_leaf && !q.done) {
         int32_t cur = q.node;
         if (cur < 0) {
-            if (q.sp == 0) { q.done = true; continue; }
-            --q.sp;
-            if (st.get_d(q.sp) > q.best * slack) continue;
-            cur = st.get_node(q.sp);
+            T dd;
+            if (q.top) {
+                cur = q.tnode;
+                dd = q.tdist;
+                q.top = false;
+            } else {
+                if (q.sp == 0) { q.done = true; continue; }
+                --q.sp;
+                cur = st.get_node(q.sp);
+                dd = st.get_d(q.sp);
+            }
+            if (dd > q.best * slack) continue;
             if (cur < 0) { q.leaf = cur; q.has_leaf = true; continue; }   // a postponed leaf
         }
         NodeData<T, D> nd;
@@ -452,8 +467,14 @@ __device__ __forceinline__ void query_round(const Scene<T>& s, const StageView& 
         const bool near0 = d0 <= d1;
         int32_t next = -1;
         if (h0 && h1) {
-            if (q.sp < kStackSize) { st.put(q.sp, near0 ? nd.c1 : nd.c0, near0 ? d1 : d0); ++q.sp; }
-            else qc.overflow++;
+            if (q.sp + (q.top ? 1 : 0) < kStackSize) {
+                if (q.top) { st.put(q.sp, q.tnode, q.tdist); ++q.sp; }
+                q.tnode = near0 ? nd.c1 : nd.c0;
+                q.tdist = near0 ? d1 : d0;
+                q.top = true;
+            } else {
+                qc.overflow++;
+            }
             next = near0 ? nd.c0 : nd.c1;
         } else if (h0) {
             next = nd.c0;
