@@ -115,7 +115,8 @@ double u24pos(uint32_t w) { return (double)((w >> 8) + 1u) * 0x1p-24; }
 
 // Identity of one walk's random stream: key = seed; counter =
 // (step k, walk m, point p, purpose | nested index << 8 | instance << 16).
-// purpose bit 1: nested walk; bit 2: second draw of a step (source sample).
+// purpose bit 1: nested walk; bit 2: second draw of a step (3D source-point
+// direction; 2D takes it from the first draw's second word).
 struct Stream {
     uint32_t key[2];
     uint32_t m, p, tag;
@@ -682,8 +683,10 @@ double walk_on_spheres(const Scene& sc, const double* x0, const Stream& st, uint
             }
         }
         if (sc.has_source()) {                          // source contribution
-            uint32_t wb[4];
-            st.draw(k, extra | 2u, wb);
+            // ball-point direction: in 2D the step's second word (the step
+            // direction uses only the first), in 3D a second draw
+            uint32_t wb[4] = {w[1], 0, 0, 0};
+            if (D == 3) st.draw(k, extra | 2u, wb);
             double dir[3];
             sphere_dir(D, wb[0], wb[1], dir);
             double rad = d * std::pow(u24pos(w[3]), 1.0 / D);   // uniform in the ball
@@ -839,8 +842,8 @@ DiffOut diff_walk_on_spheres(const Scene& sc, const double* x0, const Stream& st
         uint32_t w[4];
         st.draw(k, 0u, w);
         if (sc.has_source()) {   // sources only enter the joint u estimate
-            uint32_t wb[4];
-            st.draw(k, 2u, wb);
+            uint32_t wb[4] = {w[1], 0, 0, 0};
+            if (D == 3) st.draw(k, 2u, wb);
             double dir[3];
             sphere_dir(D, wb[0], wb[1], dir);
             double rad = d * std::pow(u24pos(w[3]), 1.0 / D);

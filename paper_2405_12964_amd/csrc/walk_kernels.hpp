@@ -877,9 +877,15 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
                 }
             }
             if (a.prm.has_source) {
-                const u4 r2 = philox10(u4{k, m, p, tag | 2u}, key0, key1);
+                // ball-point direction: 2D uses the step draw's second word
+                // (the step direction needs only the first), 3D a second draw
                 T dir[3];
-                unit_dir<T, D>(r2.x, r2.y, dir);
+                if constexpr (D == 2) {
+                    unit_dir<T, D>(r.y, 0u, dir);
+                } else {
+                    const u4 r2 = philox10(u4{k, m, p, tag | 2u}, key0, key1);
+                    unit_dir<T, D>(r2.x, r2.y, dir);
+                }
                 T rho;
                 if constexpr (D == 2) rho = sqrt(unif_pos<T>(r.w));
                 else rho = cbrt(unif_pos<T>(r.w));
