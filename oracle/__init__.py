@@ -54,6 +54,10 @@ def lib():
         L.oracle_green_mass.argtypes = [C.c_int, C.c_double, C.c_double]
         L.oracle_green_mass.restype = C.c_double
         L.oracle_closest.argtypes = [sp, dp, dp]
+        L.oracle_neumann_weight.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double]
+        L.oracle_neumann_weight.restype = C.c_double
+        L.oracle_silhouette.argtypes = [sp, dp, C.c_int32, dp, C.c_double, dp]
+        L.oracle_ray.argtypes = [sp, dp, dp, C.c_double, C.c_int32, dp]
         L.oracle_walk_records.argtypes = [sp, dp, C.c_int64, C.c_int32, C.c_uint64, C.c_int32,
                                           C.c_int32, dp, dp, lp, ip, dp, lp, dp, C.c_int]
         L.oracle_solve.argtypes = [sp, dp, C.c_int64, C.c_int32, C.c_uint64, C.c_int32, dp, dp,
@@ -89,6 +93,8 @@ class OracleScene(C.Structure):
         ("bc_quad", C.POINTER(C.c_double)), ("gvert", C.POINTER(C.c_double)),
         ("N", C.c_int32), ("rowptr", C.POINTER(C.c_int64)), ("pid", C.POINTER(C.c_int32)),
         ("vel", C.POINTER(C.c_double)), ("bc_pid", C.POINTER(C.c_int32)),
+        ("n_nv", C.c_int32), ("NV", C.POINTER(C.c_double)), ("n_ns", C.c_int32),
+        ("nsegs", C.POINTER(C.c_int32)), ("start_seg", C.POINTER(C.c_int32)),
     ]
 
 
@@ -156,7 +162,24 @@ class Oracle:
         s.pid = _ptr(self._pid, C.c_int32)
         s.vel = _ptr(self._vel, C.c_double)
         s.bc_pid = _ptr(self._bcpid, C.c_int32)
+        if getattr(scene, "nsegs", None) is not None and len(scene.nsegs) > 0:
+            self._NV = np.ascontiguousarray(scene.NV, dtype=np.float64)
+            self._nsegs = np.ascontiguousarray(scene.nsegs, dtype=np.int32)
+            s.n_nv = self._NV.shape[0]
+            s.NV = _ptr(self._NV, C.c_double)
+            s.n_ns = self._nsegs.shape[0]
+            s.nsegs = _ptr(self._nsegs, C.c_int32)
+        self._start = None
         self._s = s
+
+    def _starts(self, start_seg, P):
+        """Per-point start segments (None: every point inside the domain)."""
+        if start_seg is None:
+            self._start = None
+        else:
+            self._start = np.ascontiguousarray(start_seg, dtype=np.int32)
+            assert self._start.shape == (P,)
+        self._s.start_seg = _ptr(self._start, C.c_int32)
 
     @staticmethod
     def _X(X):
@@ -169,9 +192,10 @@ class Oracle:
         assert rc == 0
         return dict(d=out[0], prim=int(out[1]), bary=out[2:5].copy(), xbar=out[5:8].copy())
 
-    def walk_records(self, X, W, seed, mode=0, instance=0, want_udot=True):
+    def walk_records(self, X, W, seed, mode=0, instance=0, want_udot=True, start_seg=None):
         X = self._X(X)
         P = X.shape[0]
+        self._starts(start_seg, P)
         N = self.scene.N
         u = np.zeros(P * W)
         udot = np.zeros(P * W * N) if (mode == 1 and want_udot and N > 0) else None
@@ -192,9 +216,10 @@ class Oracle:
             out["udot"] = udot.reshape(P, W, N)
         return out
 
-    def solve(self, X, W, seed, instance=0):
+    def solve(self, X, W, seed, instance=0, start_seg=None):
         X = self._X(X)
         P = X.shape[0]
+        self._starts(start_seg, P)
         m, v, st = np.zeros(P), np.zeros(P), np.zeros(1, np.int64)
         rc = lib().oracle_solve(C.byref(self._s), _ptr(X, C.c_double), P, W, seed, instance,
                                 _ptr(m, C.c_double), _ptr(v, C.c_double), _ptr(st, C.c_int64),
@@ -202,9 +227,10 @@ class Oracle:
         assert rc == 0
         return m, v, int(st[0])
 
-    def jvp(self, X, W, seed, instance=0, cv=None):
+    def jvp(self, X, W, seed, instance=0, cv=None, start_seg=None):
         X = self._X(X)
         P = X.shape[0]
+        self._starts(start_seg, P)
         N = self.scene.N
         m, v, um, st = np.zeros(P * N), np.zeros(P * N), np.zeros(P), np.zeros(1, np.int64)
         rc = lib().oracle_jvp(C.byref(self._s), _ptr(X, C.c_double), P, W, seed, instance,
@@ -213,9 +239,10 @@ class Oracle:
         assert rc == 0
         return m.reshape(P, N), v.reshape(P, N), um, int(st[0])
 
-    def grad(self, X, w, W, seed, instance=0, cv=None):
+    def grad(self, X, w, W, seed, instance=0, cv=None, start_seg=None):
         X = self._X(X)
         P = X.shape[0]
+        self._starts(start_seg, P)
         w = np.ascontiguousarray(w, dtype=np.float64)
         g, um, st = np.zeros(self.scene.N), np.zeros(P), np.zeros(1, np.int64)
         rc = lib().oracle_grad(C.byref(self._s), _ptr(X, C.c_double), P, _ptr(w, C.c_double), W,
@@ -224,9 +251,10 @@ class Oracle:
         assert rc == 0
         return g, um, int(st[0])
 
-    def grad_sqloss(self, X, uref, W, B, seed, instance=0, cv=None):
+    def grad_sqloss(self, X, uref, W, B, seed, instance=0, cv=None, start_seg=None):
         X = self._X(X)
         P = X.shape[0]
+        self._starts(start_seg, P)
         uref = np.ascontiguousarray(uref, dtype=np.float64)
         g, um, st, L = np.zeros(self.scene.N), np.zeros(P), np.zeros(1, np.int64), np.zeros(1)
         rc = lib().oracle_grad_sqloss(C.byref(self._s), _ptr(X, C.c_double), P,
@@ -238,12 +266,34 @@ class Oracle:
             raise ValueError("oracle_grad_sqloss: invalid arguments")
         return float(L[0]), g, um, int(st[0])
 
+    def silhouette(self, x, on=-1, nin=None, cap=np.inf):
+        """Distance from x to the closest silhouette point of the reflecting
+        boundary (x on segment ``on`` with domain side ``nin``, or inside)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        n = np.ascontiguousarray(np.zeros(2) if nin is None else nin, dtype=np.float64)
+        out = np.zeros(1)
+        rc = lib().oracle_silhouette(C.byref(self._s), _ptr(x, C.c_double), int(on),
+                                     _ptr(n, C.c_double), float(cap), _ptr(out, C.c_double))
+        assert rc == 0
+        return float(out[0])
+
+    def ray(self, x, d, tmax=np.inf, skip=-1):
+        """First reflecting segment hit by x + t d, 0 < t < tmax: (t, seg)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        d = np.ascontiguousarray(d, dtype=np.float64)
+        out = np.zeros(2)
+        rc = lib().oracle_ray(C.byref(self._s), _ptr(x, C.c_double), _ptr(d, C.c_double),
+                              float(tmax), int(skip), _ptr(out, C.c_double))
+        assert rc == 0
+        return float(out[0]), int(out[1])
+
     def walk_records_cv(self, X, W, seed, cv, instance=0):
         """Differential walks with the control variate: per-walk records
         (run, xoff, uoff plain, uoff_cv, target, u, prim) and per nested walk
         (S, alive, xstop, y, rho, d)."""
         X = self._X(X)
         P = X.shape[0]
+        self._starts(None, P)
         K = int(self.scene.K)
         walk = np.zeros(P * W * 9)
         nested = np.zeros(P * W * K * 10)
@@ -351,3 +401,7 @@ def poisson_scale(dim, sigma, R):
 
 def green_mass(dim, sigma, R):
     return lib().oracle_green_mass(dim, sigma, R)
+
+
+def neumann_weight(dim, sigma, r, R):
+    return lib().oracle_neumann_weight(dim, sigma, r, R)

@@ -38,6 +38,10 @@
 //   * Mapped data: udot = gdot_ref - grad_G g . V - V_n du/dn (Appendix A
 //     with tangential components of the velocity kept explicitly).
 //
+//   * Mixed Dirichlet / zero-flux problems (Sec. 3.4, Sec. 4.4): walk on
+//     stars, restated from the walk-on-stars papers the paper cites; see
+//     "Walk on stars" below for the steps and the readings taken.
+//
 // Extension (not in the paper, which lists variance reduction and caches that
 // estimate u without a walk as future work in Sec. 8 and Appendix B): a
 // learned control variate for the nested walks, see "Control variate" below.
@@ -71,6 +75,17 @@ struct oracle_scene {
     const int32_t* pid;      // nnz parameter ids
     const double* vel;       // nnz*dim velocities dv_i/dpi_j
     const int32_t* bc_pid;   // nv parameter id of the mapped value, -1 none (NULL: none)
+    // Reflecting (zero-flux Neumann) part of the boundary, 2D only: segments
+    // over their own vertex array, fixed (independent of the parameters).
+    // n_ns = 0: a Dirichlet-only problem, solved by walk on spheres.
+    int32_t n_nv;
+    const double* NV;        // n_nv*dim
+    int32_t n_ns;
+    const int32_t* nsegs;    // n_ns*2 vertex indices into NV
+    // per query point: the reflecting segment the point lies on, with the
+    // domain to the left of the segment (from its first to its second
+    // vertex), or -1 for an interior point (NULL: all interior)
+    const int32_t* start_seg;
 };
 
 // Learned control variate of the nested walks: network N(x) (frequencies B,
@@ -189,7 +204,14 @@ void tri_closest(const double* x, const double* a, const double* b, const double
 struct Scene {
     const oracle_scene& s;
     int D;
-    explicit Scene(const oracle_scene& sc) : s(sc), D(sc.dim) {}
+    std::vector<std::vector<int>> ninc;   // reflecting segments incident to each vertex
+    explicit Scene(const oracle_scene& sc) : s(sc), D(sc.dim) {
+        if (sc.n_ns > 0) {
+            ninc.assign(sc.n_nv, {});
+            for (int i = 0; i < sc.n_ns; ++i)
+                for (int k = 0; k < 2; ++k) ninc[sc.nsegs[2 * i + k]].push_back(i);
+        }
+    }
     const double* vert(int i) const { return s.V + (size_t)i * D; }
     int pv(int prim, int k) const { return s.prims[(size_t)prim * D + k]; }
     int lab(int prim) const { return s.label ? s.label[prim] : 0; }
@@ -327,6 +349,90 @@ struct Scene {
         return v;
     }
     bool has_source() const { return s.src_c0 != 0.0 || s.n_gauss > 0; }
+
+    // ----- reflecting boundary (walk on stars) ------------------------------
+    bool has_neumann() const { return s.n_ns > 0; }
+    const double* nvert(int i) const { return s.NV + (size_t)i * 2; }
+    int nsv(int seg, int k) const { return s.nsegs[2 * seg + k]; }
+
+    // Unit normal of a reflecting segment pointing to its left (the domain
+    // side of a start segment).
+    void nleft(int seg, double n[2]) const {
+        const double* a = nvert(nsv(seg, 0));
+        const double* b = nvert(nsv(seg, 1));
+        double tx = b[0] - a[0], ty = b[1] - a[1], L = std::sqrt(tx * tx + ty * ty);
+        n[0] = -ty / L; n[1] = tx / L;
+    }
+
+    // Is reflecting vertex v a silhouette point as seen from x?  Seen from x,
+    // the boundary turns back at v when both edges at v leave it on the same
+    // side of the line through x and v.  A vertex with one edge (an open end)
+    // or more than two is always counted.  An edge seen edge-on (x on its
+    // line) does not decide: if x lies on the reflecting boundary (segment
+    // `on`, domain side `nin`), v is a silhouette when its other edge leaves
+    // to the outside of that line; the edges at v that are the segment x lies
+    // on are edge-on by construction.  Off the boundary an edge-on view counts
+    // as a silhouette (a conservative choice for a null set of points).
+    bool silhouette(int v, const double* x, int on, const double* nin) const {
+        const std::vector<int>& e = ninc[v];
+        if (e.size() != 2) return true;
+        const double* pv = nvert(v);
+        int nb[2];
+        for (int k = 0; k < 2; ++k) nb[k] = nsv(e[k], 0) == v ? nsv(e[k], 1) : nsv(e[k], 0);
+        auto outside = [&](int w) {
+            const double* pw = nvert(w);
+            return nin[0] * (pw[0] - pv[0]) + nin[1] * (pw[1] - pv[1]) < 0;
+        };
+        if (on >= 0 && e[0] == on) return outside(nb[1]);
+        if (on >= 0 && e[1] == on) return outside(nb[0]);
+        const double vx = pv[0] - x[0], vy = pv[1] - x[1];
+        const double lv = std::sqrt(vx * vx + vy * vy);
+        double c[2];
+        bool zero[2];
+        for (int k = 0; k < 2; ++k) {
+            const double* pw = nvert(nb[k]);
+            const double ex = pw[0] - pv[0], ey = pw[1] - pv[1];
+            c[k] = vx * ey - vy * ex;
+            zero[k] = std::fabs(c[k]) <= 1e-10 * lv * std::sqrt(ex * ex + ey * ey);
+        }
+        if (zero[0] && zero[1]) return false;
+        if (zero[0] || zero[1]) return on >= 0 ? outside(zero[0] ? nb[1] : nb[0]) : true;
+        return (c[0] > 0) == (c[1] > 0);
+    }
+
+    // Squared distance from x to its closest silhouette point, capped at cap2.
+    double silhouette_d2(const double* x, int on, const double* nin, double cap2) const {
+        double best = cap2;
+        for (int v = 0; v < s.n_nv; ++v) {
+            if (ninc[v].empty()) continue;
+            const double* p = nvert(v);
+            double d2 = (p[0] - x[0]) * (p[0] - x[0]) + (p[1] - x[1]) * (p[1] - x[1]);
+            if (d2 < best && silhouette(v, x, on, nin)) best = d2;
+        }
+        return best;
+    }
+
+    // First intersection of the ray x + t dir, 0 < t < tmax, with a
+    // reflecting segment other than `skip`.  Returns the segment (lowest
+    // index on a tie) or -1, and its t.
+    int ray(const double* x, const double* dir, double tmax, int skip, double& t_out) const {
+        int hit = -1;
+        double best = tmax;
+        for (int i = 0; i < s.n_ns; ++i) {
+            if (i == skip) continue;
+            const double* a = nvert(nsv(i, 0));
+            const double* b = nvert(nsv(i, 1));
+            const double ex = b[0] - a[0], ey = b[1] - a[1];
+            const double den = dir[0] * ey - dir[1] * ex;        // cross(dir, e)
+            if (den == 0.0) continue;                            // parallel
+            const double ax = a[0] - x[0], ay = a[1] - x[1];
+            const double t = (ax * ey - ay * ex) / den;          // cross(a - x, e) / den
+            const double u = (ax * dir[1] - ay * dir[0]) / den;  // cross(a - x, dir) / den
+            if (t > 0 && t < best && u >= 0 && u <= 1) { best = t; hit = i; }
+        }
+        t_out = hit >= 0 ? best : tmax;
+        return hit;
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -393,6 +499,30 @@ void sphere_dir(int D, uint32_t w0, uint32_t w1, double s[3]) {
     }
 }
 
+// Walk on stars (reflecting boundary): weight of a step that ends on the
+// reflecting boundary at distance r < R inside the ball of radius R.  The
+// boundary integral over the star-shaped region carries the Poisson kernel
+// -dG/dn_z of the ball at the boundary point z; the density of z under
+// uniform direction sampling is |n_z.(z - x)| / (|dS_1| r^D), so the ratio is
+//   |dS_1| r^(D-1) |dG/dr|(r; R)
+// with |dS_1| = 2 pi (2D) or 4 pi (3D) and G from green():
+//   2D: kr [K1(kr) + K0(kR) I1(kr) / I0(kR)]
+//   3D: [kr cosh(k(R - r)) + sinh(k(R - r))] / sinh(kR)
+// It equals poisson_scale at r = R, tends to 1 as r -> 0, and is 1 for
+// sigma = 0.  A walk at a reflecting boundary point samples the half of the
+// directions that enter the domain, with twice the density, and the boundary
+// integral equation there carries a factor 1/2 on the left (the solid-angle
+// fraction of a smooth boundary point), so the weights are unchanged.
+double neumann_weight(int D, double sigma, double r, double R) {
+    if (sigma == 0.0) return 1.0;
+    const double k = std::sqrt(sigma);
+    if (D == 2) {
+        const double a = k * r, b = k * R;
+        return a * (std::cyl_bessel_k(1.0, a) +
+                    std::cyl_bessel_k(0.0, b) * std::cyl_bessel_i(1.0, a) / std::cyl_bessel_i(0.0, b));
+    }
+    return (k * r * std::cosh(k * (R - r)) + std::sinh(k * (R - r))) / std::sinh(k * R);
+}
 
 // ---------------------------------------------------------------------------
 // The control-variate network (an extension; see the file header).
@@ -703,6 +833,89 @@ double walk_on_spheres(const Scene& sc, const double* x0, const Stream& st, uint
     }
 }
 
+// ---------------------------------------------------------------------------
+// Walk on stars for the mixed problem of Sec. 3.4 (eq. (mixed_bvp)) with a
+// zero-flux reflecting boundary (Robin coefficient 0, Robin data 0), the
+// case of the paper's thermal design example.  The paper defers the
+// estimator to the walk-on-stars papers (Sawhney et al. 2023; Miller et al.
+// 2024); one step, restated:
+//   * d = distance to the Dirichlet boundary; in its eps-shell the walk
+//     stops with g as in Algorithm 1.
+//   * star radius R = min(d, distance to the closest silhouette point of the
+//     reflecting boundary): the part of the ball visible from x is then a
+//     star-shaped region bounded by the sphere and the reflecting boundary.
+//   * direction v uniform on the circle (at a reflecting boundary point: on
+//     the half that enters the domain, by reflecting the other half).
+//   * march along v: the first reflecting boundary point at distance t < R
+//     becomes the next point with weight neumann_weight(t, R), else x + R v
+//     with weight alpha(R) as in Algorithm 1; Russian roulette on the weight.
+//   * source: one point y = x + rho v of the ball along the same direction,
+//     rho = R U^(1/D), contributing |B_R| G(rho; R) f(y) if it lies in the
+//     star-shaped region (rho < t).
+// One random draw per step: w0 (and w1 in 3D) the direction, w2 the
+// roulette, w3 the source radius.
+// ---------------------------------------------------------------------------
+struct StarStep {
+    bool stop = false;     // stopped by roulette
+    int on = -1;           // reflecting segment of the new point, -1 none
+};
+
+StarStep star_step(const Scene& sc, double* x, int on, double* nin, double d2, uint32_t k,
+                   const Stream& st, uint32_t extra, double& acc) {
+    const int D = sc.D;
+    const double R = std::sqrt(sc.silhouette_d2(x, on, nin, d2));
+    uint32_t w[4];
+    st.draw(k, extra, w);
+    double v[3];
+    sphere_dir(D, w[0], w[1], v);
+    if (on >= 0) {
+        const double c = dot(v, nin, D);
+        if (c < 0) for (int i = 0; i < D; ++i) v[i] -= 2 * c * nin[i];
+    }
+    double t;
+    const int seg = sc.ray(x, v, R, on, t);
+    if (sc.has_source()) {
+        const double rho = R * std::pow(u24pos(w[3]), 1.0 / D);
+        if (seg < 0 || rho < t) {
+            double y[3] = {0, 0, 0};
+            for (int i = 0; i < D; ++i) y[i] = x[i] + rho * v[i];
+            acc += green(D, sc.s.sigma, rho, R) * ball_volume(D, R) * sc.f(y);
+        }
+    }
+    const double wgt = seg >= 0 ? neumann_weight(D, sc.s.sigma, t, R) : poisson_scale(D, sc.s.sigma, R);
+    StarStep out;
+    if (sc.s.rr && wgt < u24(w[2])) { out.stop = true; return out; }
+    for (int i = 0; i < D; ++i) x[i] += t * v[i];
+    out.on = seg;
+    if (seg >= 0) {   // domain side of the segment: the side the walk came from
+        sc.nleft(seg, nin);
+        if (dot(nin, v, D) > 0) for (int i = 0; i < D; ++i) nin[i] = -nin[i];
+    }
+    return out;
+}
+
+double walk_on_stars(const Scene& sc, const double* x0, int on0, const double* nin0,
+                     const Stream& st, uint32_t extra, WalkCount& cnt) {
+    const int D = sc.D;
+    double x[3] = {0, 0, 0}, nin[3] = {0, 0, 0};
+    for (int i = 0; i < D; ++i) { x[i] = x0[i]; if (on0 >= 0) nin[i] = nin0[i]; }
+    int on = on0;
+    double acc = 0.0;
+    for (uint32_t k = 0;; ++k) {
+        Hit h = sc.closest(x);                          // Dirichlet boundary only
+        cnt.steps++;
+        const double d = std::sqrt(h.d2);
+        const bool cap = (int64_t)k + 1 >= sc.s.kmax;
+        if (d < sc.s.eps || cap) {
+            if (cap && !(d < sc.s.eps)) cnt.truncated++;
+            return acc + sc.g(h);
+        }
+        StarStep r = star_step(sc, x, on, nin, h.d2, k, st, extra, acc);
+        if (r.stop) return acc;
+        on = r.on;
+    }
+}
+
 struct DiffOut {
     double u = 0;          // joint estimate of u (sources + g at the terminal)
     bool terminal = false; // reached the shell (false: stopped by roulette)
@@ -748,14 +961,19 @@ void cv_combine(const Scene& sc, const oracle_cv& cv, DiffOut& o) {
 // estimate of u.  At the shell it launches K forward walks from the offset
 // point xbar - delta n and forms the differential boundary value.
 // ---------------------------------------------------------------------------
+// With a reflecting boundary the walk takes walk-on-stars steps (Sec. 4.4:
+// the differential walk on stars nests through the Dirichlet boundary
+// only), starting on reflecting segment on0 (domain side nin0) or inside.
 DiffOut diff_walk_on_spheres(const Scene& sc, const double* x0, const Stream& st,
-                             WalkCount& cnt, bool want_udot, const oracle_cv* cv = nullptr) {
+                             WalkCount& cnt, bool want_udot, const oracle_cv* cv = nullptr,
+                             int on0 = -1, const double* nin0 = nullptr) {
     const int D = sc.D;
     const int N = sc.s.N;
     DiffOut out;
     if (want_udot) out.udot.assign(N, 0.0);
-    double x[3] = {0, 0, 0};
-    for (int i = 0; i < D; ++i) x[i] = x0[i];
+    double x[3] = {0, 0, 0}, nin[3] = {0, 0, 0};
+    for (int i = 0; i < D; ++i) { x[i] = x0[i]; if (on0 >= 0) nin[i] = nin0[i]; }
+    int on = on0;
     double acc = 0.0;
     for (uint32_t k = 0;; ++k) {
         Hit h = sc.closest(x);
@@ -783,8 +1001,10 @@ DiffOut diff_walk_on_spheres(const Scene& sc, const double* x0, const Stream& st
             if (cv) out.traces.assign(out.run == 1 ? sc.s.K : 0, CvTrace());
             for (int i = 0; out.run == 1 && i < sc.s.K; ++i) {  // nested forward walks
                 WalkCount c2;
-                usum += walk_on_spheres(sc, xoff, st, 1u | ((uint32_t)i << 8), c2,
-                                        cv ? &out.traces[i] : nullptr);
+                const uint32_t tag = 1u | ((uint32_t)i << 8);
+                usum += sc.has_neumann()
+                            ? walk_on_stars(sc, xoff, -1, nullptr, st, tag, c2)
+                            : walk_on_spheres(sc, xoff, st, tag, c2, cv ? &out.traces[i] : nullptr);
                 out.nested_steps += c2.steps;
                 cnt.truncated += c2.truncated;
             }
@@ -839,6 +1059,12 @@ DiffOut diff_walk_on_spheres(const Scene& sc, const double* x0, const Stream& st
             }
             return out;
         }
+        if (sc.has_neumann()) {
+            StarStep r = star_step(sc, x, on, nin, h.d2, k, st, 0u, acc);
+            if (r.stop) { out.u = acc; return out; }   // roulette: udot = 0, u = sources
+            on = r.on;
+            continue;
+        }
         uint32_t w[4];
         st.draw(k, 0u, w);
         if (sc.has_source()) {   // sources only enter the joint u estimate
@@ -882,7 +1108,52 @@ void parallel_points(int64_t P, int threads, F&& fn) {
 int check_scene(const oracle_scene* s) {
     if (!s || (s->dim != 2 && s->dim != 3) || s->nv <= 0 || s->np <= 0) return 1;
     if (!(s->eps > 0) || s->sigma < 0 || s->K < 1 || s->kmax < 1) return 1;
+    // without roulette the walks would have to carry the product of the
+    // alpha factors; only sigma = 0 (alpha = 1) is accepted then
+    if (!s->rr && s->sigma > 0) return 1;
+    if (s->n_ns < 0) return 1;
+    if (s->n_ns > 0) {
+        if (s->dim != 2 || !s->NV || !s->nsegs || s->n_nv <= 0) return 1;
+        for (int64_t i = 0; i < 2 * (int64_t)s->n_ns; ++i)
+            if (s->nsegs[i] < 0 || s->nsegs[i] >= s->n_nv) return 1;
+    }
     return 0;
+}
+
+// start segments of P query points must name reflecting segments (or -1)
+int check_starts(const oracle_scene* s, int64_t P) {
+    if (!s->start_seg) return 0;
+    for (int64_t p = 0; p < P; ++p)
+        if (s->start_seg[p] < -1 || s->start_seg[p] >= s->n_ns) return 1;
+    return 0;
+}
+
+// Where the walks of query point p start: on a reflecting segment (the
+// domain to its left) or inside the domain.
+struct Start {
+    int on = -1;
+    double nin[3] = {0, 0, 0};
+};
+
+Start start_of(const Scene& sc, int64_t p) {
+    Start s0;
+    if (sc.has_neumann() && sc.s.start_seg && sc.s.start_seg[p] >= 0) {
+        s0.on = sc.s.start_seg[p];
+        sc.nleft(s0.on, s0.nin);
+    }
+    return s0;
+}
+
+// Algorithm 1, or walk on stars when there is a reflecting boundary.
+double forward_walk(const Scene& sc, const double* x, const Start& s0, const Stream& st,
+                    WalkCount& c) {
+    return sc.has_neumann() ? walk_on_stars(sc, x, s0.on, s0.nin, st, 0u, c)
+                            : walk_on_spheres(sc, x, st, 0u, c);
+}
+
+DiffOut diff_walk(const Scene& sc, const double* x, const Start& s0, const Stream& st,
+                  WalkCount& c, bool want_udot, const oracle_cv* cv) {
+    return diff_walk_on_spheres(sc, x, st, c, want_udot, cv, s0.on, s0.nin);
 }
 
 }  // namespace
@@ -909,6 +1180,34 @@ int oracle_closest(const oracle_scene* s, const double* x, double* out) {
     return 0;
 }
 
+double oracle_neumann_weight(int dim, double sigma, double r, double R) {
+    return neumann_weight(dim, sigma, r, R);
+}
+
+// Distance from x to its closest silhouette point of the reflecting boundary
+// (capped at cap), for x inside the domain (on = -1) or on reflecting
+// segment `on` with the domain on the side of nin.
+int oracle_silhouette(const oracle_scene* s, const double* x, int32_t on, const double* nin,
+                      double cap, double* out) {
+    if (check_scene(s) || s->n_ns <= 0 || on < -1 || on >= s->n_ns) return 1;
+    Scene sc(*s);
+    const double zero[3] = {0, 0, 0};
+    *out = std::sqrt(sc.silhouette_d2(x, on, on >= 0 ? nin : zero, cap * cap));
+    return 0;
+}
+
+// First reflecting segment hit by x + t dir, 0 < t < tmax (skipping `skip`):
+// out = {t (tmax if none), segment or -1}.
+int oracle_ray(const oracle_scene* s, const double* x, const double* dir, double tmax,
+               int32_t skip, double* out) {
+    if (check_scene(s) || s->n_ns <= 0) return 1;
+    Scene sc(*s);
+    double t;
+    out[1] = sc.ray(x, dir, tmax, skip, t);
+    out[0] = t;
+    return 0;
+}
+
 // Per-walk records.  mode 0: Algorithm 1 from each point; mode 1: Algorithm 2.
 // u[P*W]; udot[P*W*N] (mode 1, may be NULL); steps[P*W] total closest-point
 // queries including nested walks (may be NULL); prim[P*W] terminal primitive or
@@ -918,7 +1217,7 @@ int oracle_walk_records(const oracle_scene* s, const double* X, int64_t P, int32
                         uint64_t seed, int32_t mode, int32_t instance, double* u, double* udot,
                         int64_t* steps, int32_t* prim, double* uoff, int64_t* truncated,
                         double* xbar, int threads) {
-    if (check_scene(s) || W < 1 || P < 0) return 1;
+    if (check_scene(s) || W < 1 || P < 0 || check_starts(s, P)) return 1;
     Scene sc(*s);
     const int D = s->dim;
     std::vector<int64_t> trunc(std::max(1, threads > 0 ? threads : oracle_threads()) + 64, 0);
@@ -928,11 +1227,11 @@ int oracle_walk_records(const oracle_scene* s, const double* X, int64_t P, int32
             Stream st = make_stream(seed, (uint32_t)p, (uint32_t)m, (uint32_t)instance);
             WalkCount c;
             if (mode == 0) {
-                u[id] = walk_on_spheres(sc, X + p * D, st, 0u, c);
+                u[id] = forward_walk(sc, X + p * D, start_of(sc, p), st, c);
                 if (prim) prim[id] = -1;
                 if (uoff) uoff[id] = 0;
             } else {
-                DiffOut o = diff_walk_on_spheres(sc, X + p * D, st, c, udot != nullptr);
+                DiffOut o = diff_walk(sc, X + p * D, start_of(sc, p), st, c, udot != nullptr, nullptr);
                 u[id] = o.u;
                 c.steps += o.nested_steps;
                 if (udot) std::memcpy(udot + id * s->N, o.udot.data(), sizeof(double) * s->N);
@@ -951,7 +1250,7 @@ int oracle_walk_records(const oracle_scene* s, const double* X, int64_t P, int32
 // Per-point mean and (sample) variance of the mean of W forward walks.
 int oracle_solve(const oracle_scene* s, const double* X, int64_t P, int32_t W, uint64_t seed,
                  int32_t instance, double* u_mean, double* u_var, int64_t* steps_total, int threads) {
-    if (check_scene(s) || W < 1 || P < 0) return 1;
+    if (check_scene(s) || W < 1 || P < 0 || check_starts(s, P)) return 1;
     Scene sc(*s);
     const int D = s->dim;
     std::vector<int64_t> st_steps(256, 0);
@@ -962,7 +1261,7 @@ int oracle_solve(const oracle_scene* s, const double* X, int64_t P, int32_t W, u
         for (int m = 0; m < W; ++m) {
             Stream st = make_stream(seed, (uint32_t)p, (uint32_t)m, (uint32_t)instance);
             WalkCount c;
-            double v = walk_on_spheres(sc, X + p * D, st, 0u, c);
+            double v = forward_walk(sc, X + p * D, start_of(sc, p), st, c);
             s1 += v; s2 += v * v;
             st_steps[t] += c.steps;
         }
@@ -978,7 +1277,8 @@ int oracle_solve(const oracle_scene* s, const double* X, int64_t P, int32_t W, u
 int oracle_jvp(const oracle_scene* s, const double* X, int64_t P, int32_t W, uint64_t seed,
                int32_t instance, double* udot_mean, double* udot_var, double* u_mean,
                int64_t* steps_total, int threads, const oracle_cv* cv) {
-    if (check_scene(s) || W < 1 || P < 0) return 1;
+    if (check_scene(s) || W < 1 || P < 0 || check_starts(s, P)) return 1;
+    if (cv && s->n_ns > 0) return 1;   // the control variate is for walk on spheres only
     Scene sc(*s);
     const int D = s->dim, N = s->N;
     std::vector<int64_t> st_steps(256, 0);
@@ -990,7 +1290,7 @@ int oracle_jvp(const oracle_scene* s, const double* X, int64_t P, int32_t W, uin
         for (int m = 0; m < W; ++m) {
             Stream st = make_stream(seed, (uint32_t)p, (uint32_t)m, (uint32_t)instance);
             WalkCount c;
-            DiffOut o = diff_walk_on_spheres(sc, X + p * D, st, c, true, cv);
+            DiffOut o = diff_walk(sc, X + p * D, start_of(sc, p), st, c, true, cv);
             for (int j = 0; j < N; ++j) { s1[j] += o.udot[j]; s2[j] += o.udot[j] * o.udot[j]; }
             us += o.u;
             st_steps[t] += c.steps + o.nested_steps;
@@ -1010,7 +1310,8 @@ int oracle_jvp(const oracle_scene* s, const double* X, int64_t P, int32_t W, uin
 int oracle_grad(const oracle_scene* s, const double* X, int64_t P, const double* w, int32_t W,
                 uint64_t seed, int32_t instance, double* grad, double* u_mean,
                 int64_t* steps_total, int threads, const oracle_cv* cv) {
-    if (check_scene(s) || W < 1 || P < 0) return 1;
+    if (check_scene(s) || W < 1 || P < 0 || check_starts(s, P)) return 1;
+    if (cv && s->n_ns > 0) return 1;   // the control variate is for walk on spheres only
     Scene sc(*s);
     const int D = s->dim, N = s->N;
     int T = threads > 0 ? threads : oracle_threads();
@@ -1023,7 +1324,7 @@ int oracle_grad(const oracle_scene* s, const double* X, int64_t P, const double*
         for (int m = 0; m < W; ++m) {
             Stream st = make_stream(seed, (uint32_t)p, (uint32_t)m, (uint32_t)instance);
             WalkCount c;
-            DiffOut o = diff_walk_on_spheres(sc, X + p * D, st, c, true, cv);
+            DiffOut o = diff_walk(sc, X + p * D, start_of(sc, p), st, c, true, cv);
             for (int j = 0; j < N; ++j) s1[j] += o.udot[j];
             us += o.u;
             st_steps[t] += c.steps + o.nested_steps;
@@ -1045,7 +1346,8 @@ int oracle_grad_sqloss(const oracle_scene* s, const double* X, int64_t P, const 
                        int32_t W, int32_t B, uint64_t seed, int32_t instance, double* loss,
                        double* grad, double* u_mean, int64_t* steps_total, int threads,
                        const oracle_cv* cv) {
-    if (check_scene(s) || W < 1 || P < 0 || B < 2 || W % B != 0) return 1;
+    if (check_scene(s) || W < 1 || P < 0 || B < 2 || W % B != 0 || check_starts(s, P)) return 1;
+    if (cv && s->n_ns > 0) return 1;   // the control variate is for walk on spheres only
     Scene sc(*s);
     const int D = s->dim, N = s->N;
     int T = threads > 0 ? threads : oracle_threads();
@@ -1064,7 +1366,7 @@ int oracle_grad_sqloss(const oracle_scene* s, const double* X, int64_t P, const 
                 int m = b * B + q;
                 Stream st = make_stream(seed, (uint32_t)p, (uint32_t)m, (uint32_t)instance);
                 WalkCount c;
-                DiffOut o = diff_walk_on_spheres(sc, X + p * D, st, c, true, cv);
+                DiffOut o = diff_walk(sc, X + p * D, start_of(sc, p), st, c, true, cv);
                 ud[q] = o.udot; uh[q] = o.u; us += o.u;
                 st_steps[t] += c.steps + o.nested_steps;
             }
@@ -1145,7 +1447,8 @@ void oracle_adam(int64_t n, double* theta, double* m, double* v, const double* g
 int oracle_walk_records_cv(const oracle_scene* s, const oracle_cv* cv, const double* X,
                            int64_t P, int32_t W, uint64_t seed, int32_t instance,
                            double* walk, double* nested, int threads) {
-    if (check_scene(s) || !cv || W < 1 || P < 0) return 1;
+    if (check_scene(s) || !cv || W < 1 || P < 0 || check_starts(s, P)) return 1;
+    if (s->n_ns > 0) return 1;   // the control variate is for walk on spheres only
     Scene sc(*s);
     const int D = s->dim, K = s->K;
     parallel_points(P, threads, [&](int, int64_t p) {
@@ -1153,7 +1456,7 @@ int oracle_walk_records_cv(const oracle_scene* s, const oracle_cv* cv, const dou
             size_t id = (size_t)p * W + m;
             Stream st = make_stream(seed, (uint32_t)p, (uint32_t)m, (uint32_t)instance);
             WalkCount c;
-            DiffOut o = diff_walk_on_spheres(sc, X + p * D, st, c, false, cv);
+            DiffOut o = diff_walk(sc, X + p * D, start_of(sc, p), st, c, false, cv);
             double* r = walk + id * 9;
             r[0] = o.run;
             for (int i = 0; i < 3; ++i) r[1 + i] = o.xoff[i];

@@ -33,7 +33,9 @@ __all__ = [
     "Scene", "c1_polygon", "c2_star", "c3_icosphere", "c4_batch",
     "disk_polygon", "icosphere", "box_triangles", "sphere_scene",
     "shell_scene", "annulus_scene", "points_in_disk", "points_on_box_faces",
-    "points_in_ball", "vertices_at",
+    "points_in_ball", "vertices_at", "lshape_scene", "half_disk_scene",
+    "annulus_reflecting_scene", "points_in_lshape", "points_in_half_disk",
+    "points_on_segments",
 ]
 
 
@@ -72,6 +74,11 @@ class Scene:
     V_base: Optional[np.ndarray] = None   # V(pi) = V_base + J pi
     pi0: Optional[np.ndarray] = None      # parameter values giving V
     name: str = ""
+    # reflecting (zero-flux) part of the boundary, 2D: segments over their
+    # own vertices, independent of the parameters; walks start on segment s
+    # with the domain to the left of s (first to second vertex)
+    NV: Optional[np.ndarray] = None       # (n_nv, 2) float64
+    nsegs: Optional[np.ndarray] = None    # (n_ns, 2) int32
 
     @property
     def nv(self) -> int:
@@ -230,6 +237,121 @@ def annulus_scene(a: float, b: float, n: int = 1024, sigma: float = 0.0,
                  gvert=np.zeros(2 * n), sigma=sigma, eps=eps, delta=delta,
                  N=1, rowptr=rowptr, pid=pid, vel=vel, V_base=Vb,
                  pi0=np.array([a]), name=f"annulus{n}")
+
+
+# --------------------------------------------------------------------------
+# 2D mixed problems: Dirichlet boundary plus a reflecting (zero-flux) part
+# --------------------------------------------------------------------------
+
+def _subdivide(points, h: float) -> np.ndarray:
+    """Points along the polyline through ``points``, every edge split into
+    equal pieces no longer than h (the given points are kept)."""
+    P = np.asarray(points, float)
+    out = [P[0]]
+    for a, b in zip(P[:-1], P[1:]):
+        n = max(1, int(math.ceil(np.linalg.norm(b - a) / h - 1e-9)))
+        t = np.arange(1, n + 1)[:, None] / n
+        out.extend(list(a + t * (b - a)))
+    return np.array(out)
+
+
+def _chain(n_pts: int, closed: bool = False) -> np.ndarray:
+    """Segments joining consecutive points (and the last to the first if closed)."""
+    i = np.arange(n_pts if closed else n_pts - 1)
+    return np.stack([i, (i + 1) % n_pts], axis=1).astype(np.int32)
+
+
+def corner_harmonic(r, theta):
+    """r^(2/3) cos(2 theta / 3): harmonic, with zero normal derivative on the
+    rays theta = 0 and theta = 3 pi / 2."""
+    return np.power(r, 2.0 / 3.0) * np.cos(2.0 * theta / 3.0)
+
+
+def lshape_scene(h: float = 1.0 / 128, n_arm: int = 16, sigma: float = 0.0,
+                 eps: float = 1e-4, delta: float = 1e-3, gfun=None) -> Scene:
+    """L-shaped domain [-1,1]^2 minus [0,1]x[-1,0].
+
+    The two edges at the re-entrant corner (the origin) are reflecting walls
+    (n_arm segments each); the outer edges are Dirichlet, split into pieces of
+    length <= h, with mapped vertex values gfun(r, theta), theta in
+    [0, 3 pi/2] measured from the +x axis (default: ``corner_harmonic``, the
+    solution for sigma = 0).
+    """
+    gfun = corner_harmonic if gfun is None else gfun
+    V = _subdivide([[1, 0], [1, 1], [-1, 1], [-1, -1], [0, -1]], h)
+    th = np.mod(np.arctan2(V[:, 1], V[:, 0]), 2 * np.pi)
+    gv = gfun(np.hypot(V[:, 0], V[:, 1]), th)
+    NV = _subdivide([[0, -1], [0, 0], [1, 0]], 1.0 / n_arm)
+    return Scene(dim=2, V=V, prims=_chain(len(V)), label=np.zeros(len(V) - 1, np.int32),
+                 bc=[_mapped()], gvert=gv, sigma=sigma, eps=eps, delta=delta,
+                 NV=NV, nsegs=_chain(len(NV)), name="lshape")
+
+
+def points_in_lshape(P: int, seed: int, lim: float = 0.95) -> np.ndarray:
+    """P points uniform in [-lim, lim]^2 minus the quadrant x >= 0, y <= 0."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros((0, 2))
+    while len(out) < P:
+        X = rng.uniform(-lim, lim, (2 * P, 2))
+        X = X[~((X[:, 0] >= 0) & (X[:, 1] <= 0))]
+        out = np.concatenate([out, X])
+    return out[:P]
+
+
+def half_disk_scene(n_arc: int = 256, n_diam: int = 64, R: float = 1.0, sigma: float = 0.0,
+                    g: str = "x2-y2", eps: float = 1e-4, delta: float = 1e-3,
+                    K: int = 1) -> Scene:
+    """Upper half of the disk of radius R: Dirichlet arc (n_arc segments,
+    vertices on the circle), reflecting diameter (n_diam segments).  Data
+    restricted x^2 - y^2 (``g='x2-y2'``) or 1 (``g='one'``), both even in y,
+    so the solution is the full disk's (``g='zero'`` for source tests).  One
+    parameter pi = R with
+    dv/dR = v/R on the arc (the diameter has no normal motion)."""
+    th = np.pi * np.arange(n_arc + 1) / n_arc
+    U = np.stack([np.cos(th), np.sin(th)], axis=1)
+    fld = {"x2-y2": _restricted(0.0, None, [[1.0, 0.0], [0.0, -1.0]], 2),
+           "one": _restricted(1.0, None, None, 2), "zero": _restricted(0.0, None, None, 2)}[g]
+    NV = _subdivide([[-R, 0.0], [R, 0.0]], 2 * R / n_diam)
+    return Scene(dim=2, V=R * U, prims=_chain(n_arc + 1), label=np.zeros(n_arc, np.int32),
+                 bc=[fld], gvert=np.zeros(n_arc + 1), sigma=sigma, eps=eps, delta=delta, K=K,
+                 N=1, rowptr=np.arange(n_arc + 2, dtype=np.int64),
+                 pid=np.zeros(n_arc + 1, np.int32), vel=U.copy(),
+                 V_base=np.zeros((n_arc + 1, 2)), pi0=np.array([R]),
+                 NV=NV, nsegs=_chain(len(NV)), name="half_disk")
+
+
+def points_in_half_disk(P: int, seed: int, rmax: float = 0.9) -> np.ndarray:
+    """P points area-uniform in the half disk r < rmax, y > 0."""
+    rng = np.random.default_rng(seed)
+    r = rmax * np.sqrt(rng.random(P))
+    th = np.pi * rng.random(P)
+    return np.stack([r * np.cos(th), r * np.sin(th)], axis=1)
+
+
+def annulus_reflecting_scene(a: float = 0.4, b: float = 1.0, n_in: int = 256, n_out: int = 512,
+                             sigma: float = 4.0, eps: float = 1e-4, delta: float = 1e-3,
+                             K: int = 1) -> Scene:
+    """Dirichlet inner n_in-gon of radius a with g = 1 inside a reflecting
+    outer n_out-gon of radius b (CCW: the domain on its left).  One
+    parameter: the inner radius a (dv/da = v/a)."""
+    Vi, Ui, pi_ = disk_polygon(n_in, a)
+    NV, _, nsegs = disk_polygon(n_out, b)
+    return Scene(dim=2, V=Vi, prims=pi_, label=np.zeros(n_in, np.int32),
+                 bc=[_restricted(1.0, dim=2)], gvert=np.ones(n_in), sigma=sigma, eps=eps,
+                 delta=delta, K=K, N=1, rowptr=np.arange(n_in + 1, dtype=np.int64),
+                 pid=np.zeros(n_in, np.int32), vel=Ui.copy(), V_base=np.zeros_like(Vi),
+                 pi0=np.array([a]), NV=NV, nsegs=nsegs.astype(np.int32), name="annulus_reflecting")
+
+
+def points_on_segments(NV: np.ndarray, nsegs: np.ndarray, P: int, seed: int, segs=None):
+    """P points on reflecting segments (uniform segment from ``segs`` or all,
+    uniform parameter in [0.05, 0.95]): returns (X, start_seg)."""
+    rng = np.random.default_rng(seed)
+    pool = np.arange(len(nsegs)) if segs is None else np.asarray(segs)
+    s = pool[rng.integers(0, len(pool), P)]
+    t = rng.uniform(0.05, 0.95, P)[:, None]
+    a, b = NV[nsegs[s, 0]], NV[nsegs[s, 1]]
+    return a + t * (b - a), s.astype(np.int32)
 
 
 # --------------------------------------------------------------------------
