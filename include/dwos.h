@@ -376,6 +376,63 @@ dwos_status dwos_cv_train(dwos_ctx* ctx, int32_t steps, int32_t batch, float lr,
 dwos_status dwos_cv_walk_records(dwos_ctx* ctx, const double* X, int64_t P, int32_t W, uint64_t seed,
                                  double* walk, double* nested);
 
+/* ---------------------------------------------------------------------------
+ * Reflecting (zero-flux) boundaries: walk on stars.
+ *
+ * The mixed problem of Sec. 3.4, eq. (mixed_bvp), with Robin coefficient 0
+ * and Robin data 0: du/dn = 0 on a fixed part of the boundary that does not
+ * depend on the parameters, the Dirichlet data g elsewhere.  Its parameter
+ * derivative (Sec. 4.4, eq. (mixed_bvp_deriv)) nests through the Dirichlet
+ * boundary only.  The paper takes the estimator from the walk-on-stars
+ * papers it cites; each step uses the star radius R = min(distance to the
+ * Dirichlet boundary, distance to the closest silhouette vertex of the
+ * reflecting boundary), a uniform direction (at a reflecting boundary point:
+ * uniform over the directions entering the domain), and the first
+ * reflecting point hit along it before R as the next point, weighted by the
+ * ratio of the ball's Poisson kernel there to the direction density
+ * (dwos_eval_reflect_weight); the source is sampled along the same
+ * direction and counted inside the visible region.  One Philox draw per
+ * step: word 0 the direction, word 2 the roulette, word 3 the source radius.
+ * Every solve / grad / jvp / records call then runs walks on stars; the
+ * control variate and batch contexts are not available with a reflecting
+ * boundary (ESTATE).
+ * ------------------------------------------------------------------------- */
+
+/* Reflecting boundary as ns segments (host, ns x 2 vertex indices) over nv
+ * vertices (host, nv x 2, FP64) of its own; ns = 0 removes it.  Segments
+ * meeting at a shared vertex index are adjacent; a vertex with one segment
+ * (an open end) or with more than two always counts as a silhouette.
+ * Builds a BVH over the segments.  2D only.  Errors: EINVAL (3D, index out
+ * of range, zero-length segment, non-finite coordinate), ESTATE (batch
+ * context), ENOMEM. */
+dwos_status dwos_set_reflecting(dwos_ctx* ctx, const double* V, int64_t nv, const int32_t* segs, int64_t ns);
+
+/* Query points that lie on the reflecting boundary (host, P entries: the
+ * segment index a point lies on, with the domain to the left of the segment
+ * from its first to its second vertex, or -1 for a point inside).  Applies
+ * to every later call, which must then have exactly P points; seg = NULL or
+ * P = 0 clears it.  Errors: EINVAL (index out of range), ESTATE (no
+ * reflecting boundary). */
+dwos_status dwos_set_start_segments(dwos_ctx* ctx, const int32_t* seg, int64_t P);
+
+/* The two reflecting-boundary queries of a walk-on-stars step at n rows
+ * (device arrays): X (n x 2), dir (n x 2, unit), cap (n), on (n, int32:
+ * segment the point lies on or -1), nin (n x 2: domain side when on >= 0).
+ * out (n x 3): distance to the closest silhouette vertex (capped at cap), t
+ * of the first reflecting segment hit by X + t dir with 0 < t < cap (cap if
+ * none), that segment or -1.  A row with an invalid `on` gets NaN.
+ * Errors: ESTATE (no reflecting boundary), EINVAL. */
+dwos_status dwos_reflect_query(dwos_ctx* ctx, const double* X, const double* dir, const double* cap,
+                               const int32_t* on, const double* nin, int64_t n, double* out);
+
+/* Step weight at a reflecting boundary point at distance r inside the ball
+ * of radius R (device arrays of n): |dS_1| r^(dim-1) |dG/dr|(r; R) with G
+ * the ball's Green's function, i.e. k r [K1(kr) + K0(kR) I1(kr)/I0(kR)]
+ * (2D) or [kr cosh(k(R-r)) + sinh(k(R-r))]/sinh(kR) (3D), k = sqrt(sigma),
+ * in the context's working precision.  Errors: EINVAL. */
+dwos_status dwos_eval_reflect_weight(dwos_ctx* ctx, const double* r, const double* R, int64_t n,
+                                     double sigma, double* w);
+
 #ifdef __cplusplus
 }
 #endif

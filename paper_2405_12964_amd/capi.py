@@ -92,6 +92,10 @@ def lib():
             "dwos_cv_beta": [vp, dp],
             "dwos_cv_train": [vp, C.c_int32, C.c_int32, C.c_float, C.c_uint64, vp],
             "dwos_cv_walk_records": [vp, vp, C.c_int64, C.c_int32, C.c_uint64, vp, vp],
+            "dwos_set_reflecting": [vp, dp, C.c_int64, i32p, C.c_int64],
+            "dwos_set_start_segments": [vp, i32p, C.c_int64],
+            "dwos_reflect_query": [vp, vp, vp, vp, vp, vp, C.c_int64, vp],
+            "dwos_eval_reflect_weight": [vp, vp, vp, C.c_int64, C.c_double, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -116,6 +120,7 @@ EXPORTED = [
     "dwos_set_variant", "dwos_mlp_theta_size", "dwos_mlp_create", "dwos_mlp_destroy",
     "dwos_mlp_set_params", "dwos_mlp_get_params", "dwos_mlp_eval", "dwos_mlp_loss_grad",
     "dwos_mlp_vjp", "dwos_mlp_adam_step", "dwos_cv_attach", "dwos_cv_beta", "dwos_cv_train", "dwos_cv_walk_records",
+    "dwos_set_reflecting", "dwos_set_start_segments", "dwos_reflect_query", "dwos_eval_reflect_weight",
 ]
 
 

@@ -167,6 +167,75 @@ __device__ inline T k0_small(T z) {    // K0(z) for 0 < z <= 2 from F - (ln(z/2)
     return sf - (log(T(0.5) * z) + T(0.57721566490153286061)) * s;
 }
 
+// I1 and K1 for the reflecting-boundary step weight:
+//   I1(z) = (z/2) sum_k t_k,  t_k = (z^2/4)^k / (k! (k+1)!)
+//   z K1(z) = 1 + z (ln(z/2) + gamma) I1(z) - (z^2/4) sum_k (H_k + H_{k+1}) t_k
+// (Abramowitz-Stegun 9.6.11 with n = 1; the second line is the series times
+// z, free of the 1/z pole).  Scaled forms for z > 2: e^z K1(z) by the
+// trapezoidal rule on int_0^inf cosh(t) exp(-z (cosh t - 1)) dt (z <= 20) or
+// its asymptotic series sqrt(pi/(2z)) sum_k c_k z^-k, c_k = c_{k-1}
+// (4 - (2k-1)^2)/(8k); e^-z I1(z) by the series (z <= 20) or
+// (2 pi z)^-1/2 sum_k (-1)^k c_k z^-k.
+template <class T>
+__device__ inline T i1_series(T z) {
+    const T q = T(0.25) * z * z;
+    T t = T(1), s = T(1);
+    for (int k = 1; k < 64; ++k) {
+        t *= q / (T(k) * T(k + 1));
+        s += t;
+        if (t < BesselCfg<T>::tol * s) break;
+    }
+    return T(0.5) * z * s;
+}
+
+template <class T>
+__device__ inline T i1_scaled(T z) {   // e^-z I1(z), z >= 0
+    if (z <= T(20)) return i1_series<T>(z) * exp(-z);
+    T a = T(1), s = T(1);
+    for (int k = 1; k < 30; ++k) {
+        a *= -(T(4) - T((2 * k - 1) * (2 * k - 1))) / (T(8) * T(k) * z);
+        s += a;
+        if (fabs(a) < BesselCfg<T>::tol * s) break;
+    }
+    return s / sqrt(T(6.283185307179586) * z);
+}
+
+template <class T>
+__device__ inline T zk1_small(T z) {   // z K1(z), 0 < z <= 2
+    const T q = T(0.25) * z * z;
+    T t = T(1), si = T(1), sh = T(1);   // t_0 = 1, H_0 + H_1 = 1
+    for (int k = 1; k < 63; ++k) {      // harm[] has entries up to index 63
+        t *= q / (T(k) * T(k + 1));
+        si += t;
+        sh += T(kSeries.harm[k] + kSeries.harm[k + 1]) * t;
+        if (t < BesselCfg<T>::tol * si) break;
+    }
+    const T i1 = T(0.5) * z * si;
+    return T(1) + z * (log(T(0.5) * z) + T(0.57721566490153286061)) * i1 - q * sh;
+}
+
+template <class T>
+__device__ inline T k1_scaled(T z) {   // e^z K1(z), z > 2
+    if (z > T(20)) {
+        T a = T(1), s = T(1);
+        for (int k = 1; k < 30; ++k) {
+            a *= (T(4) - T((2 * k - 1) * (2 * k - 1))) / (T(8) * T(k) * z);
+            s += a;
+            if (fabs(a) < BesselCfg<T>::tol * s) break;
+        }
+        return sqrt(T(1.5707963267948966) / z) * s;
+    }
+    const T h = BesselCfg<T>::h;
+    T s = T(0.5);
+    for (int j = 1; j < 128; ++j) {
+        const T c = cosh(T(j) * h);
+        const T e = c * exp(-z * (c - T(1)));
+        s += e;
+        if (e < BesselCfg<T>::tol * s) break;
+    }
+    return h * s;
+}
+
 // ---------------------------------------------------------------------------
 // Ball kernels for Algorithm 1 (Sec. 3.3.1), k = sqrt(sigma):
 //   alpha(R) = P(R)/p^dB = 1/I0(kR) (2D),  kR/sinh(kR) (3D),  1 (sigma = 0)
@@ -249,6 +318,32 @@ __device__ inline T green_ball_t(T kappa, T rho, T R) {
         if (kappa == T(0)) return R * R * (R - r) / (T(3) * r);
         const T ratio = exp(-kappa * r) * (expm1(T(-2) * kappa * (R - r)) / expm1(T(-2) * kappa * R));
         return R * R * R * ratio / (T(3) * r);
+    }
+}
+
+// Weight of a walk-on-stars step that ends on the reflecting boundary at
+// distance r < R: the ball's Poisson kernel there (-dG/dn, the normal
+// derivative of G from green_ball_t's Green's function) over the density of
+// that point under uniform direction sampling, |dS_1| r^(D-1) |dG/dr|:
+//   2D: a [K1(a) + K0(b) I1(a) / I0(b)],  a = k r, b = k R
+//   3D: [a cosh(b - a) + sinh(b - a)] / sinh(b)
+//       = e^-a [a (2 + E) - E] / (1 - e^-2b),  E = e^{-2(b - a)} - 1
+// It is 1 at sigma = 0, tends to 1 as r -> 0 and equals poisson_scale at
+// r = R.  2D with b > 2 uses the scaled functions:
+//   K0(b) I1(a) / I0(b) = K0s(b) I1s(a) / I0s(b) e^{a - 2b}.
+template <int D, class T>
+__device__ inline T reflect_weight(T kappa, T r, T R) {
+    if (kappa == T(0)) return T(1);
+    const T a = kappa * r, b = kappa * R;
+    if constexpr (D == 2) {
+        const T t1 = a <= T(2) ? zk1_small<T>(a) : a * k1_scaled<T>(a) * exp(-a);
+        T t2;
+        if (b <= T(2)) t2 = a * k0_small<T>(b) * i1_series<T>(a) / i0_series<T>(b);
+        else t2 = a * k0_scaled<T>(b) * (i1_scaled<T>(a) / i0_scaled<T>(b)) * exp(a - T(2) * b);
+        return t1 + t2;
+    } else {
+        const T E = expm1(T(-2) * (b - a));
+        return exp(-a) * (a * (T(2) + E) - E) / (-expm1(T(-2) * b));
     }
 }
 

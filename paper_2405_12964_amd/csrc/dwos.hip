@@ -20,6 +20,7 @@
 #include "host_common.hpp"
 #include "mlp.hpp"
 #include "bvh.hpp"
+#include "wost_kernels.hpp"
 
 namespace {
 
@@ -89,6 +90,12 @@ struct dwos_ctx {
     DevBuf prim_dep;              // per primitive: 1 if a vertex of it does
     bool cv_fresh = true;         // beta must be reset to 1 before the next use
     int64_t cv_nrec = 0;          // walks recorded by the last differential chunk
+    // reflecting (zero-flux) boundary, 2D: walks on stars when present
+    bool has_ref = false;
+    int64_t ref_n = 0;
+    DevBuf ref_nodes, ref_geo, ref_info, ref_leaf_of;
+    DevBuf start_seg;             // per query point: reflecting segment or -1
+    int64_t start_n = 0;          // points covered by start_seg (0: none)
 };
 
 namespace {
@@ -167,16 +174,11 @@ dwos::ParamCSR make_csr(dwos_ctx* c) {
 }
 
 
-// Upload a built BVH + geometry in the working precision T.
+// Pair nodes of a built BVH in the device layout of bvh.hpp (working precision T).
 template <class T>
-dwos_status upload_geometry(dwos_ctx* c, const std::vector<double>& V, const std::vector<int32_t>& prims,
-                            const std::vector<int32_t>& label, const std::vector<double>& gvert,
-                            const std::vector<dwos::HostNode>& hn, const std::vector<int32_t>& order) {
-    const int D = c->D;
-    const int NS = dwos::node_scalars(D), PS = dwos::prim_scalars(D);
-    const int64_t np = (int64_t)prims.size() / D, nv = (int64_t)V.size() / D;
+std::vector<T> pack_nodes(int D, const std::vector<dwos::HostNode>& hn) {
+    const int NS = dwos::node_scalars(D);
     std::vector<T> nodes((size_t)hn.size() * NS, T(0));
-    std::vector<int32_t> ranges((size_t)hn.size() * 4);
     for (size_t i = 0; i < hn.size(); ++i) {
         T* p = &nodes[i * NS];
         for (int k = 0; k < D; ++k) {
@@ -192,13 +194,78 @@ dwos_status upload_geometry(dwos_ctx* c, const std::vector<double>& V, const std
             }
             sl[D] = T(hn[i].o[c]);
             sl[D + 1] = hn[i].t[c] < 0 ? T(hn[i].t[c]) : T(hn[i].t[c]) + dwos::slab_pad_host<T>(T(scale));
-            ranges[i * 4 + 2 * c] = hn[i].range[c][0];
-            ranges[i * 4 + 2 * c + 1] = hn[i].range[c][1];
         }
         int32_t* r = reinterpret_cast<int32_t*>(p + dwos::ref_offset(D));
         r[0] = hn[i].child[0];
         r[1] = hn[i].child[1];
     }
+    return nodes;
+}
+
+// Reflecting segments: BVH nodes, per-segment geometry and adjacency in
+// leaf order (the layout of wost_kernels.hpp's RefScene).  inc[v]: the
+// segments at vertex v.
+template <class T>
+dwos_status upload_reflecting(dwos_ctx* c, const double* V, const int32_t* segs, int64_t ns,
+                              const std::vector<std::vector<int32_t>>& inc, const dwos::HostBVH& bvh) {
+    std::vector<T> nodes = pack_nodes<T>(2, bvh.nodes);
+    std::vector<int32_t> leaf_of(ns);
+    for (int64_t i = 0; i < ns; ++i) leaf_of[bvh.order[i]] = (int32_t)i;
+    std::vector<T> geo((size_t)ns * dwos::kRefGeo, T(0));
+    std::vector<int32_t> info((size_t)ns * 4, -1);
+    for (int64_t lp = 0; lp < ns; ++lp) {
+        const int32_t o = bvh.order[lp];
+        T* g = &geo[(size_t)lp * dwos::kRefGeo];
+        int32_t* f = &info[(size_t)lp * 4];
+        f[0] = 0;
+        f[3] = o;
+        for (int e = 0; e < 2; ++e) {
+            const int32_t v = segs[2 * o + e];
+            for (int k = 0; k < 2; ++k) g[2 * e + k] = T(V[2 * (size_t)v + k]);
+            const std::vector<int32_t>& at = inc[v];
+            if (at[0] == o) f[0] |= 1 << e;                 // lowest segment at v tests it
+            if (at.size() != 2) { f[0] |= 4 << e; continue; }
+            const int32_t j = at[0] == o ? at[1] : at[0];  // the other segment at v
+            const int32_t far = segs[2 * j] == v ? segs[2 * j + 1] : segs[2 * j];
+            for (int k = 0; k < 2; ++k) g[4 + 2 * e + k] = T(V[2 * (size_t)far + k]);
+            f[1 + e] = leaf_of[j];
+        }
+    }
+    hipStream_t s = c->stream;
+    HIP_OK(upload(c->ref_nodes, nodes.data(), nodes.size(), s));
+    HIP_OK(upload(c->ref_geo, geo.data(), geo.size(), s));
+    HIP_OK(upload(c->ref_info, info.data(), info.size(), s));
+    HIP_OK(upload(c->ref_leaf_of, leaf_of.data(), leaf_of.size(), s));
+    c->ref_n = ns;
+    return DWOS_OK;
+}
+
+template <class T>
+dwos::RefScene<T> make_ref(dwos_ctx* c) {
+    dwos::RefScene<T> r{};
+    r.nodes = c->ref_nodes.as<T>();
+    r.geo = c->ref_geo.as<T>();
+    r.info = c->ref_info.as<int4>();
+    r.leaf_of = c->ref_leaf_of.as<int32_t>();
+    r.n = c->ref_n;
+    return r;
+}
+
+// Upload a built BVH + geometry in the working precision T.
+template <class T>
+dwos_status upload_geometry(dwos_ctx* c, const std::vector<double>& V, const std::vector<int32_t>& prims,
+                            const std::vector<int32_t>& label, const std::vector<double>& gvert,
+                            const std::vector<dwos::HostNode>& hn, const std::vector<int32_t>& order) {
+    const int D = c->D;
+    const int PS = dwos::prim_scalars(D);
+    const int64_t np = (int64_t)prims.size() / D, nv = (int64_t)V.size() / D;
+    std::vector<T> nodes = pack_nodes<T>(D, hn);
+    std::vector<int32_t> ranges((size_t)hn.size() * 4);
+    for (size_t i = 0; i < hn.size(); ++i)
+        for (int c = 0; c < 2; ++c) {
+            ranges[i * 4 + 2 * c] = hn[i].range[c][0];
+            ranges[i * 4 + 2 * c + 1] = hn[i].range[c][1];
+        }
     std::vector<T> pr((size_t)np * PS, T(0));
     for (int64_t lp = 0; lp < np; ++lp) {
         const int32_t o = order[lp];
@@ -342,6 +409,45 @@ dwos_status launch_shape(dwos_ctx* c, dwos::WalkArgs<T>& a) {
     HIP_OK(hipEventCreate(&e1));
     HIP_OK(hipEventRecord(e0, s));
     hipLaunchKernelGGL(kern, dim3(grid), dim3(block), smem, s, a);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipEventRecord(e1, s));
+    c->pending.push_back({e0, e1, MODE});
+    if (c->pending.size() > 4096) {
+        dwos_status st = drain_events(c, nullptr, c->pending.size());
+        if (st) return st;
+    }
+    return DWOS_OK;
+}
+
+// Launch the persistent walk-on-stars kernel (2D, reflecting boundary).
+template <class T, int MODE>
+dwos_status launch_wost(dwos_ctx* c, dwos::WalkArgs<T>& a) {
+    hipStream_t s = c->stream;
+    a.tot = c->totals.as<dwos::Counters>() + MODE;
+    hipLaunchKernelGGL(dwos::fill_u64_kernel, dim3(1), dim3(64), 0, s, a.queue, (int64_t)1);
+    constexpr int block = dwos::kBlock;
+    auto kern = dwos::wost_kernel<T, MODE>;
+    static int occ_per_cu = 0;
+    if (occ_per_cu == 0) {
+        int per = 0;
+        HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, block, 0));
+        occ_per_cu = std::max(1, per);
+    }
+    const int64_t need = (a.total + block - 1) / block;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)occ_per_cu * c->cu_count));
+    const int32_t* starts = c->start_n > 0 ? c->start_seg.as<int32_t>() : nullptr;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_OK(hipStreamIsCapturing(s, &cap));
+    if (cap != hipStreamCaptureStatusNone) {
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, a, make_ref<T>(c), starts);
+        HIP_OK(hipGetLastError());
+        return DWOS_OK;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    HIP_OK(hipEventRecord(e0, s));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, a, make_ref<T>(c), starts);
     HIP_OK(hipGetLastError());
     HIP_OK(hipEventRecord(e1, s));
     c->pending.push_back({e0, e1, MODE});
@@ -597,6 +703,11 @@ dwos_status run_op(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
     const int64_t P = o.P;
     const int32_t W = o.W;
     hipStream_t s = c->stream;
+    if (c->has_ref && diff && c->cv)
+        return fail(DWOS_ESTATE, "the control variate is not supported with a reflecting boundary");
+    if (c->start_n > 0 && c->start_n != P)
+        return fail(DWOS_EINVAL, "start segments were set for " + std::to_string(c->start_n) +
+                                     " points, the call has " + std::to_string(P));
     const int64_t chunk_pts = std::max<int64_t>(1, kMaxWalksPerChunk / W);
     const int64_t max_walks = std::min<int64_t>(P, chunk_pts) * W;
     dwos_status rc = ensure_records<T>(c, std::max<int64_t>(1, max_walks), diff, op == Op::Records);
@@ -641,7 +752,12 @@ dwos_status run_op(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
         if (use_cv) cv_args<T>(c, a);
         // walk ids within a chunk restart at 0; the instance's p_counter = p0
         // keeps the Philox point word absolute
-        rc = diff ? launch_walks<T, D, 1>(c, a) : launch_walks<T, D, 0>(c, a);
+        if constexpr (D == 2) {
+            if (c->has_ref) rc = diff ? launch_wost<T, 1>(c, a) : launch_wost<T, 0>(c, a);
+            else rc = diff ? launch_walks<T, D, 1>(c, a) : launch_walks<T, D, 0>(c, a);
+        } else {
+            rc = diff ? launch_walks<T, D, 1>(c, a) : launch_walks<T, D, 0>(c, a);
+        }
         if (rc) return rc;
         if (use_cv) {
             rc = cv_apply<T, D>(c, walks);
@@ -853,6 +969,10 @@ dwos_status dwos_set_problem(dwos_ctx* c, const dwos_problem* p) {
     if (!(p->delta > 0) || !std::isfinite(p->delta)) return fail(DWOS_EINVAL, "set_problem: delta must be > 0");
     if (p->K < 1 || p->K > 255) return fail(DWOS_EINVAL, "set_problem: K must be in 1..255");
     if (p->kmax < 1) return fail(DWOS_EINVAL, "set_problem: kmax must be >= 1");
+    if (p->rr != 0 && p->rr != 1) return fail(DWOS_EINVAL, "set_problem: rr must be 0 or 1");
+    if (!p->rr && p->sigma > 0)
+        return fail(DWOS_EINVAL, "set_problem: sigma > 0 needs Russian roulette (rr = 1): the walks do not carry "
+                                 "the product of the attenuation factors");
     if (p->n_gauss < 0 || p->n_gauss > DWOS_MAX_GAUSS) return fail(DWOS_EINVAL, "set_problem: n_gauss out of range");
     if (p->n_labels < 1 || p->n_labels > DWOS_MAX_LABELS) return fail(DWOS_EINVAL, "set_problem: n_labels out of range");
     if (!std::isfinite(p->src_c0)) return fail(DWOS_EINVAL, "set_problem: non-finite source");
@@ -1178,6 +1298,88 @@ dwos_status dwos_eval_ball_kernels(dwos_ctx* c, const double* r, const double* R
     return DWOS_OK;
 }
 
+dwos_status dwos_set_reflecting(dwos_ctx* c, const double* V, int64_t nv, const int32_t* segs, int64_t ns) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (ns == 0) {   // back to a Dirichlet-only problem
+        c->has_ref = false;
+        c->ref_n = 0;
+        return DWOS_OK;
+    }
+    if (c->D != 2) return fail(DWOS_EINVAL, "set_reflecting: reflecting boundaries are supported in 2D only");
+    if (!c->instances.empty()) return fail(DWOS_ESTATE, "set_reflecting: context is a batch context");
+    dwos_status rc = check_geometry(2, V, nv, segs, ns, nullptr, 1);
+    if (rc) return fail(rc, "set_reflecting: " + dwos_host::g_last_error.substr(std::min<size_t>(14, dwos_host::g_last_error.size())));
+    std::vector<std::vector<int32_t>> inc(nv);
+    for (int64_t i = 0; i < ns; ++i)
+        for (int e = 0; e < 2; ++e) inc[segs[2 * i + e]].push_back((int32_t)i);
+    HIP_OK(hipSetDevice(c->device));
+    dwos::HostBVH bvh = dwos::build_bvh(V, segs, ns, 2);
+    if (bvh.max_depth >= dwos::kMaxDepth) return fail(DWOS_EINVAL, "set_reflecting: BVH too deep");
+    dwos::reorder_bfs(bvh);
+    rc = c->prec == DWOS_FP32 ? upload_reflecting<float>(c, V, segs, ns, inc, bvh)
+                              : upload_reflecting<double>(c, V, segs, ns, inc, bvh);
+    if (rc) return rc;
+    c->has_ref = true;
+    return DWOS_OK;
+}
+
+dwos_status dwos_set_start_segments(dwos_ctx* c, const int32_t* seg, int64_t P) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (!seg || P == 0) {
+        c->start_n = 0;
+        return DWOS_OK;
+    }
+    if (P < 0) return fail(DWOS_EINVAL, "set_start_segments: negative count");
+    if (!c->has_ref) return fail(DWOS_ESTATE, "set_start_segments: no reflecting boundary");
+    for (int64_t p = 0; p < P; ++p)
+        if (seg[p] < -1 || seg[p] >= c->ref_n)
+            return fail(DWOS_EINVAL, "set_start_segments: segment index out of range at point " + std::to_string(p));
+    HIP_OK(hipSetDevice(c->device));
+    HIP_OK(upload(c->start_seg, seg, (size_t)P, c->stream));
+    c->start_n = P;
+    return DWOS_OK;
+}
+
+dwos_status dwos_reflect_query(dwos_ctx* c, const double* X, const double* dir, const double* cap,
+                               const int32_t* on, const double* nin, int64_t n, double* out) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (!c->has_ref) return fail(DWOS_ESTATE, "reflect_query: no reflecting boundary");
+    if (n < 0 || (n > 0 && (!X || !dir || !cap || !on || !nin || !out)))
+        return fail(DWOS_EINVAL, "reflect_query: bad arguments");
+    if (n == 0) return DWOS_OK;
+    HIP_OK(hipSetDevice(c->device));
+    auto run = [&](auto tag) {
+        using T = decltype(tag);
+        hipLaunchKernelGGL(dwos::ref_query_kernel<T>, dim3(blocks_for(n, 64)), dim3(64), 0, c->stream,
+                           make_ref<T>(c), X, dir, cap, on, nin, n, out);
+    };
+    if (c->prec == DWOS_FP32) run(float{}); else run(double{});
+    HIP_OK(hipGetLastError());
+    return DWOS_OK;
+}
+
+dwos_status dwos_eval_reflect_weight(dwos_ctx* c, const double* r, const double* R, int64_t n, double sigma,
+                                     double* w) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (n < 0 || (n > 0 && (!r || !R || !w)) || !(sigma >= 0))
+        return fail(DWOS_EINVAL, "eval_reflect_weight: bad arguments");
+    if (n == 0) return DWOS_OK;
+    HIP_OK(hipSetDevice(c->device));
+    const double kappa = std::sqrt(sigma);
+    auto run = [&](auto tag) {
+        using T = decltype(tag);
+        if (c->D == 2)
+            hipLaunchKernelGGL((dwos::reflect_weight_eval<T, 2>), dim3(blocks_for(n, 256)), dim3(256), 0, c->stream,
+                               r, R, n, T(kappa), w);
+        else
+            hipLaunchKernelGGL((dwos::reflect_weight_eval<T, 3>), dim3(blocks_for(n, 256)), dim3(256), 0, c->stream,
+                               r, R, n, T(kappa), w);
+    };
+    if (c->prec == DWOS_FP32) run(float{}); else run(double{});
+    HIP_OK(hipGetLastError());
+    return DWOS_OK;
+}
+
 dwos_status dwos_set_variant(dwos_ctx* c, int32_t variant) {
     if (!c) return fail(DWOS_EINVAL, "NULL context");
     if (variant != 0 && variant != 1) return fail(DWOS_EINVAL, "set_variant: variant must be 0 or 1");
@@ -1255,6 +1457,7 @@ dwos_status dwos_walk_timing(dwos_ctx* c, int32_t kind, int32_t reset, double* w
 dwos_status dwos_batch_add_instance(dwos_ctx* c, const double* V, int64_t nv, const int32_t* prims, int64_t np,
                                     const int32_t* label, double sigma, double eps, double delta, int32_t* index) {
     if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (c->has_ref) return fail(DWOS_ESTATE, "batch_add_instance: context has a reflecting boundary");
     const int D = c->D;
     dwos_status rc = check_geometry(D, V, nv, prims, np, label, DWOS_MAX_LABELS);
     if (rc) return rc;

@@ -1,0 +1,584 @@
+// Walk on stars on gfx950: the screened Poisson problem with a Dirichlet
+// boundary and a fixed zero-flux (reflecting) boundary, 2D (the mixed
+// problem of Sec. 3.4 with Robin coefficient and data 0, and its
+// differential version of Sec. 4.4, which nests through the Dirichlet
+// boundary only).  The paper defers the estimator to the walk-on-stars
+// papers; one step, as implemented here:
+//   * d = distance to the Dirichlet boundary (the Dirichlet BVH); in its
+//     eps-shell the walk ends as in Algorithm 1 / Algorithm 2.
+//   * star radius R = min(d, distance to the closest silhouette vertex of the
+//     reflecting boundary), so that the part of B(x, R) visible from x is
+//     star-shaped and bounded by the sphere and the reflecting boundary only.
+//   * a direction v uniform on the circle (at a reflecting boundary point:
+//     the half entering the domain, by reflection of the other half); the
+//     first reflecting segment hit along v before R is the next point, with
+//     weight reflect_weight(t, R), else x + R v with weight alpha(R);
+//     Russian roulette on the weight.
+//   * source: y = x + rho v along the same direction, counted if rho < t.
+// Random numbers: one Philox draw per step, word 0 the direction, word 2 the
+// roulette, word 3 the source radius.
+//
+// The persistent kernel and its records are those of the walk-on-spheres
+// kernel (one walk per lane, wave-level work queue, per-walk records reduced
+// afterwards), so every reduction kernel applies unchanged.
+#pragma once
+#include "walk_kernels.hpp"
+
+namespace dwos {
+
+// Reflecting segments with a pair-node BVH in the layout of bvh.hpp.  Per
+// segment in leaf order:
+//   geo  (8 scalars): a[2] b[2] na[2] nb[2] -- the endpoints and, for each,
+//        the far end of the other segment at that vertex (unused if none);
+//   info (int4): flags, leaf of the other segment at a, at b (-1 none),
+//        original index.
+// flags: 1 this segment tests vertex a, 2 vertex b (every vertex is tested
+// by one of its segments); 4 vertex a is always a silhouette (an open end or
+// a vertex of more than two segments), 8 the same for b.
+constexpr int kRefGeo = 8;
+
+template <class T>
+struct RefScene {
+    const T* nodes;
+    const T* geo;
+    const int4* info;
+    const int32_t* leaf_of;   // original segment -> leaf position
+    int64_t n;
+};
+
+// Relative size below which a cross product counts as zero in the silhouette
+// test (an edge seen edge-on): well above the rounding of the working
+// precision, far below any geometric angle of interest.
+template <class T> struct SilTol;
+template <> struct SilTol<float> { static constexpr float v = 1e-4f; };
+template <> struct SilTol<double> { static constexpr double v = 1e-10; };
+// Tolerance on a ray hit's segment parameter: in FP32 a ray through a shared
+// vertex must not slip between its two segments.
+template <class T> struct RayTol;
+template <> struct RayTol<float> { static constexpr float v = 1e-5f; };
+template <> struct RayTol<double> { static constexpr double v = 0.0; };
+
+// Is vertex v a silhouette point seen from x?  u, w: the far ends of its two
+// segments; own = 1 if u's segment is the one x lies on, 2 if w's, else 0.
+// Seen from x the boundary turns back at v iff both segments leave v on the
+// same side of the line through x and v.  A segment seen edge-on does not
+// decide: on the reflecting boundary (domain side nin) v is then a silhouette
+// iff the other segment leaves to the outside of that line; off it, an
+// edge-on view counts as a silhouette.
+template <class T>
+__device__ __forceinline__ bool sil_test(const T* v, const T* u, const T* w, int own, const T* x,
+                                         const T* nin, bool on) {
+    auto outside = [&](const T* q) { return nin[0] * (q[0] - v[0]) + nin[1] * (q[1] - v[1]) < T(0); };
+    if (own == 1) return outside(w);
+    if (own == 2) return outside(u);
+    const T vx = v[0] - x[0], vy = v[1] - x[1];
+    const T lv = sqrt(vx * vx + vy * vy);
+    const T ux = u[0] - v[0], uy = u[1] - v[1], wx = w[0] - v[0], wy = w[1] - v[1];
+    const T cu = vx * uy - vy * ux, cw = vx * wy - vy * wx;
+    const bool zu = fabs(cu) <= SilTol<T>::v * lv * sqrt(ux * ux + uy * uy);
+    const bool zw = fabs(cw) <= SilTol<T>::v * lv * sqrt(wx * wx + wy * wy);
+    if (zu && zw) return false;
+    if (zu || zw) return on ? outside(zu ? w : u) : true;
+    return (cu > T(0)) == (cw > T(0));
+}
+
+// Squared distance from x to its closest silhouette vertex, if below `best`
+// (else `best`).  x lies on leaf segment `on` (domain side nin) or inside (-1).
+template <class T, class Stack>
+__device__ T silhouette_d2(const RefScene<T>& r, const T* x, int32_t on, const T* nin, T best,
+                           QueryCount& qc, Stack& st) {
+    int sp = 0;
+    int32_t cur = 0;   // the root pair node
+    bool have = true;
+#pragma unroll 1
+    while (have) {
+        if (cur >= 0) {
+            NodeData<T, 2> nd;
+            load_node<T, 2>(r.nodes, cur, nd);
+            qc.nodes++;
+            const T d0 = fmax(box_d2<T, 2>(nd.lo0, nd.hi0, x), slab_d2<T, 2>(nd.n0, nd.o0, nd.t0, x));
+            const T d1 = fmax(box_d2<T, 2>(nd.lo1, nd.hi1, x), slab_d2<T, 2>(nd.n1, nd.o1, nd.t1, x));
+            const bool h0 = d0 < best, h1 = d1 < best;
+            if (h0 && h1) {
+                const bool n0 = d0 <= d1;
+                if (sp < kStackSize) {
+                    st.put(sp, n0 ? nd.c1 : nd.c0, n0 ? d1 : d0);
+                    ++sp;
+                } else {
+                    qc.overflow++;
+                }
+                cur = n0 ? nd.c0 : nd.c1;
+            } else if (h0) {
+                cur = nd.c0;
+            } else if (h1) {
+                cur = nd.c1;
+            } else {
+                have = false;
+            }
+        } else {
+            const int32_t v = -1 - cur;
+            const int32_t start = v >> 3, n = (v & 7) + 1;
+            for (int32_t i = start; i < start + n; ++i) {
+                const int4 inf = r.info[i];
+                const T* g = r.geo + (size_t)i * kRefGeo;
+                qc.prims++;
+                if (inf.x & 1) {   // vertex a: segments i (far end b) and inf.y (far end na)
+                    const T dx = g[0] - x[0], dy = g[1] - x[1];
+                    const T d2 = dx * dx + dy * dy;
+                    if (d2 < best) {
+                        const int own = on < 0 ? 0 : (on == i ? 1 : (on == inf.y ? 2 : 0));
+                        if ((inf.x & 4) || sil_test<T>(g, g + 2, g + 4, own, x, nin, on >= 0)) best = d2;
+                    }
+                }
+                if (inf.x & 2) {   // vertex b: segments i (far end a) and inf.z (far end nb)
+                    const T dx = g[2] - x[0], dy = g[3] - x[1];
+                    const T d2 = dx * dx + dy * dy;
+                    if (d2 < best) {
+                        const int own = on < 0 ? 0 : (on == i ? 1 : (on == inf.z ? 2 : 0));
+                        if ((inf.x & 8) || sil_test<T>(g + 2, g, g + 6, own, x, nin, on >= 0)) best = d2;
+                    }
+                }
+            }
+            have = false;
+        }
+        if (!have) {
+#pragma unroll 1
+            while (sp > 0) {
+                --sp;
+                if (st.get_d(sp) < best) {
+                    cur = st.get_node(sp);
+                    have = true;
+                    break;
+                }
+            }
+        }
+    }
+    return best;
+}
+
+// Entry distance of the ray x + t dir (t in [0, tmax]) into a child's box
+// and oriented slab, or +inf if it misses them.  inv = 1/dir per axis.
+template <class T>
+__device__ __forceinline__ T ray_child(const T* lo, const T* hi, const T* n, T o, T th, const T* x,
+                                       const T* dir, const T* inv, T tmax) {
+    if (th < T(0)) return T(INFINITY);   // empty child
+    T tn = T(0), tf = tmax;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        if (dir[k] != T(0)) {
+            const T t1 = (lo[k] - x[k]) * inv[k], t2 = (hi[k] - x[k]) * inv[k];
+            tn = fmax(tn, fmin(t1, t2));
+            tf = fmin(tf, fmax(t1, t2));
+        } else if (x[k] < lo[k] || x[k] > hi[k]) {
+            return T(INFINITY);
+        }
+    }
+    const T pn = n[0] * dir[0] + n[1] * dir[1];
+    const T q = n[0] * x[0] + n[1] * x[1] - o;
+    if (pn != T(0)) {
+        const T s1 = (-th - q) / pn, s2 = (th - q) / pn;
+        tn = fmax(tn, fmin(s1, s2));
+        tf = fmin(tf, fmax(s1, s2));
+    } else if (fabs(q) > th) {
+        return T(INFINITY);
+    }
+    return tn <= tf * Slack<T>::v + T(1e-30) ? tn : T(INFINITY);
+}
+
+// First reflecting segment (leaf position) hit by x + t dir with
+// 0 < t < tmax, skipping leaf `skip`; -1 if none.  t_out: its t, or tmax.
+// Equal t go to the lowest original index.
+template <class T, class Stack>
+__device__ int32_t ray_first(const RefScene<T>& r, const T* x, const T* dir, T tmax, int32_t skip, T& t_out,
+                             QueryCount& qc, Stack& st) {
+    T inv[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) inv[k] = dir[k] != T(0) ? T(1) / dir[k] : T(0);
+    T best = tmax;
+    int32_t hit = -1;
+    int sp = 0;
+    int32_t cur = 0;
+    bool have = true;
+#pragma unroll 1
+    while (have) {
+        if (cur >= 0) {
+            NodeData<T, 2> nd;
+            load_node<T, 2>(r.nodes, cur, nd);
+            qc.nodes++;
+            const T e0 = ray_child<T>(nd.lo0, nd.hi0, nd.n0, nd.o0, nd.t0, x, dir, inv, best);
+            const T e1 = ray_child<T>(nd.lo1, nd.hi1, nd.n1, nd.o1, nd.t1, x, dir, inv, best);
+            const bool h0 = e0 <= best, h1 = e1 <= best;
+            if (h0 && h1) {
+                const bool n0 = e0 <= e1;
+                if (sp < kStackSize) {
+                    st.put(sp, n0 ? nd.c1 : nd.c0, n0 ? e1 : e0);
+                    ++sp;
+                } else {
+                    qc.overflow++;
+                }
+                cur = n0 ? nd.c0 : nd.c1;
+            } else if (h0) {
+                cur = nd.c0;
+            } else if (h1) {
+                cur = nd.c1;
+            } else {
+                have = false;
+            }
+        } else {
+            const int32_t v = -1 - cur;
+            const int32_t start = v >> 3, n = (v & 7) + 1;
+            for (int32_t i = start; i < start + n; ++i) {
+                if (i == skip) continue;
+                const T* g = r.geo + (size_t)i * kRefGeo;
+                qc.prims++;
+                const T ex = g[2] - g[0], ey = g[3] - g[1];
+                const T den = dir[0] * ey - dir[1] * ex;
+                if (den == T(0)) continue;
+                const T ax = g[0] - x[0], ay = g[1] - x[1];
+                const T t = quot<T>(ax * ey - ay * ex, den);
+                const T u = quot<T>(ax * dir[1] - ay * dir[0], den);
+                if (!(t > T(0)) || u < -RayTol<T>::v || u > T(1) + RayTol<T>::v) continue;
+                if (t < best || (t == best && hit >= 0 && r.info[i].w < r.info[hit].w)) {
+                    best = t;
+                    hit = i;
+                }
+            }
+            have = false;
+        }
+        if (!have) {
+#pragma unroll 1
+            while (sp > 0) {
+                --sp;
+                if (st.get_d(sp) <= best) {
+                    cur = st.get_node(sp);
+                    have = true;
+                    break;
+                }
+            }
+        }
+    }
+    t_out = best;
+    return hit;
+}
+
+// unit normal to the left of leaf segment i (from its first to its second vertex)
+template <class T>
+__device__ __forceinline__ void ref_left_normal(const RefScene<T>& r, int32_t i, T* n) {
+    const T* g = r.geo + (size_t)i * kRefGeo;
+    const T tx = g[2] - g[0], ty = g[3] - g[1];
+    const T inv = T(1) / sqrt(tx * tx + ty * ty);
+    n[0] = -ty * inv;
+    n[1] = tx * inv;
+}
+
+// ---------------------------------------------------------------------------
+// the walk-on-stars kernel (2D)
+//   MODE 0: forward walks, rec_u = walk estimate
+//   MODE 1: differential walks with the joint u estimate and K nested
+//           walks on stars from xbar - delta n at the Dirichlet terminal
+// start_seg (per point row of X, original reflecting segment or -1; NULL:
+// none): walks of that point start on the segment with the domain on its
+// left.
+// ---------------------------------------------------------------------------
+template <class T, int MODE>
+__global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T> ref, const int32_t* start_seg) {
+    constexpr int D = 2;
+    const int lane = threadIdx.x & 63;
+    TravStack<T, false> stack;
+    const StageView sv{0, -1};
+    uint32_t key0 = a.key0, key1 = a.key1;
+    if (a.seed_ptr) {
+        const unsigned long long sd = *a.seed_ptr + (((unsigned long long)a.key1 << 32) | a.key0);
+        key0 = (uint32_t)sd;
+        key1 = (uint32_t)(sd >> 32);
+    }
+    unsigned long long pool_next = 0, pool_end = 0;   // wave-uniform
+    bool done = false;
+    int64_t wid = -1;
+    T x[D], xoff[D], nin[D];
+    T acc = T(0), u_main = T(0), usum = T(0);
+    T kappa = T(0), eps = T(1), delta = T(1);
+    uint32_t k = 0, m = 0, p = 0, inst_tag = 0;
+    int64_t first_row = 0;
+    int32_t root = 0, warm = -1, term_leaf = -1, term_code = -1, phase = 0, on = -1;
+    T term_b1 = T(0);
+    int64_t wsteps = 0;
+    unsigned long long c_walks = 0, c_nested = 0, c_steps = 0, c_term = 0, c_trunc = 0,
+                       c_nodes = 0, c_prims = 0, c_ovf = 0, c_invalid = 0;
+#pragma unroll 1
+    while (true) {
+        // ---- hand new walks to idle lanes ------------------------------------
+        const bool need = (wid < 0) && !done;
+        const unsigned long long mask = __ballot(need);
+        if (mask) {
+            const int n = __popcll(mask);
+            const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+            const unsigned long long avail = pool_end - pool_next;
+            unsigned long long myid;
+            if (avail >= (unsigned long long)n) {
+                myid = pool_next + rank;
+                pool_next += n;
+            } else {
+                const int leader = __ffsll((long long)mask) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(a.queue, (unsigned long long)kQueueChunk);
+                base = bcast64(base, leader);
+                myid = (unsigned long long)rank < avail ? pool_next + rank : base + (rank - avail);
+                pool_next = base + (n - avail);
+                pool_end = base + kQueueChunk;
+            }
+            if (need) {
+                if (myid >= (unsigned long long)a.total) {
+                    done = true;
+                } else {
+                    wid = (int64_t)myid;
+                    const int64_t gid = wid + a.wid_offset;
+                    const Instance<T> in = a.inst[0];
+                    const int64_t local = gid - in.walk_begin;
+                    const int64_t pin = local / a.W;
+                    m = (uint32_t)(local - pin * a.W);
+                    p = (uint32_t)(pin + in.p_counter);
+                    root = in.root;
+                    kappa = in.kappa; eps = in.eps; delta = in.delta;
+                    inst_tag = 0;
+                    const int64_t row = in.point_begin + pin;
+                    const double* xp = a.X + (size_t)row * D;
+                    first_row = row - a.x_base;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) x[i] = T(xp[i]);
+                    on = -1;
+                    if (start_seg && start_seg[row] >= 0) {
+                        on = ref.leaf_of[start_seg[row]];
+                        ref_left_normal<T>(ref, on, nin);
+                    }
+                    acc = T(0); k = 0; warm = -1; phase = 0; usum = T(0); wsteps = 0;
+                    c_walks++;
+                }
+            }
+        }
+        if (__ballot(!done) == 0ull) break;
+        if (done) continue;
+
+        // ---- Dirichlet distance ----------------------------------------------
+        QueryCount qc{0, 0, 0};
+        T d2;
+        int32_t leaf;
+        if (a.first_leaf && phase == 0 && k == 0) {
+            leaf = a.first_leaf[first_row];
+            d2 = a.first_d2[first_row];
+        } else {
+            leaf = closest_leaf<T, D>(a.s, sv, root, x, warm, d2, qc, stack);
+        }
+        c_steps++;
+        wsteps++;
+        if (leaf < 0 || !(d2 >= T(0))) {
+            c_invalid++;
+            const T nanv = T(NAN);
+            a.rec_u[wid] = nanv;
+            if (MODE == 1) {
+                a.rec_prim[wid] = -1;
+                a.rec_uoff[wid] = nanv;
+            }
+            if (a.rec_steps) a.rec_steps[wid] = wsteps;
+            wid = -1;
+            c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;
+            continue;
+        }
+        const T d = sqrt(d2);
+        const bool cap = (int)(k + 1) >= a.prm.kmax;
+        const bool nested = MODE == 1 && phase > 0;
+        bool finished = false;
+        T result = T(0);
+        if (d < eps || cap) {
+            if (cap && !(d < eps)) c_trunc++;
+            T P[9], bary[3];
+            scene_prim<T, D>(a.s, sv, leaf, P);
+            prim_closest<T, D>(P, x, bary);
+            const int32_t orig = a.s.orig[leaf];
+            T V[9];
+            int32_t vid[3];
+            prim_vertices<T, D>(a.s, orig, V, vid);
+            T xbar[3] = {T(0), T(0), T(0)};
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                T v = T(0);
+#pragma unroll
+                for (int kk = 0; kk < D; ++kk) v += bary[kk] * V[kk * D + c];
+                xbar[c] = v;
+            }
+            const T g = boundary_value<T, D>(a.s, a.prm, orig, bary, xbar, vid);
+            if (MODE == 1 && phase == 0) {
+                T n[3] = {T(0), T(0), T(0)};
+                geo_normal<T, D>(V, n);
+                T dn = T(0);
+#pragma unroll
+                for (int c = 0; c < D; ++c) dn += n[c] * (xbar[c] - x[c]);
+                const int flip = dn < T(0) ? 1 : 0;
+                if (flip) {
+#pragma unroll
+                    for (int c = 0; c < D; ++c) n[c] = -n[c];
+                }
+                u_main = acc + g;
+                term_code = orig * 2 + flip;
+                term_b1 = bary[1];
+                term_leaf = leaf;
+#pragma unroll
+                for (int c = 0; c < D; ++c) xoff[c] = xbar[c] - delta * n[c];
+                c_term++;
+                if (a.prim_dep && !a.prim_dep[orig]) {
+                    a.rec_u[wid] = u_main;
+                    a.rec_prim[wid] = term_code;
+                    a.rec_b[wid] = term_b1;
+                    a.rec_uoff[wid] = g;
+                    if (a.rec_steps) a.rec_steps[wid] = wsteps;
+                    wid = -1;
+                    c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;
+                    continue;
+                }
+                // the first nested walk on stars starts at the offset point
+                phase = 1;
+#pragma unroll
+                for (int c = 0; c < D; ++c) x[c] = xoff[c];
+                acc = T(0); k = 0; warm = term_leaf; on = -1;
+                c_nested++;
+                c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;
+                continue;
+            }
+            finished = true;
+            result = acc + g;
+        } else {
+            // ---- one step on the star-shaped region ---------------------------
+            const T R = sqrt(silhouette_d2<T>(ref, x, on, nin, d2, qc, stack));
+            const uint32_t tag = inst_tag | (nested ? (1u | ((uint32_t)(phase - 1) << 8)) : 0u);
+            const u4 r = philox10(u4{k, m, p, tag}, key0, key1);
+            T dir[2];
+            unit_dir<T, D>(r.x, r.y, dir);
+            if (on >= 0) {
+                const T c = dir[0] * nin[0] + dir[1] * nin[1];
+                if (c < T(0)) {
+                    dir[0] -= T(2) * c * nin[0];
+                    dir[1] -= T(2) * c * nin[1];
+                }
+            }
+            T t;
+            const int32_t seg = ray_first<T>(ref, x, dir, R, on, t, qc, stack);
+            if (a.prm.has_source) {
+                const T rho = sqrt(unif_pos<T>(r.w));
+                if (seg < 0 || rho * R < t) {
+                    T y[3];
+#pragma unroll
+                    for (int c = 0; c < D; ++c) y[c] = x[c] + rho * R * dir[c];
+                    acc += green_ball_t<D, T>(kappa, rho, R) * source_f<T, D>(a.prm, y);
+                }
+            }
+            const T wgt = seg >= 0 ? reflect_weight<D, T>(kappa, t, R) : poisson_scale<T, D>(kappa, R);
+            if (a.prm.rr && wgt < unif<T>(r.z)) {
+                finished = true;
+                result = acc;
+                if (MODE == 1 && phase == 0) term_code = -1;
+            } else {
+#pragma unroll
+                for (int c = 0; c < D; ++c) x[c] += t * dir[c];
+                on = seg;
+                if (seg >= 0) {   // domain side: the side the walk came from
+                    ref_left_normal<T>(ref, seg, nin);
+                    if (nin[0] * dir[0] + nin[1] * dir[1] > T(0)) { nin[0] = -nin[0]; nin[1] = -nin[1]; }
+                }
+                ++k;
+                warm = leaf;
+            }
+        }
+        c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;
+        if (!finished) continue;
+
+        if (MODE == 0) {
+            a.rec_u[wid] = result;
+            if (a.rec_steps) a.rec_steps[wid] = wsteps;
+            wid = -1;
+        } else if (phase == 0) {
+            a.rec_u[wid] = result;
+            a.rec_prim[wid] = -1;
+            a.rec_uoff[wid] = T(0);
+            if (a.rec_steps) a.rec_steps[wid] = wsteps;
+            wid = -1;
+        } else {
+            usum += result;
+            if (phase >= a.prm.K) {
+                a.rec_u[wid] = u_main;
+                a.rec_prim[wid] = term_code;
+                a.rec_b[wid] = term_b1;
+                a.rec_uoff[wid] = usum / T(a.prm.K);
+                if (a.rec_steps) a.rec_steps[wid] = wsteps;
+                wid = -1;
+            } else {
+                ++phase;
+#pragma unroll
+                for (int c = 0; c < D; ++c) x[c] = xoff[c];
+                acc = T(0); k = 0; warm = term_leaf; on = -1;
+                c_nested++;
+            }
+        }
+    }
+    c_walks = wave_sum_u64(c_walks);
+    c_nested = wave_sum_u64(c_nested);
+    c_steps = wave_sum_u64(c_steps);
+    c_term = wave_sum_u64(c_term);
+    c_nodes = wave_sum_u64(c_nodes);
+    c_prims = wave_sum_u64(c_prims);
+    c_trunc = wave_sum_u64(c_trunc);
+    c_ovf = wave_sum_u64(c_ovf);
+    c_invalid = wave_sum_u64(c_invalid);
+    if (lane == 0) {
+        Counters* dst[2] = {a.cnt, a.tot};
+        for (int q = 0; q < 2; ++q) {
+            Counters* c = dst[q];
+            atomicAdd(&c->walks, c_walks);
+            atomicAdd(&c->nested, c_nested);
+            atomicAdd(&c->steps, c_steps);
+            atomicAdd(&c->terminal, c_term);
+            atomicAdd(&c->nodes, c_nodes);
+            atomicAdd(&c->prims, c_prims);
+            if (c_trunc) atomicAdd(&c->truncated, c_trunc);
+            if (c_ovf) atomicAdd(&c->overflow, c_ovf);
+            if (c_invalid) atomicAdd(&c->invalid, c_invalid);
+        }
+    }
+}
+
+// Closest silhouette distance and first ray hit for query rows (parity
+// checks of the two reflecting-boundary queries).  out per row:
+// {silhouette distance capped at cap[row], ray t (cap[row] if none), ray
+// hit as an original segment index or -1}.  on: original segment or -1;
+// a row with any other value gets NaN outputs.
+template <class T>
+__global__ void ref_query_kernel(RefScene<T> ref, const double* X, const double* dir, const double* cap,
+                                 const int32_t* on_orig, const double* nin, int64_t n, double* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    T x[2] = {T(X[2 * i]), T(X[2 * i + 1])};
+    T dv[2] = {T(dir[2 * i]), T(dir[2 * i + 1])};
+    T nn[2] = {T(nin[2 * i]), T(nin[2 * i + 1])};
+    const int32_t oo = on_orig[i];
+    if (oo < -1 || oo >= ref.n) {
+        out[3 * i] = out[3 * i + 1] = out[3 * i + 2] = NAN;
+        return;
+    }
+    const int32_t on = oo >= 0 ? ref.leaf_of[oo] : -1;
+    QueryCount qc{0, 0, 0};
+    TravStack<T, false> st;
+    const T c = T(cap[i]);
+    out[3 * i] = double(sqrt(silhouette_d2<T>(ref, x, on, nn, c * c, qc, st)));
+    T t;
+    const int32_t hit = ray_first<T>(ref, x, dv, c, on, t, qc, st);
+    out[3 * i + 1] = double(t);
+    out[3 * i + 2] = hit >= 0 ? double(ref.info[hit].w) : -1.0;
+}
+
+template <class T, int D>
+__global__ void reflect_weight_eval(const double* r, const double* R, int64_t n, T kappa, double* w) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    w[i] = double(reflect_weight<D, T>(kappa, T(r[i]), T(R[i])));
+}
+
+}  // namespace dwos

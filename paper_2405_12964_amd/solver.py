@@ -129,11 +129,44 @@ class Solver:
                                        _ip(bcp) if bcp is not None else None))
         self.N = int(N)
 
+    def set_reflecting(self, V, segs):
+        """Fixed zero-flux boundary (2D segments over vertices V); walks on
+        stars from then on.  An empty ``segs`` removes it."""
+        V = np.ascontiguousarray(V, dtype=np.float64).reshape(-1, 2)
+        segs = np.ascontiguousarray(segs, dtype=np.int32).reshape(-1, 2)
+        check(capi.dwos_set_reflecting(self._ctx, _dp(V), V.shape[0], _ip(segs), segs.shape[0]))
+
+    def set_start_segments(self, seg):
+        """Per query point of the following calls: the reflecting segment it
+        lies on (domain to the segment's left) or -1; None clears."""
+        if seg is None:
+            check(capi.dwos_set_start_segments(self._ctx, None, 0))
+            return
+        seg = np.ascontiguousarray(seg, dtype=np.int32)
+        check(capi.dwos_set_start_segments(self._ctx, _ip(seg), seg.shape[0]))
+
+    def reflect_query(self, X, dirs, cap, on, nin):
+        """Per row: (silhouette distance capped at cap, first ray hit t (cap if
+        none), hit segment or -1) on the reflecting boundary."""
+        X = self._X(X)
+        n = X.shape[0]
+        out = torch.empty(n, 3, dtype=torch.float64, device=X.device)
+        check(capi.dwos_reflect_query(self._ctx, _dev(X), _dev(dirs), _dev(cap), _dev(on, torch.int32),
+                                      _dev(nin), n, _dev(out)))
+        return out
+
+    def eval_reflect_weight(self, r, R, sigma):
+        w = torch.empty_like(r)
+        check(capi.dwos_eval_reflect_weight(self._ctx, _dev(r), _dev(R), r.numel(), float(sigma), _dev(w)))
+        return w
+
     @classmethod
     def from_scene(cls, scene, precision: str = "fp32", V=None, stream=None) -> "Solver":
         """Configure from a scene description (attributes as in ``scenes.Scene``)."""
         s = cls(scene.dim, precision, stream)
         s.set_boundary(scene.V if V is None else V, scene.prims, scene.label, scene.gvert)
+        if getattr(scene, "nsegs", None) is not None and len(scene.nsegs) > 0:
+            s.set_reflecting(scene.NV, scene.nsegs)
         s.set_problem(make_problem(scene.sigma, scene.eps, scene.delta, scene.K, scene.kmax,
                                    scene.rr, scene.src_c0, scene.gauss, scene.bc, scene.dim))
         if scene.N > 0 and scene.rowptr is not None:
