@@ -278,14 +278,112 @@ def run_c4(args):
     }
 
 
+def run_thermal(args):
+    """Walk on stars: one optimisation step of the 2D thermal-design stand-in
+    (four heating wires of 125 segments, g = 1, 64 shape coefficients; a fixed
+    zero-flux slice of 65,536 segments between them; a cold box, Laplace).
+    16384 points on the slice surface, where the loss lives, with their walks
+    starting on the wall; W forward and W differential walks (K = 1 nested
+    walk on stars at each wire terminal); squared loss against the solution
+    of a second coefficient draw; Adam on the coefficients."""
+    import numpy as np
+    import torch
+    import scenes
+    import paper_2405_12964_amd as dw
+
+    dev = torch.device("cuda:0")
+    P, W = args.points or 16384, args.walks or 256
+    sc = scenes.thermal_scene()
+    X, seg = scenes.points_on_segments(sc.NV, sc.nsegs, P, 1)
+    Xt = torch.tensor(X, dtype=torch.float64, device=dev)
+    ref = dw.Solver.from_scene(scenes.thermal_scene(coef_seed=3), "fp32")
+    ref.set_start_segments(seg)
+    uref, _ = ref.solve(Xt, W, 99)
+    torch.cuda.synchronize()
+    print("reference solution done", file=sys.stderr, flush=True)
+    del ref
+    model = dw.ShapeModel(sc, "fp32")
+    model.solver.set_start_segments(seg)
+    pi = torch.tensor(sc.pi0, dtype=torch.float64, device=dev, requires_grad=True)
+    opt = torch.optim.Adam([pi], lr=1e-3)
+
+    def step(i):
+        opt.zero_grad(set_to_none=True)
+        u = dw.DWoSFunction.apply(pi, Xt, model, W, 1000 + 2 * i, W, 1001 + 2 * i)
+        loss = 0.5 * ((u - uref) ** 2).sum()
+        loss.backward()
+        opt.step()
+        return loss
+
+    for i in range(args.warmup):
+        step(i)
+        torch.cuda.synchronize()
+        print(f"warmup step {i} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    for kind in (0, 1):
+        model.solver.walk_timing(kind, reset=True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        loss = step(args.warmup + i)
+        print(f"step {i} queued", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms0, n0, tot0 = model.solver.walk_timing(0)
+    ms1, n1, tot1 = model.solver.walk_timing(1)
+    assert tot0["stack_overflow"] == 0 and tot1["stack_overflow"] == 0
+    assert tot0["invalid"] == 0 and tot1["invalid"] == 0
+    kind, ms, n, tot = (1, ms1, n1, tot1) if ms1 >= ms0 else (0, ms0, n0, tot0)
+    avg_s = ms / max(1, n) / 1e3
+    ops = kernel_ops(tot, has_source=False) / max(1, n)
+    out = {
+        "metric": METRIC, "value": (tot0["steps"] + tot1["steps"]) / elapsed, "unit": "walk-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "walk on stars, 2D thermal design: 4 heating wires (500 segments, g = 1, "
+                               "64 shape coefficients), zero-flux slice of 65,536 segments, cold box, "
+                               f"Laplace; {P} points on the slice x {W} walks, forward + differential "
+                               "(K=1) via autograd",
+                   "points": P, "walks_per_point": W, "reflecting_segments": int(len(sc.nsegs)),
+                   "dirichlet_segments": int(len(sc.prims)), "params": int(sc.N)},
+        "grad_evals_per_s": args.steps / elapsed,
+        "walk_steps": {"forward": tot0["steps"], "differential": tot1["steps"],
+                       "forward_ms": ms0, "differential_ms": ms1,
+                       "truncated": tot0["truncated"] + tot1["truncated"]},
+        "loss": float(loss.item()),
+        "roofline": {"bound": "alu", "achieved": ops / avg_s / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                     "unit": "TFLOP/s", "frac": ops / avg_s / PEAK_FP32_VALU, "traffic": None,
+                     "kernel": f"wost_kernel<float,{kind}>", "avg_launch_ms": ms / max(1, n),
+                     "launches": n, "ops_per_launch": ops,
+                     "steps_per_launch": tot["steps"] / max(1, n),
+                     "nodes_per_step": tot["nodes"] / max(1, tot["steps"]),
+                     "prims_per_step": tot["prims"] / max(1, tot["steps"])},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = min(16, len(os.sched_getaffinity(0)))
+        o = oracle.Oracle(sc, threads=threads)
+        npts, Wc = 32, 32
+        t0 = time.perf_counter()
+        _, _, s1 = o.solve(X[:npts], Wc, 7, start_seg=seg[:npts])
+        _, _, s2 = o.grad(X[:npts], np.ones(npts), Wc, 8, start_seg=seg[:npts])
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": (s1 + s2) / dt, "unit": "walk-steps/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"{npts} points x {Wc} forward + {Wc} differential walks on stars "
+                                         f"of the same scene, brute-force FP64, {dt:.1f} s"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", choices=["c2", "c4", "c5"], default="c2",
-                    help="c2: 2D star (the reported configuration); c5: 3D shape from diffusion "
-                         "with the learned control variate")
+    ap.add_argument("--workload", choices=["c2", "c4", "c5", "thermal"], default="c2",
+                    help="c2: 2D star (the reported configuration); c4: batched instances; c5: 3D "
+                         "shape from diffusion with the learned control variate; thermal: walk on "
+                         "stars with a reflecting boundary")
     ap.add_argument("--points", type=int, default=0)
     ap.add_argument("--walks", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -307,6 +405,11 @@ def main():
     if args.workload == "c4":
         args.steps = 3 if args.steps is None else args.steps
         print(json.dumps(run_c4(args)), flush=True)
+        return
+    if args.workload == "thermal":
+        args.steps = 5 if args.steps is None else args.steps
+        args.warmup = 2 if args.warmup is None else args.warmup
+        print(json.dumps(run_thermal(args)), flush=True)
         return
     if args.workload == "c5":
         args.steps = 50 if args.steps is None else args.steps

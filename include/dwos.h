@@ -386,9 +386,10 @@ dwos_status dwos_cv_walk_records(dwos_ctx* ctx, const double* X, int64_t P, int3
  * boundary only.  The paper takes the estimator from the walk-on-stars
  * papers it cites; each step uses the star radius R = min(distance to the
  * Dirichlet boundary, distance to the closest silhouette vertex of the
- * reflecting boundary), a uniform direction (at a reflecting boundary point:
- * uniform over the directions entering the domain), and the first
- * reflecting point hit along it before R as the next point, weighted by the
+ * reflecting boundary, at least 16 units of rounding of the position), a
+ * uniform direction (at a reflecting boundary point: uniform over the
+ * directions entering the domain), and the first reflecting point hit along
+ * it before R as the next point, weighted by the
  * ratio of the ball's Poisson kernel there to the direction density
  * (dwos_eval_reflect_weight); the source is sampled along the same
  * direction and counted inside the visible region.  One Philox draw per
@@ -399,12 +400,17 @@ dwos_status dwos_cv_walk_records(dwos_ctx* ctx, const double* X, int64_t P, int3
  * ------------------------------------------------------------------------- */
 
 /* Reflecting boundary as ns segments (host, ns x 2 vertex indices) over nv
- * vertices (host, nv x 2, FP64) of its own; ns = 0 removes it.  Segments
- * meeting at a shared vertex index are adjacent; a vertex with one segment
- * (an open end) or with more than two always counts as a silhouette.
- * Builds a BVH over the segments.  2D only.  Errors: EINVAL (3D, index out
- * of range, zero-length segment, non-finite coordinate), ESTATE (batch
- * context), ENOMEM. */
+ * vertices (host, nv x 2, FP64) of its own; ns = 0 removes it.  Every
+ * segment must have the domain on its left (from its first to its second
+ * vertex): closed outer walls counter-clockwise, obstacles clockwise.  The
+ * walls are one-way: a walk meets a wall only from its domain side, so a
+ * walk that rounding puts just behind a wall passes back into the domain
+ * (in exact arithmetic this is the same as taking the side a walk arrives
+ * from).  Segments meeting at a shared vertex index are adjacent; a vertex
+ * with one segment (an open end) or with more than two always counts as a
+ * silhouette.  Builds a BVH over the segments.  2D only.
+ * Errors: EINVAL (3D, index out of range, zero-length segment, non-finite
+ * coordinate), ESTATE (batch context), ENOMEM. */
 dwos_status dwos_set_reflecting(dwos_ctx* ctx, const double* V, int64_t nv, const int32_t* segs, int64_t ns);
 
 /* Query points that lie on the reflecting boundary (host, P entries: the

@@ -93,7 +93,7 @@ struct dwos_ctx {
     // reflecting (zero-flux) boundary, 2D: walks on stars when present
     bool has_ref = false;
     int64_t ref_n = 0;
-    DevBuf ref_nodes, ref_geo, ref_info, ref_leaf_of;
+    DevBuf ref_nodes, ref_geo, ref_info, ref_leaf_of, ref_cones;
     DevBuf start_seg;             // per query point: reflecting segment or -1
     int64_t start_n = 0;          // points covered by start_seg (0: none)
 };
@@ -231,7 +231,50 @@ dwos_status upload_reflecting(dwos_ctx* c, const double* V, const int32_t* segs,
             f[1 + e] = leaf_of[j];
         }
     }
+    // normal cones of every node's two children (layout in wost_kernels.hpp)
+    const double margin = sizeof(T) == 4 ? 2e-3 : 1e-8;
+    std::vector<T> cones(bvh.nodes.size() * 2 * dwos::kRefCone);
+    for (size_t ni = 0; ni < bvh.nodes.size(); ++ni)
+        for (int ch = 0; ch < 2; ++ch) {
+            T* q = &cones[(ni * 2 + ch) * dwos::kRefCone];
+            q[0] = T(0); q[1] = T(0); q[2] = T(2); q[3] = T(-1);   // never pruned
+            const int32_t b0 = bvh.nodes[ni].range[ch][0], b1 = bvh.nodes[ni].range[ch][1];
+            std::vector<double> nrm;
+            bool forced = b1 <= b0;
+            auto add = [&](double tx, double ty) {
+                const double L = std::sqrt(tx * tx + ty * ty);
+                nrm.push_back(ty / L);
+                nrm.push_back(-tx / L);
+            };
+            for (int32_t lp = b0; lp < b1 && !forced; ++lp) {
+                const T* g = &geo[(size_t)lp * dwos::kRefGeo];
+                const int32_t f = info[(size_t)lp * 4];
+                const int32_t o = bvh.order[lp];
+                const double* a = V + 2 * (size_t)segs[2 * o];
+                const double* b = V + 2 * (size_t)segs[2 * o + 1];
+                add(b[0] - a[0], b[1] - a[1]);
+                if ((f & 1) && (f & 4)) forced = true;
+                if ((f & 2) && (f & 8)) forced = true;
+                if (forced) break;
+                // the other segment at a tested vertex, along the polyline through it
+                if (f & 1) add(a[0] - double(g[4]), a[1] - double(g[5]));
+                if (f & 2) add(double(g[6]) - b[0], double(g[7]) - b[1]);
+            }
+            if (forced || nrm.empty()) continue;
+            double ax = 0, ay = 0;
+            for (size_t k = 0; k < nrm.size(); k += 2) { ax += nrm[k]; ay += nrm[k + 1]; }
+            const double L = std::sqrt(ax * ax + ay * ay);
+            if (!(L > 1e-9 * (double)nrm.size())) continue;
+            ax /= L; ay /= L;
+            double th = 0;
+            for (size_t k = 0; k < nrm.size(); k += 2)
+                th = std::max(th, std::acos(std::min(1.0, std::max(-1.0, ax * nrm[k] + ay * nrm[k + 1]))));
+            const double s0 = th + margin;
+            if (!(s0 < 1.5707963267948966)) continue;
+            q[0] = T(ax); q[1] = T(ay); q[2] = T(std::sin(s0)); q[3] = T(std::cos(s0));
+        }
     hipStream_t s = c->stream;
+    HIP_OK(upload(c->ref_cones, cones.data(), cones.size(), s));
     HIP_OK(upload(c->ref_nodes, nodes.data(), nodes.size(), s));
     HIP_OK(upload(c->ref_geo, geo.data(), geo.size(), s));
     HIP_OK(upload(c->ref_info, info.data(), info.size(), s));
@@ -247,6 +290,7 @@ dwos::RefScene<T> make_ref(dwos_ctx* c) {
     r.geo = c->ref_geo.as<T>();
     r.info = c->ref_info.as<int4>();
     r.leaf_of = c->ref_leaf_of.as<int32_t>();
+    r.cones = c->ref_cones.as<T>();
     r.n = c->ref_n;
     return r;
 }

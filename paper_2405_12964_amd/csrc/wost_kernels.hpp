@@ -37,14 +37,44 @@ namespace dwos {
 // a vertex of more than two segments), 8 the same for b.
 constexpr int kRefGeo = 8;
 
+// Normal cones of the silhouette query, per node and child (4 scalars
+// each): a unit axis a and sin, cos of s0 = theta + margin, theta the
+// largest angle between a and the normals involved in the child's vertex
+// tests (its segments' and, at each vertex it tests, the other segment's,
+// all oriented along the polyline through that vertex).  A vertex is a
+// silhouette only if the view direction v - x is perpendicular to some
+// normal of the cone, so a child whose view cone (from x, half-angle beta
+// over the child box's bounding circle) keeps every such dot product of one
+// sign, i.e. |cos angle(a, c - x)| > sin(s0 + beta) with s0 + beta < pi/2,
+// holds none.  The margin covers the edge-on tolerance of the test and
+// rounding; children that hold an always-silhouette vertex, or whose
+// normals spread by pi/2 or more, store sin = 2, cos = -1 (never pruned).
+constexpr int kRefCone = 4;
+
 template <class T>
 struct RefScene {
     const T* nodes;
     const T* geo;
     const int4* info;
     const int32_t* leaf_of;   // original segment -> leaf position
+    const T* cones;           // per node: child 0 then child 1, kRefCone each
     int64_t n;
 };
+
+// Can the child with box lo..hi and cone q hold a silhouette seen from x?
+template <class T>
+__device__ __forceinline__ bool cone_may_hold(const T* lo, const T* hi, const T* q, const T* x) {
+    const T cx = T(0.5) * (lo[0] + hi[0]) - x[0], cy = T(0.5) * (lo[1] + hi[1]) - x[1];
+    const T ex = T(0.5) * (hi[0] - lo[0]), ey = T(0.5) * (hi[1] - lo[1]);
+    const T d2 = cx * cx + cy * cy, r2 = ex * ex + ey * ey;
+    if (!(d2 > r2)) return true;          // x inside the bounding circle
+    const T inv = T(1) / sqrt(d2);
+    const T sb = sqrt(r2) * inv, cb = sqrt(T(1) - sb * sb);
+    const T cs = q[3] * cb - q[2] * sb;   // cos(s0 + beta)
+    if (!(cs > T(0))) return true;
+    const T ss = q[2] * cb + q[3] * sb;   // sin(s0 + beta)
+    return !(fabs((q[0] * cx + q[1] * cy) * inv) > ss);
+}
 
 // Relative size below which a cross product counts as zero in the silhouette
 // test (an edge seen edge-on): well above the rounding of the working
@@ -52,11 +82,13 @@ struct RefScene {
 template <class T> struct SilTol;
 template <> struct SilTol<float> { static constexpr float v = 1e-4f; };
 template <> struct SilTol<double> { static constexpr double v = 1e-10; };
-// Tolerance on a ray hit's segment parameter: in FP32 a ray through a shared
-// vertex must not slip between its two segments.
-template <class T> struct RayTol;
-template <> struct RayTol<float> { static constexpr float v = 1e-5f; };
-template <> struct RayTol<double> { static constexpr double v = 0.0; };
+
+// How far (relative to the coordinates' magnitude) a ray origin may lie
+// behind a wall and still be taken as on its domain side: a few units of
+// rounding of the working precision.
+template <class T> struct kBehind;
+template <> struct kBehind<float> { static constexpr float v = 16 * 1.1920929e-07f; };
+template <> struct kBehind<double> { static constexpr double v = 16 * 2.220446049250313e-16; };
 
 // Is vertex v a silhouette point seen from x?  u, w: the far ends of its two
 // segments; own = 1 if u's segment is the one x lies on, 2 if w's, else 0.
@@ -98,7 +130,9 @@ __device__ T silhouette_d2(const RefScene<T>& r, const T* x, int32_t on, const T
             qc.nodes++;
             const T d0 = fmax(box_d2<T, 2>(nd.lo0, nd.hi0, x), slab_d2<T, 2>(nd.n0, nd.o0, nd.t0, x));
             const T d1 = fmax(box_d2<T, 2>(nd.lo1, nd.hi1, x), slab_d2<T, 2>(nd.n1, nd.o1, nd.t1, x));
-            const bool h0 = d0 < best, h1 = d1 < best;
+            const T* q = r.cones + (size_t)cur * (2 * kRefCone);
+            const bool h0 = d0 < best && cone_may_hold<T>(nd.lo0, nd.hi0, q, x);
+            const bool h1 = d1 < best && cone_may_hold<T>(nd.lo1, nd.hi1, q + kRefCone, x);
             if (h0 && h1) {
                 const bool n0 = d0 <= d1;
                 if (sp < kStackSize) {
@@ -185,9 +219,9 @@ __device__ __forceinline__ T ray_child(const T* lo, const T* hi, const T* n, T o
     return tn <= tf * Slack<T>::v + T(1e-30) ? tn : T(INFINITY);
 }
 
-// First reflecting segment (leaf position) hit by x + t dir with
-// 0 < t < tmax, skipping leaf `skip`; -1 if none.  t_out: its t, or tmax.
-// Equal t go to the lowest original index.
+// First reflecting segment (leaf position) entered from its domain side
+// (its left) by x + t dir with 0 <= t < tmax, skipping leaf `skip`; -1 if
+// none.  t_out: its t, or tmax.  Equal t go to the lowest original index.
 template <class T, class Stack>
 __device__ int32_t ray_first(const RefScene<T>& r, const T* x, const T* dir, T tmax, int32_t skip, T& t_out,
                              QueryCount& qc, Stack& st) {
@@ -231,13 +265,29 @@ __device__ int32_t ray_first(const RefScene<T>& r, const T* x, const T* dir, T t
                 if (i == skip) continue;
                 const T* g = r.geo + (size_t)i * kRefGeo;
                 qc.prims++;
+                // walls are one-way: only a ray entering the wall from the
+                // domain side (the segment's left) is stopped, so a walk that
+                // rounding left just behind a wall passes back into the domain
                 const T ex = g[2] - g[0], ey = g[3] - g[1];
-                const T den = dir[0] * ey - dir[1] * ex;
-                if (den == T(0)) continue;
+                const T dn = ey * dir[0] - ex * dir[1];          // -dir . left normal (times |e|)
+                if (!(dn > T(0))) continue;
                 const T ax = g[0] - x[0], ay = g[1] - x[1];
-                const T t = quot<T>(ax * ey - ay * ex, den);
-                const T u = quot<T>(ax * dir[1] - ay * dir[0], den);
-                if (!(t > T(0)) || u < -RayTol<T>::v || u > T(1) + RayTol<T>::v) continue;
+                const T h = ey * ax - ex * ay;                   // height of x over the wall (times |e|)
+                // an origin further behind the wall than rounding explains
+                // is not on the domain side of this wall
+                if (h < T(0) && h * h > kBehind<T>::v * kBehind<T>::v * (ex * ex + ey * ey) *
+                                            (fabs(x[0]) + fabs(x[1]) + fabs(g[0]) + fabs(g[1])) *
+                                            (fabs(x[0]) + fabs(x[1]) + fabs(g[0]) + fabs(g[1])))
+                    continue;
+                // the segment is crossed iff its endpoints lie on opposite
+                // sides of the ray's line; a shared vertex gets the same side
+                // from both of its segments (same operands, same rounding),
+                // so no ray slips between two segments
+                const T bx = g[2] - x[0], by = g[3] - x[1];
+                const T sa = dir[0] * ay - dir[1] * ax;
+                const T sb = dir[0] * by - dir[1] * bx;
+                if ((sa >= T(0)) == (sb >= T(0))) continue;
+                const T t = fmax(T(0), quot<T>(h, dn));
                 if (t < best || (t == best && hit >= 0 && r.info[i].w < r.info[hit].w)) {
                     best = t;
                     hit = i;
@@ -269,6 +319,22 @@ __device__ __forceinline__ void ref_left_normal(const RefScene<T>& r, int32_t i,
     const T inv = T(1) / sqrt(tx * tx + ty * ty);
     n[0] = -ty * inv;
     n[1] = tx * inv;
+}
+
+// Keep a point on leaf segment i a few units of rounding in front of the
+// segment's line (on the domain side nin): the rounded hit point may land
+// on or just behind the line, and a later step almost parallel to the wall
+// would otherwise round to either side.
+template <class T>
+__device__ __forceinline__ void keep_on_domain_side(const RefScene<T>& r, int32_t i, const T* nin, T* x) {
+    const T* g = r.geo + (size_t)i * kRefGeo;
+    const T s = nin[0] * (x[0] - g[0]) + nin[1] * (x[1] - g[1]);
+    const T ulp = sizeof(T) == 4 ? T(1.1920929e-07) : T(2.220446049250313e-16);
+    const T margin = T(8) * ulp * (fabs(x[0]) + fabs(x[1]) + fabs(g[0]) + fabs(g[1]));
+    if (s < margin) {
+        x[0] += (margin - s) * nin[0];
+        x[1] += (margin - s) * nin[1];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -350,6 +416,7 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
                     if (start_seg && start_seg[row] >= 0) {
                         on = ref.leaf_of[start_seg[row]];
                         ref_left_normal<T>(ref, on, nin);
+                        keep_on_domain_side<T>(ref, on, nin, x);
                     }
                     acc = T(0); k = 0; warm = -1; phase = 0; usum = T(0); wsteps = 0;
                     c_walks++;
@@ -448,7 +515,15 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
             result = acc + g;
         } else {
             // ---- one step on the star-shaped region ---------------------------
-            const T R = sqrt(silhouette_d2<T>(ref, x, on, nin, d2, qc, stack));
+            // The star radius is kept above 16 units of rounding of the
+            // position: a walk next to a silhouette vertex must still move
+            // (a step below the position's resolution would leave it in
+            // place).  Rays still stop at the first wall, so the walk stays
+            // in the domain; the region may lose star shape only at that
+            // scale.  In FP64 the floor is ~1e-15 and never binds in practice.
+            const T ulp = sizeof(T) == 4 ? T(1.1920929e-07) : T(2.220446049250313e-16);
+            const T rmin = T(16) * ulp * (fabs(x[0]) + fabs(x[1]));
+            const T R = fmin(d, fmax(sqrt(silhouette_d2<T>(ref, x, on, nin, d2, qc, stack)), rmin));
             const uint32_t tag = inst_tag | (nested ? (1u | ((uint32_t)(phase - 1) << 8)) : 0u);
             const u4 r = philox10(u4{k, m, p, tag}, key0, key1);
             T dir[2];
@@ -460,8 +535,12 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
                     dir[1] -= T(2) * c * nin[1];
                 }
             }
+            // The march looks a few units of rounding past R: a wall that the
+            // rounded end point x + R v could land behind counts as hit.
             T t;
-            const int32_t seg = ray_first<T>(ref, x, dir, R, on, t, qc, stack);
+            const T reach = R + T(8) * ulp * (fabs(x[0]) + fabs(x[1]) + R);
+            int32_t seg = ray_first<T>(ref, x, dir, reach, on, t, qc, stack);
+            if (seg < 0) t = R;
             if (a.prm.has_source) {
                 const T rho = sqrt(unif_pos<T>(r.w));
                 if (seg < 0 || rho * R < t) {
@@ -480,9 +559,9 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
 #pragma unroll
                 for (int c = 0; c < D; ++c) x[c] += t * dir[c];
                 on = seg;
-                if (seg >= 0) {   // domain side: the side the walk came from
+                if (seg >= 0) {   // the domain is on the wall's left
                     ref_left_normal<T>(ref, seg, nin);
-                    if (nin[0] * dir[0] + nin[1] * dir[1] > T(0)) { nin[0] = -nin[0]; nin[1] = -nin[1]; }
+                    keep_on_domain_side<T>(ref, seg, nin, x);
                 }
                 ++k;
                 warm = leaf;

@@ -35,7 +35,7 @@ __all__ = [
     "shell_scene", "annulus_scene", "points_in_disk", "points_on_box_faces",
     "points_in_ball", "vertices_at", "lshape_scene", "half_disk_scene",
     "annulus_reflecting_scene", "points_in_lshape", "points_in_half_disk",
-    "points_on_segments",
+    "points_on_segments", "thermal_scene",
 ]
 
 
@@ -341,6 +341,64 @@ def annulus_reflecting_scene(a: float = 0.4, b: float = 1.0, n_in: int = 256, n_
                  delta=delta, K=K, N=1, rowptr=np.arange(n_in + 1, dtype=np.int64),
                  pid=np.zeros(n_in, np.int32), vel=Ui.copy(), V_base=np.zeros_like(Vi),
                  pi0=np.array([a]), NV=NV, nsegs=nsegs.astype(np.int32), name="annulus_reflecting")
+
+
+def thermal_scene(n_slice: int = 65536, n_wire: int = 125, n_modes: int = 8,
+                  coef: Optional[np.ndarray] = None, coef_seed: int = 0, sigma: float = 0.0,
+                  eps: float = 1e-3, delta: float = 1e-2, K: int = 1) -> Scene:
+    """2D stand-in for the paper's thermal-design example (Sec. 7.3): four
+    heating wires -- closed loops of n_wire segments each (500 in all), g = 1
+    (label 1) -- whose shapes are the parameters, a fixed zero-flux slice
+    between them (n_slice segments), inside a cold box [-2, 2]^2 (g = 0,
+    label 0).
+
+    Wire w has centre c_w = (+-1.35, +-0.45) and radius
+    r(phi) = 0.15 + sum_{k < n_modes} (a_k cos k phi + b_k sin k phi); its
+    2 n_modes coefficients are parameters (64 in all) with
+    dv/da_k = cos(k phi) u, dv/db_k = sin(k phi) u (u the radial unit
+    vector).  The slice is the superellipse |x/0.9|^4 + |y/0.6|^4 = 1 with a
+    crust ripple of 1% at 24 lobes, listed clockwise so that the domain (the
+    outside) is on the left of each segment.  coef: all 64 coefficients
+    (default: N(0, 0.01^2) draws of seed coef_seed, mode 0 of each wire
+    shifted by 0)."""
+    n_wires = 4
+    N = 2 * n_modes * n_wires
+    if coef is None:
+        coef = np.random.default_rng(coef_seed).normal(0.0, 0.01, N)
+    coef = np.asarray(coef, float)
+    centres = np.array([[-1.35, -0.45], [-1.35, 0.45], [1.35, -0.45], [1.35, 0.45]])
+    box = np.array([[-2.0, -2.0], [2.0, -2.0], [2.0, 2.0], [-2.0, 2.0]])
+    V = [box]
+    prims = [_chain(4, closed=True)]
+    label = [np.zeros(4, np.int32)]
+    Vb = [box.copy()]
+    rows, pids, vels = [np.zeros(4, np.int64)], [], []
+    k = np.arange(n_modes)
+    nv = 4
+    for w in range(n_wires):
+        phi = 2 * np.pi * np.arange(n_wire) / n_wire
+        U = np.stack([np.cos(phi), np.sin(phi)], 1)
+        basis = np.concatenate([np.cos(np.outer(phi, k)), np.sin(np.outer(phi, k))], 1)
+        cw = coef[w * 2 * n_modes:(w + 1) * 2 * n_modes]
+        V.append(centres[w] + U * (0.15 + basis @ cw)[:, None])
+        Vb.append(centres[w] + 0.15 * U)
+        prims.append(_chain(n_wire, closed=True) + nv)
+        label.append(np.ones(n_wire, np.int32))
+        rows.append(np.full(n_wire, 2 * n_modes, np.int64))
+        pids.append(np.tile(np.arange(2 * n_modes, dtype=np.int32) + w * 2 * n_modes, n_wire))
+        vels.append((basis[:, :, None] * U[:, None, :]).reshape(-1, 2))
+        nv += n_wire
+    th = -2 * np.pi * np.arange(n_slice) / n_slice          # clockwise
+    c, s_ = np.cos(th), np.sin(th)
+    rs = 1.0 / (np.abs(c / 0.9) ** 4 + np.abs(s_ / 0.6) ** 4) ** 0.25 * (1 + 0.01 * np.cos(24 * th))
+    NV = np.stack([rs * c, rs * s_], 1)
+    rowptr = np.concatenate([[0], np.cumsum(np.concatenate(rows))]).astype(np.int64)
+    return Scene(dim=2, V=np.concatenate(V), prims=np.concatenate(prims).astype(np.int32),
+                 label=np.concatenate(label), bc=[_restricted(0.0, dim=2), _restricted(1.0, dim=2)],
+                 gvert=np.zeros(nv), sigma=sigma, eps=eps, delta=delta, K=K, N=N,
+                 rowptr=rowptr, pid=np.concatenate(pids), vel=np.concatenate(vels),
+                 V_base=np.concatenate(Vb), pi0=coef.copy(), NV=NV,
+                 nsegs=_chain(n_slice, closed=True), name=f"thermal{n_slice}")
 
 
 def points_on_segments(NV: np.ndarray, nsegs: np.ndarray, P: int, seed: int, segs=None):

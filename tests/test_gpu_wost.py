@@ -100,6 +100,9 @@ def test_reflect_queries_match_oracle(dev, dwos, oracle_mod, name):
     sc = scenes.lshape_scene() if name == "lshape" else scenes.half_disk_scene()
     X, D, cap, on, N = _query_cases(sc, 7)
     o = oracle_mod.Oracle(sc)
+    # as in a walk step, the reach is within the Dirichlet distance (rays
+    # then stay in the domain and meet walls from their domain side)
+    cap = np.minimum(cap, [o.closest(x)["d"] for x in X])
     ref = np.zeros((len(X), 3))
     for i in range(len(X)):
         ref[i, 0] = o.silhouette(X[i], int(on[i]), N[i], cap[i])
