@@ -49,15 +49,19 @@ PEAK_HBM = 8.0e12             # bytes/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_kernel_c2_star4096_hbm.txt")
 
 
+# the files the walk kernel is compiled from, and its build flags
+WALK_KERNEL_SOURCES = ["csrc/walk_kernels.hpp", "csrc/device_math.hpp", "csrc/bvh.hpp", "build.py"]
+
+
 def sources_sha256():
-    """Hash of the kernel sources; HBM counters taken on other sources are stale."""
+    """Hash of the walk kernel's sources; HBM counters taken on other sources
+    are stale."""
     import hashlib
-    d = os.path.join(ROOT, "paper_2405_12964_amd", "csrc")
+    d = os.path.join(ROOT, "paper_2405_12964_amd")
     h = hashlib.sha256()
-    for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".hpp", ".cpp", ".h")):
-            with open(os.path.join(d, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in WALK_KERNEL_SOURCES:
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 
