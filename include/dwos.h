@@ -439,6 +439,49 @@ dwos_status dwos_reflect_query(dwos_ctx* ctx, const double* X, const double* dir
 dwos_status dwos_eval_reflect_weight(dwos_ctx* ctx, const double* r, const double* R, int64_t n,
                                      double sigma, double* w);
 
+/* ---------------------------------------------------------------------------
+ * Shape-optimisation step for mesh vertices (the optimiser of the paper's
+ * experiments, Sec. 6 "Implementation and evaluation" and Sec. 7.2
+ * "Gradient preconditioning"): vector Adam (second moment per vertex from
+ * the squared norm of its gradient) on u = (I + lambda L) x, L the
+ * combinatorial Laplacian of the mesh over edges between movable vertices,
+ * with the step size set by the largest second moment over the movable
+ * vertices:
+ *   g_u = M^-1 g_x,  m = b1 m + (1-b1) g_u,  v_i = b2 v_i + (1-b2)|g_u,i|^2,
+ *   u -= lr m_hat / (sqrt(max_i v_hat_i) + eps),  x = M^-1 u,
+ * M = I + lambda L.  The solves are Jacobi-preconditioned conjugate
+ * gradients on the device, warm-started from the previous solution and
+ * stopped when the preconditioned residual norm falls below tol times its
+ * starting value (or after max_iters).  Device arrays x and g are nv x dim,
+ * row-major; calls are asynchronous on the stream given at creation except
+ * for one small device-to-host read of a convergence flag every 16
+ * iterations.
+ * ------------------------------------------------------------------------- */
+typedef struct dwos_opt dwos_opt;
+
+/* Build M from the primitives (host, np x dim vertex indices: segments or
+ * triangles) over nv vertices; movable (host, nv, nonzero = movable; NULL:
+ * all) marks the vertices the optimiser may move (a fixed vertex keeps its
+ * position and its row of M is the identity); lambda >= 0.
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+dwos_status dwos_opt_create(int32_t dim, int64_t nv, const int32_t* prims, int64_t np, const int32_t* movable,
+                            double lambda, void* stream, dwos_opt** out);
+void dwos_opt_destroy(dwos_opt* opt);
+
+/* Start from vertex positions x (device): u = M x, zero moments. */
+dwos_status dwos_opt_reset(dwos_opt* opt, const double* x);
+
+/* One step with the gradient g = dJ/dx (device); x (device) is updated in
+ * place.  iters (host, 2, may be NULL): CG iterations of the two solves.
+ * Errors: EINVAL, ESTATE (no reset). */
+dwos_status dwos_opt_step(dwos_opt* opt, const double* g, double* x, double lr, double beta1, double beta2,
+                          double eps, int32_t max_iters, double tol, int32_t* iters);
+
+/* x := M^-1 b (device arrays), starting from the x given.  iters (host):
+ * CG iterations used. */
+dwos_status dwos_opt_solve(dwos_opt* opt, const double* b, double* x, int32_t max_iters, double tol,
+                           int32_t* iters);
+
 #ifdef __cplusplus
 }
 #endif

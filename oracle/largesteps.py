@@ -79,6 +79,7 @@ class LargeSteps:
         self.solve = spla.factorized(self.M)
         self.u = self.M @ x
         self.x = x.copy()
+        self.mv = np.ones(self.nv, bool) if movable is None else np.asarray(movable, bool)
         self.m = np.zeros_like(x)
         self.v = np.zeros(self.nv)
         self.t = 0
@@ -90,12 +91,15 @@ class LargeSteps:
         return np.stack([self.solve(gx[:, c]) for c in range(self.D)], axis=1)
 
     def step(self, gx):
+        """One step; fixed vertices (movable False) keep their moments at
+        zero and do not move."""
         g = self.grad_u(gx)
+        g[~self.mv] = 0.0
         self.t += 1
         self.m = self.b1 * self.m + (1 - self.b1) * g
         self.v = self.b2 * self.v + (1 - self.b2) * np.sum(g * g, axis=1)
         mhat = self.m / (1 - self.b1 ** self.t)
         vhat = self.v / (1 - self.b2 ** self.t)
-        self.u = self.u - self.lr * mhat / (math.sqrt(vhat.max()) + self.eps)
+        self.u = self.u - self.lr * mhat / (math.sqrt(vhat[self.mv].max()) + self.eps)
         self.x = np.stack([self.solve(self.u[:, c]) for c in range(self.D)], axis=1)
         return self.x

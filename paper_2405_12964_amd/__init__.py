@@ -11,5 +11,6 @@ from .capi import DwosError, lib  # noqa: F401  (loads libdwos.so or raises)
 from .solver import Solver, make_problem  # noqa: F401
 from .autograd import DWoSFunction, ShapeModel  # noqa: F401
 from .cv import Network  # noqa: F401
+from .opt import LargeSteps  # noqa: F401
 
-__all__ = ["Solver", "make_problem", "DWoSFunction", "ShapeModel", "Network", "DwosError", "lib"]
+__all__ = ["Solver", "make_problem", "DWoSFunction", "ShapeModel", "Network", "LargeSteps", "DwosError", "lib"]

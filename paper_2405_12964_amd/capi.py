@@ -96,6 +96,11 @@ def lib():
             "dwos_set_start_segments": [vp, i32p, C.c_int64],
             "dwos_reflect_query": [vp, vp, vp, vp, vp, vp, C.c_int64, vp],
             "dwos_eval_reflect_weight": [vp, vp, vp, C.c_int64, C.c_double, vp],
+            "dwos_opt_create": [C.c_int32, C.c_int64, i32p, C.c_int64, i32p, C.c_double, vp, C.POINTER(vp)],
+            "dwos_opt_reset": [vp, vp],
+            "dwos_opt_step": [vp, vp, vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32,
+                              C.c_double, i32p],
+            "dwos_opt_solve": [vp, vp, vp, C.c_int32, C.c_double, i32p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -107,6 +112,8 @@ def lib():
         L.dwos_mlp_theta_size.restype = C.c_int32
         L.dwos_mlp_destroy.argtypes = [vp]
         L.dwos_mlp_destroy.restype = None
+        L.dwos_opt_destroy.argtypes = [vp]
+        L.dwos_opt_destroy.restype = None
         _lib = L
     return _lib
 
@@ -121,6 +128,7 @@ EXPORTED = [
     "dwos_mlp_set_params", "dwos_mlp_get_params", "dwos_mlp_eval", "dwos_mlp_loss_grad",
     "dwos_mlp_vjp", "dwos_mlp_adam_step", "dwos_cv_attach", "dwos_cv_beta", "dwos_cv_train", "dwos_cv_walk_records",
     "dwos_set_reflecting", "dwos_set_start_segments", "dwos_reflect_query", "dwos_eval_reflect_weight",
+    "dwos_opt_create", "dwos_opt_destroy", "dwos_opt_reset", "dwos_opt_step", "dwos_opt_solve",
 ]
 
 
