@@ -39,7 +39,7 @@ class VertexShapeOptimizer:
     """Optimise the movable vertices of a scene's Dirichlet boundary."""
 
     def __init__(self, scene, movable, lam=20.0, lr=1e-3, W0=8, WT=64, T=100, precision="fp32",
-                 device="cuda"):
+                 device="cuda", cg_tol=1e-7):
         self.scene, self.dim = scene, scene.dim
         self.mv = np.asarray(movable, bool)
         self.solver = Solver(scene.dim, precision)
@@ -53,6 +53,9 @@ class VertexShapeOptimizer:
         self.opt = LargeSteps(scene.dim, scene.nv, scene.prims, lam, self.mv.astype(np.int32))
         self.opt.reset(self.x)
         self.lr, self.W0, self.WT, self.T = lr, W0, WT, T
+        # relative residual of the two solves: far below the gradient noise
+        # of a few walks per point
+        self.cg_tol = cg_tol
         self.t = 0
         self.gx = torch.zeros_like(self.x)
 
@@ -65,7 +68,7 @@ class VertexShapeOptimizer:
         g, _ = self.solver.grad(X, w, W, 2 * seed + 1, u_mean=False)
         self.gx.zero_()
         self.gx[self.idx] = g.view(-1, self.dim)
-        its = self.opt.step(self.gx, self.x, lr=self.lr)
+        its = self.opt.step(self.gx, self.x, lr=self.lr, tol=self.cg_tol)
         self.solver.update_vertices(self.x)
         self.t += 1
         return 0.5 * float(((u - uref) ** 2).sum()), W, its
