@@ -58,6 +58,7 @@ def lib():
         L.oracle_neumann_weight.restype = C.c_double
         L.oracle_silhouette.argtypes = [sp, dp, C.c_int32, dp, C.c_double, dp]
         L.oracle_ray.argtypes = [sp, dp, dp, C.c_double, C.c_int32, dp]
+        L.oracle_safe_radius.argtypes = [sp, dp, dp]
         L.oracle_walk_records.argtypes = [sp, dp, C.c_int64, C.c_int32, C.c_uint64, C.c_int32,
                                           C.c_int32, dp, dp, lp, ip, dp, lp, dp, C.c_int]
         L.oracle_solve.argtypes = [sp, dp, C.c_int64, C.c_int32, C.c_uint64, C.c_int32, dp, dp,
@@ -95,6 +96,7 @@ class OracleScene(C.Structure):
         ("vel", C.POINTER(C.c_double)), ("bc_pid", C.POINTER(C.c_int32)),
         ("n_nv", C.c_int32), ("NV", C.POINTER(C.c_double)), ("n_ns", C.c_int32),
         ("nsegs", C.POINTER(C.c_int32)), ("start_seg", C.POINTER(C.c_int32)),
+        ("n_mono", C.c_int32), ("mono", C.POINTER(C.c_double)), ("mono_c", C.c_double),
     ]
 
 
@@ -169,6 +171,11 @@ class Oracle:
             s.NV = _ptr(self._NV, C.c_double)
             s.n_ns = self._nsegs.shape[0]
             s.nsegs = _ptr(self._nsegs, C.c_int32)
+        if getattr(scene, "mono", None) is not None and len(scene.mono) > 0:
+            self._mono = np.ascontiguousarray(scene.mono, dtype=np.float64).reshape(-1, 3)
+            s.n_mono = self._mono.shape[0]
+            s.mono = _ptr(self._mono, C.c_double)
+            s.mono_c = float(scene.mono_c)
         self._start = None
         self._s = s
 
@@ -286,6 +293,15 @@ class Oracle:
                               float(tmax), int(skip), _ptr(out, C.c_double))
         assert rc == 0
         return float(out[0]), int(out[1])
+
+    def safe_radius(self, x, harnack=False):
+        """Radius of a disk around x on which the implicit h stays positive
+        (harnack=True: the Harnack radius alone)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        out = np.zeros(2)
+        rc = lib().oracle_safe_radius(C.byref(self._s), _ptr(x, C.c_double), _ptr(out, C.c_double))
+        assert rc == 0
+        return float(out[1 if harnack else 0])
 
     def walk_records_cv(self, X, W, seed, cv, instance=0):
         """Differential walks with the control variate: per-walk records

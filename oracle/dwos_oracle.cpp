@@ -86,6 +86,14 @@ struct oracle_scene {
     // domain to the left of the segment (from its first to its second
     // vertex), or -1 for an interior point (NULL: all interior)
     const int32_t* start_seg;
+    // Implicit Dirichlet boundary (2D, Sec. 7.4): the zero set of
+    // h(x) = mono_c + sum_n a_n / |x - p_n|, rows (a_n, p_n) of mono, with
+    // the domain {h > 0}; n_mono = 0: the explicit boundary above.  The
+    // parameters are (a_n, p_n) per monopole (N = 3 n_mono); the boundary
+    // data is label 0's restricted field.
+    int32_t n_mono;
+    const double* mono;      // n_mono*3
+    double mono_c;
 };
 
 // Learned control variate of the nested walks: network N(x) (frequencies B,
@@ -349,6 +357,103 @@ struct Scene {
         return v;
     }
     bool has_source() const { return s.src_c0 != 0.0 || s.n_gauss > 0; }
+
+    // ----- implicit boundary (harmonic monopoles) ---------------------------
+    bool implicit() const { return s.n_mono > 0; }
+
+    // h and its gradient at x
+    double hval(const double* x, double gr[2]) const {
+        double h = s.mono_c;
+        gr[0] = gr[1] = 0;
+        for (int n = 0; n < s.n_mono; ++n) {
+            const double* m = s.mono + 3 * n;
+            const double dx = x[0] - m[1], dy = x[1] - m[2];
+            const double r = std::sqrt(dx * dx + dy * dy);
+            h += m[0] / r;
+            const double q = m[0] / (r * r * r);
+            gr[0] -= q * dx;
+            gr[1] -= q * dy;
+        }
+        return h;
+    }
+
+    // Radius of a disk around x (h(x) > 0) on which h > 0, from Harnack's
+    // inequality: 1/|y - p| is harmonic in 3D, so f = h - c > 0 (all a_n > 0)
+    // is a positive harmonic function on the 3D ball of radius R = distance
+    // to the nearest pole, and f(y) >= f(x) R (R - r) / (R + r)^2 at distance
+    // r.  h stays positive while that bound exceeds -c = A: with t = r / R,
+    // A (1 + t)^2 = f (1 - t), whose root in [0, 1) is
+    // t = 2 (f - A) / ((2A + f) + sqrt(f^2 + 8 A f)).  The planar disk is a
+    // cross-section of the ball.
+    double harnack_radius(const double* x, double h) const {
+        double R = INFINITY;
+        for (int n = 0; n < s.n_mono; ++n) {
+            const double* m = s.mono + 3 * n;
+            R = std::min(R, std::hypot(x[0] - m[1], x[1] - m[2]));
+        }
+        const double A = -s.mono_c, f = h - s.mono_c;
+        const double t = 2 * (f - A) / ((2 * A + f) + std::sqrt(f * f + 8 * A * f));
+        return t * R;
+    }
+
+    // Radius of a disk around x on which h > 0: the larger of the Harnack
+    // radius above and a direct bound.  With every a_n > 0, each monopole
+    // term on B(x, d) is at least a_n / (|x - p_n| + d), so h > 0 there while
+    // S(d) = sum_n a_n / (|x - p_n| + d) > -c.  1/S is the parallel sum of
+    // the linear functions (|x - p_n| + d) / a_n, hence increasing and
+    // concave, so Newton's iterates for 1/S(d) = -1/c from d = 0 rise
+    // monotonically towards the root and each is a safe radius; eight are
+    // taken (one is exact for a single monopole).  The direct bound is not
+    // limited by the distance to a pole, as the Harnack radius is.
+    double safe_radius(const double* x, double h) const {
+        const double A = -s.mono_c;
+        double d = 0;
+        for (int it = 0; it < 8; ++it) {
+            double S = 0, T = 0;
+            for (int n = 0; n < s.n_mono; ++n) {
+                const double* m = s.mono + 3 * n;
+                const double q = std::hypot(x[0] - m[1], x[1] - m[2]) + d;
+                S += m[0] / q;
+                T += m[0] / (q * q);
+            }
+            // (1/S)' = T / S^2:  d += (1/A - 1/S) S^2 / T
+            d += (S * S / A - S) / T;
+        }
+        return std::max(d, harnack_radius(x, h));
+    }
+
+    // The shell of Sec. 7.4, h <= |grad h| eps (which takes in points at or
+    // past the zero set), applied only where h < -c: next to a pole |grad h|
+    // grows faster than h and the test would hold far from the boundary.
+    bool in_shell(double h, double gn) const { return h <= gn * s.eps && h < -s.mono_c; }
+
+    // dh/dpi_j at x for pi = (a_n, p_n) per monopole
+    void hparam(const double* x, double* dh) const {
+        for (int n = 0; n < s.n_mono; ++n) {
+            const double* m = s.mono + 3 * n;
+            const double dx = x[0] - m[1], dy = x[1] - m[2];
+            const double r = std::sqrt(dx * dx + dy * dy);
+            dh[3 * n] = 1 / r;
+            dh[3 * n + 1] = m[0] * dx / (r * r * r);
+            dh[3 * n + 2] = m[0] * dy / (r * r * r);
+        }
+    }
+
+    // restricted data of label 0 and its gradient at a point
+    double g_field(const double* x, double gr[3]) const {
+        const int D = 2;
+        const double* q = s.bc_quad;
+        double v = q[0];
+        for (int i = 0; i < D; ++i) v += q[1 + i] * x[i];
+        for (int i = 0; i < D; ++i)
+            for (int j = 0; j < D; ++j) v += x[i] * q[1 + D + i * D + j] * x[j];
+        gr[0] = gr[1] = gr[2] = 0;
+        for (int i = 0; i < D; ++i) {
+            gr[i] = q[1 + i];
+            for (int j = 0; j < D; ++j) gr[i] += (q[1 + D + i * D + j] + q[1 + D + j * D + i]) * x[j];
+        }
+        return v;
+    }
 
     // ----- reflecting boundary (walk on stars) ------------------------------
     bool has_neumann() const { return s.n_ns > 0; }
@@ -916,6 +1021,54 @@ double walk_on_stars(const Scene& sc, const double* x0, int on0, const double* n
     }
 }
 
+// ---------------------------------------------------------------------------
+// Algorithm 1 on the implicit boundary of Sec. 7.4.  The ball is the safe
+// disk of the point (safe_radius: inside the domain, not the largest empty
+// one); the walk stops in the shell (in_shell) at the boundary point of one
+// Newton projection xbar = x - h grad h / |grad h|^2.  Every other step is
+// Algorithm 1's, with the same random numbers.
+// ---------------------------------------------------------------------------
+void source_and_step(const Scene& sc, double* x, double d, const uint32_t w[4], const Stream& st,
+                     uint32_t k, uint32_t extra, double& acc) {
+    const int D = sc.D;
+    if (sc.has_source()) {
+        uint32_t wb[4] = {w[1], 0, 0, 0};
+        if (D == 3) st.draw(k, extra | 2u, wb);
+        double dir[3];
+        sphere_dir(D, wb[0], wb[1], dir);
+        double rad = d * std::pow(u24pos(w[3]), 1.0 / D);
+        double y[3] = {0, 0, 0};
+        for (int i = 0; i < D; ++i) y[i] = x[i] + rad * dir[i];
+        acc += green(D, sc.s.sigma, rad, d) * ball_volume(D, d) * sc.f(y);
+    }
+}
+
+double walk_implicit(const Scene& sc, const double* x0, const Stream& st, uint32_t extra, WalkCount& cnt) {
+    double x[3] = {x0[0], x0[1], 0};
+    double acc = 0.0;
+    for (uint32_t k = 0;; ++k) {
+        double gr[2];
+        const double h = sc.hval(x, gr);
+        cnt.steps++;
+        const double gn = std::hypot(gr[0], gr[1]);
+        const bool shell = sc.in_shell(h, gn);
+        const bool cap = (int64_t)k + 1 >= sc.s.kmax;
+        if (shell || cap) {
+            if (cap && !shell) cnt.truncated++;
+            double xb[3] = {x[0] - h * gr[0] / (gn * gn), x[1] - h * gr[1] / (gn * gn), 0}, gg[3];
+            return acc + sc.g_field(xb, gg);
+        }
+        const double d = sc.safe_radius(x, h);
+        uint32_t w[4];
+        st.draw(k, extra, w);
+        source_and_step(sc, x, d, w, st, k, extra, acc);
+        if (sc.s.rr && poisson_scale(2, sc.s.sigma, d) < u24(w[2])) return acc;
+        double dir[3];
+        sphere_dir(2, w[0], w[1], dir);
+        for (int i = 0; i < 2; ++i) x[i] += d * dir[i];
+    }
+}
+
 struct DiffOut {
     double u = 0;          // joint estimate of u (sources + g at the terminal)
     bool terminal = false; // reached the shell (false: stopped by roulette)
@@ -1088,6 +1241,68 @@ DiffOut diff_walk_on_spheres(const Scene& sc, const double* x0, const Stream& st
     }
 }
 
+// Algorithm 2 on the implicit boundary: at the shell, the boundary point
+// xbar (Newton projection), the outward normal n = -grad h / |grad h| there,
+// K nested walks from xbar - delta n, and for each parameter the normal
+// velocity V_n = (dh/dpi) / |grad h| (the paper's level-set formula, Sec.
+// 3.1) in eq. (boundary_deriv_restricted): udot = V_n (dg/dn - du/dn).
+DiffOut diff_walk_implicit(const Scene& sc, const double* x0, const Stream& st, WalkCount& cnt,
+                           bool want_udot) {
+    const int N = sc.s.N;
+    DiffOut out;
+    if (want_udot) out.udot.assign(N, 0.0);
+    double x[3] = {x0[0], x0[1], 0};
+    double acc = 0.0;
+    for (uint32_t k = 0;; ++k) {
+        double gr[2];
+        const double h = sc.hval(x, gr);
+        cnt.steps++;
+        const double gn = std::hypot(gr[0], gr[1]);
+        const bool shell = sc.in_shell(h, gn);
+        const bool cap = (int64_t)k + 1 >= sc.s.kmax;
+        if (shell || cap) {
+            if (cap && !shell) cnt.truncated++;
+            double xb[3] = {x[0] - h * gr[0] / (gn * gn), x[1] - h * gr[1] / (gn * gn), 0};
+            double gb[2];
+            sc.hval(xb, gb);
+            const double gbn = std::hypot(gb[0], gb[1]);
+            const double n[3] = {-gb[0] / gbn, -gb[1] / gbn, 0};
+            double xoff[3] = {xb[0] - sc.s.delta * n[0], xb[1] - sc.s.delta * n[1], 0};
+            double usum = 0;
+            for (int i = 0; i < sc.s.K; ++i) {
+                WalkCount c2;
+                usum += walk_implicit(sc, xoff, st, 1u | ((uint32_t)i << 8), c2);
+                out.nested_steps += c2.steps;
+                cnt.truncated += c2.truncated;
+            }
+            double ggr[3];
+            const double gx = sc.g_field(xb, ggr);
+            out.uoff = usum / sc.s.K;
+            out.run = 1;
+            for (int i = 0; i < 3; ++i) { out.xoff[i] = xoff[i]; out.xbar[i] = xb[i]; }
+            const double dudn = (gx - out.uoff) / sc.s.delta;
+            const double dgdn = ggr[0] * n[0] + ggr[1] * n[1];
+            out.u = acc + gx;
+            out.terminal = true;
+            out.prim = 0;
+            if (want_udot) {
+                std::vector<double> dh(3 * sc.s.n_mono);
+                sc.hparam(xb, dh.data());
+                for (int j = 0; j < N && j < 3 * sc.s.n_mono; ++j) out.udot[j] = dh[j] / gbn * (dgdn - dudn);
+            }
+            return out;
+        }
+        const double d = sc.safe_radius(x, h);
+        uint32_t w[4];
+        st.draw(k, 0u, w);
+        source_and_step(sc, x, d, w, st, k, 0u, acc);
+        if (sc.s.rr && poisson_scale(2, sc.s.sigma, d) < u24(w[2])) { out.u = acc; return out; }
+        double dir[3];
+        sphere_dir(2, w[0], w[1], dir);
+        for (int i = 0; i < 2; ++i) x[i] += d * dir[i];
+    }
+}
+
 Stream make_stream(uint64_t seed, uint32_t p, uint32_t m, uint32_t instance) {
     Stream st;
     st.key[0] = (uint32_t)seed; st.key[1] = (uint32_t)(seed >> 32);
@@ -1106,7 +1321,16 @@ void parallel_points(int64_t P, int threads, F&& fn) {
 }
 
 int check_scene(const oracle_scene* s) {
-    if (!s || (s->dim != 2 && s->dim != 3) || s->nv <= 0 || s->np <= 0) return 1;
+    if (!s) return 1;
+    if (s->n_mono < 0) return 1;
+    if (s->n_mono > 0) {   // implicit boundary: 2D, c < 0, positive scales, restricted data
+        if (s->dim != 2 || !s->mono || !(s->mono_c < 0) || s->n_ns > 0 || !s->bc_kind || s->bc_kind[0] != 0)
+            return 1;
+        for (int n = 0; n < s->n_mono; ++n) if (!(s->mono[3 * n] > 0)) return 1;
+        if (!(s->eps > 0) || s->sigma < 0 || s->K < 1 || s->kmax < 1 || (!s->rr && s->sigma > 0)) return 1;
+        return 0;
+    }
+    if ((s->dim != 2 && s->dim != 3) || s->nv <= 0 || s->np <= 0) return 1;
     if (!(s->eps > 0) || s->sigma < 0 || s->K < 1 || s->kmax < 1) return 1;
     // without roulette the walks would have to carry the product of the
     // alpha factors; only sigma = 0 (alpha = 1) is accepted then
@@ -1147,12 +1371,14 @@ Start start_of(const Scene& sc, int64_t p) {
 // Algorithm 1, or walk on stars when there is a reflecting boundary.
 double forward_walk(const Scene& sc, const double* x, const Start& s0, const Stream& st,
                     WalkCount& c) {
+    if (sc.implicit()) return walk_implicit(sc, x, st, 0u, c);
     return sc.has_neumann() ? walk_on_stars(sc, x, s0.on, s0.nin, st, 0u, c)
                             : walk_on_spheres(sc, x, st, 0u, c);
 }
 
 DiffOut diff_walk(const Scene& sc, const double* x, const Start& s0, const Stream& st,
                   WalkCount& c, bool want_udot, const oracle_cv* cv) {
+    if (sc.implicit()) return diff_walk_implicit(sc, x, st, c, want_udot);
     return diff_walk_on_spheres(sc, x, st, c, want_udot, cv, s0.on, s0.nin);
 }
 
@@ -1177,6 +1403,18 @@ int oracle_closest(const oracle_scene* s, const double* x, double* out) {
     Hit h = sc.closest(x);
     out[0] = std::sqrt(h.d2); out[1] = h.prim;
     for (int i = 0; i < 3; ++i) { out[2 + i] = h.bary[i]; out[5 + i] = h.xbar[i]; }
+    return 0;
+}
+
+// Safe disk radius at x for an implicit boundary (h(x) > 0): out[0] the
+// radius used by the walks, out[1] the Harnack radius alone.
+int oracle_safe_radius(const oracle_scene* s, const double* x, double* out) {
+    if (check_scene(s) || s->n_mono <= 0) return 1;
+    Scene sc(*s);
+    double gr[2];
+    const double h = sc.hval(x, gr);
+    out[0] = sc.safe_radius(x, h);
+    out[1] = sc.harnack_radius(x, h);
     return 0;
 }
 
@@ -1278,7 +1516,7 @@ int oracle_jvp(const oracle_scene* s, const double* X, int64_t P, int32_t W, uin
                int32_t instance, double* udot_mean, double* udot_var, double* u_mean,
                int64_t* steps_total, int threads, const oracle_cv* cv) {
     if (check_scene(s) || W < 1 || P < 0 || check_starts(s, P)) return 1;
-    if (cv && s->n_ns > 0) return 1;   // the control variate is for walk on spheres only
+    if (cv && (s->n_ns > 0 || s->n_mono > 0)) return 1;   // the control variate is for walk on spheres only
     Scene sc(*s);
     const int D = s->dim, N = s->N;
     std::vector<int64_t> st_steps(256, 0);
@@ -1311,7 +1549,7 @@ int oracle_grad(const oracle_scene* s, const double* X, int64_t P, const double*
                 uint64_t seed, int32_t instance, double* grad, double* u_mean,
                 int64_t* steps_total, int threads, const oracle_cv* cv) {
     if (check_scene(s) || W < 1 || P < 0 || check_starts(s, P)) return 1;
-    if (cv && s->n_ns > 0) return 1;   // the control variate is for walk on spheres only
+    if (cv && (s->n_ns > 0 || s->n_mono > 0)) return 1;   // the control variate is for walk on spheres only
     Scene sc(*s);
     const int D = s->dim, N = s->N;
     int T = threads > 0 ? threads : oracle_threads();
@@ -1347,7 +1585,7 @@ int oracle_grad_sqloss(const oracle_scene* s, const double* X, int64_t P, const 
                        double* grad, double* u_mean, int64_t* steps_total, int threads,
                        const oracle_cv* cv) {
     if (check_scene(s) || W < 1 || P < 0 || B < 2 || W % B != 0 || check_starts(s, P)) return 1;
-    if (cv && s->n_ns > 0) return 1;   // the control variate is for walk on spheres only
+    if (cv && (s->n_ns > 0 || s->n_mono > 0)) return 1;   // the control variate is for walk on spheres only
     Scene sc(*s);
     const int D = s->dim, N = s->N;
     int T = threads > 0 ? threads : oracle_threads();
@@ -1448,7 +1686,7 @@ int oracle_walk_records_cv(const oracle_scene* s, const oracle_cv* cv, const dou
                            int64_t P, int32_t W, uint64_t seed, int32_t instance,
                            double* walk, double* nested, int threads) {
     if (check_scene(s) || !cv || W < 1 || P < 0 || check_starts(s, P)) return 1;
-    if (s->n_ns > 0) return 1;   // the control variate is for walk on spheres only
+    if (s->n_ns > 0 || s->n_mono > 0) return 1;   // the control variate is for walk on spheres only
     Scene sc(*s);
     const int D = s->dim, K = s->K;
     parallel_points(P, threads, [&](int, int64_t p) {

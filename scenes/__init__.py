@@ -35,7 +35,7 @@ __all__ = [
     "shell_scene", "annulus_scene", "points_in_disk", "points_on_box_faces",
     "points_in_ball", "vertices_at", "lshape_scene", "half_disk_scene",
     "annulus_reflecting_scene", "points_in_lshape", "points_in_half_disk",
-    "points_on_segments", "thermal_scene",
+    "points_on_segments", "thermal_scene", "monopole_scene", "inflation_scene",
 ]
 
 
@@ -79,6 +79,10 @@ class Scene:
     # with the domain to the left of s (first to second vertex)
     NV: Optional[np.ndarray] = None       # (n_nv, 2) float64
     nsegs: Optional[np.ndarray] = None    # (n_ns, 2) int32
+    # implicit Dirichlet boundary (2D): zero set of
+    # h(x) = mono_c + sum_n a_n / |x - p_n|, rows (a_n, p_n); domain h > 0
+    mono: Optional[np.ndarray] = None     # (n, 3) float64
+    mono_c: float = -1.0
 
     @property
     def nv(self) -> int:
@@ -399,6 +403,30 @@ def thermal_scene(n_slice: int = 65536, n_wire: int = 125, n_modes: int = 8,
                  rowptr=rowptr, pid=np.concatenate(pids), vel=np.concatenate(vels),
                  V_base=np.concatenate(Vb), pi0=coef.copy(), NV=NV,
                  nsegs=_chain(n_slice, closed=True), name=f"thermal{n_slice}")
+
+
+def monopole_scene(mono, c: float = -1.0, sigma: float = 0.0, src_c0: float = 0.0, g=(0.0, None, None),
+                   eps: float = 1e-4, delta: float = 1e-3, K: int = 1) -> Scene:
+    """Implicit boundary of Sec. 7.4: the zero set of
+    h(x) = c + sum_n a_n / |x - p_n| (rows (a_n, p_x, p_y) of mono, a_n > 0,
+    c < 0), domain {h > 0}; restricted data g = (c0, b, A); parameters
+    (a_n, p_n) per monopole."""
+    mono = np.asarray(mono, float).reshape(-1, 3)
+    c0, b, A = g
+    return Scene(dim=2, V=np.zeros((0, 2)), prims=np.zeros((0, 2), np.int32),
+                 label=np.zeros(0, np.int32), bc=[_restricted(c0, b, A, 2)], gvert=np.zeros(0),
+                 sigma=sigma, eps=eps, delta=delta, K=K, src_c0=src_c0, N=3 * len(mono),
+                 mono=mono, mono_c=float(c), pi0=mono.ravel().copy(), name="monopoles")
+
+
+def inflation_scene(n: int = 16, seed: int = 0, c: float = -1.0, eps: float = 1e-3,
+                    delta: float = 1e-2) -> Scene:
+    """Curve inflation (Sec. 7.4): -Lap u = 4, g = 0 inside the zero set of
+    n monopoles with scales a_n ~ U(0.02, 0.06) and positions in
+    [-0.6, 0.6]^2 (seed), c = -1: a blob domain that may split."""
+    rng = np.random.default_rng(seed)
+    mono = np.stack([rng.uniform(0.02, 0.06, n), rng.uniform(-0.6, 0.6, n), rng.uniform(-0.6, 0.6, n)], 1)
+    return monopole_scene(mono, c=c, src_c0=4.0, eps=eps, delta=delta).with_(name=f"inflation{n}")
 
 
 def points_on_segments(NV: np.ndarray, nsegs: np.ndarray, P: int, seed: int, segs=None):
