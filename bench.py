@@ -443,16 +443,140 @@ def run_thermal(args):
     return out
 
 
+# Algorithmic FP32 operations per step of a walk on the implicit boundary of
+# n monopoles: h and grad h (per monopole: 2 differences, squared norm 3,
+# sqrt, a/r, accumulate, a/r^3 with 2 products, 4 for the gradient = 15),
+# eight Newton steps of the direct safe radius counting each |x - p_n| once
+# (per monopole and step: r + d, a/q, add, q^2, a/q^2, add = 6), the nearest
+# pole (1 per monopole), and ~40 for the Harnack radius, roulette, direction
+# and position update.
+def imp_ops_per_step(n):
+    return 15 * n + 8 * 6 * n + n + 40
+
+
+def run_inflation(args):
+    """Curve inflation (Sec. 7.4) on an implicit boundary: 32 harmonic
+    monopoles (c = -1), -Lap u = 4, g = 0, 128 x 128 pixel centres on
+    [-1, 1]^2, W = 4 differential walks per pixel with K = 4 nested walks,
+    eps = 1e-3, delta = 1e-2 (the paper's table row for this example).  One
+    iteration: the band term of the shape derivative over every pixel
+    (band eps_band = 2 pixels, loss 1/2 uref^2 at the zero boundary value),
+    the squared-loss U-statistic gradient over the pixels inside the domain
+    (all W walks of a pixel form one batch), Adam on the 96 monopole
+    coordinates with the scales kept >= 1e-3, and the new monopoles
+    uploaded."""
+    import numpy as np
+    import torch
+    import scenes
+    import paper_2405_12964_amd as dw
+
+    dev = torch.device("cuda:0")
+    side = int(round(math.sqrt(args.points))) if args.points else 128
+    W = args.walks or 4
+    g1 = -1.0 + (np.arange(side) + 0.5) * 2.0 / side
+    X = np.stack(np.meshgrid(g1, g1), -1).reshape(-1, 2)
+    dA = (2.0 / side) ** 2
+    eps_band = 2 * 2.0 / side
+    Xt = torch.tensor(X, dtype=torch.float64, device=dev)
+    target = scenes.inflation_scene(32, seed=1).with_(K=4)
+    start = scenes.inflation_scene(32, seed=2).with_(K=4)
+    ref = dw.Solver.from_scene(target, "fp32")
+    zero = torch.zeros(len(X), dtype=torch.float64, device=dev)
+    _, reg = ref.implicit_band_grad(Xt, zero, eps_band, want_mask=True)
+    inside = torch.nonzero(reg > 0).squeeze(1)
+    uref = torch.zeros(len(X), dtype=torch.float64, device=dev)
+    uref[inside] = ref.solve(Xt[inside].contiguous(), 256, 99)[0]
+    torch.cuda.synchronize()
+    del ref
+    print("reference heightfield done", file=sys.stderr, flush=True)
+    s = dw.Solver.from_scene(start, "fp32")
+    c = start.mono_c
+    pi = torch.tensor(start.mono.ravel(), dtype=torch.float64, device=dev, requires_grad=True)
+    opt = torch.optim.Adam([pi], lr=2e-3)
+    coef = (dA * 0.5 * uref ** 2 / eps_band).contiguous()
+    amin = 1e-3
+
+    def step(i):
+        g, region = s.implicit_band_grad(Xt, coef, eps_band, want_mask=True)
+        idx = torch.nonzero(region == 2).squeeze(1)
+        L, gd, _ = s.grad_sqloss(Xt[idx].contiguous(), uref[idx].contiguous(), W, W, 5000 + i)
+        out = uref[region == 0]
+        loss = dA * (L + 0.5 * (out * out).sum())
+        pi.grad = g + dA * gd
+        opt.step()
+        with torch.no_grad():
+            pi.view(-1, 3)[:, 0].clamp_(min=amin)
+        s.set_implicit(pi.detach().view(-1, 3).cpu().numpy(), c)
+        return loss, len(idx)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    print(f"{args.warmup} warmup iterations done", file=sys.stderr, flush=True)
+    s.walk_timing(1, reset=True)
+    npx = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        loss, n_in = step(args.warmup + i)
+        npx.append(n_in)
+        if i % 50 == 49:
+            print(f"iteration {i + 1} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms1, n1, tot1 = s.walk_timing(1)
+    assert tot1["invalid"] == 0
+    n = len(start.mono)
+    avg_s = ms1 / max(1, n1) / 1e3
+    ops = tot1["steps"] * imp_ops_per_step(n) / max(1, n1)
+    out = {
+        "metric": METRIC, "value": tot1["steps"] / elapsed, "unit": "walk-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"curve inflation on an implicit boundary: {n} harmonic monopoles (c = -1), "
+                               f"-Lap u = 4, g = 0; {side}x{side} pixels on [-1,1]^2, {W} differential walks "
+                               f"per pixel inside the domain (K = 4 nested), squared-loss U-statistic + "
+                               f"band term, Adam on the {3 * n} monopole coordinates",
+                   "pixels": side * side, "walks_per_point": W, "monopoles": n, "params": 3 * n,
+                   "mean_pixels_inside": float(np.mean(npx))},
+        "grad_evals_per_s": args.steps / elapsed,
+        "walk_steps": {"differential": tot1["steps"], "differential_ms": ms1, "walks": tot1["walks"],
+                       "nested_walks": tot1["nested_walks"], "truncated": tot1["truncated"]},
+        "loss": float(loss.item()),
+        "roofline": {"bound": "alu", "achieved": ops / avg_s / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                     "unit": "TFLOP/s", "frac": ops / avg_s / PEAK_FP32_VALU, "traffic": None,
+                     "kernel": "implicit_kernel<float,1>", "avg_launch_ms": ms1 / max(1, n1),
+                     "launches": n1, "ops_per_launch": ops, "ops_per_step": imp_ops_per_step(n),
+                     "steps_per_launch": tot1["steps"] / max(1, n1)},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = min(16, len(os.sched_getaffinity(0)))
+        o = oracle.Oracle(start.with_(mono=pi.detach().view(-1, 3).cpu().numpy()), threads=threads)
+        reg = s.implicit_band_grad(Xt, coef, eps_band, want_mask=True)[1].cpu().numpy()
+        sel = np.nonzero(reg == 2)[0][:8192]
+        Wc = 256
+        t0 = time.perf_counter()
+        _, _, _, st = o.grad_sqloss(X[sel], uref.cpu().numpy()[sel], Wc, 4, 7)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": st / dt, "unit": "walk-steps/s", "cores": threads, "kind": "oracle",
+                               "sample": f"{len(sel)} pixels inside the domain x {Wc} differential walks "
+                                         f"(K = 4 nested, batches of 4) at the final monopoles, squared-loss "
+                                         f"U-statistic, brute-force FP64, {dt:.1f} s"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", choices=["c2", "c4", "c5", "c5ls", "thermal"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c4", "c5", "c5ls", "thermal", "inflation"], default="c2",
                     help="c2: 2D star (the reported configuration); c4: batched instances; c5: 3D "
                          "shape from diffusion with the learned control variate; c5ls: 3D shape from "
                          "diffusion with vertex parameters and the preconditioned vector Adam; "
-                         "thermal: walk on stars with a reflecting boundary")
+                         "thermal: walk on stars with a reflecting boundary; inflation: curve inflation "
+                         "on an implicit boundary of harmonic monopoles")
     ap.add_argument("--points", type=int, default=0)
     ap.add_argument("--walks", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -484,6 +608,11 @@ def main():
         args.steps = 5 if args.steps is None else args.steps
         args.warmup = 2 if args.warmup is None else args.warmup
         print(json.dumps(run_thermal(args)), flush=True)
+        return
+    if args.workload == "inflation":
+        args.steps = 150 if args.steps is None else args.steps
+        args.warmup = 10 if args.warmup is None else args.warmup
+        print(json.dumps(run_inflation(args)), flush=True)
         return
     if args.workload == "c5":
         args.steps = 50 if args.steps is None else args.steps

@@ -440,6 +440,58 @@ dwos_status dwos_eval_reflect_weight(dwos_ctx* ctx, const double* r, const doubl
                                      double sigma, double* w);
 
 /* ---------------------------------------------------------------------------
+ * Implicit boundaries from harmonic monopoles (2D; Sec. 7.4, "Image-space
+ * curve inflation").  The boundary is the zero set of
+ *   h(x) = c + sum_n a_n / |x - p_n|,   c < 0, every a_n > 0,
+ * and the domain is {h > 0} (the points nearer the monopoles).  The
+ * parameters are pi = (a_0, p_0x, p_0y, a_1, ...) (N = 3n), and their
+ * normal velocity is the level-set one of Sec. 3.1,
+ * eq. (normal_velocity): V_n = (dh/dpi) / |grad h|.
+ * Each step of Algorithm 1 and Algorithm 2 takes a safe disk instead of the
+ * largest empty one: the larger of the Harnack radius of h - c (a positive
+ * harmonic function of 3D space, with the poles at the p_n) and the radius
+ * at which sum_n a_n / (|x - p_n| + d) falls to -c.  A walk stops when
+ * h <= |grad h| eps where h < -c (the gradient-sensitive shell; the second
+ * condition keeps the test from firing next to a pole), and takes the
+ * boundary value at the Newton projection xbar = x - h grad h / |grad h|^2.
+ * The boundary data are the restricted data of label 0 (dwos_set_problem,
+ * kind 0); the outward normal at xbar is -grad h / |grad h|.  The random
+ * numbers and step order are those of the walk-on-spheres kernel.
+ * Every solve / grad / grad_sqloss / jvp / walk_records call then walks on
+ * the implicit boundary and differentiates with respect to the 3n monopole
+ * parameters (dwos_set_parameters is not used).  A context holds either a
+ * mesh boundary or an implicit one; reflecting boundaries, the control
+ * variate and batch contexts are not available with it (ESTATE).
+ * ------------------------------------------------------------------------- */
+
+/* Implicit boundary of n monopoles (host, n x 3 FP64: a_n, p_nx, p_ny) and
+ * the constant c; n = 0 removes it.  The table is copied (converted to the
+ * working precision); the call returns once the copy is done.
+ * Errors: EINVAL (3D context, n > 1024, a_n <= 0, c >= 0, non-finite
+ * values), ESTATE (mesh or reflecting boundary, attached control variate,
+ * batch context), ENOMEM. */
+dwos_status dwos_set_implicit(dwos_ctx* ctx, const double* mono, int64_t n, double c);
+
+/* The band term of the shape-functional derivative on an implicit boundary
+ * (Sec. 7.4, "Implicit boundary integrals"): the boundary integral of
+ * eq. (functional_deriv) taken as a volume integral over the band of the
+ * domain next to the boundary.  For every point x_p (device, P x 2 FP64)
+ * in the band, adds coef_p V_n(x_p) to grad (device, 3n FP64, accumulated,
+ * not cleared):
+ *   grad_j += coef_p (dh/dpi_j)(x_p) / |grad h(x_p)|.
+ * The band is h > 0, h < eps_band |grad h| and h < -c, i.e. the first-order
+ * distance h / |grad h| to the zero set is below eps_band (away from the
+ * poles).  The caller folds its quadrature weight, the loss at x_p and the
+ * band normalisation into coef (device, P FP64).  region (device, P int32)
+ * receives, if non-null, 1 for the points in the band, 2 for the other
+ * points of the domain (h > 0) and 0 for the points outside, so that the
+ * domain term can take the points labelled 2.
+ * Errors: EINVAL (bad arguments, eps_band <= 0), ESTATE (no implicit
+ * boundary). */
+dwos_status dwos_implicit_band_grad(dwos_ctx* ctx, const double* X, int64_t P, const double* coef,
+                                    double eps_band, double* grad, int32_t* region);
+
+/* ---------------------------------------------------------------------------
  * Shape-optimisation step for mesh vertices (the optimiser of the paper's
  * experiments, Sec. 6 "Implementation and evaluation" and Sec. 7.2
  * "Gradient preconditioning"): vector Adam (second moment per vertex from

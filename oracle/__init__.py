@@ -303,6 +303,20 @@ class Oracle:
         assert rc == 0
         return float(out[1 if harnack else 0])
 
+    def band_grad(self, X, coef, eps_band):
+        """Band term on an implicit boundary: (sum over the points in the band
+        of coef_p (dh/dpi)/|grad h|, region per point: 1 band, 2 rest of the
+        domain, 0 outside)."""
+        X = self._X(X)
+        coef = np.ascontiguousarray(coef, dtype=np.float64)
+        g = np.zeros(3 * len(self.scene.mono))
+        m = np.zeros(len(X), np.int32)
+        rc = lib().oracle_band_grad(C.byref(self._s), _ptr(X, C.c_double), C.c_int64(len(X)),
+                                    _ptr(coef, C.c_double), C.c_double(eps_band), _ptr(g, C.c_double),
+                                    _ptr(m, C.c_int32))
+        assert rc == 0
+        return g, m
+
     def walk_records_cv(self, X, W, seed, cv, instance=0):
         """Differential walks with the control variate: per-walk records
         (run, xoff, uoff plain, uoff_cv, target, u, prim) and per nested walk

@@ -1418,6 +1418,33 @@ int oracle_safe_radius(const oracle_scene* s, const double* x, double* out) {
     return 0;
 }
 
+// Band term of the shape-functional derivative on an implicit boundary
+// (Sec. 7.4, implicit boundary integrals): the boundary integral of
+// eq. (functional_deriv) becomes a volume integral over the points of the
+// domain next to the zero set.  A point is in the band when h > 0 and its
+// first-order distance h / |grad h| to the zero set is below eps_band (and
+// h < -c, away from the poles); each such point adds coef_p times the normal
+// velocity (dh/dpi) / |grad h| of eq. (normal_velocity) to grad (3n values,
+// accumulated).  region (may be NULL) receives per point 1 in the band, 2
+// elsewhere in the domain (h > 0), 0 outside.
+int oracle_band_grad(const oracle_scene* s, const double* X, int64_t P, const double* coef, double eps_band,
+                     double* grad, int32_t* region) {
+    if (check_scene(s) || s->n_mono <= 0 || !(eps_band > 0) || P < 0) return 1;
+    Scene sc(*s);
+    std::vector<double> dh(3 * s->n_mono);
+    for (int64_t p = 0; p < P; ++p) {
+        double gr[2];
+        const double h = sc.hval(X + 2 * p, gr);
+        const double gn = std::hypot(gr[0], gr[1]);
+        const bool band = h > 0 && h < eps_band * gn && h < -s->mono_c;
+        if (region) region[p] = band ? 1 : (h > 0 ? 2 : 0);
+        if (!band) continue;
+        sc.hparam(X + 2 * p, dh.data());
+        for (int j = 0; j < 3 * s->n_mono; ++j) grad[j] += coef[p] * dh[j] / gn;
+    }
+    return 0;
+}
+
 double oracle_neumann_weight(int dim, double sigma, double r, double R) {
     return neumann_weight(dim, sigma, r, R);
 }

@@ -96,6 +96,8 @@ def lib():
             "dwos_set_start_segments": [vp, i32p, C.c_int64],
             "dwos_reflect_query": [vp, vp, vp, vp, vp, vp, C.c_int64, vp],
             "dwos_eval_reflect_weight": [vp, vp, vp, C.c_int64, C.c_double, vp],
+            "dwos_set_implicit": [vp, dp, C.c_int64, C.c_double],
+            "dwos_implicit_band_grad": [vp, vp, C.c_int64, vp, C.c_double, vp, vp],
             "dwos_opt_create": [C.c_int32, C.c_int64, i32p, C.c_int64, i32p, C.c_double, vp, C.POINTER(vp)],
             "dwos_opt_reset": [vp, vp],
             "dwos_opt_step": [vp, vp, vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32,
@@ -128,6 +130,7 @@ EXPORTED = [
     "dwos_mlp_set_params", "dwos_mlp_get_params", "dwos_mlp_eval", "dwos_mlp_loss_grad",
     "dwos_mlp_vjp", "dwos_mlp_adam_step", "dwos_cv_attach", "dwos_cv_beta", "dwos_cv_train", "dwos_cv_walk_records",
     "dwos_set_reflecting", "dwos_set_start_segments", "dwos_reflect_query", "dwos_eval_reflect_weight",
+    "dwos_set_implicit", "dwos_implicit_band_grad",
     "dwos_opt_create", "dwos_opt_destroy", "dwos_opt_reset", "dwos_opt_step", "dwos_opt_solve",
 ]
 

@@ -21,6 +21,7 @@
 #include "mlp.hpp"
 #include "bvh.hpp"
 #include "wost_kernels.hpp"
+#include "implicit_kernels.hpp"
 
 namespace {
 
@@ -96,6 +97,13 @@ struct dwos_ctx {
     DevBuf ref_nodes, ref_geo, ref_info, ref_leaf_of, ref_cones;
     DevBuf start_seg;             // per query point: reflecting segment or -1
     int64_t start_n = 0;          // points covered by start_seg (0: none)
+    // implicit boundary (2D): zero set of c + sum_n a_n / |x - p_n|
+    bool has_imp = false;
+    int64_t imp_n = 0;
+    double imp_c = 0.0;
+    DevBuf imp_mono;              // n x 3 in the working precision
+    DevBuf imp_xbar, imp_s, imp_coef;   // per-walk terminal data and reverse-mode weights
+    DevBuf imp_bx, imp_bs;              // band points and their 1/|grad h|
 };
 
 namespace {
@@ -665,9 +673,11 @@ dwos_status set_single_instance(dwos_ctx* c, int64_t p0, int64_t P, int32_t W) {
 
 dwos_status begin_call(dwos_ctx* c, bool need_params) {
     if (!c) return fail(DWOS_EINVAL, "NULL context");
-    if (!c->has_boundary) return fail(DWOS_ESTATE, "no boundary: call dwos_set_boundary first");
+    if (!c->has_boundary && !c->has_imp)
+        return fail(DWOS_ESTATE, "no boundary: call dwos_set_boundary (or dwos_set_implicit) first");
     if (!c->has_problem) return fail(DWOS_ESTATE, "no problem: call dwos_set_problem first");
-    if (need_params && !c->has_params) return fail(DWOS_ESTATE, "no parameters: call dwos_set_parameters first");
+    if (need_params && !c->has_params && !c->has_imp)
+        return fail(DWOS_ESTATE, "no parameters: call dwos_set_parameters first");
     HIP_OK(hipSetDevice(c->device));
     HIP_OK(c->counters.reserve(sizeof(dwos::Counters)));
     hipLaunchKernelGGL(dwos::fill_u64_kernel, dim3(1), dim3(64), 0, c->stream,
@@ -881,7 +891,127 @@ dwos_status run_op(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
     return finish_call(c, st, ev_from);
 }
 
+// Launch the persistent implicit-boundary walk kernel (2D).
+template <class T, int MODE>
+dwos_status launch_imp(dwos_ctx* c, dwos::WalkArgs<T>& a) {
+    hipStream_t s = c->stream;
+    a.tot = c->totals.as<dwos::Counters>() + MODE;
+    hipLaunchKernelGGL(dwos::fill_u64_kernel, dim3(1), dim3(64), 0, s, a.queue, (int64_t)1);
+    constexpr int block = dwos::kBlock;
+    auto kern = dwos::implicit_kernel<T, MODE>;
+    const size_t lds = (size_t)std::max<int64_t>(c->imp_n, dwos::kImpRegs) * 3 * sizeof(T);
+    int per = 0;
+    HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, block, lds));
+    per = std::max(1, per);
+    const int64_t need = (a.total + block - 1) / block;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)per * c->cu_count));
+    dwos::ImpArgs<T> im{};
+    im.mono = c->imp_mono.as<T>();
+    im.n = (int32_t)c->imp_n;
+    im.c = T(c->imp_c);
+    im.xbar = c->imp_xbar.as<T>();
+    im.s = c->imp_s.as<T>();
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_OK(hipStreamIsCapturing(s, &cap));
+    if (cap != hipStreamCaptureStatusNone) {
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, a, im);
+        HIP_OK(hipGetLastError());
+        return DWOS_OK;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    HIP_OK(hipEventRecord(e0, s));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, a, im);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipEventRecord(e1, s));
+    c->pending.push_back({e0, e1, MODE});
+    if (c->pending.size() > 4096) {
+        dwos_status st = drain_events(c, nullptr, c->pending.size());
+        if (st) return st;
+    }
+    return DWOS_OK;
+}
+
+// The driver for an implicit boundary: the same chunking, records and
+// per-point statistics as run_op; the parameters are the 3n monopole
+// coordinates (a_n, p_n), so forward and reverse mode reduce the per-walk
+// terminal data (xbar, s) with imp_jvp_kernel and imp_grad_kernel.
+template <class T>
+dwos_status run_imp(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
+    const bool diff = op != Op::Solve && !(op == Op::Records && o.mode == 0);
+    const int64_t P = o.P;
+    const int32_t W = o.W;
+    hipStream_t s = c->stream;
+    if (c->cv) return fail(DWOS_ESTATE, "the control variate is not supported on an implicit boundary");
+    if (c->prob.bc[0].kind != 0)
+        return fail(DWOS_ESTATE, "an implicit boundary takes restricted (quadratic) boundary data of label 0");
+    const int64_t chunk_pts = std::max<int64_t>(1, kMaxWalksPerChunk / W);
+    const int64_t max_walks = std::max<int64_t>(1, std::min<int64_t>(P, chunk_pts) * W);
+    dwos_status rc = ensure_records<T>(c, max_walks, diff, op == Op::Records);
+    if (rc) return rc;
+    const bool needA = op == Op::Grad || op == Op::SqLoss;
+    if (diff) {
+        HIP_OK(c->imp_xbar.reserve(max_walks * 2 * sizeof(T)));
+        HIP_OK(c->imp_s.reserve(max_walks * sizeof(T)));
+    }
+    if (needA) {
+        HIP_OK(c->imp_coef.reserve(max_walks * sizeof(double)));
+        hipLaunchKernelGGL(dwos::fill_f64_kernel, dim3(blocks_for(c->N, 256)), dim3(256), 0, s, o.grad, c->N);
+    }
+    const size_t ev_from = c->pending.size();
+    const int32_t n = (int32_t)c->imp_n;
+    for (int64_t p0 = 0; p0 < P; p0 += chunk_pts) {
+        const int64_t Pc = std::min(chunk_pts, P - p0);
+        const int64_t walks = Pc * W;
+        rc = set_single_instance<T>(c, p0, Pc, W);
+        if (rc) return rc;
+        dwos::WalkArgs<T> a = base_args<T>(c, o.X, W, o.seed);
+        a.inst = c->instbuf.as<dwos::Instance<T>>();
+        a.n_inst = 1;
+        a.total = walks;
+        a.wid_offset = 0;
+        a.x_base = p0;
+        a.rec_steps = op == Op::Records ? c->rec_steps.as<int64_t>() : nullptr;
+        rc = diff ? launch_imp<T, 1>(c, a) : launch_imp<T, 0>(c, a);
+        if (rc) return rc;
+        if (o.u_mean) {
+            hipLaunchKernelGGL(dwos::point_stats_kernel<T>, dim3(blocks_for(Pc, 4)), dim3(256), 0, s,
+                               c->rec_u.as<T>(), Pc, W, o.u_mean + p0, o.u_var ? o.u_var + p0 : nullptr);
+        }
+        if (needA) {
+            hipLaunchKernelGGL(dwos::imp_coef_kernel<T>, dim3(blocks_for(walks, 256)), dim3(256), 0, s,
+                               c->rec_u.as<T>(), c->rec_prim.as<int32_t>(), walks, W,
+                               op == Op::SqLoss ? o.B : 1, op == Op::Grad ? 0 : 1, p0, o.w, o.uref,
+                               c->imp_coef.as<double>());
+            hipLaunchKernelGGL(dwos::imp_grad_kernel<T>, dim3(blocks_for(walks, dwos::kImpTile)), dim3(256), 0, s,
+                               c->imp_xbar.as<T>(), c->imp_s.as<T>(), c->imp_coef.as<double>(), walks,
+                               c->imp_mono.as<T>(), n, o.grad);
+        }
+        if (op == Op::Jvp || (op == Op::Records && diff && o.rec_udot_out)) {
+            hipLaunchKernelGGL(dwos::imp_jvp_kernel<T>, dim3((unsigned)Pc), dim3(64), 0, s, c->rec_prim.as<int32_t>(),
+                               c->imp_xbar.as<T>(), c->imp_s.as<T>(), c->imp_mono.as<T>(), n, Pc, W, p0,
+                               op == Op::Jvp ? o.udot : nullptr, op == Op::Jvp ? o.udot_var : nullptr,
+                               op == Op::Records ? o.rec_udot_out + p0 * W * c->N : nullptr);
+        }
+        if (op == Op::Records) {
+            hipLaunchKernelGGL(copy_records_kernel<T>, dim3(blocks_for(walks, 256)), dim3(256), 0, s,
+                               c->rec_u.as<T>(), diff ? c->rec_prim.as<int32_t>() : nullptr,
+                               diff ? c->rec_uoff.as<T>() : nullptr, walks, p0 * W, o.rec_u_out,
+                               o.rec_prim_out, o.rec_uoff_out, diff ? 1 : 0);
+            if (o.rec_steps_out)
+                hipLaunchKernelGGL(copy_steps_kernel, dim3(blocks_for(walks, 256)), dim3(256), 0, s,
+                                   c->rec_steps.as<int64_t>(), walks, p0 * W, o.rec_steps_out);
+        }
+    }
+    if (op == Op::SqLoss && o.loss) {
+        hipLaunchKernelGGL(dwos::sqloss_kernel, dim3(1), dim3(256), 0, s, o.u_mean, o.uref, P, o.loss);
+    }
+    return finish_call(c, st, ev_from);
+}
+
 dwos_status dispatch(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
+    if (c->has_imp) return c->prec == DWOS_FP32 ? run_imp<float>(c, op, o, st) : run_imp<double>(c, op, o, st);
     if (c->prec == DWOS_FP32) {
         return c->D == 2 ? run_op<float, 2>(c, op, o, st) : run_op<float, 3>(c, op, o, st);
     }
@@ -937,6 +1067,7 @@ dwos_status dwos_set_boundary(dwos_ctx* c, const double* V, int64_t nv, const in
     if (!c) return fail(DWOS_EINVAL, "NULL context");
     const int D = c->D;
     if (!c->instances.empty()) return fail(DWOS_ESTATE, "set_boundary: context is a batch context");
+    if (c->has_imp) return fail(DWOS_ESTATE, "set_boundary: context has an implicit boundary");
     dwos_status rc = check_geometry(D, V, nv, prims, np, label, DWOS_MAX_LABELS);
     if (rc) return rc;
     HIP_OK(hipSetDevice(c->device));
@@ -1351,6 +1482,7 @@ dwos_status dwos_set_reflecting(dwos_ctx* c, const double* V, int64_t nv, const 
     }
     if (c->D != 2) return fail(DWOS_EINVAL, "set_reflecting: reflecting boundaries are supported in 2D only");
     if (!c->instances.empty()) return fail(DWOS_ESTATE, "set_reflecting: context is a batch context");
+    if (c->has_imp) return fail(DWOS_ESTATE, "set_reflecting: context has an implicit boundary");
     dwos_status rc = check_geometry(2, V, nv, segs, ns, nullptr, 1);
     if (rc) return fail(rc, "set_reflecting: " + dwos_host::g_last_error.substr(std::min<size_t>(14, dwos_host::g_last_error.size())));
     std::vector<std::vector<int32_t>> inc(nv);
@@ -1420,6 +1552,69 @@ dwos_status dwos_eval_reflect_weight(dwos_ctx* c, const double* r, const double*
                                r, R, n, T(kappa), w);
     };
     if (c->prec == DWOS_FP32) run(float{}); else run(double{});
+    HIP_OK(hipGetLastError());
+    return DWOS_OK;
+}
+
+dwos_status dwos_set_implicit(dwos_ctx* c, const double* mono, int64_t n, double cconst) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (n == 0) {   // back to no boundary
+        c->has_imp = false;
+        c->imp_n = 0;
+        c->N = 0;
+        return DWOS_OK;
+    }
+    if (c->D != 2) return fail(DWOS_EINVAL, "set_implicit: implicit boundaries are supported in 2D only");
+    if (n < 0 || n > dwos::kMaxMono) return fail(DWOS_EINVAL, "set_implicit: n must be in 0..1024");
+    if (!mono) return fail(DWOS_EINVAL, "set_implicit: NULL monopoles");
+    if (!(cconst < 0) || !std::isfinite(cconst)) return fail(DWOS_EINVAL, "set_implicit: c must be finite and < 0");
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(mono[3 * i] > 0) || !std::isfinite(mono[3 * i]))
+            return fail(DWOS_EINVAL, "set_implicit: scale a_" + std::to_string(i) + " must be finite and > 0");
+        if (!std::isfinite(mono[3 * i + 1]) || !std::isfinite(mono[3 * i + 2]))
+            return fail(DWOS_EINVAL, "set_implicit: non-finite position of monopole " + std::to_string(i));
+    }
+    if (c->has_boundary) return fail(DWOS_ESTATE, "set_implicit: context has a mesh boundary");
+    if (c->has_ref) return fail(DWOS_ESTATE, "set_implicit: context has a reflecting boundary");
+    if (c->cv) return fail(DWOS_ESTATE, "set_implicit: a control variate is attached");
+    if (!c->instances.empty()) return fail(DWOS_ESTATE, "set_implicit: context is a batch context");
+    HIP_OK(hipSetDevice(c->device));
+    if (c->prec == DWOS_FP32) {
+        std::vector<float> h(mono, mono + 3 * n);
+        HIP_OK(upload(c->imp_mono, h.data(), h.size(), c->stream));
+    } else {
+        HIP_OK(upload(c->imp_mono, mono, (size_t)(3 * n), c->stream));
+    }
+    c->has_imp = true;
+    c->imp_n = n;
+    c->imp_c = cconst;
+    c->N = 3 * n;
+    return DWOS_OK;
+}
+
+dwos_status dwos_implicit_band_grad(dwos_ctx* c, const double* X, int64_t P, const double* coef, double eps_band,
+                                    double* grad, int32_t* region) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (!c->has_imp) return fail(DWOS_ESTATE, "implicit_band_grad: no implicit boundary");
+    if (P < 0 || (P > 0 && (!X || !coef)) || !grad) return fail(DWOS_EINVAL, "implicit_band_grad: bad arguments");
+    if (!(eps_band > 0) || !std::isfinite(eps_band)) return fail(DWOS_EINVAL, "implicit_band_grad: eps_band must be > 0");
+    if (P == 0) return DWOS_OK;
+    HIP_OK(hipSetDevice(c->device));
+    auto run = [&](auto tag) -> dwos_status {
+        using T = decltype(tag);
+        HIP_OK(c->imp_bx.reserve(P * 2 * sizeof(T)));
+        HIP_OK(c->imp_bs.reserve(P * sizeof(T)));
+        HIP_OK(c->imp_coef.reserve(P * sizeof(double)));
+        hipLaunchKernelGGL(dwos::imp_band_kernel<T>, dim3(blocks_for(P, 256)), dim3(256), 0, c->stream, X, P, coef,
+                           c->imp_mono.as<T>(), (int32_t)c->imp_n, T(c->imp_c), T(eps_band), c->imp_bx.as<T>(),
+                           c->imp_bs.as<T>(), c->imp_coef.as<double>(), region);
+        hipLaunchKernelGGL(dwos::imp_grad_kernel<T>, dim3(blocks_for(P, dwos::kImpTile)), dim3(256), 0, c->stream,
+                           c->imp_bx.as<T>(), c->imp_bs.as<T>(), c->imp_coef.as<double>(), P, c->imp_mono.as<T>(),
+                           (int32_t)c->imp_n, grad);
+        return DWOS_OK;
+    };
+    dwos_status rc = c->prec == DWOS_FP32 ? run(float{}) : run(double{});
+    if (rc) return rc;
     HIP_OK(hipGetLastError());
     return DWOS_OK;
 }
@@ -1502,6 +1697,7 @@ dwos_status dwos_batch_add_instance(dwos_ctx* c, const double* V, int64_t nv, co
                                     const int32_t* label, double sigma, double eps, double delta, int32_t* index) {
     if (!c) return fail(DWOS_EINVAL, "NULL context");
     if (c->has_ref) return fail(DWOS_ESTATE, "batch_add_instance: context has a reflecting boundary");
+    if (c->has_imp) return fail(DWOS_ESTATE, "batch_add_instance: context has an implicit boundary");
     const int D = c->D;
     dwos_status rc = check_geometry(D, V, nv, prims, np, label, DWOS_MAX_LABELS);
     if (rc) return rc;

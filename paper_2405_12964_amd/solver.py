@@ -160,16 +160,42 @@ class Solver:
         check(capi.dwos_eval_reflect_weight(self._ctx, _dev(r), _dev(R), r.numel(), float(sigma), _dev(w)))
         return w
 
+    def set_implicit(self, mono, c):
+        """Implicit boundary: the zero set of c + sum_n a_n / |x - p_n| (rows
+        (a_n, p_nx, p_ny) of ``mono``); the parameters become the 3n monopole
+        coordinates.  An empty ``mono`` removes it."""
+        mono = np.ascontiguousarray(mono, dtype=np.float64).reshape(-1, 3)
+        check(capi.dwos_set_implicit(self._ctx, _dp(mono), mono.shape[0], float(c)))
+        self.N = 3 * mono.shape[0]
+
+    def implicit_band_grad(self, X, coef, eps_band, grad=None, want_mask=False):
+        """Adds, over the points of X in the band next to the implicit
+        boundary (first-order distance h/|grad h| below eps_band), coef_p
+        times the normal velocity (dh/dpi)/|grad h| at the point to ``grad``
+        (a new zero vector if None).  Returns grad, or (grad, region) with
+        region 1 in the band, 2 elsewhere in the domain, 0 outside."""
+        X = self._X(X)
+        if grad is None:
+            grad = torch.zeros(self.N, dtype=torch.float64, device=X.device)
+        mask = torch.empty(X.shape[0], dtype=torch.int32, device=X.device) if want_mask else None
+        check(capi.dwos_implicit_band_grad(self._ctx, _dev(X), X.shape[0], _dev(coef), float(eps_band), _dev(grad),
+                                           _dev(mask, torch.int32) if mask is not None else None))
+        return (grad, mask) if want_mask else grad
+
     @classmethod
     def from_scene(cls, scene, precision: str = "fp32", V=None, stream=None) -> "Solver":
         """Configure from a scene description (attributes as in ``scenes.Scene``)."""
         s = cls(scene.dim, precision, stream)
-        s.set_boundary(scene.V if V is None else V, scene.prims, scene.label, scene.gvert)
+        mono = getattr(scene, "mono", None)
+        if mono is not None and len(mono) > 0:
+            s.set_implicit(mono, scene.mono_c)
+        else:
+            s.set_boundary(scene.V if V is None else V, scene.prims, scene.label, scene.gvert)
         if getattr(scene, "nsegs", None) is not None and len(scene.nsegs) > 0:
             s.set_reflecting(scene.NV, scene.nsegs)
         s.set_problem(make_problem(scene.sigma, scene.eps, scene.delta, scene.K, scene.kmax,
                                    scene.rr, scene.src_c0, scene.gauss, scene.bc, scene.dim))
-        if scene.N > 0 and scene.rowptr is not None:
+        if scene.N > 0 and scene.rowptr is not None and (mono is None or len(mono) == 0):
             s.set_parameters(scene.N, scene.rowptr, scene.pid, scene.vel, scene.bc_pid)
         return s
 

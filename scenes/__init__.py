@@ -422,10 +422,12 @@ def monopole_scene(mono, c: float = -1.0, sigma: float = 0.0, src_c0: float = 0.
 def inflation_scene(n: int = 16, seed: int = 0, c: float = -1.0, eps: float = 1e-3,
                     delta: float = 1e-2) -> Scene:
     """Curve inflation (Sec. 7.4): -Lap u = 4, g = 0 inside the zero set of
-    n monopoles with scales a_n ~ U(0.02, 0.06) and positions in
+    n monopoles with scales a_n ~ U(0.02, 0.06) * 16 / n (their sum stays
+    near 0.64, so the far-field zero set has radius ~0.64) and positions in
     [-0.6, 0.6]^2 (seed), c = -1: a blob domain that may split."""
     rng = np.random.default_rng(seed)
-    mono = np.stack([rng.uniform(0.02, 0.06, n), rng.uniform(-0.6, 0.6, n), rng.uniform(-0.6, 0.6, n)], 1)
+    mono = np.stack([rng.uniform(0.02, 0.06, n) * 16.0 / n, rng.uniform(-0.6, 0.6, n),
+                     rng.uniform(-0.6, 0.6, n)], 1)
     return monopole_scene(mono, c=c, src_c0=4.0, eps=eps, delta=delta).with_(name=f"inflation{n}")
 
 

@@ -184,3 +184,52 @@ def test_restricted_harmonic_data_has_zero_derivative(oracle_mod):
     jm, jv, _, _ = oracle_mod.Oracle(sc).jvp(X, 4096, 17)
     for j in range(3):
         check_vs_exact(jm[:, j], _se(jv[:, j]), np.zeros(len(X)), 0.02, f"harmonic data d/dpi_{j}")
+
+
+def _grid(lo, hi, n):
+    g1 = lo + (np.arange(n) + 0.5) * (hi - lo) / n
+    X = np.stack(np.meshgrid(g1, g1), -1).reshape(-1, 2)
+    return X, ((hi - lo) / n) ** 2
+
+
+def test_band_term_is_the_area_derivative_of_a_disk(oracle_mod):
+    """Reynolds transport with integrand 1: d(area)/dpi is the boundary
+    integral of V_n.  One monopole: the domain is the disk of radius
+    r0 = a/|c|, so d(area)/da = 2 pi r0 / |c| and d(area)/dp = 0; the band
+    sum (1/eps) sum_band V_n dA approaches it as eps -> 0 (the first-order
+    band h/|grad h| < eps is r (r0 - r)/r0 < eps, width ~eps)."""
+    a, c, p = 0.5, -1.0, (0.05, -0.1)
+    r0 = a / -c
+    X, dA = _grid(-0.6, 0.6, 1200)
+    o = oracle_mod.Oracle(scenes.monopole_scene([[a, *p]], c=c))
+    for eps in (0.02, 0.005):
+        g, m = o.band_grad(X, np.full(len(X), dA / eps), eps)
+        exact = 2 * np.pi * r0 / -c
+        assert abs(g[0] - exact) < (1.5 * eps / r0 + 0.003) * exact, (eps, g[0], exact)
+        assert np.all(np.abs(g[1:]) < 0.003 * exact), g
+        # the band is the annulus r (r0 - r)/r0 < eps inside the disk
+        r = np.hypot(X[:, 0] - p[0], X[:, 1] - p[1])
+        inner = r0 / 2 + np.sqrt(r0 ** 2 / 4 - eps * r0)
+        away = (np.abs(r - inner) > 1e-3) & (np.abs(r - r0) > 1e-3)
+        assert np.array_equal(m[away], np.where((r > inner) & (r < r0), 1, np.where(r < r0, 2, 0))[away])
+
+
+def test_band_term_matches_finite_differences_of_a_weighted_area(oracle_mod):
+    """Two overlapping monopoles, J = integral over the domain of
+    f(x) = 1 + x + y^2: dJ/dpi (boundary integral of V_n f) against central
+    differences of J counted on the same grid."""
+    mono = np.array([[0.3, -0.25, 0.0], [0.25, 0.25, 0.05]])
+    c = -1.0
+    X, dA = _grid(-0.9, 0.9, 1800)
+    f = 1 + X[:, 0] + X[:, 1] ** 2
+    eps = 0.004
+    g, _ = oracle_mod.Oracle(scenes.monopole_scene(mono, c=c)).band_grad(X, f * dA / eps, eps)
+    hh = 4e-3
+    for j in range(6):
+        mp, mm = mono.copy(), mono.copy()
+        mp.ravel()[j] += hh
+        mm.ravel()[j] -= hh
+        Jp = np.sum(f * (_h(mp, c, X) > 0)) * dA
+        Jm = np.sum(f * (_h(mm, c, X) > 0)) * dA
+        fd = (Jp - Jm) / (2 * hh)
+        assert abs(g[j] - fd) < 0.03 * np.abs(g).max(), (j, g[j], fd)
