@@ -461,7 +461,9 @@ dwos_status dwos_eval_reflect_weight(dwos_ctx* ctx, const double* r, const doubl
  * the implicit boundary and differentiates with respect to the 3n monopole
  * parameters (dwos_set_parameters is not used).  A context holds either a
  * mesh boundary or an implicit one; reflecting boundaries, the control
- * variate and batch contexts are not available with it (ESTATE).
+ * variate and batch contexts are not available with it (ESTATE).  A walk
+ * that lands exactly on a monopole's position (where h is not defined) ends
+ * with a NaN result and counts as invalid in dwos_stats.
  * ------------------------------------------------------------------------- */
 
 /* Implicit boundary of n monopoles (host, n x 3 FP64: a_n, p_nx, p_ny) and

@@ -384,20 +384,26 @@ template <class T> struct TravStack<T, true> {
 // every lane holds a leaf or has finished, then test the held leaves
 // together, so that node and primitive work are not interleaved within one
 // iteration.
-// The traversal stack's most recent entry is kept in registers (tnode,
-// tdist); a push moves the previous one to the stack memory only when it is
-// still there, and a pop reads memory only when it is not.  Depth-first
-// descent alternates pushes and pops, so most entries never reach memory.
+// The traversal stack's kStackRegs most recent entries are kept in
+// registers (rn, rd; rn[0] the newest); a push moves the oldest of them to
+// the stack memory only when all are in use, and a pop reads memory only
+// when none is left.  Depth-first descent alternates pushes and pops, so
+// most entries never reach memory (the stack's order is unchanged).
+#ifndef DWOS_STACK_REGS
+#define DWOS_STACK_REGS 2
+#endif
+constexpr int kStackRegs = DWOS_STACK_REGS;
 template <class T>
 struct Query {
     T best;          // squared distance of the best primitive so far
-    T tdist;         // register-held top entry: squared bound distance
     int32_t bleaf;   // its leaf position, -1 none
     int32_t node;    // internal node to expand next, or -1 (pop)
     int32_t leaf;    // held leaf reference
     int32_t sp;      // entries in stack memory
-    int32_t tnode;   // register-held top entry: node reference
-    bool has_leaf, done, top;
+    int32_t rt;      // register-held entries in use
+    int32_t rn[kStackRegs];   // register-held entries: node reference
+    T rd[kStackRegs];         // ... and squared bound distance
+    bool has_leaf, done;
 };
 
 template <class T, int D>
@@ -430,7 +436,7 @@ __device__ __forceinline__ void query_begin(const Scene<T>& s, const StageView& 
     q.sp = 0;
     q.has_leaf = false;
     q.done = false;
-    q.top = false;
+    q.rt = 0;
 }
 
 // One round for the lanes with `active` set (a query in progress).
@@ -444,10 +450,12 @@ __device__ __forceinline__ void query_round(const Scene<T>& s, const StageView& 
         int32_t cur = q.node;
         if (cur < 0) {
             T dd;
-            if (q.top) {
-                cur = q.tnode;
-                dd = q.tdist;
-                q.top = false;
+            if (q.rt > 0) {
+                cur = q.rn[0];
+                dd = q.rd[0];
+#pragma unroll
+                for (int i = 0; i + 1 < kStackRegs; ++i) { q.rn[i] = q.rn[i + 1]; q.rd[i] = q.rd[i + 1]; }
+                --q.rt;
             } else {
                 if (q.sp == 0) { q.done = true; continue; }
                 --q.sp;
@@ -467,11 +475,16 @@ __device__ __forceinline__ void query_round(const Scene<T>& s, const StageView& 
         const bool near0 = d0 <= d1;
         int32_t next = -1;
         if (h0 && h1) {
-            if (q.sp + (q.top ? 1 : 0) < kStackSize) {
-                if (q.top) { st.put(q.sp, q.tnode, q.tdist); ++q.sp; }
-                q.tnode = near0 ? nd.c1 : nd.c0;
-                q.tdist = near0 ? d1 : d0;
-                q.top = true;
+            if (q.sp + q.rt < kStackSize) {
+                if (q.rt == kStackRegs) {
+                    st.put(q.sp, q.rn[kStackRegs - 1], q.rd[kStackRegs - 1]);
+                    ++q.sp;
+                }
+#pragma unroll
+                for (int i = kStackRegs - 1; i > 0; --i) { q.rn[i] = q.rn[i - 1]; q.rd[i] = q.rd[i - 1]; }
+                q.rn[0] = near0 ? nd.c1 : nd.c0;
+                q.rd[0] = near0 ? d1 : d0;
+                q.rt = q.rt < kStackRegs ? q.rt + 1 : kStackRegs;
             } else {
                 qc.overflow++;
             }
