@@ -97,6 +97,7 @@ class OracleScene(C.Structure):
         ("n_nv", C.c_int32), ("NV", C.POINTER(C.c_double)), ("n_ns", C.c_int32),
         ("nsegs", C.POINTER(C.c_int32)), ("start_seg", C.POINTER(C.c_int32)),
         ("n_mono", C.c_int32), ("mono", C.POINTER(C.c_double)), ("mono_c", C.c_double),
+        ("dudn", C.c_int32),
     ]
 
 
@@ -176,6 +177,7 @@ class Oracle:
             s.n_mono = self._mono.shape[0]
             s.mono = _ptr(self._mono, C.c_double)
             s.mono_c = float(scene.mono_c)
+        s.dudn = int(getattr(scene, "dudn", 0))
         self._start = None
         self._s = s
 

@@ -10,7 +10,9 @@
 //   * WoS for the screened Poisson Dirichlet problem (Sec. 3.3, eq. (wos),
 //     Algorithm 1) with Russian roulette (Sec. 3.3, "Russian roulette").
 //   * Differential WoS (Sec. 5.1, eq. (wos_deriv), Algorithm 2) with the
-//     backward-difference normal derivative (eq. (dudn_fd_estimate)), the
+//     backward-difference normal derivative (eq. (dudn_fd_estimate)) or,
+//     as the paper's ablation, the offset-point gradient estimator of
+//     eq. (dudn_mc_estimate), the
 //     joint solution estimate from the same walk (Sec. 5.1, observation 2)
 //     and K nested forward walks per differential walk (Table 1).
 //   * Differential boundary data for restricted fields
@@ -94,6 +96,11 @@ struct oracle_scene {
     int32_t n_mono;
     const double* mono;      // n_mono*3
     double mono_c;
+    // Normal-derivative estimator of the differential walks: 0 the backward
+    // difference of eq. (dudn_fd_estimate), 1 the offset-point gradient
+    // estimator of eq. (dudn_mc_estimate) (Laplace only: sigma = 0, no
+    // source, no reflecting or implicit boundary).
+    int32_t dudn;
 };
 
 // Learned control variate of the nested walks: network N(x) (frequencies B,
@@ -1152,17 +1159,40 @@ DiffOut diff_walk_on_spheres(const Scene& sc, const double* x0, const Stream& st
                 out.run = (wq[0] >> 8) < cv_threshold(cv->q) ? 1 : 0;
             }
             if (cv) out.traces.assign(out.run == 1 ? sc.s.K : 0, CvTrace());
+            const double gx = sc.g(h);
+            // offset-point gradient estimator (eq. (dudn_mc_estimate)): the
+            // largest empty ball around xoff has radius R; the first step of
+            // a nested walk from xoff lands at y = xoff + R s, s uniform on
+            // the unit sphere, and (without source or roulette, sigma = 0)
+            // the walk's value is u(y).  D/R (s.n) u(y) is unbiased for
+            // n . grad u(xoff) (the mean-value property differentiated at
+            // the centre); g(xbar) is subtracted as a control variate
+            // (E[s] = 0).  The paper prints 3/delta (3D, R = delta); D/R is
+            // that factor in D dimensions for the ball the walk samples.
+            double bsum = 0;
+            double R0 = 0;
+            if (sc.s.dudn == 1 && out.run == 1) R0 = std::sqrt(sc.closest(xoff).d2);
             for (int i = 0; out.run == 1 && i < sc.s.K; ++i) {  // nested forward walks
                 WalkCount c2;
                 const uint32_t tag = 1u | ((uint32_t)i << 8);
-                usum += sc.has_neumann()
+                const double v = sc.has_neumann()
                             ? walk_on_stars(sc, xoff, -1, nullptr, st, tag, c2)
                             : walk_on_spheres(sc, xoff, st, tag, c2, cv ? &out.traces[i] : nullptr);
+                usum += v;
+                if (sc.s.dudn == 1 && R0 >= sc.s.eps && sc.s.kmax > 1) {
+                    uint32_t w0[4];
+                    st.draw(0, tag, w0);
+                    double s0[3];
+                    sphere_dir(D, w0[0], w0[1], s0);
+                    bsum += D / R0 * dot(s0, n, D) * (v - gx);
+                }
                 out.nested_steps += c2.steps;
                 cnt.truncated += c2.truncated;
             }
-            double gx = sc.g(h);
             double uhat = dep ? usum / sc.s.K : gx;
+            // the gradient estimate, stated as the offset value that the
+            // backward difference would turn into it
+            if (sc.s.dudn == 1 && dep && out.run == 1) uhat = gx - sc.s.delta * (bsum / sc.s.K);
             for (int i = 0; i < 3; ++i) out.xoff[i] = xoff[i];
             out.uoff = uhat;
             if (cv && dep) {
@@ -1323,6 +1353,7 @@ void parallel_points(int64_t P, int threads, F&& fn) {
 int check_scene(const oracle_scene* s) {
     if (!s) return 1;
     if (s->n_mono < 0) return 1;
+    if (s->dudn != 0 && (s->dudn != 1 || s->n_mono > 0)) return 1;
     if (s->n_mono > 0) {   // implicit boundary: 2D, c < 0, positive scales, restricted data
         if (s->dim != 2 || !s->mono || !(s->mono_c < 0) || s->n_ns > 0 || !s->bc_kind || s->bc_kind[0] != 0)
             return 1;
@@ -1330,6 +1361,9 @@ int check_scene(const oracle_scene* s) {
         if (!(s->eps > 0) || s->sigma < 0 || s->K < 1 || s->kmax < 1 || (!s->rr && s->sigma > 0)) return 1;
         return 0;
     }
+    if (s->dudn != 0 && s->dudn != 1) return 1;
+    if (s->dudn == 1 && (s->sigma != 0 || s->src_c0 != 0 || s->n_gauss > 0 || s->n_ns > 0 || s->n_mono > 0))
+        return 1;
     if ((s->dim != 2 && s->dim != 3) || s->nv <= 0 || s->np <= 0) return 1;
     if (!(s->eps > 0) || s->sigma < 0 || s->K < 1 || s->kmax < 1) return 1;
     // without roulette the walks would have to carry the product of the
@@ -1543,7 +1577,7 @@ int oracle_jvp(const oracle_scene* s, const double* X, int64_t P, int32_t W, uin
                int32_t instance, double* udot_mean, double* udot_var, double* u_mean,
                int64_t* steps_total, int threads, const oracle_cv* cv) {
     if (check_scene(s) || W < 1 || P < 0 || check_starts(s, P)) return 1;
-    if (cv && (s->n_ns > 0 || s->n_mono > 0)) return 1;   // the control variate is for walk on spheres only
+    if (cv && (s->n_ns > 0 || s->n_mono > 0 || s->dudn != 0)) return 1;   // the control variate is for walk on spheres only
     Scene sc(*s);
     const int D = s->dim, N = s->N;
     std::vector<int64_t> st_steps(256, 0);
@@ -1576,7 +1610,7 @@ int oracle_grad(const oracle_scene* s, const double* X, int64_t P, const double*
                 uint64_t seed, int32_t instance, double* grad, double* u_mean,
                 int64_t* steps_total, int threads, const oracle_cv* cv) {
     if (check_scene(s) || W < 1 || P < 0 || check_starts(s, P)) return 1;
-    if (cv && (s->n_ns > 0 || s->n_mono > 0)) return 1;   // the control variate is for walk on spheres only
+    if (cv && (s->n_ns > 0 || s->n_mono > 0 || s->dudn != 0)) return 1;   // the control variate is for walk on spheres only
     Scene sc(*s);
     const int D = s->dim, N = s->N;
     int T = threads > 0 ? threads : oracle_threads();
@@ -1612,7 +1646,7 @@ int oracle_grad_sqloss(const oracle_scene* s, const double* X, int64_t P, const 
                        double* grad, double* u_mean, int64_t* steps_total, int threads,
                        const oracle_cv* cv) {
     if (check_scene(s) || W < 1 || P < 0 || B < 2 || W % B != 0 || check_starts(s, P)) return 1;
-    if (cv && (s->n_ns > 0 || s->n_mono > 0)) return 1;   // the control variate is for walk on spheres only
+    if (cv && (s->n_ns > 0 || s->n_mono > 0 || s->dudn != 0)) return 1;   // the control variate is for walk on spheres only
     Scene sc(*s);
     const int D = s->dim, N = s->N;
     int T = threads > 0 ? threads : oracle_threads();
@@ -1713,7 +1747,7 @@ int oracle_walk_records_cv(const oracle_scene* s, const oracle_cv* cv, const dou
                            int64_t P, int32_t W, uint64_t seed, int32_t instance,
                            double* walk, double* nested, int threads) {
     if (check_scene(s) || !cv || W < 1 || P < 0 || check_starts(s, P)) return 1;
-    if (s->n_ns > 0 || s->n_mono > 0) return 1;   // the control variate is for walk on spheres only
+    if (s->n_ns > 0 || s->n_mono > 0 || s->dudn != 0) return 1;   // the control variate is for walk on spheres only
     Scene sc(*s);
     const int D = s->dim, K = s->K;
     parallel_points(P, threads, [&](int, int64_t p) {

@@ -83,6 +83,9 @@ class Scene:
     # h(x) = mono_c + sum_n a_n / |x - p_n|, rows (a_n, p_n); domain h > 0
     mono: Optional[np.ndarray] = None     # (n, 3) float64
     mono_c: float = -1.0
+    # normal-derivative estimator of the differential walks: 0 backward
+    # difference, 1 offset-point gradient estimator (Laplace only)
+    dudn: int = 0
 
     @property
     def nv(self) -> int:
