@@ -85,7 +85,18 @@ typedef struct dwos_bc {
  *  rr     0/1     Russian roulette with probability alpha = P/p^dB (Sec. 3.3)
  *  source f(x) = src_c0 + sum_i gauss[i][0] exp(-|x - m_i|^2 / (2 s_i^2)),
  *         m_i = gauss[i][1..dim], s_i = gauss[i][4]  (n_gauss <= 8)
- *  bc[l]  boundary data for primitives with label l (n_labels <= 16) */
+ *  bc[l]  boundary data for primitives with label l (n_labels <= 16)
+ *  dudn   0/1     normal-derivative estimator of the differential walks:
+ *                 0 the backward difference (g - u(xoff))/delta of
+ *                 eq. (dudn_fd_estimate); 1 the offset-point gradient
+ *                 estimator of eq. (dudn_mc_estimate), the paper's ablation:
+ *                 each nested walk's first step goes from xoff to
+ *                 y = xoff + R s (R the largest empty ball at xoff, s
+ *                 uniform) and D/R (s.n) (u(y) - g(xbar)) estimates du/dn
+ *                 (g(xbar) a control variate; the paper prints 3/delta for
+ *                 R = delta in 3D).  Laplace only: dudn = 1 needs sigma = 0
+ *                 and no source (EINVAL), and no control variate, reflecting
+ *                 or implicit boundary (ESTATE at the call). */
 typedef struct dwos_problem {
     double sigma;
     double eps;
@@ -97,7 +108,7 @@ typedef struct dwos_problem {
     double src_c0;
     double gauss[DWOS_MAX_GAUSS][5];
     int32_t n_labels;
-    int32_t pad_;
+    int32_t dudn;
     dwos_bc bc[DWOS_MAX_LABELS];
 } dwos_problem;
 

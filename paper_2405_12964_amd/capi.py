@@ -26,7 +26,7 @@ class dwos_problem(C.Structure):
     _fields_ = [("sigma", C.c_double), ("eps", C.c_double), ("delta", C.c_double),
                 ("K", C.c_int32), ("kmax", C.c_int32), ("rr", C.c_int32), ("n_gauss", C.c_int32),
                 ("src_c0", C.c_double), ("gauss", (C.c_double * 5) * MAX_GAUSS),
-                ("n_labels", C.c_int32), ("pad_", C.c_int32), ("bc", dwos_bc * MAX_LABELS)]
+                ("n_labels", C.c_int32), ("dudn", C.c_int32), ("bc", dwos_bc * MAX_LABELS)]
 
 
 class dwos_stats(C.Structure):

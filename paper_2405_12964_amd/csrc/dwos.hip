@@ -414,7 +414,7 @@ dwos_status launch_shape(dwos_ctx* c, dwos::WalkArgs<T>& a);
 template <class T, int D, int MODE>
 dwos_status launch_walks(dwos_ctx* c, dwos::WalkArgs<T>& a) {
     hipStream_t s = c->stream;
-    a.tot = c->totals.as<dwos::Counters>() + MODE;
+    a.tot = c->totals.as<dwos::Counters>() + (MODE ? 1 : 0);
     hipLaunchKernelGGL(dwos::fill_u64_kernel, dim3(1), dim3(64), 0, s, a.queue, (int64_t)1);
     if constexpr (sizeof(T) == 4) {
         if (c->variant == 1) return launch_shape<T, D, MODE, false>(c, a);
@@ -463,7 +463,7 @@ dwos_status launch_shape(dwos_ctx* c, dwos::WalkArgs<T>& a) {
     hipLaunchKernelGGL(kern, dim3(grid), dim3(block), smem, s, a);
     HIP_OK(hipGetLastError());
     HIP_OK(hipEventRecord(e1, s));
-    c->pending.push_back({e0, e1, MODE});
+    c->pending.push_back({e0, e1, MODE ? 1 : 0});
     if (c->pending.size() > 4096) {
         dwos_status st = drain_events(c, nullptr, c->pending.size());
         if (st) return st;
@@ -759,6 +759,10 @@ dwos_status run_op(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
     hipStream_t s = c->stream;
     if (c->has_ref && diff && c->cv)
         return fail(DWOS_ESTATE, "the control variate is not supported with a reflecting boundary");
+    const bool bvc = diff && c->prob.dudn == 1;
+    if (bvc && (c->cv || c->has_ref))
+        return fail(DWOS_ESTATE, "the gradient normal-derivative estimator takes neither a control variate "
+                                 "nor a reflecting boundary");
     if (c->start_n > 0 && c->start_n != P)
         return fail(DWOS_EINVAL, "start segments were set for " + std::to_string(c->start_n) +
                                      " points, the call has " + std::to_string(P));
@@ -808,9 +812,11 @@ dwos_status run_op(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
         // keeps the Philox point word absolute
         if constexpr (D == 2) {
             if (c->has_ref) rc = diff ? launch_wost<T, 1>(c, a) : launch_wost<T, 0>(c, a);
+            else if (bvc) rc = launch_walks<T, D, 2>(c, a);
             else rc = diff ? launch_walks<T, D, 1>(c, a) : launch_walks<T, D, 0>(c, a);
         } else {
-            rc = diff ? launch_walks<T, D, 1>(c, a) : launch_walks<T, D, 0>(c, a);
+            if (bvc) rc = launch_walks<T, D, 2>(c, a);
+            else rc = diff ? launch_walks<T, D, 1>(c, a) : launch_walks<T, D, 0>(c, a);
         }
         if (rc) return rc;
         if (use_cv) {
@@ -944,6 +950,8 @@ dwos_status run_imp(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
     const int32_t W = o.W;
     hipStream_t s = c->stream;
     if (c->cv) return fail(DWOS_ESTATE, "the control variate is not supported on an implicit boundary");
+    if (diff && c->prob.dudn != 0)
+        return fail(DWOS_ESTATE, "the gradient normal-derivative estimator is not available on an implicit boundary");
     if (c->prob.bc[0].kind != 0)
         return fail(DWOS_ESTATE, "an implicit boundary takes restricted (quadratic) boundary data of label 0");
     const int64_t chunk_pts = std::max<int64_t>(1, kMaxWalksPerChunk / W);
@@ -1150,6 +1158,10 @@ dwos_status dwos_set_problem(dwos_ctx* c, const dwos_problem* p) {
                                  "the product of the attenuation factors");
     if (p->n_gauss < 0 || p->n_gauss > DWOS_MAX_GAUSS) return fail(DWOS_EINVAL, "set_problem: n_gauss out of range");
     if (p->n_labels < 1 || p->n_labels > DWOS_MAX_LABELS) return fail(DWOS_EINVAL, "set_problem: n_labels out of range");
+    if (p->dudn != 0 && p->dudn != 1) return fail(DWOS_EINVAL, "set_problem: dudn must be 0 or 1");
+    if (p->dudn == 1 && (p->sigma != 0 || p->src_c0 != 0 || p->n_gauss != 0))
+        return fail(DWOS_EINVAL, "set_problem: the gradient normal-derivative estimator (dudn = 1) is for the "
+                                 "Laplace equation (sigma = 0, no source)");
     if (!std::isfinite(p->src_c0)) return fail(DWOS_EINVAL, "set_problem: non-finite source");
     for (int i = 0; i < p->n_gauss; ++i) {
         for (int k = 0; k < 5; ++k)

@@ -605,7 +605,14 @@ __device__ __forceinline__ unsigned long long bcast64(unsigned long long v, int 
 // the walk kernel
 //   MODE 0: Algorithm 1 (forward walks): rec_u = walk estimate
 //   MODE 1: Algorithm 2 (differential walks) with the joint u estimate and K
-//           nested forward walks from xbar - delta n at the terminal point
+//           nested forward walks from xbar - delta n at the terminal point;
+//           rec_uoff = their mean (eq. (dudn_fd_estimate) follows from it)
+//   MODE 2: as MODE 1 with the offset-point gradient estimator of
+//           eq. (dudn_mc_estimate) (Laplace only): the first step of each
+//           nested walk goes from xoff to y = xoff + R s (R the largest empty
+//           ball), and D/R (s.n) (u(y) - g(xbar)) estimates du/dn; rec_uoff
+//           is g - delta times their mean, so that (g - rec_uoff)/delta is
+//           that estimate
 // ---------------------------------------------------------------------------
 template <class T, int D, int MODE, bool STAGED>
 __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(WalkArgs<T> a) {
@@ -652,6 +659,10 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
     int32_t root = 0, warm = -1, term_leaf = -1, term_code = -1, phase = 0;
     T term_b1 = T(0), term_b2 = T(0);
     int64_t wsteps = 0;
+    // MODE 2: terminal normal and data, and the current nested walk's weight
+    T bvc_n[D], bvc_g = T(0), bvc_w = T(0);
+#pragma unroll
+    for (int c = 0; c < D; ++c) bvc_n[c] = T(0);
     // closest-point query in progress (resumable across iterations)
     Query<T> q;
     bool qpend = false;
@@ -766,7 +777,7 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
             c_invalid++;
             const T nanv = T(NAN);
             a.rec_u[wid] = nanv;
-            if (MODE == 1) {
+            if (MODE >= 1) {
                 a.rec_prim[wid] = -1;
                 a.rec_uoff[wid] = nanv;
                 if (a.cv_run) a.cv_run[wid] = -1;
@@ -777,7 +788,7 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
         }
         const T d = sqrt(d2);
         const bool cap = (int)(k + 1) >= a.prm.kmax;
-        const bool nested = MODE == 1 && phase > 0;
+        const bool nested = MODE >= 1 && phase > 0;
         bool finished = false;     // the current (main or nested) walk ended
         bool alive = false;        // ... in the shell or at the cap (not by roulette)
         T result = T(0);           // its value
@@ -800,7 +811,7 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
                 xbar[c] = v;
             }
             const T g = boundary_value<T, D>(a.s, a.prm, orig, bary, xbar, vid);
-            if (MODE == 1 && phase == 0) {
+            if (MODE >= 1 && phase == 0) {
                 // BoundaryNormal, oriented out of the domain (away from x)
                 T n[3] = {T(0), T(0), T(0)};
                 geo_normal<T, D>(V, n);
@@ -813,6 +824,12 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
                     for (int c = 0; c < D; ++c) n[c] = -n[c];
                 }
                 u_main = acc + g;
+                if constexpr (MODE == 2) {
+#pragma unroll
+                    for (int c = 0; c < D; ++c) bvc_n[c] = n[c];
+                    bvc_g = g;
+                    bvc_w = T(0);
+                }
                 term_code = orig * 2 + flip;
                 term_b1 = bary[1]; term_b2 = bary[2];
                 term_leaf = leaf;
@@ -870,7 +887,7 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
         } else {
             const uint32_t tag = inst_tag | (nested ? (1u | ((uint32_t)(phase - 1) << 8)) : 0u);
             const u4 r = philox10(u4{k, m, p, tag}, key0, key1);
-            if (MODE == 1 && nested && a.cv_run) {
+            if (MODE >= 1 && nested && a.cv_run) {
                 // weighted reservoir choice of one source step (probability
                 // proportional to its ball's Green's-function mass) with one
                 // uniform point of its ball
@@ -911,10 +928,18 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
             if (a.prm.rr && alpha < unif<T>(r.z)) {
                 finished = true;
                 result = acc;
-                if (MODE == 1 && phase == 0) term_code = -1;
+                if (MODE >= 1 && phase == 0) term_code = -1;
             } else {
                 T dir[3];
                 unit_dir<T, D>(r.x, r.y, dir);
+                if constexpr (MODE == 2) {
+                    if (nested && k == 0) {
+                        T sn = T(0);
+#pragma unroll
+                        for (int c = 0; c < D; ++c) sn += dir[c] * bvc_n[c];
+                        bvc_w = T(D) / d * sn;
+                    }
+                }
 #pragma unroll
                 for (int c = 0; c < D; ++c) x[c] += d * dir[c];
                 ++k;
@@ -936,7 +961,8 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
             if (a.rec_steps) a.rec_steps[wid] = wsteps;
             wid = -1;
         } else {
-            usum += result;
+            if constexpr (MODE == 2) usum += bvc_w * (result - bvc_g);
+            else usum += result;
             if (a.cv_run) {
                 const size_t q = (size_t)wid * a.prm.K + (phase - 1);
 #pragma unroll
@@ -954,11 +980,13 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
                 a.rec_prim[wid] = term_code;
                 a.rec_b[(size_t)wid * (D - 1)] = term_b1;
                 if constexpr (D == 3) a.rec_b[(size_t)wid * 2 + 1] = term_b2;
-                a.rec_uoff[wid] = usum / T(a.prm.K);
+                if constexpr (MODE == 2) a.rec_uoff[wid] = bvc_g - delta * (usum / T(a.prm.K));
+                else a.rec_uoff[wid] = usum / T(a.prm.K);
                 if (a.rec_steps) a.rec_steps[wid] = wsteps;
                 wid = -1;
             } else {
                 ++phase;
+                if constexpr (MODE == 2) bvc_w = T(0);
 #pragma unroll
                 for (int c = 0; c < D; ++c) x[c] = xoff[c];
                 acc = T(0); k = 0; warm = term_leaf;

@@ -41,10 +41,13 @@ def _dev(t: Optional[torch.Tensor], dtype=torch.float64):
 
 
 def make_problem(sigma=0.0, eps=1e-3, delta=1e-2, K=1, kmax=65536, rr=1, src_c0=0.0,
-                 gauss=None, bc=None, dim=3) -> capi.dwos_problem:
+                 gauss=None, bc=None, dim=3, dudn=0) -> capi.dwos_problem:
     """Fill a dwos_problem.  bc: list of dicts kind='restricted' (c, b, A) or
-    kind='mapped'; gauss: rows (amplitude, centre[dim], width)."""
+    kind='mapped'; gauss: rows (amplitude, centre[dim], width); dudn: 0 the
+    backward-difference normal derivative, 1 the offset-point gradient
+    estimator (Laplace only)."""
     p = capi.dwos_problem()
+    p.dudn = int(dudn)
     p.sigma, p.eps, p.delta = float(sigma), float(eps), float(delta)
     p.K, p.kmax, p.rr = int(K), int(kmax), int(rr)
     p.src_c0 = float(src_c0)
@@ -194,7 +197,8 @@ class Solver:
         if getattr(scene, "nsegs", None) is not None and len(scene.nsegs) > 0:
             s.set_reflecting(scene.NV, scene.nsegs)
         s.set_problem(make_problem(scene.sigma, scene.eps, scene.delta, scene.K, scene.kmax,
-                                   scene.rr, scene.src_c0, scene.gauss, scene.bc, scene.dim))
+                                   scene.rr, scene.src_c0, scene.gauss, scene.bc, scene.dim,
+                                   getattr(scene, "dudn", 0)))
         if scene.N > 0 and scene.rowptr is not None and (mono is None or len(mono) == 0):
             s.set_parameters(scene.N, scene.rowptr, scene.pid, scene.vel, scene.bc_pid)
         return s
