@@ -505,6 +505,41 @@ dwos_status dwos_implicit_band_grad(dwos_ctx* ctx, const double* X, int64_t P, c
                                     double eps_band, double* grad, int32_t* region);
 
 /* ---------------------------------------------------------------------------
+ * Remeshing (host code): the periodic isotropic remeshing of the paper's
+ * shape-optimisation loop (Sec. 7.2, "Gradient preconditioning", after
+ * Botsch and Kobbelt).  Each of `iters` iterations splits edges longer than
+ * 4L/3, collapses edges shorter than 4L/5 (never creating an edge longer
+ * than 4L/3, changing the topology or flipping a triangle), flips edges
+ * toward valence 6 (3D), moves free vertices to their neighbours' centroid
+ * within the tangent plane (line) and projects them back onto the input.
+ * ------------------------------------------------------------------------- */
+typedef struct dwos_mesh dwos_mesh;
+
+/* Remesh a boundary: dim 2 (polylines: every vertex has at most one
+ * segment in and one out; open ends stay) or 3 (triangles: no edge in more
+ * than two; vertices on border edges stay), V host nv x dim FP64, prims host
+ * np x dim, fixed host nv int32 or NULL (nonzero: the vertex neither moves
+ * nor disappears, and an edge between two fixed vertices is neither split
+ * nor collapsed), target edge length L > 0, iters in 0..100.  The result
+ * is owned by *out (dwos_mesh_destroy); orientation is preserved.  Runs on
+ * the host only (no device or stream is touched).
+ * Errors: EINVAL (bad dim, empty mesh, index out of range, degenerate
+ * primitive, non-finite coordinate, L <= 0, non-manifold input). */
+dwos_status dwos_remesh(int32_t dim, const double* V, int64_t nv, const int32_t* prims, int64_t np,
+                        const int32_t* fixed, double target, int32_t iters, dwos_mesh** out);
+
+/* Vertex and primitive counts of a remeshed boundary. */
+dwos_status dwos_mesh_size(const dwos_mesh* m, int64_t* nv, int64_t* np);
+
+/* Copy out (host buffers sized by dwos_mesh_size; any may be NULL) the
+ * vertices (nv x dim), primitives (np x dim) and, per vertex, the index of
+ * the input vertex it continues, or -1 for a vertex a split created. */
+dwos_status dwos_mesh_get(const dwos_mesh* m, double* V, int32_t* prims, int64_t* src);
+
+/* Release a remeshed boundary (NULL is ignored). */
+void dwos_mesh_destroy(dwos_mesh* m);
+
+/* ---------------------------------------------------------------------------
  * Shape-optimisation step for mesh vertices (the optimiser of the paper's
  * experiments, Sec. 6 "Implementation and evaluation" and Sec. 7.2
  * "Gradient preconditioning"): vector Adam (second moment per vertex from

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdwos.so")
-SOURCES = ["dwos.hip", "mlp.hip", "opt.hip", "bvh_build.cpp"]
+SOURCES = ["dwos.hip", "mlp.hip", "opt.hip", "bvh_build.cpp", "remesh.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

@@ -98,6 +98,10 @@ def lib():
             "dwos_eval_reflect_weight": [vp, vp, vp, C.c_int64, C.c_double, vp],
             "dwos_set_implicit": [vp, dp, C.c_int64, C.c_double],
             "dwos_implicit_band_grad": [vp, vp, C.c_int64, vp, C.c_double, vp, vp],
+            "dwos_remesh": [C.c_int32, dp, C.c_int64, i32p, C.c_int64, i32p, C.c_double, C.c_int32,
+                            C.POINTER(vp)],
+            "dwos_mesh_size": [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
+            "dwos_mesh_get": [vp, dp, i32p, i64p],
             "dwos_opt_create": [C.c_int32, C.c_int64, i32p, C.c_int64, i32p, C.c_double, vp, C.POINTER(vp)],
             "dwos_opt_reset": [vp, vp],
             "dwos_opt_step": [vp, vp, vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32,
@@ -116,6 +120,8 @@ def lib():
         L.dwos_mlp_destroy.restype = None
         L.dwos_opt_destroy.argtypes = [vp]
         L.dwos_opt_destroy.restype = None
+        L.dwos_mesh_destroy.argtypes = [vp]
+        L.dwos_mesh_destroy.restype = None
         _lib = L
     return _lib
 
@@ -131,6 +137,7 @@ EXPORTED = [
     "dwos_mlp_vjp", "dwos_mlp_adam_step", "dwos_cv_attach", "dwos_cv_beta", "dwos_cv_train", "dwos_cv_walk_records",
     "dwos_set_reflecting", "dwos_set_start_segments", "dwos_reflect_query", "dwos_eval_reflect_weight",
     "dwos_set_implicit", "dwos_implicit_band_grad",
+    "dwos_remesh", "dwos_mesh_size", "dwos_mesh_get", "dwos_mesh_destroy",
     "dwos_opt_create", "dwos_opt_destroy", "dwos_opt_reset", "dwos_opt_step", "dwos_opt_solve",
 ]
 

@@ -3,9 +3,12 @@ forward walks at the measurement points, the squared loss against a
 reference, reverse-mode differential walks for dJ/dx of every movable
 vertex, one vector-Adam step on the Laplacian-preconditioned variable
 (dwos_opt_step), and the boundary moved to the new vertices (BVH refit),
-with the walks per point annealed by eq. (update_rule).
+with the walks per point annealed by eq. (update_rule) and the movable part
+remeshed periodically (dwos_remesh; the paper remeshes every 100
+iterations).
 
-Orchestration only: every walk, solve and update runs in the HIP library.
+Orchestration only: every walk, solve, update and remesh runs in the
+library.
 """
 from __future__ import annotations
 
@@ -39,29 +42,86 @@ class VertexShapeOptimizer:
     """Optimise the movable vertices of a scene's Dirichlet boundary."""
 
     def __init__(self, scene, movable, lam=20.0, lr=1e-3, W0=8, WT=64, T=100, precision="fp32",
-                 device="cuda", cg_tol=1e-7):
+                 device="cuda", cg_tol=1e-7, remesh_every=0, remesh_len=None, remesh_iters=5):
         self.scene, self.dim = scene, scene.dim
-        self.mv = np.asarray(movable, bool)
+        self.device, self.lam = device, lam
         self.solver = Solver(scene.dim, precision)
-        self.solver.set_boundary(scene.V, scene.prims, scene.label, scene.gvert)
         self.solver.set_problem(make_problem(scene.sigma, scene.eps, scene.delta, scene.K, scene.kmax,
                                              scene.rr, scene.src_c0, scene.gauss, scene.bc, scene.dim))
-        N, rowptr, pid, vel = vertex_jacobian(scene.nv, scene.dim, self.mv)
-        self.solver.set_parameters(N, rowptr, pid, vel)
-        self.x = torch.tensor(scene.V, dtype=torch.float64, device=device).contiguous()
-        self.idx = torch.tensor(np.nonzero(self.mv)[0], dtype=torch.int64, device=device)
-        self.opt = LargeSteps(scene.dim, scene.nv, scene.prims, lam, self.mv.astype(np.int32))
-        self.opt.reset(self.x)
         self.lr, self.W0, self.WT, self.T = lr, W0, WT, T
         # relative residual of the two solves: far below the gradient noise
         # of a few walks per point
         self.cg_tol = cg_tol
         self.t = 0
+        mv = np.asarray(movable, bool)
+        if remesh_len is None:
+            P = np.asarray(scene.prims)
+            e = P[mv[P].all(1)]
+            e = np.concatenate([e[:, [k, (k + 1) % self.dim]] for k in range(self.dim)]) if self.dim == 3 else e
+            remesh_len = float(np.linalg.norm(scene.V[e[:, 0]] - scene.V[e[:, 1]], axis=1).mean()) if len(e) else 0.0
+        self.remesh_every, self.remesh_len, self.remesh_iters = remesh_every, remesh_len, remesh_iters
+        self._load(np.asarray(scene.V, float), np.asarray(scene.prims, np.int32), np.asarray(scene.label, np.int32),
+                   np.asarray(scene.gvert, float), mv)
+
+    def _load(self, V, P, label, gvert, mv):
+        """(Re)build the boundary, the vertex Jacobian and the optimiser for a
+        mesh; the optimiser's moments start from zero."""
+        self.V, self.P, self.label, self.gvert, self.mv = V, P, label, gvert, mv
+        self.solver.set_boundary(V, P, label, gvert)
+        N, rowptr, pid, vel = vertex_jacobian(len(V), self.dim, mv)
+        self.solver.set_parameters(N, rowptr, pid, vel)
+        self.x = torch.tensor(V, dtype=torch.float64, device=self.device).contiguous()
+        self.idx = torch.tensor(np.nonzero(mv)[0], dtype=torch.int64, device=self.device)
+        self.opt = LargeSteps(self.dim, len(V), P, self.lam, mv.astype(np.int32))
+        self.opt.reset(self.x)
         self.gx = torch.zeros_like(self.x)
+
+    def remesh(self, target=None, iters=None):
+        """Remesh the primitives that touch a movable vertex toward edge
+        length ``target`` (dwos_remesh); fixed vertices keep their place, the
+        rest of the boundary is carried over.  The remeshed primitives must
+        share one label with restricted data.  Restarts the optimiser's
+        moments on the new mesh."""
+        from .remesh import remesh as _remesh
+        target = self.remesh_len if target is None else target
+        iters = self.remesh_iters if iters is None else iters
+        X = self.x.cpu().numpy()
+        P, mv, lab = self.P, self.mv, self.label
+        touch = mv[P].any(1)
+        labs = np.unique(lab[touch])
+        if len(labs) != 1:
+            raise ValueError("remesh: the movable primitives must share one label")
+        if self.scene.bc[int(labs[0])].get("kind", "restricted") != "restricted":
+            raise ValueError("remesh: mapped boundary data is not carried over")
+        used = np.unique(P[touch])
+        loc = -np.ones(len(X), np.int64)
+        loc[used] = np.arange(len(used))
+        V2, P2, src = _remesh(X[used], loc[P[touch]], target, iters, fixed=~mv[used])
+        # vertices of the untouched primitives: kept ones are found through
+        # src, the others appended
+        rest = P[~touch]
+        newidx = -np.ones(len(X), np.int64)
+        kept = src >= 0
+        newidx[used[src[kept]]] = np.nonzero(kept)[0]
+        only = np.setdiff1d(np.unique(rest), used) if len(rest) else np.zeros(0, np.int64)
+        newidx[only] = len(V2) + np.arange(len(only))
+        assert np.all(newidx[rest] >= 0) if len(rest) else True
+        Vn = np.concatenate([V2, X[only]])
+        Pn = np.concatenate([P2, newidx[rest]]).astype(np.int32)
+        labn = np.concatenate([np.full(len(P2), labs[0], np.int32), lab[~touch]])
+        mvn = np.zeros(len(Vn), bool)
+        mvn[:len(V2)] = True
+        mvn[np.nonzero(kept)[0]] = mv[used[src[kept]]]
+        gv = np.zeros(len(Vn))
+        gv[len(V2):] = self.gvert[only]
+        self._load(Vn, Pn, labn, gv, mvn)
 
     def step(self, X: torch.Tensor, uref: torch.Tensor, seed: int):
         """One iteration; returns (loss from the forward walks, W used, CG
-        iterations of the two solves)."""
+        iterations of the two solves).  Every ``remesh_every`` iterations
+        (0: never) the movable part is remeshed first."""
+        if self.remesh_every and self.t > 0 and self.t % self.remesh_every == 0:
+            self.remesh()
         W = wpp(self.W0, self.WT, self.t, self.T)
         u, _ = self.solver.solve(X, W, 2 * seed, var=False)
         w = (u - uref).contiguous()

@@ -146,3 +146,37 @@ def test_shape_from_diffusion_loop_reduces_loss(dev, dwos):
     assert np.mean(losses[-5:]) < 0.5 * np.mean(losses[:3]), losses
     # the fixed box did not move
     assert np.array_equal(opt.x.cpu().numpy()[n:], start.V[n:])
+
+
+def test_loop_with_periodic_remeshing(dev, dwos):
+    """The same loop remeshed every 10 iterations toward a finer edge length:
+    the loss still falls, the box is carried over unchanged, and the object
+    ends with edges within [4L/5, 4L/3] of the target."""
+    from paper_2405_12964_amd.shapeopt import VertexShapeOptimizer
+    n = 96
+    target = _object_in_box(n, lambda th: 0.55 + 0.15 * np.cos(2 * th), sigma=1.0)
+    start = _object_in_box(n, lambda th: 0.5 + 0 * th, sigma=1.0)
+    rng = np.random.default_rng(3)
+    s_ = rng.uniform(-1.8, 1.8, 512)
+    side = rng.integers(0, 4, 512)
+    X = np.where(side[:, None] == 0, np.stack([s_, -1.8 + 0 * s_], 1),
+        np.where(side[:, None] == 1, np.stack([1.8 + 0 * s_, s_], 1),
+        np.where(side[:, None] == 2, np.stack([s_, 1.8 + 0 * s_], 1), np.stack([-1.8 + 0 * s_, s_], 1))))
+    Xt = T(X, dev)
+    uref, _ = dwos.Solver.from_scene(target, "fp32").solve(Xt, 4096, 7)
+    mv = np.concatenate([np.ones(n, bool), np.zeros(4, bool)])
+    L = 0.8 * 2 * np.pi * 0.5 / n
+    opt = VertexShapeOptimizer(start, mv, lam=10.0, lr=1e-2, W0=32, WT=256, T=40, remesh_every=10, remesh_len=L)
+    losses = []
+    for t in range(40):
+        Lt, W, its = opt.step(Xt, uref, 100 + t)
+        losses.append(Lt)
+    assert np.mean(losses[-5:]) < 0.5 * np.mean(losses[:3]), losses
+    V, P, mvf = opt.V, opt.P, opt.mv
+    assert len(V) != n + 4                                   # the object was remeshed
+    box = np.array([[-2.0, -2.0], [2.0, -2.0], [2.0, 2.0], [-2.0, 2.0]])
+    assert np.array_equal(V[~mvf], box)
+    seg = P[mvf[P].all(1)]
+    l = np.linalg.norm(opt.x.cpu().numpy()[seg[:, 0]] - opt.x.cpu().numpy()[seg[:, 1]], axis=1)
+    # edges at the last remesh were in the band; 9 optimisation steps since
+    assert 0.6 * L < l.mean() < 1.5 * L
