@@ -69,7 +69,8 @@ __device__ __forceinline__ T imp_h(const T* mono, int n, T c, const T* x, T* gr)
 // Safe radius: the larger of the direct bound (eight Newton steps on the
 // concave 1/S(d) = 1/sum_n a_n / (r_n + d) towards -1/c from d = 0) and the
 // Harnack radius of f = h - c out to the nearest pole.  FP32: r_n = |x - p_n|
-// once per step, the Newton sums with the hardware reciprocal.
+// once per step, the Newton sums with the hardware reciprocal, and the
+// iteration stops once converged to FP32 resolution.
 template <class T>
 __device__ __forceinline__ T imp_safe_radius(const T* mono, int n, T c, const T* x, T h) {
     const T A = -c;
@@ -111,7 +112,12 @@ __device__ __forceinline__ T imp_safe_radius(const T* mono, int n, T c, const T*
                 S += t;
                 Tt = fmaf(t, rq, Tt);
             }
-            d += (S * S / A - S) / Tt;
+            const float inc = (S * S / A - S) / Tt;
+            d += inc;
+            // the iterates rise monotonically to the root, quadratically
+            // near it: once a step is below 1e-5 of the radius the rest are
+            // below FP32 resolution (an earlier stop only shortens the step)
+            if (inc <= 1e-5f * d) break;
         }
     } else {
         for (int it = 0; it < 8; ++it) {
