@@ -93,7 +93,7 @@ struct dwos_ctx {
     int64_t cv_nrec = 0;          // walks recorded by the last differential chunk
     // reflecting (zero-flux) boundary, 2D: walks on stars when present
     bool has_ref = false;
-    int64_t ref_n = 0;
+    int64_t ref_n = 0, ref_nn = 0;   // reflecting segments, pair nodes
     DevBuf ref_nodes, ref_geo, ref_info, ref_leaf_of, ref_cones;
     DevBuf start_seg;             // per query point: reflecting segment or -1
     int64_t start_n = 0;          // points covered by start_seg (0: none)
@@ -288,6 +288,7 @@ dwos_status upload_reflecting(dwos_ctx* c, const double* V, const int32_t* segs,
     HIP_OK(upload(c->ref_info, info.data(), info.size(), s));
     HIP_OK(upload(c->ref_leaf_of, leaf_of.data(), leaf_of.size(), s));
     c->ref_n = ns;
+    c->ref_nn = (int64_t)bvh.nodes.size();
     return DWOS_OK;
 }
 
@@ -473,17 +474,37 @@ dwos_status launch_shape(dwos_ctx* c, dwos::WalkArgs<T>& a) {
 
 // Launch the persistent walk-on-stars kernel (2D, reflecting boundary).
 template <class T, int MODE>
-dwos_status launch_wost(dwos_ctx* c, dwos::WalkArgs<T>& a) {
+dwos_status launch_wost(dwos_ctx* c, dwos::WalkArgs<T>& a0) {
     hipStream_t s = c->stream;
+    dwos::WalkArgs<T> a = a0;
     a.tot = c->totals.as<dwos::Counters>() + MODE;
     hipLaunchKernelGGL(dwos::fill_u64_kernel, dim3(1), dim3(64), 0, s, a.queue, (int64_t)1);
     constexpr int block = dwos::kBlock;
     auto kern = dwos::wost_kernel<T, MODE>;
-    static int occ_per_cu = 0;
-    if (occ_per_cu == 0) {
+    dwos::RefScene<T> ref = make_ref<T>(c);
+    size_t lds = 0;
+    if constexpr (sizeof(T) == 4) {
+        // LDS per block (a few blocks per CU): up to 256 Dirichlet nodes, its
+        // primitives up to 16 KB, the reflecting BVH's first 128 nodes
+        a.s.n_stage_nodes = (int32_t)std::min<int64_t>(c->n_nodes, 256);
+        a.s.stage_prims = c->np * (int64_t)(dwos::prim_scalars(2) * sizeof(T)) <= 16384 ? 1 : 0;
+        ref.n_stage = (int32_t)std::min<int64_t>(c->ref_nn, 128);
+        const int64_t w_nodes = dwos::node_scalars(2) / 4;
+        ref.stage_off4 = (int64_t)a.s.n_stage_nodes * w_nodes + (a.s.stage_prims ? c->np : 0);
+        lds = (size_t)(ref.stage_off4 + (int64_t)ref.n_stage * (w_nodes + 2)) * 16;
+    } else {
+        a.s.n_stage_nodes = 0;
+        a.s.stage_prims = 0;
+        ref.n_stage = 0;
+        ref.stage_off4 = 0;
+    }
+    static size_t occ_lds = ~size_t(0);
+    static int occ_per_cu = 1;
+    if (occ_lds != lds) {
         int per = 0;
-        HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, block, 0));
+        HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, block, lds));
         occ_per_cu = std::max(1, per);
+        occ_lds = lds;
     }
     const int64_t need = (a.total + block - 1) / block;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)occ_per_cu * c->cu_count));
@@ -491,7 +512,7 @@ dwos_status launch_wost(dwos_ctx* c, dwos::WalkArgs<T>& a) {
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     HIP_OK(hipStreamIsCapturing(s, &cap));
     if (cap != hipStreamCaptureStatusNone) {
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, a, make_ref<T>(c), starts);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, a, ref, starts);
         HIP_OK(hipGetLastError());
         return DWOS_OK;
     }
@@ -499,7 +520,7 @@ dwos_status launch_wost(dwos_ctx* c, dwos::WalkArgs<T>& a) {
     HIP_OK(hipEventCreate(&e0));
     HIP_OK(hipEventCreate(&e1));
     HIP_OK(hipEventRecord(e0, s));
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, a, make_ref<T>(c), starts);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, a, ref, starts);
     HIP_OK(hipGetLastError());
     HIP_OK(hipEventRecord(e1, s));
     c->pending.push_back({e0, e1, MODE});

@@ -59,7 +59,41 @@ struct RefScene {
     const int32_t* leaf_of;   // original segment -> leaf position
     const T* cones;           // per node: child 0 then child 1, kRefCone each
     int64_t n;
+    // FP32 walk kernel: the first n_stage nodes (breadth-first, the top
+    // levels every query visits) and their cones are copied to LDS at
+    // g_stage + stage_off4 (16-byte words: nodes, then cones); 0: none
+    int32_t n_stage;
+    int64_t stage_off4;
 };
+
+// A reflecting-BVH node and its children's cones, from LDS for the staged
+// prefix, from global memory otherwise.
+template <class T>
+__device__ __forceinline__ void ref_node(const RefScene<T>& r, int32_t i, NodeData<T, 2>& nd) {
+    if constexpr (sizeof(T) == 4) {
+        if (i < r.n_stage) {
+            decode_node_f32<2>(g_stage + r.stage_off4 + (int64_t)i * (node_scalars(2) / 4), nd);
+            return;
+        }
+    }
+    load_node<T, 2>(r.nodes, i, nd);
+}
+
+template <class T>
+__device__ __forceinline__ void ref_cones(const RefScene<T>& r, int32_t i, T* q) {
+    if constexpr (sizeof(T) == 4) {
+        if (i < r.n_stage) {
+            const float4* w = g_stage + r.stage_off4 + (int64_t)r.n_stage * (node_scalars(2) / 4) + (int64_t)i * 2;
+            const float4 a = w[0], b = w[1];
+            q[0] = a.x; q[1] = a.y; q[2] = a.z; q[3] = a.w;
+            q[4] = b.x; q[5] = b.y; q[6] = b.z; q[7] = b.w;
+            return;
+        }
+    }
+    const T* g = r.cones + (size_t)i * (2 * kRefCone);
+#pragma unroll
+    for (int k = 0; k < 2 * kRefCone; ++k) q[k] = g[k];
+}
 
 // Can the child with box lo..hi and cone q hold a silhouette seen from x?
 template <class T>
@@ -126,11 +160,12 @@ __device__ T silhouette_d2(const RefScene<T>& r, const T* x, int32_t on, const T
     while (have) {
         if (cur >= 0) {
             NodeData<T, 2> nd;
-            load_node<T, 2>(r.nodes, cur, nd);
+            ref_node<T>(r, cur, nd);
             qc.nodes++;
             const T d0 = fmax(box_d2<T, 2>(nd.lo0, nd.hi0, x), slab_d2<T, 2>(nd.n0, nd.o0, nd.t0, x));
             const T d1 = fmax(box_d2<T, 2>(nd.lo1, nd.hi1, x), slab_d2<T, 2>(nd.n1, nd.o1, nd.t1, x));
-            const T* q = r.cones + (size_t)cur * (2 * kRefCone);
+            T q[2 * kRefCone];
+            ref_cones<T>(r, cur, q);
             const bool h0 = d0 < best && cone_may_hold<T>(nd.lo0, nd.hi0, q, x);
             const bool h1 = d1 < best && cone_may_hold<T>(nd.lo1, nd.hi1, q + kRefCone, x);
             if (h0 && h1) {
@@ -237,7 +272,7 @@ __device__ int32_t ray_first(const RefScene<T>& r, const T* x, const T* dir, T t
     while (have) {
         if (cur >= 0) {
             NodeData<T, 2> nd;
-            load_node<T, 2>(r.nodes, cur, nd);
+            ref_node<T>(r, cur, nd);
             qc.nodes++;
             const T e0 = ray_child<T>(nd.lo0, nd.hi0, nd.n0, nd.o0, nd.t0, x, dir, inv, best);
             const T e1 = ray_child<T>(nd.lo1, nd.hi1, nd.n1, nd.o1, nd.t1, x, dir, inv, best);
@@ -351,7 +386,28 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
     constexpr int D = 2;
     const int lane = threadIdx.x & 63;
     TravStack<T, false> stack;
-    const StageView sv{0, -1};
+    StageView sv{0, -1};
+    if constexpr (sizeof(T) == 4) {
+        // LDS: the Dirichlet BVH's first nodes (and its primitives when they
+        // fit), then the reflecting BVH's top nodes and their cones
+        const int64_t nn4 = (int64_t)a.s.n_stage_nodes * (node_scalars(D) / 4);
+        const float4* gn = reinterpret_cast<const float4*>(a.s.nodes);
+        for (int64_t i = threadIdx.x; i < nn4; i += blockDim.x) g_stage[i] = gn[i];
+        if (a.s.stage_prims) {
+            const int64_t np4 = a.s.n_prims * (prim_scalars(D) / 4);
+            const float4* gp = reinterpret_cast<const float4*>(a.s.prims);
+            for (int64_t i = threadIdx.x; i < np4; i += blockDim.x) g_stage[nn4 + i] = gp[i];
+        }
+        const int64_t rn4 = (int64_t)ref.n_stage * (node_scalars(D) / 4);
+        const float4* rn = reinterpret_cast<const float4*>(ref.nodes);
+        for (int64_t i = threadIdx.x; i < rn4; i += blockDim.x) g_stage[ref.stage_off4 + i] = rn[i];
+        const float4* rc = reinterpret_cast<const float4*>(ref.cones);
+        for (int64_t i = threadIdx.x; i < 2 * (int64_t)ref.n_stage; i += blockDim.x)
+            g_stage[ref.stage_off4 + rn4 + i] = rc[i];
+        __syncthreads();
+        sv.n_lnodes = a.s.n_stage_nodes;
+        sv.prim_off4 = a.s.stage_prims ? nn4 : -1;
+    }
     uint32_t key0 = a.key0, key1 = a.key1;
     if (a.seed_ptr) {
         const unsigned long long sd = *a.seed_ptr + (((unsigned long long)a.key1 << 32) | a.key0);
