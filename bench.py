@@ -605,7 +605,7 @@ def main():
                     help="run a plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; the walks shard across GPUs "
+        print(json.dumps({"error": "the benchmark runs on one GPU; the walks shard across GPUs "
                                    "by (point, walk) ranges but no multi-GPU path is built",
                           "n_gpus": args.gpus}))
         sys.exit(2)
