@@ -99,7 +99,10 @@ class Solver:
     def __del__(self):
         ctx = getattr(self, "_ctx", None)
         if ctx is not None and ctx.value:
-            capi.dwos_destroy(ctx)
+            try:
+                capi.dwos_destroy(ctx)
+            except Exception:   # interpreter shutdown: module globals already gone
+                pass
             self._ctx = None
 
     # ---- setup (host arrays) ------------------------------------------------

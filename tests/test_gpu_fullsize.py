@@ -12,7 +12,7 @@ BVH equal brute force.
 
 Workloads: the 2D star with 4096 segments, 4096 points x 4096 walks (the
 benchmark); the 3D displaced icosphere with 200,000 triangles, 65536 points
-x 64 walks (the shape-from-diffusion iteration).
+x 1024 walks (the shape-from-diffusion configuration).
 """
 import numpy as np
 import pytest
@@ -119,14 +119,15 @@ def test_icosphere_fullsize_solve_sampled_and_reverse_mode(dev, dwos, oracle_mod
     sc, X = ico
     s = dwos.Solver.from_scene(sc, "fp32")
     Xt = T(X, dev)
-    m, v = s.solve(Xt, 64, 41)
-    idx = np.random.default_rng(9).choice(len(X), 4, replace=False)
+    # the configuration's 1024 walks per point
+    m, v = s.solve(Xt, 1024, 41)
+    idx = np.random.default_rng(9).choice(len(X), 8, replace=False)
     om, ov, _ = oracle_mod.Oracle(sc).solve(X[idx], 128, 42)
     print(parity(m.cpu().numpy()[idx], _se(v.cpu().numpy()[idx]), om, _se(ov), name="icosphere full solve"))
     # reverse mode = weighted forward mode over all 65536 points and 1024 parameters
-    ud, _, _ = s.jvp(Xt, 64, 43, var=False)
+    ud, _, _ = s.jvp(Xt, 1024, 43, var=False)
     w = np.random.default_rng(10).normal(size=len(X))
-    g, _ = s.grad(Xt, T(w, dev), 64, 43)
+    g, _ = s.grad(Xt, T(w, dev), 1024, 43)
     g_fwd = (torch.tensor(w, device=dev)[:, None] * ud).sum(0)
     np.testing.assert_allclose(g.cpu().numpy(), g_fwd.cpu().numpy(), rtol=1e-9,
                                atol=1e-9 * float(g_fwd.abs().max()))
