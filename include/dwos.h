@@ -281,6 +281,26 @@ dwos_status dwos_batch_add_instance(dwos_ctx* ctx, const double* V, int64_t nv,
                                     const int32_t* prims, int64_t np, const int32_t* label,
                                     double sigma, double eps, double delta, int32_t* index);
 
+/* Parameter Jacobian of instance `index` (host arrays over that instance's
+ * own vertices, laid out as dwos_set_parameters' rowptr / pid / vel; N = 0
+ * clears it).  In dwos_batch_grad the parameters of instance i come after
+ * those of instances 0..i-1.  Errors: EINVAL (no such instance, bad N,
+ * rowptr, pid or velocity). */
+dwos_status dwos_batch_set_parameters(dwos_ctx* ctx, int32_t index, int64_t N, const int64_t* rowptr,
+                                      const int32_t* pid, const double* vel);
+
+/* Reverse mode over every instance in one persistent launch (Algorithm 2
+ * with each instance's constants, Sec. 5.3's weighted sum): grad (device,
+ * sum_i N_i FP64) = sum_p w_p udot(x_p) over all instances' points, X_all
+ * and w (device) back to back as in dwos_batch_solve, P (host) the counts;
+ * u_mean (device, sum_i P[i], or NULL) the joint u estimates.  Every instance
+ * must share delta (the offset of the normal derivative).
+ * Errors: EINVAL (counts, NULL arguments, differing delta), ESTATE (no
+ * instances, problem or parameters; control variate or gradient normal-
+ * derivative estimator set), ENOMEM (more than 2^26 walks). */
+dwos_status dwos_batch_grad(dwos_ctx* ctx, const double* X_all, const int64_t* P, const double* w,
+                            int32_t W, uint64_t seed, double* grad, double* u_mean, dwos_stats* stats);
+
 /* Solve every instance in one persistent launch: X_all (device) holds the
  * instances' points back to back (sum_i P[i] x dim), P (host, I counts),
  * W walks per point; u_mean/u_var (device, sum_i P[i]).  Errors as solve. */

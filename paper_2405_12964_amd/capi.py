@@ -81,6 +81,8 @@ def lib():
             "dwos_batch_add_instance": [vp, dp, C.c_int64, i32p, C.c_int64, i32p, C.c_double,
                                         C.c_double, C.c_double, i32p],
             "dwos_batch_solve": [vp, vp, i64p, C.c_int32, C.c_uint64, vp, vp, C.POINTER(dwos_stats)],
+            "dwos_batch_set_parameters": [vp, C.c_int32, C.c_int64, i64p, i32p, dp],
+            "dwos_batch_grad": [vp, vp, i64p, vp, C.c_int32, C.c_uint64, vp, vp, C.POINTER(dwos_stats)],
             "dwos_mlp_create": [C.c_int32, C.c_int32, C.POINTER(C.c_float), vp, C.POINTER(vp)],
             "dwos_mlp_set_params": [vp, vp],
             "dwos_mlp_get_params": [vp, vp],
@@ -131,7 +133,7 @@ EXPORTED = [
     "dwos_apply_parameters",
     "dwos_set_problem", "dwos_set_parameters", "dwos_solve", "dwos_grad", "dwos_grad_sqloss",
     "dwos_jvp", "dwos_walk_records", "dwos_closest", "dwos_eval_ball_kernels", "dwos_walk_timing",
-    "dwos_batch_add_instance", "dwos_batch_solve", "dwos_set_seed_buffer", "dwos_autotune",
+    "dwos_batch_add_instance", "dwos_batch_solve", "dwos_batch_set_parameters", "dwos_batch_grad", "dwos_set_seed_buffer", "dwos_autotune",
     "dwos_set_variant", "dwos_mlp_theta_size", "dwos_mlp_create", "dwos_mlp_destroy",
     "dwos_mlp_set_params", "dwos_mlp_get_params", "dwos_mlp_eval", "dwos_mlp_loss_grad",
     "dwos_mlp_vjp", "dwos_mlp_adam_step", "dwos_cv_attach", "dwos_cv_beta", "dwos_cv_train", "dwos_cv_walk_records",

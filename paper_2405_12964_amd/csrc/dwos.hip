@@ -60,6 +60,11 @@ struct dwos_ctx {
     std::vector<int32_t> hostOrder;
     bool batch_dirty = false;
     std::vector<unsigned char> inst_host;     // last uploaded instance table
+    // per-instance parameter Jacobians (instance-local vertices), combined
+    // into one Jacobian of the batch's vertex array before a batch gradient
+    struct BatchParams { int64_t N = 0; std::vector<int64_t> rowptr; std::vector<int32_t> pid; std::vector<double> vel; };
+    std::vector<BatchParams> batch_params;
+    bool batch_params_dirty = false;
     // problem
     bool has_problem = false;
     dwos_problem prob{};
@@ -1200,11 +1205,15 @@ dwos_status dwos_set_problem(dwos_ctx* c, const dwos_problem* p) {
     return DWOS_OK;
 }
 
-dwos_status dwos_set_parameters(dwos_ctx* c, int64_t N, const int64_t* rowptr, const int32_t* pid,
+}  // extern "C"
+
+namespace {
+
+// The parameter Jacobian of the context's (possibly combined batch) vertex
+// array: validation, parameter-sorted rows, the transpose, mapped-value
+// parameters and the per-primitive dependence flags.
+dwos_status set_parameters_impl(dwos_ctx* c, int64_t N, const int64_t* rowptr, const int32_t* pid,
                                 const double* vel, const int32_t* bc_pid) {
-    if (!c) return fail(DWOS_EINVAL, "NULL context");
-    if (!c->has_boundary) return fail(DWOS_ESTATE, "set_parameters: no boundary");
-    if (!c->instances.empty()) return fail(DWOS_ESTATE, "set_parameters: not supported on batch contexts");
     if (N < 1 || N > INT32_MAX || !rowptr) return fail(DWOS_EINVAL, "set_parameters: bad N or NULL rowptr");
     const int D = c->D;
     const int64_t nv = c->nv;
@@ -1292,6 +1301,18 @@ dwos_status dwos_set_parameters(dwos_ctx* c, int64_t N, const int64_t* rowptr, c
     c->N = N;
     c->has_params = true;
     return DWOS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dwos_status dwos_set_parameters(dwos_ctx* c, int64_t N, const int64_t* rowptr, const int32_t* pid,
+                                const double* vel, const int32_t* bc_pid) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (!c->has_boundary) return fail(DWOS_ESTATE, "set_parameters: no boundary");
+    if (!c->instances.empty()) return fail(DWOS_ESTATE, "set_parameters: not supported on batch contexts");
+    return set_parameters_impl(c, N, rowptr, pid, vel, bc_pid);
 }
 
 static dwos_status check_points(const double* X, int64_t P, int32_t W) {
@@ -1766,6 +1787,8 @@ dwos_status dwos_batch_add_instance(dwos_ctx* c, const double* V, int64_t nv, co
     c->hostV.insert(c->hostV.end(), V, V + nv * D);
     c->hostG.resize(c->hostV.size() / D, 0.0);
     c->instances.push_back({node_off, nv_off, np_off, sigma, eps, delta});
+    c->batch_params.emplace_back();
+    c->batch_params_dirty = true;
     c->batch_dirty = true;
     c->has_params = false;
     if (index) *index = (int32_t)c->instances.size() - 1;
@@ -1822,9 +1845,189 @@ dwos_status run_batch(dwos_ctx* c, const double* X, const int64_t* P, int32_t W,
     return finish_call(c, st, ev_from);
 }
 
+// Reverse mode over every instance in one persistent launch: the
+// differential walks with their instance constants, the per-vertex
+// scatter over the batch's vertex array and the SpMV with the combined
+// Jacobian (instance i's parameters after those of instances < i).
+template <class T, int D>
+dwos_status run_batch_grad(dwos_ctx* c, const double* X, const int64_t* P, const double* w, int32_t W,
+                           uint64_t seed, double* grad, double* u_mean, dwos_stats* st) {
+    hipStream_t s = c->stream;
+    const int n = (int)c->instances.size();
+    std::vector<dwos::Instance<T>> tab(n);
+    int64_t walks = 0, pts = 0;
+    for (int i = 0; i < n; ++i) {
+        tab[i].walk_begin = walks;
+        tab[i].point_begin = pts;
+        tab[i].p_counter = 0;
+        tab[i].root = c->instances[i].root;
+        tab[i].P = (int32_t)P[i];
+        tab[i].kappa = T(std::sqrt(c->instances[i].sigma));
+        tab[i].eps = T(c->instances[i].eps);
+        tab[i].delta = T(c->instances[i].delta);
+        walks += P[i] * W;
+        pts += P[i];
+    }
+    if (walks > (int64_t(1) << 26)) return fail(DWOS_ENOMEM, "batch_grad: more than 2^26 walks in one batch");
+    dwos_status rc = ensure_records<T>(c, std::max<int64_t>(1, walks), true, false);
+    if (rc) return rc;
+    rc = upload_instances<T>(c, tab.data(), tab.size());
+    if (rc) return rc;
+    const size_t ev_from = c->pending.size();
+    const dwos::Scene<T> scene = make_scene<T>(c);
+    HIP_OK(c->accA.reserve(c->nv * D * sizeof(double)));
+    HIP_OK(c->accB.reserve(c->nv * sizeof(double)));
+    hipLaunchKernelGGL(dwos::fill_f64_kernel, dim3(blocks_for(c->nv * D, 256)), dim3(256), 0, s,
+                       c->accA.as<double>(), c->nv * D);
+    hipLaunchKernelGGL(dwos::fill_f64_kernel, dim3(blocks_for(c->nv, 256)), dim3(256), 0, s,
+                       c->accB.as<double>(), c->nv);
+    if (pts > 0) {
+        HIP_OK(c->first_leaf.reserve(pts * sizeof(int32_t)));
+        HIP_OK(c->first_d2.reserve(pts * sizeof(T)));
+        hipLaunchKernelGGL((dwos::first_query_kernel<T, D>), dim3(blocks_for(pts, 64)), dim3(64), 0, s, scene,
+                           c->instbuf.as<dwos::Instance<T>>(), n, X, (int64_t)0, pts, c->first_leaf.as<int32_t>(),
+                           c->first_d2.as<T>());
+        dwos::WalkArgs<T> a = base_args<T>(c, X, W, seed);
+        a.inst = c->instbuf.as<dwos::Instance<T>>();
+        a.n_inst = n;
+        a.total = walks;
+        a.wid_offset = 0;
+        a.first_leaf = c->first_leaf.as<int32_t>();
+        a.first_d2 = c->first_d2.as<T>();
+        a.x_base = 0;
+        rc = launch_walks<T, D, 1>(c, a);
+        if (rc) return rc;
+        if (u_mean)
+            hipLaunchKernelGGL(dwos::point_stats_kernel<T>, dim3(blocks_for(pts, 4)), dim3(256), 0, s,
+                               c->rec_u.as<T>(), pts, W, u_mean, nullptr);
+        dwos::AccArgs<T> aa{};
+        aa.s = scene;
+        aa.prm = make_params<T>(c->prob);
+        aa.delta = T(c->instances[0].delta);   // one delta for the batch (checked by the caller)
+        aa.rec_u = c->rec_u.as<T>();
+        aa.rec_prim = c->rec_prim.as<int32_t>();
+        aa.rec_b = c->rec_b.as<T>();
+        aa.rec_uoff = c->rec_uoff.as<T>();
+        aa.nwalks = walks;
+        aa.p_offset = 0;
+        aa.W = W;
+        aa.B = 1;
+        aa.mode = 0;
+        aa.w = w;
+        aa.uref = nullptr;
+        aa.bc_pid = nullptr;
+        aa.prim_dep = c->prim_dep.as<int32_t>();
+        aa.vparam = c->vparam.as<int32_t>();
+        aa.A = c->accA.as<double>();
+        aa.Bacc = c->accB.as<double>();
+        hipLaunchKernelGGL((dwos::accumulate_kernel<T, D>), dim3(blocks_for(walks, 256)), dim3(256), 0, s, aa);
+    }
+    hipLaunchKernelGGL(dwos::spmv_kernel<D>, dim3(blocks_for(c->N, 4)), dim3(256), 0, s, make_csr(c),
+                       c->accA.as<double>(), c->accB.as<double>(), grad);
+    return finish_call(c, st, ev_from);
+}
+
 }  // namespace
 
 extern "C" {
+
+dwos_status dwos_batch_set_parameters(dwos_ctx* c, int32_t index, int64_t N, const int64_t* rowptr,
+                                     const int32_t* pid, const double* vel) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (index < 0 || index >= (int32_t)c->instances.size())
+        return fail(DWOS_EINVAL, "batch_set_parameters: no instance " + std::to_string(index));
+    const int D = c->D;
+    const int64_t nv0 = c->instances[index].nv_off;
+    const int64_t nv1 = index + 1 < (int32_t)c->instances.size() ? c->instances[index + 1].nv_off
+                                                                 : (int64_t)c->hostV.size() / D;
+    const int64_t nv = nv1 - nv0;
+    if (N < 0 || N > INT32_MAX) return fail(DWOS_EINVAL, "batch_set_parameters: bad N");
+    dwos_ctx::BatchParams bp;
+    bp.N = N;
+    if (N > 0) {
+        if (!rowptr) return fail(DWOS_EINVAL, "batch_set_parameters: NULL rowptr");
+        if (rowptr[0] != 0) return fail(DWOS_EINVAL, "batch_set_parameters: rowptr[0] must be 0");
+        for (int64_t i = 0; i < nv; ++i)
+            if (rowptr[i + 1] < rowptr[i]) return fail(DWOS_EINVAL, "batch_set_parameters: rowptr not monotone");
+        const int64_t nnz = rowptr[nv];
+        if (nnz > 0 && (!pid || !vel)) return fail(DWOS_EINVAL, "batch_set_parameters: NULL pid/vel");
+        for (int64_t e = 0; e < nnz; ++e) {
+            if (pid[e] < 0 || pid[e] >= N) return fail(DWOS_EINVAL, "batch_set_parameters: pid out of range");
+            for (int k = 0; k < D; ++k)
+                if (!std::isfinite(vel[e * D + k])) return fail(DWOS_EINVAL, "batch_set_parameters: non-finite velocity");
+        }
+        bp.rowptr.assign(rowptr, rowptr + nv + 1);
+        bp.pid.assign(pid, pid + nnz);
+        bp.vel.assign(vel, vel + nnz * D);
+    }
+    c->batch_params[index] = std::move(bp);
+    c->batch_params_dirty = true;
+    return DWOS_OK;
+}
+
+dwos_status dwos_batch_grad(dwos_ctx* c, const double* X_all, const int64_t* P, const double* w, int32_t W,
+                            uint64_t seed, double* grad, double* u_mean, dwos_stats* stats) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (c->instances.empty()) return fail(DWOS_ESTATE, "batch_grad: no instances");
+    if (!c->has_problem) return fail(DWOS_ESTATE, "batch_grad: no problem: call dwos_set_problem first");
+    if (c->cv) return fail(DWOS_ESTATE, "batch_grad: the control variate is not supported on batch contexts");
+    if (c->prob.dudn != 0) return fail(DWOS_ESTATE, "batch_grad: the gradient normal-derivative estimator is not supported on batch contexts");
+    if (!P || W < 1 || !grad) return fail(DWOS_EINVAL, "batch_grad: bad P, W or grad");
+    int64_t pts = 0, Ntot = 0;
+    for (size_t i = 0; i < c->instances.size(); ++i) {
+        if (P[i] < 0 || P[i] > INT32_MAX) return fail(DWOS_EINVAL, "batch_grad: bad point count");
+        pts += P[i];
+        Ntot += c->batch_params[i].N;
+        if (c->instances[i].delta != c->instances[0].delta)
+            return fail(DWOS_EINVAL, "batch_grad: every instance must have the same delta");
+    }
+    if (Ntot < 1) return fail(DWOS_ESTATE, "batch_grad: no parameters: call dwos_batch_set_parameters");
+    if (pts > 0 && (!X_all || !w)) return fail(DWOS_EINVAL, "batch_grad: NULL points or weights");
+    HIP_OK(hipSetDevice(c->device));
+    if (c->batch_dirty) {
+        dwos_status rc = c->prec == DWOS_FP32
+            ? upload_geometry<float>(c, c->hostV, c->hostP, c->hostL, c->hostG, c->hostNodes, c->hostOrder)
+            : upload_geometry<double>(c, c->hostV, c->hostP, c->hostL, c->hostG, c->hostNodes, c->hostOrder);
+        if (rc) return rc;
+        c->batch_dirty = false;
+        c->has_boundary = true;
+        c->batch_params_dirty = true;
+    }
+    if (c->batch_params_dirty || !c->has_params) {
+        // the combined Jacobian over the batch's vertex array
+        const int D = c->D;
+        const int64_t nv = (int64_t)c->hostV.size() / D;
+        std::vector<int64_t> rp(nv + 1, 0);
+        std::vector<int32_t> pv;
+        std::vector<double> vv;
+        int64_t poff = 0;
+        for (size_t i = 0; i < c->instances.size(); ++i) {
+            const auto& bp = c->batch_params[i];
+            const int64_t v0 = c->instances[i].nv_off;
+            const int64_t v1 = i + 1 < c->instances.size() ? c->instances[i + 1].nv_off : nv;
+            for (int64_t v = v0; v < v1; ++v) {
+                const int64_t lv = v - v0;
+                if (bp.N > 0)
+                    for (int64_t e = bp.rowptr[lv]; e < bp.rowptr[lv + 1]; ++e) {
+                        pv.push_back((int32_t)(bp.pid[e] + poff));
+                        for (int k = 0; k < D; ++k) vv.push_back(bp.vel[e * D + k]);
+                    }
+                rp[v + 1] = (int64_t)pv.size();
+            }
+            poff += bp.N;
+        }
+        dwos_status rc = set_parameters_impl(c, Ntot, rp.data(), pv.data(), vv.data(), nullptr);
+        if (rc) return rc;
+        c->batch_params_dirty = false;
+    }
+    dwos_status rc = begin_call(c, true);
+    if (rc) return rc;
+    if (c->prec == DWOS_FP32)
+        return c->D == 2 ? run_batch_grad<float, 2>(c, X_all, P, w, W, seed, grad, u_mean, stats)
+                         : run_batch_grad<float, 3>(c, X_all, P, w, W, seed, grad, u_mean, stats);
+    return c->D == 2 ? run_batch_grad<double, 2>(c, X_all, P, w, W, seed, grad, u_mean, stats)
+                     : run_batch_grad<double, 3>(c, X_all, P, w, W, seed, grad, u_mean, stats);
+}
 
 dwos_status dwos_batch_solve(dwos_ctx* c, const double* X_all, const int64_t* P, int32_t W, uint64_t seed,
                              double* u_mean, double* u_var, dwos_stats* stats) {

@@ -308,6 +308,36 @@ class Solver:
                                     C.byref(st) if st is not None else None))
         return (m, v, st.as_dict()) if stats else (m, v)
 
+    def batch_set_parameters(self, index, N, rowptr=None, pid=None, vel=None):
+        """Parameter Jacobian of instance ``index`` over its own vertices
+        (CSR by vertex, as set_parameters); its parameters follow those of
+        the instances before it in batch_grad's output."""
+        rp = None if rowptr is None else np.ascontiguousarray(rowptr, dtype=np.int64)
+        pd = None if pid is None else np.ascontiguousarray(pid, dtype=np.int32)
+        vl = None if vel is None else np.ascontiguousarray(vel, dtype=np.float64)
+        check(capi.dwos_batch_set_parameters(self._ctx, int(index), int(N), _lp(rp) if rp is not None else None,
+                                             _ip(pd) if pd is not None else None,
+                                             _dp(vl) if vl is not None else None))
+        self._batch_N = getattr(self, "_batch_N", {})
+        self._batch_N[int(index)] = int(N)
+
+    def batch_grad(self, X_all, P, w, W, seed, u_mean=True, stats=False):
+        """Reverse mode over every instance in one launch: the gradient with
+        respect to all instances' parameters, instance by instance."""
+        X_all = self._X(X_all)
+        Pn = np.ascontiguousarray(P, dtype=np.int64)
+        tot = int(Pn.sum())
+        if tot != X_all.shape[0]:
+            raise ValueError("sum of P must equal the number of points")
+        N = sum(getattr(self, "_batch_N", {}).values())
+        g = torch.empty(max(1, N), dtype=torch.float64, device=X_all.device)
+        um = torch.empty(tot, dtype=torch.float64, device=X_all.device) if u_mean else None
+        st = capi.dwos_stats() if stats else None
+        check(capi.dwos_batch_grad(self._ctx, _dev(X_all), _lp(Pn), _dev(w), int(W), int(seed), _dev(g), _dev(um),
+                                   C.byref(st) if st is not None else None))
+        g = g[:N]
+        return (g, um, st.as_dict()) if stats else (g, um)
+
     def autotune(self, X, W, seed=0):
         """Pick the faster walk-kernel launch shape on a sample of X; returns
         (variant, [ms variant 0, ms variant 1])."""
