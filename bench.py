@@ -269,6 +269,20 @@ def run_c4(args):
     torch.cuda.synchronize()
     elapsed_seq = time.perf_counter() - t1
     steps_total = tot["steps"]
+    # reverse mode over the same batch: every instance's radial-basis
+    # coefficients, all differential walks (K = 1) in one launch
+    for i, (sc, _) in enumerate(insts):
+        s.batch_set_parameters(i, sc.N, sc.rowptr, sc.pid, sc.vel)
+    wts = torch.cat([torch.full((len(x),), 1.0 / len(x), dtype=torch.float64, device=dev) for _, x in insts])
+    s.batch_grad(X, P, wts, W, 2, u_mean=False)
+    torch.cuda.synchronize()
+    s.walk_timing(1, reset=True)
+    t2 = time.perf_counter()
+    for i in range(args.steps):
+        s.batch_grad(X, P, wts, W, 20 + i, u_mean=False)
+    torch.cuda.synchronize()
+    elapsed_g = time.perf_counter() - t2
+    ms_g, n_g, tot_g = s.walk_timing(1)
     return {
         "metric": METRIC, "value": steps_total / elapsed, "unit": "walk-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": 1, "ms_per_step": 1e3 * elapsed / args.steps,
@@ -281,6 +295,8 @@ def run_c4(args):
         "walk_kernel_ms": ms / max(1, n),
         "per_instance_launches": {"ms_per_step": 1e3 * elapsed_seq / args.steps,
                                   "speedup_of_one_launch": elapsed_seq / elapsed},
+        "batch_grad": {"ms_per_call": 1e3 * elapsed_g / args.steps, "walk_steps_per_s": tot_g["steps"] / elapsed_g,
+                       "params": int(sum(sc.N for sc, _ in insts)), "walk_kernel_ms": ms_g / max(1, n_g)},
     }
 
 

@@ -297,7 +297,7 @@ dwos_status dwos_batch_set_parameters(dwos_ctx* ctx, int32_t index, int64_t N, c
  * must share delta (the offset of the normal derivative).
  * Errors: EINVAL (counts, NULL arguments, differing delta), ESTATE (no
  * instances, problem or parameters; control variate or gradient normal-
- * derivative estimator set), ENOMEM (more than 2^26 walks). */
+ * derivative estimator set), ENOMEM (more than 2^28 walks). */
 dwos_status dwos_batch_grad(dwos_ctx* ctx, const double* X_all, const int64_t* P, const double* w,
                             int32_t W, uint64_t seed, double* grad, double* u_mean, dwos_stats* stats);
 

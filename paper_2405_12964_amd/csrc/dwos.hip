@@ -1868,7 +1868,7 @@ dwos_status run_batch_grad(dwos_ctx* c, const double* X, const int64_t* P, const
         walks += P[i] * W;
         pts += P[i];
     }
-    if (walks > (int64_t(1) << 26)) return fail(DWOS_ENOMEM, "batch_grad: more than 2^26 walks in one batch");
+    if (walks > (int64_t(1) << 28)) return fail(DWOS_ENOMEM, "batch_grad: more than 2^28 walks in one batch");
     dwos_status rc = ensure_records<T>(c, std::max<int64_t>(1, walks), true, false);
     if (rc) return rc;
     rc = upload_instances<T>(c, tab.data(), tab.size());
