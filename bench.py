@@ -610,7 +610,8 @@ def main():
                          "on an implicit boundary of harmonic monopoles")
     ap.add_argument("--points", type=int, default=0)
     ap.add_argument("--walks", type=int, default=0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle timing (and, for the default workload, the fixed-RMSE gradient rate)")
     ap.add_argument("--cv-freq", type=float, default=0.125, help="c5: Fourier frequency scale")
     ap.add_argument("--cv-features", type=int, default=30, help="c5: Fourier frequencies (2F + 3 <= 64)")
     ap.add_argument("--cv-steps", type=int, default=16, help="c5: network Adam steps per iteration")
@@ -740,9 +741,41 @@ def main():
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
+        out["fixed_rmse"] = fixed_rmse_rate(model, pi, Xt, uref, W)
         threads = min(16, len(os.sched_getaffinity(0)))
         out["cpu_baseline"] = cpu_baseline(sc, X, uref.cpu().numpy(), 7, threads)
     print(json.dumps(out), flush=True)
+
+
+def fixed_rmse_rate(model, pi, Xt, uref, W, target=0.1, W_probe=512, reps=4):
+    """Shape-gradient evaluations per second at a fixed RMSE (the second
+    half of the metric), after the timed window: the reverse-mode gradient
+    with weights w = u - uref at the final coefficients; the reference g*
+    from 64 W walks per point; the RMSE at W_probe walks over `reps` seeds,
+    extrapolated by RMSE ~ W^-1/2 to the walks per point W* that give
+    RMSE = target ||g*||_RMS; the rate is timed at W*."""
+    import numpy as np
+    import torch
+    with torch.no_grad():
+        model.apply(pi)
+        u, _ = model.solver.solve(Xt, W, 777)
+        w = (u - uref).contiguous()
+    gstar = model.solver.grad(Xt, w, 64 * W, 4242, u_mean=False)[0].cpu().numpy()
+    rms = lambda v: float(np.sqrt(np.mean(np.square(v))))
+    errs = [rms(model.solver.grad(Xt, w, W_probe, 5000 + r, u_mean=False)[0].cpu().numpy() - gstar)
+            for r in range(reps)]
+    rmse = float(np.sqrt(np.mean(np.square(errs))))
+    Wstar = max(1, int(math.ceil(W_probe * (rmse / (target * rms(gstar))) ** 2)))
+    model.solver.grad(Xt, w, Wstar, 6000, u_mean=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(3):
+        model.solver.grad(Xt, w, Wstar, 6001 + r, u_mean=False)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / 3
+    return {"target_rel_rmse": target, "walks_per_point": Wstar, "grad_evals_per_s": 1.0 / t,
+            "ms_per_grad": 1e3 * t, "rmse_at_probe": rmse, "probe_walks_per_point": W_probe,
+            "reference_walks_per_point": 64 * W, "grad_rms": rms(gstar)}
 
 
 if __name__ == "__main__":
