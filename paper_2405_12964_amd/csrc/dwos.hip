@@ -711,6 +711,13 @@ dwos_status begin_call(dwos_ctx* c, bool need_params) {
     return ensure_totals(c);
 }
 
+// Entry points of a single problem (not a batch context's instances).
+dwos_status single_call(dwos_ctx* c, bool need_params) {
+    if (c && !c->instances.empty())
+        return fail(DWOS_ESTATE, "batch context: use dwos_batch_solve / dwos_batch_grad");
+    return begin_call(c, need_params);
+}
+
 dwos_status finish_call(dwos_ctx* c, dwos_stats* st, size_t ev_from) {
     HIP_OK(hipGetLastError());
     if (!st) return DWOS_OK;
@@ -1325,7 +1332,7 @@ static dwos_status check_points(const double* X, int64_t P, int32_t W) {
 
 dwos_status dwos_solve(dwos_ctx* c, const double* X, int64_t P, int32_t W, uint64_t seed, double* u_mean,
                        double* u_var, dwos_stats* stats) {
-    dwos_status rc = begin_call(c, false);
+    dwos_status rc = single_call(c, false);
     if (rc) return rc;
     if ((rc = check_points(X, P, W))) return rc;
     if (P > 0 && !u_mean) return fail(DWOS_EINVAL, "solve: NULL u_mean");
@@ -1337,7 +1344,7 @@ dwos_status dwos_solve(dwos_ctx* c, const double* X, int64_t P, int32_t W, uint6
 
 dwos_status dwos_grad(dwos_ctx* c, const double* X, int64_t P, const double* w, int32_t W, uint64_t seed,
                       double* grad, double* u_mean, dwos_stats* stats) {
-    dwos_status rc = begin_call(c, true);
+    dwos_status rc = single_call(c, true);
     if (rc) return rc;
     if ((rc = check_points(X, P, W))) return rc;
     if (!grad || (P > 0 && !w)) return fail(DWOS_EINVAL, "grad: NULL grad or w");
@@ -1348,7 +1355,7 @@ dwos_status dwos_grad(dwos_ctx* c, const double* X, int64_t P, const double* w, 
 
 dwos_status dwos_grad_sqloss(dwos_ctx* c, const double* X, int64_t P, const double* u_ref, int32_t W, int32_t B,
                              uint64_t seed, double* loss, double* grad, double* u_mean, dwos_stats* stats) {
-    dwos_status rc = begin_call(c, true);
+    dwos_status rc = single_call(c, true);
     if (rc) return rc;
     if ((rc = check_points(X, P, W))) return rc;
     if (B < 2 || W % B != 0) return fail(DWOS_EINVAL, "grad_sqloss: need B >= 2 and W % B == 0");
@@ -1362,7 +1369,7 @@ dwos_status dwos_grad_sqloss(dwos_ctx* c, const double* X, int64_t P, const doub
 
 dwos_status dwos_jvp(dwos_ctx* c, const double* X, int64_t P, int32_t W, uint64_t seed, double* udot,
                      double* udot_var, double* u_mean, dwos_stats* stats) {
-    dwos_status rc = begin_call(c, true);
+    dwos_status rc = single_call(c, true);
     if (rc) return rc;
     if ((rc = check_points(X, P, W))) return rc;
     if (P > 0 && !udot) return fail(DWOS_EINVAL, "jvp: NULL udot");
@@ -1374,7 +1381,7 @@ dwos_status dwos_jvp(dwos_ctx* c, const double* X, int64_t P, int32_t W, uint64_
 
 dwos_status dwos_walk_records(dwos_ctx* c, const double* X, int64_t P, int32_t W, uint64_t seed, int32_t mode,
                               double* u, int64_t* steps, int32_t* prim, double* uoff, double* udot) {
-    dwos_status rc = begin_call(c, mode == 1 && udot != nullptr);
+    dwos_status rc = single_call(c, mode == 1 && udot != nullptr);
     if (rc) return rc;
     if ((rc = check_points(X, P, W))) return rc;
     if (mode != 0 && mode != 1) return fail(DWOS_EINVAL, "walk_records: mode must be 0 or 1");
@@ -1467,7 +1474,7 @@ dwos_status dwos_cv_train(dwos_ctx* c, int32_t steps, int32_t batch, float lr, u
 
 dwos_status dwos_cv_walk_records(dwos_ctx* c, const double* X, int64_t P, int32_t W, uint64_t seed,
                                  double* walk, double* nested) {
-    dwos_status rc = begin_call(c, false);
+    dwos_status rc = single_call(c, false);
     if (rc) return rc;
     if ((rc = check_points(X, P, W))) return rc;
     if (!c->cv) return fail(DWOS_ESTATE, "cv_walk_records: no network attached");
@@ -1486,6 +1493,7 @@ dwos_status dwos_cv_walk_records(dwos_ctx* c, const double* X, int64_t P, int32_
 dwos_status dwos_closest(dwos_ctx* c, const double* X, int64_t P, double* out) {
     if (!c) return fail(DWOS_EINVAL, "NULL context");
     if (!c->has_boundary) return fail(DWOS_ESTATE, "closest: no boundary");
+    if (!c->instances.empty()) return fail(DWOS_ESTATE, "closest: batch context");
     if (P < 0 || (P > 0 && (!X || !out))) return fail(DWOS_EINVAL, "closest: bad arguments");
     if (P == 0) return DWOS_OK;
     HIP_OK(hipSetDevice(c->device));
@@ -1683,6 +1691,7 @@ dwos_status dwos_set_variant(dwos_ctx* c, int32_t variant) {
 dwos_status dwos_autotune(dwos_ctx* c, const double* X, int64_t P, int32_t W, uint64_t seed, int32_t* chosen,
                           double* ms) {
     if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (!c->instances.empty()) return fail(DWOS_ESTATE, "autotune: batch context");
     if (P <= 0 || W < 1 || !X) return fail(DWOS_EINVAL, "autotune: need points and W >= 1");
     const int64_t Ps = std::min<int64_t>(P, 512);
     DevBuf mean;

@@ -7,7 +7,8 @@
 * FP32: two screened disks of different radius and screening, g = 1, each
   with its radius as parameter: each slice against the closed form
   mean_p du/dR = -mean_p I0(k r_p) k I1(k R) / I0(k R)^2.
-* Error paths: instances with different delta, no parameters.
+* Error paths: instances with different delta, no parameters, single-problem
+  calls on a batch context.
 """
 import numpy as np
 import pytest
@@ -104,3 +105,8 @@ def test_batch_grad_error_paths(dev, dwos):
     with pytest.raises(DwosError) as e:
         s.batch_set_parameters(5, 1, a.rowptr, a.pid, a.vel)
     assert e.value.code == DWOS_EINVAL
+    # single-problem calls on a batch context
+    for call in (lambda: s.solve(X, 4, 1), lambda: s.grad(X, w, 4, 1), lambda: s.closest(X)):
+        with pytest.raises(DwosError) as e:
+            call()
+        assert e.value.code == DWOS_ESTATE
