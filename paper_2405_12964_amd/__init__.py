@@ -12,5 +12,7 @@ from .solver import Solver, make_problem  # noqa: F401
 from .autograd import DWoSFunction, ShapeModel  # noqa: F401
 from .cv import Network  # noqa: F401
 from .opt import LargeSteps  # noqa: F401
+from .shapeopt import VertexShapeOptimizer, ImplicitShapeOptimizer  # noqa: F401
 
-__all__ = ["Solver", "make_problem", "DWoSFunction", "ShapeModel", "Network", "LargeSteps", "DwosError", "lib"]
+__all__ = ["Solver", "make_problem", "DWoSFunction", "ShapeModel", "Network", "LargeSteps", "VertexShapeOptimizer",
+           "ImplicitShapeOptimizer", "DwosError", "lib"]

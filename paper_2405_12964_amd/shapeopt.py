@@ -132,3 +132,70 @@ class VertexShapeOptimizer:
         self.solver.update_vertices(self.x)
         self.t += 1
         return 0.5 * float(((u - uref) ** 2).sum()), W, its
+
+
+class ImplicitShapeOptimizer:
+    """Curve inflation on an implicit boundary (Sec. 7.4): the monopoles
+    (a_n, p_n) of h = c + sum_n a_n / |x - p_n| fitted so that the height
+    field matches a reference uref at the pixel centres X (each of area dA)
+    over the whole image, the height being u inside the domain and 0
+    outside it.
+
+    The derivative takes the paper's two parts: the volume term over the
+    pixels inside the domain beyond the band (squared-loss U-statistic, W
+    walks per pixel in one batch), and the band term (one-sided band of
+    width eps_band, weight dA / eps_band).  A pixel that the boundary sweeps
+    over trades its outside loss uref^2/2 for l(u) = (u - uref)^2/2, so the
+    band integrand is l(u) - uref^2/2 = u^2/2 - u uref, with u at the band
+    pixels from W forward walks (u^2 taken as mean^2 minus the variance of
+    the mean, which is unbiased).  With zero boundary data this term is of
+    the order of the band width.  After each Adam step on the 3n
+    coordinates the scales are kept >= a_min and the new monopoles are
+    uploaded (dwos_set_implicit)."""
+
+    def __init__(self, scene, X: torch.Tensor, uref: torch.Tensor, dA: float, eps_band: float,
+                 lr=2e-3, W=4, a_min=1e-3, precision="fp32"):
+        self.solver = Solver.from_scene(scene, precision)
+        self.c = float(scene.mono_c)
+        self.X, self.uref, self.dA, self.eps_band = X, uref, float(dA), float(eps_band)
+        self.W, self.a_min = int(W), float(a_min)
+        self.pi = torch.tensor(np.asarray(scene.mono, float).ravel(), dtype=torch.float64, device=X.device,
+                               requires_grad=True)
+        self.opt = torch.optim.Adam([self.pi], lr=lr)
+        self._zero = torch.zeros(X.shape[0], dtype=torch.float64, device=X.device)
+        self.region = None
+        self.t = 0
+
+    @property
+    def mono(self) -> np.ndarray:
+        return self.pi.detach().view(-1, 3).cpu().numpy()
+
+    def regions(self) -> torch.Tensor:
+        """Per pixel: 0 outside the domain, 1 in the band, 2 inside beyond it."""
+        return self.solver.implicit_band_grad(self.X, self._zero, self.eps_band, want_mask=True)[1]
+
+    def step(self, seed: int):
+        """One iteration; returns (image loss, pixels inside beyond the band)."""
+        region = self.regions()
+        inner = torch.nonzero(region == 2).squeeze(1)
+        band = torch.nonzero(region == 1).squeeze(1)
+        out = self.uref[region == 0]
+        L, gd, _ = self.solver.grad_sqloss(self.X[inner].contiguous(), self.uref[inner].contiguous(), self.W,
+                                           self.W, seed)
+        grad = self.dA * gd
+        lb = 0.0
+        if band.numel():
+            Xb, ub_ref = self.X[band].contiguous(), self.uref[band]
+            ub, vb = self.solver.solve(Xb, self.W, (seed * 0x9E3779B1 + 0x7F4A7C15) & 0xFFFFFFFF)
+            coef = (self.dA / self.eps_band) * (0.5 * (ub * ub - vb) - ub * ub_ref)
+            self.solver.implicit_band_grad(Xb, coef.contiguous(), self.eps_band, grad=grad)
+            lb = 0.5 * float(((ub - ub_ref) ** 2).sum())
+        loss = self.dA * (float(L) + lb + 0.5 * float((out * out).sum()))
+        self.pi.grad = grad
+        self.opt.step()
+        with torch.no_grad():
+            self.pi.view(-1, 3)[:, 0].clamp_(min=self.a_min)
+        self.solver.set_implicit(self.mono, self.c)
+        self.region = region
+        self.t += 1
+        return loss, int(inner.numel())
