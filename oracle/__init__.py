@@ -79,6 +79,8 @@ def lib():
                                   C.c_double, C.c_int64]
         L.oracle_walk_records_cv.argtypes = [sp, cvp, dp, C.c_int64, C.c_int32, C.c_uint64,
                                              C.c_int32, dp, dp, C.c_int]
+        L.oracle_adjoint_grad.argtypes = [sp, ip, dp, dp, C.c_int64, dp, C.c_int32, C.c_uint64, dp, dp, dp,
+                                          lp, C.c_int]
         _lib = L
     return _lib
 
@@ -304,6 +306,30 @@ class Oracle:
         rc = lib().oracle_safe_radius(C.byref(self._s), _ptr(x, C.c_double), _ptr(out, C.c_double))
         assert rc == 0
         return float(out[1 if harnack else 0])
+
+    def adjoint_grad(self, code, bary, wq, ref, W, seed):
+        """Adjoint formulation (Appendix B) of the squared-loss shape
+        derivative over the domain, uref(x) = c + b.x + x^T A x with
+        ref = (c, b, A): boundary samples (prim * 2 + flip, barycentrics
+        b1 (, b2), quadrature weights), W walks each.  Returns (grad,
+        per-walk adjoint estimates at the offset points, per-walk offset
+        means, per-walk step counts), the records S x W."""
+        D = self.scene.dim
+        code = np.ascontiguousarray(code, dtype=np.int32)
+        S = len(code)
+        bary = np.ascontiguousarray(np.asarray(bary, float).reshape(S, D - 1))
+        wq = np.ascontiguousarray(wq, dtype=np.float64)
+        ref = np.ascontiguousarray(ref, dtype=np.float64)
+        assert ref.size == 1 + D + D * D
+        g = np.zeros(self.scene.N)
+        lam, uoff, st = np.zeros((S, W)), np.zeros((S, W)), np.zeros((S, W), np.int64)
+        rc = lib().oracle_adjoint_grad(C.byref(self._s), _ptr(code, C.c_int32), _ptr(bary, C.c_double),
+                                       _ptr(wq, C.c_double), C.c_int64(S), _ptr(ref, C.c_double), W, seed,
+                                       _ptr(g, C.c_double), _ptr(lam, C.c_double), _ptr(uoff, C.c_double),
+                                       _ptr(st, C.c_int64), self.threads)
+        if rc != 0:
+            raise ValueError("oracle_adjoint_grad: invalid arguments")
+        return g, lam, uoff, st
 
     def band_grad(self, X, coef, eps_band):
         """Band term on an implicit boundary: (sum over the points in the band

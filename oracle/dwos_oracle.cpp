@@ -20,6 +20,9 @@
 //     (eq. (boundary_deriv_mapped), Appendix A).
 //   * Reverse-mode accumulation with the U-statistic product estimator
 //     (Sec. 5.3, eq. (ustatistics)).
+//   * The adjoint formulation of the shape derivative (Appendix B), the
+//     paper's rejected alternative, as an ablation: an adjoint walk whose
+//     source is a whole forward walk at every step, on boundary samples.
 // Closest points are found by brute force over every primitive, ties going to
 // the lowest primitive index.  Random numbers come from Philox4x32-10
 // (Salmon, Moraes, Dror, Shaw, SC'11), written here from its definition.
@@ -1116,6 +1119,54 @@ void cv_combine(const Scene& sc, const oracle_cv& cv, DiffOut& o) {
 }
 
 // ---------------------------------------------------------------------------
+// Boundary value of the differential problem at the boundary point h with
+// outward normal n, for every parameter j (eq. (boundary_deriv_restricted);
+// for mapped data eq. (boundary_deriv_mapped) with the tangential components
+// of the velocity kept explicitly, Appendix A), given du/dn there.  vn, if
+// given, receives the normal velocity V_n,j = n . V_j.
+// ---------------------------------------------------------------------------
+void boundary_udot(const Scene& sc, const Hit& h, const double* n, double dudn, std::vector<double>& udot,
+                   std::vector<double>* vn) {
+    const int D = sc.D;
+    const int N = sc.s.N;
+    udot.assign(N, 0.0);
+    if (vn) vn->assign(N, 0.0);
+    // velocity field at xbar for each parameter: V_j = sum_k b_k dv_{i_k}/dpi_j
+    std::vector<double> Vj((size_t)N * 3, 0.0);
+    std::vector<char> touched(N, 0);
+    std::vector<double> gdot(N, 0.0);
+    for (int kk = 0; kk < D; ++kk) {
+        int vi = sc.pv(h.prim, kk);
+        for (int64_t e = sc.s.rowptr[vi]; e < sc.s.rowptr[vi + 1]; ++e) {
+            int j = sc.s.pid[e];
+            touched[j] = 1;
+            for (int c = 0; c < D; ++c) Vj[(size_t)j * 3 + c] += h.bary[kk] * sc.s.vel[e * D + c];
+        }
+        if (sc.s.bc_pid && sc.s.bc_pid[vi] >= 0 && sc.mapped(h.prim)) {
+            gdot[sc.s.bc_pid[vi]] += h.bary[kk];
+            touched[sc.s.bc_pid[vi]] = 1;
+        }
+    }
+    bool mp = sc.mapped(h.prim);
+    double gr[3];
+    if (mp) sc.grad_surface(h, gr); else sc.grad_field(h, gr);
+    double dgdn = dot(gr, n, D);
+    for (int j = 0; j < N; ++j) {
+        if (!touched[j]) continue;
+        const double* V = &Vj[(size_t)j * 3];
+        double Vn = dot(n, V, D);
+        if (vn) (*vn)[j] = Vn;
+        if (mp) {
+            // gdot_ref - grad_G g . V - V_n du/dn
+            udot[j] = gdot[j] - dot(gr, V, D) - Vn * dudn;
+        } else {
+            // eq. (boundary_deriv_restricted): gdot_field (= 0) + (dg/dn - du/dn) V_n
+            udot[j] = (dgdn - dudn) * Vn;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Algorithm 2: DiffWalkOnSpheres(x, eps, delta).  The walk follows the same
 // steps (and random numbers) as Algorithm 1 so that it also returns the joint
 // estimate of u.  At the shell it launches K forward walks from the offset
@@ -1204,42 +1255,7 @@ DiffOut diff_walk_on_spheres(const Scene& sc, const double* x0, const Stream& st
             out.terminal = true;
             out.prim = h.prim;
             for (int i = 0; i < 3; ++i) out.xbar[i] = h.xbar[i];
-            if (want_udot) {
-                // velocity field at xbar for each parameter: V_j = sum_k b_k dv_{i_k}/dpi_j
-                std::vector<double> Vj((size_t)N * 3, 0.0);
-                std::vector<char> touched(N, 0);
-                std::vector<double> gdot(N, 0.0);
-                for (int kk = 0; kk < D; ++kk) {
-                    int vi = sc.pv(h.prim, kk);
-                    for (int64_t e = sc.s.rowptr[vi]; e < sc.s.rowptr[vi + 1]; ++e) {
-                        int j = sc.s.pid[e];
-                        touched[j] = 1;
-                        for (int c = 0; c < D; ++c) Vj[(size_t)j * 3 + c] += h.bary[kk] * sc.s.vel[e * D + c];
-                    }
-                    if (sc.s.bc_pid && sc.s.bc_pid[vi] >= 0 && sc.mapped(h.prim)) {
-                        gdot[sc.s.bc_pid[vi]] += h.bary[kk];
-                        touched[sc.s.bc_pid[vi]] = 1;
-                    }
-                }
-                bool mp = sc.mapped(h.prim);
-                double gr[3];
-                if (mp) sc.grad_surface(h, gr); else sc.grad_field(h, gr);
-                double dgdn = dot(gr, n, D);
-                for (int j = 0; j < N; ++j) {
-                    if (!touched[j]) continue;
-                    const double* V = &Vj[(size_t)j * 3];
-                    double Vn = dot(n, V, D);
-                    double val;
-                    if (mp) {
-                        // gdot_ref - grad_G g . V - V_n du/dn
-                        val = gdot[j] - dot(gr, V, D) - Vn * dudn;
-                    } else {
-                        // eq. (boundary_deriv_restricted): gdot_field (= 0) + (dg/dn - du/dn) V_n
-                        val = (dgdn - dudn) * Vn;
-                    }
-                    out.udot[j] = val;
-                }
-            }
+            if (want_udot) boundary_udot(sc, h, n, dudn, out.udot, nullptr);
             return out;
         }
         if (sc.has_neumann()) {
@@ -1416,11 +1432,181 @@ DiffOut diff_walk(const Scene& sc, const double* x, const Start& s0, const Strea
     return diff_walk_on_spheres(sc, x, st, c, want_udot, cv, s0.on, s0.nin);
 }
 
+// ---------------------------------------------------------------------------
+// The adjoint formulation of the shape derivative (Appendix B, eq.
+// (functional_deriv_adjoint)), which the paper sets against Algorithm 2 and
+// rejects for its quadratic nesting; built here as that ablation.  For the
+// squared loss J = int_Omega l(u), l(u) = 1/2 (u - uref)^2, with a quadratic
+// reference uref(x) = c + b.x + x^T A x, the adjoint solves
+//   -Lap lambda + sigma lambda = l'(u) = u - uref  in Omega,  lambda = 0 on
+//   the boundary
+// (eq. (bvp_adjoint) writes the operator with the other sign, so its adjoint
+// is minus this one), and Green's second identity turns the domain term of
+// eq. (functional_deriv) into a boundary integral:
+//   dJ/dpi_j = int_boundary [ -dlambda/dn udot_j + l(g) V_n,j ] dsigma,
+// udot_j the boundary value of the differential problem (as at a terminal of
+// Algorithm 2), l(g) V_n,j the boundary term of eq. (functional_deriv), which
+// the printed adjoint formula leaves out (it vanishes where uref = g).
+// At a boundary sample y with outward normal n, dlambda/dn is the backward
+// difference (0 - lambda(y - delta n)) / delta and du/dn the backward
+// difference of the mean of K forward walks from the same offset point.
+// ---------------------------------------------------------------------------
+double uref_quad(int D, const double* q, const double* x) {
+    double v = q[0];
+    for (int i = 0; i < D; ++i) v += q[1 + i] * x[i];
+    for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) v += x[i] * q[1 + D + i * D + j] * x[j];
+    return v;
+}
+
+// Random streams of one adjoint sample walk (key = seed, counter (k, m, s,
+// purpose)): purpose 0x10 the adjoint walk's step k (0x12 its second draw in
+// 3D), 0x20 | k' << 8 the forward walk at the source point of adjoint step
+// k', 0x30 | i << 8 the i-th forward walk from the offset point.
+constexpr uint32_t kAdjStep = 0x10u, kAdjSource = 0x20u, kAdjOffset = 0x30u;
+
+// Algorithm 1 for the adjoint problem: zero boundary data, and at every step
+// the source term G |B| l'(u(y)) at a uniform point y of the ball, with u(y)
+// from a whole forward walk started at y.
+double adjoint_walk(const Scene& sc, const double* x0, const double* ref, const Stream& st, WalkCount& cnt,
+                    int64_t& nested_steps) {
+    const int D = sc.D;
+    double x[3] = {0, 0, 0};
+    for (int i = 0; i < D; ++i) x[i] = x0[i];
+    double acc = 0.0;
+    for (uint32_t k = 0;; ++k) {
+        Hit h = sc.closest(x);
+        cnt.steps++;
+        double d = std::sqrt(h.d2);
+        bool cap = (int64_t)k + 1 >= sc.s.kmax;
+        if (d < sc.s.eps || cap) {
+            if (cap && !(d < sc.s.eps)) cnt.truncated++;
+            return acc;                                     // lambda = 0 on the boundary
+        }
+        uint32_t w[4];
+        st.draw(k, kAdjStep, w);
+        uint32_t wb[4] = {w[1], 0, 0, 0};
+        if (D == 3) st.draw(k, kAdjStep | 2u, wb);
+        double dir[3];
+        sphere_dir(D, wb[0], wb[1], dir);
+        double rad = d * std::pow(u24pos(w[3]), 1.0 / D);
+        double y[3] = {0, 0, 0};
+        for (int i = 0; i < D; ++i) y[i] = x[i] + rad * dir[i];
+        WalkCount c2;
+        const double uy = walk_on_spheres(sc, y, st, kAdjSource | (k << 8), c2);
+        nested_steps += c2.steps;
+        cnt.truncated += c2.truncated;
+        acc += green(D, sc.s.sigma, rad, d) * ball_volume(D, d) * (uy - uref_quad(D, ref, y));
+        double alpha = poisson_scale(D, sc.s.sigma, d);
+        if (sc.s.rr && alpha < u24(w[2])) return acc;
+        double s[3];
+        sphere_dir(D, w[0], w[1], s);
+        for (int i = 0; i < D; ++i) x[i] += d * s[i];
+    }
+}
+
+// Outward normal of primitive `prim` from a side code: the geometric normal
+// (segment a->b: (b - a) turned clockwise; triangle: (b - a) x (c - a)),
+// negated when the code's flip bit is set.
+void side_normal(const Scene& sc, int prim, int flip, double n[3]) {
+    const int D = sc.D;
+    n[0] = n[1] = n[2] = 0;
+    if (D == 2) {
+        const double* a = sc.vert(sc.pv(prim, 0));
+        const double* b = sc.vert(sc.pv(prim, 1));
+        double tx = b[0] - a[0], ty = b[1] - a[1];
+        double L = std::sqrt(tx * tx + ty * ty);
+        n[0] = ty / L; n[1] = -tx / L;
+    } else {
+        const double* a = sc.vert(sc.pv(prim, 0));
+        const double* b = sc.vert(sc.pv(prim, 1));
+        const double* c = sc.vert(sc.pv(prim, 2));
+        double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+        double e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+        double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        double L = std::sqrt(dot(cr, cr, 3));
+        for (int i = 0; i < 3; ++i) n[i] = cr[i] / L;
+    }
+    if (flip) for (int i = 0; i < 3; ++i) n[i] = -n[i];
+}
+
 }  // namespace
 
 extern "C" {
 
 int oracle_threads(void) { return (int)std::max(1u, std::thread::hardware_concurrency()); }
+
+// Adjoint formulation (Appendix B) of the squared-loss shape derivative:
+// S boundary samples (primitive code = prim * 2 + flip, barycentrics
+// b1 (, b2), quadrature weight wq), W walks each; grad (N) receives
+//   sum_s wq_s / W sum_m [ lambda_m / delta udot_j(y_s; uoff_m) + l(g) V_n,j ]
+// (lambda_m the adjoint estimate at the offset point, uoff_m the mean of the
+// K forward walks there).  lam, uoff, steps (S x W, may be NULL) receive the
+// per-walk records (steps: all walks of the record, nested included).
+int oracle_adjoint_grad(const oracle_scene* s, const int32_t* code, const double* bary, const double* wq,
+                        int64_t S, const double* ref, int32_t W, uint64_t seed, double* grad, double* lam,
+                        double* uoff, int64_t* steps, int threads) {
+    if (check_scene(s) || s->n_ns > 0 || s->n_mono > 0 || s->dudn != 0 || W < 1 || S < 0 || !ref) return 1;
+    if (s->N < 0 || (s->N > 0 && !s->rowptr)) return 1;
+    for (int64_t i = 0; i < S; ++i)
+        if (code[i] < 0 || (code[i] >> 1) >= s->np) return 1;
+    Scene sc(*s);
+    const int D = s->dim;
+    const int N = s->N;
+    if (threads <= 0) threads = (int)std::max(1u, std::thread::hardware_concurrency());
+    std::vector<std::vector<double>> part(threads, std::vector<double>(N, 0.0));
+    parallel_points(S, threads, [&](int t, int64_t si) {
+        Hit h;
+        h.prim = code[si] >> 1;
+        if (D == 2) { h.bary[1] = bary[si]; h.bary[0] = 1 - h.bary[1]; }
+        else { h.bary[1] = bary[2 * si]; h.bary[2] = bary[2 * si + 1]; h.bary[0] = 1 - h.bary[1] - h.bary[2]; }
+        for (int c = 0; c < D; ++c) {
+            double v = 0;
+            for (int k = 0; k < D; ++k) v += h.bary[k] * sc.vert(sc.pv(h.prim, k))[c];
+            h.xbar[c] = v;
+        }
+        h.d2 = 0;
+        double n[3];
+        side_normal(sc, h.prim, code[si] & 1, n);
+        double xoff[3] = {0, 0, 0};
+        for (int c = 0; c < D; ++c) xoff[c] = h.xbar[c] - s->delta * n[c];
+        const double gx = sc.g(h);
+        const double e = gx - uref_quad(D, ref, h.xbar);
+        const bool dep = sc.depends(h.prim);
+        std::vector<double> ud, vn;
+        for (int32_t m = 0; m < W; ++m) {
+            const Stream st = make_stream(seed, (uint32_t)si, (uint32_t)m, 0);
+            WalkCount c1;
+            int64_t nested = 0;
+            double lm = 0, uo = gx;
+            if (dep) {   // a primitive that moves with no parameter adds nothing; its walks are not run
+                lm = adjoint_walk(sc, xoff, ref, st, c1, nested);
+                double usum = 0;
+                for (int i = 0; i < s->K; ++i) {
+                    WalkCount c2;
+                    usum += walk_on_spheres(sc, xoff, st, kAdjOffset | ((uint32_t)i << 8), c2);
+                    nested += c2.steps;
+                }
+                uo = usum / s->K;
+                if (N > 0) {
+                    boundary_udot(sc, h, n, (gx - uo) / s->delta, ud, &vn);
+                    for (int j = 0; j < N; ++j)
+                        part[t][j] += wq[si] / W * (lm / s->delta * ud[j] + 0.5 * e * e * vn[j]);
+                }
+            }
+            const int64_t r = si * W + m;
+            if (lam) lam[r] = lm;
+            if (uoff) uoff[r] = uo;
+            if (steps) steps[r] = c1.steps + nested;
+        }
+    });
+    for (int j = 0; j < N; ++j) {
+        double v = 0;
+        for (int t = 0; t < threads; ++t) v += part[t][j];
+        grad[j] = v;
+    }
+    return 0;
+}
 
 void oracle_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
     philox4x32_10(ctr, key, out);

@@ -697,3 +697,57 @@ def mlp_init(dim: int, seed: int, freq_scale: float = 1.0, F: int = MLP_FREQS):
     off = MLP_LAYERS * (H * H + H)
     theta[off:off + H] = rng.uniform(-math.sqrt(6.0 / (H + 1)), math.sqrt(6.0 / (H + 1)), size=H)
     return B, theta
+
+
+def _winding(scene: Scene, x: np.ndarray) -> np.ndarray:
+    """Generalised winding number of the boundary mesh at points x (about 1
+    inside a closed, outward-oriented boundary, 0 outside; its sign flips with
+    the orientation): angles subtended by the segments / 2 pi in 2D, solid
+    angles of the triangles / 4 pi in 3D (Van Oosterom and Strackee)."""
+    V, F = scene.V, scene.prims
+    out = np.zeros(len(x))
+    for i, p in enumerate(x):
+        if scene.dim == 2:
+            a, b = V[F[:, 0]] - p, V[F[:, 1]] - p
+            ang = np.arctan2(a[:, 0] * b[:, 1] - a[:, 1] * b[:, 0], np.einsum("ij,ij->i", a, b))
+            out[i] = ang.sum() / (2 * np.pi)
+        else:
+            a, b, c = V[F[:, 0]] - p, V[F[:, 1]] - p, V[F[:, 2]] - p
+            la, lb, lc = (np.linalg.norm(v, axis=1) for v in (a, b, c))
+            num = np.einsum("ij,ij->i", a, np.cross(b, c))
+            den = la * lb * lc + np.einsum("ij,ij->i", a, b) * lc + np.einsum("ij,ij->i", b, c) * la \
+                + np.einsum("ij,ij->i", c, a) * lb
+            out[i] = 2 * np.arctan2(num, den).sum() / (4 * np.pi)
+    return out
+
+
+def boundary_samples(scene: Scene, S: int, seed: int, h: float = 1e-6):
+    """S points on the boundary mesh, uniform by length (2D) or area (3D):
+    (code = prim * 2 + flip, barycentrics b1 (, b2), quadrature weight
+    |boundary| / S).  flip = 0 when the domain lies on the side opposite the
+    primitive's geometric normal (segment a->b: (b - a) turned clockwise;
+    triangle: (b - a) x (c - a)), decided by the winding number of a point a
+    distance h along that normal."""
+    rng = np.random.default_rng(seed)
+    V, F, D = scene.V, scene.prims, scene.dim
+    if D == 2:
+        t = V[F[:, 1]] - V[F[:, 0]]
+        meas = np.linalg.norm(t, axis=1)
+        nrm = np.stack([t[:, 1], -t[:, 0]], 1) / meas[:, None]
+    else:
+        cr = np.cross(V[F[:, 1]] - V[F[:, 0]], V[F[:, 2]] - V[F[:, 0]])
+        meas = 0.5 * np.linalg.norm(cr, axis=1)
+        nrm = cr / (2 * meas[:, None])
+    prim = rng.choice(len(F), size=S, p=meas / meas.sum())
+    if D == 2:
+        b = rng.random((S, 1))
+        bary = np.concatenate([1 - b, b], 1)
+    else:
+        u, v = rng.random(S), rng.random(S)
+        fold = u + v > 1
+        u[fold], v[fold] = 1 - u[fold], 1 - v[fold]
+        bary = np.stack([1 - u - v, u, v], 1)
+    y = np.einsum("sk,skc->sc", bary, V[F[prim]])
+    inside = np.abs(_winding(scene, y + h * nrm[prim])) > 0.5
+    code = (prim * 2 + inside.astype(np.int64)).astype(np.int32)
+    return code, np.ascontiguousarray(bary[:, 1:]), np.full(S, meas.sum() / S)
