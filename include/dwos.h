@@ -260,13 +260,60 @@ dwos_status dwos_eval_ball_kernels(dwos_ctx* ctx, const double* r, const double*
 
 /* Accumulated device time and counters of the walk-kernel launches of one
  * kind (kind 0: forward walks, Algorithm 1; kind 1: differential walks with
- * their nested forward walks, Algorithm 2) since the last reset.  Time comes
+ * their nested forward walks, Algorithm 2; kind 2: the adjoint walks of
+ * dwos_adjoint_grad with all their nested walks) since the last reset.  Time comes
  * from events recorded on the context stream around each launch; this call
  * synchronises them.  walk_ms, launches and totals may be NULL; totals gets
  * the summed counters (walk_ms field = the same total time).
  * reset != 0 clears the accumulators of that kind after reading. */
 dwos_status dwos_walk_timing(dwos_ctx* ctx, int32_t kind, int32_t reset, double* walk_ms,
                              int64_t* launches, dwos_stats* totals);
+
+/* ---- The adjoint formulation (Appendix B), an ablation ------------------
+ * eq. (functional_deriv_adjoint): the derivative of a shape functional as a
+ * boundary integral of the adjoint's normal derivative, the alternative to
+ * the differential walks that the paper rejects because the adjoint's
+ * source needs a forward walk at every step of the adjoint walk (quadratic
+ * nesting).  For J = int_Omega 1/2 (u - uref)^2 with the quadratic reference
+ * uref(x) = c + b.x + x^T A x (A row-major 3 x 3, the top-left dim x dim
+ * used), the adjoint solves -Lap lambda + sigma lambda = u - uref in Omega,
+ * lambda = 0 on the boundary (eq. (bvp_adjoint) with the operator's sign and
+ * lambda flipped together), and
+ *   dJ/dpi_j = int_boundary [ -dlambda/dn udot_j + l(g) V_n,j ] dsigma
+ * with udot_j the boundary value of the differential problem (as at a
+ * terminal of Algorithm 2, eqs. (boundary_deriv_restricted) and
+ * (boundary_deriv_mapped)) and l(g) V_n,j the boundary term of
+ * eq. (functional_deriv).  At each of S boundary samples y (outward normal
+ * n) and for each of W walks: lambda(y - delta n) by walk on spheres with
+ * zero boundary data and the source u - uref, u at each step's ball point
+ * from a whole forward walk, -dlambda/dn = lambda / delta, and du/dn from K
+ * forward walks from y - delta n (backward difference).
+ *   grad_j = sum_s wq_s / W sum_m [ lambda_sm / delta udot_j(y_s; uoff_sm)
+ *                                   + 1/2 (g(y_s) - uref(y_s))^2 V_n,j(y_s) ]
+ * code (device int32 [S]): primitive * 2 + flip, flip = 1 when the outward
+ * normal is minus the primitive's geometric normal ((b - a) turned clockwise
+ * for a segment a->b, (b - a) x (c - a) for a triangle); bary (device FP64
+ * S x (dim - 1)): barycentrics b1 (, b2) of the vertices 1 (, 2), vertex 0
+ * taking the rest; wq (device FP64 [S]): quadrature weights (|boundary| / S
+ * for uniform samples).  grad (device FP64 [N]) is overwritten.  rec_lambda
+ * and rec_uoff (device FP64 S x W, may be NULL) receive lambda_sm and the
+ * offset means uoff_sm.  Walk m of sample s draws Philox4x32-10 counters
+ * (k, m, s, 0x10) for adjoint step k (0x12: a 3D step's second draw),
+ * (k, m, s, 0x20 | k' << 8) for the forward walk at adjoint step k', and
+ * (k, m, s, 0x30 | i << 8) for the i-th offset walk.  Samples on a primitive
+ * that moves with no parameter run no walks (lambda 0, uoff = g).
+ * Errors: EINVAL (NULL or bad arguments, a code naming no primitive, more
+ * than 2^30 walks); ESTATE (no boundary, problem or parameters, a batch
+ * context, an implicit or reflecting boundary, an attached control variate,
+ * dudn != 0). */
+typedef struct dwos_quad {
+    double c;
+    double b[3];
+    double A[9];
+} dwos_quad;
+dwos_status dwos_adjoint_grad(dwos_ctx* ctx, const int32_t* code, const double* bary, const double* wq,
+                              int64_t S, const dwos_quad* uref, int32_t W, uint64_t seed, double* grad,
+                              double* rec_lambda, double* rec_uoff, dwos_stats* stats);
 
 /* ---- Batched instances: many boundaries and query sets in one launch ----
  * A batch context holds I instances, each with its own boundary, BVH, sigma,

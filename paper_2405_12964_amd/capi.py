@@ -39,6 +39,10 @@ class dwos_stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class dwos_quad(C.Structure):
+    _fields_ = [("c", C.c_double), ("b", C.c_double * 3), ("A", C.c_double * 9)]
+
+
 class DwosError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"dwos error {code}: {msg}")
@@ -83,6 +87,8 @@ def lib():
             "dwos_batch_solve": [vp, vp, i64p, C.c_int32, C.c_uint64, vp, vp, C.POINTER(dwos_stats)],
             "dwos_batch_set_parameters": [vp, C.c_int32, C.c_int64, i64p, i32p, dp],
             "dwos_batch_grad": [vp, vp, i64p, vp, C.c_int32, C.c_uint64, vp, vp, C.POINTER(dwos_stats)],
+            "dwos_adjoint_grad": [vp, vp, vp, vp, C.c_int64, C.POINTER(dwos_quad), C.c_int32, C.c_uint64, vp, vp,
+                                  vp, C.POINTER(dwos_stats)],
             "dwos_mlp_create": [C.c_int32, C.c_int32, C.POINTER(C.c_float), vp, C.POINTER(vp)],
             "dwos_mlp_set_params": [vp, vp],
             "dwos_mlp_get_params": [vp, vp],
@@ -138,7 +144,7 @@ EXPORTED = [
     "dwos_mlp_set_params", "dwos_mlp_get_params", "dwos_mlp_eval", "dwos_mlp_loss_grad",
     "dwos_mlp_vjp", "dwos_mlp_adam_step", "dwos_cv_attach", "dwos_cv_beta", "dwos_cv_train", "dwos_cv_walk_records",
     "dwos_set_reflecting", "dwos_set_start_segments", "dwos_reflect_query", "dwos_eval_reflect_weight",
-    "dwos_set_implicit", "dwos_implicit_band_grad",
+    "dwos_set_implicit", "dwos_implicit_band_grad", "dwos_adjoint_grad",
     "dwos_remesh", "dwos_mesh_size", "dwos_mesh_get", "dwos_mesh_destroy",
     "dwos_opt_create", "dwos_opt_destroy", "dwos_opt_reset", "dwos_opt_step", "dwos_opt_solve",
 ]

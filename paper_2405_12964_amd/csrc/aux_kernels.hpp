@@ -32,6 +32,7 @@ struct Terminal {
     T bary[3];
     int32_t vid[3];
     T Tvec[3];
+    T n[3];        // outward normal
     bool mapped;
 };
 
@@ -59,6 +60,8 @@ __device__ __forceinline__ void terminal_term(const Scene<T>& s, const Params<T>
 #pragma unroll
         for (int c = 0; c < D; ++c) n[c] = -n[c];
     }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) t.n[c] = n[c];
     const T dudn = (g - uoff) / delta;
     const int L = s.label[orig];
     t.mapped = prm.kind[L] == 1;
@@ -188,6 +191,8 @@ __global__ void sqloss_kernel(const double* mean, const double* uref, int64_t P,
 //   mode 0 (weights): omega = w_p / W
 //   mode 1 (squared loss, U-statistics over batches of B walks):
 //     omega = [(S_b - u_m)/(B(B-1)) - uref_p/B] / (W/B),  S_b = sum of the batch
+//   mode 2 (per-walk weights, the adjoint formulation): omega = w[i], plus
+//     e[i] b_k n for the term e V_n of each record
 // ---------------------------------------------------------------------------
 template <class T>
 struct AccArgs {
@@ -201,8 +206,9 @@ struct AccArgs {
     int64_t nwalks;          // records in this chunk
     int64_t p_offset;        // first point of this chunk
     int32_t W, B, mode;
-    const double* w;         // mode 0
+    const double* w;         // mode 0: per point; mode 2: per walk
     const double* uref;      // mode 1
+    const double* e;         // mode 2: per-walk coefficient of V_n
     const int32_t* bc_pid;
     // skip lists (NULL: none): terminals on primitives that depend on no
     // parameter, and vertices without a Jacobian row or value parameter --
@@ -223,9 +229,12 @@ __global__ void __launch_bounds__(256) accumulate_kernel(AccArgs<T> a) {
     const int64_t pl = i / a.W;
     const int32_t m = (int32_t)(i - pl * a.W);
     const int64_t p = pl + a.p_offset;
-    double omega;
+    double omega, ev = 0.0;
     if (a.mode == 0) {
         omega = a.w[p] / a.W;
+    } else if (a.mode == 2) {
+        omega = a.w[i];
+        ev = a.e[i];
     } else {
         const int32_t b0 = (m / a.B) * a.B;
         const T* ub = a.rec_u + pl * a.W + b0;
@@ -240,8 +249,10 @@ __global__ void __launch_bounds__(256) accumulate_kernel(AccArgs<T> a) {
     for (int k = 0; k < D; ++k) {
         if (a.vparam && !a.vparam[t.vid[k]]) continue;
         const double wb = omega * double(t.bary[k]);
+        const double eb = ev * double(t.bary[k]);
 #pragma unroll
-        for (int c = 0; c < D; ++c) unsafeAtomicAdd(&a.A[(size_t)t.vid[k] * D + c], wb * double(t.Tvec[c]));
+        for (int c = 0; c < D; ++c)
+            unsafeAtomicAdd(&a.A[(size_t)t.vid[k] * D + c], wb * double(t.Tvec[c]) + eb * double(t.n[c]));
         if (t.mapped && a.bc_pid && a.bc_pid[t.vid[k]] >= 0) unsafeAtomicAdd(&a.Bacc[t.vid[k]], wb);
     }
 }

@@ -22,6 +22,7 @@
 #include "bvh.hpp"
 #include "wost_kernels.hpp"
 #include "implicit_kernels.hpp"
+#include "adjoint_kernels.hpp"
 
 namespace {
 
@@ -82,9 +83,9 @@ struct dwos_ctx {
     // timing and cumulative counters per walk kind (0 forward, 1 differential)
     struct Pending { hipEvent_t e0, e1; int kind; };
     std::vector<Pending> pending;
-    double timed_ms[2] = {0.0, 0.0};
-    int64_t timed_launches[2] = {0, 0};
-    DevBuf totals;   // 2 x Counters
+    double timed_ms[3] = {0.0, 0.0, 0.0};
+    int64_t timed_launches[3] = {0, 0, 0};
+    DevBuf totals;   // 3 x Counters (kind 2: adjoint walks)
     // learned control variate of the nested walks (not owned)
     dwos_mlp* cv = nullptr;
     uint32_t cv_qthresh = 1u << 24;
@@ -109,6 +110,8 @@ struct dwos_ctx {
     DevBuf imp_mono;              // n x 3 in the working precision
     DevBuf imp_xbar, imp_s, imp_coef;   // per-walk terminal data and reverse-mode weights
     DevBuf imp_bx, imp_bs;              // band points and their 1/|grad h|
+    // adjoint formulation: per-walk weights of udot and of V_n
+    DevBuf adj_w, adj_e;
 };
 
 namespace {
@@ -404,10 +407,10 @@ dwos_status drain_events(dwos_ctx* c, double* call_ms, size_t from) {
 }
 
 dwos_status ensure_totals(dwos_ctx* c) {
-    if (c->totals.bytes >= 2 * sizeof(dwos::Counters)) return DWOS_OK;
-    HIP_OK(c->totals.reserve(2 * sizeof(dwos::Counters)));
+    if (c->totals.bytes >= 3 * sizeof(dwos::Counters)) return DWOS_OK;
+    HIP_OK(c->totals.reserve(3 * sizeof(dwos::Counters)));
     hipLaunchKernelGGL(dwos::fill_u64_kernel, dim3(1), dim3(64), 0, c->stream,
-                       c->totals.as<unsigned long long>(), (int64_t)(2 * sizeof(dwos::Counters) / 8));
+                       c->totals.as<unsigned long long>(), (int64_t)(3 * sizeof(dwos::Counters) / 8));
     return DWOS_OK;
 }
 
@@ -1048,6 +1051,95 @@ dwos_status run_imp(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
     if (op == Op::SqLoss && o.loss) {
         hipLaunchKernelGGL(dwos::sqloss_kernel, dim3(1), dim3(256), 0, s, o.u_mean, o.uref, P, o.loss);
     }
+    return finish_call(c, st, ev_from);
+}
+
+// Adjoint formulation (Appendix B): one lane per (sample, walk) writes the
+// terminal record and its two weights, the mode-2 scatter and the SpMV give
+// grad.
+template <class T, int D>
+dwos_status run_adjoint(dwos_ctx* c, const int32_t* code, const double* bary, const double* wq, int64_t S,
+                        const dwos_quad* uref, int32_t W, uint64_t seed, double* grad, double* lam, double* uoff,
+                        dwos_stats* st) {
+    hipStream_t s = c->stream;
+    const int64_t walks = S * W;
+    const size_t ev_from = c->pending.size();
+    dwos_status rc = ensure_records<T>(c, std::max<int64_t>(1, walks), true, false);
+    if (rc) return rc;
+    HIP_OK(c->adj_w.reserve(std::max<int64_t>(1, walks) * sizeof(double)));
+    HIP_OK(c->adj_e.reserve(std::max<int64_t>(1, walks) * sizeof(double)));
+    HIP_OK(c->accA.reserve(c->nv * D * sizeof(double)));
+    HIP_OK(c->accB.reserve(c->nv * sizeof(double)));
+    hipLaunchKernelGGL(dwos::fill_f64_kernel, dim3(blocks_for(c->nv * D, 256)), dim3(256), 0, s,
+                       c->accA.as<double>(), c->nv * D);
+    hipLaunchKernelGGL(dwos::fill_f64_kernel, dim3(blocks_for(c->nv, 256)), dim3(256), 0, s,
+                       c->accB.as<double>(), c->nv);
+    if (walks > 0) {
+        dwos::AdjArgs<T> a{};
+        a.s = make_scene<T>(c);
+        a.s.n_stage_nodes = 0;
+        a.s.stage_prims = 0;
+        a.prm = make_params<T>(c->prob);
+        a.kappa = T(std::sqrt(c->prob.sigma));
+        a.eps = T(c->prob.eps);
+        a.delta = T(c->prob.delta);
+        a.code = code;
+        a.bary = bary;
+        a.wq = wq;
+        a.S = S;
+        a.W = W;
+        a.ref[0] = uref->c;
+        for (int i = 0; i < 3; ++i) a.ref[1 + i] = uref->b[i];
+        for (int i = 0; i < 9; ++i) a.ref[4 + i] = uref->A[i];
+        a.key0 = (uint32_t)seed;
+        a.key1 = (uint32_t)(seed >> 32);
+        a.prim_dep = c->prim_dep.as<int32_t>();
+        a.rec_prim = c->rec_prim.as<int32_t>();
+        a.rec_b = c->rec_b.as<T>();
+        a.rec_uoff = c->rec_uoff.as<T>();
+        a.rec_w = c->adj_w.as<double>();
+        a.rec_e = c->adj_e.as<double>();
+        a.out_lam = lam;
+        a.out_uoff = uoff;
+        a.cnt = c->counters.as<dwos::Counters>();
+        a.tot = c->totals.as<dwos::Counters>() + 2;
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        HIP_OK(hipStreamIsCapturing(s, &cap));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (cap == hipStreamCaptureStatusNone) {
+            HIP_OK(hipEventCreate(&e0));
+            HIP_OK(hipEventCreate(&e1));
+            HIP_OK(hipEventRecord(e0, s));
+        }
+        hipLaunchKernelGGL((dwos::adjoint_kernel<T, D>), dim3(blocks_for(walks, 256)), dim3(256), 0, s, a);
+        HIP_OK(hipGetLastError());
+        if (cap == hipStreamCaptureStatusNone) {
+            HIP_OK(hipEventRecord(e1, s));
+            c->pending.push_back({e0, e1, 2});
+        }
+        dwos::AccArgs<T> aa{};
+        aa.s = a.s;
+        aa.prm = a.prm;
+        aa.delta = a.delta;
+        aa.rec_prim = c->rec_prim.as<int32_t>();
+        aa.rec_b = c->rec_b.as<T>();
+        aa.rec_uoff = c->rec_uoff.as<T>();
+        aa.nwalks = walks;
+        aa.p_offset = 0;
+        aa.W = W;
+        aa.B = 1;
+        aa.mode = 2;
+        aa.w = c->adj_w.as<double>();
+        aa.e = c->adj_e.as<double>();
+        aa.bc_pid = c->has_bc_params ? c->bc_pid.as<int32_t>() : nullptr;
+        aa.prim_dep = c->prim_dep.as<int32_t>();
+        aa.vparam = c->vparam.as<int32_t>();
+        aa.A = c->accA.as<double>();
+        aa.Bacc = c->accB.as<double>();
+        hipLaunchKernelGGL((dwos::accumulate_kernel<T, D>), dim3(blocks_for(walks, 256)), dim3(256), 0, s, aa);
+    }
+    hipLaunchKernelGGL(dwos::spmv_kernel<D>, dim3(blocks_for(c->N, 4)), dim3(256), 0, s, make_csr(c),
+                       c->accA.as<double>(), c->accB.as<double>(), grad);
     return finish_call(c, st, ev_from);
 }
 
@@ -1720,10 +1812,39 @@ dwos_status dwos_set_seed_buffer(dwos_ctx* c, const uint64_t* seed_dev) {
     return DWOS_OK;
 }
 
+dwos_status dwos_adjoint_grad(dwos_ctx* c, const int32_t* code, const double* bary, const double* wq, int64_t S,
+                              const dwos_quad* uref, int32_t W, uint64_t seed, double* grad, double* rec_lambda,
+                              double* rec_uoff, dwos_stats* stats) {
+    dwos_status rc = single_call(c, true);
+    if (rc) return rc;
+    if (c->has_imp) return fail(DWOS_ESTATE, "adjoint_grad: needs a mesh boundary, not an implicit one");
+    if (c->has_ref) return fail(DWOS_ESTATE, "adjoint_grad: reflecting boundaries are not supported");
+    if (c->cv) return fail(DWOS_ESTATE, "adjoint_grad: detach the control variate first");
+    if (c->prob.dudn != 0) return fail(DWOS_ESTATE, "adjoint_grad: needs the backward-difference du/dn (dudn = 0)");
+    if (S < 0 || W < 1) return fail(DWOS_EINVAL, "adjoint_grad: need S >= 0 and W >= 1");
+    if (!grad || !uref || (S > 0 && (!code || !bary || !wq)))
+        return fail(DWOS_EINVAL, "adjoint_grad: NULL argument");
+    if (S > INT32_MAX || S * (int64_t)W > (int64_t(1) << 30))
+        return fail(DWOS_EINVAL, "adjoint_grad: more than 2^30 walks");
+    if (S > 0) {   // every code must name a primitive
+        std::vector<int32_t> h((size_t)S);
+        HIP_OK(hipMemcpyAsync(h.data(), code, S * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        HIP_OK(hipStreamSynchronize(c->stream));
+        for (int64_t i = 0; i < S; ++i)
+            if (h[i] < 0 || (int64_t)(h[i] >> 1) >= c->np)
+                return fail(DWOS_EINVAL, "adjoint_grad: code " + std::to_string(i) + " names no primitive");
+    }
+    if (c->prec == DWOS_FP32)
+        return c->D == 2 ? run_adjoint<float, 2>(c, code, bary, wq, S, uref, W, seed, grad, rec_lambda, rec_uoff, stats)
+                         : run_adjoint<float, 3>(c, code, bary, wq, S, uref, W, seed, grad, rec_lambda, rec_uoff, stats);
+    return c->D == 2 ? run_adjoint<double, 2>(c, code, bary, wq, S, uref, W, seed, grad, rec_lambda, rec_uoff, stats)
+                     : run_adjoint<double, 3>(c, code, bary, wq, S, uref, W, seed, grad, rec_lambda, rec_uoff, stats);
+}
+
 dwos_status dwos_walk_timing(dwos_ctx* c, int32_t kind, int32_t reset, double* walk_ms, int64_t* launches,
                              dwos_stats* totals) {
     if (!c) return fail(DWOS_EINVAL, "NULL context");
-    if (kind != 0 && kind != 1) return fail(DWOS_EINVAL, "walk_timing: kind must be 0 or 1");
+    if (kind < 0 || kind > 2) return fail(DWOS_EINVAL, "walk_timing: kind must be 0, 1 or 2");
     HIP_OK(hipSetDevice(c->device));
     dwos_status rc = drain_events(c, nullptr, 0);
     if (rc) return rc;

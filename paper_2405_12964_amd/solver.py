@@ -338,6 +338,37 @@ class Solver:
         g = g[:N]
         return (g, um, st.as_dict()) if stats else (g, um)
 
+    def adjoint_grad(self, code, bary, wq, uref, W, seed, records=False, stats=False):
+        """Adjoint formulation (Appendix B) of the derivative of
+        J = int_Omega 1/2 (u - uref)^2, uref = (c, b, A) the quadratic
+        c + b.x + x^T A x, from boundary samples (GPU tensors: code int32
+        prim * 2 + flip, bary S x (dim - 1), wq quadrature weights) with W
+        walks each.  Returns grad, plus (lambda, uoff) S x W records if
+        ``records``, plus the stats dict if ``stats``."""
+        c0, b, A = uref
+        q = capi.dwos_quad()
+        q.c = float(c0)
+        bb = np.zeros(3)
+        bb[:self.dim] = np.asarray(b if b is not None else np.zeros(self.dim), float).ravel()[:self.dim]
+        AA = np.zeros((3, 3))
+        if A is not None:
+            AA[:self.dim, :self.dim] = np.asarray(A, float).reshape(self.dim, self.dim)
+        for i in range(3):
+            q.b[i] = bb[i]
+        for i in range(9):
+            q.A[i] = AA.ravel()[i]
+        S = int(code.shape[0])
+        dev = code.device
+        g = torch.empty(max(1, self.N), dtype=torch.float64, device=dev)
+        lam = torch.empty((S, W), dtype=torch.float64, device=dev) if records else None
+        uo = torch.empty((S, W), dtype=torch.float64, device=dev) if records else None
+        st = capi.dwos_stats() if stats else None
+        check(capi.dwos_adjoint_grad(self._ctx, _dev(code, torch.int32), _dev(bary), _dev(wq), S, C.byref(q), int(W),
+                                     int(seed), _dev(g), _dev(lam), _dev(uo), C.byref(st) if st is not None else None))
+        g = g[:self.N]
+        out = (g,) + ((lam, uo) if records else ()) + ((st.as_dict(),) if stats else ())
+        return out if len(out) > 1 else g
+
     def autotune(self, X, W, seed=0):
         """Pick the faster walk-kernel launch shape on a sample of X; returns
         (variant, [ms variant 0, ms variant 1])."""
