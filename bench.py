@@ -589,17 +589,133 @@ def run_inflation(args):
     return out
 
 
+def run_adjoint(args):
+    """Ablation of Appendix B: the adjoint formulation against the
+    differential walks on the same derivative.  Unit disk as a 1024-gon,
+    -Lap u = 4, g = 0, eps = 1e-4, delta = 1e-2; J = int 1/2 (u - uref)^2
+    with uref = c0 (1 - |x|^2), c0 = 1/2 (zero on the boundary, so neither
+    formulation has a boundary term), pi = R, dJ/dR = pi (1 - c0) exactly.
+      differential: P points uniform in the domain x W walks (the
+        squared-loss U-statistic over each point's W walks) times |Omega|/P;
+      adjoint: S boundary samples x W walks (dwos_adjoint_grad).
+    Each is repeated with independent seeds; reported per formulation: time
+    and walk steps per gradient, RMSE against the exact value, and
+    time x RMSE^2 (the time to reach unit variance).  value = walk steps per
+    second of the adjoint kernel."""
+    import numpy as np
+    import torch
+    import scenes
+    import paper_2405_12964_amd as dw
+
+    dev = torch.device("cuda:0")
+    n, c0 = 1024, 0.5
+    sc = scenes.c1_polygon(n, eps=1e-4, delta=1e-2).with_(bc=[scenes._restricted(0.0, dim=2)], src_c0=4.0)
+    exact = math.pi * (1 - c0)
+    P = S = args.points or 16384
+    W = args.walks or 8
+    reps = args.steps
+    s = dw.Solver.from_scene(sc, "fp32")
+    # differential walks over the domain: points at least 2e-3 inside (a walk
+    # started within rounding of the boundary has no defined side); the band
+    # left out holds ~1e-5 of the integral, whose integrand vanishes on the
+    # boundary
+    rmax = math.cos(math.pi / n) - 2e-3
+    X = scenes.points_in_disk(P, rmax, 5)
+    Xt = torch.tensor(X, dtype=torch.float64, device=dev)
+    uref_p = torch.tensor(c0 * (1 - (X ** 2).sum(1)), dtype=torch.float64, device=dev)
+    area = math.pi * rmax * rmax
+    # adjoint: boundary samples
+    code, bary, wq = scenes.boundary_samples(sc, S, 6)
+    ct = torch.tensor(code, dtype=torch.int32, device=dev)
+    bt = torch.tensor(bary, dtype=torch.float64, device=dev)
+    wt = torch.tensor(wq, dtype=torch.float64, device=dev)
+    uref_q = (c0, None, np.diag([-c0, -c0]))
+
+    def diff(seed):
+        _, g, _, st = s.grad_sqloss(Xt, uref_p, W, W, seed, stats=True)
+        return float(g[0]) * area / P, st["steps"]
+
+    def adj(seed):
+        g, st = s.adjoint_grad(ct, bt, wt, uref_q, W, seed, stats=True)
+        return float(g[0]), st["steps"]
+
+    out = {}
+    for name, fn in (("differential", diff), ("adjoint", adj)):
+        for i in range(args.warmup):
+            fn(10 + i)
+        torch.cuda.synchronize()
+        for kind in (1, 2):
+            s.walk_timing(kind, reset=True)
+        vals, steps, t = [], 0, 0.0
+        for r in range(reps):
+            t0 = time.perf_counter()
+            v, st = fn(1000 + r)
+            torch.cuda.synchronize()
+            t += time.perf_counter() - t0
+            vals.append(v)
+            steps += st
+        print(f"{name}: {reps} gradients done", file=sys.stderr, flush=True)
+        vals = np.array(vals)
+        rmse = float(np.sqrt(np.mean((vals - exact) ** 2)))
+        kind = 1 if name == "differential" else 2
+        kms, kn, ktot = s.walk_timing(kind)
+        out[name] = {"ms_per_grad": 1e3 * t / reps, "walk_steps_per_grad": steps / reps,
+                     "rmse": rmse, "rel_rmse": rmse / exact, "mean": float(vals.mean()),
+                     "bias": float(vals.mean() - exact), "ms_x_rmse2": 1e3 * t / reps * rmse ** 2,
+                     "kernel_ms_per_grad": kms / max(1, kn), "kernel_totals": ktot}
+    d, a = out["differential"], out["adjoint"]
+    ktot = a["kernel_totals"]
+    avg_s = a["kernel_ms_per_grad"] / 1e3
+    ops = kernel_ops(ktot)
+    res = {
+        "metric": METRIC, "value": ktot["steps"] / max(1e-12, ktot["walk_ms"] / 1e3), "unit": "walk-steps/s",
+        "n_gpus": 1, "steps": reps, "warmup": args.warmup,
+        "ms_per_step": a["ms_per_grad"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"adjoint ablation (Appendix B): unit disk as a {n}-gon, -Lap u = 4, g = 0, "
+                               f"uref = {c0} (1 - |x|^2), d/dR; differential walks at {P} interior points "
+                               f"x {W} walks vs the adjoint at {S} boundary samples x {W} walks, "
+                               f"eps 1e-4, delta 1e-2",
+                   "points": P, "samples": S, "walks_per_point": W, "exact": exact},
+        "ablation": {"differential": {k: v for k, v in d.items() if k != "kernel_totals"},
+                     "adjoint": {k: v for k, v in a.items() if k != "kernel_totals"},
+                     "steps_ratio": a["walk_steps_per_grad"] / d["walk_steps_per_grad"],
+                     "cost_to_variance_ratio": a["ms_x_rmse2"] / d["ms_x_rmse2"]},
+        "roofline": {"bound": "alu", "achieved": ops / max(1e-12, ktot["walk_ms"] / 1e3) / 1e12,
+                     "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                     "frac": ops / max(1e-12, ktot["walk_ms"] / 1e3) / PEAK_FP32_VALU, "traffic": None,
+                     "kernel": "adjoint_kernel<float,2>", "avg_launch_ms": a["kernel_ms_per_grad"],
+                     "steps_per_launch": ktot["steps"] / max(1, reps)},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = min(16, len(os.sched_getaffinity(0)))
+        o = oracle.Oracle(sc, threads=threads)
+        Sc = 1024
+        ref = np.concatenate([[c0], np.zeros(2), np.diag([-c0, -c0]).ravel()])
+        t0 = time.perf_counter()
+        _, _, _, st = o.adjoint_grad(code[:Sc], bary[:Sc], wq[:Sc], ref, W, 7)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": float(st.sum()) / dt, "unit": "walk-steps/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"{Sc} boundary samples x {W} adjoint walks with their nested "
+                                         f"forward walks, brute-force FP64, {dt:.1f} s"}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", choices=["c2", "c4", "c5", "c5ls", "thermal", "inflation"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c4", "c5", "c5ls", "thermal", "inflation", "adjoint"],
+                    default="c2",
                     help="c2: 2D star (the reported configuration); c4: batched instances; c5: 3D "
                          "shape from diffusion with the learned control variate; c5ls: 3D shape from "
                          "diffusion with vertex parameters and the preconditioned vector Adam; "
                          "thermal: walk on stars with a reflecting boundary; inflation: curve inflation "
-                         "on an implicit boundary of harmonic monopoles")
+                         "on an implicit boundary of harmonic monopoles; adjoint: the adjoint formulation "
+                         "of Appendix B against the differential walks")
     ap.add_argument("--points", type=int, default=0)
     ap.add_argument("--walks", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true",
@@ -637,6 +753,11 @@ def main():
         args.steps = 150 if args.steps is None else args.steps
         args.warmup = 10 if args.warmup is None else args.warmup
         print(json.dumps(run_inflation(args)), flush=True)
+        return
+    if args.workload == "adjoint":
+        args.steps = 16 if args.steps is None else args.steps
+        args.warmup = 1 if args.warmup is None else args.warmup
+        print(json.dumps(run_adjoint(args)), flush=True)
         return
     if args.workload == "c5":
         args.steps = 50 if args.steps is None else args.steps

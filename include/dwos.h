@@ -27,7 +27,10 @@
  *    (point-major): X[p*dim + c], V[i*dim + c], udot[p*N + j].
  *  - A non-NULL dwos_stats* is host memory; filling it synchronises the stream.
  *  - Query points must lie inside Omega (the paper's eps-shell is defined
- *    inside the domain, Sec. 3.3.1); this is not checked.
+ *    inside the domain, Sec. 3.3.1); this is not checked.  A differential
+ *    walk orients the boundary normal away from its last position, so a
+ *    walk that starts within rounding distance of the boundary has no
+ *    defined side: its offset point may fall outside the domain.
  */
 #ifndef DWOS_H
 #define DWOS_H

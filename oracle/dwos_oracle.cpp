@@ -36,7 +36,11 @@
 //              sinh(k(R-r))/(4 pi r sinh(kR)) (3D); k = sqrt(sigma).
 //   * Shell test d < eps; Russian roulette stops iff alpha < U, U in [0,1).
 //   * Normal at the closest point: geometric normal of the closest primitive,
-//     flipped so that n.(xbar - x) >= 0 (points out of the domain).  The
+//     flipped so that n.(xbar - x') >= 0 (points out of the domain), x' the
+//     walk's previous position (inside by at least eps; the terminal
+//     position itself can lie within rounding of the boundary, where the
+//     side is undecided), or the start point for a walk that starts in the
+//     shell.  The
 //     closest primitive is the lowest-index one among those whose squared
 //     distance is within a relative 1e-12 of the minimum.
 //   * Walk-length cap kmax: the kmax-th query is treated as terminal.
@@ -262,7 +266,8 @@ struct Scene {
     }
 
     // BoundaryNormal (Algorithm 2): geometric normal of the primitive,
-    // oriented so that it points from x towards xbar (out of the domain).
+    // oriented so that it points from the reference position x (inside the
+    // domain) towards xbar, i.e. out of the domain.
     void normal(const Hit& h, const double* x, double n[3]) const {
         if (D == 2) {
             const double* a = vert(pv(h.prim, 0));
@@ -1182,7 +1187,7 @@ DiffOut diff_walk_on_spheres(const Scene& sc, const double* x0, const Stream& st
     const int N = sc.s.N;
     DiffOut out;
     if (want_udot) out.udot.assign(N, 0.0);
-    double x[3] = {0, 0, 0}, nin[3] = {0, 0, 0};
+    double x[3] = {0, 0, 0}, nin[3] = {0, 0, 0}, xprev[3] = {0, 0, 0};
     for (int i = 0; i < D; ++i) { x[i] = x0[i]; if (on0 >= 0) nin[i] = nin0[i]; }
     int on = on0;
     double acc = 0.0;
@@ -1194,7 +1199,7 @@ DiffOut diff_walk_on_spheres(const Scene& sc, const double* x0, const Stream& st
         if (d < sc.s.eps || cap) {
             if (cap && !(d < sc.s.eps)) cnt.truncated++;
             double n[3];
-            sc.normal(h, x, n);                                // BoundaryNormal
+            sc.normal(h, k > 0 ? xprev : x, n);                // BoundaryNormal
             double xoff[3] = {0, 0, 0};
             for (int i = 0; i < D; ++i) xoff[i] = h.xbar[i] - sc.s.delta * n[i];
             double usum = 0;
@@ -1259,6 +1264,7 @@ DiffOut diff_walk_on_spheres(const Scene& sc, const double* x0, const Stream& st
             return out;
         }
         if (sc.has_neumann()) {
+            for (int i = 0; i < D; ++i) xprev[i] = x[i];
             StarStep r = star_step(sc, x, on, nin, h.d2, k, st, 0u, acc);
             if (r.stop) { out.u = acc; return out; }   // roulette: udot = 0, u = sources
             on = r.on;
@@ -1283,6 +1289,7 @@ DiffOut diff_walk_on_spheres(const Scene& sc, const double* x0, const Stream& st
         }
         double s[3];
         sphere_dir(D, w[0], w[1], s);
+        for (int i = 0; i < D; ++i) xprev[i] = x[i];
         for (int i = 0; i < D; ++i) x[i] += d * s[i];
     }
 }

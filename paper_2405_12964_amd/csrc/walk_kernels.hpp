@@ -812,12 +812,17 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
             }
             const T g = boundary_value<T, D>(a.s, a.prm, orig, bary, xbar, vid);
             if (MODE >= 1 && phase == 0) {
-                // BoundaryNormal, oriented out of the domain (away from x)
+                // BoundaryNormal, oriented out of the domain: away from the
+                // walk's previous position (held in xoff until now), which
+                // lies inside by at least eps; the terminal position itself
+                // may sit within rounding of the boundary, or past it, where
+                // the side test has no reliable sign.  A walk that starts in
+                // the shell uses its start point.
                 T n[3] = {T(0), T(0), T(0)};
                 geo_normal<T, D>(V, n);
                 T dn = T(0);
 #pragma unroll
-                for (int c = 0; c < D; ++c) dn += n[c] * (xbar[c] - x[c]);
+                for (int c = 0; c < D; ++c) dn += n[c] * (xbar[c] - (k > 0 ? xoff[c] : x[c]));
                 const int flip = dn < T(0) ? 1 : 0;
                 if (flip) {
 #pragma unroll
@@ -939,6 +944,10 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
                         for (int c = 0; c < D; ++c) sn += dir[c] * bvc_n[c];
                         bvc_w = T(D) / d * sn;
                     }
+                }
+                if (MODE >= 1 && phase == 0) {
+#pragma unroll
+                    for (int c = 0; c < D; ++c) xoff[c] = x[c];   // previous position
                 }
 #pragma unroll
                 for (int c = 0; c < D; ++c) x[c] += d * dir[c];

@@ -533,9 +533,11 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
             if (MODE == 1 && phase == 0) {
                 T n[3] = {T(0), T(0), T(0)};
                 geo_normal<T, D>(V, n);
+                // oriented away from the previous position (inside by at
+                // least eps; held in xoff until now), or the start point
                 T dn = T(0);
 #pragma unroll
-                for (int c = 0; c < D; ++c) dn += n[c] * (xbar[c] - x[c]);
+                for (int c = 0; c < D; ++c) dn += n[c] * (xbar[c] - (k > 0 ? xoff[c] : x[c]));
                 const int flip = dn < T(0) ? 1 : 0;
                 if (flip) {
 #pragma unroll
@@ -612,6 +614,10 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
                 result = acc;
                 if (MODE == 1 && phase == 0) term_code = -1;
             } else {
+                if (MODE == 1 && phase == 0) {
+#pragma unroll
+                    for (int c = 0; c < D; ++c) xoff[c] = x[c];   // previous position
+                }
 #pragma unroll
                 for (int c = 0; c < D; ++c) x[c] += t * dir[c];
                 on = seg;

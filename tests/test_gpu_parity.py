@@ -378,3 +378,24 @@ def test_launch_variants_identical_and_autotune(dev, dwos, which):
     assert torch.allclose(res[0][2], res[1][2], rtol=1e-12, atol=1e-14)
     v, ms = s.autotune(Xt, 256)
     assert v in (0, 1) and all(t > 0 for t in ms)
+
+
+def test_fp32_terminal_side_when_a_step_lands_on_the_boundary(dev, dwos):
+    """A walk step can end within FP32 rounding of the boundary (or just past
+    it); the terminal normal is oriented from the previous position, so the
+    offset point stays inside.  Poisson disk as a 1024-gon, -Lap u = 4, g = 0
+    (u = 1 - r^2, du/dR = 2 at R = 1): with the normal oriented from the
+    terminal position a few offset walks started outside and returned values
+    ~1e5; now every offset mean stays within the solution's range plus noise
+    and the mean udot matches 2."""
+    n = 1024
+    sc = scenes.c1_polygon(n, eps=1e-4, delta=1e-2).with_(bc=[scenes._restricted(0.0, dim=2)], src_c0=4.0)
+    X = scenes.points_in_disk(16384, math.cos(math.pi / n) - 2e-3, 5)
+    s = dwos.Solver.from_scene(sc, "fp32")
+    rec = s.walk_records(T(X, dev), 8, 1000, mode=1, udot=True)
+    uoff = rec["uoff"].cpu().numpy()
+    assert np.abs(uoff).max() < 20.0, np.abs(uoff).max()
+    ud = rec["udot"].cpu().numpy()[..., 0]
+    term = rec["prim"].cpu().numpy() >= 0
+    m, se = ud[term].mean(), ud[term].std() / np.sqrt(term.sum())
+    assert abs(m - 2.0) < 5 * se + 0.03, (m, se)
