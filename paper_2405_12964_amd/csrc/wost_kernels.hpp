@@ -148,81 +148,107 @@ __device__ __forceinline__ bool sil_test(const T* v, const T* u, const T* w, int
     return (cu > T(0)) == (cw > T(0));
 }
 
-// Squared distance from x to its closest silhouette vertex, if below `best`
-// (else `best`).  x lies on leaf segment `on` (domain side nin) or inside (-1).
+// Closest silhouette vertex as a resumable query: the traversal state of one
+// lane (node to visit next or a held leaf, stack depth, best squared
+// distance so far).  sil_round processes one node or one leaf; a lane keeps
+// its state (and its entries in the traversal stack) across iterations of
+// the walk loop, so a wavefront can take its step once enough lanes are
+// answered (see wost_kernel).  x lies on leaf segment `on` (domain side nin)
+// or inside (-1).
+template <class T>
+struct SilQuery {
+    int32_t cur;   // node (>= 0) or leaf reference (< 0) to process next
+    int32_t sp;    // entries in the traversal stack
+    bool have;     // cur is valid; false once the query is answered
+    T best;        // squared distance of the closest silhouette vertex so far
+};
+
+template <class T>
+__device__ __forceinline__ void sil_begin(SilQuery<T>& q, T best) {
+    q.cur = 0;   // the root pair node
+    q.sp = 0;
+    q.have = true;
+    q.best = best;
+}
+
 template <class T, class Stack>
-__device__ T silhouette_d2(const RefScene<T>& r, const T* x, int32_t on, const T* nin, T best,
-                           QueryCount& qc, Stack& st) {
-    int sp = 0;
-    int32_t cur = 0;   // the root pair node
-    bool have = true;
-#pragma unroll 1
-    while (have) {
-        if (cur >= 0) {
-            NodeData<T, 2> nd;
-            ref_node<T>(r, cur, nd);
-            qc.nodes++;
-            const T d0 = fmax(box_d2<T, 2>(nd.lo0, nd.hi0, x), slab_d2<T, 2>(nd.n0, nd.o0, nd.t0, x));
-            const T d1 = fmax(box_d2<T, 2>(nd.lo1, nd.hi1, x), slab_d2<T, 2>(nd.n1, nd.o1, nd.t1, x));
-            T q[2 * kRefCone];
-            ref_cones<T>(r, cur, q);
-            const bool h0 = d0 < best && cone_may_hold<T>(nd.lo0, nd.hi0, q, x);
-            const bool h1 = d1 < best && cone_may_hold<T>(nd.lo1, nd.hi1, q + kRefCone, x);
-            if (h0 && h1) {
-                const bool n0 = d0 <= d1;
-                if (sp < kStackSize) {
-                    st.put(sp, n0 ? nd.c1 : nd.c0, n0 ? d1 : d0);
-                    ++sp;
-                } else {
-                    qc.overflow++;
-                }
-                cur = n0 ? nd.c0 : nd.c1;
-            } else if (h0) {
-                cur = nd.c0;
-            } else if (h1) {
-                cur = nd.c1;
+__device__ __forceinline__ void sil_round(const RefScene<T>& r, const T* x, int32_t on, const T* nin,
+                                          SilQuery<T>& q, QueryCount& qc, Stack& st) {
+    if (q.cur >= 0) {
+        NodeData<T, 2> nd;
+        ref_node<T>(r, q.cur, nd);
+        qc.nodes++;
+        const T d0 = fmax(box_d2<T, 2>(nd.lo0, nd.hi0, x), slab_d2<T, 2>(nd.n0, nd.o0, nd.t0, x));
+        const T d1 = fmax(box_d2<T, 2>(nd.lo1, nd.hi1, x), slab_d2<T, 2>(nd.n1, nd.o1, nd.t1, x));
+        T qn[2 * kRefCone];
+        ref_cones<T>(r, q.cur, qn);
+        const bool h0 = d0 < q.best && cone_may_hold<T>(nd.lo0, nd.hi0, qn, x);
+        const bool h1 = d1 < q.best && cone_may_hold<T>(nd.lo1, nd.hi1, qn + kRefCone, x);
+        if (h0 && h1) {
+            const bool n0 = d0 <= d1;
+            if (q.sp < kStackSize) {
+                st.put(q.sp, n0 ? nd.c1 : nd.c0, n0 ? d1 : d0);
+                ++q.sp;
             } else {
-                have = false;
+                qc.overflow++;
             }
+            q.cur = n0 ? nd.c0 : nd.c1;
+        } else if (h0) {
+            q.cur = nd.c0;
+        } else if (h1) {
+            q.cur = nd.c1;
         } else {
-            const int32_t v = -1 - cur;
-            const int32_t start = v >> 3, n = (v & 7) + 1;
-            for (int32_t i = start; i < start + n; ++i) {
-                const int4 inf = r.info[i];
-                const T* g = r.geo + (size_t)i * kRefGeo;
-                qc.prims++;
-                if (inf.x & 1) {   // vertex a: segments i (far end b) and inf.y (far end na)
-                    const T dx = g[0] - x[0], dy = g[1] - x[1];
-                    const T d2 = dx * dx + dy * dy;
-                    if (d2 < best) {
-                        const int own = on < 0 ? 0 : (on == i ? 1 : (on == inf.y ? 2 : 0));
-                        if ((inf.x & 4) || sil_test<T>(g, g + 2, g + 4, own, x, nin, on >= 0)) best = d2;
-                    }
-                }
-                if (inf.x & 2) {   // vertex b: segments i (far end a) and inf.z (far end nb)
-                    const T dx = g[2] - x[0], dy = g[3] - x[1];
-                    const T d2 = dx * dx + dy * dy;
-                    if (d2 < best) {
-                        const int own = on < 0 ? 0 : (on == i ? 1 : (on == inf.z ? 2 : 0));
-                        if ((inf.x & 8) || sil_test<T>(g + 2, g, g + 6, own, x, nin, on >= 0)) best = d2;
-                    }
+            q.have = false;
+        }
+    } else {
+        const int32_t v = -1 - q.cur;
+        const int32_t start = v >> 3, n = (v & 7) + 1;
+        for (int32_t i = start; i < start + n; ++i) {
+            const int4 inf = r.info[i];
+            const T* g = r.geo + (size_t)i * kRefGeo;
+            qc.prims++;
+            if (inf.x & 1) {   // vertex a: segments i (far end b) and inf.y (far end na)
+                const T dx = g[0] - x[0], dy = g[1] - x[1];
+                const T d2 = dx * dx + dy * dy;
+                if (d2 < q.best) {
+                    const int own = on < 0 ? 0 : (on == i ? 1 : (on == inf.y ? 2 : 0));
+                    if ((inf.x & 4) || sil_test<T>(g, g + 2, g + 4, own, x, nin, on >= 0)) q.best = d2;
                 }
             }
-            have = false;
-        }
-        if (!have) {
-#pragma unroll 1
-            while (sp > 0) {
-                --sp;
-                if (st.get_d(sp) < best) {
-                    cur = st.get_node(sp);
-                    have = true;
-                    break;
+            if (inf.x & 2) {   // vertex b: segments i (far end a) and inf.z (far end nb)
+                const T dx = g[2] - x[0], dy = g[3] - x[1];
+                const T d2 = dx * dx + dy * dy;
+                if (d2 < q.best) {
+                    const int own = on < 0 ? 0 : (on == i ? 1 : (on == inf.z ? 2 : 0));
+                    if ((inf.x & 8) || sil_test<T>(g + 2, g, g + 6, own, x, nin, on >= 0)) q.best = d2;
                 }
+            }
+        }
+        q.have = false;
+    }
+    if (!q.have) {
+#pragma unroll 1
+        while (q.sp > 0) {
+            --q.sp;
+            if (st.get_d(q.sp) < q.best) {
+                q.cur = st.get_node(q.sp);
+                q.have = true;
+                break;
             }
         }
     }
-    return best;
+}
+
+// Squared distance from x to its closest silhouette vertex, if below `best`
+// (else `best`): the whole query.
+template <class T, class Stack>
+__device__ T silhouette_d2(const RefScene<T>& r, const T* x, int32_t on, const T* nin, T best,
+                           QueryCount& qc, Stack& st) {
+    SilQuery<T> q;
+    sil_begin<T>(q, best);
+#pragma unroll 1
+    while (q.have) sil_round<T>(r, x, on, nin, q, qc, st);
+    return q.best;
 }
 
 // Entry distance of the ray x + t dir (t in [0, tmax]) into a child's box
@@ -425,6 +451,13 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
     int32_t root = 0, warm = -1, term_leaf = -1, term_code = -1, phase = 0, on = -1;
     T term_b1 = T(0);
     int64_t wsteps = 0;
+    // silhouette query in progress (resumable across iterations) and the
+    // Dirichlet answer of its step
+    SilQuery<T> sq;
+    sq.have = false;
+    bool spend = false;
+    T sd2 = T(0);
+    int32_t sleaf = -1;
     unsigned long long c_walks = 0, c_nested = 0, c_steps = 0, c_term = 0, c_trunc = 0,
                        c_nodes = 0, c_prims = 0, c_ovf = 0, c_invalid = 0;
 #pragma unroll 1
@@ -482,96 +515,126 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
         if (__ballot(!done) == 0ull) break;
         if (done) continue;
 
-        // ---- Dirichlet distance ----------------------------------------------
         QueryCount qc{0, 0, 0};
-        T d2;
-        int32_t leaf;
-        if (a.first_leaf && phase == 0 && k == 0) {
-            leaf = a.first_leaf[first_row];
-            d2 = a.first_d2[first_row];
-        } else {
-            leaf = closest_leaf<T, D>(a.s, sv, root, x, warm, d2, qc, stack);
-        }
-        c_steps++;
-        wsteps++;
-        if (leaf < 0 || !(d2 >= T(0))) {
-            c_invalid++;
-            const T nanv = T(NAN);
-            a.rec_u[wid] = nanv;
-            if (MODE == 1) {
-                a.rec_prim[wid] = -1;
-                a.rec_uoff[wid] = nanv;
-            }
-            if (a.rec_steps) a.rec_steps[wid] = wsteps;
-            wid = -1;
-            c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;
-            continue;
-        }
-        const T d = sqrt(d2);
-        const bool cap = (int)(k + 1) >= a.prm.kmax;
-        const bool nested = MODE == 1 && phase > 0;
         bool finished = false;
         T result = T(0);
-        if (d < eps || cap) {
-            if (cap && !(d < eps)) c_trunc++;
-            T P[9], bary[3];
-            scene_prim<T, D>(a.s, sv, leaf, P);
-            prim_closest<T, D>(P, x, bary);
-            const int32_t orig = a.s.orig[leaf];
-            T V[9];
-            int32_t vid[3];
-            prim_vertices<T, D>(a.s, orig, V, vid);
-            T xbar[3] = {T(0), T(0), T(0)};
-#pragma unroll
-            for (int c = 0; c < D; ++c) {
-                T v = T(0);
-#pragma unroll
-                for (int kk = 0; kk < D; ++kk) v += bary[kk] * V[kk * D + c];
-                xbar[c] = v;
+        if (!spend) {
+            // ---- Dirichlet distance ----------------------------------------------
+            T d2;
+            int32_t leaf;
+            if (a.first_leaf && phase == 0 && k == 0) {
+                leaf = a.first_leaf[first_row];
+                d2 = a.first_d2[first_row];
+            } else {
+                leaf = closest_leaf<T, D>(a.s, sv, root, x, warm, d2, qc, stack);
             }
-            const T g = boundary_value<T, D>(a.s, a.prm, orig, bary, xbar, vid);
-            if (MODE == 1 && phase == 0) {
-                T n[3] = {T(0), T(0), T(0)};
-                geo_normal<T, D>(V, n);
-                // oriented away from the previous position (inside by at
-                // least eps; held in xoff until now), or the start point
-                T dn = T(0);
-#pragma unroll
-                for (int c = 0; c < D; ++c) dn += n[c] * (xbar[c] - (k > 0 ? xoff[c] : x[c]));
-                const int flip = dn < T(0) ? 1 : 0;
-                if (flip) {
-#pragma unroll
-                    for (int c = 0; c < D; ++c) n[c] = -n[c];
+            c_steps++;
+            wsteps++;
+            if (leaf < 0 || !(d2 >= T(0))) {
+                c_invalid++;
+                const T nanv = T(NAN);
+                a.rec_u[wid] = nanv;
+                if (MODE == 1) {
+                    a.rec_prim[wid] = -1;
+                    a.rec_uoff[wid] = nanv;
                 }
-                u_main = acc + g;
-                term_code = orig * 2 + flip;
-                term_b1 = bary[1];
-                term_leaf = leaf;
-#pragma unroll
-                for (int c = 0; c < D; ++c) xoff[c] = xbar[c] - delta * n[c];
-                c_term++;
-                if (a.prim_dep && !a.prim_dep[orig]) {
-                    a.rec_u[wid] = u_main;
-                    a.rec_prim[wid] = term_code;
-                    a.rec_b[wid] = term_b1;
-                    a.rec_uoff[wid] = g;
-                    if (a.rec_steps) a.rec_steps[wid] = wsteps;
-                    wid = -1;
-                    c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;
-                    continue;
-                }
-                // the first nested walk on stars starts at the offset point
-                phase = 1;
-#pragma unroll
-                for (int c = 0; c < D; ++c) x[c] = xoff[c];
-                acc = T(0); k = 0; warm = term_leaf; on = -1;
-                c_nested++;
+                if (a.rec_steps) a.rec_steps[wid] = wsteps;
+                wid = -1;
                 c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;
                 continue;
             }
-            finished = true;
-            result = acc + g;
-        } else {
+            const T d = sqrt(d2);
+            const bool cap = (int)(k + 1) >= a.prm.kmax;
+            if (d < eps || cap) {
+                if (cap && !(d < eps)) c_trunc++;
+                T P[9], bary[3];
+                scene_prim<T, D>(a.s, sv, leaf, P);
+                prim_closest<T, D>(P, x, bary);
+                const int32_t orig = a.s.orig[leaf];
+                T V[9];
+                int32_t vid[3];
+                prim_vertices<T, D>(a.s, orig, V, vid);
+                T xbar[3] = {T(0), T(0), T(0)};
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    T v = T(0);
+#pragma unroll
+                    for (int kk = 0; kk < D; ++kk) v += bary[kk] * V[kk * D + c];
+                    xbar[c] = v;
+                }
+                const T g = boundary_value<T, D>(a.s, a.prm, orig, bary, xbar, vid);
+                if (MODE == 1 && phase == 0) {
+                    T n[3] = {T(0), T(0), T(0)};
+                    geo_normal<T, D>(V, n);
+                    // oriented away from the previous position (inside by at
+                    // least eps; held in xoff until now), or the start point
+                    T dn = T(0);
+#pragma unroll
+                    for (int c = 0; c < D; ++c) dn += n[c] * (xbar[c] - (k > 0 ? xoff[c] : x[c]));
+                    const int flip = dn < T(0) ? 1 : 0;
+                    if (flip) {
+#pragma unroll
+                        for (int c = 0; c < D; ++c) n[c] = -n[c];
+                    }
+                    u_main = acc + g;
+                    term_code = orig * 2 + flip;
+                    term_b1 = bary[1];
+                    term_leaf = leaf;
+#pragma unroll
+                    for (int c = 0; c < D; ++c) xoff[c] = xbar[c] - delta * n[c];
+                    c_term++;
+                    if (a.prim_dep && !a.prim_dep[orig]) {
+                        a.rec_u[wid] = u_main;
+                        a.rec_prim[wid] = term_code;
+                        a.rec_b[wid] = term_b1;
+                        a.rec_uoff[wid] = g;
+                        if (a.rec_steps) a.rec_steps[wid] = wsteps;
+                        wid = -1;
+                        c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;
+                        continue;
+                    }
+                    // the first nested walk on stars starts at the offset point
+                    phase = 1;
+#pragma unroll
+                    for (int c = 0; c < D; ++c) x[c] = xoff[c];
+                    acc = T(0); k = 0; warm = term_leaf; on = -1;
+                    c_nested++;
+                    c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;
+                    continue;
+                }
+                finished = true;
+                result = acc + g;
+            } else {
+                sil_begin<T>(sq, d2);
+                spend = true;
+                sd2 = d2;
+                sleaf = leaf;
+            }
+        }
+        // ---- closest silhouette point (resumable) -----------------------------
+        // The wavefront runs rounds of the lanes' silhouette queries until at
+        // least kParkLanes of its lanes are not traversing (answered, or at a
+        // terminal); the others keep their query state and resume it in the
+        // next iteration instead of starting a new step.
+        {
+#pragma unroll 1
+            while (true) {
+                const bool trav = spend && sq.have;
+                const unsigned long long sm = __ballot(trav);
+                const unsigned long long present = __ballot(true);
+                if (sm == 0ull || __popcll(present & ~sm) >= kParkLanes) break;
+                if (trav) sil_round<T>(ref, x, on, nin, sq, qc, stack);
+            }
+        }
+        if (spend && sq.have) {
+            c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;
+            continue;
+        }
+        if (spend) {
+            spend = false;
+            const T d = sqrt(sd2);
+            const int32_t leaf = sleaf;
+            const bool nested = MODE == 1 && phase > 0;
             // ---- one step on the star-shaped region ---------------------------
             // The star radius is kept above 16 units of rounding of the
             // position: a walk next to a silhouette vertex must still move
@@ -581,7 +644,7 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
             // scale.  In FP64 the floor is ~1e-15 and never binds in practice.
             const T ulp = sizeof(T) == 4 ? T(1.1920929e-07) : T(2.220446049250313e-16);
             const T rmin = T(16) * ulp * (fabs(x[0]) + fabs(x[1]));
-            const T R = fmin(d, fmax(sqrt(silhouette_d2<T>(ref, x, on, nin, d2, qc, stack)), rmin));
+            const T R = fmin(d, fmax(sqrt(sq.best), rmin));
             const uint32_t tag = inst_tag | (nested ? (1u | ((uint32_t)(phase - 1) << 8)) : 0u);
             const u4 r = philox10(u4{k, m, p, tag}, key0, key1);
             T dir[2];
