@@ -39,9 +39,9 @@ def test_struct_layout_matches_header():
 #include <cstddef>
 #include "dwos.h"
 int main() {
-  std::printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(dwos_problem), sizeof(dwos_bc), sizeof(dwos_stats),
+  std::printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(dwos_problem), sizeof(dwos_bc), sizeof(dwos_stats),
     offsetof(dwos_problem, src_c0), offsetof(dwos_problem, gauss), offsetof(dwos_problem, n_labels),
-    offsetof(dwos_problem, bc), offsetof(dwos_stats, walk_ms));
+    offsetof(dwos_problem, bc), offsetof(dwos_stats, walk_ms), sizeof(dwos_quad), offsetof(dwos_quad, A));
 }
 '''
     d = tempfile.mkdtemp()
@@ -51,8 +51,9 @@ int main() {
     subprocess.check_call(["g++", "-std=c++17", "-I", os.path.dirname(HEADER), "-o", exe, f])
     vals = [int(v) for v in subprocess.check_output([exe]).split()]
     P, S = capi.dwos_problem, capi.dwos_stats
+    Q = capi.dwos_quad
     assert vals == [C.sizeof(P), C.sizeof(capi.dwos_bc), C.sizeof(S), P.src_c0.offset, P.gauss.offset,
-                    P.n_labels.offset, P.bc.offset, S.walk_ms.offset]
+                    P.n_labels.offset, P.bc.offset, S.walk_ms.offset, C.sizeof(Q), Q.A.offset]
 
 
 def test_create_without_gpu_reports_device_error():
@@ -75,3 +76,13 @@ def test_create_without_gpu_reports_device_error():
     assert capi.dwos_mlp_create(2, 40, B, None, C.byref(m)) == capi.DWOS_EINVAL
     assert capi.dwos_mlp_theta_size() == 4 * (64 * 64 + 64) + 65
     assert capi.dwos_cv_attach(None, None, 1.0) == capi.DWOS_EINVAL
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    """No fallback: without libdwos.so the binding raises instead of
+    computing anything elsewhere."""
+    from paper_2405_12964_amd import capi
+    monkeypatch.setattr(capi, "_lib", None)
+    monkeypatch.setattr(capi, "LIB_PATH", str(tmp_path / "libdwos.so"))
+    with pytest.raises(ImportError):
+        capi.lib()
