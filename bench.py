@@ -5,7 +5,8 @@ Workload (N = 1): the 2D screened-Poisson star polygon -- 4096 boundary
 segments, r(th) = 1 + sum_{k<=32} a_k cos k th + b_k sin k th with
 a_k, b_k ~ N(0, (0.02/k)^2), sigma = 10, Gaussian source, restricted data
 g = x^2 - y^2, eps = 1e-3, delta = 1e-2 -- with 4096 query points x 4096
-walks, FP32 walks, gradients with respect to the 64 Fourier coefficients
+walks, K = 8 nested forward walks per differential terminal (--nested),
+FP32 walks, gradients with respect to the 64 Fourier coefficients
 through DWoSFunction.  One step = move the boundary to the current
 coefficients (device V(pi) + BVH refit), forward walks (u), squared loss
 against a reference solution, backward (differential walks with nested
@@ -67,17 +68,17 @@ def sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, nested):
     """Scaled FETCH_SIZE + WRITE_SIZE bytes per launch of `kernel` from the
     committed counter summary, or None when it is missing or was taken on
-    different kernel sources."""
+    different kernel sources or another nested-walk count."""
     try:
         with open(TRAFFIC_FILE) as f:
             text = f.read()
     except OSError:
         return None
     kv = dict(re.findall(r"^# (\w+): (\S+)$", text, re.M))
-    if kv.get("sources_sha256") != sources_sha256():
+    if kv.get("sources_sha256") != sources_sha256() or kv.get("nested_walks_per_terminal") != str(nested):
         return None
     m = re.search(r"^traffic_bytes_per_launch +" + re.escape(kernel) + r" +(\S+)$", text, re.M)
     return float(m.group(1)) if m else None
@@ -103,7 +104,7 @@ def cpu_baseline(sc, X, uref_np, seed, threads, npts=1024, W=1024):
     dt = time.perf_counter() - t0
     return {"value": (s1 + s2) / dt, "unit": "walk-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{npts} points x {W} forward walks + {npts} x {W} differential walks "
-                      f"(K=1 nested) of the same scene, brute-force FP64, {dt:.1f} s"}
+                      f"(K={sc.K} nested) of the same scene, brute-force FP64, {dt:.1f} s"}
 
 
 def run_c5(args):
@@ -717,6 +718,9 @@ def main():
                          "on an implicit boundary of harmonic monopoles; adjoint: the adjoint formulation "
                          "of Appendix B against the differential walks")
     ap.add_argument("--points", type=int, default=0)
+    ap.add_argument("--nested", type=int, default=8,
+                    help="default workload: nested forward walks per differential terminal (K; the paper "
+                         "uses 2-16, 8 for its thermal design)")
     ap.add_argument("--walks", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle timing (and, for the default workload, the fixed-RMSE gradient rate)")
@@ -774,7 +778,7 @@ def main():
 
     dev = torch.device("cuda:0")
     P, W = args.points or 4096, args.walks or 4096
-    sc = scenes.c2_star(n=4096, coef_seed=0)
+    sc = scenes.c2_star(n=4096, coef_seed=0, K=args.nested)
     X = scenes.star_points(P, 1)
     Xt = torch.tensor(X, dtype=torch.float64, device=dev)
 
@@ -829,7 +833,7 @@ def main():
     # the default launch shape: the LDS-staged 1024-thread walk kernel
     kname = f"walk_kernel<float,2,{kind},true>"
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": measured_traffic(kname),
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": measured_traffic(kname, args.nested),
             "kernel": kname, "avg_launch_ms": ms / max(1, n),
             "launches": n, "ops_per_launch": ops,
             "steps_per_launch": tot["steps"] / max(1, n),
@@ -845,8 +849,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "2D screened Poisson star polygon, 4096 segments, sigma=10, "
                                f"Gaussian source, {P} points x {W} walks, grads wrt 64 coeffs "
-                               "via autograd (forward walks + differential walks, K=1)",
-                   "points": P, "walks_per_point": W, "segments": 4096, "params": 64},
+                               f"via autograd (forward walks + differential walks, K={args.nested} nested)",
+                   "points": P, "walks_per_point": W, "segments": 4096, "params": 64,
+                   "nested_walks_per_terminal": args.nested},
         "grad_evals_per_s": args.steps / elapsed,
         "walk_steps": {"forward": tot0["steps"], "differential": tot1["steps"],
                        "forward_ms": ms0, "differential_ms": ms1},
@@ -856,7 +861,9 @@ def main():
     if not args.no_cpu_baseline:
         out["fixed_rmse"] = fixed_rmse_rate(model, pi, Xt, uref, W)
         threads = min(16, len(os.sched_getaffinity(0)))
-        out["cpu_baseline"] = cpu_baseline(sc, X, uref.cpu().numpy(), 7, threads)
+        # a sample of ~20 s: 1024 points at K = 1, fewer as the nested walks grow
+        npts = max(128, 1024 // max(1, (args.nested + 1) // 2) * 2)
+        out["cpu_baseline"] = cpu_baseline(sc, X, uref.cpu().numpy(), 7, threads, npts=min(1024, npts))
     print(json.dumps(out), flush=True)
 
 
