@@ -382,9 +382,10 @@ def run_thermal(args):
     (four heating wires of 125 segments, g = 1, 64 shape coefficients; a fixed
     zero-flux slice of 65,536 segments between them; a cold box, Laplace).
     16384 points on the slice surface, where the loss lives, with their walks
-    starting on the wall; W forward and W differential walks (K = 1 nested
-    walk on stars at each wire terminal); squared loss against the solution
-    of a second coefficient draw; Adam on the coefficients."""
+    starting on the wall; W forward and W differential walks (K nested walks
+    on stars at each wire terminal, --nested, 8 as in the paper's thermal
+    design); squared loss against the solution of a second coefficient draw;
+    Adam on the coefficients."""
     import numpy as np
     import torch
     import scenes
@@ -392,7 +393,7 @@ def run_thermal(args):
 
     dev = torch.device("cuda:0")
     P, W = args.points or 16384, args.walks or 256
-    sc = scenes.thermal_scene()
+    sc = scenes.thermal_scene(K=args.nested)
     X, seg = scenes.points_on_segments(sc.NV, sc.nsegs, P, 1)
     Xt = torch.tensor(X, dtype=torch.float64, device=dev)
     ref = dw.Solver.from_scene(scenes.thermal_scene(coef_seed=3), "fp32")
@@ -442,7 +443,7 @@ def run_thermal(args):
         "config": {"workload": "walk on stars, 2D thermal design: 4 heating wires (500 segments, g = 1, "
                                "64 shape coefficients), zero-flux slice of 65,536 segments, cold box, "
                                f"Laplace; {P} points on the slice x {W} walks, forward + differential "
-                               "(K=1) via autograd",
+                               f"(K={sc.K} nested) via autograd",
                    "points": P, "walks_per_point": W, "reflecting_segments": int(len(sc.nsegs)),
                    "dirichlet_segments": int(len(sc.prims)), "params": int(sc.N)},
         "grad_evals_per_s": args.steps / elapsed,
@@ -462,7 +463,7 @@ def run_thermal(args):
         import oracle
         threads = min(16, len(os.sched_getaffinity(0)))
         o = oracle.Oracle(sc, threads=threads)
-        npts, Wc = 32, 32
+        npts, Wc = 64, 64
         t0 = time.perf_counter()
         _, _, s1 = o.solve(X[:npts], Wc, 7, start_seg=seg[:npts])
         _, _, s2 = o.grad(X[:npts], np.ones(npts), Wc, 8, start_seg=seg[:npts])
@@ -470,6 +471,7 @@ def run_thermal(args):
         out["cpu_baseline"] = {"value": (s1 + s2) / dt, "unit": "walk-steps/s", "cores": threads,
                                "kind": "oracle",
                                "sample": f"{npts} points x {Wc} forward + {Wc} differential walks on stars "
+                                         f"(K = {sc.K} nested) "
                                          f"of the same scene, brute-force FP64, {dt:.1f} s"}
     return out
 
@@ -719,8 +721,8 @@ def main():
                          "of Appendix B against the differential walks")
     ap.add_argument("--points", type=int, default=0)
     ap.add_argument("--nested", type=int, default=8,
-                    help="default workload: nested forward walks per differential terminal (K; the paper "
-                         "uses 2-16, 8 for its thermal design)")
+                    help="default and thermal workloads: nested forward walks per differential terminal "
+                         "(K; the paper uses 2-16, 8 for its thermal design)")
     ap.add_argument("--walks", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle timing (and, for the default workload, the fixed-RMSE gradient rate)")
