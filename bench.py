@@ -497,7 +497,8 @@ def run_inflation(args):
     One iteration (ImplicitShapeOptimizer): the pixel regions, the
     squared-loss U-statistic gradient over the pixels inside the domain
     beyond the band (all W walks of a pixel form one batch), W forward walks
-    at the band pixels (band eps_band = 2 pixels) for the band term with
+    at the band pixels (band eps_band = 2 pixels; a second context and stream,
+    overlapping the differential walks) for the band term with
     integrand l(u) - uref^2/2, Adam on the 96 monopole coordinates with the
     scales kept >= 1e-3, and the new monopoles uploaded.  The rate counts
     the steps of both kinds of walks."""
@@ -536,7 +537,8 @@ def run_inflation(args):
         step(i)
     torch.cuda.synchronize()
     print(f"{args.warmup} warmup iterations done", file=sys.stderr, flush=True)
-    s.walk_timing(0, reset=True)
+    sb = opt.band_solver
+    sb.walk_timing(0, reset=True)
     s.walk_timing(1, reset=True)
     npx = []
     t0 = time.perf_counter()
@@ -547,7 +549,7 @@ def run_inflation(args):
             print(f"iteration {i + 1} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    ms0, n0, tot0 = s.walk_timing(0)
+    ms0, n0, tot0 = sb.walk_timing(0)
     ms1, n1, tot1 = s.walk_timing(1)
     assert tot0["invalid"] == 0 and tot1["invalid"] == 0
     n = len(start.mono)

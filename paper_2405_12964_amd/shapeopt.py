@@ -156,6 +156,11 @@ class ImplicitShapeOptimizer:
     def __init__(self, scene, X: torch.Tensor, uref: torch.Tensor, dA: float, eps_band: float,
                  lr=2e-3, W=4, a_min=1e-3, precision="fp32"):
         self.solver = Solver.from_scene(scene, precision)
+        # the band pixels' forward walks run on a second context and stream
+        # (default priority), overlapping the differential walks: the two
+        # launches are small and independent given the monopoles
+        self.band_stream = torch.cuda.Stream(device=X.device)
+        self.band_solver = Solver.from_scene(scene, precision, stream=self.band_stream)
         self.c = float(scene.mono_c)
         self.X, self.uref, self.dA, self.eps_band = X, uref, float(dA), float(eps_band)
         self.W, self.a_min = int(W), float(a_min)
@@ -180,13 +185,21 @@ class ImplicitShapeOptimizer:
         inner = torch.nonzero(region == 2).squeeze(1)
         band = torch.nonzero(region == 1).squeeze(1)
         out = self.uref[region == 0]
+        main = torch.cuda.current_stream(self.X.device)
+        if band.numel():
+            Xb = self.X[band].contiguous()
+            self.band_stream.wait_stream(main)
+            with torch.cuda.stream(self.band_stream):
+                ub, vb = self.band_solver.solve(Xb, self.W, (seed * 0x9E3779B1 + 0x7F4A7C15) & 0xFFFFFFFF)
         L, gd, _ = self.solver.grad_sqloss(self.X[inner].contiguous(), self.uref[inner].contiguous(), self.W,
                                            self.W, seed)
         grad = self.dA * gd
         lb = 0.0
         if band.numel():
-            Xb, ub_ref = self.X[band].contiguous(), self.uref[band]
-            ub, vb = self.solver.solve(Xb, self.W, (seed * 0x9E3779B1 + 0x7F4A7C15) & 0xFFFFFFFF)
+            main.wait_stream(self.band_stream)
+            for t in (Xb, ub, vb):
+                t.record_stream(main)
+            ub_ref = self.uref[band]
             coef = (self.dA / self.eps_band) * (0.5 * (ub * ub - vb) - ub * ub_ref)
             self.solver.implicit_band_grad(Xb, coef.contiguous(), self.eps_band, grad=grad)
             lb = 0.5 * float(((ub - ub_ref) ** 2).sum())
@@ -195,7 +208,9 @@ class ImplicitShapeOptimizer:
         self.opt.step()
         with torch.no_grad():
             self.pi.view(-1, 3)[:, 0].clamp_(min=self.a_min)
-        self.solver.set_implicit(self.mono, self.c)
+        mono = self.mono
+        self.solver.set_implicit(mono, self.c)
+        self.band_solver.set_implicit(mono, self.c)
         self.region = region
         self.t += 1
         return loss, int(inner.numel())
