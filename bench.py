@@ -871,7 +871,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def fixed_rmse_rate(model, pi, Xt, uref, W, target=0.1, W_probe=512, reps=4):
+def fixed_rmse_rate(model, pi, Xt, uref, W, target=0.1, W_probe=512, reps=8):
     """Shape-gradient evaluations per second at a fixed RMSE (the second
     half of the metric), after the timed window: the reverse-mode gradient
     with weights w = u - uref at the final coefficients; the reference g*
