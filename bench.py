@@ -1,22 +1,30 @@
 #!/usr/bin/env python
 """Benchmark: one shape-optimisation step of differential walk on spheres.
 
-Workload (N = 1): the 2D screened-Poisson star polygon -- 4096 boundary
-segments, r(th) = 1 + sum_{k<=32} a_k cos k th + b_k sin k th with
-a_k, b_k ~ N(0, (0.02/k)^2), sigma = 10, Gaussian source, restricted data
-g = x^2 - y^2, eps = 1e-3, delta = 1e-2 -- with 4096 query points x 4096
-walks, K = 8 nested forward walks per differential terminal (--nested),
-FP32 walks, gradients with respect to the 64 Fourier coefficients
-through DWoSFunction.  One step = move the boundary to the current
-coefficients (device V(pi) + BVH refit), forward walks (u), squared loss
-against a reference solution, backward (differential walks with nested
-forward walks, reverse-mode scatter, SpMV) and an Adam update of the
-coefficients.
+Default workload (N = 1, --workload c3): 3D shape from diffusion -- a
+class-I geodesic icosphere of frequency 100 (200,000 triangles) displaced
+along the normal by 1024 angular Gaussian bumps with coefficients
+N(0, 0.05^2), inside the box [-2, 2]^3, u = 1 on the object and 0 on the
+box, sigma = 4, eps = 4e-3, delta = 4e-2, K = 1 nested walk per
+differential terminal -- with 65536 query points on the box faces
+|coord| = 1.9 x 1024 walks, FP32 walks, gradients with respect to the 1024
+coefficients through DWoSFunction.  One step = move the boundary to the
+current coefficients (device V(pi) + BVH refit), forward walks (u), squared
+loss against a reference solution, backward (differential walks with the
+nested forward walks, reverse-mode scatter, SpMV) and an Adam update.
 
-value = walk steps (closest-point queries of every forward, differential and
-nested walk) per second over the timed steps.  The roofline object reports
-the differential walk kernel against the FP32 vector-ALU peak; see the
-design notes for the per-unit operation counts.
+value = walk steps (closest-point queries executed by every forward,
+differential and nested walk) per second over the timed steps.  The
+roofline object prices the dominant walk kernel's node and triangle reads
+against the HBM peak, with the project's random-gather probe at the scene's
+working-set size beside it.  After the timed window, at a pinned state (the
+initial coefficients, independent of --steps), the second half of the
+metric: shape-gradient evaluations per second at a fixed relative RMSE of
+0.1, plain walks, the paper's 16 nested walks per terminal (Table 1) and
+the learned control variate (the surrogate), and the surrogate's speedup.
+
+--workload c2 is the 2D screened-Poisson star (4096 segments, 4096 points x
+4096 walks, K = 8); the other workloads are listed under --workload.
 """
 import argparse
 import json
@@ -47,7 +55,28 @@ OPS_STEP_2D = 40
 OPS_SOURCE_2D = 200
 PEAK_FP32_VALU = 157.3e12     # MI355X FP32 vector, FLOP/s
 PEAK_HBM = 8.0e12             # bytes/s
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_kernel_c2_star4096_hbm.txt")
+TRAFFIC_FILES = {
+    "c2": os.path.join(ROOT, "profiles", "walk_kernel_c2_star4096_hbm.txt"),
+    "c3": os.path.join(ROOT, "profiles", "walk_kernel_c3_icosphere200k_hbm.txt"),
+}
+
+# Algorithmic bytes per counted unit of the 3D walk kernel: a pair-node visit
+# reads both children's boxes and slabs and the two child references (24
+# FP32 words, 96 B); a triangle test reads its three vertices (9 FP32 words,
+# 36 B; the 12 B that pad the stored record to three 16-byte words are not
+# counted).
+BYTES_NODE_3D = 96
+BYTES_PRIM_3D = 36
+# Algorithmic FP32 operations per counted unit (3D), for the ALU side of the
+# same kernel: a pair-node visit is two point-box squared distances (3 dims
+# x [2 sub, 2 max, 1 fma] = 15) and two point-slab ones (3 fma, abs-sub,
+# max, mul = 6) and their maxima (2 x 21 + 2 = 44); a point-triangle test
+# ~70 (Voronoi-region classification, Ericson Sec. 5.1.5); a walk step ~100
+# (one Philox4x32-10 call, ~40 integer operations, direction, roulette
+# scale, position update).
+OPS_NODE_3D = 44
+OPS_PRIM_3D = 70
+OPS_STEP_3D = 100
 
 
 # the files the walk kernel is compiled from (its build flags are hashed too)
@@ -68,12 +97,12 @@ def sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, nested):
+def measured_traffic(kernel, nested, workload="c2"):
     """Scaled FETCH_SIZE + WRITE_SIZE bytes per launch of `kernel` from the
-    committed counter summary, or None when it is missing or was taken on
-    different kernel sources or another nested-walk count."""
+    committed counter summary of the workload, or None when it is missing or
+    was taken on different kernel sources or another nested-walk count."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILES[workload]) as f:
             text = f.read()
     except OSError:
         return None
@@ -90,7 +119,7 @@ def kernel_ops(tot, has_source=True):
             + (nonterm * OPS_SOURCE_2D if has_source else 0))
 
 
-def cpu_baseline(sc, X, uref_np, seed, threads, npts=1024, W=1024):
+def cpu_baseline(sc, X, seed, threads, npts=1024, W=1024, what=""):
     """The FP64 oracle on a bounded sample of the same workload (forward and
     differential walks of npts points x W walks each)."""
     import numpy as np
@@ -104,7 +133,8 @@ def cpu_baseline(sc, X, uref_np, seed, threads, npts=1024, W=1024):
     dt = time.perf_counter() - t0
     return {"value": (s1 + s2) / dt, "unit": "walk-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{npts} points x {W} forward walks + {npts} x {W} differential walks "
-                      f"(K={sc.K} nested) of the same scene, brute-force FP64, {dt:.1f} s"}
+                      f"(K={sc.K} nested) of the same scene ({what}brute-force closest points), FP64, "
+                      f"{dt:.1f} s", "walk_steps": int(s1 + s2)}
 
 
 def run_c5(args):
@@ -393,7 +423,7 @@ def run_thermal(args):
 
     dev = torch.device("cuda:0")
     P, W = args.points or 16384, args.walks or 256
-    sc = scenes.thermal_scene(K=args.nested)
+    sc = scenes.thermal_scene(K=8 if args.nested is None else args.nested)
     X, seg = scenes.points_on_segments(sc.NV, sc.nsegs, P, 1)
     Xt = torch.tensor(X, dtype=torch.float64, device=dev)
     ref = dw.Solver.from_scene(scenes.thermal_scene(coef_seed=3), "fp32")
@@ -708,32 +738,277 @@ def run_adjoint(args):
     return res
 
 
+def probe_gather(ws_bytes):
+    """The project's random-gather probe (dwos_probe_bandwidth): GB/s of
+    random 64-byte gathers over a buffer of the walk kernel's working-set
+    size, of the same gathers over 4 GiB (HBM-resident), and of a streaming
+    read of 4 GiB."""
+    import ctypes as C
+    from paper_2405_12964_amd import capi
+
+    def run(nbytes, line, mode):
+        g, ms = C.c_double(), C.c_double()
+        capi.check(capi.dwos_probe_bandwidth(int(nbytes), int(line), int(mode), C.byref(g), C.byref(ms)))
+        return g.value
+
+    ws = max(1 << 16, int(ws_bytes))
+    return {"working_set_bytes": ws,
+            "gather64_working_set_GBs": run(ws, 64, 0),
+            "gather64_4GiB_GBs": run(4 << 30, 64, 0),
+            "stream_4GiB_GBs": run(4 << 30, 64, 1)}
+
+
+def grad_rmse_rate(solver, Xt, w, target=0.1, W_probe=256, reps=12, seed0=60000, W_time_max=4096):
+    """Shape-gradient evaluations per second at a fixed relative RMSE.
+
+    The reverse-mode gradient g = sum_p w_p udot(x_p) (dwos_grad, fixed
+    weights w) is unbiased, so its RMSE about the exact gradient g* is the
+    root of its variance.  `reps` independent gradients at W_probe walks per
+    point give the per-parameter variance (ddof 1) and, from their mean, the
+    bias-corrected ||g*||^2 = mean(gbar^2) - var/reps.  With variance ~ 1/W,
+    the walks per point that reach RMSE = target ||g*||_RMS are
+    W* = W_probe (rel_rmse / target)^2.  The time per gradient is measured at
+    min(W*, W_time_max) walks per point and scaled linearly in W beyond it
+    (a gradient at W walks runs ceil(P W / 2^26) identical launches)."""
+    import numpy as np
+    import torch
+    gs, ts = [], []
+    solver.grad(Xt, w, W_probe, seed0 - 1, u_mean=False)
+    for r in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g, _ = solver.grad(Xt, w, W_probe, seed0 + r, u_mean=False)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+        gs.append(g.cpu().numpy())
+    G = np.array(gs)
+    var = G.var(axis=0, ddof=1)
+    mse = float(var.mean())
+    gstar2 = float(np.mean(G.mean(axis=0) ** 2) - var.mean() / reps)
+    if not gstar2 > 0:
+        return {"error": "gradient not resolved above its noise at the probe", "mse_at_probe": mse}
+    rel = math.sqrt(mse / gstar2)
+    Wstar = max(1, int(math.ceil(W_probe * (rel / target) ** 2)))
+    Wt = min(Wstar, W_time_max)
+    solver.grad(Xt, w, Wt, seed0 + 1000, u_mean=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(2):
+        solver.grad(Xt, w, Wt, seed0 + 1001 + r, u_mean=False)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / 2 * (Wstar / Wt)
+    return {"target_rel_rmse": target, "walks_per_point": Wstar, "grad_evals_per_s": 1.0 / t,
+            "ms_per_grad": 1e3 * t, "timed_walks_per_point": Wt, "extrapolated": Wstar > Wt,
+            "rel_rmse_at_probe": rel, "probe_walks_per_point": W_probe, "probe_replicates": reps,
+            "ms_per_grad_at_probe": 1e3 * float(np.median(ts)),
+            "grad_rms": math.sqrt(gstar2),
+            # relative standard error of the ||g*|| estimate from the pooled replicates
+            "grad_rms_rel_se": 0.5 * rel / math.sqrt(reps)}
+
+
+def run_c3(args):
+    """The default workload: 3D shape from diffusion on the 200,000-triangle
+    displaced icosphere, 65536 box-face points x 1024 walks, gradients with
+    respect to the 1024 coefficients through DWoSFunction (see the module
+    docstring)."""
+    import numpy as np
+    import torch
+    import scenes
+    import paper_2405_12964_amd as dw
+
+    dev = torch.device("cuda:0")
+    P, W = args.points or 65536, args.walks or 1024
+    K = args.nested if args.nested is not None else 1
+    nb = 1024
+    sc = scenes.c3_icosphere(nu=100, n_basis=nb, coef_seed=0, K=K)
+    X = scenes.points_on_box_faces(P, 1)
+    Xt = torch.tensor(X, dtype=torch.float64, device=dev)
+    print(f"scene: {sc.prims.shape[0]} triangles, {P} points", file=sys.stderr, flush=True)
+
+    if args.calib_copy_mb:
+        a = torch.empty(args.calib_copy_mb * (1 << 20) // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        b = a.clone()
+        torch.cuda.synchronize()
+        del a, b
+
+    # reference solution at the target coefficients (seed 3; setup, untimed)
+    coef_t = np.random.default_rng(3).normal(0.0, 0.05, nb)
+    ref = dw.Solver.from_scene(sc, "fp32", V=scenes.vertices_at(sc, coef_t))
+    uref, _ = ref.solve(Xt, W, 99, var=False)
+    torch.cuda.synchronize()
+    del ref
+    print("reference solution done", file=sys.stderr, flush=True)
+
+    model = dw.ShapeModel(sc, "fp32")
+    pi = torch.tensor(sc.pi0, dtype=torch.float64, device=dev, requires_grad=True)
+    opt = torch.optim.Adam([pi], lr=1e-3)
+
+    def step(i):
+        opt.zero_grad(set_to_none=True)
+        u = dw.DWoSFunction.apply(pi, Xt, model, W, 1000 + 2 * i, W, 1001 + 2 * i)
+        loss = 0.5 * ((u - uref) ** 2).sum()
+        loss.backward()
+        opt.step()
+        return loss
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    print(f"{args.warmup} warmup steps done", file=sys.stderr, flush=True)
+    for kind in (0, 1):
+        model.solver.walk_timing(kind, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        loss = step(args.warmup + i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    print(f"{args.steps} timed steps done", file=sys.stderr, flush=True)
+    ms0, n0, tot0 = model.solver.walk_timing(0)
+    ms1, n1, tot1 = model.solver.walk_timing(1)
+    for t in (tot0, tot1):
+        assert t["stack_overflow"] == 0 and t["invalid"] == 0 and t["truncated"] == 0, t
+    steps_total = tot0["steps"] + tot1["steps"]
+    kind, ms, n, tot = (1, ms1, n1, tot1) if ms1 >= ms0 else (0, ms0, n0, tot0)
+    avg_s = ms / max(1, n) / 1e3
+    kname = f"walk_kernel<float,3,{kind},true>"
+    bytes_launch = (tot["nodes"] * BYTES_NODE_3D + tot["prims"] * BYTES_PRIM_3D) / max(1, n)
+    ops_launch = (tot["nodes"] * OPS_NODE_3D + tot["prims"] * OPS_PRIM_3D + tot["steps"] * OPS_STEP_3D) / max(1, n)
+    achieved = bytes_launch / avg_s
+    # the scene's node and primitive arrays: what the traversals gather from
+    info = model.solver.scene_info()
+    probe = probe_gather(info["node_bytes"] + info["prim_bytes"])
+    roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM, "traffic": measured_traffic(kname, K, "c3"),
+            "kernel": kname, "avg_launch_ms": ms / max(1, n), "launches": n,
+            "algorithmic_bytes_per_launch": bytes_launch,
+            "bytes_per_step": bytes_launch / max(1.0, tot["steps"] / max(1, n)),
+            "steps_per_launch": tot["steps"] / max(1, n),
+            "nodes_per_step": tot["nodes"] / max(1, tot["steps"]),
+            "prims_per_step": tot["prims"] / max(1, tot["steps"]),
+            "scene": info,
+            "gather_probe": probe,
+            "frac_of_gather_probe": achieved / (probe["gather64_working_set_GBs"] * 1e9),
+            "alu": {"achieved_TFLOPs": ops_launch / avg_s / 1e12, "peak_TFLOPs": PEAK_FP32_VALU / 1e12,
+                    "frac": ops_launch / avg_s / PEAK_FP32_VALU}}
+    out = {
+        "metric": METRIC, "value": steps_total / elapsed, "unit": "walk-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "3D shape from diffusion: displaced icosphere (200,000 triangles, 1024 "
+                               "radial-basis coefficients N(0,0.05^2)) in the box [-2,2]^3, u=1 on the object, "
+                               f"0 on the box, sigma=4, eps=4e-3, delta=4e-2; {P} box-face points x {W} walks, "
+                               f"grads wrt the 1024 coefficients via autograd (forward walks + differential "
+                               f"walks, K={K} nested)",
+                   "points": P, "walks_per_point": W, "triangles": int(sc.prims.shape[0]), "params": nb,
+                   "nested_walks_per_terminal": K},
+        "grad_evals_per_s": args.steps / elapsed,
+        "walk_steps": {"forward": tot0["steps"], "differential": tot1["steps"],
+                       "forward_ms": ms0, "differential_ms": ms1,
+                       "forward_walks": tot0["walks"], "differential_walks": tot1["walks"],
+                       "nested_walks": tot1["nested_walks"]},
+        "loss": float(loss.item()),
+        "roofline": roof,
+    }
+    if not args.no_fixed_rmse:
+        out["fixed_rmse"] = c3_fixed_rmse(args, sc, Xt, uref)
+    if not args.no_cpu_baseline:
+        threads = min(16, len(os.sched_getaffinity(0)))
+        out["cpu_baseline"] = cpu_baseline(sc, X, 7, threads, npts=args.cpu_points or 64, W=args.cpu_walks or 16,
+                                           what="full 200,000-triangle mesh, ")
+    return out
+
+
+def c3_fixed_rmse(args, sc, Xt, uref):
+    """The metric's second half at a pinned state: the initial coefficients
+    (seed 0) and fixed weights w = u - uref (u from 1024 walks per point,
+    seed 777), independent of the timed steps.  Three estimators of the same
+    gradient: plain walks with K = 1 nested walk per terminal, the paper's
+    Table 1 setting of 16 nested walks, and the learned control variate of
+    the nested walks (q = 1, trained online at this state on earlier walks
+    only).  Reported per estimator: walks per point for a relative RMSE of
+    0.1 and gradient evaluations per second there; and the surrogate's
+    speedup at equal RMSE over plain walks."""
+    import numpy as np
+    import torch
+    import scenes
+    import paper_2405_12964_amd as dw
+
+    s = dw.Solver.from_scene(sc.with_(K=1), "fp32")
+    u, _ = s.solve(Xt, 1024, 777, var=False)
+    w = (u - uref).contiguous()
+    res = {"state": "initial coefficients (seed 0), w = u(1024 walks, seed 777) - uref",
+           "estimator": "reverse mode sum_p w_p udot(x_p), fixed w"}
+    res["plain"] = grad_rmse_rate(s, Xt, w, W_probe=args.probe_walks, seed0=60000)
+    print("fixed-RMSE plain done", file=sys.stderr, flush=True)
+    s16 = dw.Solver.from_scene(sc.with_(K=16), "fp32")
+    res["nested16"] = grad_rmse_rate(s16, Xt, w, W_probe=args.probe_walks, seed0=70000)
+    del s16
+    print("fixed-RMSE K=16 done", file=sys.stderr, flush=True)
+    # the surrogate: the control-variate network trained online at this state
+    B, th = scenes.mlp_init(3, args.cv_seed, args.cv_freq, args.cv_features)
+    th[-(scenes.MLP_WIDTH + 1):] = 0.0        # N = 0: the first calls are plain
+    net = dw.Network(3, B, th)
+    s.attach_cv(net, 1.0)
+    t0 = time.perf_counter()
+    for i in range(args.cv_iters):
+        s.grad(Xt, w, args.cv_walks, 80000 + i, u_mean=False)
+        s.cv_train(args.cv_steps, args.cv_batch, args.cv_lr, 90000 + i)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    cv = grad_rmse_rate(s, Xt, w, W_probe=args.probe_walks, seed0=100000)
+    cv["beta"] = s.cv_beta()
+    cv["training"] = {"iterations": args.cv_iters, "walks_per_point": args.cv_walks,
+                      "adam_steps_per_iteration": args.cv_steps, "batch": args.cv_batch, "lr": args.cv_lr,
+                      "frequencies": args.cv_features, "freq_scale": args.cv_freq, "init_seed": args.cv_seed,
+                      "seconds": train_s}
+    res["control_variate"] = cv
+    print("fixed-RMSE control variate done", file=sys.stderr, flush=True)
+    p = res["plain"]
+    if "ms_per_grad" in p and "ms_per_grad" in cv:
+        res["surrogate_speedup_at_equal_rmse"] = p["ms_per_grad"] / cv["ms_per_grad"]
+    if "ms_per_grad" in p and "ms_per_grad" in res["nested16"]:
+        res["nested16_speedup_at_equal_rmse"] = p["ms_per_grad"] / res["nested16"]["ms_per_grad"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", choices=["c2", "c4", "c5", "c5ls", "thermal", "inflation", "adjoint"],
-                    default="c2",
-                    help="c2: 2D star (the reported configuration); c4: batched instances; c5: 3D "
-                         "shape from diffusion with the learned control variate; c5ls: 3D shape from "
-                         "diffusion with vertex parameters and the preconditioned vector Adam; "
-                         "thermal: walk on stars with a reflecting boundary; inflation: curve inflation "
-                         "on an implicit boundary of harmonic monopoles; adjoint: the adjoint formulation "
-                         "of Appendix B against the differential walks")
+    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5", "c5ls", "thermal", "inflation", "adjoint"],
+                    default="c3",
+                    help="c3: 3D shape from diffusion on the 200,000-triangle icosphere (the reported "
+                         "configuration); c2: 2D star; c4: batched instances; c5: 3D shape from diffusion "
+                         "with the learned control variate; c5ls: 3D shape from diffusion with vertex "
+                         "parameters and the preconditioned vector Adam; thermal: walk on stars with a "
+                         "reflecting boundary; inflation: curve inflation on an implicit boundary of harmonic "
+                         "monopoles; adjoint: the adjoint formulation of Appendix B against the differential "
+                         "walks")
     ap.add_argument("--points", type=int, default=0)
-    ap.add_argument("--nested", type=int, default=8,
-                    help="default and thermal workloads: nested forward walks per differential terminal "
-                         "(K; the paper uses 2-16, 8 for its thermal design)")
+    ap.add_argument("--nested", type=int, default=None,
+                    help="nested forward walks per differential terminal (K): c3 1, c2 and thermal 8 "
+                         "(the paper uses 2-16, 8 for its thermal design)")
     ap.add_argument("--walks", type=int, default=0)
-    ap.add_argument("--no-cpu-baseline", action="store_true",
-                    help="skip the oracle timing (and, for the default workload, the fixed-RMSE gradient rate)")
-    ap.add_argument("--cv-freq", type=float, default=0.125, help="c5: Fourier frequency scale")
-    ap.add_argument("--cv-features", type=int, default=30, help="c5: Fourier frequencies (2F + 3 <= 64)")
-    ap.add_argument("--cv-steps", type=int, default=16, help="c5: network Adam steps per iteration")
-    ap.add_argument("--cv-batch", type=int, default=8192, help="c5: walks per network Adam step")
-    ap.add_argument("--cv-lr", type=float, default=1e-3, help="c5: network learning rate")
-    ap.add_argument("--cv-seed", type=int, default=4, help="c5: network initialisation seed")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--no-fixed-rmse", action="store_true",
+                    help="c3, c2: skip the gradient rate at fixed RMSE (and the control variate's speedup)")
+    ap.add_argument("--probe-walks", type=int, default=256,
+                    help="c3, c2: walks per point of the replicate gradients that measure the RMSE")
+    ap.add_argument("--cpu-points", type=int, default=0, help="c3: points of the oracle's sample (64)")
+    ap.add_argument("--cpu-walks", type=int, default=0, help="c3: walks per point of the oracle's sample (16)")
+    ap.add_argument("--cv-freq", type=float, default=0.125, help="c3, c5: Fourier frequency scale")
+    ap.add_argument("--cv-features", type=int, default=16, help="c3, c5: Fourier frequencies (2F + 3 <= 64)")
+    ap.add_argument("--cv-steps", type=int, default=16, help="c3, c5: network Adam steps per iteration")
+    ap.add_argument("--cv-batch", type=int, default=8192, help="c3, c5: walks per network Adam step")
+    ap.add_argument("--cv-lr", type=float, default=1e-3, help="c3, c5: network learning rate")
+    ap.add_argument("--cv-seed", type=int, default=4, help="c3, c5: network initialisation seed")
+    ap.add_argument("--cv-iters", type=int, default=100,
+                    help="c3: training iterations of the control variate at the pinned state")
+    ap.add_argument("--cv-walks", type=int, default=64,
+                    help="c3: walks per point of each training iteration's differential call")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -772,9 +1047,21 @@ def main():
         args.warmup = 150 if args.warmup is None else args.warmup
         print(json.dumps(run_c5(args)), flush=True)
         return
+    if args.workload == "c2":
+        args.steps = 5 if args.steps is None else args.steps
+        args.warmup = 2 if args.warmup is None else args.warmup
+        args.nested = 8 if args.nested is None else args.nested
+        print(json.dumps(run_c2(args)), flush=True)
+        return
     args.steps = 5 if args.steps is None else args.steps
     args.warmup = 2 if args.warmup is None else args.warmup
+    print(json.dumps(run_c3(args)), flush=True)
 
+
+def run_c2(args):
+    """2D screened-Poisson star: 4096 segments, 4096 points x 4096 walks,
+    K nested walks (--nested, 8 by default), gradients with respect to the 64
+    Fourier coefficients through DWoSFunction."""
     import numpy as np
     import torch
     import scenes
@@ -837,7 +1124,7 @@ def main():
     # the default launch shape: the LDS-staged 1024-thread walk kernel
     kname = f"walk_kernel<float,2,{kind},true>"
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": measured_traffic(kname, args.nested),
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": measured_traffic(kname, args.nested, "c2"),
             "kernel": kname, "avg_launch_ms": ms / max(1, n),
             "launches": n, "ops_per_launch": ops,
             "steps_per_launch": tot["steps"] / max(1, n),
@@ -863,43 +1150,27 @@ def main():
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        out["fixed_rmse"] = fixed_rmse_rate(model, pi, Xt, uref, W)
+        out["fixed_rmse"] = c2_fixed_rmse(args, sc, Xt, uref)
         threads = min(16, len(os.sched_getaffinity(0)))
         # a sample of ~20 s: 1024 points at K = 1, fewer as the nested walks grow
         npts = max(128, 1024 // max(1, (args.nested + 1) // 2) * 2)
-        out["cpu_baseline"] = cpu_baseline(sc, X, uref.cpu().numpy(), 7, threads, npts=min(1024, npts))
-    print(json.dumps(out), flush=True)
+        out["cpu_baseline"] = cpu_baseline(sc, X, 7, threads, npts=min(1024, npts))
+    return out
 
 
-def fixed_rmse_rate(model, pi, Xt, uref, W, target=0.1, W_probe=512, reps=8):
-    """Shape-gradient evaluations per second at a fixed RMSE (the second
-    half of the metric), after the timed window: the reverse-mode gradient
-    with weights w = u - uref at the final coefficients; the reference g*
-    from 64 W walks per point; the RMSE at W_probe walks over `reps` seeds,
-    extrapolated by RMSE ~ W^-1/2 to the walks per point W* that give
-    RMSE = target ||g*||_RMS; the rate is timed at W*."""
-    import numpy as np
-    import torch
-    with torch.no_grad():
-        model.apply(pi)
-        u, _ = model.solver.solve(Xt, W, 777)
-        w = (u - uref).contiguous()
-    gstar = model.solver.grad(Xt, w, 64 * W, 4242, u_mean=False)[0].cpu().numpy()
-    rms = lambda v: float(np.sqrt(np.mean(np.square(v))))
-    errs = [rms(model.solver.grad(Xt, w, W_probe, 5000 + r, u_mean=False)[0].cpu().numpy() - gstar)
-            for r in range(reps)]
-    rmse = float(np.sqrt(np.mean(np.square(errs))))
-    Wstar = max(1, int(math.ceil(W_probe * (rmse / (target * rms(gstar))) ** 2)))
-    model.solver.grad(Xt, w, Wstar, 6000, u_mean=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for r in range(3):
-        model.solver.grad(Xt, w, Wstar, 6001 + r, u_mean=False)
-    torch.cuda.synchronize()
-    t = (time.perf_counter() - t0) / 3
-    return {"target_rel_rmse": target, "walks_per_point": Wstar, "grad_evals_per_s": 1.0 / t,
-            "ms_per_grad": 1e3 * t, "rmse_at_probe": rmse, "probe_walks_per_point": W_probe,
-            "reference_walks_per_point": 64 * W, "grad_rms": rms(gstar)}
+
+
+def c2_fixed_rmse(args, sc, Xt, uref):
+    """Gradient evaluations per second at a fixed relative RMSE of 0.1 on the
+    star, at a pinned state: the initial coefficients (seed 0) and weights
+    w = u - uref with u from 4096 walks per point (seed 777)."""
+    import paper_2405_12964_amd as dw
+    s = dw.Solver.from_scene(sc, "fp32")
+    u, _ = s.solve(Xt, 4096, 777, var=False)
+    w = (u - uref).contiguous()
+    res = grad_rmse_rate(s, Xt, w, W_probe=args.probe_walks, seed0=60000)
+    res["state"] = "initial coefficients (seed 0), w = u(4096 walks, seed 777) - uref"
+    return res
 
 
 if __name__ == "__main__":

@@ -119,7 +119,9 @@ typedef struct dwos_problem {
 typedef struct dwos_stats {
     int64_t walks;         /* forward or differential walks started */
     int64_t nested_walks;  /* forward walks nested at differential terminals */
-    int64_t steps;         /* closest-point queries, all walks (the walk-step unit) */
+    int64_t steps;         /* closest-point queries executed, all walks (the walk-step
+                              unit); the first query of a point, shared by all its
+                              walks, counts once */
     int64_t terminal;      /* main walks that reached the eps-shell */
     int64_t truncated;     /* walks cut at kmax */
     int64_t nodes;         /* BVH pair nodes visited */
@@ -214,6 +216,15 @@ dwos_status dwos_grad_sqloss(dwos_ctx* ctx, const double* X, int64_t P, const do
 dwos_status dwos_jvp(dwos_ctx* ctx, const double* X, int64_t P, int32_t W, uint64_t seed,
                      double* udot, double* udot_var, double* u_mean, dwos_stats* stats);
 
+/* Sizes of the closest-point structures of a mesh boundary (host output,
+ * 8 int64): [0] BVH pair nodes, [1] bytes of the node array, [2] bytes of the
+ * primitive array (in the working precision, Sec. 6 layout), [3] pair nodes
+ * the FP32 walk kernel stages in LDS (the breadth-first prefix), [4] 1 if it
+ * stages every primitive as well, [5] primitives, [6] vertices, [7] LDS bytes
+ * per block of the staged launch.  Errors: EINVAL (NULL), ESTATE (no mesh
+ * boundary). */
+dwos_status dwos_scene_info(dwos_ctx* ctx, int64_t* info);
+
 /* Launch-shape autotuner.  Times a forward solve of the first min(P, 512)
  * points with W walks under each walk-kernel launch shape and keeps the
  * fastest for the context (FP32 only):
@@ -271,6 +282,21 @@ dwos_status dwos_eval_ball_kernels(dwos_ctx* ctx, const double* r, const double*
  * reset != 0 clears the accumulators of that kind after reading. */
 dwos_status dwos_walk_timing(dwos_ctx* ctx, int32_t kind, int32_t reset, double* walk_ms,
                              int64_t* launches, dwos_stats* totals);
+
+/* Memory-bandwidth probe (a measurement aid, no part of the estimator).  A
+ * closest-point traversal (Algorithm 1, DistanceToBoundary) reads one BVH
+ * node or primitive at an address that depends on its query, so its memory
+ * roofline is the rate of random gathers of short records over the scene's
+ * working set, not the streaming rate.  On the current device, with a
+ * buffer of `bytes` (64 KiB .. 64 GiB, allocated and freed by the call):
+ *   mode 0: random gathers of line_bytes (16, 32, 48, 64, 96 or 128) at
+ *           uniformly drawn line addresses, 64 per thread, many in flight;
+ *   mode 1: one coalesced streaming read of the whole buffer (line_bytes
+ *           ignored).
+ * The pattern is run once to warm the caches, then timed 8 times; gbps
+ * (host) gets the bytes read per second of the fastest run in GB/s, ms
+ * (host, may be NULL) its duration.  Errors: EINVAL, ENOMEM, EDEVICE. */
+dwos_status dwos_probe_bandwidth(int64_t bytes, int32_t line_bytes, int32_t mode, double* gbps, double* ms);
 
 /* ---- The adjoint formulation (Appendix B), an ablation ------------------
  * eq. (functional_deriv_adjoint): the derivative of a shape functional as a
@@ -345,7 +371,8 @@ dwos_status dwos_batch_set_parameters(dwos_ctx* ctx, int32_t index, int64_t N, c
  * and w (device) back to back as in dwos_batch_solve, P (host) the counts;
  * u_mean (device, sum_i P[i], or NULL) the joint u estimates.  Every instance
  * must share delta (the offset of the normal derivative).
- * Errors: EINVAL (counts, NULL arguments, differing delta), ESTATE (no
+ * Errors: EINVAL (counts, NULL arguments, differing delta, an instance with
+ * sigma > 0 while the problem's rr = 0), ESTATE (no
  * instances, problem or parameters; control variate or gradient normal-
  * derivative estimator set), ENOMEM (more than 2^28 walks). */
 dwos_status dwos_batch_grad(dwos_ctx* ctx, const double* X_all, const int64_t* P, const double* w,
@@ -353,7 +380,9 @@ dwos_status dwos_batch_grad(dwos_ctx* ctx, const double* X_all, const int64_t* P
 
 /* Solve every instance in one persistent launch: X_all (device) holds the
  * instances' points back to back (sum_i P[i] x dim), P (host, I counts),
- * W walks per point; u_mean/u_var (device, sum_i P[i]).  Errors as solve. */
+ * W walks per point; u_mean/u_var (device, sum_i P[i]).  Errors as solve;
+ * EINVAL also for an instance with sigma > 0 while the problem's rr = 0
+ * (screening needs Russian roulette, Sec. 3.3). */
 dwos_status dwos_batch_solve(dwos_ctx* ctx, const double* X_all, const int64_t* P,
                              int32_t W, uint64_t seed, double* u_mean, double* u_var,
                              dwos_stats* stats);

@@ -1773,6 +1773,29 @@ dwos_status dwos_implicit_band_grad(dwos_ctx* c, const double* X, int64_t P, con
     return DWOS_OK;
 }
 
+dwos_status dwos_scene_info(dwos_ctx* c, int64_t* info) {
+    if (!c || !info) return fail(DWOS_EINVAL, "scene_info: NULL argument");
+    if (!c->has_boundary) return fail(DWOS_ESTATE, "scene_info: no mesh boundary");
+    const size_t el = c->prec == DWOS_FP32 ? sizeof(float) : sizeof(double);
+    const int64_t nb = dwos::node_scalars(c->D) * (int64_t)el, pb = dwos::prim_scalars(c->D) * (int64_t)el;
+    int64_t stage_nodes = 0, stage_prims = 0, lds = 0;
+    if (c->prec == DWOS_FP32) {
+        const dwos::Scene<float> sc = make_scene<float>(c);
+        stage_nodes = sc.n_stage_nodes;
+        stage_prims = sc.stage_prims;
+        lds = (int64_t)stage_bytes<float>(sc, c->D);
+    }
+    info[0] = c->n_nodes;
+    info[1] = c->n_nodes * nb;
+    info[2] = c->np * pb;
+    info[3] = stage_nodes;
+    info[4] = stage_prims;
+    info[5] = c->np;
+    info[6] = c->nv;
+    info[7] = lds;
+    return DWOS_OK;
+}
+
 dwos_status dwos_set_variant(dwos_ctx* c, int32_t variant) {
     if (!c) return fail(DWOS_EINVAL, "NULL context");
     if (variant != 0 && variant != 1) return fail(DWOS_EINVAL, "set_variant: variant must be 0 or 1");
@@ -1928,6 +1951,18 @@ dwos_status dwos_batch_add_instance(dwos_ctx* c, const double* V, int64_t nv, co
 }  // extern "C"
 
 namespace {
+
+// A screened instance (sigma > 0) needs Russian roulette: the walks do not
+// carry the product of the attenuation factors (Sec. 3.3).  The problem's rr
+// flag is shared by every instance of a batch, while sigma is per instance.
+dwos_status check_batch_roulette(const dwos_ctx* c, const char* who) {
+    if (c->prob.rr) return DWOS_OK;
+    for (size_t i = 0; i < c->instances.size(); ++i)
+        if (c->instances[i].sigma > 0)
+            return fail(DWOS_EINVAL, std::string(who) + ": instance " + std::to_string(i) +
+                                         " has sigma > 0, which needs Russian roulette (rr = 1)");
+    return DWOS_OK;
+}
 
 template <class T, int D>
 dwos_status run_batch(dwos_ctx* c, const double* X, const int64_t* P, int32_t W, uint64_t seed, double* u_mean,
@@ -2103,6 +2138,7 @@ dwos_status dwos_batch_grad(dwos_ctx* c, const double* X_all, const int64_t* P, 
     if (c->cv) return fail(DWOS_ESTATE, "batch_grad: the control variate is not supported on batch contexts");
     if (c->prob.dudn != 0) return fail(DWOS_ESTATE, "batch_grad: the gradient normal-derivative estimator is not supported on batch contexts");
     if (!P || W < 1 || !grad) return fail(DWOS_EINVAL, "batch_grad: bad P, W or grad");
+    if (dwos_status rr = check_batch_roulette(c, "batch_grad")) return rr;
     int64_t pts = 0, Ntot = 0;
     for (size_t i = 0; i < c->instances.size(); ++i) {
         if (P[i] < 0 || P[i] > INT32_MAX) return fail(DWOS_EINVAL, "batch_grad: bad point count");
@@ -2165,6 +2201,7 @@ dwos_status dwos_batch_solve(dwos_ctx* c, const double* X_all, const int64_t* P,
     if (c->instances.empty()) return fail(DWOS_ESTATE, "batch_solve: no instances");
     if (!c->has_problem) return fail(DWOS_ESTATE, "batch_solve: no problem: call dwos_set_problem first");
     if (!P || W < 1) return fail(DWOS_EINVAL, "batch_solve: bad P or W");
+    if (dwos_status rr = check_batch_roulette(c, "batch_solve")) return rr;
     int64_t pts = 0;
     for (size_t i = 0; i < c->instances.size(); ++i) {
         if (P[i] < 0 || P[i] > INT32_MAX) return fail(DWOS_EINVAL, "batch_solve: bad point count");

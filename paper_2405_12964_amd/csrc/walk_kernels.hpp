@@ -738,6 +738,7 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
         // unfinished skip the rest of this iteration and resume it in the
         // next, so that fast queries do not wait for the slowest one.
         bool ready = false;
+        bool shared = false;   // answered by the point's shared first query
         T d2 = T(0);
         int32_t leaf = -1;
         if (!qpend) {
@@ -745,6 +746,7 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
                 leaf = a.first_leaf[first_row];
                 d2 = a.first_d2[first_row];
                 ready = true;
+                shared = true;
             } else {
                 query_begin<T, D>(a.s, sv, root, x, warm, q);
                 qpend = true;
@@ -769,7 +771,9 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
             ready = true;
         }
         if (!ready) continue;
-        c_steps++;
+        // executed queries: the shared first query of a point (run once for
+        // all its walks) counts once, on the point's walk 0
+        if (!shared || m == 0) c_steps++;
         wsteps++;
         if (leaf < 0 || !(d2 >= T(0))) {
             // non-finite position (e.g. a NaN query point): end the walk with

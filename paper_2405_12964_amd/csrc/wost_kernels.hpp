@@ -522,13 +522,17 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
             // ---- Dirichlet distance ----------------------------------------------
             T d2;
             int32_t leaf;
+            // the first query of a point is run once for all its walks: it
+            // counts as one executed query, on the point's walk 0
+            bool executed = true;
             if (a.first_leaf && phase == 0 && k == 0) {
                 leaf = a.first_leaf[first_row];
                 d2 = a.first_d2[first_row];
+                executed = m == 0;
             } else {
                 leaf = closest_leaf<T, D>(a.s, sv, root, x, warm, d2, qc, stack);
             }
-            c_steps++;
+            if (executed) c_steps++;
             wsteps++;
             if (leaf < 0 || !(d2 >= T(0))) {
                 c_invalid++;

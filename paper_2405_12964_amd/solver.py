@@ -378,6 +378,14 @@ class Solver:
         check(capi.dwos_autotune(self._ctx, _dev(X), X.shape[0], int(W), int(seed), C.byref(ch), ms))
         return ch.value, [ms[0], ms[1]]
 
+    def scene_info(self) -> dict:
+        """Sizes of the BVH and primitive arrays and the LDS staging plan."""
+        info = (C.c_int64 * 8)()
+        check(capi.dwos_scene_info(self._ctx, info))
+        keys = ["nodes", "node_bytes", "prim_bytes", "staged_nodes", "staged_prims", "prims", "vertices",
+                "lds_bytes"]
+        return {k: int(info[i]) for i, k in enumerate(keys)}
+
     def set_variant(self, v: int):
         check(capi.dwos_set_variant(self._ctx, int(v)))
 

@@ -51,8 +51,14 @@ def test_thermal_fullsize(dev, dwos, oracle_mod):
     m, v = s.solve(Xt, 256, 11)
     idx = np.random.default_rng(5).choice(len(X), 8, replace=False)
     om, ov, _ = oracle_mod.Oracle(sc).solve(X[idx], 512, 12, start_seg=seg[idx])
-    print(parity(m.cpu().numpy()[idx], _se(v.cpu().numpy()[idx]), om, _se(ov), abs_tol=2e-3,
+    print(parity(m.cpu().numpy()[idx], _se(v.cpu().numpy()[idx]), om, _se(ov), abs_tol=1e-4,
                  name="thermal solve, sampled"))
+    # forward mode at the sampled points (64 wire-shape parameters)
+    ud_s, uv_s, _ = s.jvp(Xt, 256, 14)
+    oud, ouv, _, _ = oracle_mod.Oracle(sc).jvp(X[idx], 256, 15, start_seg=seg[idx])
+    print(parity(ud_s.cpu().numpy()[idx], _se(uv_s.cpu().numpy()[idx]), oud, _se(ouv), abs_tol=1e-4,
+                 name="thermal jvp, sampled"))
+    del ud_s, uv_s
     w = np.random.default_rng(6).normal(size=len(X))
     ud, _, _ = s.jvp(Xt, 16, 13, var=False)
     g, _ = s.grad(Xt, T(w, dev), 16, 13)
