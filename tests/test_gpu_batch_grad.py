@@ -110,3 +110,28 @@ def test_batch_grad_error_paths(dev, dwos):
         with pytest.raises(DwosError) as e:
             call()
         assert e.value.code == DWOS_ESTATE
+
+
+def test_batch_screened_instance_needs_roulette(dev, dwos):
+    """An instance with sigma > 0 in a batch whose problem has roulette off
+    (rr = 0) is rejected by both batch calls: without roulette the walks would
+    drop the attenuation factors of the screened walk (Sec. 3.3)."""
+    from paper_2405_12964_amd.capi import DwosError, DWOS_EINVAL
+    from paper_2405_12964_amd.solver import make_problem
+    a = scenes.c1_polygon(32, g="one", eps=1e-3, delta=1e-2, sigma=0.0)
+    b = scenes.c1_polygon(32, g="one", eps=1e-3, delta=1e-2, sigma=3.0)
+    X = T(np.concatenate([scenes.points_in_disk(2, 0.5, 1), scenes.points_in_disk(2, 0.5, 2)]), dev)
+    w = T(np.ones(4), dev)
+    s = dwos.Solver(2, "fp32")
+    s.set_problem(make_problem(0.0, a.eps, a.delta, 1, a.kmax, 0, 0.0, None, a.bc, 2))
+    for sc in (a, b):
+        i = s.batch_add_instance(sc.V, sc.prims, sc.label, sc.sigma, sc.eps, sc.delta)
+        s.batch_set_parameters(i, sc.N, sc.rowptr, sc.pid, sc.vel)
+    for call in (lambda: s.batch_solve(X, [2, 2], 4, 1), lambda: s.batch_grad(X, [2, 2], w, 4, 1)):
+        with pytest.raises(DwosError) as e:
+            call()
+        assert e.value.code == DWOS_EINVAL
+    # with roulette on, the same batch runs
+    s.set_problem(make_problem(0.0, a.eps, a.delta, 1, a.kmax, 1, 0.0, None, a.bc, 2))
+    m, _ = s.batch_solve(X, [2, 2], 16, 1)
+    assert np.all(np.isfinite(m.cpu().numpy()))
