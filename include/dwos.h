@@ -189,6 +189,25 @@ dwos_status dwos_set_parameters(dwos_ctx* ctx, int64_t N, const int64_t* rowptr,
 dwos_status dwos_solve(dwos_ctx* ctx, const double* X, int64_t P, int32_t W, uint64_t seed,
                        double* u_mean, double* u_var, dwos_stats* stats);
 
+/* Allocation-free variant of dwos_solve, for callers that cannot allocate
+ * device memory during the call: code under hipGraph stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same walks, random
+ * streams and outputs as dwos_solve with the same arguments (u_mean[P],
+ * u_var[P] or NULL, device FP64; X device P x dim FP64), but every workspace
+ * (work-queue counter, walk counters, the per-point shared first query and
+ * the per-walk values) lives in one fixed device array of 32 MiB that the
+ * library holds on each device from load to process exit; the call allocates
+ * and frees nothing and records no events.  Limit: the workspace must fit,
+ * 1 KiB + P (4 + s) + P W s bytes with s = 4 (FP32) or 8 (FP64), each part
+ * rounded up to 256 bytes: about 8.3 million walks in FP32.  Calls on one
+ * device share that array and its contents persist between calls (each call
+ * clears what it needs): calls that overlap in time on one device, from any
+ * context or stream, race and give wrong results.  No statistics or timing.
+ * Errors: EINVAL (P < 0, W < 1, NULL, workspace too small), ESTATE (no mesh
+ * boundary or problem; batch, reflecting or implicit boundary). */
+dwos_status dwos_solve_noalloc(dwos_ctx* ctx, const double* X, int64_t P, int32_t W, uint64_t seed,
+                               double* u_mean, double* u_var);
+
 /* Reverse mode (Sec. 4, eq. (functional_deriv), domain term): with one
  * differential walk per (p, m) (Algorithm 2, with K nested forward walks at
  * the terminal), accumulates grad[j] = sum_p w[p] * mean_m udot_m[j] into

@@ -24,6 +24,8 @@
 #include "implicit_kernels.hpp"
 #include "adjoint_kernels.hpp"
 
+#include <mutex>
+
 namespace {
 
 using dwos_host::fail;
@@ -32,6 +34,42 @@ using dwos_host::upload;
 using dwos_host::blocks_for;
 
 constexpr int64_t kMaxWalksPerChunk = int64_t(1) << 26;
+
+// Workspace of the allocation-free solve (dwos_solve_noalloc): one fixed
+// array per device, held from module load to process exit.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in for
+// the symbol); it uses the device address resolved per device by
+// resolve_scratch() when a context is created.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+constexpr int kScratchMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+// Device address of `scratch` on device `dev` (which must be current),
+// resolved once per device.
+dwos_status resolve_scratch(int dev) {
+    if (dev < 0 || dev >= kScratchMaxDevices) return fail(DWOS_EDEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return DWOS_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(DWOS_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+    return DWOS_OK;
+}
+
+void* scratch_ptr(int dev) {
+    if (dev < 0 || dev >= kScratchMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
 
 struct InstanceHost {
     int32_t root;            // root pair node in the combined node array
@@ -415,26 +453,28 @@ dwos_status ensure_totals(dwos_ctx* c) {
 }
 
 template <class T, int D, int MODE, bool staged>
-dwos_status launch_shape(dwos_ctx* c, dwos::WalkArgs<T>& a);
+dwos_status launch_shape(dwos_ctx* c, dwos::WalkArgs<T>& a, bool timed);
 
 // Launch the persistent walk kernel over `total` walks.  FP32 uses the
 // LDS-staged kernel (one large block per CU); the FP64 debug build keeps
-// everything in global memory.
+// everything in global memory.  `tot` (cumulative counters of this walk
+// kind) defaults to the context's; an untimed launch records no events.
 template <class T, int D, int MODE>
-dwos_status launch_walks(dwos_ctx* c, dwos::WalkArgs<T>& a) {
+dwos_status launch_walks(dwos_ctx* c, dwos::WalkArgs<T>& a, dwos::Counters* tot = nullptr,
+                         bool timed = true) {
     hipStream_t s = c->stream;
-    a.tot = c->totals.as<dwos::Counters>() + (MODE ? 1 : 0);
+    a.tot = tot ? tot : c->totals.as<dwos::Counters>() + (MODE ? 1 : 0);
     hipLaunchKernelGGL(dwos::fill_u64_kernel, dim3(1), dim3(64), 0, s, a.queue, (int64_t)1);
     if constexpr (sizeof(T) == 4) {
-        if (c->variant == 1) return launch_shape<T, D, MODE, false>(c, a);
-        return launch_shape<T, D, MODE, true>(c, a);
+        if (c->variant == 1) return launch_shape<T, D, MODE, false>(c, a, timed);
+        return launch_shape<T, D, MODE, true>(c, a, timed);
     } else {
-        return launch_shape<T, D, MODE, false>(c, a);
+        return launch_shape<T, D, MODE, false>(c, a, timed);
     }
 }
 
 template <class T, int D, int MODE, bool staged>
-dwos_status launch_shape(dwos_ctx* c, dwos::WalkArgs<T>& a) {
+dwos_status launch_shape(dwos_ctx* c, dwos::WalkArgs<T>& a, bool timed) {
     hipStream_t s = c->stream;
     constexpr int block = staged ? dwos::kBlockStaged : dwos::kBlock;
     const size_t smem = staged ? stage_bytes<T>(a.s, D) : 0;
@@ -460,7 +500,7 @@ dwos_status launch_shape(dwos_ctx* c, dwos::WalkArgs<T>& a) {
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)per_cu * c->cu_count));
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     HIP_OK(hipStreamIsCapturing(s, &cap));
-    if (cap != hipStreamCaptureStatusNone) {   // captured launches are not timed
+    if (cap != hipStreamCaptureStatusNone || !timed) {   // captured launches are not timed
         hipLaunchKernelGGL(kern, dim3(grid), dim3(block), smem, s, a);
         HIP_OK(hipGetLastError());
         return DWOS_OK;
@@ -933,6 +973,77 @@ dwos_status run_op(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
     return finish_call(c, st, ev_from);
 }
 
+// ---------------------------------------------------------------------------
+// allocation-free solve: every workspace in the device's `scratch` array
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void set_instance_kernel(dwos::Instance<T>* dst, dwos::Instance<T> v) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *dst = v;
+}
+
+// Layout of the scratch array for a solve of P points x W walks: work-queue
+// counter, this call's and the cumulative walk counters, the instance, then
+// 256-byte aligned per-point first queries and per-walk values.
+struct NoAllocLayout {
+    size_t queue = 0, cnt = 64, tot = 256, inst = 512, head = 1024;
+    size_t leaf, d2, rec, end;
+    NoAllocLayout(int64_t P, int32_t W, size_t el) {
+        auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+        leaf = head;
+        d2 = leaf + up((size_t)P * sizeof(int32_t));
+        rec = d2 + up((size_t)P * el);
+        end = rec + up((size_t)P * (size_t)W * el);
+    }
+};
+
+template <class T, int D>
+dwos_status run_solve_noalloc(dwos_ctx* c, const double* X, int64_t P, int32_t W, uint64_t seed, double* u_mean,
+                              double* u_var, unsigned char* base) {
+    static_assert(sizeof(dwos::Counters) <= 192 && sizeof(dwos::Instance<T>) <= 512, "scratch header layout");
+    hipStream_t s = c->stream;
+    const NoAllocLayout L(P, W, sizeof(T));
+    // clear the header (queue, counters, instance slot) with a fill kernel
+    hipLaunchKernelGGL(dwos::fill_u64_kernel, dim3(blocks_for((int64_t)(L.head / 8), 64)), dim3(64), 0, s,
+                       reinterpret_cast<unsigned long long*>(base), (int64_t)(L.head / 8));
+    dwos::Instance<T> in{};
+    in.walk_begin = 0;
+    in.point_begin = 0;
+    in.p_counter = 0;
+    in.root = 0;
+    in.P = (int32_t)P;
+    in.kappa = T(std::sqrt(c->prob.sigma));
+    in.eps = T(c->prob.eps);
+    in.delta = T(c->prob.delta);
+    auto* inst = reinterpret_cast<dwos::Instance<T>*>(base + L.inst);
+    hipLaunchKernelGGL(set_instance_kernel<T>, dim3(1), dim3(64), 0, s, inst, in);
+    const dwos::Scene<T> scene = make_scene<T>(c);
+    auto* leaf = reinterpret_cast<int32_t*>(base + L.leaf);
+    auto* d2 = reinterpret_cast<T*>(base + L.d2);
+    hipLaunchKernelGGL((dwos::first_query_kernel<T, D>), dim3(blocks_for(P, 64)), dim3(64), 0, s, scene, inst, 1, X,
+                       (int64_t)0, P, leaf, d2);
+    dwos::WalkArgs<T> a = base_args<T>(c, X, W, seed);
+    a.inst = inst;
+    a.n_inst = 1;
+    a.total = P * (int64_t)W;
+    a.wid_offset = 0;
+    a.queue = reinterpret_cast<unsigned long long*>(base + L.queue);
+    a.cnt = reinterpret_cast<dwos::Counters*>(base + L.cnt);
+    a.rec_u = reinterpret_cast<T*>(base + L.rec);
+    a.rec_prim = nullptr;
+    a.rec_b = nullptr;
+    a.rec_uoff = nullptr;
+    a.rec_steps = nullptr;
+    a.first_leaf = leaf;
+    a.first_d2 = d2;
+    a.x_base = 0;
+    dwos_status rc = launch_walks<T, D, 0>(c, a, reinterpret_cast<dwos::Counters*>(base + L.tot), false);
+    if (rc) return rc;
+    hipLaunchKernelGGL(dwos::point_stats_kernel<T>, dim3(blocks_for(P, 4)), dim3(256), 0, s, a.rec_u, P, W, u_mean,
+                       u_var);
+    HIP_OK(hipGetLastError());
+    return DWOS_OK;
+}
+
 // Launch the persistent implicit-boundary walk kernel (2D).
 template <class T, int MODE>
 dwos_status launch_imp(dwos_ctx* c, dwos::WalkArgs<T>& a) {
@@ -1183,6 +1294,10 @@ dwos_status dwos_create(int32_t dim, int32_t precision, void* stream, dwos_ctx**
     int smem = 0;
     if (hipDeviceGetAttribute(&smem, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) smem = 65536;
     c->max_smem = (size_t)smem;
+    if (dwos_status rs = resolve_scratch(dev)) {
+        delete c;
+        return rs;
+    }
     *out = c;
     return DWOS_OK;
 }
@@ -1432,6 +1547,34 @@ dwos_status dwos_solve(dwos_ctx* c, const double* X, int64_t P, int32_t W, uint6
     OpArgs o{};
     o.X = X; o.P = P; o.W = W; o.seed = seed; o.u_mean = u_mean; o.u_var = u_var;
     return dispatch(c, Op::Solve, o, stats);
+}
+
+dwos_status dwos_solve_noalloc(dwos_ctx* c, const double* X, int64_t P, int32_t W, uint64_t seed, double* u_mean,
+                               double* u_var) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (!c->instances.empty()) return fail(DWOS_ESTATE, "solve_noalloc: batch context");
+    if (!c->has_boundary) return fail(DWOS_ESTATE, "solve_noalloc: no mesh boundary: call dwos_set_boundary first");
+    if (c->has_ref || c->has_imp)
+        return fail(DWOS_ESTATE, "solve_noalloc: reflecting or implicit boundaries are not supported");
+    if (!c->has_problem) return fail(DWOS_ESTATE, "solve_noalloc: no problem: call dwos_set_problem first");
+    if (P < 0 || W < 1) return fail(DWOS_EINVAL, "solve_noalloc: need P >= 0 and W >= 1");
+    if (P > 0 && (!X || !u_mean)) return fail(DWOS_EINVAL, "solve_noalloc: NULL points or output");
+    const size_t el = c->prec == DWOS_FP32 ? sizeof(float) : sizeof(double);
+    if (P > (int64_t(1) << 26) || (double)P * (double)W > (double)kScratchBytes)
+        return fail(DWOS_EINVAL, "solve_noalloc: P x W too large for the fixed workspace");
+    const NoAllocLayout L(P, W, el);
+    if (L.end > kScratchBytes)
+        return fail(DWOS_EINVAL, "solve_noalloc: P x W needs " + std::to_string(L.end) + " bytes of workspace, more than the " +
+                                     std::to_string(kScratchBytes) + " bytes of the fixed array");
+    HIP_OK(hipSetDevice(c->device));
+    auto* base = static_cast<unsigned char*>(scratch_ptr(c->device));
+    if (!base) return fail(DWOS_ESTATE, "solve_noalloc: workspace address not resolved for this device");
+    if (P == 0) return DWOS_OK;
+    if (c->prec == DWOS_FP32)
+        return c->D == 2 ? run_solve_noalloc<float, 2>(c, X, P, W, seed, u_mean, u_var, base)
+                         : run_solve_noalloc<float, 3>(c, X, P, W, seed, u_mean, u_var, base);
+    return c->D == 2 ? run_solve_noalloc<double, 2>(c, X, P, W, seed, u_mean, u_var, base)
+                     : run_solve_noalloc<double, 3>(c, X, P, W, seed, u_mean, u_var, base);
 }
 
 dwos_status dwos_grad(dwos_ctx* c, const double* X, int64_t P, const double* w, int32_t W, uint64_t seed,

@@ -222,6 +222,14 @@ class Solver:
                               C.byref(st) if st is not None else None))
         return (m, v, st.as_dict()) if stats else (m, v)
 
+    def solve_noalloc(self, X, W, seed, u_mean: torch.Tensor, u_var: Optional[torch.Tensor] = None):
+        """dwos_solve_noalloc into caller-provided outputs (no device
+        allocation inside the call)."""
+        X = self._X(X)
+        check(capi.dwos_solve_noalloc(self._ctx, _dev(X), X.shape[0], int(W), int(seed), _dev(u_mean),
+                                      _dev(u_var)))
+        return u_mean, u_var
+
     def grad(self, X, w, W, seed, u_mean=True, stats=False):
         X = self._X(X)
         P = X.shape[0]
