@@ -99,7 +99,7 @@ class OracleScene(C.Structure):
         ("n_nv", C.c_int32), ("NV", C.POINTER(C.c_double)), ("n_ns", C.c_int32),
         ("nsegs", C.POINTER(C.c_int32)), ("start_seg", C.POINTER(C.c_int32)),
         ("n_mono", C.c_int32), ("mono", C.POINTER(C.c_double)), ("mono_c", C.c_double),
-        ("dudn", C.c_int32),
+        ("dudn", C.c_int32), ("robin_mu", C.c_double), ("robin_quad", C.POINTER(C.c_double)),
     ]
 
 
@@ -180,6 +180,13 @@ class Oracle:
             s.mono = _ptr(self._mono, C.c_double)
             s.mono_c = float(scene.mono_c)
         s.dudn = int(getattr(scene, "dudn", 0))
+        s.robin_mu = float(getattr(scene, "robin_mu", 0.0))
+        rh = getattr(scene, "robin_h", None)
+        self._robin = None
+        if rh is not None:
+            self._robin = np.ascontiguousarray(np.concatenate([[rh["c"]], np.asarray(rh["b"], float).ravel(),
+                                                               np.asarray(rh["A"], float).ravel()]))
+            s.robin_quad = _ptr(self._robin, C.c_double)
         self._start = None
         self._s = s
 

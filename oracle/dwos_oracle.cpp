@@ -108,6 +108,13 @@ struct oracle_scene {
     // estimator of eq. (dudn_mc_estimate) (Laplace only: sigma = 0, no
     // source, no reflecting or implicit boundary).
     int32_t dudn;
+    // Robin condition on the reflecting boundary (eq. (mixed_bvp)):
+    // du/dn - robin_mu u = h with n the normal into the domain, robin_mu >= 0
+    // constant and the Robin data h the field c + b.x + x^T A x given by
+    // robin_quad (1 + dim + dim*dim values; NULL: h = 0).  robin_mu = 0 and
+    // no data: the zero-flux boundary.
+    double robin_mu;
+    const double* robin_quad;
 };
 
 // Learned control variate of the nested walks: network N(x) (frequencies B,
@@ -553,6 +560,72 @@ struct Scene {
         t_out = hit >= 0 ? best : tmax;
         return hit;
     }
+
+    // ----- Robin condition on the reflecting boundary -----------------------
+    bool has_robin() const { return s.robin_mu > 0 || s.robin_quad != nullptr; }
+
+    // the Robin data h at a boundary point
+    double robin_h(const double* z) const {
+        if (!s.robin_quad) return 0.0;
+        const double* q = s.robin_quad;
+        double v = q[0];
+        for (int i = 0; i < D; ++i) v += q[1 + i] * z[i];
+        for (int i = 0; i < D; ++i)
+            for (int j = 0; j < D; ++j) v += z[i] * q[1 + D + i * D + j] * z[j];
+        return v;
+    }
+
+    // Parameter interval [t0, t1] of the part of reflecting segment i inside
+    // the disk |z - x| < R (t along the segment from its first vertex);
+    // returns its length (0: the segment misses the disk).
+    double clip(int i, const double* x, double R, double& t0, double& t1) const {
+        const double* a = nvert(nsv(i, 0));
+        const double* b = nvert(nsv(i, 1));
+        const double ex = b[0] - a[0], ey = b[1] - a[1];
+        const double ax = a[0] - x[0], ay = a[1] - x[1];
+        const double ee = ex * ex + ey * ey, ea = ex * ax + ey * ay;
+        const double disc = ea * ea - ee * (ax * ax + ay * ay - R * R);
+        if (!(disc > 0)) return 0.0;
+        const double sq = std::sqrt(disc);
+        t0 = std::max(0.0, (-ea - sq) / ee);
+        t1 = std::min(1.0, (-ea + sq) / ee);
+        if (!(t1 > t0)) return 0.0;
+        return std::sqrt(ee) * (t1 - t0);
+    }
+
+    // A point z uniform by length on the reflecting boundary inside the disk
+    // B(x, R), and that length L (seg = -1, L = 0 when the disk holds none).
+    // The segment is chosen with probability proportional to its clipped
+    // length by an exponential race -- segment i draws E_i = -ln(U_i) / l_i
+    // and the smallest E_i wins -- with U_i from its own Philox counter
+    // (k, m, p, tag | 8 | i << 16), so the choice does not depend on the
+    // order in which segments are visited; the position along the winner's
+    // clipped part is word 1 of the same draw.
+    int boundary_sample(const double* x, double R, const Stream& st, uint32_t k, uint32_t extra,
+                        double& L, double z[2]) const {
+        L = 0.0;
+        int win = -1;
+        double best = INFINITY, wt0 = 0, wt1 = 0;
+        uint32_t wpos = 0;
+        for (int i = 0; i < s.n_ns; ++i) {
+            double t0 = 0, t1 = 0;
+            const double l = clip(i, x, R, t0, t1);
+            if (!(l > 0)) continue;
+            L += l;
+            uint32_t w[4];
+            st.draw(k, extra | 8u | ((uint32_t)i << 16), w);
+            const double e = -std::log(u24pos(w[0])) / l;
+            if (e < best) { best = e; win = i; wt0 = t0; wt1 = t1; wpos = w[1]; }
+        }
+        if (win >= 0) {
+            const double* a = nvert(nsv(win, 0));
+            const double* b = nvert(nsv(win, 1));
+            const double t = wt0 + u24(wpos) * (wt1 - wt0);
+            z[0] = a[0] + t * (b[0] - a[0]);
+            z[1] = a[1] + t * (b[1] - a[1]);
+        }
+        return win;
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -954,26 +1027,49 @@ double walk_on_spheres(const Scene& sc, const double* x0, const Stream& st, uint
 }
 
 // ---------------------------------------------------------------------------
-// Walk on stars for the mixed problem of Sec. 3.4 (eq. (mixed_bvp)) with a
-// zero-flux reflecting boundary (Robin coefficient 0, Robin data 0), the
-// case of the paper's thermal design example.  The paper defers the
-// estimator to the walk-on-stars papers (Sawhney et al. 2023; Miller et al.
-// 2024); one step, restated:
+// Walk on stars for the mixed problem of Sec. 3.4 (eq. (mixed_bvp)): the
+// Dirichlet boundary and a fixed reflecting boundary with the Robin condition
+// du/dn - mu u = h (n into the domain; mu = 0, h = 0: zero flux, the case of
+// the paper's thermal design example).  The paper defers the estimator to
+// the walk-on-stars papers (Sawhney et al. 2023; Miller et al. 2024); it is
+// restated here from Green's second identity on the star-shaped region
+// St = B(x, R) ∩ Omega with the ball's Green's function G (zero on the
+// sphere): for x inside,
+//   u(x) = int_St G f + int_{sphere part} P u
+//          + int_{reflecting part in B} [P_z u - G (mu u + h)] dz,
+// P = -dG/dn_out the ball's Poisson kernel (at a reflecting point z, taken
+// with the domain's outward normal there).  At a point on a wall the left
+// side is u(x)/2.  One step:
 //   * d = distance to the Dirichlet boundary; in its eps-shell the walk
 //     stops with g as in Algorithm 1.
 //   * star radius R = min(d, distance to the closest silhouette point of the
-//     reflecting boundary): the part of the ball visible from x is then a
-//     star-shaped region bounded by the sphere and the reflecting boundary.
+//     reflecting boundary[, 1/mu]): the part of the ball visible from x is
+//     then a star-shaped region bounded by the sphere and the reflecting
+//     boundary, all of whose reflecting points in the ball x sees.  (1/mu
+//     bounds the Robin term's mass per step, a variance choice.)
 //   * direction v uniform on the circle (at a reflecting boundary point: on
-//     the half that enters the domain, by reflecting the other half).
+//     the half that enters the domain, by reflecting the other half, which
+//     doubles the density and pays the factor 2 of the wall's left side).
 //   * march along v: the first reflecting boundary point at distance t < R
-//     becomes the next point with weight neumann_weight(t, R), else x + R v
-//     with weight alpha(R) as in Algorithm 1; Russian roulette on the weight.
+//     is the direction-sampled point, weight neumann_weight(t, R), else
+//     x + R v with weight alpha(R) as in Algorithm 1.
 //   * source: one point y = x + rho v of the ball along the same direction,
 //     rho = R U^(1/D), contributing |B_R| G(rho; R) f(y) if it lies in the
 //     star-shaped region (rho < t).
-// One random draw per step: w0 (and w1 in 3D) the direction, w2 the
-// roulette, w3 the source radius.
+//   * Robin terms (mu > 0 or h != 0): z uniform by length on the reflecting
+//     boundary inside the ball (length L, boundary_sample); the data term
+//     adds -c L G(|z - x|; R) h(z), c = 2 on a wall (the left side's 1/2)
+//     and 1 inside.  The mu term needs u(z): with probability
+//     q = min(1/2, c mu L G) the walk continues at z with weight
+//     -c mu L G / q, else at the direction-sampled point with its weight
+//     divided by 1 - q (either choice is unbiased for any q in (0, 1)).
+//   * Russian roulette keeps the walk with probability s = min(1, |w|) and
+//     multiplies its throughput tau by w / s, so tau stays 1 unless the
+//     Robin term flips its sign or a weight exceeds 1; every term the walk
+//     adds and its terminal value are multiplied by tau.
+// Random numbers: one draw per step, w0 (and w1 in 3D) the direction, w1
+// (2D) the Robin branch, w2 the roulette, w3 the source radius; and the
+// boundary sample's own draws (boundary_sample).
 // ---------------------------------------------------------------------------
 struct StarStep {
     bool stop = false;     // stopped by roulette
@@ -981,9 +1077,11 @@ struct StarStep {
 };
 
 StarStep star_step(const Scene& sc, double* x, int on, double* nin, double d2, uint32_t k,
-                   const Stream& st, uint32_t extra, double& acc) {
+                   const Stream& st, uint32_t extra, double& acc, double& tau) {
     const int D = sc.D;
-    const double R = std::sqrt(sc.silhouette_d2(x, on, nin, d2));
+    const double mu = sc.s.robin_mu;
+    double R = std::sqrt(sc.silhouette_d2(x, on, nin, d2));
+    if (mu > 0) R = std::min(R, 1.0 / mu);
     uint32_t w[4];
     st.draw(k, extra, w);
     double v[3];
@@ -999,12 +1097,44 @@ StarStep star_step(const Scene& sc, double* x, int on, double* nin, double d2, u
         if (seg < 0 || rho < t) {
             double y[3] = {0, 0, 0};
             for (int i = 0; i < D; ++i) y[i] = x[i] + rho * v[i];
-            acc += green(D, sc.s.sigma, rho, R) * ball_volume(D, R) * sc.f(y);
+            acc += tau * green(D, sc.s.sigma, rho, R) * ball_volume(D, R) * sc.f(y);
         }
     }
-    const double wgt = seg >= 0 ? neumann_weight(D, sc.s.sigma, t, R) : poisson_scale(D, sc.s.sigma, R);
+    // Robin terms over the reflecting boundary inside the ball
+    const double cx = on >= 0 ? 2.0 : 1.0;
+    double z[2] = {0, 0}, L = 0, Gz = 0;
+    int zseg = -1;
+    if (sc.has_robin()) {
+        zseg = sc.boundary_sample(x, R, st, k, extra, L, z);
+        if (zseg >= 0) {
+            Gz = green(D, sc.s.sigma, std::hypot(z[0] - x[0], z[1] - x[1]), R);
+            acc -= tau * cx * L * Gz * sc.robin_h(z);
+        }
+    }
+    const double q = (mu > 0 && zseg >= 0) ? std::min(0.5, cx * mu * L * Gz) : 0.0;
+    const bool to_z = q > 0 && u24(w[1]) < q;
+    const double wgt = to_z ? -cx * mu * L * Gz / q
+                            : (seg >= 0 ? neumann_weight(D, sc.s.sigma, t, R) : poisson_scale(D, sc.s.sigma, R)) /
+                                  (1 - q);
     StarStep out;
-    if (sc.s.rr && wgt < u24(w[2])) { out.stop = true; return out; }
+    if (sc.s.rr) {
+        const double keep = std::min(1.0, std::fabs(wgt));
+        if (!(keep > 0) || keep < u24(w[2])) { out.stop = true; return out; }
+        tau *= wgt / keep;
+    } else {
+        tau *= wgt;
+    }
+    if (to_z) {   // continue on the wall at z; domain side: towards x
+        if (zseg != on) {
+            sc.nleft(zseg, nin);
+            const double dx[2] = {x[0] - z[0], x[1] - z[1]};
+            if (dot(nin, dx, 2) < 0) for (int i = 0; i < 2; ++i) nin[i] = -nin[i];
+        }
+        x[0] = z[0];
+        x[1] = z[1];
+        out.on = zseg;
+        return out;
+    }
     for (int i = 0; i < D; ++i) x[i] += t * v[i];
     out.on = seg;
     if (seg >= 0) {   // domain side of the segment: the side the walk came from
@@ -1020,7 +1150,7 @@ double walk_on_stars(const Scene& sc, const double* x0, int on0, const double* n
     double x[3] = {0, 0, 0}, nin[3] = {0, 0, 0};
     for (int i = 0; i < D; ++i) { x[i] = x0[i]; if (on0 >= 0) nin[i] = nin0[i]; }
     int on = on0;
-    double acc = 0.0;
+    double acc = 0.0, tau = 1.0;
     for (uint32_t k = 0;; ++k) {
         Hit h = sc.closest(x);                          // Dirichlet boundary only
         cnt.steps++;
@@ -1028,9 +1158,9 @@ double walk_on_stars(const Scene& sc, const double* x0, int on0, const double* n
         const bool cap = (int64_t)k + 1 >= sc.s.kmax;
         if (d < sc.s.eps || cap) {
             if (cap && !(d < sc.s.eps)) cnt.truncated++;
-            return acc + sc.g(h);
+            return acc + tau * sc.g(h);
         }
-        StarStep r = star_step(sc, x, on, nin, h.d2, k, st, extra, acc);
+        StarStep r = star_step(sc, x, on, nin, h.d2, k, st, extra, acc, tau);
         if (r.stop) return acc;
         on = r.on;
     }
@@ -1090,6 +1220,7 @@ struct DiffOut {
     int prim = -1;
     double xbar[3] = {0, 0, 0};   // terminal closest point
     double uoff = 0;       // mean of the K nested walks at the offset point
+    double tau = 1;        // walk-on-stars throughput at the terminal (udot carries it)
     int64_t nested_steps = 0;
     std::vector<double> udot;  // dense N-vector
     // with the control variate:
@@ -1190,7 +1321,7 @@ DiffOut diff_walk_on_spheres(const Scene& sc, const double* x0, const Stream& st
     double x[3] = {0, 0, 0}, nin[3] = {0, 0, 0}, xprev[3] = {0, 0, 0};
     for (int i = 0; i < D; ++i) { x[i] = x0[i]; if (on0 >= 0) nin[i] = nin0[i]; }
     int on = on0;
-    double acc = 0.0;
+    double acc = 0.0, tau = 1.0;   // tau: walk-on-stars throughput (1 otherwise)
     for (uint32_t k = 0;; ++k) {
         Hit h = sc.closest(x);
         cnt.steps++;
@@ -1256,16 +1387,20 @@ DiffOut diff_walk_on_spheres(const Scene& sc, const double* x0, const Stream& st
                 uhat = out.uoff_cv;
             }
             double dudn = (gx - uhat) / sc.s.delta;            // eq. (dudn_fd_estimate)
-            out.u = acc + gx;
+            out.u = acc + tau * gx;
+            out.tau = tau;
             out.terminal = true;
             out.prim = h.prim;
             for (int i = 0; i < 3; ++i) out.xbar[i] = h.xbar[i];
-            if (want_udot) boundary_udot(sc, h, n, dudn, out.udot, nullptr);
+            if (want_udot) {
+                boundary_udot(sc, h, n, dudn, out.udot, nullptr);
+                if (tau != 1.0) for (double& e : out.udot) e *= tau;
+            }
             return out;
         }
         if (sc.has_neumann()) {
             for (int i = 0; i < D; ++i) xprev[i] = x[i];
-            StarStep r = star_step(sc, x, on, nin, h.d2, k, st, 0u, acc);
+            StarStep r = star_step(sc, x, on, nin, h.d2, k, st, 0u, acc, tau);
             if (r.stop) { out.u = acc; return out; }   // roulette: udot = 0, u = sources
             on = r.on;
             continue;
@@ -1398,6 +1533,10 @@ int check_scene(const oracle_scene* s) {
         for (int64_t i = 0; i < 2 * (int64_t)s->n_ns; ++i)
             if (s->nsegs[i] < 0 || s->nsegs[i] >= s->n_nv) return 1;
     }
+    // the Robin condition lives on the reflecting boundary; the boundary
+    // sample's counter holds a segment index in 16 bits
+    if (!(s->robin_mu >= 0) || !std::isfinite(s->robin_mu)) return 1;
+    if ((s->robin_mu > 0 || s->robin_quad) && (s->n_ns <= 0 || s->n_ns > 65536)) return 1;
     return 0;
 }
 

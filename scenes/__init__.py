@@ -86,6 +86,11 @@ class Scene:
     # normal-derivative estimator of the differential walks: 0 backward
     # difference, 1 offset-point gradient estimator (Laplace only)
     dudn: int = 0
+    # Robin condition du/dn - robin_mu u = h on the reflecting part (n into
+    # the domain): robin_mu >= 0 and h a restricted field dict(c=, b=, A=)
+    # (None: h = 0)
+    robin_mu: float = 0.0
+    robin_h: Optional[dict] = None
 
     @property
     def nv(self) -> int:
@@ -311,12 +316,15 @@ def half_disk_scene(n_arc: int = 256, n_diam: int = 64, R: float = 1.0, sigma: f
     """Upper half of the disk of radius R: Dirichlet arc (n_arc segments,
     vertices on the circle), reflecting diameter (n_diam segments).  Data
     restricted x^2 - y^2 (``g='x2-y2'``) or 1 (``g='one'``), both even in y,
-    so the solution is the full disk's (``g='zero'`` for source tests).  One
+    so the solution is the full disk's (``g='zero'`` for source tests;
+    ``g='x2-y2+y'``, harmonic with du/dy = 1 on the diameter, for Neumann and
+    Robin data there).  One
     parameter pi = R with
     dv/dR = v/R on the arc (the diameter has no normal motion)."""
     th = np.pi * np.arange(n_arc + 1) / n_arc
     U = np.stack([np.cos(th), np.sin(th)], axis=1)
     fld = {"x2-y2": _restricted(0.0, None, [[1.0, 0.0], [0.0, -1.0]], 2),
+           "x2-y2+y": _restricted(0.0, [0.0, 1.0], [[1.0, 0.0], [0.0, -1.0]], 2),
            "one": _restricted(1.0, None, None, 2), "zero": _restricted(0.0, None, None, 2)}[g]
     NV = _subdivide([[-R, 0.0], [R, 0.0]], 2 * R / n_diam)
     return Scene(dim=2, V=R * U, prims=_chain(n_arc + 1), label=np.zeros(n_arc, np.int32),
