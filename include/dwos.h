@@ -542,6 +542,27 @@ dwos_status dwos_cv_walk_records(dwos_ctx* ctx, const double* X, int64_t P, int3
  * coordinate), ESTATE (batch context), ENOMEM. */
 dwos_status dwos_set_reflecting(dwos_ctx* ctx, const double* V, int64_t nv, const int32_t* segs, int64_t ns);
 
+/* Robin condition on the reflecting boundary (Sec. 3.4, eq. (mixed_bvp)):
+ *   du/dn - mu u = h    with n the unit normal pointing into the domain,
+ * mu >= 0 a constant and h (host struct, NULL: h = 0) a restricted field
+ * h(x) = c + b.x + x^T A x (kind 0; A row-major 3 x 3, the top-left 2 x 2
+ * used).  mu = 0 and h = NULL restore the zero-flux boundary.  Neither may
+ * depend on the parameters.  The differential walks (Sec. 4.4,
+ * eq. (mixed_bvp_deriv)) keep mu with zero data and nest through the
+ * Dirichlet boundary only.  Each walk-on-stars step then also estimates the
+ * boundary terms -int G (mu u + h) of the star-shaped region's integral
+ * equation over the reflecting boundary inside its ball: a point z uniform
+ * by length there (the segment chosen by an exponential race in which
+ * reflecting segment o draws Philox counter (k, m, p, tag | 8 | o << 16)),
+ * the data term added directly and the mu term by continuing the walk at z
+ * with probability q = min(1/2, c mu L G) (c = 2 on a wall, 1 inside; L the
+ * reflecting length in the ball; word 1 of the step's draw decides), with
+ * the walk's throughput carrying the weights' signs and sizes; with mu > 0
+ * the star radius is also capped at 1/mu.  Errors: EINVAL (mu < 0 or not
+ * finite, h not kind 0 or not finite, more than 65536 reflecting segments),
+ * ESTATE (no reflecting boundary when mu > 0 or h != NULL). */
+dwos_status dwos_set_robin(dwos_ctx* ctx, double mu, const dwos_bc* h);
+
 /* Query points that lie on the reflecting boundary (host, P entries: the
  * segment index a point lies on, with the domain to the left of the segment
  * from its first to its second vertex, or -1 for a point inside).  Applies

@@ -118,6 +118,7 @@ def lib():
             "dwos_probe_bandwidth": [C.c_int64, C.c_int32, C.c_int32, dp, dp],
             "dwos_scene_info": [vp, i64p],
             "dwos_solve_noalloc": [vp, vp, C.c_int64, C.c_int32, C.c_uint64, vp, vp],
+            "dwos_set_robin": [vp, C.c_double, C.POINTER(dwos_bc)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -150,7 +151,7 @@ EXPORTED = [
     "dwos_set_implicit", "dwos_implicit_band_grad", "dwos_adjoint_grad",
     "dwos_remesh", "dwos_mesh_size", "dwos_mesh_get", "dwos_mesh_destroy",
     "dwos_opt_create", "dwos_opt_destroy", "dwos_opt_reset", "dwos_opt_step", "dwos_opt_solve",
-    "dwos_probe_bandwidth", "dwos_scene_info", "dwos_solve_noalloc",
+    "dwos_probe_bandwidth", "dwos_scene_info", "dwos_solve_noalloc", "dwos_set_robin",
 ]
 
 

@@ -203,6 +203,7 @@ struct AccArgs {
     const int32_t* rec_prim;
     const T* rec_b;
     const T* rec_uoff;
+    const T* rec_w;          // per-walk throughput multiplying udot (null: 1)
     int64_t nwalks;          // records in this chunk
     int64_t p_offset;        // first point of this chunk
     int32_t W, B, mode;
@@ -243,6 +244,7 @@ __global__ void __launch_bounds__(256) accumulate_kernel(AccArgs<T> a) {
         const double nb = double(a.W / a.B);
         omega = ((S - double(a.rec_u[i])) / (double(a.B) * (a.B - 1)) - a.uref[p] / a.B) / nb;
     }
+    if (a.rec_w) omega *= double(a.rec_w[i]);
     Terminal<T, D> t;
     terminal_term<T, D>(a.s, a.prm, a.delta, code, a.rec_b + i * (D - 1), a.rec_uoff[i], t);
 #pragma unroll
@@ -289,6 +291,7 @@ struct JvpArgs {
     const int32_t* rec_prim;
     const T* rec_b;
     const T* rec_uoff;
+    const T* rec_w;          // per-walk throughput multiplying udot (null: 1)
     int64_t P;
     int64_t p_offset;
     int32_t W;
@@ -311,6 +314,7 @@ __global__ void __launch_bounds__(64) jvp_kernel(JvpArgs<T> a) {
             Terminal<T, D> t;
             terminal_term<T, D>(a.s, a.prm, a.delta, code, a.rec_b + i * (D - 1), a.rec_uoff[i], t);
             v = udot_component<T, D>(a.J, t, (int32_t)j);
+            if (a.rec_w) v *= double(a.rec_w[i]);
         }
         if (a.walk_udot) a.walk_udot[i * a.J.N + j] = v;
         s1 += v;
@@ -364,6 +368,74 @@ __global__ void closest_kernel(Scene<T> s, int32_t root, const double* X, int64_
 }
 
 // closest primitive of each start point (shared first query of its walks);
+// ---------------------------------------------------------------------------
+// Spatial scheduling order of a chunk's points: the walk kernel hands out
+// walks point by point in this order, so the walks in flight at any time
+// start close together and gather from the same part of the BVH (the L2 of
+// each XCD then holds that part).  A counting sort by cell of a 16^3 (3D) or
+// 64^2 (2D) grid over the boundary's bounding box, cells in Morton order;
+// the order within a cell is whatever the atomics give -- walks and their
+// records are indexed by point, so no result depends on it.
+// ---------------------------------------------------------------------------
+constexpr int kOrderCells = 4096;
+
+__device__ __forceinline__ uint32_t spread_bits(uint32_t v, int D) {
+    uint32_t out = 0;
+    const int nb = D == 3 ? 4 : 6;
+    for (int b = 0; b < nb; ++b) out |= ((v >> b) & 1u) << (b * D);
+    return out;
+}
+
+template <class T, int D>
+__global__ void order_cell_kernel(const T* nodes, const double* X, int64_t P, int32_t* cell, uint32_t* hist) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    NodeData<T, D> nd;
+    load_node<T, D>(nodes, 0, nd);
+    const int side = D == 3 ? 16 : 64;
+    uint32_t code = 0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        T lo = T(INFINITY), hi = T(-INFINITY);
+        if (!(nd.t0 < T(0))) { lo = fmin(lo, nd.lo0[c]); hi = fmax(hi, nd.hi0[c]); }
+        if (!(nd.t1 < T(0))) { lo = fmin(lo, nd.lo1[c]); hi = fmax(hi, nd.hi1[c]); }
+        const double ext = double(hi) - double(lo);
+        double f = ext > 0.0 ? (X[i * D + c] - double(lo)) / ext : 0.0;
+        f = f == f ? fmin(fmax(f, 0.0), 1.0) : 0.0;          // NaN -> cell 0
+        const uint32_t q = (uint32_t)fmin(f * side, double(side - 1));
+        code |= spread_bits(q, D) << c;
+    }
+    cell[i] = (int32_t)code;
+    atomicAdd(&hist[code], 1u);
+}
+
+// exclusive scan of the kOrderCells counts, in place, by one 1024-thread block
+__global__ void __launch_bounds__(1024) order_scan_kernel(uint32_t* hist) {
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    uint32_t v[4], s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { v[k] = hist[t * 4 + k]; s += v[k]; }
+    part[t] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const uint32_t add = t >= o ? part[t - o] : 0u;
+        __syncthreads();
+        part[t] += add;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - s;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { hist[t * 4 + k] = run; run += v[k]; }
+}
+
+__global__ void order_scatter_kernel(const int32_t* cell, int64_t P, uint32_t* cursor, int32_t* perm) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const uint32_t slot = atomicAdd(&cursor[cell[i]], 1u);
+    perm[slot] = (int32_t)i;
+}
+
 // row r of X is global point x_base + r, which lies in the instance whose
 // point range contains it
 template <class T, int D>

@@ -116,6 +116,7 @@ struct dwos_ctx {
     DevBuf rec_u, rec_prim, rec_b, rec_uoff, rec_steps, accA, accB, queue, counters, instbuf, export_u;
     DevBuf vtmp;   // V(pi) for dwos_apply_parameters
     DevBuf first_leaf, first_d2;   // shared first query of each start point
+    DevBuf order_cell, order_perm, order_hist;   // spatial scheduling order of a chunk's points
     const uint64_t* seed_dev = nullptr;   // optional device seed offset
     int variant = 0;                      // walk-kernel launch shape (FP32)
     // timing and cumulative counters per walk kind (0 forward, 1 differential)
@@ -141,6 +142,11 @@ struct dwos_ctx {
     DevBuf ref_nodes, ref_geo, ref_info, ref_leaf_of, ref_cones;
     DevBuf start_seg;             // per query point: reflecting segment or -1
     int64_t start_n = 0;          // points covered by start_seg (0: none)
+    // Robin condition on the reflecting boundary (mu, data h as c, b, A)
+    bool robin = false;
+    double robin_mu = 0.0;
+    double robin_hq[7] = {0, 0, 0, 0, 0, 0, 0};
+    DevBuf rec_w;                 // per differential walk: throughput at the terminal
     // implicit boundary (2D): zero set of c + sum_n a_n / |x - p_n|
     bool has_imp = false;
     int64_t imp_n = 0;
@@ -347,6 +353,9 @@ dwos::RefScene<T> make_ref(dwos_ctx* c) {
     r.leaf_of = c->ref_leaf_of.as<int32_t>();
     r.cones = c->ref_cones.as<T>();
     r.n = c->ref_n;
+    r.robin = c->robin ? 1 : 0;
+    r.mu = T(c->robin_mu);
+    for (int i = 0; i < 7; ++i) r.hq[i] = T(c->robin_hq[i]);
     return r;
 }
 
@@ -882,8 +891,32 @@ dwos_status run_op(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
         a.first_d2 = c->first_d2.as<T>();
         a.x_base = p0;
         a.rec_steps = op == Op::Records ? c->rec_steps.as<int64_t>() : nullptr;
+        // 3D meshes: hand the points out in a spatially coherent order (the
+        // walks in flight then share the BVH's cache lines); only scheduling
+        // changes, every walk and record is the same
+        a.perm = nullptr;
+        if (D == 3 && Pc >= 1024) {
+            HIP_OK(c->order_cell.reserve(Pc * sizeof(int32_t)));
+            HIP_OK(c->order_perm.reserve(Pc * sizeof(int32_t)));
+            HIP_OK(c->order_hist.reserve(dwos::kOrderCells * sizeof(uint32_t)));
+            hipLaunchKernelGGL(dwos::fill_u64_kernel, dim3(blocks_for(dwos::kOrderCells / 2, 64)), dim3(64), 0, s,
+                               c->order_hist.as<unsigned long long>(), (int64_t)(dwos::kOrderCells / 2));
+            hipLaunchKernelGGL((dwos::order_cell_kernel<T, D>), dim3(blocks_for(Pc, 256)), dim3(256), 0, s,
+                               c->nodes.as<T>(), o.X + p0 * D, Pc, c->order_cell.as<int32_t>(),
+                               c->order_hist.as<uint32_t>());
+            hipLaunchKernelGGL(dwos::order_scan_kernel, dim3(1), dim3(1024), 0, s, c->order_hist.as<uint32_t>());
+            hipLaunchKernelGGL(dwos::order_scatter_kernel, dim3(blocks_for(Pc, 256)), dim3(256), 0, s,
+                               c->order_cell.as<int32_t>(), Pc, c->order_hist.as<uint32_t>(),
+                               c->order_perm.as<int32_t>());
+            a.perm = c->order_perm.as<int32_t>();
+        }
         const bool use_cv = diff && c->cv != nullptr;
         if (use_cv) cv_args<T>(c, a);
+        const bool robin_w = diff && c->has_ref && c->robin;
+        if (robin_w) {
+            HIP_OK(c->rec_w.reserve(std::max<int64_t>(1, max_walks) * sizeof(T)));
+            a.rec_w = c->rec_w.as<T>();
+        }
         // walk ids within a chunk restart at 0; the instance's p_counter = p0
         // keeps the Philox point word absolute
         if constexpr (D == 2) {
@@ -921,6 +954,7 @@ dwos_status run_op(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
             aa.rec_prim = c->rec_prim.as<int32_t>();
             aa.rec_b = c->rec_b.as<T>();
             aa.rec_uoff = c->rec_uoff.as<T>();
+            aa.rec_w = robin_w ? c->rec_w.as<T>() : nullptr;
             aa.nwalks = walks;
             aa.p_offset = p0;
             aa.W = W;
@@ -944,6 +978,7 @@ dwos_status run_op(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
             ja.rec_prim = c->rec_prim.as<int32_t>();
             ja.rec_b = c->rec_b.as<T>();
             ja.rec_uoff = c->rec_uoff.as<T>();
+            ja.rec_w = robin_w ? c->rec_w.as<T>() : nullptr;
             ja.P = Pc;
             ja.p_offset = p0;
             ja.W = W;
@@ -1778,6 +1813,8 @@ dwos_status dwos_set_reflecting(dwos_ctx* c, const double* V, int64_t nv, const 
         return DWOS_OK;
     }
     if (c->D != 2) return fail(DWOS_EINVAL, "set_reflecting: reflecting boundaries are supported in 2D only");
+    if (c->robin && ns > 65536)
+        return fail(DWOS_EINVAL, "set_reflecting: a Robin condition allows at most 65536 reflecting segments");
     if (!c->instances.empty()) return fail(DWOS_ESTATE, "set_reflecting: context is a batch context");
     if (c->has_imp) return fail(DWOS_ESTATE, "set_reflecting: context has an implicit boundary");
     dwos_status rc = check_geometry(2, V, nv, segs, ns, nullptr, 1);
@@ -1793,6 +1830,32 @@ dwos_status dwos_set_reflecting(dwos_ctx* c, const double* V, int64_t nv, const 
                               : upload_reflecting<double>(c, V, segs, ns, inc, bvh);
     if (rc) return rc;
     c->has_ref = true;
+    return DWOS_OK;
+}
+
+dwos_status dwos_set_robin(dwos_ctx* c, double mu, const dwos_bc* h) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (!(mu >= 0) || !std::isfinite(mu)) return fail(DWOS_EINVAL, "set_robin: mu must be finite and >= 0");
+    double hq[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (h) {
+        if (h->kind != 0) return fail(DWOS_EINVAL, "set_robin: the Robin data must be a restricted field (kind 0)");
+        hq[0] = h->c;
+        hq[1] = h->b[0];
+        hq[2] = h->b[1];
+        hq[3] = h->A[0];
+        hq[4] = h->A[1];
+        hq[5] = h->A[3];
+        hq[6] = h->A[4];
+        for (double v : hq)
+            if (!std::isfinite(v)) return fail(DWOS_EINVAL, "set_robin: non-finite Robin data");
+    }
+    const bool on = mu > 0 || h != nullptr;
+    if (on && !c->has_ref) return fail(DWOS_ESTATE, "set_robin: no reflecting boundary");
+    if (on && c->ref_n > 65536)
+        return fail(DWOS_EINVAL, "set_robin: a Robin condition allows at most 65536 reflecting segments");
+    c->robin = on;
+    c->robin_mu = mu;
+    for (int i = 0; i < 7; ++i) c->robin_hq[i] = hq[i];
     return DWOS_OK;
 }
 

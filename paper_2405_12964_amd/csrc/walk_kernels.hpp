@@ -106,11 +106,16 @@ struct WalkArgs {
     T* rec_b;                // barycentrics b1 (2D) or b1,b2 (3D)
     T* rec_uoff;             // mean of the nested walks
     int64_t* rec_steps;      // optional per-walk query count
+    T* rec_w;                // walk-on-stars differential walks with a Robin
+                             // condition: the throughput at the terminal (null: 1)
     // closest primitive of every start point (all walks of a point share
     // their first query), indexed by X row - x_base; null: query per walk
     const int32_t* first_leaf;
     const T* first_d2;
     int64_t x_base;
+    // scheduling order of the points (slot -> point of the chunk), or null
+    // for the identity; only for a single instance with wid_offset 0
+    const int32_t* perm;
     // control variate of the nested walks (MODE 1; cv_run == nullptr: off).
     // Per walk: cv_run (-1 no terminal, 0 nested walks skipped, 1 run),
     // the offset point, the terminal point and g there.  Per nested walk
@@ -713,8 +718,12 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
                     }
                     const Instance<T> in = a.inst[ii];
                     const int64_t local = gid - in.walk_begin;
-                    const int64_t pin = local / a.W;
+                    int64_t pin = local / a.W;
                     m = (uint32_t)(local - pin * a.W);
+                    if (a.perm) {   // the slot's point; records stay indexed by point
+                        pin = a.perm[pin];
+                        wid = pin * a.W + m;
+                    }
                     p = (uint32_t)(pin + in.p_counter);
                     root = in.root;
                     kappa = in.kappa; eps = in.eps; delta = in.delta;

@@ -64,7 +64,121 @@ struct RefScene {
     // g_stage + stage_off4 (16-byte words: nodes, then cones); 0: none
     int32_t n_stage;
     int64_t stage_off4;
+    // Robin condition du/dn - mu u = h on the reflecting boundary (n into
+    // the domain) with h = hq[0] + hq[1] x + hq[2] y + [x y] [hq[3] hq[4];
+    // hq[5] hq[6]] [x y]^T; robin = 0: zero flux (mu = 0, h = 0)
+    int32_t robin;
+    T mu;
+    T hq[7];
 };
+
+// Robin data h at a reflecting boundary point z
+template <class T>
+__device__ __forceinline__ T robin_data(const RefScene<T>& r, const T* z) {
+    T v = r.hq[0] + r.hq[1] * z[0] + r.hq[2] * z[1];
+    v += z[0] * r.hq[3] * z[0] + z[0] * r.hq[4] * z[1];
+    v += z[1] * r.hq[5] * z[0] + z[1] * r.hq[6] * z[1];
+    return v;
+}
+
+// Length of the part of leaf segment i inside the disk |z - x| < R, and its
+// parameter interval [t0, t1] along the segment from its first vertex.
+template <class T>
+__device__ __forceinline__ T ref_clip(const RefScene<T>& r, int32_t i, const T* x, T R, T& t0, T& t1) {
+    const T* g = r.geo + (size_t)i * kRefGeo;
+    const T ex = g[2] - g[0], ey = g[3] - g[1];
+    const T ax = g[0] - x[0], ay = g[1] - x[1];
+    const T ee = ex * ex + ey * ey, ea = ex * ax + ey * ay;
+    const T disc = ea * ea - ee * (ax * ax + ay * ay - R * R);
+    if (!(disc > T(0))) return T(0);
+    const T sq = sqrt(disc);
+    t0 = fmax(T(0), (-ea - sq) / ee);
+    t1 = fmin(T(1), (-ea + sq) / ee);
+    if (!(t1 > t0)) return T(0);
+    return sqrt(ee) * (t1 - t0);
+}
+
+// A point z uniform by length on the reflecting boundary inside the disk
+// B(x, R) and that length L; returns the leaf of z's segment, or -1 (L = 0)
+// when the disk holds no reflecting point.  The segment is chosen with
+// probability proportional to its clipped length by an exponential race:
+// every segment o in the disk draws E_o = -ln(U_o) / l_o from its own
+// Philox counter (k, m, p, tag | 8 | o << 16) -- `ctr` holds the step's
+// (k, m, p, tag) -- and the smallest E_o wins, so the choice does not
+// depend on the order of the traversal; the position along the winner's
+// clipped part is word 1 of the same draw.
+template <class T, class Stack>
+__device__ int32_t ref_boundary_sample(const RefScene<T>& r, const T* x, T R, u4 ctr, uint32_t key0,
+                                       uint32_t key1, T& L, T* z, QueryCount& qc, Stack& st) {
+    const T R2 = R * R;
+    L = T(0);
+    int32_t win = -1;
+    T best = T(INFINITY), wt0 = T(0), wt1 = T(0);
+    uint32_t wpos = 0;
+    int sp = 0;
+    int32_t cur = 0;
+    bool have = true;
+#pragma unroll 1
+    while (have) {
+        if (cur >= 0) {
+            NodeData<T, 2> nd;
+            ref_node<T>(r, cur, nd);
+            qc.nodes++;
+            const bool h0 = !(nd.t0 < T(0)) &&
+                            fmax(box_d2<T, 2>(nd.lo0, nd.hi0, x), slab_d2<T, 2>(nd.n0, nd.o0, nd.t0, x)) < R2;
+            const bool h1 = !(nd.t1 < T(0)) &&
+                            fmax(box_d2<T, 2>(nd.lo1, nd.hi1, x), slab_d2<T, 2>(nd.n1, nd.o1, nd.t1, x)) < R2;
+            if (h0 && h1) {
+                if (sp < kStackSize) {
+                    st.put(sp, nd.c1, T(0));
+                    ++sp;
+                } else {
+                    qc.overflow++;
+                }
+                cur = nd.c0;
+            } else if (h0) {
+                cur = nd.c0;
+            } else if (h1) {
+                cur = nd.c1;
+            } else {
+                have = false;
+            }
+        } else {
+            const int32_t v = -1 - cur;
+            const int32_t start = v >> 3, n = (v & 7) + 1;
+            for (int32_t i = start; i < start + n; ++i) {
+                T t0 = T(0), t1 = T(0);
+                const T l = ref_clip<T>(r, i, x, R, t0, t1);
+                qc.prims++;
+                if (!(l > T(0))) continue;
+                L += l;
+                const uint32_t o = (uint32_t)r.info[i].w;
+                const u4 w = philox10(u4{ctr.x, ctr.y, ctr.z, ctr.w | 8u | (o << 16)}, key0, key1);
+                const T e = -log(unif_pos<T>(w.x)) / l;
+                if (e < best) {
+                    best = e;
+                    win = i;
+                    wt0 = t0;
+                    wt1 = t1;
+                    wpos = w.y;
+                }
+            }
+            have = false;
+        }
+        if (!have && sp > 0) {
+            --sp;
+            cur = st.get_node(sp);
+            have = true;
+        }
+    }
+    if (win >= 0) {
+        const T* g = r.geo + (size_t)win * kRefGeo;
+        const T t = wt0 + unif<T>(wpos) * (wt1 - wt0);
+        z[0] = g[0] + t * (g[2] - g[0]);
+        z[1] = g[1] + t * (g[3] - g[1]);
+    }
+    return win;
+}
 
 // A reflecting-BVH node and its children's cones, from LDS for the staged
 // prefix, from global memory otherwise.
@@ -445,6 +559,9 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
     int64_t wid = -1;
     T x[D], xoff[D], nin[D];
     T acc = T(0), u_main = T(0), usum = T(0);
+    // throughput of the current walk (Robin steps may flip its sign or
+    // exceed 1) and, during nested walks, that of the main walk
+    T tau = T(1), tau_main = T(1);
     T kappa = T(0), eps = T(1), delta = T(1);
     uint32_t k = 0, m = 0, p = 0, inst_tag = 0;
     int64_t first_row = 0;
@@ -508,6 +625,7 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
                         keep_on_domain_side<T>(ref, on, nin, x);
                     }
                     acc = T(0); k = 0; warm = -1; phase = 0; usum = T(0); wsteps = 0;
+                    tau = T(1);
                     c_walks++;
                 }
             }
@@ -541,6 +659,7 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
                 if (MODE == 1) {
                     a.rec_prim[wid] = -1;
                     a.rec_uoff[wid] = nanv;
+                    if (a.rec_w) a.rec_w[wid] = T(1);
                 }
                 if (a.rec_steps) a.rec_steps[wid] = wsteps;
                 wid = -1;
@@ -580,7 +699,8 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
 #pragma unroll
                         for (int c = 0; c < D; ++c) n[c] = -n[c];
                     }
-                    u_main = acc + g;
+                    u_main = acc + tau * g;
+                    tau_main = tau;
                     term_code = orig * 2 + flip;
                     term_b1 = bary[1];
                     term_leaf = leaf;
@@ -592,6 +712,7 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
                         a.rec_prim[wid] = term_code;
                         a.rec_b[wid] = term_b1;
                         a.rec_uoff[wid] = g;
+                        if (a.rec_w) a.rec_w[wid] = tau_main;
                         if (a.rec_steps) a.rec_steps[wid] = wsteps;
                         wid = -1;
                         c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;
@@ -601,13 +722,13 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
                     phase = 1;
 #pragma unroll
                     for (int c = 0; c < D; ++c) x[c] = xoff[c];
-                    acc = T(0); k = 0; warm = term_leaf; on = -1;
+                    acc = T(0); k = 0; warm = term_leaf; on = -1; tau = T(1);
                     c_nested++;
                     c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;
                     continue;
                 }
                 finished = true;
-                result = acc + g;
+                result = acc + tau * g;
             } else {
                 sil_begin<T>(sq, d2);
                 spend = true;
@@ -648,7 +769,10 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
             // scale.  In FP64 the floor is ~1e-15 and never binds in practice.
             const T ulp = sizeof(T) == 4 ? T(1.1920929e-07) : T(2.220446049250313e-16);
             const T rmin = T(16) * ulp * (fabs(x[0]) + fabs(x[1]));
-            const T R = fmin(d, fmax(sqrt(sq.best), rmin));
+            T R = fmin(d, fmax(sqrt(sq.best), rmin));
+            // a Robin coefficient also caps the radius at 1/mu (a variance
+            // choice: it bounds the Robin term's mass per step)
+            if (ref.mu > T(0)) R = fmin(R, fmax(T(1) / ref.mu, rmin));
             const uint32_t tag = inst_tag | (nested ? (1u | ((uint32_t)(phase - 1) << 8)) : 0u);
             const u4 r = philox10(u4{k, m, p, tag}, key0, key1);
             T dir[2];
@@ -672,25 +796,56 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
                     T y[3];
 #pragma unroll
                     for (int c = 0; c < D; ++c) y[c] = x[c] + rho * R * dir[c];
-                    acc += green_ball_t<D, T>(kappa, rho, R) * source_f<T, D>(a.prm, y);
+                    acc += tau * green_ball_t<D, T>(kappa, rho, R) * source_f<T, D>(a.prm, y);
                 }
             }
-            const T wgt = seg >= 0 ? reflect_weight<D, T>(kappa, t, R) : poisson_scale<T, D>(kappa, R);
-            if (a.prm.rr && wgt < unif<T>(r.z)) {
+            // Robin terms of the star-shaped region's integral equation over
+            // the reflecting boundary in the ball, -int G (mu u + h): z
+            // uniform by length on that part (length Lz); the data term
+            // directly, the mu term by continuing at z with probability q;
+            // both doubled at a wall point (the equation's u/2 there)
+            T zr[2] = {T(0), T(0)}, Lz = T(0), Gz = T(0);
+            int32_t zleaf = -1;
+            const T cx = on >= 0 ? T(2) : T(1);
+            if (ref.robin) {
+                zleaf = ref_boundary_sample<T>(ref, x, R, u4{k, m, p, tag}, key0, key1, Lz, zr, qc, stack);
+                if (zleaf >= 0) {
+                    const T rz = fmax(sqrt((zr[0] - x[0]) * (zr[0] - x[0]) + (zr[1] - x[1]) * (zr[1] - x[1])), rmin);
+                    // G(r; R) = (G |B_R|) / |B_R|
+                    Gz = green_ball_t<D, T>(kappa, fmin(rz / R, T(1)), R) / (T(3.14159265358979323846) * R * R);
+                    acc -= tau * cx * Lz * Gz * robin_data<T>(ref, zr);
+                }
+            }
+            const T q = (ref.mu > T(0) && zleaf >= 0) ? fmin(T(0.5), cx * ref.mu * Lz * Gz) : T(0);
+            const bool to_z = q > T(0) && unif<T>(r.y) < q;
+            const T wgt = to_z ? -cx * ref.mu * Lz * Gz / q
+                               : (seg >= 0 ? reflect_weight<D, T>(kappa, t, R) : poisson_scale<T, D>(kappa, R)) /
+                                     (T(1) - q);
+            // roulette keeps the walk with probability min(1, |wgt|), and the
+            // throughput carries the rest of the weight
+            const T keep = fmin(T(1), fabs(wgt));
+            if (a.prm.rr && (!(keep > T(0)) || keep < unif<T>(r.z))) {
                 finished = true;
                 result = acc;
                 if (MODE == 1 && phase == 0) term_code = -1;
             } else {
+                tau *= a.prm.rr ? wgt / keep : wgt;
                 if (MODE == 1 && phase == 0) {
 #pragma unroll
                     for (int c = 0; c < D; ++c) xoff[c] = x[c];   // previous position
                 }
+                if (to_z) {   // continue on the wall at z
+                    x[0] = zr[0];
+                    x[1] = zr[1];
+                    on = zleaf;
+                } else {
 #pragma unroll
-                for (int c = 0; c < D; ++c) x[c] += t * dir[c];
-                on = seg;
-                if (seg >= 0) {   // the domain is on the wall's left
-                    ref_left_normal<T>(ref, seg, nin);
-                    keep_on_domain_side<T>(ref, seg, nin, x);
+                    for (int c = 0; c < D; ++c) x[c] += t * dir[c];
+                    on = seg;
+                }
+                if (on >= 0) {   // the domain is on the wall's left
+                    ref_left_normal<T>(ref, on, nin);
+                    keep_on_domain_side<T>(ref, on, nin, x);
                 }
                 ++k;
                 warm = leaf;
@@ -707,6 +862,7 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
             a.rec_u[wid] = result;
             a.rec_prim[wid] = -1;
             a.rec_uoff[wid] = T(0);
+            if (a.rec_w) a.rec_w[wid] = T(1);
             if (a.rec_steps) a.rec_steps[wid] = wsteps;
             wid = -1;
         } else {
@@ -716,13 +872,14 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
                 a.rec_prim[wid] = term_code;
                 a.rec_b[wid] = term_b1;
                 a.rec_uoff[wid] = usum / T(a.prm.K);
+                if (a.rec_w) a.rec_w[wid] = tau_main;
                 if (a.rec_steps) a.rec_steps[wid] = wsteps;
                 wid = -1;
             } else {
                 ++phase;
 #pragma unroll
                 for (int c = 0; c < D; ++c) x[c] = xoff[c];
-                acc = T(0); k = 0; warm = term_leaf; on = -1;
+                acc = T(0); k = 0; warm = term_leaf; on = -1; tau = T(1);
                 c_nested++;
             }
         }

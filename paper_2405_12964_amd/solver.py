@@ -142,6 +142,14 @@ class Solver:
         segs = np.ascontiguousarray(segs, dtype=np.int32).reshape(-1, 2)
         check(capi.dwos_set_reflecting(self._ctx, _dp(V), V.shape[0], _ip(segs), segs.shape[0]))
 
+    def set_robin(self, mu: float, h=None):
+        """Robin condition du/dn - mu u = h on the reflecting boundary (n into
+        the domain); h a restricted field dict(c=, b=, A=) or None."""
+        hb = None
+        if h is not None:
+            hb = make_problem(bc=[h], dim=2).bc[0]
+        check(capi.dwos_set_robin(self._ctx, float(mu), C.byref(hb) if hb is not None else None))
+
     def set_start_segments(self, seg):
         """Per query point of the following calls: the reflecting segment it
         lies on (domain to the segment's left) or -1; None clears."""
@@ -199,6 +207,8 @@ class Solver:
             s.set_boundary(scene.V if V is None else V, scene.prims, scene.label, scene.gvert)
         if getattr(scene, "nsegs", None) is not None and len(scene.nsegs) > 0:
             s.set_reflecting(scene.NV, scene.nsegs)
+            if getattr(scene, "robin_mu", 0.0) > 0 or getattr(scene, "robin_h", None) is not None:
+                s.set_robin(scene.robin_mu, scene.robin_h)
         s.set_problem(make_problem(scene.sigma, scene.eps, scene.delta, scene.K, scene.kmax,
                                    scene.rr, scene.src_c0, scene.gauss, scene.bc, scene.dim,
                                    getattr(scene, "dudn", 0)))
