@@ -135,3 +135,82 @@ def test_batch_screened_instance_needs_roulette(dev, dwos):
     s.set_problem(make_problem(0.0, a.eps, a.delta, 1, a.kmax, 1, 0.0, None, a.bc, 2))
     m, _ = s.batch_solve(X, [2, 2], 16, 1)
     assert np.all(np.isfinite(m.cpu().numpy()))
+
+
+def _batch3d(dwos, insts, stream=None):
+    from paper_2405_12964_amd.solver import make_problem
+    s = dwos.Solver(3, "fp32", stream=stream)
+    sc0 = insts[0][0]
+    s.set_problem(make_problem(0.0, sc0.eps, sc0.delta, 1, sc0.kmax, 1, 0.0, None, sc0.bc, 3))
+    for i, (sc, _) in enumerate(insts):
+        assert s.batch_add_instance(sc.V, sc.prims, sc.label, sc.sigma, sc.eps, sc.delta) == i
+        s.batch_set_parameters(i, sc.N, sc.rowptr, sc.pid, sc.vel)
+    return s
+
+
+def test_batch_graph_capture_replays_match_eager(dev, dwos):
+    """Batched instances of the 3D generator of the batch workload (displaced
+    icospheres in boxes, uneven sizes, screening sigma ~ U(0, 20)): the
+    batched solve and reverse mode captured in one hipGraph on the context
+    stream and replayed with a new device seed each time equal the eager calls
+    with that seed (the gradient to the FP64 atomics' summation order), with
+    eager work between replays."""
+    insts = scenes.c4_batch(n_inst=6, tri_lo=200, tri_hi=3000, p_lo=32, p_hi=256, n_basis=16)
+    X = T(np.concatenate([x for _, x in insts]), dev)
+    P = [len(x) for _, x in insts]
+    w = torch.linspace(-1, 1, X.shape[0], dtype=torch.float64, device=dev)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        s = _batch3d(dwos, insts, stream)
+        seed_buf = torch.zeros(1, dtype=torch.int64, device=dev)
+        s.set_seed_buffer(seed_buf)
+        s.batch_solve(X, P, 64, 5)
+        s.batch_grad(X, P, w, 64, 6)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        mg, vg = s.batch_solve(X, P, 64, 5)
+        gg, ug = s.batch_grad(X, P, w, 64, 6)
+    outs = []
+    for r in range(4):
+        with torch.cuda.stream(stream):
+            seed_buf.fill_(2000 + r)
+            g.replay()
+            me, ve = s.batch_solve(X, P, 64, 5)
+            ge, ue = s.batch_grad(X, P, w, 64, 6)
+        torch.cuda.synchronize()
+        assert torch.equal(mg, me) and torch.equal(vg, ve), r
+        assert torch.allclose(gg, ge, rtol=1e-12, atol=1e-14) and torch.equal(ug, ue), r
+        outs.append(mg.clone())
+        _ = torch.randn(1000, device=dev).sum().item()
+    assert not torch.equal(outs[0], outs[1])
+    s.set_seed_buffer(None)
+
+
+def test_batch_grad_3d_equals_oracle_per_instance(dev, dwos, oracle_mod):
+    """3D instances of the batch generator (FP64 walk for walk): each
+    instance's slice of the batch gradient equals the oracle's reverse mode of
+    that instance with its instance index in the Philox counter."""
+    insts = scenes.c4_batch(n_inst=3, tri_lo=150, tri_hi=800, p_lo=6, p_hi=10, n_basis=16)
+    from paper_2405_12964_amd.solver import make_problem
+    s = dwos.Solver(3, "fp64")
+    sc0 = insts[0][0]
+    s.set_problem(make_problem(0.0, sc0.eps, sc0.delta, 1, sc0.kmax, 1, 0.0, None, sc0.bc, 3))
+    for i, (sc, _) in enumerate(insts):
+        s.batch_add_instance(sc.V, sc.prims, sc.label, sc.sigma, sc.eps, sc.delta)
+        s.batch_set_parameters(i, sc.N, sc.rowptr, sc.pid, sc.vel)
+    X = np.concatenate([x for _, x in insts])
+    P = [len(x) for _, x in insts]
+    rng = np.random.default_rng(7)
+    w = rng.normal(size=len(X))
+    W, seed = 16, 31
+    g, um = s.batch_grad(T(X, dev), P, T(w, dev), W, seed)
+    g = g.cpu().numpy()
+    off, p0 = 0, 0
+    for i, (sc, x) in enumerate(insts):
+        og, oum, _ = oracle_mod.Oracle(sc).grad(x, w[p0:p0 + len(x)], W, seed, instance=i)
+        gi = g[off:off + sc.N]
+        assert np.allclose(gi, og, rtol=1e-9, atol=1e-9 * max(1.0, float(np.abs(og).max()))), (i, gi, og)
+        assert np.allclose(um.cpu().numpy()[p0:p0 + len(x)], oum, rtol=0, atol=1e-9), i
+        off += sc.N
+        p0 += len(x)
