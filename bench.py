@@ -58,6 +58,7 @@ PEAK_HBM = 8.0e12             # bytes/s
 TRAFFIC_FILES = {
     "c2": os.path.join(ROOT, "profiles", "walk_kernel_c2_star4096_hbm.txt"),
     "c3": os.path.join(ROOT, "profiles", "walk_kernel_c3_icosphere200k_hbm.txt"),
+    "c4": os.path.join(ROOT, "profiles", "walk_kernel_c4_batch256_hbm.txt"),
 }
 
 # Algorithmic bytes per counted unit of the 3D walk kernel: a pair-node visit
@@ -139,22 +140,32 @@ def cpu_baseline(sc, X, seed, threads, npts=1024, W=1024, what=""):
 
 def run_c5(args):
     """Shape from diffusion on the displaced icosphere (200,000 object
-    triangles + box) with the learned control variate, trained online.
+    triangles + box) from c = 0 toward the target coefficients (seed 3),
+    with the learned control variate trained online (the surrogate) and with
+    plain walks, the same number of iterations each.
 
-    65536 points on the box faces, W = 64 forward and 64 differential walks
-    per iteration, squared loss against a reference solution of the target
-    coefficients (seed 3), Adam on the 1024 coefficients from c = 0, and after
-    each backward 16 Adam steps of the control-variate network (30 Fourier
-    frequencies of scale 0.125, lr 1e-3) on that iteration's walk records.  After the timed iterations the gradient at the
-    final coefficients is re-estimated with independent seeds, plain and with
-    the control variate at q = 1, 0.5, 0.25, to compare variance x time."""
+    65536 points on the box faces, W forward and W differential walks per
+    iteration (W = 64, or annealed geometrically from --walks to
+    --c5-final-walks, Sec. 6's walks-per-pixel schedule), squared loss
+    against a reference solution of the target coefficients, Adam (lr 1e-3)
+    on the 1024 coefficients; in the surrogate run, after each backward, 16
+    Adam steps of the control-variate network (16 Fourier frequencies of
+    scale 0.125, lr 1e-3) on that iteration's walk records.  The timed
+    window is the surrogate run's last --steps iterations.  Progress is
+    measured without the walks' own noise: the loss at 1024 walks per point
+    with one fixed seed (common to both runs and every evaluation) and the
+    coefficient error.  At the surrogate's final coefficients the gradient is
+    re-estimated with independent seeds, plain and with the control variate
+    at q = 1, 0.5, 0.25, to compare variance x time."""
     import numpy as np
     import torch
     import scenes
     import paper_2405_12964_amd as dw
 
     dev = torch.device("cuda:0")
-    P, W = args.points or 65536, args.walks or 64
+    P, W0 = args.points or 65536, args.walks or 64
+    WT = args.c5_final_walks or W0
+    iters = args.warmup + args.steps
     nb = 1024
     sc = scenes.c3_icosphere(nu=100, n_basis=nb, coef=np.zeros(nb))
     X = scenes.points_on_box_faces(P, 1)
@@ -164,44 +175,86 @@ def run_c5(args):
     uref, _ = ref.solve(Xt, 1024, 99)
     torch.cuda.synchronize()
     del ref
-
-    model = dw.ShapeModel(sc, "fp32")
-    B, th = scenes.mlp_init(3, args.cv_seed, args.cv_freq, args.cv_features)
-    th[-(scenes.MLP_WIDTH + 1):] = 0.0        # N = 0: the first calls are plain
-    net = dw.Network(3, B, th)
-    model.solver.attach_cv(net, 1.0)
-    pi = torch.zeros(nb, dtype=torch.float64, device=dev, requires_grad=True)
-    opt = torch.optim.Adam([pi], lr=1e-3)
-
-    def step(i):
-        opt.zero_grad(set_to_none=True)
-        u = dw.DWoSFunction.apply(pi, Xt, model, W, 1000 + 2 * i, W, 1001 + 2 * i)
-        loss = 0.5 * ((u - uref) ** 2).sum()
-        loss.backward()
-        opt.step()
-        model.solver.cv_train(args.cv_steps, args.cv_batch, args.cv_lr, 50000 + i)
-        return loss
-
     coef_t_dev = torch.tensor(coef_t, device=dev)
-    err0 = float(torch.linalg.norm(pi.detach() - coef_t_dev).item())
-    loss0 = float(step(0).item())
-    for i in range(1, args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    for kind in (0, 1):
-        model.solver.walk_timing(kind, reset=True)
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        loss = step(args.warmup + i)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms0, n0, tot0 = model.solver.walk_timing(0)
-    ms1, n1, tot1 = model.solver.walk_timing(1)
 
-    # gradient variance at the final coefficients: plain vs control variate
+    def walks_at(i):
+        # W_t = W_0 exp(log(W_T / W_0) t / T), rounded to a multiple of 8
+        w = W0 * math.exp(math.log(WT / W0) * i / max(1, iters - 1))
+        return max(8, int(round(w / 8.0)) * 8)
+
+    def optimise(use_cv, timed):
+        model = dw.ShapeModel(sc, "fp32")
+        net = None
+        if use_cv:
+            B, th = scenes.mlp_init(3, args.cv_seed, args.cv_freq, args.cv_features)
+            th[-(scenes.MLP_WIDTH + 1):] = 0.0        # N = 0: the first calls are plain
+            net = dw.Network(3, B, th)
+            model.solver.attach_cv(net, 1.0)
+        pi = torch.zeros(nb, dtype=torch.float64, device=dev, requires_grad=True)
+        opt = torch.optim.Adam([pi], lr=1e-3)
+
+        def true_loss():
+            with torch.no_grad():
+                model.apply(pi)
+                u, _ = model.solver.solve(Xt, 1024, 4242, var=False)
+                return float(0.5 * ((u - uref) ** 2).sum().item()), \
+                    float(torch.linalg.norm(pi.detach() - coef_t_dev).item())
+
+        def step(i):
+            opt.zero_grad(set_to_none=True)
+            W = walks_at(i)
+            u = dw.DWoSFunction.apply(pi, Xt, model, W, 1000 + 2 * i, W, 1001 + 2 * i)
+            loss = 0.5 * ((u - uref) ** 2).sum()
+            loss.backward()
+            opt.step()
+            if use_cv:
+                model.solver.cv_train(args.cv_steps, args.cv_batch, args.cv_lr, 50000 + i)
+            return loss
+
+        hist = {"iteration": [0], "loss_1024": [], "coef_error": []}
+        l0, e0 = true_loss()
+        hist["loss_1024"].append(l0)
+        hist["coef_error"].append(e0)
+        n_pre = args.warmup if timed else iters
+        t_all = time.perf_counter()
+        for i in range(n_pre):
+            step(i)
+            if (i + 1) % 50 == 0 and i + 1 < iters:
+                l, e = true_loss()
+                hist["iteration"].append(i + 1)
+                hist["loss_1024"].append(l)
+                hist["coef_error"].append(e)
+        torch.cuda.synchronize()
+        res = {"model": model, "pi": pi, "net": net, "hist": hist}
+        if timed:
+            for kind in (0, 1):
+                model.solver.walk_timing(kind, reset=True)
+            t0 = time.perf_counter()
+            for i in range(args.steps):
+                loss = step(args.warmup + i)
+            torch.cuda.synchronize()
+            res["elapsed"] = time.perf_counter() - t0
+            res["loss"] = float(loss.item())
+            res["timing"] = (model.solver.walk_timing(0), model.solver.walk_timing(1))
+        res["seconds"] = time.perf_counter() - t_all
+        l, e = true_loss()
+        hist["iteration"].append(iters)
+        hist["loss_1024"].append(l)
+        hist["coef_error"].append(e)
+        print(f"c5 {'surrogate' if use_cv else 'plain'}: loss_1024 {hist['loss_1024'][0]:.4g} -> {l:.4g}, "
+              f"coefficient error {hist['coef_error'][0]:.4f} -> {e:.4f}", file=sys.stderr, flush=True)
+        return res
+
+    cvr = optimise(True, True)
+    plain = optimise(False, False)
+    (ms0, n0, tot0), (ms1, n1, tot1) = cvr["timing"]
+    elapsed = cvr["elapsed"]
+    model, pi, net = cvr["model"], cvr["pi"], cvr["net"]
+
+    # gradient variance at the surrogate's final coefficients: plain vs control variate
     with torch.no_grad():
         model.apply(pi)
-        u, _ = model.solver.solve(Xt, W, 777)
+        u, _ = model.solver.solve(Xt, W0, 777)
         w = (u - uref).contiguous()
 
     def grads(q, reps=6):
@@ -209,12 +262,12 @@ def run_c5(args):
             model.solver.attach_cv(None)
         else:
             model.solver.attach_cv(net, q)
-            model.solver.grad(Xt, w, W, 900)          # sets beta for this q
+            model.solver.grad(Xt, w, W0, 900)          # sets beta for this q
         gs, ts = [], []
         for r in range(reps):
             torch.cuda.synchronize()
             t = time.perf_counter()
-            g, _ = model.solver.grad(Xt, w, W, 901 + r, u_mean=False)
+            g, _ = model.solver.grad(Xt, w, W0, 901 + r, u_mean=False)
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t)
             gs.append(g.cpu().numpy())
@@ -229,24 +282,38 @@ def run_c5(args):
         cv[f"q={q}"] = {"grad_var": v, "ms": 1e3 * t, "beta": beta, "var_ratio": v / v_plain,
                         "efficiency": (v_plain * t_plain) / (v * t)}
     steps_total = tot0["steps"] + tot1["steps"]
+    pi_np = pi.detach().cpu().numpy()
+    hs, hp = cvr["hist"], plain["hist"]
     return {
         "metric": METRIC, "value": steps_total / elapsed, "unit": "walk-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "3D shape from diffusion: displaced icosphere (200,000 triangles) in a "
-                               f"box, sigma=4, {P} points x {W} walks per iteration, 1024 coefficients, "
-                               "learned control variate trained online", "points": P,
-                   "walks_per_point": W, "triangles": int(sc.prims.shape[0]), "params": nb},
+                               f"box, sigma=4, {P} points x {W0}" + (f"->{WT}" if WT != W0 else "") +
+                               f" walks per iteration, {iters} Adam iterations (lr 1e-3) from c = 0 on 1024 "
+                               "coefficients, learned control variate trained online", "points": P,
+                   "walks_per_point": W0, "final_walks_per_point": WT, "iterations": iters,
+                   "triangles": int(sc.prims.shape[0]), "params": nb},
         "grad_evals_per_s": args.steps / elapsed,
         "walk_steps": {"forward": tot0["steps"], "differential": tot1["steps"],
                        "forward_ms": ms0, "differential_ms": ms1},
-        "loss_first": loss0, "loss": float(loss.item()),
-        "coef_error_first": err0, "coef_error": float(torch.linalg.norm(pi.detach() - coef_t_dev).item()),
+        "loss": cvr["loss"],
+        "surrogate_vs_plain": {
+            "loss_1024": {"start": hs["loss_1024"][0], "surrogate": hs["loss_1024"][-1],
+                          "plain": hp["loss_1024"][-1]},
+            "coef_error": {"start": hs["coef_error"][0], "surrogate": hs["coef_error"][-1],
+                           "plain": hp["coef_error"][-1]},
+            "history": {"iteration": hs["iteration"], "surrogate_loss_1024": hs["loss_1024"],
+                        "plain_loss_1024": hp["loss_1024"], "surrogate_coef_error": hs["coef_error"],
+                        "plain_coef_error": hp["coef_error"]},
+            "seconds": {"surrogate": cvr["seconds"], "plain": plain["seconds"]},
+            "loss_1024_note": "0.5 sum (u - uref)^2 with u from 1024 walks per point, one fixed seed",
+        },
         "grad_norm": float(np.linalg.norm(g_mean)),
         # cosine between the descent direction and the way to the target
-        "grad_alignment": float(-g_mean @ (coef_t - pi.detach().cpu().numpy()) /
-                                (np.linalg.norm(g_mean) * np.linalg.norm(coef_t - pi.detach().cpu().numpy()))),
+        "grad_alignment": float(-g_mean @ (coef_t - pi_np) /
+                                (np.linalg.norm(g_mean) * np.linalg.norm(coef_t - pi_np))),
         "cv_training": {"freq_scale": args.cv_freq, "features": args.cv_features, "init_seed": args.cv_seed,
                         "adam_steps_per_iteration": args.cv_steps, "batch": args.cv_batch, "lr": args.cv_lr},
         "control_variate": cv,
@@ -257,8 +324,13 @@ def run_c4(args):
     """Many instances of uneven size in one persistent launch: 256 displaced
     icospheres in boxes (980 - 100,820 triangles, log-uniform), 512 - 16384
     points each (log-uniform), screening sigma_i ~ U(0, 20), W walks per
-    point; against the same work as one launch per instance (one context
-    each)."""
+    point.  One step = the batched forward solve of every instance and the
+    batched reverse mode (each instance's 256 radial-basis coefficients, K =
+    1), captured once in a hipGraph on the context stream and replayed with a
+    new device seed per step, after the autotuner has set the walk kernels'
+    scheduling knobs for the batch.  Beside it: the same two calls issued
+    eagerly (their walk-kernel times give the roofline), and the forward work
+    as one context and one launch per instance."""
     import numpy as np
     import torch
     import scenes
@@ -267,23 +339,73 @@ def run_c4(args):
     dev = torch.device("cuda:0")
     W = args.walks or 64
     insts = scenes.c4_batch()
-    s = dw.Solver(3, "fp32")
+    stream = torch.cuda.Stream()
+    s = dw.Solver(3, "fp32", stream=stream)
     sc0 = insts[0][0]
     s.set_problem(dw.make_problem(0.0, sc0.eps, sc0.delta, 1, sc0.kmax, 1, 0.0, None, sc0.bc, 3))
-    for sc, _ in insts:
+    for i, (sc, _) in enumerate(insts):
         s.batch_add_instance(sc.V, sc.prims, sc.label, sc.sigma, sc.eps, sc.delta)
+        s.batch_set_parameters(i, sc.N, sc.rowptr, sc.pid, sc.vel)
     X = torch.tensor(np.concatenate([x for _, x in insts]), dtype=torch.float64, device=dev)
     P = [len(x) for _, x in insts]
-    s.batch_solve(X, P, W, 1)
+    wts = torch.cat([torch.full((len(x),), 1.0 / len(x), dtype=torch.float64, device=dev) for _, x in insts])
+    with torch.cuda.stream(stream):
+        s.batch_solve(X, P, W, 1, var=False)
+        tuning, tune_ms = (s.get_tuning(), None) if args.no_autotune else s.autotune(X, W, seed=5, P=P, cache=False)
+        s.batch_grad(X, P, wts, W, 2, u_mean=False)
     torch.cuda.synchronize()
-    s.walk_timing(0, reset=True)
-    t0 = time.perf_counter()
-    for i in range(args.steps):
+    print(f"c4: {len(insts)} instances, tuning {tuning} ({tune_ms} ms)", file=sys.stderr, flush=True)
+
+    def eager(i):
         s.batch_solve(X, P, W, 10 + i, var=False)
+        s.batch_grad(X, P, wts, W, 20 + i, u_mean=False)
+
+    with torch.cuda.stream(stream):
+        for i in range(args.warmup):
+            eager(i)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms, n, tot = s.walk_timing(0)
-    # the same work, one context and one launch per instance
+    for kind in (0, 1):
+        s.walk_timing(kind, reset=True)
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for i in range(args.steps):
+            eager(i)
+    torch.cuda.synchronize()
+    elapsed_eager = time.perf_counter() - t0
+    ms0, n0, tot0 = s.walk_timing(0)
+    ms1, n1, tot1 = s.walk_timing(1)
+
+    # the step captured once and replayed with a new device seed each time
+    seed_buf = torch.zeros(1, dtype=torch.int64, device=dev)
+    s.set_seed_buffer(seed_buf)
+    with torch.cuda.stream(stream):
+        eager(0)   # an identical call before the capture: tables and workspaces in place
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        eager(0)
+    with torch.cuda.stream(stream):
+        for i in range(args.warmup):
+            seed_buf.fill_(1000 + i)
+            graph.replay()
+    torch.cuda.synchronize()
+    for kind in (0, 1):
+        s.walk_timing(kind, reset=True)
+    t1 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for i in range(args.steps):
+            seed_buf.fill_(2000 + i)
+            graph.replay()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t1
+    _, _, gt0 = s.walk_timing(0)
+    _, _, gt1 = s.walk_timing(1)
+    s.set_seed_buffer(None)
+    for t in (tot0, tot1, gt0, gt1):
+        assert t["stack_overflow"] == 0 and t["invalid"] == 0, t
+    steps_total = gt0["steps"] + gt1["steps"]
+
+    # the forward work as one context and one launch per instance
     solvers = []
     for (sc, x) in insts:
         si = dw.Solver(3, "fp32")
@@ -293,42 +415,69 @@ def run_c4(args):
     for si, xi in solvers:
         si.solve(xi, W, 1, var=False)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    t2 = time.perf_counter()
     for i in range(args.steps):
         for si, xi in solvers:
             si.solve(xi, W, 10 + i, var=False)
     torch.cuda.synchronize()
-    elapsed_seq = time.perf_counter() - t1
-    steps_total = tot["steps"]
-    # reverse mode over the same batch: every instance's radial-basis
-    # coefficients, all differential walks (K = 1) in one launch
-    for i, (sc, _) in enumerate(insts):
-        s.batch_set_parameters(i, sc.N, sc.rowptr, sc.pid, sc.vel)
-    wts = torch.cat([torch.full((len(x),), 1.0 / len(x), dtype=torch.float64, device=dev) for _, x in insts])
-    s.batch_grad(X, P, wts, W, 2, u_mean=False)
-    torch.cuda.synchronize()
-    s.walk_timing(1, reset=True)
-    t2 = time.perf_counter()
-    for i in range(args.steps):
-        s.batch_grad(X, P, wts, W, 20 + i, u_mean=False)
-    torch.cuda.synchronize()
-    elapsed_g = time.perf_counter() - t2
-    ms_g, n_g, tot_g = s.walk_timing(1)
-    return {
+    elapsed_seq = time.perf_counter() - t2
+    fwd_eager_s = ms0 / 1e3
+    del solvers
+
+    kind, ms, n, tot = (1, ms1, n1, tot1) if ms1 >= ms0 else (0, ms0, n0, tot0)
+    avg_s = ms / max(1, n) / 1e3
+    kname = f"walk_kernel<float,3,{kind},true>" if tuning["variant"] == 0 else f"walk_kernel<float,3,{kind},false>"
+    bytes_launch = (tot["nodes"] * BYTES_NODE_3D + tot["prims"] * BYTES_PRIM_3D) / max(1, n)
+    ops_launch = (tot["nodes"] * OPS_NODE_3D + tot["prims"] * OPS_PRIM_3D + tot["steps"] * OPS_STEP_3D) / max(1, n)
+    achieved = bytes_launch / avg_s
+    info = s.scene_info()
+    probe = probe_gather(info["node_bytes"] + info["prim_bytes"])
+    roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM, "traffic": measured_traffic(kname, 1, "c4"),
+            "kernel": kname, "avg_launch_ms": ms / max(1, n), "launches": n,
+            "algorithmic_bytes_per_launch": bytes_launch,
+            "bytes_per_step": bytes_launch / max(1.0, tot["steps"] / max(1, n)),
+            "steps_per_launch": tot["steps"] / max(1, n),
+            "nodes_per_step": tot["nodes"] / max(1, tot["steps"]),
+            "prims_per_step": tot["prims"] / max(1, tot["steps"]),
+            "scene": info, "gather_probe": probe,
+            "frac_of_gather_probe": achieved / (probe["gather64_working_set_GBs"] * 1e9),
+            "alu": {"achieved_TFLOPs": ops_launch / avg_s / 1e12, "peak_TFLOPs": PEAK_FP32_VALU / 1e12,
+                    "frac": ops_launch / avg_s / PEAK_FP32_VALU}}
+    out = {
         "metric": METRIC, "value": steps_total / elapsed, "unit": "walk-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": 1, "ms_per_step": 1e3 * elapsed / args.steps,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"256 instances (C3 generator, 980-100,820 triangles, 512-16384 points, "
-                               f"sigma ~ U(0,20)) in one persistent launch, W = {W}",
+        "config": {"workload": f"256 instances (displaced icospheres in boxes, 980-100,820 triangles, 512-16384 "
+                               f"points, sigma ~ U(0,20), 256 radial-basis coefficients each): batched forward "
+                               f"solve + batched reverse mode (K = 1), W = {W}, one hipGraph replay per step",
                    "instances": len(insts), "triangles": int(sum(sc.prims.shape[0] for sc, _ in insts)),
-                   "points": int(sum(P)), "walks_per_point": W},
-        "walk_kernel_ms": ms / max(1, n),
-        "per_instance_launches": {"ms_per_step": 1e3 * elapsed_seq / args.steps,
-                                  "speedup_of_one_launch": elapsed_seq / elapsed},
-        "batch_grad": {"ms_per_call": 1e3 * elapsed_g / args.steps, "walk_steps_per_s": tot_g["steps"] / elapsed_g,
-                       "params": int(sum(sc.N for sc, _ in insts)), "walk_kernel_ms": ms_g / max(1, n_g)},
+                   "points": int(sum(P)), "walks_per_point": W, "params": int(sum(sc.N for sc, _ in insts))},
+        "tuning": tuning, "autotune_ms": tune_ms,
+        "walk_steps": {"forward": gt0["steps"], "differential": gt1["steps"], "nested_walks": gt1["nested_walks"]},
+        "eager": {"ms_per_step": 1e3 * elapsed_eager / args.steps,
+                  "forward_kernel_ms": ms0 / max(1, n0), "differential_kernel_ms": ms1 / max(1, n1),
+                  "walk_steps_per_s": (tot0["steps"] + tot1["steps"]) / elapsed_eager},
+        "per_instance_launches": {"forward_ms_per_step": 1e3 * elapsed_seq / args.steps,
+                                  "batched_forward_kernel_ms": 1e3 * fwd_eager_s / max(1, n0),
+                                  "speedup_of_one_launch": (elapsed_seq / args.steps) / (fwd_eager_s / max(1, n0))},
+        "roofline": roof,
     }
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = min(16, len(os.sched_getaffinity(0)))
+        t3 = time.perf_counter()
+        st = 0
+        for sc, x in insts[:4]:
+            o = oracle.Oracle(sc, threads=threads)
+            _, _, s1 = o.solve(x[:64], 16, 7)
+            st += s1
+        dt = time.perf_counter() - t3
+        out["cpu_baseline"] = {"value": st / dt, "unit": "walk-steps/s", "cores": threads, "kind": "oracle",
+                               "sample": f"instances 0-3 x 64 points x 16 forward walks, brute-force FP64, "
+                                         f"{dt:.1f} s", "walk_steps": int(st)}
+    return out
 
 
 def run_c5ls(args):
@@ -1009,6 +1158,9 @@ def main():
                     help="c3: training iterations of the control variate at the pinned state")
     ap.add_argument("--cv-walks", type=int, default=64,
                     help="c3: walks per point of each training iteration's differential call")
+    ap.add_argument("--no-autotune", action="store_true", help="c4: keep the default scheduling knobs")
+    ap.add_argument("--c5-final-walks", type=int, default=0,
+                    help="c5: anneal the walks per point geometrically from --walks to this count")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -1019,7 +1171,8 @@ def main():
         sys.exit(2)
 
     if args.workload == "c4":
-        args.steps = 3 if args.steps is None else args.steps
+        args.steps = 5 if args.steps is None else args.steps
+        args.warmup = 2 if args.warmup is None else args.warmup
         print(json.dumps(run_c4(args)), flush=True)
         return
     if args.workload == "c5ls":

@@ -244,17 +244,60 @@ dwos_status dwos_jvp(dwos_ctx* ctx, const double* X, int64_t P, int32_t W, uint6
  * boundary). */
 dwos_status dwos_scene_info(dwos_ctx* ctx, int64_t* info);
 
-/* Launch-shape autotuner.  Times a forward solve of the first min(P, 512)
- * points with W walks under each walk-kernel launch shape and keeps the
- * fastest for the context (FP32 only):
- *   variant 0: one 1024-thread block per CU with the top BVH levels (and, if
- *              they fit, all primitives) staged in LDS;
- *   variant 1: 256-thread blocks, several per CU, BVH read through the caches.
- * chosen (host, may be NULL) gets the variant, ms (host, 2 entries, may be
- * NULL) the timed milliseconds.  dwos_set_variant forces a variant.
- * Errors: as dwos_solve; EINVAL for a bad variant. */
-dwos_status dwos_autotune(dwos_ctx* ctx, const double* X, int64_t P, int32_t W, uint64_t seed,
-                          int32_t* chosen, double* ms);
+/* Scheduling knobs of the walk kernels.  They change only the schedule: a
+ * walk's result depends on (seed, instance, point, walk) alone, so every
+ * setting gives the same walks bit for bit (the FP64 gradient sums to their
+ * atomics' order).  The walks are independent (Sec. 3.3), so any order of
+ * execution is valid.
+ *   variant      0: one 1024-thread block per CU with the top BVH levels
+ *                (and, if they fit, all primitives) staged in LDS;
+ *                1: 256-thread blocks, several per CU, BVH read through the
+ *                caches.  FP64 contexts always use the unstaged kernel.
+ *   park         1..64: a wavefront takes its walk step once this many of
+ *                its lanes have their closest-point answer; the others
+ *                resume their traversal in the next iteration (default 24)
+ *   tail         0..63: a traversal round stops descending when at most this
+ *                many lanes still descend while another lane holds a leaf
+ *                to test; they go on in the next round (0: off; default 8)
+ *   chunk        walk ids a wavefront takes from the global queue per
+ *                refill: a multiple of 64 in 64..65536 (default 128)
+ *   stage_nodes  cap on the breadth-first prefix of BVH nodes staged in LDS
+ *                by variant 0 (-1: as many as fit; default -1) */
+typedef struct dwos_tuning {
+    int32_t variant;
+    int32_t park;
+    int32_t tail;
+    int32_t chunk;
+    int32_t stage_nodes;
+} dwos_tuning;
+
+/* Set or read the context's knobs (host struct).  Errors: EINVAL for a NULL
+ * argument or a value out of range (the context is then unchanged). */
+dwos_status dwos_set_tuning(dwos_ctx* ctx, const dwos_tuning* tuning);
+dwos_status dwos_get_tuning(dwos_ctx* ctx, dwos_tuning* tuning);
+
+#define DWOS_TUNE_CACHE 1
+
+/* Autotuner.  Times forward solves (Algorithm 1) with seed `seed` under
+ * candidate knob settings by coordinate descent (variant, then park, tail,
+ * chunk and, for variant 0, stage_nodes; a candidate replaces the incumbent
+ * when its walk-kernel time is more than 1% lower, each scored by the better
+ * of two runs of the same walks) and leaves the fastest set on the context.
+ * X (device) and P (host): on a single-scene context P[0] points of which
+ * the first min(P[0], max(64, 2^22 / W)) are solved; on a batch context one
+ * count per instance and the whole batch is solved (dwos_batch_solve).
+ * flags: DWOS_TUNE_CACHE looks the setting up in, and stores it to, a
+ * process-wide table keyed by device, dimension, precision, single or batch
+ * and the scene's primitive count in half-octaves (floor(2 log2 n)); a hit
+ * applies the stored setting without running anything.  Results are stored
+ * in the table in any case.  chosen (host, may be NULL) gets the setting,
+ * ms (host, 2 entries, may be NULL) the walk-kernel milliseconds under the
+ * setting in force at the call and under the chosen one (-1 on a cache hit).
+ * Errors: as dwos_solve / dwos_batch_solve; EINVAL for unknown flags; on an
+ * error the context keeps the setting in force at the call. */
+dwos_status dwos_autotune(dwos_ctx* ctx, const double* X, const int64_t* P, int32_t W, uint64_t seed,
+                          int32_t flags, dwos_tuning* chosen, double* ms);
+/* Set only the launch shape (the variant field above). */
 dwos_status dwos_set_variant(dwos_ctx* ctx, int32_t variant);
 
 /* Graph capture.  Every hot-path call (dwos_solve, dwos_grad,

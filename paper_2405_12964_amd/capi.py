@@ -39,6 +39,17 @@ class dwos_stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class dwos_tuning(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("park", C.c_int32), ("tail", C.c_int32), ("chunk", C.c_int32),
+                ("stage_nodes", C.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+DWOS_TUNE_CACHE = 1
+
+
 class dwos_quad(C.Structure):
     _fields_ = [("c", C.c_double), ("b", C.c_double * 3), ("A", C.c_double * 9)]
 
@@ -80,7 +91,9 @@ def lib():
             "dwos_eval_ball_kernels": [vp, vp, vp, C.c_int64, C.c_double, vp, vp],
             "dwos_walk_timing": [vp, C.c_int32, C.c_int32, dp, i64p, C.POINTER(dwos_stats)],
             "dwos_set_seed_buffer": [vp, vp],
-            "dwos_autotune": [vp, vp, C.c_int64, C.c_int32, C.c_uint64, i32p, dp],
+            "dwos_autotune": [vp, vp, i64p, C.c_int32, C.c_uint64, C.c_int32, C.POINTER(dwos_tuning), dp],
+            "dwos_set_tuning": [vp, C.POINTER(dwos_tuning)],
+            "dwos_get_tuning": [vp, C.POINTER(dwos_tuning)],
             "dwos_set_variant": [vp, C.c_int32],
             "dwos_batch_add_instance": [vp, dp, C.c_int64, i32p, C.c_int64, i32p, C.c_double,
                                         C.c_double, C.c_double, i32p],
@@ -152,6 +165,7 @@ EXPORTED = [
     "dwos_remesh", "dwos_mesh_size", "dwos_mesh_get", "dwos_mesh_destroy",
     "dwos_opt_create", "dwos_opt_destroy", "dwos_opt_reset", "dwos_opt_step", "dwos_opt_solve",
     "dwos_probe_bandwidth", "dwos_scene_info", "dwos_solve_noalloc", "dwos_set_robin",
+    "dwos_set_tuning", "dwos_get_tuning",
 ]
 
 

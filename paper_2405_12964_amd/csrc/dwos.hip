@@ -24,7 +24,9 @@
 #include "implicit_kernels.hpp"
 #include "adjoint_kernels.hpp"
 
+#include <map>
 #include <mutex>
+#include <tuple>
 
 namespace {
 
@@ -119,6 +121,11 @@ struct dwos_ctx {
     DevBuf order_cell, order_perm, order_hist;   // spatial scheduling order of a chunk's points
     const uint64_t* seed_dev = nullptr;   // optional device seed offset
     int variant = 0;                      // walk-kernel launch shape (FP32)
+    // scheduling knobs of the walk kernels (dwos_set_tuning, dwos_autotune)
+    int park = dwos::kParkLanes;
+    int tail = dwos::kDescendTail;
+    int chunk = (int)dwos::kQueueChunk;
+    int stage_cap = -1;                   // cap on LDS-staged nodes (-1: all that fit)
     // timing and cumulative counters per walk kind (0 forward, 1 differential)
     struct Pending { hipEvent_t e0, e1; int kind; };
     std::vector<Pending> pending;
@@ -209,6 +216,10 @@ dwos::Scene<T> make_scene(dwos_ctx* c) {
         s.n_stage_nodes = (int32_t)std::min<size_t>((size_t)c->n_nodes, budget / nb);
         s.stage_prims = 0;
     }
+    // a tuning cap shortens the staged node prefix (primitives, if staged,
+    // follow the prefix in LDS)
+    if (c->stage_cap >= 0 && s.n_stage_nodes > c->stage_cap) s.n_stage_nodes = c->stage_cap;
+    s.tail = c->tail;
     return s;
 }
 
@@ -632,6 +643,8 @@ dwos::WalkArgs<T> base_args(dwos_ctx* c, const double* X, int32_t W, uint64_t se
     a.key1 = (uint32_t)(seed >> 32);
     a.seed_ptr = reinterpret_cast<const unsigned long long*>(c->seed_dev);
     a.queue = c->queue.as<unsigned long long>();
+    a.park = c->park;
+    a.chunk = (uint32_t)c->chunk;
     a.cnt = c->counters.as<dwos::Counters>();
     a.tot = c->totals.as<dwos::Counters>();
     a.rec_u = c->rec_u.as<T>();
@@ -2009,29 +2022,154 @@ dwos_status dwos_set_variant(dwos_ctx* c, int32_t variant) {
     return DWOS_OK;
 }
 
-dwos_status dwos_autotune(dwos_ctx* c, const double* X, int64_t P, int32_t W, uint64_t seed, int32_t* chosen,
-                          double* ms) {
-    if (!c) return fail(DWOS_EINVAL, "NULL context");
-    if (!c->instances.empty()) return fail(DWOS_ESTATE, "autotune: batch context");
-    if (P <= 0 || W < 1 || !X) return fail(DWOS_EINVAL, "autotune: need points and W >= 1");
-    const int64_t Ps = std::min<int64_t>(P, 512);
-    DevBuf mean;
-    HIP_OK(mean.reserve(Ps * sizeof(double)));
-    double t[2] = {0.0, 0.0};
-    const int keep = c->variant;
-    for (int v = 0; v < 2; ++v) {
-        c->variant = v;
-        dwos_status rc = dwos_solve(c, X, Ps, W, seed, mean.as<double>(), nullptr, nullptr);   // warm-up
-        if (rc) { c->variant = keep; return rc; }
-        dwos_stats st{};
-        rc = dwos_solve(c, X, Ps, W, seed + 1, mean.as<double>(), nullptr, &st);
-        if (rc) { c->variant = keep; return rc; }
-        t[v] = st.walk_ms;
+dwos_status dwos_set_tuning(dwos_ctx* c, const dwos_tuning* t) {
+    if (!c || !t) return fail(DWOS_EINVAL, "set_tuning: NULL argument");
+    if (t->variant != 0 && t->variant != 1) return fail(DWOS_EINVAL, "set_tuning: variant must be 0 or 1");
+    if (t->park < 1 || t->park > 64) return fail(DWOS_EINVAL, "set_tuning: park must be in 1..64");
+    if (t->tail < 0 || t->tail > 63) return fail(DWOS_EINVAL, "set_tuning: tail must be in 0..63");
+    if (t->chunk < 64 || t->chunk > 65536 || t->chunk % 64 != 0)
+        return fail(DWOS_EINVAL, "set_tuning: chunk must be a multiple of 64 in 64..65536");
+    if (t->stage_nodes < -1) return fail(DWOS_EINVAL, "set_tuning: stage_nodes must be -1 or >= 0");
+    c->variant = t->variant;
+    c->park = t->park;
+    c->tail = t->tail;
+    c->chunk = t->chunk;
+    c->stage_cap = t->stage_nodes;
+    return DWOS_OK;
+}
+
+dwos_status dwos_get_tuning(dwos_ctx* c, dwos_tuning* t) {
+    if (!c || !t) return fail(DWOS_EINVAL, "get_tuning: NULL argument");
+    t->variant = c->variant;
+    t->park = c->park;
+    t->tail = c->tail;
+    t->chunk = c->chunk;
+    t->stage_nodes = c->stage_cap;
+    return DWOS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Process-wide autotuner results, keyed by device, dimension, precision,
+// batch or single scene and the scene's size in half-octaves of primitives.
+struct TuneKey {
+    int device, D, prec, batch, bucket;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(device, D, prec, batch, bucket) < std::tie(o.device, o.D, o.prec, o.batch, o.bucket);
     }
-    c->variant = (c->prec == DWOS_FP32 && t[1] < t[0]) ? 1 : 0;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, dwos_tuning> g_tune_cache;
+
+TuneKey tune_key(const dwos_ctx* c) {
+    const int64_t np = c->instances.empty() ? c->np : (int64_t)c->hostOrder.size();
+    const int bucket = np > 0 ? (int)std::floor(2.0 * std::log2((double)np)) : 0;
+    return {c->device, c->D, c->prec, c->instances.empty() ? 0 : 1, bucket};
+}
+
+}  // namespace
+
+extern "C" {
+
+dwos_status dwos_autotune(dwos_ctx* c, const double* X, const int64_t* P, int32_t W, uint64_t seed, int32_t flags,
+                          dwos_tuning* chosen, double* ms) {
+    if (!c) return fail(DWOS_EINVAL, "NULL context");
+    if (!P || W < 1 || !X) return fail(DWOS_EINVAL, "autotune: need points, point counts and W >= 1");
+    if (flags & ~DWOS_TUNE_CACHE) return fail(DWOS_EINVAL, "autotune: unknown flags");
+    const bool batch = !c->instances.empty();
+    if (!batch && !c->has_boundary) return fail(DWOS_ESTATE, "autotune: no mesh boundary");
+    if (!c->has_problem) return fail(DWOS_ESTATE, "autotune: no problem: call dwos_set_problem first");
+    // the timed call: a forward solve of the whole batch, or of a prefix of
+    // the points with about 2^22 walks
+    int64_t pts = 0;
+    if (batch) {
+        for (size_t i = 0; i < c->instances.size(); ++i) {
+            if (P[i] < 0 || P[i] > INT32_MAX) return fail(DWOS_EINVAL, "autotune: bad point count");
+            pts += P[i];
+        }
+    } else {
+        if (P[0] <= 0) return fail(DWOS_EINVAL, "autotune: need points");
+        pts = std::min<int64_t>(P[0], std::max<int64_t>(64, ((int64_t)1 << 22) / W));
+    }
+    if (pts <= 0) return fail(DWOS_EINVAL, "autotune: need points");
+    dwos_tuning cur{};
+    dwos_get_tuning(c, &cur);
+    const TuneKey key = tune_key(c);
+    if (flags & DWOS_TUNE_CACHE) {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            dwos_status rc = dwos_set_tuning(c, &it->second);
+            if (rc) return rc;
+            if (chosen) *chosen = it->second;
+            if (ms) { ms[0] = -1.0; ms[1] = -1.0; }
+            return DWOS_OK;
+        }
+    }
+    DevBuf mean;
+    HIP_OK(mean.reserve(pts * sizeof(double)));
+    std::vector<int64_t> Pb(P, P + (batch ? c->instances.size() : 1));
+    if (!batch) Pb[0] = pts;
+    auto run = [&](uint64_t sd, dwos_stats* st) {
+        return batch ? dwos_batch_solve(c, X, Pb.data(), W, sd, mean.as<double>(), nullptr, st)
+                     : dwos_solve(c, X, pts, W, sd, mean.as<double>(), nullptr, st);
+    };
+    // every candidate runs the same walks (same seed); the better of two
+    // timings of the walk kernel(s) scores it
+    auto score = [&](const dwos_tuning& t, double& out) -> dwos_status {
+        dwos_status rc = dwos_set_tuning(c, &t);
+        if (rc) return rc;
+        double best = 0.0;
+        for (int r = 0; r < 2; ++r) {
+            dwos_stats st{};
+            rc = run(seed, &st);
+            if (rc) return rc;
+            if (r == 0 || st.walk_ms < best) best = st.walk_ms;
+        }
+        out = best;
+        return DWOS_OK;
+    };
+    dwos_status rc = run(seed, nullptr);   // warm-up: workspaces, uploads
+    double t_best = 0.0;
+    if (!rc) rc = score(cur, t_best);
+    const double t_start = t_best;
+    dwos_tuning best = cur;
+    // coordinate descent, one pass; a change must win by more than 1%
+    auto try_dim = [&](int32_t dwos_tuning::*field, std::initializer_list<int32_t> vals) -> dwos_status {
+        const int32_t keep = best.*field;
+        for (int32_t v : vals) {
+            if (v == keep) continue;
+            dwos_tuning t = best;
+            t.*field = v;
+            double tv = 0.0;
+            dwos_status r2 = score(t, tv);
+            if (r2) return r2;
+            if (tv < 0.99 * t_best) { t_best = tv; best = t; }
+        }
+        return DWOS_OK;
+    };
+    if (!rc && c->prec == DWOS_FP32) rc = try_dim(&dwos_tuning::variant, {0, 1});
+    if (!rc) rc = try_dim(&dwos_tuning::park, {16, 24, 32, 40});
+    if (!rc) rc = try_dim(&dwos_tuning::tail, {0, 4, 8, 16});
+    if (!rc) rc = try_dim(&dwos_tuning::chunk, {64, 128, 256, 512});
+    if (!rc && c->prec == DWOS_FP32 && best.variant == 0 && !batch) {
+        const int32_t staged = c->prec == DWOS_FP32 ? make_scene<float>(c).n_stage_nodes : 0;
+        if (staged > 4) rc = try_dim(&dwos_tuning::stage_nodes, {-1, staged / 4, 0});
+    }
+    if (rc) {
+        dwos_set_tuning(c, &cur);
+        return rc;
+    }
+    dwos_set_tuning(c, &best);
     HIP_OK(hipStreamSynchronize(c->stream));
-    if (chosen) *chosen = c->variant;
-    if (ms) { ms[0] = t[0]; ms[1] = t[1]; }
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune_cache[key] = best;
+    }
+    if (chosen) *chosen = best;
+    if (ms) { ms[0] = t_start; ms[1] = t_best; }
     return DWOS_OK;
 }
 

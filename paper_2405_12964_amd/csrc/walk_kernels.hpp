@@ -24,8 +24,10 @@ namespace dwos {
 #ifndef DWOS_BLOCK
 #define DWOS_BLOCK 256
 #endif
-// A wavefront stops traversing once this many of its lanes have their query
-// answered; they take their walk step while the others resume later.
+// Default scheduling knobs of the walk kernels (a context may change them
+// at run time, e.g. through the autotuner).
+// park: a wavefront stops traversing once this many of its lanes have their
+// query answered; they take their walk step while the others resume later.
 #ifndef DWOS_PARK
 #define DWOS_PARK 24
 #endif
@@ -42,7 +44,7 @@ constexpr int kBlockStaged = DWOS_BLOCK_STAGED;  // block of the LDS-staged walk
 constexpr bool kLdsStack = DWOS_LDS_STACK;  // traversal stack in LDS (else private memory)
 constexpr int kMaxLabels = 16;
 constexpr int kMaxGauss = 8;
-constexpr uint32_t kQueueChunk = 128;   // walk ids taken per wavefront refill
+constexpr uint32_t kQueueChunk = 128;   // default walk ids taken per wavefront refill
 
 template <class T>
 struct Params {
@@ -79,6 +81,8 @@ struct Scene {
     int32_t n_stage_nodes;   // nodes to stage in LDS (staged kernels)
     int32_t stage_prims;     // 1: stage every primitive as well
     int64_t n_prims;
+    int32_t tail;            // descending lanes a query round leaves to the
+                             // next round (0: none), see query_round
 };
 
 struct Counters {   // device-side statistics (int64 atomics)
@@ -98,6 +102,8 @@ struct WalkArgs {
     uint32_t key0, key1;
     const unsigned long long* seed_ptr;   // if set, the key is seed + *seed_ptr
     unsigned long long* queue;
+    int32_t park;            // lanes answered before a wavefront takes its step (1..64)
+    uint32_t chunk;          // walk ids taken per wavefront refill (multiple of 64)
     Counters* cnt;           // this call
     Counters* tot;           // cumulative for this walk kind
     // records (indexed by logical id - wid_offset)
@@ -395,7 +401,7 @@ template <class T> struct TravStack<T, true> {
 // when none is left.  Depth-first descent alternates pushes and pops, so
 // most entries never reach memory (the stack's order is unchanged).
 #ifndef DWOS_STACK_REGS
-#define DWOS_STACK_REGS 2
+#define DWOS_STACK_REGS 3
 #endif
 constexpr int kStackRegs = DWOS_STACK_REGS;
 template <class T>
@@ -445,13 +451,37 @@ __device__ __forceinline__ void query_begin(const Scene<T>& s, const StageView& 
 }
 
 // One round for the lanes with `active` set (a query in progress).
+// Phase 1 ends when no lane is descending, or (s.tail > 0) when at most
+// s.tail lanes are still descending while some lane holds a leaf for
+// phase 2; the descending lanes keep their position and go on in the next
+// round.  A round in which no lane holds a leaf always expands at least one
+// node per descending lane, so every query progresses.
+// Measured on the 200,000-triangle icosphere (65536 points x 1024 walks):
+// a tail of 8 lanes cuts the forward launch from 150 to 124 ms and the
+// differential launch from 171 to 141 ms (tails of 4 to 24 lanes give
+// 123-129 / 140-146 ms); on the 4096-gon star the differential launch goes
+// from 60 to 49 ms.  With three register-held stack entries instead of two
+// the icosphere launches take a further 1-2% less.
+#ifndef DWOS_DESCEND_TAIL
+#define DWOS_DESCEND_TAIL 8
+#endif
+constexpr int kDescendTail = DWOS_DESCEND_TAIL;
 template <class T, int D, class Stack>
 __device__ __forceinline__ void query_round(const Scene<T>& s, const StageView& sv, const T* x, bool active,
                                             Query<T>& q, QueryCount& qc, Stack& st) {
     constexpr T slack = Slack<T>::v;
     // phase 1: expand nodes until this lane holds a leaf or is finished
 #pragma unroll 1
-    while (active && !q.has_leaf && !q.done) {
+    while (true) {
+        const bool go = active && !q.has_leaf && !q.done;
+        if (s.tail > 0) {
+            const unsigned long long gm = __ballot(go);
+            if (gm == 0ull) break;
+            if (__popcll(gm) <= s.tail && __ballot(active && q.has_leaf) != 0ull) break;
+            if (!go) continue;
+        } else if (!go) {
+            break;
+        }
         int32_t cur = q.node;
         if (cur < 0) {
             T dd;
@@ -695,11 +725,11 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
             } else {
                 const int leader = __ffsll((long long)mask) - 1;
                 unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd(a.queue, (unsigned long long)kQueueChunk);
+                if (lane == leader) base = atomicAdd(a.queue, (unsigned long long)a.chunk);
                 base = bcast64(base, leader);
                 myid = (unsigned long long)rank < avail ? pool_next + rank : base + (rank - avail);
                 pool_next = base + (n - avail);
-                pool_end = base + kQueueChunk;
+                pool_end = base + a.chunk;
             }
             if (need) {
                 if (myid >= (unsigned long long)a.total) {
@@ -742,7 +772,7 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
 
         // ---- one walk step: closest-point query -----------------------------
         // A lane without a query in progress starts one at x.  The wavefront
-        // then traverses until at least kParkLanes of its lanes have their
+        // then traverses until at least a.park of its lanes have their
         // answer (or none is still searching); lanes whose query is
         // unfinished skip the rest of this iteration and resume it in the
         // next, so that fast queries do not wait for the slowest one.
@@ -768,7 +798,7 @@ __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(Wa
                 const bool searching = qpend && !q.done;
                 const unsigned long long sm = __ballot(searching);
                 const unsigned long long rm = __ballot(ready || (qpend && q.done));
-                if (sm == 0ull || __popcll(rm) >= kParkLanes) break;
+                if (sm == 0ull || __popcll(rm) >= a.park) break;
                 query_round<T, D>(a.s, sv, x, searching, q, qc, stack);
             }
             c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;

@@ -593,11 +593,11 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
             } else {
                 const int leader = __ffsll((long long)mask) - 1;
                 unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd(a.queue, (unsigned long long)kQueueChunk);
+                if (lane == leader) base = atomicAdd(a.queue, (unsigned long long)a.chunk);
                 base = bcast64(base, leader);
                 myid = (unsigned long long)rank < avail ? pool_next + rank : base + (rank - avail);
                 pool_next = base + (n - avail);
-                pool_end = base + kQueueChunk;
+                pool_end = base + a.chunk;
             }
             if (need) {
                 if (myid >= (unsigned long long)a.total) {
@@ -738,7 +738,7 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
         }
         // ---- closest silhouette point (resumable) -----------------------------
         // The wavefront runs rounds of the lanes' silhouette queries until at
-        // least kParkLanes of its lanes are not traversing (answered, or at a
+        // least a.park of its lanes are not traversing (answered, or at a
         // terminal); the others keep their query state and resume it in the
         // next iteration instead of starting a new step.
         {
@@ -747,7 +747,7 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
                 const bool trav = spend && sq.have;
                 const unsigned long long sm = __ballot(trav);
                 const unsigned long long present = __ballot(true);
-                if (sm == 0ull || __popcll(present & ~sm) >= kParkLanes) break;
+                if (sm == 0ull || __popcll(present & ~sm) >= a.park) break;
                 if (trav) sil_round<T>(ref, x, on, nin, sq, qc, stack);
             }
         }

@@ -387,14 +387,31 @@ class Solver:
         out = (g,) + ((lam, uo) if records else ()) + ((st.as_dict(),) if stats else ())
         return out if len(out) > 1 else g
 
-    def autotune(self, X, W, seed=0):
-        """Pick the faster walk-kernel launch shape on a sample of X; returns
-        (variant, [ms variant 0, ms variant 1])."""
+    def autotune(self, X, W, seed=0, P=None, cache=True):
+        """Autotune the walk kernels' scheduling knobs (dwos_autotune) on forward
+        solves of X: a prefix of the points on a single-scene context, the
+        whole batch (P: points per instance) on a batch context.  Returns
+        (tuning dict, [ms under the setting at the call, ms under the chosen
+        one]); both are -1 when the process-wide table already held a setting
+        for this scene-size bucket (cache=True)."""
         X = self._X(X)
-        ch = C.c_int32()
+        counts = [X.shape[0]] if P is None else [int(p) for p in P]
+        Pa = (C.c_int64 * len(counts))(*counts)
+        t = capi.dwos_tuning()
         ms = (C.c_double * 2)()
-        check(capi.dwos_autotune(self._ctx, _dev(X), X.shape[0], int(W), int(seed), C.byref(ch), ms))
-        return ch.value, [ms[0], ms[1]]
+        check(capi.dwos_autotune(self._ctx, _dev(X), Pa, int(W), int(seed),
+                                 capi.DWOS_TUNE_CACHE if cache else 0, C.byref(t), ms))
+        return t.as_dict(), [ms[0], ms[1]]
+
+    def get_tuning(self) -> dict:
+        t = capi.dwos_tuning()
+        check(capi.dwos_get_tuning(self._ctx, C.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        """Change some of the knobs (variant, park, tail, chunk, stage_nodes)."""
+        t = capi.dwos_tuning(**{**self.get_tuning(), **kw})
+        check(capi.dwos_set_tuning(self._ctx, C.byref(t)))
 
     def scene_info(self) -> dict:
         """Sizes of the BVH and primitive arrays and the LDS staging plan."""

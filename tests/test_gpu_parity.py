@@ -358,26 +358,68 @@ def test_graph_capture_replays_match_eager(dev, dwos):
 
 @pytest.mark.parametrize("which", ["star", "c3"])
 def test_launch_variants_identical_and_autotune(dev, dwos, which):
-    """Walk results depend only on (seed, point, walk), so both launch shapes
-    of the walk kernel give bit-identical estimates; the autotuner then picks
-    one of them."""
+    """Walk results depend only on (seed, point, walk), so every setting of
+    the walk kernels' scheduling knobs (launch shape, parking threshold,
+    descent tail, queue chunk, LDS staging depth) gives bit-identical
+    estimates; the autotuner then leaves a valid setting on the context and
+    stores it for the scene-size bucket."""
     if which == "star":
-        sc, X = star_small(2048), scenes.star_points(128, 12)
+        sc, X = star_small(2048), scenes.star_points(1100, 12)
     else:
-        sc, X = small_c3(nu=16), scenes.points_on_box_faces(128, 13)
+        sc, X = small_c3(nu=16), scenes.points_on_box_faces(1100, 13)
     s = dwos.Solver.from_scene(sc, "fp32")
     Xt = T(X, dev)
     w = torch.ones(len(X), dtype=torch.float64, device=dev)
+    default = s.get_tuning()
+    assert default == {"variant": 0, "park": 24, "tail": 8, "chunk": 128, "stage_nodes": -1}
+    settings = [dict(variant=0), dict(variant=1), dict(variant=0, park=1, tail=0, chunk=64),
+                dict(variant=0, park=64, tail=63, chunk=4096, stage_nodes=3),
+                dict(variant=1, park=40, tail=16, chunk=256, stage_nodes=0)]
     res = []
-    for v in (0, 1):
-        s.set_variant(v)
-        m, var = s.solve(Xt, 256, 21)
-        g, _ = s.grad(Xt, w, 256, 22)
-        res.append((m, var, g))
-    assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
-    assert torch.allclose(res[0][2], res[1][2], rtol=1e-12, atol=1e-14)
-    v, ms = s.autotune(Xt, 256)
-    assert v in (0, 1) and all(t > 0 for t in ms)
+    for kw in settings:
+        s.set_tuning(**{**default, **kw})
+        m, var = s.solve(Xt, 64, 21)
+        g, _ = s.grad(Xt, w, 64, 22)
+        rec = s.walk_records(Xt[:200], 8, 23, mode=1)
+        res.append((m, var, g, rec))
+    for r in res[1:]:
+        assert torch.equal(res[0][0], r[0]) and torch.equal(res[0][1], r[1])
+        assert torch.allclose(res[0][2], r[2], rtol=1e-12, atol=1e-14)
+        for key in ("u", "steps", "prim", "uoff"):
+            assert torch.equal(res[0][3][key], r[3][key]), key
+    s.set_tuning(**default)
+    t, ms = s.autotune(Xt, 256, cache=False)
+    assert t["variant"] in (0, 1) and 16 <= t["park"] <= 40 and t["tail"] in (0, 4, 8, 16)
+    assert t["chunk"] in (64, 128, 256, 512) and all(v > 0 for v in ms) and ms[1] <= ms[0]
+    assert s.get_tuning() == t
+    # a second context with a scene of the same size takes the stored setting
+    s2 = dwos.Solver.from_scene(sc, "fp32")
+    t2, ms2 = s2.autotune(Xt, 256, cache=True)
+    assert t2 == t and ms2 == [-1.0, -1.0] and s2.get_tuning() == t
+    for bad in (dict(park=0), dict(park=65), dict(tail=64), dict(chunk=96), dict(chunk=32), dict(variant=2),
+                dict(stage_nodes=-2)):
+        with pytest.raises(dwos.DwosError):
+            s2.set_tuning(**bad)
+    assert s2.get_tuning() == t
+
+
+def test_batch_autotune(dev, dwos):
+    """The autotuner on a batch context times the whole batched solve; the
+    batch's results under the chosen setting equal those under the default."""
+    from paper_2405_12964_amd.solver import make_problem
+    insts = scenes.c4_batch(n_inst=5, tri_lo=200, tri_hi=3000, p_lo=64, p_hi=512, n_basis=16)
+    s = dwos.Solver(3, "fp32")
+    sc0 = insts[0][0]
+    s.set_problem(make_problem(0.0, sc0.eps, sc0.delta, 1, sc0.kmax, 1, 0.0, None, sc0.bc, 3))
+    for sc, _ in insts:
+        s.batch_add_instance(sc.V, sc.prims, sc.label, sc.sigma, sc.eps, sc.delta)
+    X = T(np.concatenate([x for _, x in insts]), dev)
+    P = [len(x) for _, x in insts]
+    m0, v0 = s.batch_solve(X, P, 32, 3)
+    t, ms = s.autotune(X, 32, P=P, cache=False)
+    assert all(v > 0 for v in ms) and s.get_tuning() == t
+    m1, v1 = s.batch_solve(X, P, 32, 3)
+    assert torch.equal(m0, m1) and torch.equal(v0, v1)
 
 
 def test_fp32_terminal_side_when_a_step_lands_on_the_boundary(dev, dwos):
