@@ -286,9 +286,12 @@ class Oracle:
 
     def silhouette(self, x, on=-1, nin=None, cap=np.inf):
         """Distance from x to the closest silhouette point of the reflecting
-        boundary (x on segment ``on`` with domain side ``nin``, or inside)."""
+        boundary (x on reflecting primitive ``on`` with domain side ``nin``,
+        or inside)."""
         x = np.ascontiguousarray(x, dtype=np.float64)
-        n = np.ascontiguousarray(np.zeros(2) if nin is None else nin, dtype=np.float64)
+        n = np.zeros(3)
+        if nin is not None:
+            n[:len(nin)] = nin
         out = np.zeros(1)
         rc = lib().oracle_silhouette(C.byref(self._s), _ptr(x, C.c_double), int(on),
                                      _ptr(n, C.c_double), float(cap), _ptr(out, C.c_double))
@@ -296,7 +299,7 @@ class Oracle:
         return float(out[0])
 
     def ray(self, x, d, tmax=np.inf, skip=-1):
-        """First reflecting segment hit by x + t d, 0 < t < tmax: (t, seg)."""
+        """First reflecting primitive hit by x + t d, 0 < t < tmax: (t, index)."""
         x = np.ascontiguousarray(x, dtype=np.float64)
         d = np.ascontiguousarray(d, dtype=np.float64)
         out = np.zeros(2)

@@ -60,6 +60,7 @@
 #include <thread>
 #include <vector>
 #include <algorithm>
+#include <array>
 
 extern "C" {
 
@@ -84,16 +85,19 @@ struct oracle_scene {
     const int32_t* pid;      // nnz parameter ids
     const double* vel;       // nnz*dim velocities dv_i/dpi_j
     const int32_t* bc_pid;   // nv parameter id of the mapped value, -1 none (NULL: none)
-    // Reflecting (zero-flux Neumann) part of the boundary, 2D only: segments
-    // over their own vertex array, fixed (independent of the parameters).
-    // n_ns = 0: a Dirichlet-only problem, solved by walk on spheres.
+    // Reflecting (Neumann or Robin) part of the boundary: segments (2D) or
+    // triangles (3D) over their own vertex array, fixed (independent of the
+    // parameters).  n_ns = 0: a Dirichlet-only problem, solved by walk on
+    // spheres.
     int32_t n_nv;
     const double* NV;        // n_nv*dim
     int32_t n_ns;
-    const int32_t* nsegs;    // n_ns*2 vertex indices into NV
-    // per query point: the reflecting segment the point lies on, with the
-    // domain to the left of the segment (from its first to its second
-    // vertex), or -1 for an interior point (NULL: all interior)
+    const int32_t* nsegs;    // n_ns*dim vertex indices into NV
+    // per query point: the reflecting primitive the point lies on, with the
+    // domain on the side of its left normal (2D: to the left of the segment
+    // from its first to its second vertex; 3D: the side that
+    // (b - a) x (c - a) points to, a, b, c its vertices), or -1 for an
+    // interior point (NULL: all interior)
     const int32_t* start_seg;
     // Implicit Dirichlet boundary (2D, Sec. 7.4): the zero set of
     // h(x) = mono_c + sum_n a_n / |x - p_n|, rows (a_n, p_n) of mono, with
@@ -184,6 +188,12 @@ double dot(const double* a, const double* b, int D) {
     double s = 0; for (int i = 0; i < D; ++i) s += a[i] * b[i]; return s;
 }
 
+void cross3(const double* a, const double* b, double* c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
 // closest point on segment a-b to x; returns t in [0,1] with point a + t(b-a)
 double seg_param(const double* x, const double* a, const double* b, int D) {
     double ab[3], ax[3];
@@ -233,12 +243,30 @@ void tri_closest(const double* x, const double* a, const double* b, const double
 struct Scene {
     const oracle_scene& s;
     int D;
-    std::vector<std::vector<int>> ninc;   // reflecting segments incident to each vertex
+    std::vector<std::vector<int>> ninc;   // 2D: reflecting segments incident to each vertex
+    // 3D: the edges of the reflecting triangles, each with its incident
+    // triangles (in increasing index order)
+    struct Edge { int a, b; std::vector<int> f; };
+    std::vector<Edge> edges;
     explicit Scene(const oracle_scene& sc) : s(sc), D(sc.dim) {
-        if (sc.n_ns > 0) {
+        if (sc.n_ns > 0 && D == 2) {
             ninc.assign(sc.n_nv, {});
             for (int i = 0; i < sc.n_ns; ++i)
                 for (int k = 0; k < 2; ++k) ninc[sc.nsegs[2 * i + k]].push_back(i);
+        }
+        if (sc.n_ns > 0 && D == 3) {
+            std::vector<std::array<int, 3>> e;   // (low vertex, high vertex, triangle)
+            for (int i = 0; i < sc.n_ns; ++i)
+                for (int k = 0; k < 3; ++k) {
+                    const int u = sc.nsegs[3 * i + k], v = sc.nsegs[3 * i + (k + 1) % 3];
+                    e.push_back({std::min(u, v), std::max(u, v), i});
+                }
+            std::sort(e.begin(), e.end());
+            for (size_t j = 0; j < e.size(); ++j) {
+                if (j == 0 || e[j][0] != e[j - 1][0] || e[j][1] != e[j - 1][1])
+                    edges.push_back({e[j][0], e[j][1], {}});
+                edges.back().f.push_back(e[j][2]);
+            }
         }
     }
     const double* vert(int i) const { return s.V + (size_t)i * D; }
@@ -479,16 +507,87 @@ struct Scene {
 
     // ----- reflecting boundary (walk on stars) ------------------------------
     bool has_neumann() const { return s.n_ns > 0; }
-    const double* nvert(int i) const { return s.NV + (size_t)i * 2; }
-    int nsv(int seg, int k) const { return s.nsegs[2 * seg + k]; }
+    const double* nvert(int i) const { return s.NV + (size_t)i * D; }
+    int nsv(int seg, int k) const { return s.nsegs[(size_t)D * seg + k]; }
 
-    // Unit normal of a reflecting segment pointing to its left (the domain
-    // side of a start segment).
-    void nleft(int seg, double n[2]) const {
+    // Unit left normal of a reflecting primitive (the domain side of a start
+    // primitive): 2D the segment's tangent turned by +90 degrees, 3D
+    // (b - a) x (c - a) normalised.
+    void nleft(int seg, double n[3]) const {
         const double* a = nvert(nsv(seg, 0));
         const double* b = nvert(nsv(seg, 1));
-        double tx = b[0] - a[0], ty = b[1] - a[1], L = std::sqrt(tx * tx + ty * ty);
-        n[0] = -ty / L; n[1] = tx / L;
+        if (D == 2) {
+            double tx = b[0] - a[0], ty = b[1] - a[1], L = std::sqrt(tx * tx + ty * ty);
+            n[0] = -ty / L; n[1] = tx / L; n[2] = 0;
+            return;
+        }
+        const double* c = nvert(nsv(seg, 2));
+        const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+        const double e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+        double cr[3];
+        cross3(e1, e2, cr);
+        const double L = std::sqrt(dot(cr, cr, 3));
+        for (int i = 0; i < 3; ++i) n[i] = cr[i] / L;
+    }
+
+    // Area of reflecting triangle i (3D).
+    double tri_area(int i) const {
+        const double* a = nvert(nsv(i, 0));
+        const double* b = nvert(nsv(i, 1));
+        const double* c = nvert(nsv(i, 2));
+        const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+        const double e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+        double cr[3];
+        cross3(e1, e2, cr);
+        return 0.5 * std::sqrt(dot(cr, cr, 3));
+    }
+
+    // Is the edge of reflecting triangles (3D) a silhouette as seen from x?
+    // The 3D form of the vertex rule below: seen from x the surface turns
+    // back at the edge when both triangles at it lie on the same side of the
+    // plane through x and the edge.  An edge with one triangle (a rim) or
+    // more than two is always counted.  A triangle seen edge-on (x in its
+    // plane) does not decide: if x lies on reflecting triangle `on` (domain
+    // side `nin`), an edge of `on` is a silhouette when the other triangle
+    // at it leaves to the outside of the plane of `on`; otherwise an edge
+    // whose triangles are both edge-on is not a silhouette (a flat part of
+    // the surface containing x), and one with a single edge-on triangle is
+    // decided by the other triangle's side of the plane of `on` (x on a
+    // wall) or counted (x inside, a null set of points).
+    bool silhouette_edge(const Edge& e, const double* x, int on, const double* nin) const {
+        if (e.f.size() != 2) return true;
+        const double* p = nvert(e.a);
+        const double* q = nvert(e.b);
+        int w[2];
+        for (int k = 0; k < 2; ++k) {
+            w[k] = -1;
+            for (int j = 0; j < 3; ++j) {
+                const int v = nsv(e.f[k], j);
+                if (v != e.a && v != e.b) w[k] = v;
+            }
+        }
+        auto outside = [&](int v) {
+            const double* pw = nvert(v);
+            return nin[0] * (pw[0] - p[0]) + nin[1] * (pw[1] - p[1]) + nin[2] * (pw[2] - p[2]) < 0;
+        };
+        if (on >= 0 && e.f[0] == on) return outside(w[1]);
+        if (on >= 0 && e.f[1] == on) return outside(w[0]);
+        const double t[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]};
+        const double r[3] = {x[0] - p[0], x[1] - p[1], x[2] - p[2]};
+        double m[3];
+        cross3(t, r, m);   // normal of the plane through the edge and x
+        const double lm = std::sqrt(dot(m, m, 3));
+        double c[2];
+        bool zero[2];
+        for (int k = 0; k < 2; ++k) {
+            const double* pw = nvert(w[k]);
+            const double d[3] = {pw[0] - p[0], pw[1] - p[1], pw[2] - p[2]};
+            c[k] = dot(m, d, 3);
+            zero[k] = std::fabs(c[k]) <= 1e-10 * lm * std::sqrt(dot(d, d, 3));
+        }
+        if (zero[0] && zero[1]) return false;
+        if (zero[0] || zero[1]) return on >= 0 ? outside(zero[0] ? w[1] : w[0]) : true;
+        return (c[0] > 0) == (c[1] > 0);
     }
 
     // Is reflecting vertex v a silhouette point as seen from x?  Seen from x,
@@ -527,9 +626,24 @@ struct Scene {
         return (c[0] > 0) == (c[1] > 0);
     }
 
-    // Squared distance from x to its closest silhouette point, capped at cap2.
+    // Squared distance from x to its closest silhouette point, capped at cap2
+    // (3D: the closest point of the silhouette edges).
     double silhouette_d2(const double* x, int on, const double* nin, double cap2) const {
         double best = cap2;
+        if (D == 3) {
+            for (const Edge& e : edges) {
+                const double* p = nvert(e.a);
+                const double* q = nvert(e.b);
+                const double t = seg_param(x, p, q, 3);
+                double d2 = 0;
+                for (int i = 0; i < 3; ++i) {
+                    const double di = p[i] + t * (q[i] - p[i]) - x[i];
+                    d2 += di * di;
+                }
+                if (d2 < best && silhouette_edge(e, x, on, nin)) best = d2;
+            }
+            return best;
+        }
         for (int v = 0; v < s.n_nv; ++v) {
             if (ninc[v].empty()) continue;
             const double* p = nvert(v);
@@ -545,6 +659,33 @@ struct Scene {
     int ray(const double* x, const double* dir, double tmax, int skip, double& t_out) const {
         int hit = -1;
         double best = tmax;
+        if (D == 3) {
+            // Moller-Trumbore: x + t dir = a + u e1 + v e2 with u, v >= 0,
+            // u + v <= 1 (a direction parallel to the triangle misses it)
+            for (int i = 0; i < s.n_ns; ++i) {
+                if (i == skip) continue;
+                const double* a = nvert(nsv(i, 0));
+                const double* b = nvert(nsv(i, 1));
+                const double* c = nvert(nsv(i, 2));
+                const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+                const double e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+                double pv[3];
+                cross3(dir, e2, pv);
+                const double det = dot(e1, pv, 3);
+                if (det == 0.0) continue;
+                const double tv[3] = {x[0] - a[0], x[1] - a[1], x[2] - a[2]};
+                const double u = dot(tv, pv, 3) / det;
+                if (u < 0 || u > 1) continue;
+                double qv[3];
+                cross3(tv, e1, qv);
+                const double v = dot(dir, qv, 3) / det;
+                if (v < 0 || u + v > 1) continue;
+                const double t = dot(e2, qv, 3) / det;
+                if (t > 0 && t < best) { best = t; hit = i; }
+            }
+            t_out = hit >= 0 ? best : tmax;
+            return hit;
+        }
         for (int i = 0; i < s.n_ns; ++i) {
             if (i == skip) continue;
             const double* a = nvert(nsv(i, 0));
@@ -601,9 +742,49 @@ struct Scene {
     // (k, m, p, tag | 8 | i << 16), so the choice does not depend on the
     // order in which segments are visited; the position along the winner's
     // clipped part is word 1 of the same draw.
+    //
+    // 3D: the triangles that reach into the ball B(x, R) (closest point
+    // nearer than R) with their whole areas A_i; L = sum A_i and the race
+    // with weights A_i picks a triangle, z is uniform on it (words 1 and 2
+    // of the winner's draw: with r = sqrt(U1), z = (1 - r) a + r (1 - U2) b
+    // + r U2 c).  A z outside the ball returns -1 (it adds nothing): the
+    // expected value of L 1(z in B) phi(z) is the integral of phi over the
+    // reflecting boundary inside the ball, as with the clipped lengths in
+    // 2D.  branch (3D) gets word 3 of the winner's draw, a uniform word
+    // independent of the choice, for the Robin branch of the step.
     int boundary_sample(const double* x, double R, const Stream& st, uint32_t k, uint32_t extra,
-                        double& L, double z[2]) const {
+                        double& L, double z[3], uint32_t* branch = nullptr) const {
         L = 0.0;
+        if (D == 3) {
+            int win = -1;
+            double best = INFINITY;
+            uint32_t ww[4] = {0, 0, 0, 0};
+            for (int i = 0; i < s.n_ns; ++i) {
+                double bary[3], q[3];
+                tri_closest(x, nvert(nsv(i, 0)), nvert(nsv(i, 1)), nvert(nsv(i, 2)), bary, q);
+                double d2 = 0;
+                for (int j = 0; j < 3; ++j) d2 += (q[j] - x[j]) * (q[j] - x[j]);
+                if (!(d2 < R * R)) continue;
+                const double A = tri_area(i);
+                L += A;
+                uint32_t w[4];
+                st.draw(k, extra | 8u | ((uint32_t)i << 16), w);
+                const double e = -std::log(u24pos(w[0])) / A;
+                if (e < best) { best = e; win = i; for (int j = 0; j < 4; ++j) ww[j] = w[j]; }
+            }
+            if (win < 0) return -1;
+            const double* a = nvert(nsv(win, 0));
+            const double* b = nvert(nsv(win, 1));
+            const double* c = nvert(nsv(win, 2));
+            const double r = std::sqrt(u24(ww[1])), t = u24(ww[2]);
+            double d2 = 0;
+            for (int j = 0; j < 3; ++j) {
+                z[j] = (1 - r) * a[j] + r * (1 - t) * b[j] + r * t * c[j];
+                d2 += (z[j] - x[j]) * (z[j] - x[j]);
+            }
+            if (branch) *branch = ww[3];
+            return d2 < R * R ? win : -1;
+        }
         int win = -1;
         double best = INFINITY, wt0 = 0, wt1 = 0;
         uint32_t wpos = 0;
@@ -1102,17 +1283,20 @@ StarStep star_step(const Scene& sc, double* x, int on, double* nin, double d2, u
     }
     // Robin terms over the reflecting boundary inside the ball
     const double cx = on >= 0 ? 2.0 : 1.0;
-    double z[2] = {0, 0}, L = 0, Gz = 0;
+    double z[3] = {0, 0, 0}, L = 0, Gz = 0;
     int zseg = -1;
+    uint32_t wbranch = w[1];   // 2D: word 1 of the step's draw; 3D: the boundary sample's
     if (sc.has_robin()) {
-        zseg = sc.boundary_sample(x, R, st, k, extra, L, z);
+        zseg = sc.boundary_sample(x, R, st, k, extra, L, z, &wbranch);
         if (zseg >= 0) {
-            Gz = green(D, sc.s.sigma, std::hypot(z[0] - x[0], z[1] - x[1]), R);
+            double r2 = 0;
+            for (int i = 0; i < D; ++i) r2 += (z[i] - x[i]) * (z[i] - x[i]);
+            Gz = green(D, sc.s.sigma, std::sqrt(r2), R);
             acc -= tau * cx * L * Gz * sc.robin_h(z);
         }
     }
     const double q = (mu > 0 && zseg >= 0) ? std::min(0.5, cx * mu * L * Gz) : 0.0;
-    const bool to_z = q > 0 && u24(w[1]) < q;
+    const bool to_z = q > 0 && u24(wbranch) < q;
     const double wgt = to_z ? -cx * mu * L * Gz / q
                             : (seg >= 0 ? neumann_weight(D, sc.s.sigma, t, R) : poisson_scale(D, sc.s.sigma, R)) /
                                   (1 - q);
@@ -1127,11 +1311,11 @@ StarStep star_step(const Scene& sc, double* x, int on, double* nin, double d2, u
     if (to_z) {   // continue on the wall at z; domain side: towards x
         if (zseg != on) {
             sc.nleft(zseg, nin);
-            const double dx[2] = {x[0] - z[0], x[1] - z[1]};
-            if (dot(nin, dx, 2) < 0) for (int i = 0; i < 2; ++i) nin[i] = -nin[i];
+            double dx[3] = {0, 0, 0};
+            for (int i = 0; i < D; ++i) dx[i] = x[i] - z[i];
+            if (dot(nin, dx, D) < 0) for (int i = 0; i < D; ++i) nin[i] = -nin[i];
         }
-        x[0] = z[0];
-        x[1] = z[1];
+        for (int i = 0; i < D; ++i) x[i] = z[i];
         out.on = zseg;
         return out;
     }
@@ -1529,8 +1713,8 @@ int check_scene(const oracle_scene* s) {
     if (!s->rr && s->sigma > 0) return 1;
     if (s->n_ns < 0) return 1;
     if (s->n_ns > 0) {
-        if (s->dim != 2 || !s->NV || !s->nsegs || s->n_nv <= 0) return 1;
-        for (int64_t i = 0; i < 2 * (int64_t)s->n_ns; ++i)
+        if (!s->NV || !s->nsegs || s->n_nv <= 0) return 1;
+        for (int64_t i = 0; i < s->dim * (int64_t)s->n_ns; ++i)
             if (s->nsegs[i] < 0 || s->nsegs[i] >= s->n_nv) return 1;
     }
     // the Robin condition lives on the reflecting boundary; the boundary

@@ -36,6 +36,8 @@ __all__ = [
     "points_in_ball", "vertices_at", "lshape_scene", "half_disk_scene",
     "annulus_reflecting_scene", "points_in_lshape", "points_in_half_disk",
     "points_on_segments", "thermal_scene", "monopole_scene", "inflation_scene",
+    "lprism_scene", "points_in_lprism", "box_wall_scene", "half_ball_scene",
+    "points_in_half_ball", "points_on_triangles",
 ]
 
 
@@ -74,11 +76,13 @@ class Scene:
     V_base: Optional[np.ndarray] = None   # V(pi) = V_base + J pi
     pi0: Optional[np.ndarray] = None      # parameter values giving V
     name: str = ""
-    # reflecting (zero-flux) part of the boundary, 2D: segments over their
-    # own vertices, independent of the parameters; walks start on segment s
-    # with the domain to the left of s (first to second vertex)
-    NV: Optional[np.ndarray] = None       # (n_nv, 2) float64
-    nsegs: Optional[np.ndarray] = None    # (n_ns, 2) int32
+    # reflecting part of the boundary: segments (2D) or triangles (3D) over
+    # their own vertices, independent of the parameters; walks start on
+    # primitive s with the domain on its left normal (2D: left of the
+    # segment from its first to its second vertex; 3D: the side
+    # (b - a) x (c - a) points to)
+    NV: Optional[np.ndarray] = None       # (n_nv, dim) float64
+    nsegs: Optional[np.ndarray] = None    # (n_ns, dim) int32
     # implicit Dirichlet boundary (2D): zero set of
     # h(x) = mono_c + sum_n a_n / |x - p_n|, rows (a_n, p_n); domain h > 0
     mono: Optional[np.ndarray] = None     # (n, 3) float64
@@ -673,6 +677,181 @@ def c4_batch(n_inst: int = 256, seed0: int = 100, tri_lo: float = 1e3,
         X = points_on_box_faces(P, seed0 + i)
         out.append((sc, X))
     return out
+
+
+# --------------------------------------------------------------------------
+# 3D reflecting boundaries (walk on stars)
+# --------------------------------------------------------------------------
+
+def _grid_rect(p0, e1, e2, n1: int, n2: int):
+    """Rectangle p0 + s e1 + t e2 (s, t in [0, 1]) as an n1 x n2 grid of
+    cells, two triangles each, wound so that e1 x e2 is the left normal."""
+    p0, e1, e2 = (np.asarray(a, float) for a in (p0, e1, e2))
+    i, j = np.meshgrid(np.arange(n1 + 1), np.arange(n2 + 1), indexing="ij")
+    V = p0 + (i.reshape(-1, 1) / n1) * e1 + (j.reshape(-1, 1) / n2) * e2
+    idx = lambda a, b: a * (n2 + 1) + b
+    T = []
+    for a in range(n1):
+        for b in range(n2):
+            T.append((idx(a, b), idx(a + 1, b), idx(a + 1, b + 1)))
+            T.append((idx(a, b), idx(a + 1, b + 1), idx(a, b + 1)))
+    return V, np.array(T, np.int32)
+
+
+def _weld(parts, tol: float = 1e-9):
+    """Concatenate (V, T) meshes and merge vertices closer than tol."""
+    V = np.concatenate([v for v, _ in parts])
+    offs = np.cumsum([0] + [len(v) for v, _ in parts])[:-1]
+    T = np.concatenate([t + o for (_, t), o in zip(parts, offs)])
+    key = np.round(V / tol).astype(np.int64)
+    _, first, inv = np.unique(key, axis=0, return_index=True, return_inverse=True)
+    inv = inv.ravel()
+    return V[first], inv[T].astype(np.int32)
+
+
+def lprism_scene(n: int = 8, n_wall: int = 8, H: float = 1.0, sigma: float = 0.0,
+                 eps: float = 1e-4, delta: float = 1e-3, gfun=None) -> Scene:
+    """L-shaped prism: the L-shaped domain [-1,1]^2 minus [0,1]x[-1,0]
+    extruded over z in [-H, H].  The two faces at the re-entrant edge (the z
+    axis) are reflecting walls (n_wall cells per unit, sharing the edge's
+    vertices); the outer faces and the caps z = +-H are Dirichlet (n cells
+    per unit) with mapped vertex values gfun(r, theta), theta in [0, 3 pi/2]
+    from the +x axis (default ``corner_harmonic``: the z-independent solution
+    for sigma = 0).  Wall A is y = 0, x in [0, 1] (domain side +y); wall B is
+    x = 0, y in [-1, 0] (domain side -x); both are wound with the domain on
+    their left normal."""
+    gfun = corner_harmonic if gfun is None else gfun
+    parts = []
+    path = [[1, 0], [1, 1], [-1, 1], [-1, -1], [0, -1]]
+    for a, b in zip(path[:-1], path[1:]):
+        a3, b3 = np.array([a[0], a[1], -H]), np.array([b[0], b[1], -H])
+        L = float(np.hypot(b[0] - a[0], b[1] - a[1]))
+        parts.append(_grid_rect(a3, b3 - a3, [0, 0, 2 * H], max(1, int(round(n * L))),
+                                max(1, int(round(2 * H * n)))))
+    for z in (-H, H):
+        for x0, y0 in ((-1, 0), (0, 0), (-1, -1)):
+            parts.append(_grid_rect([x0, y0, z], [1, 0, 0], [0, 1, 0], n, n))
+    V, T = _weld(parts)
+    th = np.mod(np.arctan2(V[:, 1], V[:, 0]), 2 * np.pi)
+    gv = gfun(np.hypot(V[:, 0], V[:, 1]), th)
+    nz = max(1, int(round(2 * H * n_wall)))
+    wa = _grid_rect([0, 0, -H], [1, 0, 0], [0, 0, 2 * H], n_wall, nz)    # left normal -y
+    wb = _grid_rect([0, -1, -H], [0, 1, 0], [0, 0, 2 * H], n_wall, nz)   # left normal +x
+    wa = (wa[0], wa[1][:, [0, 2, 1]])   # domain y > 0 on the left
+    wb = (wb[0], wb[1][:, [0, 2, 1]])   # domain x < 0 on the left
+    NV, NT = _weld([wa, wb])
+    return Scene(dim=3, V=V, prims=T, label=np.zeros(len(T), np.int32), bc=[_mapped()], gvert=gv,
+                 sigma=sigma, eps=eps, delta=delta, NV=NV, nsegs=NT, name="lprism")
+
+
+def points_in_lprism(P: int, seed: int, lim: float = 0.95, zlim: float = 0.5) -> np.ndarray:
+    """P points uniform in [-lim, lim]^2 x [-zlim, zlim] minus x >= 0, y <= 0."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros((0, 3))
+    while len(out) < P:
+        X = np.concatenate([rng.uniform(-lim, lim, (2 * P, 2)), rng.uniform(-zlim, zlim, (2 * P, 1))], 1)
+        X = X[~((X[:, 0] >= 0) & (X[:, 1] <= 0))]
+        out = np.concatenate([out, X])
+    return out[:P]
+
+
+def box_wall_scene(n_wall: int = 4, sigma: float = 0.0, eps: float = 1e-4, delta: float = 1e-3,
+                   g=None, robin_mu: float = 0.0, robin_h=None) -> Scene:
+    """Cube [-1, 1]^3: the face x = -1 is a reflecting wall (n_wall x n_wall
+    cells, domain side +x), the other five faces are Dirichlet (two triangles
+    each) with the restricted field g (dict of _restricted; default 0)."""
+    Vb, Tb = box_triangles(1.0)
+    c = (Vb[Tb[:, 0]] + Vb[Tb[:, 1]] + Vb[Tb[:, 2]]) / 3
+    keep = ~(c[:, 0] < -0.999)
+    used = np.unique(Tb[keep])
+    remap = -np.ones(len(Vb), np.int64)
+    remap[used] = np.arange(len(used))
+    V, T = Vb[used], remap[Tb[keep]].astype(np.int32)
+    NV, NT = _grid_rect([-1, -1, -1], [0, 2, 0], [0, 0, 2], n_wall, n_wall)   # left normal +x
+    return Scene(dim=3, V=V, prims=T, label=np.zeros(len(T), np.int32),
+                 bc=[g if g is not None else _restricted(0.0, dim=3)], gvert=np.zeros(len(V)),
+                 sigma=sigma, eps=eps, delta=delta, NV=NV, nsegs=NT, robin_mu=robin_mu,
+                 robin_h=robin_h, name="box_wall")
+
+
+def half_ball_scene(n_az: int = 48, n_pol: int = 12, n_rad: int = 12, R: float = 1.0,
+                    sigma: float = 0.0, g: str = "one", eps: float = 1e-3, delta: float = 1e-2,
+                    K: int = 1) -> Scene:
+    """Upper half (y > 0) of the ball of radius R: a Dirichlet hemisphere
+    (latitude-longitude mesh, n_pol rings from the pole to the equator,
+    n_az vertices per ring) and a reflecting flat disk y = 0 (n_rad rings
+    sharing the equator's n_az vertices), domain side +y.  Data restricted:
+    1 (``g='one'``) or x^2 - z^2 (``g='x2-z2'``), both even in y, so the
+    solution is the full ball's.  One parameter pi = R with dv/dR = v/R on
+    the hemisphere; the disk is fixed (its motion is tangential)."""
+    az = 2 * np.pi * np.arange(n_az) / n_az
+    pts = [[0.0, 1.0, 0.0]]
+    for j in range(1, n_pol + 1):
+        ph = 0.5 * np.pi * j / n_pol
+        pts += [[np.sin(ph) * np.cos(a), np.cos(ph), np.sin(ph) * np.sin(a)] for a in az]
+    U = np.array(pts)
+    ring = lambda j, k: 1 + (j - 1) * n_az + (k % n_az)
+    T = []
+    for k in range(n_az):
+        T.append((0, ring(1, k + 1), ring(1, k)))
+    for j in range(1, n_pol):
+        for k in range(n_az):
+            T.append((ring(j, k), ring(j, k + 1), ring(j + 1, k + 1)))
+            T.append((ring(j, k), ring(j + 1, k + 1), ring(j + 1, k)))
+    T = np.array(T, np.int32)
+    a, b, c = U[T[:, 0]], U[T[:, 1]], U[T[:, 2]]
+    flip = np.einsum("ij,ij->i", np.cross(b - a, c - a), a + b + c) < 0
+    T[flip] = T[flip][:, [0, 2, 1]]
+    dpts = [[0.0, 0.0, 0.0]]
+    for i in range(1, n_rad + 1):
+        rho = R * i / n_rad
+        dpts += [[rho * np.cos(a_), 0.0, rho * np.sin(a_)] for a_ in az]
+    NV = np.array(dpts)
+    dring = lambda i, k: 1 + (i - 1) * n_az + (k % n_az)
+    NT = []
+    for k in range(n_az):
+        NT.append((0, dring(1, k), dring(1, k + 1)))
+    for i in range(1, n_rad):
+        for k in range(n_az):
+            NT.append((dring(i, k), dring(i + 1, k), dring(i + 1, k + 1)))
+            NT.append((dring(i, k), dring(i + 1, k + 1), dring(i, k + 1)))
+    NT = np.array(NT, np.int32)
+    e1 = NV[NT[:, 1]] - NV[NT[:, 0]]
+    e2 = NV[NT[:, 2]] - NV[NT[:, 0]]
+    up = np.cross(e1, e2)[:, 1] < 0
+    NT[up] = NT[up][:, [0, 2, 1]]   # left normal +y (the domain side)
+    fld = {"one": _restricted(1.0, dim=3),
+           "x2-z2": _restricted(0.0, None, np.diag([1.0, 0.0, -1.0]), 3)}[g]
+    n = len(U)
+    return Scene(dim=3, V=R * U, prims=T, label=np.zeros(len(T), np.int32), bc=[fld],
+                 gvert=np.zeros(n), sigma=sigma, eps=eps, delta=delta, K=K, N=1,
+                 rowptr=np.arange(n + 1, dtype=np.int64), pid=np.zeros(n, np.int32), vel=U.copy(),
+                 V_base=np.zeros_like(U), pi0=np.array([R]), NV=NV, nsegs=NT, name="half_ball")
+
+
+def points_in_half_ball(P: int, seed: int, rmax: float = 0.8, ymin: float = 0.0) -> np.ndarray:
+    """P points uniform in the half ball r < rmax, y > ymin."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros((0, 3))
+    while len(out) < P:
+        X = rng.uniform(-rmax, rmax, (4 * P, 3))
+        X = X[(np.linalg.norm(X, axis=1) < rmax) & (X[:, 1] > ymin)]
+        out = np.concatenate([out, X])
+    return out[:P]
+
+
+def points_on_triangles(NV: np.ndarray, ntris: np.ndarray, P: int, seed: int, tris=None):
+    """P points on reflecting triangles (a uniform triangle from ``tris`` or
+    all, barycentrics uniform on the triangle shrunk by 10% about its
+    centroid): returns (X, start triangle)."""
+    rng = np.random.default_rng(seed)
+    pool = np.arange(len(ntris)) if tris is None else np.asarray(tris)
+    s = pool[rng.integers(0, len(pool), P)]
+    r1, r2 = np.sqrt(rng.random(P))[:, None], rng.random(P)[:, None]
+    a, b, c = NV[ntris[s, 0]], NV[ntris[s, 1]], NV[ntris[s, 2]]
+    X = (1 - r1) * a + r1 * (1 - r2) * b + r1 * r2 * c
+    cen = (a + b + c) / 3
+    return cen + 0.9 * (X - cen), s.astype(np.int32)
 
 
 # ---------------------------------------------------------------------------
