@@ -549,78 +549,94 @@ dwos_status dwos_cv_walk_records(dwos_ctx* ctx, const double* X, int64_t P, int3
                                  double* walk, double* nested);
 
 /* ---------------------------------------------------------------------------
- * Reflecting (zero-flux) boundaries: walk on stars.
+ * Reflecting boundaries: walk on stars.
  *
- * The mixed problem of Sec. 3.4, eq. (mixed_bvp), with Robin coefficient 0
- * and Robin data 0: du/dn = 0 on a fixed part of the boundary that does not
- * depend on the parameters, the Dirichlet data g elsewhere.  Its parameter
- * derivative (Sec. 4.4, eq. (mixed_bvp_deriv)) nests through the Dirichlet
- * boundary only.  The paper takes the estimator from the walk-on-stars
- * papers it cites; each step uses the star radius R = min(distance to the
- * Dirichlet boundary, distance to the closest silhouette vertex of the
- * reflecting boundary, at least 16 units of rounding of the position), a
- * uniform direction (at a reflecting boundary point: uniform over the
- * directions entering the domain), and the first reflecting point hit along
- * it before R as the next point, weighted by the
+ * The mixed problem of Sec. 3.4, eq. (mixed_bvp): the Neumann or Robin
+ * condition (dwos_set_robin; zero flux by default) on a fixed part of the
+ * boundary that does not depend on the parameters, the Dirichlet data g
+ * elsewhere.  Its parameter derivative (Sec. 4.4, eq. (mixed_bvp_deriv))
+ * nests through the Dirichlet boundary only.  The paper takes the estimator
+ * from the walk-on-stars papers it cites; each step uses the star radius
+ * R = min(distance to the Dirichlet boundary, distance to the closest
+ * silhouette point of the reflecting boundary -- a vertex of the 2D
+ * polyline, an edge of the 3D triangle mesh --, at least 16 units of
+ * rounding of the position), a uniform direction (at a reflecting boundary
+ * point: uniform over the directions entering the domain), and the first
+ * reflecting point hit along it before R as the next point, weighted by the
  * ratio of the ball's Poisson kernel there to the direction density
  * (dwos_eval_reflect_weight); the source is sampled along the same
  * direction and counted inside the visible region.  One Philox draw per
- * step: word 0 the direction, word 2 the roulette, word 3 the source radius.
- * Every solve / grad / jvp / records call then runs walks on stars; the
- * control variate and batch contexts are not available with a reflecting
- * boundary (ESTATE).
+ * step: word 0 (2D) or words 0 and 1 (3D) the direction, word 2 the
+ * roulette, word 3 the source radius.  Every solve / grad / jvp / records
+ * call then runs walks on stars; the control variate and batch contexts are
+ * not available with a reflecting boundary (ESTATE).
  * ------------------------------------------------------------------------- */
 
-/* Reflecting boundary as ns segments (host, ns x 2 vertex indices) over nv
- * vertices (host, nv x 2, FP64) of its own; ns = 0 removes it.  Every
- * segment must have the domain on its left (from its first to its second
- * vertex): closed outer walls counter-clockwise, obstacles clockwise.  The
- * walls are one-way: a walk meets a wall only from its domain side, so a
- * walk that rounding puts just behind a wall passes back into the domain
+/* Reflecting boundary as ns primitives (host, ns x dim vertex indices) over
+ * nv vertices (host, nv x dim, FP64) of its own; ns = 0 removes it.
+ * 2D: segments, each with the domain on its left (from its first to its
+ * second vertex): closed outer walls counter-clockwise, obstacles clockwise.
+ * Segments meeting at a shared vertex index are adjacent; a vertex with one
+ * segment (an open end) or with more than two always counts as a
+ * silhouette.  Builds a BVH over the segments.
+ * 3D: triangles a, b, c, each with the domain on the side its left normal
+ * (b - a) x (c - a) points to.  Triangles sharing two vertex indices share
+ * an edge; seen from x an edge of two triangles is a silhouette when both
+ * lie on the same side of the plane through x and the edge, and an edge of
+ * one triangle (a rim) or of more than two always is.  Builds a BVH over the
+ * triangles (ray hits, Robin samples) and one over the edges (silhouettes).
+ * The walls are one-way: a walk meets a wall only from its domain side, so
+ * a walk that rounding puts just behind a wall passes back into the domain
  * (in exact arithmetic this is the same as taking the side a walk arrives
- * from).  Segments meeting at a shared vertex index are adjacent; a vertex
- * with one segment (an open end) or with more than two always counts as a
- * silhouette.  Builds a BVH over the segments.  2D only.
- * Errors: EINVAL (3D, index out of range, zero-length segment, non-finite
- * coordinate), ESTATE (batch context), ENOMEM. */
+ * from).  Errors: EINVAL (index out of range, zero-length segment or
+ * zero-area triangle, non-finite coordinate, more than 65536 primitives with
+ * a Robin condition set), ESTATE (batch or implicit-boundary context),
+ * ENOMEM. */
 dwos_status dwos_set_reflecting(dwos_ctx* ctx, const double* V, int64_t nv, const int32_t* segs, int64_t ns);
 
 /* Robin condition on the reflecting boundary (Sec. 3.4, eq. (mixed_bvp)):
  *   du/dn - mu u = h    with n the unit normal pointing into the domain,
  * mu >= 0 a constant and h (host struct, NULL: h = 0) a restricted field
- * h(x) = c + b.x + x^T A x (kind 0; A row-major 3 x 3, the top-left 2 x 2
- * used).  mu = 0 and h = NULL restore the zero-flux boundary.  Neither may
+ * h(x) = c + b.x + x^T A x (kind 0; A row-major 3 x 3, the top-left
+ * dim x dim used).  mu = 0 and h = NULL restore the zero-flux boundary.  Neither may
  * depend on the parameters.  The differential walks (Sec. 4.4,
  * eq. (mixed_bvp_deriv)) keep mu with zero data and nest through the
  * Dirichlet boundary only.  Each walk-on-stars step then also estimates the
  * boundary terms -int G (mu u + h) of the star-shaped region's integral
- * equation over the reflecting boundary inside its ball: a point z uniform
- * by length there (the segment chosen by an exponential race in which
- * reflecting segment o draws Philox counter (k, m, p, tag | 8 | o << 16)),
- * the data term added directly and the mu term by continuing the walk at z
- * with probability q = min(1/2, c mu L G) (c = 2 on a wall, 1 inside; L the
- * reflecting length in the ball; word 1 of the step's draw decides), with
- * the walk's throughput carrying the weights' signs and sizes; with mu > 0
- * the star radius is also capped at 1/mu.  Errors: EINVAL (mu < 0 or not
- * finite, h not kind 0 or not finite, more than 65536 reflecting segments),
- * ESTATE (no reflecting boundary when mu > 0 or h != NULL). */
+ * equation over the reflecting boundary inside its ball.  2D: a point z
+ * uniform by length there (the segment chosen by an exponential race in
+ * which reflecting segment o draws Philox counter (k, m, p, tag | 8 |
+ * o << 16) and weighs in with its clipped length; L the reflecting length in
+ * the ball; word 1 of the step's draw decides the branch below).  3D: the
+ * triangles that reach into the ball with their whole areas (L their sum),
+ * the same race with areas as weights, z uniform on the winner (words 1 and
+ * 2 of its draw) and counted only inside the ball; word 3 of the winner's
+ * draw decides the branch.  The data term is added directly and the mu term
+ * by continuing the walk at z with probability q = min(1/2, c mu L G) (c = 2
+ * on a wall, 1 inside), with the walk's throughput carrying the weights'
+ * signs and sizes; with mu > 0 the star radius is also capped at 1/mu.
+ * Errors: EINVAL (mu < 0 or not finite, h not kind 0 or not finite, more
+ * than 65536 reflecting primitives), ESTATE (no reflecting boundary when
+ * mu > 0 or h != NULL). */
 dwos_status dwos_set_robin(dwos_ctx* ctx, double mu, const dwos_bc* h);
 
 /* Query points that lie on the reflecting boundary (host, P entries: the
- * segment index a point lies on, with the domain to the left of the segment
- * from its first to its second vertex, or -1 for a point inside).  Applies
+ * reflecting primitive a point lies on -- its domain side being the
+ * primitive's left, as for dwos_set_reflecting --, or -1 for a point
+ * inside).  Applies
  * to every later call, which must then have exactly P points; seg = NULL or
  * P = 0 clears it.  Errors: EINVAL (index out of range), ESTATE (no
  * reflecting boundary). */
 dwos_status dwos_set_start_segments(dwos_ctx* ctx, const int32_t* seg, int64_t P);
 
 /* The two reflecting-boundary queries of a walk-on-stars step at n rows
- * (device arrays): X (n x 2), dir (n x 2, unit), cap (n), on (n, int32:
- * segment the point lies on or -1), nin (n x 2: domain side when on >= 0).
- * out (n x 3): distance to the closest silhouette vertex (capped at cap), t
- * of the first reflecting segment hit by X + t dir with 0 < t < cap (cap if
- * none), that segment or -1.  A row with an invalid `on` gets NaN.
- * Errors: ESTATE (no reflecting boundary), EINVAL. */
+ * (device arrays, dim = the context's dimension): X (n x dim), dir (n x dim,
+ * unit), cap (n), on (n, int32: primitive the point lies on or -1), nin
+ * (n x dim: domain side when on >= 0).  out (n x 3): distance to the
+ * closest silhouette point (vertex in 2D, edge in 3D; capped at cap), t of
+ * the first reflecting primitive entered from its domain side by X + t dir
+ * with 0 <= t < cap (cap if none), that primitive or -1.  A row with an
+ * invalid `on` gets NaN.  Errors: ESTATE (no reflecting boundary), EINVAL. */
 dwos_status dwos_reflect_query(dwos_ctx* ctx, const double* X, const double* dir, const double* cap,
                                const int32_t* on, const double* nin, int64_t n, double* out);
 

@@ -21,6 +21,7 @@
 #include "mlp.hpp"
 #include "bvh.hpp"
 #include "wost_kernels.hpp"
+#include "wost3_kernels.hpp"
 #include "implicit_kernels.hpp"
 #include "adjoint_kernels.hpp"
 
@@ -150,9 +151,14 @@ struct dwos_ctx {
     DevBuf start_seg;             // per query point: reflecting segment or -1
     int64_t start_n = 0;          // points covered by start_seg (0: none)
     // Robin condition on the reflecting boundary (mu, data h as c, b, A)
+    // 3D reflecting mesh: ref_nodes / ref_geo / ref_leaf_of hold its triangle
+    // BVH, ref_torig the leaf -> original triangle map; its edges have a BVH
+    // of their own
+    DevBuf ref_torig, ref_enodes, ref_egeo, ref_einfo;
+    int64_t ref_ne = 0, ref_enn = 0;
     bool robin = false;
     double robin_mu = 0.0;
-    double robin_hq[7] = {0, 0, 0, 0, 0, 0, 0};
+    double robin_hq[13] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // c, b[3], A[9] (row major)
     DevBuf rec_w;                 // per differential walk: throughput at the terminal
     // implicit boundary (2D): zero set of c + sum_n a_n / |x - p_n|
     bool has_imp = false;
@@ -366,7 +372,115 @@ dwos::RefScene<T> make_ref(dwos_ctx* c) {
     r.n = c->ref_n;
     r.robin = c->robin ? 1 : 0;
     r.mu = T(c->robin_mu);
-    for (int i = 0; i < 7; ++i) r.hq[i] = T(c->robin_hq[i]);
+    // 2D: c, b0, b1, A00, A01, A10, A11
+    const int pick[7] = {0, 1, 2, 4, 5, 7, 8};
+    for (int i = 0; i < 7; ++i) r.hq[i] = T(c->robin_hq[pick[i]]);
+    return r;
+}
+
+// Reflecting triangles (3D): the triangle BVH with each leaf's vertices,
+// and the edge BVH with each edge's vertices, the third vertices of its
+// (first two) triangles and their leaf positions (layout of
+// wost3_kernels.hpp's RefScene3).
+template <class T>
+dwos_status upload_reflecting3(dwos_ctx* c, const double* V, const int32_t* tris, int64_t nt,
+                               const dwos::HostBVH& tb) {
+    std::vector<T> tnodes = pack_nodes<T>(3, tb.nodes);
+    std::vector<int32_t> leaf_of(nt), torig(nt);
+    for (int64_t i = 0; i < nt; ++i) {
+        leaf_of[tb.order[i]] = (int32_t)i;
+        torig[i] = tb.order[i];
+    }
+    std::vector<T> tgeo((size_t)nt * dwos::kTriGeo, T(0));
+    for (int64_t lp = 0; lp < nt; ++lp) {
+        const int32_t o = tb.order[lp];
+        for (int k = 0; k < 3; ++k)
+            for (int cc = 0; cc < 3; ++cc) tgeo[(size_t)lp * dwos::kTriGeo + 3 * k + cc] = T(V[3 * (size_t)tris[3 * o + k] + cc]);
+    }
+    // edges: sorted (low vertex, high vertex, triangle) triples, grouped
+    struct E { int32_t a, b, f; };
+    std::vector<E> es;
+    es.reserve(3 * (size_t)nt);
+    for (int64_t i = 0; i < nt; ++i)
+        for (int k = 0; k < 3; ++k) {
+            const int32_t u = tris[3 * i + k], v = tris[3 * i + (k + 1) % 3];
+            es.push_back({std::min(u, v), std::max(u, v), (int32_t)i});
+        }
+    std::sort(es.begin(), es.end(), [](const E& x, const E& y) {
+        return x.a != y.a ? x.a < y.a : (x.b != y.b ? x.b < y.b : x.f < y.f);
+    });
+    struct Edge { int32_t a, b, f0, f1, nf; };
+    std::vector<Edge> edges;
+    for (size_t j = 0; j < es.size(); ++j) {
+        if (j == 0 || es[j].a != es[j - 1].a || es[j].b != es[j - 1].b) edges.push_back({es[j].a, es[j].b, es[j].f, -1, 0});
+        Edge& e = edges.back();
+        if (e.nf == 1) e.f1 = es[j].f;
+        e.nf++;
+    }
+    const int64_t ne = (int64_t)edges.size();
+    if (ne > (int64_t(1) << 27)) return fail(DWOS_EINVAL, "set_reflecting: too many edges");
+    std::vector<int32_t> eprims(3 * (size_t)ne);
+    for (int64_t i = 0; i < ne; ++i) {
+        eprims[3 * i] = edges[i].a;
+        eprims[3 * i + 1] = edges[i].b;
+        eprims[3 * i + 2] = edges[i].b;
+    }
+    dwos::HostBVH eb = dwos::build_bvh(V, eprims.data(), ne, 3);
+    if (eb.max_depth >= dwos::kMaxDepth) return fail(DWOS_EINVAL, "set_reflecting: edge BVH too deep");
+    dwos::reorder_bfs(eb);
+    std::vector<T> enodes = pack_nodes<T>(3, eb.nodes);
+    std::vector<T> egeo((size_t)ne * dwos::kEdgeGeo, T(0));
+    std::vector<int32_t> einfo((size_t)ne * 4, -1);
+    auto third = [&](int32_t f, int32_t a, int32_t b) {
+        for (int k = 0; k < 3; ++k) {
+            const int32_t v = tris[3 * (size_t)f + k];
+            if (v != a && v != b) return v;
+        }
+        return tris[3 * (size_t)f];
+    };
+    for (int64_t lp = 0; lp < ne; ++lp) {
+        const Edge& e = edges[eb.order[lp]];
+        T* g = &egeo[(size_t)lp * dwos::kEdgeGeo];
+        const int32_t w0 = third(e.f0, e.a, e.b), w1 = e.nf >= 2 ? third(e.f1, e.a, e.b) : w0;
+        const int32_t vs[4] = {e.a, e.b, w0, w1};
+        for (int k = 0; k < 4; ++k)
+            for (int cc = 0; cc < 3; ++cc) g[3 * k + cc] = T(V[3 * (size_t)vs[k] + cc]);
+        int32_t* f = &einfo[(size_t)lp * 4];
+        f[0] = e.nf != 2 ? 1 : 0;
+        f[1] = leaf_of[e.f0];
+        f[2] = e.nf >= 2 ? leaf_of[e.f1] : -1;
+        f[3] = eb.order[lp];
+    }
+    hipStream_t s = c->stream;
+    HIP_OK(upload(c->ref_nodes, tnodes.data(), tnodes.size(), s));
+    HIP_OK(upload(c->ref_geo, tgeo.data(), tgeo.size(), s));
+    HIP_OK(upload(c->ref_leaf_of, leaf_of.data(), leaf_of.size(), s));
+    HIP_OK(upload(c->ref_torig, torig.data(), torig.size(), s));
+    HIP_OK(upload(c->ref_enodes, enodes.data(), enodes.size(), s));
+    HIP_OK(upload(c->ref_egeo, egeo.data(), egeo.size(), s));
+    HIP_OK(upload(c->ref_einfo, einfo.data(), einfo.size(), s));
+    c->ref_n = nt;
+    c->ref_nn = (int64_t)tb.nodes.size();
+    c->ref_ne = ne;
+    c->ref_enn = (int64_t)eb.nodes.size();
+    return DWOS_OK;
+}
+
+template <class T>
+dwos::RefScene3<T> make_ref3(dwos_ctx* c) {
+    dwos::RefScene3<T> r{};
+    r.tnodes = c->ref_nodes.as<T>();
+    r.tgeo = c->ref_geo.as<T>();
+    r.torig = c->ref_torig.as<int32_t>();
+    r.tleaf_of = c->ref_leaf_of.as<int32_t>();
+    r.nt = c->ref_n;
+    r.enodes = c->ref_enodes.as<T>();
+    r.egeo = c->ref_egeo.as<T>();
+    r.einfo = c->ref_einfo.as<int4>();
+    r.ne = c->ref_ne;
+    r.robin = c->robin ? 1 : 0;
+    r.mu = T(c->robin_mu);
+    for (int i = 0; i < 13; ++i) r.hq[i] = T(c->robin_hq[i]);
     return r;
 }
 
@@ -577,6 +691,60 @@ dwos_status launch_wost(dwos_ctx* c, dwos::WalkArgs<T>& a0) {
     const int64_t need = (a.total + block - 1) / block;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)occ_per_cu * c->cu_count));
     const int32_t* starts = c->start_n > 0 ? c->start_seg.as<int32_t>() : nullptr;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_OK(hipStreamIsCapturing(s, &cap));
+    if (cap != hipStreamCaptureStatusNone) {
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, a, ref, starts);
+        HIP_OK(hipGetLastError());
+        return DWOS_OK;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    HIP_OK(hipEventRecord(e0, s));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, a, ref, starts);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipEventRecord(e1, s));
+    c->pending.push_back({e0, e1, MODE});
+    if (c->pending.size() > 4096) {
+        dwos_status st = drain_events(c, nullptr, c->pending.size());
+        if (st) return st;
+    }
+    return DWOS_OK;
+}
+
+// Launch the persistent walk-on-stars kernel (3D reflecting mesh).
+template <class T, int MODE>
+dwos_status launch_wost3(dwos_ctx* c, dwos::WalkArgs<T>& a0) {
+    hipStream_t s = c->stream;
+    dwos::WalkArgs<T> a = a0;
+    a.tot = c->totals.as<dwos::Counters>() + MODE;
+    hipLaunchKernelGGL(dwos::fill_u64_kernel, dim3(1), dim3(64), 0, s, a.queue, (int64_t)1);
+    constexpr int block = dwos::kBlock;
+    auto kern = dwos::wost3_kernel<T, MODE>;
+    size_t lds = 0;
+    if constexpr (sizeof(T) == 4) {
+        // LDS per block: up to 256 Dirichlet nodes, its primitives up to 16 KB
+        a.s.n_stage_nodes = (int32_t)std::min<int64_t>(c->n_nodes, 256);
+        a.s.stage_prims = c->np * (int64_t)(dwos::prim_scalars(3) * sizeof(T)) <= 16384 ? 1 : 0;
+        lds = (size_t)a.s.n_stage_nodes * dwos::node_scalars(3) * sizeof(T) +
+              (a.s.stage_prims ? (size_t)c->np * dwos::prim_scalars(3) * sizeof(T) : 0);
+    } else {
+        a.s.n_stage_nodes = 0;
+        a.s.stage_prims = 0;
+    }
+    static size_t occ_lds = ~size_t(0);
+    static int occ_per_cu = 1;
+    if (occ_lds != lds) {
+        int per = 0;
+        HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, block, lds));
+        occ_per_cu = std::max(1, per);
+        occ_lds = lds;
+    }
+    const int64_t need = (a.total + block - 1) / block;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)occ_per_cu * c->cu_count));
+    const int32_t* starts = c->start_n > 0 ? c->start_seg.as<int32_t>() : nullptr;
+    const dwos::RefScene3<T> ref = make_ref3<T>(c);
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     HIP_OK(hipStreamIsCapturing(s, &cap));
     if (cap != hipStreamCaptureStatusNone) {
@@ -937,7 +1105,8 @@ dwos_status run_op(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
             else if (bvc) rc = launch_walks<T, D, 2>(c, a);
             else rc = diff ? launch_walks<T, D, 1>(c, a) : launch_walks<T, D, 0>(c, a);
         } else {
-            if (bvc) rc = launch_walks<T, D, 2>(c, a);
+            if (c->has_ref) rc = diff ? launch_wost3<T, 1>(c, a) : launch_wost3<T, 0>(c, a);
+            else if (bvc) rc = launch_walks<T, D, 2>(c, a);
             else rc = diff ? launch_walks<T, D, 1>(c, a) : launch_walks<T, D, 0>(c, a);
         }
         if (rc) return rc;
@@ -1825,13 +1994,23 @@ dwos_status dwos_set_reflecting(dwos_ctx* c, const double* V, int64_t nv, const 
         c->ref_n = 0;
         return DWOS_OK;
     }
-    if (c->D != 2) return fail(DWOS_EINVAL, "set_reflecting: reflecting boundaries are supported in 2D only");
     if (c->robin && ns > 65536)
-        return fail(DWOS_EINVAL, "set_reflecting: a Robin condition allows at most 65536 reflecting segments");
+        return fail(DWOS_EINVAL, "set_reflecting: a Robin condition allows at most 65536 reflecting primitives");
     if (!c->instances.empty()) return fail(DWOS_ESTATE, "set_reflecting: context is a batch context");
     if (c->has_imp) return fail(DWOS_ESTATE, "set_reflecting: context has an implicit boundary");
-    dwos_status rc = check_geometry(2, V, nv, segs, ns, nullptr, 1);
+    dwos_status rc = check_geometry(c->D, V, nv, segs, ns, nullptr, 1);
     if (rc) return fail(rc, "set_reflecting: " + dwos_host::g_last_error.substr(std::min<size_t>(14, dwos_host::g_last_error.size())));
+    if (c->D == 3) {
+        HIP_OK(hipSetDevice(c->device));
+        dwos::HostBVH tb = dwos::build_bvh(V, segs, ns, 3);
+        if (tb.max_depth >= dwos::kMaxDepth) return fail(DWOS_EINVAL, "set_reflecting: BVH too deep");
+        dwos::reorder_bfs(tb);
+        rc = c->prec == DWOS_FP32 ? upload_reflecting3<float>(c, V, segs, ns, tb)
+                                  : upload_reflecting3<double>(c, V, segs, ns, tb);
+        if (rc) return rc;
+        c->has_ref = true;
+        return DWOS_OK;
+    }
     std::vector<std::vector<int32_t>> inc(nv);
     for (int64_t i = 0; i < ns; ++i)
         for (int e = 0; e < 2; ++e) inc[segs[2 * i + e]].push_back((int32_t)i);
@@ -1849,26 +2028,23 @@ dwos_status dwos_set_reflecting(dwos_ctx* c, const double* V, int64_t nv, const 
 dwos_status dwos_set_robin(dwos_ctx* c, double mu, const dwos_bc* h) {
     if (!c) return fail(DWOS_EINVAL, "NULL context");
     if (!(mu >= 0) || !std::isfinite(mu)) return fail(DWOS_EINVAL, "set_robin: mu must be finite and >= 0");
-    double hq[7] = {0, 0, 0, 0, 0, 0, 0};
+    double hq[13] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (h) {
         if (h->kind != 0) return fail(DWOS_EINVAL, "set_robin: the Robin data must be a restricted field (kind 0)");
         hq[0] = h->c;
-        hq[1] = h->b[0];
-        hq[2] = h->b[1];
-        hq[3] = h->A[0];
-        hq[4] = h->A[1];
-        hq[5] = h->A[3];
-        hq[6] = h->A[4];
+        for (int i = 0; i < 3; ++i) hq[1 + i] = h->b[i];
+        // A: 3 x 3 row major, the top-left D x D block used
+        for (int i = 0; i < 9; ++i) hq[4 + i] = h->A[i];
         for (double v : hq)
             if (!std::isfinite(v)) return fail(DWOS_EINVAL, "set_robin: non-finite Robin data");
     }
     const bool on = mu > 0 || h != nullptr;
     if (on && !c->has_ref) return fail(DWOS_ESTATE, "set_robin: no reflecting boundary");
     if (on && c->ref_n > 65536)
-        return fail(DWOS_EINVAL, "set_robin: a Robin condition allows at most 65536 reflecting segments");
+        return fail(DWOS_EINVAL, "set_robin: a Robin condition allows at most 65536 reflecting primitives");
     c->robin = on;
     c->robin_mu = mu;
-    for (int i = 0; i < 7; ++i) c->robin_hq[i] = hq[i];
+    for (int i = 0; i < 13; ++i) c->robin_hq[i] = hq[i];
     return DWOS_OK;
 }
 
@@ -1899,8 +2075,12 @@ dwos_status dwos_reflect_query(dwos_ctx* c, const double* X, const double* dir, 
     HIP_OK(hipSetDevice(c->device));
     auto run = [&](auto tag) {
         using T = decltype(tag);
-        hipLaunchKernelGGL(dwos::ref_query_kernel<T>, dim3(blocks_for(n, 64)), dim3(64), 0, c->stream,
-                           make_ref<T>(c), X, dir, cap, on, nin, n, out);
+        if (c->D == 3)
+            hipLaunchKernelGGL(dwos::ref3_query_kernel<T>, dim3(blocks_for(n, 64)), dim3(64), 0, c->stream,
+                               make_ref3<T>(c), X, dir, cap, on, nin, n, out);
+        else
+            hipLaunchKernelGGL(dwos::ref_query_kernel<T>, dim3(blocks_for(n, 64)), dim3(64), 0, c->stream,
+                               make_ref<T>(c), X, dir, cap, on, nin, n, out);
     };
     if (c->prec == DWOS_FP32) run(float{}); else run(double{});
     HIP_OK(hipGetLastError());

@@ -136,10 +136,11 @@ class Solver:
         self.N = int(N)
 
     def set_reflecting(self, V, segs):
-        """Fixed zero-flux boundary (2D segments over vertices V); walks on
-        stars from then on.  An empty ``segs`` removes it."""
-        V = np.ascontiguousarray(V, dtype=np.float64).reshape(-1, 2)
-        segs = np.ascontiguousarray(segs, dtype=np.int32).reshape(-1, 2)
+        """Fixed reflecting boundary (2D segments or 3D triangles over vertices
+        V, the domain on each primitive's left normal); walks on stars from
+        then on.  An empty ``segs`` removes it."""
+        V = np.ascontiguousarray(V, dtype=np.float64).reshape(-1, self.dim)
+        segs = np.ascontiguousarray(segs, dtype=np.int32).reshape(-1, self.dim)
         check(capi.dwos_set_reflecting(self._ctx, _dp(V), V.shape[0], _ip(segs), segs.shape[0]))
 
     def set_robin(self, mu: float, h=None):
@@ -147,12 +148,12 @@ class Solver:
         the domain); h a restricted field dict(c=, b=, A=) or None."""
         hb = None
         if h is not None:
-            hb = make_problem(bc=[h], dim=2).bc[0]
+            hb = make_problem(bc=[h], dim=self.dim).bc[0]
         check(capi.dwos_set_robin(self._ctx, float(mu), C.byref(hb) if hb is not None else None))
 
     def set_start_segments(self, seg):
-        """Per query point of the following calls: the reflecting segment it
-        lies on (domain to the segment's left) or -1; None clears."""
+        """Per query point of the following calls: the reflecting primitive it
+        lies on (domain on its left normal) or -1; None clears."""
         if seg is None:
             check(capi.dwos_set_start_segments(self._ctx, None, 0))
             return
@@ -161,7 +162,8 @@ class Solver:
 
     def reflect_query(self, X, dirs, cap, on, nin):
         """Per row: (silhouette distance capped at cap, first ray hit t (cap if
-        none), hit segment or -1) on the reflecting boundary."""
+        none), hit primitive or -1) on the reflecting boundary; X, dirs and
+        nin are rows of the context's dimension."""
         X = self._X(X)
         n = X.shape[0]
         out = torch.empty(n, 3, dtype=torch.float64, device=X.device)

@@ -261,10 +261,10 @@ def test_reflecting_error_paths(dev, dwos):
     assert e.value.code == DWOS_EINVAL
     s.set_start_segments(None)
     s.solve(X, 16, 1)
-    # 3D contexts have no reflecting boundaries
+    # 3D: a degenerate reflecting triangle
     s3 = dwos.Solver(3, "fp32")
     with pytest.raises(DwosError) as e:
-        s3.set_reflecting(np.zeros((2, 2)), np.array([[0, 1]]))
+        s3.set_reflecting(np.array([[0.0, 0, 0], [1, 0, 0], [2, 0, 0]]), np.array([[0, 1, 2]]))
     assert e.value.code == DWOS_EINVAL
     # zero-length segment
     with pytest.raises(DwosError) as e:
