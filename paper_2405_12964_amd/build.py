@@ -22,7 +22,7 @@ HIPCC_FLAGS = [
 
 
 def build(verbose: bool = False, out: str = LIB, csrc: str = CSRC, defines=()) -> str:
-    """Compile libdwos.so.  `defines` are extra -D knobs (e.g. DWOS_LEAF_MAX=2)."""
+    """Compile libdwos.so.  `defines` are extra -D knobs (e.g. DWOS_LEAF_MAX_3D=2)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objdir = os.path.join(os.path.dirname(out), "_build")
     os.makedirs(objdir, exist_ok=True)

@@ -21,16 +21,28 @@
 
 namespace dwos {
 
-#ifndef DWOS_LEAF_MAX
-#define DWOS_LEAF_MAX 8
+// Largest leaf (primitives per leaf, <= 8: 3-bit count), per dimension.
+// Measured with the walk kernels on the 200,000-triangle icosphere
+// (65536 points x 1024 walks): leaves of up to 8 triangles 124 / 140 ms
+// (forward / differential launch), 6: 121 / 137, 4: 119 / 136; on 2D
+// polylines leaves of 8 segments took the star's launches from 22.0 / 29.2
+// to 18.4 / 25.0 ms against smaller leaves.
+#ifndef DWOS_LEAF_MAX_2D
+#define DWOS_LEAF_MAX_2D 8
+#endif
+#ifndef DWOS_LEAF_MAX_3D
+#define DWOS_LEAF_MAX_3D 4
 #endif
 #ifndef DWOS_STACK_SIZE
 #define DWOS_STACK_SIZE 48
 #endif
-constexpr int kLeafMax = DWOS_LEAF_MAX;     // primitives per leaf (<= 8: 3-bit count)
+constexpr int kLeafMax2 = DWOS_LEAF_MAX_2D;
+constexpr int kLeafMax3 = DWOS_LEAF_MAX_3D;
+constexpr int leaf_max(int D) { return D == 2 ? kLeafMax2 : kLeafMax3; }
 constexpr int kStackSize = DWOS_STACK_SIZE; // traversal stack entries
 constexpr int kMaxDepth = kStackSize - 2;   // builder guarantee (stack never overflows)
-static_assert(kLeafMax >= 1 && kLeafMax <= 8, "leaf size must fit the 3-bit count");
+static_assert(kLeafMax2 >= 1 && kLeafMax2 <= 8 && kLeafMax3 >= 1 && kLeafMax3 <= 8,
+              "leaf size must fit the 3-bit count");
 
 constexpr int node_scalars(int D) { return D == 2 ? 20 : 24; }
 constexpr int slab_offset(int D) { return 4 * D; }                  // n0[D] o0 t0 n1[D] o1 t1
@@ -63,8 +75,9 @@ struct HostBVH {
 };
 
 // Binned-SAH build over primitive bounding boxes.  V: nv x D vertices,
-// prims: np x D indices.  Depth is kept <= kMaxDepth by switching to
-// median splits when a subtree would otherwise get too deep.
+// prims: np x D indices; leaves of at most leaf_max(D) primitives.  Depth is
+// kept <= kMaxDepth by switching to median splits when a subtree would
+// otherwise get too deep.
 HostBVH build_bvh(const double* V, const int32_t* prims, int64_t np, int D);
 
 // Renumber the pair nodes in breadth-first order (root first, then each

@@ -80,6 +80,7 @@ void fit_normal(const std::vector<double>& pts, int D, double n[3]) {
 
 struct Builder {
     int D;
+    int LM = 8;                  // largest leaf
     const double* V = nullptr;
     const int32_t* P = nullptr;
     std::vector<Box> pbox;
@@ -96,10 +97,10 @@ struct Builder {
     // returns the child reference of the subtree over idx[b, e)
     int32_t build(int b, int e, int depth) {
         const int n = e - b;
-        if (n <= kLeafMax) return leaf_ref(b, n);
+        if (n <= LM) return leaf_ref(b, n);
         // room left below this node: a subtree of n prims needs
-        // ceil(log2(n / kLeafMax)) further levels when split at the median
-        const int levels_needed = (int)std::ceil(std::log2((double)n / kLeafMax));
+        // ceil(log2(n / LM)) further levels when split at the median
+        const int levels_needed = (int)std::ceil(std::log2((double)n / LM));
         const bool force_median = depth + 1 + levels_needed >= kMaxDepth - 2;
 
         Box cb;
@@ -144,7 +145,7 @@ struct Builder {
                 // keep the depth guarantee: neither side may need more levels
                 // than remain
                 int lmax = std::max(mid - b, e - mid);
-                int need = (int)std::ceil(std::log2(std::max(1.0, (double)lmax / kLeafMax)));
+                int need = (int)std::ceil(std::log2(std::max(1.0, (double)lmax / LM)));
                 if (depth + 1 + need >= kMaxDepth - 2) mid = -1;
             }
         }
@@ -204,6 +205,7 @@ struct Builder {
 HostBVH build_bvh(const double* V, const int32_t* prims, int64_t np, int D) {
     Builder B;
     B.D = D;
+    B.LM = leaf_max(D);
     B.V = V;
     B.P = prims;
     B.pbox.resize(np);
@@ -217,7 +219,7 @@ HostBVH build_bvh(const double* V, const int32_t* prims, int64_t np, int D) {
         B.idx[p] = (int32_t)p;
     }
     B.out.nodes.reserve(np);
-    if (np <= kLeafMax) {
+    if (np <= leaf_max(D)) {
         // a single leaf under a root pair node whose second child is empty
         HostNode nd{};
         Box bx = B.range_box(0, (int)np);
