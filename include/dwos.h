@@ -280,7 +280,8 @@ dwos_status dwos_get_tuning(dwos_ctx* ctx, dwos_tuning* tuning);
 
 /* Autotuner.  Times forward solves (Algorithm 1) with seed `seed` under
  * candidate knob settings by coordinate descent (variant, then park, tail,
- * chunk and, for variant 0, stage_nodes; a candidate replaces the incumbent
+ * chunk and, for variant 0, stage_nodes: all, a half, a quarter or none of
+ * the nodes that fit; a candidate replaces the incumbent
  * when its walk-kernel time is more than 1% lower, each scored by the better
  * of two runs of the same walks) and leaves the fastest set on the context.
  * X (device) and P (host): on a single-scene context P[0] points of which

@@ -58,6 +58,7 @@ def lib():
         L.oracle_neumann_weight.restype = C.c_double
         L.oracle_silhouette.argtypes = [sp, dp, C.c_int32, dp, C.c_double, dp]
         L.oracle_ray.argtypes = [sp, dp, dp, C.c_double, C.c_int32, dp]
+        L.oracle_boundary_sample.argtypes = [sp, dp, C.c_double, C.c_uint64, C.c_uint32, C.c_int32, dp]
         L.oracle_safe_radius.argtypes = [sp, dp, dp]
         L.oracle_walk_records.argtypes = [sp, dp, C.c_int64, C.c_int32, C.c_uint64, C.c_int32,
                                           C.c_int32, dp, dp, lp, ip, dp, lp, dp, C.c_int]
@@ -307,6 +308,16 @@ class Oracle:
                               float(tmax), int(skip), _ptr(out, C.c_double))
         assert rc == 0
         return float(out[0]), int(out[1])
+
+    def boundary_sample(self, x, R, n, seed=1, k=0):
+        """n draws of the Robin boundary sample around x with radius R: an
+        (n, 5) array of (primitive or -1, L, z)."""
+        x = np.zeros(3) if x is None else np.concatenate([np.asarray(x, float), np.zeros(3 - len(x))])
+        out = np.zeros((n, 5))
+        rc = lib().oracle_boundary_sample(C.byref(self._s), _ptr(x, C.c_double), float(R), int(seed), int(k),
+                                          int(n), _ptr(out, C.c_double))
+        assert rc == 0
+        return out
 
     def safe_radius(self, x, harnack=False):
         """Radius of a disk around x on which the implicit h stays positive

@@ -2023,6 +2023,23 @@ int oracle_ray(const oracle_scene* s, const double* x, const double* dir, double
     return 0;
 }
 
+// Draws of the Robin boundary sample around x with radius R: draw m uses the
+// stream of walk m of point 0 (seed, instance 0) at step k.  out[5 m ..]:
+// {reflecting primitive or -1, L, z[0], z[1], z[2]}.
+int oracle_boundary_sample(const oracle_scene* s, const double* x, double R, uint64_t seed, uint32_t k,
+                           int32_t n, double* out) {
+    if (check_scene(s) || s->n_ns <= 0 || n < 0 || !(R > 0)) return 1;
+    Scene sc(*s);
+    for (int32_t m = 0; m < n; ++m) {
+        const Stream st = make_stream(seed, 0u, (uint32_t)m, 0u);
+        double L = 0, z[3] = {0, 0, 0};
+        const int t = sc.boundary_sample(x, R, st, k, 0u, L, z);
+        double* o = out + 5 * (size_t)m;
+        o[0] = t; o[1] = L; o[2] = z[0]; o[3] = z[1]; o[4] = z[2];
+    }
+    return 0;
+}
+
 // Per-walk records.  mode 0: Algorithm 1 from each point; mode 1: Algorithm 2.
 // u[P*W]; udot[P*W*N] (mode 1, may be NULL); steps[P*W] total closest-point
 // queries including nested walks (may be NULL); prim[P*W] terminal primitive or

@@ -2336,7 +2336,7 @@ dwos_status dwos_autotune(dwos_ctx* c, const double* X, const int64_t* P, int32_
     if (!rc) rc = try_dim(&dwos_tuning::chunk, {64, 128, 256, 512});
     if (!rc && c->prec == DWOS_FP32 && best.variant == 0 && !batch) {
         const int32_t staged = c->prec == DWOS_FP32 ? make_scene<float>(c).n_stage_nodes : 0;
-        if (staged > 4) rc = try_dim(&dwos_tuning::stage_nodes, {-1, staged / 4, 0});
+        if (staged > 4) rc = try_dim(&dwos_tuning::stage_nodes, {-1, staged / 2, staged / 4, 0});
     }
     if (rc) {
         dwos_set_tuning(c, &cur);

@@ -698,6 +698,18 @@ def _grid_rect(p0, e1, e2, n1: int, n2: int):
     return V, np.array(T, np.int32)
 
 
+def _graded_rect(p0, e1, e2, n1: int, n2: int, power: float):
+    """As _grid_rect with the grid lines at (i/n)^power along both edges, so
+    the cells (and triangles) have unequal areas."""
+    p0, e1, e2 = (np.asarray(a, float) for a in (p0, e1, e2))
+    s1 = (np.arange(n1 + 1) / n1) ** power
+    s2 = (np.arange(n2 + 1) / n2) ** power
+    i, j = np.meshgrid(np.arange(n1 + 1), np.arange(n2 + 1), indexing="ij")
+    V = p0 + s1[i.reshape(-1)][:, None] * e1 + s2[j.reshape(-1)][:, None] * e2
+    _, T = _grid_rect(p0, e1, e2, n1, n2)
+    return V, T
+
+
 def _weld(parts, tol: float = 1e-9):
     """Concatenate (V, T) meshes and merge vertices closer than tol."""
     V = np.concatenate([v for v, _ in parts])
@@ -756,10 +768,11 @@ def points_in_lprism(P: int, seed: int, lim: float = 0.95, zlim: float = 0.5) ->
 
 
 def box_wall_scene(n_wall: int = 4, sigma: float = 0.0, eps: float = 1e-4, delta: float = 1e-3,
-                   g=None, robin_mu: float = 0.0, robin_h=None) -> Scene:
+                   g=None, robin_mu: float = 0.0, robin_h=None, graded: float = 1.0) -> Scene:
     """Cube [-1, 1]^3: the face x = -1 is a reflecting wall (n_wall x n_wall
-    cells, domain side +x), the other five faces are Dirichlet (two triangles
-    each) with the restricted field g (dict of _restricted; default 0)."""
+    cells, domain side +x; graded != 1: grid lines at (i/n)^graded, cells of
+    unequal areas), the other five faces are Dirichlet (two triangles each)
+    with the restricted field g (dict of _restricted; default 0)."""
     Vb, Tb = box_triangles(1.0)
     c = (Vb[Tb[:, 0]] + Vb[Tb[:, 1]] + Vb[Tb[:, 2]]) / 3
     keep = ~(c[:, 0] < -0.999)
@@ -767,7 +780,7 @@ def box_wall_scene(n_wall: int = 4, sigma: float = 0.0, eps: float = 1e-4, delta
     remap = -np.ones(len(Vb), np.int64)
     remap[used] = np.arange(len(used))
     V, T = Vb[used], remap[Tb[keep]].astype(np.int32)
-    NV, NT = _grid_rect([-1, -1, -1], [0, 2, 0], [0, 0, 2], n_wall, n_wall)   # left normal +x
+    NV, NT = _graded_rect([-1, -1, -1], [0, 2, 0], [0, 0, 2], n_wall, n_wall, graded)   # left normal +x
     return Scene(dim=3, V=V, prims=T, label=np.zeros(len(T), np.int32),
                  bc=[g if g is not None else _restricted(0.0, dim=3)], gvert=np.zeros(len(V)),
                  sigma=sigma, eps=eps, delta=delta, NV=NV, nsegs=NT, robin_mu=robin_mu,

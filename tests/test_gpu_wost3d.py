@@ -56,7 +56,7 @@ def _robin_cube(n_wall=3, mu=0.5):
     """u = 1 + x/2 + x^2 - z^2 with du/dn - mu u = h on the wall x = -1."""
     g = scenes._restricted(1.0, [0.5, 0.0, 0.0], np.diag([1.0, 0.0, -1.0]), 3)
     h = scenes._restricted(-1.5 - mu * 1.5, None, np.diag([0.0, 0.0, mu]), 3)
-    return scenes.box_wall_scene(n_wall=n_wall, g=g, robin_mu=mu, robin_h=h)
+    return scenes.box_wall_scene(n_wall=n_wall, g=g, robin_mu=mu, robin_h=h, graded=2.0)
 
 
 def _dirs(rng, n):

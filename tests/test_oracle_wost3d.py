@@ -245,21 +245,45 @@ def test_walks_starting_on_a_wall_3d(oracle_mod):
 def test_robin_wall_of_a_cube(oracle_mod):
     """Cube [-1, 1]^3 with the Robin condition du/dn - mu u = h on the face
     x = -1 (n = +x into the domain): u = 1 + x/2 + x^2 - z^2 has
-    du/dn = -3/2 there, so h = -3/2 - mu (5/2 - z^2) - ... written out:
-    h = -3/2 - mu (1 - 1/2 + 1) + mu z^2; Dirichlet data u on the other
-    faces."""
+    du/dn = -3/2 and u = 3/2 - z^2 there, so h = -3/2 - mu (3/2 - z^2);
+    Dirichlet data u on the other faces."""
     mu = 0.5
     g = scenes._restricted(1.0, [0.5, 0.0, 0.0], np.diag([1.0, 0.0, -1.0]), 3)
     h = scenes._restricted(-1.5 - mu * 1.5, None, np.diag([0.0, 0.0, mu]), 3)
-    sc = scenes.box_wall_scene(n_wall=3, g=g, robin_mu=mu, robin_h=h)
+    # a graded wall grid: triangles of unequal areas (the race weighs them)
+    sc = scenes.box_wall_scene(n_wall=3, g=g, robin_mu=mu, robin_h=h, graded=2.0)
     X = np.random.default_rng(29).uniform(-0.85, 0.85, (16, 3))
     m, v, _ = oracle_mod.Oracle(sc).solve(X, 4096, 30)
     u = 1 + 0.5 * X[:, 0] + X[:, 0] ** 2 - X[:, 2] ** 2
     check_vs_exact(m, _se(v), u, 1e-3, "cube Robin")
     # the Neumann data alone (mu = 0): h = du/dn = -3/2
-    sc0 = scenes.box_wall_scene(n_wall=3, g=g, robin_h=scenes._restricted(-1.5, dim=3))
+    sc0 = scenes.box_wall_scene(n_wall=3, g=g, robin_h=scenes._restricted(-1.5, dim=3), graded=2.0)
     m, v, _ = oracle_mod.Oracle(sc0).solve(X, 4096, 31)
     check_vs_exact(m, _se(v), u, 1e-3, "cube Neumann data")
+
+
+def test_robin_boundary_sample_3d_disk_moments(oracle_mod):
+    """The Robin boundary sample over the graded wall x = -1 (triangles of
+    unequal areas) around a point at height h with radius R: L 1(z in B)
+    phi(z) is unbiased for the integral of phi over the disk the ball cuts
+    from the wall, of radius a = sqrt(R^2 - h^2): pi a^2 for phi = 1 and
+    pi a^2 (h^2 + a^2 / 2) for phi = |z - x|^2.  A race that ignored the
+    areas, or points not uniform on their triangle, would miss both."""
+    sc = scenes.box_wall_scene(n_wall=3, graded=2.0, robin_mu=1.0)
+    o = oracle_mod.Oracle(sc)
+    h, R = 0.3, 0.6
+    for c in ([-1 + h, 0.1, -0.2], [-1 + h, -0.35, 0.3]):
+        x = np.array(c)
+        d = o.boundary_sample(x, R, 200000, seed=41)
+        inb = d[:, 0] >= 0
+        z = d[:, 2:]
+        r2 = np.sum((z - x) ** 2, axis=1)
+        assert np.all(r2[inb] < R * R)
+        a2 = R * R - h * h
+        for phi, exact in ((np.ones(len(d)), np.pi * a2), (r2, np.pi * a2 * (h * h + a2 / 2))):
+            v = d[:, 1] * inb * phi
+            m, se = v.mean(), v.std() / np.sqrt(len(v))
+            assert abs(m - exact) < 4 * se, (c, m, exact, se)
 
 
 def test_half_ball_mirror(oracle_mod):
