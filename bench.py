@@ -666,6 +666,103 @@ def run_thermal(args):
     return out
 
 
+def run_thermal3d(args):
+    """Walk on stars in 3D: one optimisation step of the 3D thermal-design
+    stand-in (four heating elements, displaced icospheres of 720 triangles,
+    g = 1, 64 shape coefficients; a fixed zero-flux superellipsoid slice of
+    64,980 triangles between them; a cold box, Laplace).  Points on the slice
+    surface, where the loss lives, with their walks starting on the wall; W
+    forward and W differential walks (K nested walks on stars at each element
+    terminal, 8 as in the paper's thermal design); squared loss against the
+    solution of a second coefficient draw; Adam on the coefficients."""
+    import numpy as np
+    import torch
+    import scenes
+    import paper_2405_12964_amd as dw
+
+    dev = torch.device("cuda:0")
+    P, W = args.points or 16384, args.walks or 64
+    K = 8 if args.nested is None else args.nested
+    sc = scenes.thermal3d_scene(K=K)
+    X, tri = scenes.points_on_triangles(sc.NV, sc.nsegs, P, 1)
+    Xt = torch.tensor(X, dtype=torch.float64, device=dev)
+    ref = dw.Solver.from_scene(scenes.thermal3d_scene(coef_seed=3), "fp32")
+    ref.set_start_segments(tri)
+    uref, _ = ref.solve(Xt, W, 99)
+    torch.cuda.synchronize()
+    print("reference solution done", file=sys.stderr, flush=True)
+    del ref
+    model = dw.ShapeModel(sc, "fp32")
+    model.solver.set_start_segments(tri)
+    pi = torch.tensor(sc.pi0, dtype=torch.float64, device=dev, requires_grad=True)
+    opt = torch.optim.Adam([pi], lr=1e-3)
+
+    def step(i):
+        opt.zero_grad(set_to_none=True)
+        u = dw.DWoSFunction.apply(pi, Xt, model, W, 1000 + 2 * i, W, 1001 + 2 * i)
+        loss = 0.5 * ((u - uref) ** 2).sum()
+        loss.backward()
+        opt.step()
+        return loss
+
+    for i in range(args.warmup):
+        step(i)
+        torch.cuda.synchronize()
+        print(f"warmup step {i} done", file=sys.stderr, flush=True)
+    for kind in (0, 1):
+        model.solver.walk_timing(kind, reset=True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        loss = step(args.warmup + i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms0, n0, tot0 = model.solver.walk_timing(0)
+    ms1, n1, tot1 = model.solver.walk_timing(1)
+    for t in (tot0, tot1):
+        assert t["stack_overflow"] == 0 and t["invalid"] == 0, t
+    kind, ms, n, tot = (1, ms1, n1, tot1) if ms1 >= ms0 else (0, ms0, n0, tot0)
+    avg_s = ms / max(1, n) / 1e3
+    bytes_launch = (tot["nodes"] * BYTES_NODE_3D + tot["prims"] * BYTES_PRIM_3D) / max(1, n)
+    out = {
+        "metric": METRIC, "value": (tot0["steps"] + tot1["steps"]) / elapsed, "unit": "walk-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "walk on stars, 3D thermal design: 4 heating elements (2,880 triangles, g = 1, "
+                               "64 shape coefficients), zero-flux superellipsoid slice of 64,980 triangles, cold "
+                               f"box, Laplace; {P} points on the slice x {W} walks, forward + differential "
+                               f"(K={sc.K} nested) via autograd",
+                   "points": P, "walks_per_point": W, "reflecting_triangles": int(len(sc.nsegs)),
+                   "dirichlet_triangles": int(len(sc.prims)), "params": int(sc.N)},
+        "grad_evals_per_s": args.steps / elapsed,
+        "walk_steps": {"forward": tot0["steps"], "differential": tot1["steps"],
+                       "forward_ms": ms0, "differential_ms": ms1,
+                       "truncated": tot0["truncated"] + tot1["truncated"]},
+        "loss": float(loss.item()),
+        "roofline": {"bound": "hbm", "achieved": bytes_launch / avg_s / 1e9, "peak": PEAK_HBM / 1e9,
+                     "unit": "GB/s", "frac": bytes_launch / avg_s / PEAK_HBM, "traffic": None,
+                     "kernel": f"wost3_kernel<float,{kind}>", "avg_launch_ms": ms / max(1, n),
+                     "launches": n, "algorithmic_bytes_per_launch": bytes_launch,
+                     "steps_per_launch": tot["steps"] / max(1, n),
+                     "nodes_per_step": tot["nodes"] / max(1, tot["steps"]),
+                     "prims_per_step": tot["prims"] / max(1, tot["steps"])},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = min(16, len(os.sched_getaffinity(0)))
+        o = oracle.Oracle(sc, threads=threads)
+        npts, Wc = 16, 8
+        t0 = time.perf_counter()
+        _, _, s1 = o.solve(X[:npts], Wc, 7, start_seg=tri[:npts])
+        _, _, s2 = o.grad(X[:npts], np.ones(npts), Wc, 8, start_seg=tri[:npts])
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": (s1 + s2) / dt, "unit": "walk-steps/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"{npts} points x {Wc} forward + {Wc} differential walks on stars "
+                                         f"(K = {sc.K} nested) of the same scene, brute-force FP64, {dt:.1f} s"}
+    return out
+
+
 # Algorithmic FP32 operations per step of a walk on the implicit boundary of
 # n monopoles: h and grad h (per monopole: 2 differences, squared norm 3,
 # sqrt, a/r, accumulate, a/r^3 with 2 products, 4 for the gradient = 15),
@@ -1138,7 +1235,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5", "c5ls", "thermal", "inflation", "adjoint"],
+    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5", "c5ls", "thermal", "thermal3d", "inflation",
+                                           "adjoint"],
                     default="c3",
                     help="c3: 3D shape from diffusion on the 200,000-triangle icosphere (the reported "
                          "configuration); c2: 2D star; c4: batched instances; c5: 3D shape from diffusion "
@@ -1195,6 +1293,11 @@ def main():
         args.steps = 5 if args.steps is None else args.steps
         args.warmup = 2 if args.warmup is None else args.warmup
         print(json.dumps(run_thermal(args)), flush=True)
+        return
+    if args.workload == "thermal3d":
+        args.steps = 3 if args.steps is None else args.steps
+        args.warmup = 1 if args.warmup is None else args.warmup
+        print(json.dumps(run_thermal3d(args)), flush=True)
         return
     if args.workload == "inflation":
         args.steps = 150 if args.steps is None else args.steps

@@ -154,7 +154,7 @@ struct dwos_ctx {
     // 3D reflecting mesh: ref_nodes / ref_geo / ref_leaf_of hold its triangle
     // BVH, ref_torig the leaf -> original triangle map; its edges have a BVH
     // of their own
-    DevBuf ref_torig, ref_enodes, ref_egeo, ref_einfo;
+    DevBuf ref_torig, ref_enodes, ref_egeo, ref_einfo, ref_econes;
     int64_t ref_ne = 0, ref_enn = 0;
     bool robin = false;
     double robin_mu = 0.0;
@@ -417,6 +417,24 @@ dwos_status upload_reflecting3(dwos_ctx* c, const double* V, const int32_t* tris
         if (e.nf == 1) e.f1 = es[j].f;
         e.nf++;
     }
+    // does triangle f traverse the edge a -> b (in its winding order)?
+    auto forward = [&](int32_t f, int32_t a, int32_t b) {
+        for (int k = 0; k < 3; ++k)
+            if (tris[3 * (size_t)f + k] == a && tris[3 * (size_t)f + (k + 1) % 3] == b) return true;
+        return false;
+    };
+    auto unit_normal = [&](int32_t f, double* n) {
+        const double* A = V + 3 * (size_t)tris[3 * (size_t)f];
+        const double* B = V + 3 * (size_t)tris[3 * (size_t)f + 1];
+        const double* Cc = V + 3 * (size_t)tris[3 * (size_t)f + 2];
+        const double e1[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+        const double e2[3] = {Cc[0] - A[0], Cc[1] - A[1], Cc[2] - A[2]};
+        n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+        n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+        n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        const double L = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        for (int k = 0; k < 3; ++k) n[k] /= L;
+    };
     const int64_t ne = (int64_t)edges.size();
     if (ne > (int64_t(1) << 27)) return fail(DWOS_EINVAL, "set_reflecting: too many edges");
     std::vector<int32_t> eprims(3 * (size_t)ne);
@@ -451,7 +469,44 @@ dwos_status upload_reflecting3(dwos_ctx* c, const double* V, const int32_t* tris
         f[2] = e.nf >= 2 ? leaf_of[e.f1] : -1;
         f[3] = eb.order[lp];
     }
+    // normal cones of every edge node's two children (layout in wost3_kernels.hpp)
+    const double margin = sizeof(T) == 4 ? 2e-3 : 1e-8;
+    std::vector<T> cones(eb.nodes.size() * 2 * dwos::kEdgeCone, T(0));
+    std::vector<double> nrm;
+    for (size_t ni = 0; ni < eb.nodes.size(); ++ni)
+        for (int ch = 0; ch < 2; ++ch) {
+            T* q = &cones[(ni * 2 + ch) * dwos::kEdgeCone];
+            q[3] = T(2); q[4] = T(-1);   // never pruned
+            const int32_t b0 = eb.nodes[ni].range[ch][0], b1 = eb.nodes[ni].range[ch][1];
+            if (b1 <= b0) continue;
+            nrm.clear();
+            bool forced = false;
+            for (int32_t lp = b0; lp < b1 && !forced; ++lp) {
+                const Edge& e = edges[eb.order[lp]];
+                // a rim or non-manifold edge, or two triangles wound the same
+                // way along it, is never pruned
+                if (e.nf != 2 || forward(e.f0, e.a, e.b) == forward(e.f1, e.a, e.b)) { forced = true; break; }
+                double n[3];
+                unit_normal(e.f0, n);
+                nrm.insert(nrm.end(), n, n + 3);
+                unit_normal(e.f1, n);
+                nrm.insert(nrm.end(), n, n + 3);
+            }
+            if (forced || nrm.empty()) continue;
+            double ax = 0, ay = 0, az = 0;
+            for (size_t k = 0; k < nrm.size(); k += 3) { ax += nrm[k]; ay += nrm[k + 1]; az += nrm[k + 2]; }
+            const double L = std::sqrt(ax * ax + ay * ay + az * az);
+            if (!(L > 1e-9 * (double)nrm.size())) continue;
+            ax /= L; ay /= L; az /= L;
+            double th = 0;
+            for (size_t k = 0; k < nrm.size(); k += 3)
+                th = std::max(th, std::acos(std::min(1.0, std::max(-1.0, ax * nrm[k] + ay * nrm[k + 1] + az * nrm[k + 2]))));
+            const double s0 = th + margin;
+            if (!(s0 < 1.5707963267948966)) continue;
+            q[0] = T(ax); q[1] = T(ay); q[2] = T(az); q[3] = T(std::sin(s0)); q[4] = T(std::cos(s0));
+        }
     hipStream_t s = c->stream;
+    HIP_OK(upload(c->ref_econes, cones.data(), cones.size(), s));
     HIP_OK(upload(c->ref_nodes, tnodes.data(), tnodes.size(), s));
     HIP_OK(upload(c->ref_geo, tgeo.data(), tgeo.size(), s));
     HIP_OK(upload(c->ref_leaf_of, leaf_of.data(), leaf_of.size(), s));
@@ -477,6 +532,7 @@ dwos::RefScene3<T> make_ref3(dwos_ctx* c) {
     r.enodes = c->ref_enodes.as<T>();
     r.egeo = c->ref_egeo.as<T>();
     r.einfo = c->ref_einfo.as<int4>();
+    r.econes = c->ref_econes.as<T>();
     r.ne = c->ref_ne;
     r.robin = c->robin ? 1 : 0;
     r.mu = T(c->robin_mu);

@@ -48,6 +48,21 @@ constexpr int kTriGeo = 12;
 // first triangle, of the second (-1 none), original edge index}.
 constexpr int kEdgeGeo = 12;
 
+// Normal cones of the silhouette query, per edge-BVH node and child (8
+// scalars: a unit axis a[3], sin and cos of s0 = theta + margin, 3 pad),
+// theta the largest angle between a and the left normals of the triangles
+// at the child's edges.  Seen from x, an edge of two consistently wound
+// triangles is a silhouette only if their normals' dot products with the
+// view direction differ in sign, so some normal of the cone is then
+// perpendicular to a view direction.  A child whose view cone from x
+// (half-angle beta over the child box's bounding sphere) keeps every such
+// dot product of one sign -- |cos angle(a, c - x)| > sin(s0 + beta) with
+// s0 + beta < pi/2 -- holds none.  The margin covers the edge-on tolerance
+// and rounding; children with a rim, a non-manifold or inconsistently wound
+// edge, or normals spread by pi/2 or more, store sin = 2, cos = -1 (never
+// pruned).
+constexpr int kEdgeCone = 8;
+
 template <class T>
 struct RefScene3 {
     const T* tnodes;          // triangle BVH
@@ -58,6 +73,7 @@ struct RefScene3 {
     const T* enodes;          // edge BVH
     const T* egeo;
     const int4* einfo;
+    const T* econes;          // per edge node: child 0 then child 1, kEdgeCone each
     int64_t ne;
     // Robin condition: h = hq[0] + hq[1..3] . z + z^T A z, A = hq[4..12] row
     // major; robin = 0: zero flux
@@ -152,6 +168,26 @@ __device__ __forceinline__ bool sil3_test(const T* p, const T* q, const T* w0, c
     return (c0 > T(0)) == (c1 > T(0));
 }
 
+// Can the child with box lo..hi and cone q hold a silhouette edge seen from x?
+template <class T>
+__device__ __forceinline__ bool cone3_may_hold(const T* lo, const T* hi, const T* q, const T* x) {
+    T c[3], r2 = T(0), d2 = T(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        c[k] = T(0.5) * (lo[k] + hi[k]) - x[k];
+        const T e = T(0.5) * (hi[k] - lo[k]);
+        r2 += e * e;
+        d2 += c[k] * c[k];
+    }
+    if (!(d2 > r2)) return true;           // x inside the bounding sphere
+    const T inv = T(1) / sqrt(d2);
+    const T sb = sqrt(r2) * inv, cb = sqrt(T(1) - sb * sb);
+    const T cs = q[4] * cb - q[3] * sb;   // cos(s0 + beta)
+    if (!(cs > T(0))) return true;
+    const T ss = q[3] * cb + q[4] * sb;   // sin(s0 + beta)
+    return !(fabs((q[0] * c[0] + q[1] * c[1] + q[2] * c[2]) * inv) > ss);
+}
+
 // Closest silhouette edge as a resumable query (one node or leaf per
 // round), as sil_round in 2D; x lies on leaf triangle `on` (domain side
 // nin) or inside (-1).
@@ -164,8 +200,9 @@ __device__ __forceinline__ void sil3_round(const RefScene3<T>& r, const T* x, in
         qc.nodes++;
         const T d0 = fmax(box_d2<T, 3>(nd.lo0, nd.hi0, x), slab_d2<T, 3>(nd.n0, nd.o0, nd.t0, x));
         const T d1 = fmax(box_d2<T, 3>(nd.lo1, nd.hi1, x), slab_d2<T, 3>(nd.n1, nd.o1, nd.t1, x));
-        const bool h0 = !(nd.t0 < T(0)) && d0 < q.best;
-        const bool h1 = !(nd.t1 < T(0)) && d1 < q.best;
+        const T* cq = r.econes + (size_t)q.cur * (2 * kEdgeCone);
+        const bool h0 = !(nd.t0 < T(0)) && d0 < q.best && cone3_may_hold<T>(nd.lo0, nd.hi0, cq, x);
+        const bool h1 = !(nd.t1 < T(0)) && d1 < q.best && cone3_may_hold<T>(nd.lo1, nd.hi1, cq + kEdgeCone, x);
         if (h0 && h1) {
             const bool n0 = d0 <= d1;
             if (q.sp < kStackSize) {

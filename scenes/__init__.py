@@ -37,7 +37,7 @@ __all__ = [
     "annulus_reflecting_scene", "points_in_lshape", "points_in_half_disk",
     "points_on_segments", "thermal_scene", "monopole_scene", "inflation_scene",
     "lprism_scene", "points_in_lprism", "box_wall_scene", "half_ball_scene",
-    "points_in_half_ball", "points_on_triangles",
+    "points_in_half_ball", "points_on_triangles", "thermal3d_scene",
 ]
 
 
@@ -851,6 +851,62 @@ def points_in_half_ball(P: int, seed: int, rmax: float = 0.8, ymin: float = 0.0)
         X = X[(np.linalg.norm(X, axis=1) < rmax) & (X[:, 1] > ymin)]
         out = np.concatenate([out, X])
     return out[:P]
+
+
+def thermal3d_scene(nu_slice: int = 57, nu_wire: int = 8, n_basis: int = 16, h: float = 0.6,
+                    coef: Optional[np.ndarray] = None, coef_seed: int = 0, sigma: float = 0.0,
+                    eps: float = 1e-3, delta: float = 1e-2, K: int = 1) -> Scene:
+    """3D stand-in for the paper's thermal-design example (Sec. 7.3): four
+    heating elements -- displaced icospheres of frequency nu_wire, radius
+    0.15, g = 1 (label 1) -- whose shapes are the parameters, a fixed
+    zero-flux slice between them, inside a cold box [-2, 2]^3 (g = 0, label
+    0).
+
+    Element w has centre (+-1.35, +-0.45, 0) and radius
+    0.15 (1 + sum_j c_j phi_j(u)) with n_basis angular Gaussian bumps of
+    width h at Fibonacci-sphere centres (4 n_basis parameters in all).  The
+    slice is the superellipsoid |x/0.9|^4 + |y/0.6|^4 + |z/0.6|^4 = 1 with a
+    1% ripple of 24 lobes about the z axis, an icosphere of frequency
+    nu_slice projected onto it (20 nu_slice^2 triangles, 64,980 at 57), wound
+    outward: the domain (outside) is on each triangle's left normal."""
+    n_wires = 4
+    N = n_basis * n_wires
+    if coef is None:
+        coef = np.random.default_rng(coef_seed).normal(0.0, 0.05, N)
+    coef = np.asarray(coef, float)
+    Vb, Tb = box_triangles(2.0)
+    V, prims, label, Vbase = [Vb], [Tb], [np.zeros(len(Tb), np.int32)], [Vb.copy()]
+    rows = [np.zeros(len(Vb), np.int64)]
+    pids, vels = [], []
+    nv = len(Vb)
+    Vu, Tw = icosphere(nu_wire)
+    centres = fibonacci_sphere(n_basis)
+    rp, cols, vals = radial_basis(Vu, centres, h)
+    vrows = np.repeat(np.arange(Vu.shape[0]), np.diff(rp))
+    for w, cw in enumerate([[-1.35, -0.45, 0.0], [-1.35, 0.45, 0.0], [1.35, -0.45, 0.0], [1.35, 0.45, 0.0]]):
+        cw = np.array(cw)
+        c_w = coef[w * n_basis:(w + 1) * n_basis]
+        disp = np.zeros(Vu.shape[0])
+        np.add.at(disp, vrows, vals * c_w[cols])
+        V.append(cw + 0.15 * Vu * (1.0 + disp)[:, None])
+        Vbase.append(cw + 0.15 * Vu)
+        # element winding flipped: its stored normal points into the element
+        prims.append(Tw[:, [0, 2, 1]] + nv)
+        label.append(np.ones(len(Tw), np.int32))
+        rows.append(np.diff(rp).astype(np.int64))
+        pids.append((cols + w * n_basis).astype(np.int32))
+        vels.append(0.15 * Vu[vrows] * vals[:, None])
+        nv += Vu.shape[0]
+    Us, Ts = icosphere(nu_slice)
+    rs = 1.0 / (np.abs(Us[:, 0] / 0.9) ** 4 + np.abs(Us[:, 1] / 0.6) ** 4 + np.abs(Us[:, 2] / 0.6) ** 4) ** 0.25
+    phi = np.arctan2(Us[:, 1], Us[:, 0])
+    NV = Us * (rs * (1 + 0.01 * np.cos(24 * phi)))[:, None]
+    rowptr = np.concatenate([[0], np.cumsum(np.concatenate(rows))]).astype(np.int64)
+    return Scene(dim=3, V=np.concatenate(V), prims=np.concatenate(prims).astype(np.int32),
+                 label=np.concatenate(label), bc=[_restricted(0.0, dim=3), _restricted(1.0, dim=3)],
+                 gvert=np.zeros(nv), sigma=sigma, eps=eps, delta=delta, K=K, N=N, rowptr=rowptr,
+                 pid=np.concatenate(pids), vel=np.concatenate(vels), V_base=np.concatenate(Vbase),
+                 pi0=coef.copy(), NV=NV, nsegs=Ts.astype(np.int32), name=f"thermal3d_{nu_slice}")
 
 
 def points_on_triangles(NV: np.ndarray, ntris: np.ndarray, P: int, seed: int, tris=None):

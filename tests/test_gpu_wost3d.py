@@ -169,6 +169,46 @@ def test_walk_for_walk_half_ball_derivatives(dev, dwos, oracle_mod):
     _wfw(dev, dwos, oracle_mod, sc, scenes.points_in_half_ball(8, 7), 8, 16)
 
 
+def test_walk_for_walk_closed_reflecting_surface(dev, dwos, oracle_mod):
+    """The 3D thermal stand-in at a small size (a closed, convex-ish
+    reflecting superellipsoid of 720 triangles between four heating
+    elements): the silhouette query prunes edge-BVH children by their normal
+    cones, the oracle tests every edge; walks from the slice surface and from
+    the gap, forward and differential with the elements' shape derivatives."""
+    sc = scenes.thermal3d_scene(nu_slice=6, nu_wire=3, eps=1e-3, delta=1e-2, K=2)
+    X, tri = scenes.points_on_triangles(sc.NV, sc.nsegs, 8, 17)
+    Xi = np.array([[1.1, 0.0, 0.0], [-1.1, 0.2, 0.1], [0.0, 0.9, 0.3], [0.3, -0.2, 0.9]])
+    X = np.concatenate([X, Xi])
+    tri = np.concatenate([tri, -np.ones(len(Xi), np.int32)])
+    _wfw(dev, dwos, oracle_mod, sc, X, 8, 18, start=tri)
+
+
+def test_silhouette_cones_match_oracle(dev, dwos, oracle_mod):
+    """Closest silhouette edge of the closed slice from points around it
+    (off the surface and on it): the cone-pruned query equals the oracle's
+    full search, exactly in FP64.  In FP32 an edge that is within the edge-on
+    tolerance (1e-4 of its operands) counts as a silhouette seen from a point
+    off the surface, so the FP32 distance may be shorter than the oracle's
+    (never longer: the star region stays star-shaped) for a few points."""
+    sc = scenes.thermal3d_scene(nu_slice=10, nu_wire=2)
+    rng = np.random.default_rng(19)
+    U = rng.normal(size=(300, 3))
+    U /= np.linalg.norm(U, axis=1, keepdims=True)
+    Xi = U * rng.uniform(1.02, 1.8, (300, 1)) * np.array([0.9, 0.6, 0.6])
+    X, D, cap, on, N = _query_cases(sc, Xi, 20)
+    o = oracle_mod.Oracle(sc)
+    ref = np.array([o.silhouette(X[i], int(on[i]), N[i], cap[i]) for i in range(len(X))])
+    for prec, tol in (("fp64", 1e-12), ("fp32", 2e-5)):
+        s = dwos.Solver.from_scene(sc, prec)
+        out = s.reflect_query(T(X, dev), T(D, dev), T(cap, dev), T(on, dev, torch.int32), T(N, dev)).cpu().numpy()
+        close = np.isclose(out[:, 0], ref, rtol=tol, atol=tol * 0.1)
+        if prec == "fp64":
+            assert close.all(), (prec, np.abs(out[:, 0] - ref).max())
+        else:
+            assert np.all(out[:, 0] <= ref * (1 + tol) + tol * 0.1), (out[:, 0] - ref).max()
+            assert close.mean() > 0.99, (close.mean(), np.abs(out[:, 0] - ref).max())
+
+
 # ------------------------------------------------- FP32 statistical parity --
 
 def test_fp32_parity_3d(dev, dwos, oracle_mod):
