@@ -362,7 +362,7 @@ def run_c4(args):
     wts = torch.cat([torch.full((len(x),), 1.0 / len(x), dtype=torch.float64, device=dev) for _, x in insts])
     with torch.cuda.stream(stream):
         s.batch_solve(X, P, W, 1, var=False)
-        tuning, tune_ms = (s.get_tuning(), None) if args.no_autotune else s.autotune(X, W, seed=5, P=P, cache=False)
+        tuning, tune_ms = (s.get_tuning(), None) if args.no_autotune else s.autotune(X, W, seed=5, P=P, cache=False, grad=True)
         s.batch_grad(X, P, wts, W, 2, u_mean=False)
     torch.cuda.synchronize()
     print(f"c4: {len(insts)} instances, tuning {tuning} ({tune_ms} ms)", file=sys.stderr, flush=True)

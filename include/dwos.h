@@ -277,6 +277,7 @@ dwos_status dwos_set_tuning(dwos_ctx* ctx, const dwos_tuning* tuning);
 dwos_status dwos_get_tuning(dwos_ctx* ctx, dwos_tuning* tuning);
 
 #define DWOS_TUNE_CACHE 1
+#define DWOS_TUNE_GRAD 2
 
 /* Autotuner.  Times forward solves (Algorithm 1) with seed `seed` under
  * candidate knob settings by coordinate descent (variant, then park, tail,
@@ -287,15 +288,22 @@ dwos_status dwos_get_tuning(dwos_ctx* ctx, dwos_tuning* tuning);
  * X (device) and P (host): on a single-scene context P[0] points of which
  * the first min(P[0], max(64, 2^22 / W)) are solved; on a batch context one
  * count per instance and the whole batch is solved (dwos_batch_solve).
- * flags: DWOS_TUNE_CACHE looks the setting up in, and stores it to, a
- * process-wide table keyed by device, dimension, precision, single or batch
- * and the scene's primitive count in half-octaves (floor(2 log2 n)); a hit
+ * flags: DWOS_TUNE_GRAD adds to each timed solve a reverse-mode call
+ * (Algorithm 2: dwos_grad or dwos_batch_grad, seed + 1, unit weights, on
+ * the same points) and scores the sum of both calls' walk-kernel times; it
+ * needs parameters (dwos_set_parameters / dwos_batch_set_parameters).
+ * DWOS_TUNE_CACHE looks the setting up in, and stores it to, a
+ * process-wide table keyed by device, dimension, precision, single or batch,
+ * DWOS_TUNE_GRAD and the scene's primitive count in half-octaves
+ * (floor(2 log2 n)); a hit
  * applies the stored setting without running anything.  Results are stored
  * in the table in any case.  chosen (host, may be NULL) gets the setting,
  * ms (host, 2 entries, may be NULL) the walk-kernel milliseconds under the
  * setting in force at the call and under the chosen one (-1 on a cache hit).
- * Errors: as dwos_solve / dwos_batch_solve; EINVAL for unknown flags; on an
- * error the context keeps the setting in force at the call. */
+ * Errors: as dwos_solve / dwos_batch_solve (and dwos_grad / dwos_batch_grad
+ * with DWOS_TUNE_GRAD); EINVAL for unknown flags; ESTATE for DWOS_TUNE_GRAD
+ * without parameters; on an error the context keeps the setting in force at
+ * the call. */
 dwos_status dwos_autotune(dwos_ctx* ctx, const double* X, const int64_t* P, int32_t W, uint64_t seed,
                           int32_t flags, dwos_tuning* chosen, double* ms);
 /* Set only the launch shape (the variant field above). */

@@ -48,6 +48,7 @@ class dwos_tuning(C.Structure):
 
 
 DWOS_TUNE_CACHE = 1
+DWOS_TUNE_GRAD = 2
 
 
 class dwos_quad(C.Structure):

@@ -2291,18 +2291,19 @@ namespace {
 // Process-wide autotuner results, keyed by device, dimension, precision,
 // batch or single scene and the scene's size in half-octaves of primitives.
 struct TuneKey {
-    int device, D, prec, batch, bucket;
+    int device, D, prec, batch, bucket, grad;
     bool operator<(const TuneKey& o) const {
-        return std::tie(device, D, prec, batch, bucket) < std::tie(o.device, o.D, o.prec, o.batch, o.bucket);
+        return std::tie(device, D, prec, batch, bucket, grad) <
+               std::tie(o.device, o.D, o.prec, o.batch, o.bucket, o.grad);
     }
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, dwos_tuning> g_tune_cache;
 
-TuneKey tune_key(const dwos_ctx* c) {
+TuneKey tune_key(const dwos_ctx* c, bool grad) {
     const int64_t np = c->instances.empty() ? c->np : (int64_t)c->hostOrder.size();
     const int bucket = np > 0 ? (int)std::floor(2.0 * std::log2((double)np)) : 0;
-    return {c->device, c->D, c->prec, c->instances.empty() ? 0 : 1, bucket};
+    return {c->device, c->D, c->prec, c->instances.empty() ? 0 : 1, bucket, grad ? 1 : 0};
 }
 
 }  // namespace
@@ -2313,8 +2314,9 @@ dwos_status dwos_autotune(dwos_ctx* c, const double* X, const int64_t* P, int32_
                           dwos_tuning* chosen, double* ms) {
     if (!c) return fail(DWOS_EINVAL, "NULL context");
     if (!P || W < 1 || !X) return fail(DWOS_EINVAL, "autotune: need points, point counts and W >= 1");
-    if (flags & ~DWOS_TUNE_CACHE) return fail(DWOS_EINVAL, "autotune: unknown flags");
+    if (flags & ~(DWOS_TUNE_CACHE | DWOS_TUNE_GRAD)) return fail(DWOS_EINVAL, "autotune: unknown flags");
     const bool batch = !c->instances.empty();
+    const bool with_grad = (flags & DWOS_TUNE_GRAD) != 0;
     if (!batch && !c->has_boundary) return fail(DWOS_ESTATE, "autotune: no mesh boundary");
     if (!c->has_problem) return fail(DWOS_ESTATE, "autotune: no problem: call dwos_set_problem first");
     // the timed call: a forward solve of the whole batch, or of a prefix of
@@ -2330,9 +2332,18 @@ dwos_status dwos_autotune(dwos_ctx* c, const double* X, const int64_t* P, int32_
         pts = std::min<int64_t>(P[0], std::max<int64_t>(64, ((int64_t)1 << 22) / W));
     }
     if (pts <= 0) return fail(DWOS_EINVAL, "autotune: need points");
+    int64_t Ntot = 0;
+    if (with_grad) {
+        if (batch) {
+            for (const auto& bp : c->batch_params) Ntot += bp.N;
+        } else if (c->has_params) {
+            Ntot = c->N;
+        }
+        if (Ntot < 1) return fail(DWOS_ESTATE, "autotune: DWOS_TUNE_GRAD needs parameters");
+    }
     dwos_tuning cur{};
     dwos_get_tuning(c, &cur);
-    const TuneKey key = tune_key(c);
+    const TuneKey key = tune_key(c, with_grad);
     if (flags & DWOS_TUNE_CACHE) {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         auto it = g_tune_cache.find(key);
@@ -2344,13 +2355,32 @@ dwos_status dwos_autotune(dwos_ctx* c, const double* X, const int64_t* P, int32_
             return DWOS_OK;
         }
     }
-    DevBuf mean;
+    DevBuf mean, wone, gout;
     HIP_OK(mean.reserve(pts * sizeof(double)));
+    if (with_grad) {
+        const std::vector<double> ones((size_t)pts, 1.0);
+        HIP_OK(upload(wone, ones.data(), ones.size(), c->stream));
+        HIP_OK(gout.reserve(Ntot * sizeof(double)));
+    }
     std::vector<int64_t> Pb(P, P + (batch ? c->instances.size() : 1));
     if (!batch) Pb[0] = pts;
-    auto run = [&](uint64_t sd, dwos_stats* st) {
-        return batch ? dwos_batch_solve(c, X, Pb.data(), W, sd, mean.as<double>(), nullptr, st)
-                     : dwos_solve(c, X, pts, W, sd, mean.as<double>(), nullptr, st);
+    // the timed call: a forward solve, and with DWOS_TUNE_GRAD a reverse-mode
+    // call with unit weights on the same points; *ms (if given) gets the sum
+    // of their walk-kernel times
+    auto run = [&](uint64_t sd, double* ms_out) -> dwos_status {
+        dwos_stats st{}, st2{};
+        dwos_stats* ps = ms_out ? &st : nullptr;
+        dwos_status r = batch ? dwos_batch_solve(c, X, Pb.data(), W, sd, mean.as<double>(), nullptr, ps)
+                              : dwos_solve(c, X, pts, W, sd, mean.as<double>(), nullptr, ps);
+        if (r) return r;
+        if (with_grad) {
+            dwos_stats* ps2 = ms_out ? &st2 : nullptr;
+            r = batch ? dwos_batch_grad(c, X, Pb.data(), wone.as<double>(), W, sd + 1, gout.as<double>(), nullptr, ps2)
+                      : dwos_grad(c, X, pts, wone.as<double>(), W, sd + 1, gout.as<double>(), nullptr, ps2);
+            if (r) return r;
+        }
+        if (ms_out) *ms_out = st.walk_ms + st2.walk_ms;
+        return DWOS_OK;
     };
     // every candidate runs the same walks (same seed); the better of two
     // timings of the walk kernel(s) scores it
@@ -2359,10 +2389,10 @@ dwos_status dwos_autotune(dwos_ctx* c, const double* X, const int64_t* P, int32_
         if (rc) return rc;
         double best = 0.0;
         for (int r = 0; r < 2; ++r) {
-            dwos_stats st{};
-            rc = run(seed, &st);
+            double ms_r = 0.0;
+            rc = run(seed, &ms_r);
             if (rc) return rc;
-            if (r == 0 || st.walk_ms < best) best = st.walk_ms;
+            if (r == 0 || ms_r < best) best = ms_r;
         }
         out = best;
         return DWOS_OK;

@@ -389,20 +389,23 @@ class Solver:
         out = (g,) + ((lam, uo) if records else ()) + ((st.as_dict(),) if stats else ())
         return out if len(out) > 1 else g
 
-    def autotune(self, X, W, seed=0, P=None, cache=True):
+    def autotune(self, X, W, seed=0, P=None, cache=True, grad=False):
         """Autotune the walk kernels' scheduling knobs (dwos_autotune) on forward
         solves of X: a prefix of the points on a single-scene context, the
-        whole batch (P: points per instance) on a batch context.  Returns
-        (tuning dict, [ms under the setting at the call, ms under the chosen
-        one]); both are -1 when the process-wide table already held a setting
-        for this scene-size bucket (cache=True)."""
+        whole batch (P: points per instance) on a batch context; grad=True
+        also times a reverse-mode call with unit weights on the same points
+        (DWOS_TUNE_GRAD, needs parameters).  Returns (tuning dict, [ms under
+        the setting at the call, ms under the chosen one]); both are -1 when
+        the process-wide table already held a setting for this scene-size
+        bucket (cache=True)."""
         X = self._X(X)
         counts = [X.shape[0]] if P is None else [int(p) for p in P]
         Pa = (C.c_int64 * len(counts))(*counts)
         t = capi.dwos_tuning()
         ms = (C.c_double * 2)()
         check(capi.dwos_autotune(self._ctx, _dev(X), Pa, int(W), int(seed),
-                                 capi.DWOS_TUNE_CACHE if cache else 0, C.byref(t), ms))
+                                 (capi.DWOS_TUNE_CACHE if cache else 0) | (capi.DWOS_TUNE_GRAD if grad else 0),
+                                 C.byref(t), ms))
         return t.as_dict(), [ms[0], ms[1]]
 
     def get_tuning(self) -> dict:

@@ -420,6 +420,18 @@ def test_batch_autotune(dev, dwos):
     assert all(v > 0 for v in ms) and s.get_tuning() == t
     m1, v1 = s.batch_solve(X, P, 32, 3)
     assert torch.equal(m0, m1) and torch.equal(v0, v1)
+    # scoring solve + reverse mode needs parameters
+    with pytest.raises(dwos.DwosError):
+        s.autotune(X, 32, P=P, cache=False, grad=True)
+    w = torch.ones(X.shape[0], dtype=torch.float64, device=dev)
+    for i, (sc, _) in enumerate(insts):
+        s.batch_set_parameters(i, sc.N, sc.rowptr, sc.pid, sc.vel)
+    s.set_tuning(variant=1, park=24, tail=8, chunk=128, stage_nodes=-1)
+    g0, _ = s.batch_grad(X, P, w, 32, 4)
+    t2, ms2 = s.autotune(X, 32, P=P, cache=False, grad=True)
+    assert all(v > 0 for v in ms2) and s.get_tuning() == t2
+    g1, _ = s.batch_grad(X, P, w, 32, 4)
+    assert torch.allclose(g0, g1, rtol=1e-5, atol=1e-9)
 
 
 def test_fp32_terminal_side_when_a_step_lands_on_the_boundary(dev, dwos):
