@@ -425,7 +425,8 @@ __device__ __forceinline__ void query_test_prim(const Scene<T>& s, const StageVi
     const T d2 = prim_closest<T, D>(P, x, bb);
     qc.prims++;
     if (d2 < q.best * (T(1) - TieBand<T>::v)) { q.best = d2; q.bleaf = i; }
-    else if (d2 <= q.best * (T(1) + TieBand<T>::v) && i != q.bleaf && s.orig[i] < s.orig[q.bleaf]) {
+    else if (d2 <= q.best * (T(1) + TieBand<T>::v) && i != q.bleaf && q.bleaf >= 0 &&
+             s.orig[i] < s.orig[q.bleaf]) {
         q.best = d2;
         q.bleaf = i;
     }
@@ -549,6 +550,28 @@ __device__ __forceinline__ int32_t closest_leaf(const Scene<T>& s, const StageVi
                                                 Stack& st) {
     Query<T> q;
     query_begin<T, D>(s, sv, root, x, warm, q);
+#pragma unroll 1
+    while (!q.done) query_round<T, D>(s, sv, x, true, q, qc, st);
+    best = q.best;
+    return q.bleaf;
+}
+
+// A query limited to primitives nearer than sqrt(bound2): the same leaf and
+// squared distance as closest_leaf when the closest primitive lies within
+// the bound, else -1 (best = bound2).  warm (or -1) with its squared
+// distance warm_d2 seeds the search as in closest_leaf.
+template <class T, int D, class Stack>
+__device__ __forceinline__ int32_t closest_leaf_within(const Scene<T>& s, const StageView& sv, int32_t root,
+                                                       const T* x, int32_t warm, T warm_d2, T bound2, T& best,
+                                                       QueryCount& qc, Stack& st) {
+    Query<T> q;
+    query_begin<T, D>(s, sv, root, x, -1, q);
+    if (warm >= 0 && warm_d2 < bound2) {
+        q.best = warm_d2;
+        q.bleaf = warm;
+    } else {
+        q.best = bound2;
+    }
 #pragma unroll 1
     while (!q.done) query_round<T, D>(s, sv, x, true, q, qc, st);
     best = q.best;

@@ -168,6 +168,29 @@ __device__ __forceinline__ bool sil3_test(const T* p, const T* q, const T* w0, c
     return (c0 > T(0)) == (c1 > T(0));
 }
 
+// Leaf edge i: if it is nearer to x than sqrt(best) and a silhouette seen
+// from x (x on leaf triangle `on` with domain side nin, or inside: -1),
+// lower best to its squared distance and return true.
+template <class T>
+__device__ __forceinline__ bool sil3_edge_nearer(const RefScene3<T>& r, int32_t i, const T* x, int32_t on,
+                                                 const T* nin, T& best) {
+    const T* g = r.egeo + (size_t)i * kEdgeGeo;
+    const T e[3] = {g[3] - g[0], g[4] - g[1], g[5] - g[2]};
+    const T ax[3] = {x[0] - g[0], x[1] - g[1], x[2] - g[2]};
+    const T ee = dot3d<T>(e, e);
+    const T t = ee > T(0) ? fmin(T(1), fmax(T(0), quot<T>(dot3d<T>(ax, e), ee))) : T(0);
+    const T dx = ax[0] - t * e[0], dy = ax[1] - t * e[1], dz = ax[2] - t * e[2];
+    const T d2 = dx * dx + dy * dy + dz * dz;
+    if (!(d2 < best)) return false;
+    const int4 inf = r.einfo[i];
+    const int own = on < 0 ? 0 : (on == inf.y ? 1 : (on == inf.z ? 2 : 0));
+    if ((inf.x & 1) || sil3_test<T>(g, g + 3, g + 6, g + 9, own, x, nin, on >= 0)) {
+        best = d2;
+        return true;
+    }
+    return false;
+}
+
 // Can the child with box lo..hi and cone q hold a silhouette edge seen from x?
 template <class T>
 __device__ __forceinline__ bool cone3_may_hold(const T* lo, const T* hi, const T* q, const T* x) {
@@ -223,18 +246,8 @@ __device__ __forceinline__ void sil3_round(const RefScene3<T>& r, const T* x, in
         const int32_t v = -1 - q.cur;
         const int32_t start = v >> 3, n = (v & 7) + 1;
         for (int32_t i = start; i < start + n; ++i) {
-            const T* g = r.egeo + (size_t)i * kEdgeGeo;
             qc.prims++;
-            const T e[3] = {g[3] - g[0], g[4] - g[1], g[5] - g[2]};
-            const T ax[3] = {x[0] - g[0], x[1] - g[1], x[2] - g[2]};
-            const T ee = dot3d<T>(e, e);
-            const T t = ee > T(0) ? fmin(T(1), fmax(T(0), quot<T>(dot3d<T>(ax, e), ee))) : T(0);
-            const T dx = ax[0] - t * e[0], dy = ax[1] - t * e[1], dz = ax[2] - t * e[2];
-            const T d2 = dx * dx + dy * dy + dz * dz;
-            if (!(d2 < q.best)) continue;
-            const int4 inf = r.einfo[i];
-            const int own = on < 0 ? 0 : (on == inf.y ? 1 : (on == inf.z ? 2 : 0));
-            if ((inf.x & 1) || sil3_test<T>(g, g + 3, g + 6, g + 9, own, x, nin, on >= 0)) q.best = d2;
+            if (sil3_edge_nearer<T>(r, i, x, on, nin, q.best)) q.bsil = i;
         }
         q.have = false;
     }
@@ -526,6 +539,8 @@ __global__ void __launch_bounds__(kBlock) wost3_kernel(WalkArgs<T> a, RefScene3<
     SilQuery<T> sq;
     sq.have = false;
     bool spend = false;
+    bool sexact = true;    // sd2 is the Dirichlet distance (else an upper bound)
+    int32_t swarm = -1;    // the previous step's closest silhouette edge, or -1
     T sd2 = T(0);
     int32_t sleaf = -1;
     unsigned long long c_walks = 0, c_nested = 0, c_steps = 0, c_term = 0, c_trunc = 0,
@@ -592,15 +607,35 @@ __global__ void __launch_bounds__(kBlock) wost3_kernel(WalkArgs<T> a, RefScene3<
         QueryCount qc{0, 0, 0};
         bool finished = false;
         T result = T(0);
+        bool at_term = false;   // the walk reached the Dirichlet boundary (or the cap)
+        T td2 = T(0);
+        int32_t tleaf = -1;
+        const bool cap = (int)(k + 1) >= a.prm.kmax;
         if (!spend) {
-            // ---- Dirichlet distance ----------------------------------------------
-            T d2;
-            int32_t leaf;
+            // ---- Dirichlet distance, or an upper bound of it -------------------
+            // The step's radius is min(Dirichlet distance, closest silhouette).
+            // Away from the cap and the walk's first step the silhouette query
+            // runs first, bounded by the distance to the previous step's
+            // closest primitive (warm), and the Dirichlet query afterwards
+            // only within max(silhouette distance, eps): nearer primitives
+            // are found exactly as by the full query, and when there is none
+            // the radius is the silhouette distance.  Same radius, same
+            // terminals.
+            T d2 = T(0);
+            int32_t leaf = -1;
             bool executed = true;
+            sexact = true;
             if (a.first_leaf && phase == 0 && k == 0) {
                 leaf = a.first_leaf[first_row];
                 d2 = a.first_d2[first_row];
                 executed = m == 0;
+            } else if (warm >= 0 && !cap) {
+                T P[9], bb[3];
+                scene_prim<T, D>(a.s, sv, warm, P);
+                d2 = prim_closest<T, D>(P, x, bb);
+                qc.prims++;
+                leaf = warm;
+                sexact = false;
             } else {
                 leaf = closest_leaf<T, D>(a.s, sv, root, x, warm, d2, qc, stack);
             }
@@ -620,73 +655,19 @@ __global__ void __launch_bounds__(kBlock) wost3_kernel(WalkArgs<T> a, RefScene3<
                 c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;
                 continue;
             }
-            const T d = sqrt(d2);
-            const bool cap = (int)(k + 1) >= a.prm.kmax;
-            if (d < eps || cap) {
-                if (cap && !(d < eps)) c_trunc++;
-                T P[9], bary[3];
-                scene_prim<T, D>(a.s, sv, leaf, P);
-                prim_closest<T, D>(P, x, bary);
-                const int32_t orig = a.s.orig[leaf];
-                T V[9];
-                int32_t vid[3];
-                prim_vertices<T, D>(a.s, orig, V, vid);
-                T xbar[3];
-#pragma unroll
-                for (int c = 0; c < D; ++c) {
-                    T v = T(0);
-#pragma unroll
-                    for (int kk = 0; kk < D; ++kk) v += bary[kk] * V[kk * D + c];
-                    xbar[c] = v;
-                }
-                const T g = boundary_value<T, D>(a.s, a.prm, orig, bary, xbar, vid);
-                if (MODE == 1 && phase == 0) {
-                    T n[3] = {T(0), T(0), T(0)};
-                    geo_normal<T, D>(V, n);
-                    // oriented away from the previous position (held in xoff
-                    // until now), or the start point
-                    T dn = T(0);
-#pragma unroll
-                    for (int c = 0; c < D; ++c) dn += n[c] * (xbar[c] - (k > 0 ? xoff[c] : x[c]));
-                    const int flip = dn < T(0) ? 1 : 0;
-                    if (flip) {
-#pragma unroll
-                        for (int c = 0; c < D; ++c) n[c] = -n[c];
-                    }
-                    u_main = acc + tau * g;
-                    tau_main = tau;
-                    term_code = orig * 2 + flip;
-                    term_b1 = bary[1];
-                    term_b2 = bary[2];
-                    term_leaf = leaf;
-#pragma unroll
-                    for (int c = 0; c < D; ++c) xoff[c] = xbar[c] - delta * n[c];
-                    c_term++;
-                    if (a.prim_dep && !a.prim_dep[orig]) {
-                        a.rec_u[wid] = u_main;
-                        a.rec_prim[wid] = term_code;
-                        a.rec_b[(size_t)wid * 2] = term_b1;
-                        a.rec_b[(size_t)wid * 2 + 1] = term_b2;
-                        a.rec_uoff[wid] = g;
-                        if (a.rec_w) a.rec_w[wid] = tau_main;
-                        if (a.rec_steps) a.rec_steps[wid] = wsteps;
-                        wid = -1;
-                        c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;
-                        continue;
-                    }
-                    // the first nested walk on stars starts at the offset point
-                    phase = 1;
-#pragma unroll
-                    for (int c = 0; c < D; ++c) x[c] = xoff[c];
-                    acc = T(0); k = 0; warm = term_leaf; on = -1; tau = T(1);
-                    c_nested++;
-                    c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;
-                    continue;
-                }
-                finished = true;
-                result = acc + tau * g;
+            if (sexact && (sqrt(d2) < eps || cap)) {
+                at_term = true;
+                td2 = d2;
+                tleaf = leaf;
             } else {
-                sil_begin<T>(sq, d2);
+                // seed: the previous closest silhouette edge, if it still is one
+                T sb = d2;
+                int32_t bs = -1;
+                if (swarm >= 0) {
+                    qc.prims++;
+                    if (sil3_edge_nearer<T>(ref, swarm, x, on, nin, sb)) bs = swarm;
+                }
+                sil_begin<T>(sq, sb, bs);
                 spend = true;
                 sd2 = d2;
                 sleaf = leaf;
@@ -709,87 +690,177 @@ __global__ void __launch_bounds__(kBlock) wost3_kernel(WalkArgs<T> a, RefScene3<
         }
         if (spend) {
             spend = false;
-            const T d = sqrt(sd2);
-            const int32_t leaf = sleaf;
-            const bool nested = MODE == 1 && phase > 0;
-            // ---- one step on the star-shaped region ---------------------------
+            swarm = sq.bsil;
             // radius floor of 16 units of rounding of the position (see the 2D
-            // kernel), and the Robin cap 1/mu
+            // kernel); sfl: the silhouette distance with that floor
             const T ulp = sizeof(T) == 4 ? T(1.1920929e-07) : T(2.220446049250313e-16);
             const T rmin = T(16) * ulp * (fabs(x[0]) + fabs(x[1]) + fabs(x[2]));
-            T R = fmin(d, fmax(sqrt(sq.best), rmin));
-            if (ref.mu > T(0)) R = fmin(R, fmax(T(1) / ref.mu, rmin));
-            const uint32_t tag = nested ? (1u | ((uint32_t)(phase - 1) << 8)) : 0u;
-            const u4 r = philox10(u4{k, m, p, tag}, key0, key1);
-            T dir[3];
-            unit_dir<T, D>(r.x, r.y, dir);
-            if (on >= 0) {
-                const T c = dot3d<T>(dir, nin);
-                if (c < T(0)) {
-#pragma unroll
-                    for (int cc = 0; cc < 3; ++cc) dir[cc] -= T(2) * c * nin[cc];
-                }
-            }
-            T t;
-            const T reach = R + T(8) * ulp * (fabs(x[0]) + fabs(x[1]) + fabs(x[2]) + R);
-            int32_t tri = ray3_first<T>(ref, x, dir, reach, on, t, qc, stack);
-            if (tri < 0) t = R;
-            if (a.prm.has_source) {
-                const T rho = cbrt(unif_pos<T>(r.w));
-                if (tri < 0 || rho * R < t) {
-                    T y[3];
-#pragma unroll
-                    for (int c = 0; c < D; ++c) y[c] = x[c] + rho * R * dir[c];
-                    acc += tau * green_ball_t<D, T>(kappa, rho, R) * source_f<T, D>(a.prm, y);
-                }
-            }
-            T zr[3] = {T(0), T(0), T(0)}, Lz = T(0), Gz = T(0);
-            int32_t zleaf = -1;
-            uint32_t wbranch = 0;
-            const T cx = on >= 0 ? T(2) : T(1);
-            if (ref.robin) {
-                zleaf = ref3_boundary_sample<T>(ref, x, R, u4{k, m, p, tag}, key0, key1, Lz, zr, wbranch, qc, stack);
-                if (zleaf >= 0) {
-                    const T dz[3] = {zr[0] - x[0], zr[1] - x[1], zr[2] - x[2]};
-                    const T rz = fmax(sqrt(dot3d<T>(dz, dz)), rmin);
-                    // G(r; R) = (G |B_R|) / |B_R|
-                    Gz = green_ball_t<D, T>(kappa, fmin(rz / R, T(1)), R) /
-                         (T(4.18879020478639098462) * R * R * R);
-                    acc -= tau * cx * Lz * Gz * robin_data3<T>(ref, zr);
-                }
-            }
-            const T q = (ref.mu > T(0) && zleaf >= 0) ? fmin(T(0.5), cx * ref.mu * Lz * Gz) : T(0);
-            const bool to_z = q > T(0) && unif<T>(wbranch) < q;
-            const T wgt = to_z ? -cx * ref.mu * Lz * Gz / q
-                               : (tri >= 0 ? reflect_weight<D, T>(kappa, t, R) : poisson_scale<T, D>(kappa, R)) /
-                                     (T(1) - q);
-            const T keep = fmin(T(1), fabs(wgt));
-            if (a.prm.rr && (!(keep > T(0)) || keep < unif<T>(r.z))) {
-                finished = true;
-                result = acc;
-                if (MODE == 1 && phase == 0) term_code = -1;
+            const T sfl = fmax(sqrt(sq.best), rmin);
+            T d;   // the Dirichlet distance, or a lower bound of it that is >= sfl
+            if (sexact) {
+                d = sqrt(sd2);
             } else {
-                tau *= a.prm.rr ? wgt / keep : wgt;
-                if (MODE == 1 && phase == 0) {
-#pragma unroll
-                    for (int c = 0; c < D; ++c) xoff[c] = x[c];   // previous position
-                }
-                if (to_z) {   // continue on the wall at z
-#pragma unroll
-                    for (int c = 0; c < D; ++c) x[c] = zr[c];
-                    on = zleaf;
+                // primitives nearer than B = max(sfl, eps); the bound is padded
+                // so that finding none proves a distance above B
+                const T B = fmax(sfl, eps);
+                const T B2 = B * B * (sizeof(T) == 4 ? T(1.00001) : T(1.0000000001));
+                T d2b;
+                const int32_t lb = closest_leaf_within<T, D>(a.s, sv, root, x, sleaf, sd2, B2, d2b, qc, stack);
+                if (lb >= 0) {
+                    d = sqrt(d2b);
+                    sleaf = lb;
+                    if (d < eps) {
+                        at_term = true;
+                        td2 = d2b;
+                        tleaf = lb;
+                    }
                 } else {
-#pragma unroll
-                    for (int c = 0; c < D; ++c) x[c] += t * dir[c];
-                    on = tri;
+                    d = B;
                 }
-                if (on >= 0) {   // the domain is on the wall's left normal side
-                    tri_left_normal<T>(ref, on, nin);
-                    keep_on_domain_side3<T>(ref, on, nin, x);
-                }
-                ++k;
-                warm = leaf;
             }
+            if (!at_term) {
+                const bool nested = MODE == 1 && phase > 0;
+                // ---- one step on the star-shaped region ---------------------------
+                T R = fmin(d, sfl);
+                if (ref.mu > T(0)) R = fmin(R, fmax(T(1) / ref.mu, rmin));
+                const uint32_t tag = nested ? (1u | ((uint32_t)(phase - 1) << 8)) : 0u;
+                const u4 r = philox10(u4{k, m, p, tag}, key0, key1);
+                T dir[3];
+                unit_dir<T, D>(r.x, r.y, dir);
+                if (on >= 0) {
+                    const T c = dot3d<T>(dir, nin);
+                    if (c < T(0)) {
+#pragma unroll
+                        for (int cc = 0; cc < 3; ++cc) dir[cc] -= T(2) * c * nin[cc];
+                    }
+                }
+                T t;
+                const T reach = R + T(8) * ulp * (fabs(x[0]) + fabs(x[1]) + fabs(x[2]) + R);
+                int32_t tri = ray3_first<T>(ref, x, dir, reach, on, t, qc, stack);
+                if (tri < 0) t = R;
+                if (a.prm.has_source) {
+                    const T rho = cbrt(unif_pos<T>(r.w));
+                    if (tri < 0 || rho * R < t) {
+                        T y[3];
+#pragma unroll
+                        for (int c = 0; c < D; ++c) y[c] = x[c] + rho * R * dir[c];
+                        acc += tau * green_ball_t<D, T>(kappa, rho, R) * source_f<T, D>(a.prm, y);
+                    }
+                }
+                T zr[3] = {T(0), T(0), T(0)}, Lz = T(0), Gz = T(0);
+                int32_t zleaf = -1;
+                uint32_t wbranch = 0;
+                const T cx = on >= 0 ? T(2) : T(1);
+                if (ref.robin) {
+                    zleaf = ref3_boundary_sample<T>(ref, x, R, u4{k, m, p, tag}, key0, key1, Lz, zr, wbranch, qc, stack);
+                    if (zleaf >= 0) {
+                        const T dz[3] = {zr[0] - x[0], zr[1] - x[1], zr[2] - x[2]};
+                        const T rz = fmax(sqrt(dot3d<T>(dz, dz)), rmin);
+                        // G(r; R) = (G |B_R|) / |B_R|
+                        Gz = green_ball_t<D, T>(kappa, fmin(rz / R, T(1)), R) /
+                             (T(4.18879020478639098462) * R * R * R);
+                        acc -= tau * cx * Lz * Gz * robin_data3<T>(ref, zr);
+                    }
+                }
+                const T q = (ref.mu > T(0) && zleaf >= 0) ? fmin(T(0.5), cx * ref.mu * Lz * Gz) : T(0);
+                const bool to_z = q > T(0) && unif<T>(wbranch) < q;
+                const T wgt = to_z ? -cx * ref.mu * Lz * Gz / q
+                                   : (tri >= 0 ? reflect_weight<D, T>(kappa, t, R) : poisson_scale<T, D>(kappa, R)) /
+                                         (T(1) - q);
+                const T keep = fmin(T(1), fabs(wgt));
+                if (a.prm.rr && (!(keep > T(0)) || keep < unif<T>(r.z))) {
+                    finished = true;
+                    result = acc;
+                    if (MODE == 1 && phase == 0) term_code = -1;
+                } else {
+                    tau *= a.prm.rr ? wgt / keep : wgt;
+                    if (MODE == 1 && phase == 0) {
+#pragma unroll
+                        for (int c = 0; c < D; ++c) xoff[c] = x[c];   // previous position
+                    }
+                    if (to_z) {   // continue on the wall at z
+#pragma unroll
+                        for (int c = 0; c < D; ++c) x[c] = zr[c];
+                        on = zleaf;
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < D; ++c) x[c] += t * dir[c];
+                        on = tri;
+                    }
+                    if (on >= 0) {   // the domain is on the wall's left normal side
+                        tri_left_normal<T>(ref, on, nin);
+                        keep_on_domain_side3<T>(ref, on, nin, x);
+                    }
+                    ++k;
+                    warm = sleaf;
+                }
+            }
+        }
+        if (at_term) {
+            const T d = sqrt(td2);
+            const int32_t leaf = tleaf;
+            if (cap && !(d < eps)) c_trunc++;
+            T P[9], bary[3];
+            scene_prim<T, D>(a.s, sv, leaf, P);
+            prim_closest<T, D>(P, x, bary);
+            const int32_t orig = a.s.orig[leaf];
+            T V[9];
+            int32_t vid[3];
+            prim_vertices<T, D>(a.s, orig, V, vid);
+            T xbar[3];
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                T v = T(0);
+#pragma unroll
+                for (int kk = 0; kk < D; ++kk) v += bary[kk] * V[kk * D + c];
+                xbar[c] = v;
+            }
+            const T g = boundary_value<T, D>(a.s, a.prm, orig, bary, xbar, vid);
+            if (MODE == 1 && phase == 0) {
+                T n[3] = {T(0), T(0), T(0)};
+                geo_normal<T, D>(V, n);
+                // oriented away from the previous position (held in xoff
+                // until now), or the start point
+                T dn = T(0);
+#pragma unroll
+                for (int c = 0; c < D; ++c) dn += n[c] * (xbar[c] - (k > 0 ? xoff[c] : x[c]));
+                const int flip = dn < T(0) ? 1 : 0;
+                if (flip) {
+#pragma unroll
+                    for (int c = 0; c < D; ++c) n[c] = -n[c];
+                }
+                u_main = acc + tau * g;
+                tau_main = tau;
+                term_code = orig * 2 + flip;
+                term_b1 = bary[1];
+                term_b2 = bary[2];
+                term_leaf = leaf;
+#pragma unroll
+                for (int c = 0; c < D; ++c) xoff[c] = xbar[c] - delta * n[c];
+                c_term++;
+                if (a.prim_dep && !a.prim_dep[orig]) {
+                    a.rec_u[wid] = u_main;
+                    a.rec_prim[wid] = term_code;
+                    a.rec_b[(size_t)wid * 2] = term_b1;
+                    a.rec_b[(size_t)wid * 2 + 1] = term_b2;
+                    a.rec_uoff[wid] = g;
+                    if (a.rec_w) a.rec_w[wid] = tau_main;
+                    if (a.rec_steps) a.rec_steps[wid] = wsteps;
+                    wid = -1;
+                    c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;
+                    continue;
+                }
+                // the first nested walk on stars starts at the offset point
+                phase = 1;
+#pragma unroll
+                for (int c = 0; c < D; ++c) x[c] = xoff[c];
+                acc = T(0); k = 0; warm = term_leaf; on = -1; tau = T(1);
+                c_nested++;
+                c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;
+                continue;
+            }
+            finished = true;
+            result = acc + tau * g;
         }
         c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;
         if (!finished) continue;

@@ -274,15 +274,17 @@ struct SilQuery {
     int32_t cur;   // node (>= 0) or leaf reference (< 0) to process next
     int32_t sp;    // entries in the traversal stack
     bool have;     // cur is valid; false once the query is answered
-    T best;        // squared distance of the closest silhouette vertex so far
+    T best;        // squared distance of the closest silhouette so far
+    int32_t bsil;  // the silhouette at that distance (3D: leaf edge), or -1
 };
 
 template <class T>
-__device__ __forceinline__ void sil_begin(SilQuery<T>& q, T best) {
+__device__ __forceinline__ void sil_begin(SilQuery<T>& q, T best, int32_t bsil = -1) {
     q.cur = 0;   // the root pair node
     q.sp = 0;
     q.have = true;
     q.best = best;
+    q.bsil = bsil;
 }
 
 template <class T, class Stack>
