@@ -481,6 +481,7 @@ dwos_status upload_reflecting3(dwos_ctx* c, const double* V, const int32_t* tris
             if (b1 <= b0) continue;
             nrm.clear();
             bool forced = false;
+            double min_sin = 1.0;   // sin of the smallest angle at an edge's first vertex
             for (int32_t lp = b0; lp < b1 && !forced; ++lp) {
                 const Edge& e = edges[eb.order[lp]];
                 // a rim or non-manifold edge, or two triangles wound the same
@@ -491,6 +492,18 @@ dwos_status upload_reflecting3(dwos_ctx* c, const double* V, const int32_t* tris
                 nrm.insert(nrm.end(), n, n + 3);
                 unit_normal(e.f1, n);
                 nrm.insert(nrm.end(), n, n + 3);
+                const double* pa = V + 3 * (size_t)e.a;
+                const double* pb = V + 3 * (size_t)e.b;
+                const double t[3] = {pb[0] - pa[0], pb[1] - pa[1], pb[2] - pa[2]};
+                for (int32_t f : {e.f0, e.f1}) {
+                    const double* pw = V + 3 * (size_t)third(f, e.a, e.b);
+                    const double d[3] = {pw[0] - pa[0], pw[1] - pa[1], pw[2] - pa[2]};
+                    const double cr[3] = {t[1] * d[2] - t[2] * d[1], t[2] * d[0] - t[0] * d[2], t[0] * d[1] - t[1] * d[0]};
+                    const double tt = std::sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+                    const double dd = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                    const double sn = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]) / (tt * dd);
+                    min_sin = std::min(min_sin, std::isfinite(sn) ? sn : 0.0);
+                }
             }
             if (forced || nrm.empty()) continue;
             double ax = 0, ay = 0, az = 0;
@@ -503,7 +516,22 @@ dwos_status upload_reflecting3(dwos_ctx* c, const double* V, const int32_t* tris
                 th = std::max(th, std::acos(std::min(1.0, std::max(-1.0, ax * nrm[k] + ay * nrm[k + 1] + az * nrm[k + 2]))));
             const double s0 = th + margin;
             if (!(s0 < 1.5707963267948966)) continue;
+            // range of a.p over the child's edge vertices, and kappa (an edge
+            // of zero angle leaves the plane test unable to prune: kappa inf)
+            double omin = HUGE_VAL, omax = -HUGE_VAL;
+            for (int32_t lp = b0; lp < b1; ++lp) {
+                const Edge& e = edges[eb.order[lp]];
+                for (int32_t v : {e.a, e.b}) {
+                    const double* pv = V + 3 * (size_t)v;
+                    const double o = ax * pv[0] + ay * pv[1] + az * pv[2];
+                    omin = std::min(omin, o);
+                    omax = std::max(omax, o);
+                }
+            }
+            const double tol = sizeof(T) == 4 ? 1e-4 : 1e-10;
+            const double kappa = min_sin > 0.0 ? 4.0 * tol / min_sin : HUGE_VAL;
             q[0] = T(ax); q[1] = T(ay); q[2] = T(az); q[3] = T(std::sin(s0)); q[4] = T(std::cos(s0));
+            q[5] = T(omin); q[6] = T(omax); q[7] = T(kappa);
         }
     hipStream_t s = c->stream;
     HIP_OK(upload(c->ref_econes, cones.data(), cones.size(), s));

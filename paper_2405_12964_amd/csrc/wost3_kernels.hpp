@@ -49,18 +49,28 @@ constexpr int kTriGeo = 12;
 constexpr int kEdgeGeo = 12;
 
 // Normal cones of the silhouette query, per edge-BVH node and child (8
-// scalars: a unit axis a[3], sin and cos of s0 = theta + margin, 3 pad),
-// theta the largest angle between a and the left normals of the triangles
-// at the child's edges.  Seen from x, an edge of two consistently wound
-// triangles is a silhouette only if their normals' dot products with the
-// view direction differ in sign, so some normal of the cone is then
-// perpendicular to a view direction.  A child whose view cone from x
-// (half-angle beta over the child box's bounding sphere) keeps every such
-// dot product of one sign -- |cos angle(a, c - x)| > sin(s0 + beta) with
-// s0 + beta < pi/2 -- holds none.  The margin covers the edge-on tolerance
-// and rounding; children with a rim, a non-manifold or inconsistently wound
-// edge, or normals spread by pi/2 or more, store sin = 2, cos = -1 (never
-// pruned).
+// scalars: a unit axis a[3], sin and cos of s0 = theta + margin, the range
+// [omin, omax] of a.p over the child's edge vertices p, and kappa), theta
+// the largest angle between a and the left normals of the triangles at the
+// child's edges.  Seen from x, an edge of two consistently wound triangles
+// is a silhouette only if x is in front of one triangle's plane and behind
+// the other's (or sees one edge-on).  Two tests show a child holds none:
+// (view cone) the normals' dot products with the view direction then
+// differ in sign, so some normal of the cone is perpendicular to a view
+// direction; a child whose view cone from x (half-angle beta over the child
+// box's bounding sphere) keeps every such dot product of one sign --
+// |cos angle(a, c - x)| > sin(s0 + beta) with s0 + beta < pi/2 -- holds
+// none.  (planes) For a triangle with unit normal n through edge vertex p,
+// n.(x - p) >= a.x - omax - 2 sin(s0/2) |x - p|, so a.x - omax > (2
+// sin(s0/2) + kappa) dmax (dmax >= |x - p| over the child's box) puts x in
+// front of every such plane by more than kappa |x - p|, and omin - a.x
+// beyond the same bound puts it behind all of them; kappa = 4 tol / sin phi
+// over the child's edges, phi the angle at the edge's first vertex between
+// the edge and a triangle's third vertex, keeps every triangle clear of the
+// edge-on tolerance tol.  The cone margin covers the edge-on tolerance and
+// rounding, the plane test a floor of 32 units of rounding; children with a
+// rim, a non-manifold or inconsistently wound edge, or normals spread by
+// pi/2 or more, store sin = 2, cos = -1 (never pruned).
 constexpr int kEdgeCone = 8;
 
 template <class T>
@@ -194,13 +204,22 @@ __device__ __forceinline__ bool sil3_edge_nearer(const RefScene3<T>& r, int32_t 
 // Can the child with box lo..hi and cone q hold a silhouette edge seen from x?
 template <class T>
 __device__ __forceinline__ bool cone3_may_hold(const T* lo, const T* hi, const T* q, const T* x) {
-    T c[3], r2 = T(0), d2 = T(0);
+    if (!(q[3] <= T(1))) return true;      // never pruned
+    T c[3], r2 = T(0), d2 = T(0), mag = T(0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         c[k] = T(0.5) * (lo[k] + hi[k]) - x[k];
         const T e = T(0.5) * (hi[k] - lo[k]);
         r2 += e * e;
         d2 += c[k] * c[k];
+        mag += fabs(x[k]) + fabs(lo[k]) + fabs(hi[k]);
+    }
+    {   // planes: x in front of (or behind) every triangle plane of the child
+        const T ulp = sizeof(T) == 4 ? T(1.1920929e-07) : T(2.220446049250313e-16);
+        const T ax = q[0] * x[0] + q[1] * x[1] + q[2] * x[2];
+        const T dmax = sqrt(d2) + sqrt(r2);
+        const T marg = (sqrt(fmax(T(0), T(2) - T(2) * q[4])) + q[7]) * dmax + T(32) * ulp * (mag + dmax);
+        if (ax - q[6] > marg || q[5] - ax > marg) return false;
     }
     if (!(d2 > r2)) return true;           // x inside the bounding sphere
     const T inv = T(1) / sqrt(d2);
