@@ -262,7 +262,9 @@ dwos_status dwos_scene_info(dwos_ctx* ctx, int64_t* info);
  *   chunk        walk ids a wavefront takes from the global queue per
  *                refill: a multiple of 64 in 64..65536 (default 128)
  *   stage_nodes  cap on the breadth-first prefix of BVH nodes staged in LDS
- *                by variant 0 (-1: as many as fit; default -1) */
+ *                by variant 0, and on the staged prefix of the edge BVH in
+ *                FP32 walk on stars over 3D reflecting meshes (-1: as many
+ *                as fit; default -1) */
 typedef struct dwos_tuning {
     int32_t variant;
     int32_t park;

@@ -807,12 +807,24 @@ dwos_status launch_wost3(dwos_ctx* c, dwos::WalkArgs<T>& a0) {
     constexpr int block = dwos::kBlock;
     auto kern = dwos::wost3_kernel<T, MODE>;
     size_t lds = 0;
+    dwos::RefScene3<T> ref = make_ref3<T>(c);
     if constexpr (sizeof(T) == 4) {
-        // LDS per block: up to 256 Dirichlet nodes, its primitives up to 16 KB
-        a.s.n_stage_nodes = (int32_t)std::min<int64_t>(c->n_nodes, 256);
+        // LDS per block (40 KB: four 256-thread blocks per CU): up to 64
+        // Dirichlet nodes and its primitives up to 16 KB (the Dirichlet query
+        // mostly runs bounded by the star radius), then as many of the edge
+        // BVH's first nodes with their cones as fit (every silhouette query
+        // descends through them)
+        a.s.n_stage_nodes = (int32_t)std::min<int64_t>(c->n_nodes, 64);
         a.s.stage_prims = c->np * (int64_t)(dwos::prim_scalars(3) * sizeof(T)) <= 16384 ? 1 : 0;
         lds = (size_t)a.s.n_stage_nodes * dwos::node_scalars(3) * sizeof(T) +
               (a.s.stage_prims ? (size_t)c->np * dwos::prim_scalars(3) * sizeof(T) : 0);
+        const size_t per_edge = (size_t)(dwos::node_scalars(3) + 2 * dwos::kEdgeCone) * sizeof(T);
+        const size_t budget = 40 * 1024;
+        lds = (lds + 15) & ~size_t(15);
+        ref.n_estage = lds < budget ? (int32_t)std::min<int64_t>(c->ref_enn, (int64_t)((budget - lds) / per_edge)) : 0;
+        if (c->stage_cap >= 0) ref.n_estage = std::min<int32_t>(ref.n_estage, c->stage_cap);
+        ref.estage_off4 = (int64_t)(lds / 16);
+        lds += (size_t)ref.n_estage * per_edge;
     } else {
         a.s.n_stage_nodes = 0;
         a.s.stage_prims = 0;
@@ -828,7 +840,6 @@ dwos_status launch_wost3(dwos_ctx* c, dwos::WalkArgs<T>& a0) {
     const int64_t need = (a.total + block - 1) / block;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)occ_per_cu * c->cu_count));
     const int32_t* starts = c->start_n > 0 ? c->start_seg.as<int32_t>() : nullptr;
-    const dwos::RefScene3<T> ref = make_ref3<T>(c);
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     HIP_OK(hipStreamIsCapturing(s, &cap));
     if (cap != hipStreamCaptureStatusNone) {

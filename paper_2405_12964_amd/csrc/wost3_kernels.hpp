@@ -85,6 +85,11 @@ struct RefScene3 {
     const int4* einfo;
     const T* econes;          // per edge node: child 0 then child 1, kEdgeCone each
     int64_t ne;
+    // FP32: the edge BVH's first n_estage nodes (breadth-first order) and
+    // their cones in LDS at g_stage + estage_off4 (16-byte words: the nodes,
+    // then the cones); 0: none
+    int32_t n_estage;
+    int64_t estage_off4;
     // Robin condition: h = hq[0] + hq[1..3] . z + z^T A z, A = hq[4..12] row
     // major; robin = 0: zero flux
     int32_t robin;
@@ -230,6 +235,28 @@ __device__ __forceinline__ bool cone3_may_hold(const T* lo, const T* hi, const T
     return !(fabs((q[0] * c[0] + q[1] * c[1] + q[2] * c[2]) * inv) > ss);
 }
 
+// An edge-BVH node and its children's cones, from LDS for the staged prefix.
+template <class T>
+__device__ __forceinline__ void edge_node3(const RefScene3<T>& r, int32_t i, NodeData<T, 3>& nd, T* cq) {
+    if constexpr (sizeof(T) == 4) {
+        if (i < r.n_estage) {
+            const float4* w = g_stage + r.estage_off4;
+            decode_node_f32<3>(w + (int64_t)i * (node_scalars(3) / 4), nd);
+            const float4* c = w + (int64_t)r.n_estage * (node_scalars(3) / 4) + (int64_t)i * (2 * kEdgeCone / 4);
+#pragma unroll
+            for (int k = 0; k < 2 * kEdgeCone / 4; ++k) {
+                const float4 v = c[k];
+                cq[4 * k] = v.x; cq[4 * k + 1] = v.y; cq[4 * k + 2] = v.z; cq[4 * k + 3] = v.w;
+            }
+            return;
+        }
+    }
+    load_node<T, 3>(r.enodes, i, nd);
+    const T* g = r.econes + (size_t)i * (2 * kEdgeCone);
+#pragma unroll
+    for (int k = 0; k < 2 * kEdgeCone; ++k) cq[k] = g[k];
+}
+
 // Closest silhouette edge as a resumable query (one node or leaf per
 // round), as sil_round in 2D; x lies on leaf triangle `on` (domain side
 // nin) or inside (-1).
@@ -238,11 +265,11 @@ __device__ __forceinline__ void sil3_round(const RefScene3<T>& r, const T* x, in
                                            SilQuery<T>& q, QueryCount& qc, Stack& st) {
     if (q.cur >= 0) {
         NodeData<T, 3> nd;
-        load_node<T, 3>(r.enodes, q.cur, nd);
+        T cq[2 * kEdgeCone];
+        edge_node3<T>(r, q.cur, nd, cq);
         qc.nodes++;
         const T d0 = fmax(box_d2<T, 3>(nd.lo0, nd.hi0, x), slab_d2<T, 3>(nd.n0, nd.o0, nd.t0, x));
         const T d1 = fmax(box_d2<T, 3>(nd.lo1, nd.hi1, x), slab_d2<T, 3>(nd.n1, nd.o1, nd.t1, x));
-        const T* cq = r.econes + (size_t)q.cur * (2 * kEdgeCone);
         const bool h0 = !(nd.t0 < T(0)) && d0 < q.best && cone3_may_hold<T>(nd.lo0, nd.hi0, cq, x);
         const bool h1 = !(nd.t1 < T(0)) && d1 < q.best && cone3_may_hold<T>(nd.lo1, nd.hi1, cq + kEdgeCone, x);
         if (h0 && h1) {
@@ -532,6 +559,15 @@ __global__ void __launch_bounds__(kBlock) wost3_kernel(WalkArgs<T> a, RefScene3<
             const int64_t np4 = a.s.n_prims * (prim_scalars(D) / 4);
             const float4* gp = reinterpret_cast<const float4*>(a.s.prims);
             for (int64_t i = threadIdx.x; i < np4; i += blockDim.x) g_stage[nn4 + i] = gp[i];
+        }
+        // ... and the edge BVH's first nodes with their cones
+        if (ref.n_estage > 0) {
+            const int64_t en4 = (int64_t)ref.n_estage * (node_scalars(D) / 4);
+            const int64_t ec4 = (int64_t)ref.n_estage * (2 * kEdgeCone / 4);
+            const float4* ge = reinterpret_cast<const float4*>(ref.enodes);
+            const float4* gc = reinterpret_cast<const float4*>(ref.econes);
+            for (int64_t i = threadIdx.x; i < en4; i += blockDim.x) g_stage[ref.estage_off4 + i] = ge[i];
+            for (int64_t i = threadIdx.x; i < ec4; i += blockDim.x) g_stage[ref.estage_off4 + en4 + i] = gc[i];
         }
         __syncthreads();
         sv.n_lnodes = a.s.n_stage_nodes;

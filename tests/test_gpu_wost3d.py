@@ -183,6 +183,24 @@ def test_walk_for_walk_closed_reflecting_surface(dev, dwos, oracle_mod):
     _wfw(dev, dwos, oracle_mod, sc, X, 8, 18, start=tri)
 
 
+def test_staged_edge_tree_same_walks(dev, dwos):
+    """FP32 walk on stars reads the edge BVH's first nodes and cones from
+    LDS: with the staging switched off (stage_nodes = 0) every walk is the
+    same, value and step count, forward and differential."""
+    sc = scenes.thermal3d_scene(nu_slice=24, nu_wire=3, K=2)
+    X, tri = scenes.points_on_triangles(sc.NV, sc.nsegs, 256, 23)
+    s = dwos.Solver.from_scene(sc, "fp32")
+    s.set_start_segments(tri)
+    out = {}
+    for cap in (-1, 0):
+        s.set_tuning(stage_nodes=cap)
+        out[cap] = [s.walk_records(T(X, dev), 16, 31, mode=mode) for mode in (0, 1)]
+    for r0, r1 in zip(out[-1], out[0]):
+        for key in ("u", "steps"):
+            assert torch.equal(r0[key], r1[key]), key
+    assert int(out[0][0]["steps"].max()) > 10
+
+
 def test_silhouette_cones_match_oracle(dev, dwos, oracle_mod):
     """Closest silhouette edge of the closed slice from points around it
     (off the surface and on it): the cone-pruned query equals the oracle's
