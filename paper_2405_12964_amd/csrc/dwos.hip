@@ -315,6 +315,7 @@ dwos_status upload_reflecting(dwos_ctx* c, const double* V, const int32_t* segs,
         for (int ch = 0; ch < 2; ++ch) {
             T* q = &cones[(ni * 2 + ch) * dwos::kRefCone];
             q[0] = T(0); q[1] = T(0); q[2] = T(2); q[3] = T(-1);   // never pruned
+            q[4] = T(0); q[5] = T(0); q[6] = T(0); q[7] = T(0);
             const int32_t b0 = bvh.nodes[ni].range[ch][0], b1 = bvh.nodes[ni].range[ch][1];
             std::vector<double> nrm;
             bool forced = b1 <= b0;
@@ -348,7 +349,20 @@ dwos_status upload_reflecting(dwos_ctx* c, const double* V, const int32_t* segs,
                 th = std::max(th, std::acos(std::min(1.0, std::max(-1.0, ax * nrm[k] + ay * nrm[k + 1]))));
             const double s0 = th + margin;
             if (!(s0 < 1.5707963267948966)) continue;
+            // range of a.p over the child's segment endpoints, and kappa
+            double omin = HUGE_VAL, omax = -HUGE_VAL;
+            for (int32_t lp = b0; lp < b1; ++lp) {
+                const int32_t o = bvh.order[lp];
+                for (int e = 0; e < 2; ++e) {
+                    const double* pv = V + 2 * (size_t)segs[2 * o + e];
+                    const double ov = ax * pv[0] + ay * pv[1];
+                    omin = std::min(omin, ov);
+                    omax = std::max(omax, ov);
+                }
+            }
+            const double tol = sizeof(T) == 4 ? 1e-4 : 1e-10;
             q[0] = T(ax); q[1] = T(ay); q[2] = T(std::sin(s0)); q[3] = T(std::cos(s0));
+            q[4] = T(omin); q[5] = T(omax); q[6] = T(4.0 * tol); q[7] = T(0);
         }
     hipStream_t s = c->stream;
     HIP_OK(upload(c->ref_cones, cones.data(), cones.size(), s));
@@ -757,7 +771,7 @@ dwos_status launch_wost(dwos_ctx* c, dwos::WalkArgs<T>& a0) {
         ref.n_stage = (int32_t)std::min<int64_t>(c->ref_nn, 128);
         const int64_t w_nodes = dwos::node_scalars(2) / 4;
         ref.stage_off4 = (int64_t)a.s.n_stage_nodes * w_nodes + (a.s.stage_prims ? c->np : 0);
-        lds = (size_t)(ref.stage_off4 + (int64_t)ref.n_stage * (w_nodes + 2)) * 16;
+        lds = (size_t)(ref.stage_off4 + (int64_t)ref.n_stage * (w_nodes + 2 * dwos::kRefCone / 4)) * 16;
     } else {
         a.s.n_stage_nodes = 0;
         a.s.stage_prims = 0;

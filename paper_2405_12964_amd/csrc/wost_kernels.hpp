@@ -37,19 +37,30 @@ namespace dwos {
 // a vertex of more than two segments), 8 the same for b.
 constexpr int kRefGeo = 8;
 
-// Normal cones of the silhouette query, per node and child (4 scalars
-// each): a unit axis a and sin, cos of s0 = theta + margin, theta the
-// largest angle between a and the normals involved in the child's vertex
-// tests (its segments' and, at each vertex it tests, the other segment's,
-// all oriented along the polyline through that vertex).  A vertex is a
-// silhouette only if the view direction v - x is perpendicular to some
-// normal of the cone, so a child whose view cone (from x, half-angle beta
-// over the child box's bounding circle) keeps every such dot product of one
-// sign, i.e. |cos angle(a, c - x)| > sin(s0 + beta) with s0 + beta < pi/2,
-// holds none.  The margin covers the edge-on tolerance of the test and
-// rounding; children that hold an always-silhouette vertex, or whose
-// normals spread by pi/2 or more, store sin = 2, cos = -1 (never pruned).
-constexpr int kRefCone = 4;
+// Normal cones of the silhouette query, per node and child (8 scalars
+// each): a unit axis a, sin and cos of s0 = theta + margin, the range
+// [omin, omax] of a.p over the child's segment endpoints p, kappa and a pad;
+// theta the largest angle between a and the normals involved in the child's
+// vertex tests (its segments' and, at each vertex it tests, the other
+// segment's, all oriented along the polyline through that vertex).  A
+// vertex is a silhouette only if x is in front of one of its segments'
+// lines and behind the other's (or sees one edge-on).  Two tests show a
+// child holds none: (view cone) the view direction v - x is then
+// perpendicular to some normal of the cone, so a child whose view cone
+// (from x, half-angle beta over the child box's bounding circle) keeps every
+// such dot product of one sign, i.e. |cos angle(a, c - x)| > sin(s0 + beta)
+// with s0 + beta < pi/2, holds none; (lines) for a segment with unit normal
+// n through the tested vertex p, n.(x - p) >= a.x - omax - 2 sin(s0/2)
+// |x - p|, so a.x - omax > (2 sin(s0/2) + kappa) dmax (dmax >= |x - p| over
+// the child's box) puts x in front of every such line by more than kappa
+// |x - p|, and omin - a.x beyond the same bound behind all of them; kappa =
+// 4 tol keeps every segment clear of the edge-on tolerance tol (seen
+// edge-on means a distance from the line below tol |x - p|).  The cone
+// margin covers the edge-on tolerance and rounding, the line test a floor
+// of 32 units of rounding; children that hold an always-silhouette vertex,
+// or whose normals spread by pi/2 or more, store sin = 2, cos = -1 (never
+// pruned).
+constexpr int kRefCone = 8;
 
 template <class T>
 struct RefScene {
@@ -197,10 +208,13 @@ template <class T>
 __device__ __forceinline__ void ref_cones(const RefScene<T>& r, int32_t i, T* q) {
     if constexpr (sizeof(T) == 4) {
         if (i < r.n_stage) {
-            const float4* w = g_stage + r.stage_off4 + (int64_t)r.n_stage * (node_scalars(2) / 4) + (int64_t)i * 2;
-            const float4 a = w[0], b = w[1];
-            q[0] = a.x; q[1] = a.y; q[2] = a.z; q[3] = a.w;
-            q[4] = b.x; q[5] = b.y; q[6] = b.z; q[7] = b.w;
+            const float4* w = g_stage + r.stage_off4 + (int64_t)r.n_stage * (node_scalars(2) / 4) +
+                              (int64_t)i * (2 * kRefCone / 4);
+#pragma unroll
+            for (int k = 0; k < 2 * kRefCone / 4; ++k) {
+                const float4 v = w[k];
+                q[4 * k] = v.x; q[4 * k + 1] = v.y; q[4 * k + 2] = v.z; q[4 * k + 3] = v.w;
+            }
             return;
         }
     }
@@ -212,9 +226,18 @@ __device__ __forceinline__ void ref_cones(const RefScene<T>& r, int32_t i, T* q)
 // Can the child with box lo..hi and cone q hold a silhouette seen from x?
 template <class T>
 __device__ __forceinline__ bool cone_may_hold(const T* lo, const T* hi, const T* q, const T* x) {
+    if (!(q[2] <= T(1))) return true;     // never pruned
     const T cx = T(0.5) * (lo[0] + hi[0]) - x[0], cy = T(0.5) * (lo[1] + hi[1]) - x[1];
     const T ex = T(0.5) * (hi[0] - lo[0]), ey = T(0.5) * (hi[1] - lo[1]);
     const T d2 = cx * cx + cy * cy, r2 = ex * ex + ey * ey;
+    {   // lines: x in front of (or behind) every segment line of the child
+        const T ulp = sizeof(T) == 4 ? T(1.1920929e-07) : T(2.220446049250313e-16);
+        const T ax = q[0] * x[0] + q[1] * x[1];
+        const T dmax = sqrt(d2) + sqrt(r2);
+        const T mag = fabs(x[0]) + fabs(x[1]) + fabs(lo[0]) + fabs(lo[1]) + fabs(hi[0]) + fabs(hi[1]);
+        const T marg = (sqrt(fmax(T(0), T(2) - T(2) * q[3])) + q[6]) * dmax + T(32) * ulp * (mag + dmax);
+        if (ax - q[5] > marg || q[4] - ax > marg) return false;
+    }
     if (!(d2 > r2)) return true;          // x inside the bounding circle
     const T inv = T(1) / sqrt(d2);
     const T sb = sqrt(r2) * inv, cb = sqrt(T(1) - sb * sb);
@@ -544,7 +567,7 @@ __global__ void __launch_bounds__(kBlock) wost_kernel(WalkArgs<T> a, RefScene<T>
         const float4* rn = reinterpret_cast<const float4*>(ref.nodes);
         for (int64_t i = threadIdx.x; i < rn4; i += blockDim.x) g_stage[ref.stage_off4 + i] = rn[i];
         const float4* rc = reinterpret_cast<const float4*>(ref.cones);
-        for (int64_t i = threadIdx.x; i < 2 * (int64_t)ref.n_stage; i += blockDim.x)
+        for (int64_t i = threadIdx.x; i < (2 * kRefCone / 4) * (int64_t)ref.n_stage; i += blockDim.x)
             g_stage[ref.stage_off4 + rn4 + i] = rc[i];
         __syncthreads();
         sv.n_lnodes = a.s.n_stage_nodes;
