@@ -1128,7 +1128,8 @@ def run_c3(args):
     steps_total = tot0["steps"] + tot1["steps"]
     kind, ms, n, tot = (1, ms1, n1, tot1) if ms1 >= ms0 else (0, ms0, n0, tot0)
     avg_s = ms / max(1, n) / 1e3
-    kname = f"walk_kernel<float,3,{kind},true>"
+    staged = model.solver.get_tuning()["variant"] == 0
+    kname = f"walk_kernel<float,3,{kind},{'true' if staged else 'false'}>"
     bytes_launch = (tot["nodes"] * BYTES_NODE_3D + tot["prims"] * BYTES_PRIM_3D) / max(1, n)
     ops_launch = (tot["nodes"] * OPS_NODE_3D + tot["prims"] * OPS_PRIM_3D + tot["steps"] * OPS_STEP_3D) / max(1, n)
     achieved = bytes_launch / avg_s

@@ -251,8 +251,10 @@ dwos_status dwos_scene_info(dwos_ctx* ctx, int64_t* info);
  * execution is valid.
  *   variant      0: one 1024-thread block per CU with the top BVH levels
  *                (and, if they fit, all primitives) staged in LDS;
- *                1: 256-thread blocks, several per CU, BVH read through the
- *                caches.  FP64 contexts always use the unstaged kernel.
+ *                1: 256-thread blocks, several per CU (six wavefronts per
+ *                SIMD in 3D), BVH read through the caches.  Default 1 for
+ *                3D contexts, 0 for 2D.  FP64 contexts always use the
+ *                unstaged kernel.
  *   park         1..64: a wavefront takes its walk step once this many of
  *                its lanes have their closest-point answer; the others
  *                resume their traversal in the next iteration (default 24)

@@ -121,7 +121,7 @@ struct dwos_ctx {
     DevBuf first_leaf, first_d2;   // shared first query of each start point
     DevBuf order_cell, order_perm, order_hist;   // spatial scheduling order of a chunk's points
     const uint64_t* seed_dev = nullptr;   // optional device seed offset
-    int variant = 0;                      // walk-kernel launch shape (FP32)
+    int variant = 0;                      // walk-kernel launch shape (FP32; 3D contexts start at 1)
     // scheduling knobs of the walk kernels (dwos_set_tuning, dwos_autotune)
     int park = dwos::kParkLanes;
     int tail = dwos::kDescendTail;
@@ -1614,6 +1614,7 @@ dwos_status dwos_create(int32_t dim, int32_t precision, void* stream, dwos_ctx**
     if (!c) return fail(DWOS_ENOMEM, "dwos_create: out of host memory");
     c->D = dim;
     c->prec = precision;
+    c->variant = dim == 3 ? 1 : 0;
     c->stream = static_cast<hipStream_t>(stream);
     c->device = dev;
     c->cu_count = prop.multiProcessorCount;

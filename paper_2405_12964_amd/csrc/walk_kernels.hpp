@@ -671,9 +671,19 @@ __device__ __forceinline__ unsigned long long bcast64(unsigned long long v, int 
 //           ball), and D/R (s.n) (u(y) - g(xbar)) estimates du/dn; rec_uoff
 //           is g - delta times their mean, so that (g - rec_uoff)/delta is
 //           that estimate
-// ---------------------------------------------------------------------------
+// The unstaged 3D kernel asks for six wavefronts per SIMD (at most 80
+// registers per lane, a few spilled): its closest-point queries wait on L2
+// and Infinity-Cache gathers, and the extra wavefronts hide that latency
+// (200,000-triangle icosphere: forward launch 117 -> 100 ms, differential
+// 162 -> 133 ms, against 106 / 136 ms at five and 107 / 156 ms at seven
+// wavefronts).  The staged kernel's 1024-thread block and the 2D scenes'
+// LDS-resident trees keep the compiler's choice (four).
+template <int D, bool STAGED>
+struct WalkWaves { static constexpr int v = (!STAGED && D == 3) ? 6 : 4; };
+
 template <class T, int D, int MODE, bool STAGED>
-__global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) walk_kernel(WalkArgs<T> a) {
+__global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) __attribute__((amdgpu_waves_per_eu(WalkWaves<D, STAGED>::v)))
+walk_kernel(WalkArgs<T> a) {
     const int lane = threadIdx.x & 63;
     TravStack<T, kLdsStack && !STAGED> stack;
     if constexpr (kLdsStack && !STAGED) {

@@ -371,7 +371,8 @@ def test_launch_variants_identical_and_autotune(dev, dwos, which):
     Xt = T(X, dev)
     w = torch.ones(len(X), dtype=torch.float64, device=dev)
     default = s.get_tuning()
-    assert default == {"variant": 0, "park": 24, "tail": 8, "chunk": 128, "stage_nodes": -1}
+    assert default == {"variant": 0 if which == "star" else 1, "park": 24, "tail": 8, "chunk": 128,
+                       "stage_nodes": -1}
     settings = [dict(variant=0), dict(variant=1), dict(variant=0, park=1, tail=0, chunk=64),
                 dict(variant=0, park=64, tail=63, chunk=4096, stage_nodes=3),
                 dict(variant=1, park=40, tail=16, chunk=256, stage_nodes=0)]
