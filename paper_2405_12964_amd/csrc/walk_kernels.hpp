@@ -676,13 +676,14 @@ __device__ __forceinline__ unsigned long long bcast64(unsigned long long v, int 
 // and Infinity-Cache gathers, and the extra wavefronts hide that latency
 // (200,000-triangle icosphere: forward launch 117 -> 100 ms, differential
 // 162 -> 133 ms, against 106 / 136 ms at five and 107 / 156 ms at seven
-// wavefronts).  The staged kernel's 1024-thread block and the 2D scenes'
-// LDS-resident trees keep the compiler's choice (four).
-template <int D, bool STAGED>
-struct WalkWaves { static constexpr int v = (!STAGED && D == 3) ? 6 : 4; };
+// wavefronts).  The staged kernel's 1024-thread block, the 2D scenes'
+// LDS-resident trees and the FP64 reference build keep the compiler's
+// choice.
+template <class T, int D, bool STAGED>
+struct WalkWaves { static constexpr int v = (sizeof(T) == 4 && !STAGED && D == 3) ? 6 : 1; };
 
 template <class T, int D, int MODE, bool STAGED>
-__global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) __attribute__((amdgpu_waves_per_eu(WalkWaves<D, STAGED>::v)))
+__global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) __attribute__((amdgpu_waves_per_eu(WalkWaves<T, D, STAGED>::v)))
 walk_kernel(WalkArgs<T> a) {
     const int lane = threadIdx.x & 63;
     TravStack<T, kLdsStack && !STAGED> stack;

@@ -544,8 +544,16 @@ __device__ int32_t ref3_boundary_sample(const RefScene3<T>& r, const T* x, T R, 
 // none): walks of that point start on the triangle with the domain on its
 // left normal.
 // ---------------------------------------------------------------------------
+// FP32: five wavefronts per SIMD for the forward kernel, six for the
+// differential one (at most 96 / 80 registers per lane instead of the
+// compiler's 128 / 150): the queries wait on memory, and on the 3D thermal
+// stand-in (W = 32) the launches take 848 / 907 ms against 937 / 996 ms.
 template <class T, int MODE>
-__global__ void __launch_bounds__(kBlock) wost3_kernel(WalkArgs<T> a, RefScene3<T> ref, const int32_t* start_tri) {
+struct Wost3Waves { static constexpr int v = sizeof(T) == 4 ? (MODE == 1 ? 6 : 5) : 1; };
+
+template <class T, int MODE>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Wost3Waves<T, MODE>::v)))
+wost3_kernel(WalkArgs<T> a, RefScene3<T> ref, const int32_t* start_tri) {
     constexpr int D = 3;
     const int lane = threadIdx.x & 63;
     TravStack<T, false> stack;
