@@ -11,7 +11,7 @@ import bench
 
 
 @pytest.mark.parametrize("workload,kernel", [("c2", "walk_kernel<float,2,1,true>"),
-                                             ("c3", "walk_kernel<float,3,1,true>")])
+                                             ("c3", "walk_kernel<float,3,1,false>")])
 def test_traffic_figure_matches_sources_and_workload(workload, kernel):
     path = bench.TRAFFIC_FILES[workload]
     if not os.path.exists(path):
