@@ -653,9 +653,10 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 // ---------------------------------------------------------------------------
 // wave-level work queue
 // ---------------------------------------------------------------------------
+// v of lane src (wave-uniform src), as a wave-uniform value (scalar registers)
 __device__ __forceinline__ unsigned long long bcast64(unsigned long long v, int src) {
-    const unsigned lo = (unsigned)__shfl((int)(unsigned)(v & 0xffffffffull), src);
-    const unsigned hi = (unsigned)__shfl((int)(unsigned)(v >> 32), src);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v & 0xffffffffull), src);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), src);
     return ((unsigned long long)hi << 32) | lo;
 }
 
@@ -722,7 +723,7 @@ walk_kernel(WalkArgs<T> a) {
     // walk state
     T x[D], xoff[D];
     T acc = T(0), u_main = T(0), usum = T(0);
-    T kappa = T(0), eps = T(1), delta = T(1);
+    T kappa = T(0), eps = T(1);   // the instance's delta is read at the terminal
     uint32_t k = 0, m = 0, p = 0, inst_tag = 0;
     int64_t first_row = 0;
     int32_t root = 0, warm = -1, term_leaf = -1, term_code = -1, phase = 0;
@@ -741,8 +742,15 @@ walk_kernel(WalkArgs<T> a) {
 #pragma unroll
     for (int c = 0; c < D; ++c) ysel[c] = T(0);
     // lane statistics
-    unsigned long long c_walks = 0, c_nested = 0, c_steps = 0, c_term = 0, c_trunc = 0,
-                       c_nodes = 0, c_prims = 0, c_ovf = 0, c_invalid = 0;
+    // (32 bits per lane keeps registers free; the node, primitive and step
+    // counts move to the device totals before they could wrap)
+    // (walks cut at the cap, stack overflows and non-finite positions are
+    // rare: each goes to the device totals when it happens)
+    uint32_t c_walks = 0, c_nested = 0, c_steps = 0, c_term = 0, c_nodes = 0, c_prims = 0;
+    auto count_rare = [&](unsigned long long Counters::*field, unsigned long long v) {
+        atomicAdd(&(a.cnt->*field), v);
+        atomicAdd(&(a.tot->*field), v);
+    };
 #pragma unroll 1
     while (true) {
         // ---- hand new walks to idle lanes ------------------------------------
@@ -790,7 +798,7 @@ walk_kernel(WalkArgs<T> a) {
                     }
                     p = (uint32_t)(pin + in.p_counter);
                     root = in.root;
-                    kappa = in.kappa; eps = in.eps; delta = in.delta;
+                    kappa = in.kappa; eps = in.eps;
                     inst_tag = (uint32_t)ii << 16;
                     const double* xp = a.X + (size_t)(in.point_begin + pin) * D;
                     first_row = in.point_begin + pin - a.x_base;
@@ -835,7 +843,17 @@ walk_kernel(WalkArgs<T> a) {
                 if (sm == 0ull || __popcll(rm) >= a.park) break;
                 query_round<T, D>(a.s, sv, x, searching, q, qc, stack);
             }
-            c_nodes += qc.nodes; c_prims += qc.prims; c_ovf += qc.overflow;
+            c_nodes += qc.nodes; c_prims += qc.prims;
+            if (qc.overflow) count_rare(&Counters::overflow, qc.overflow);
+            if ((c_nodes | c_prims | c_steps) >= 0x80000000u) {   // rare: move to the totals
+                Counters* dst[2] = {a.cnt, a.tot};
+                for (int t = 0; t < 2; ++t) {
+                    atomicAdd(&dst[t]->nodes, (unsigned long long)c_nodes);
+                    atomicAdd(&dst[t]->prims, (unsigned long long)c_prims);
+                    atomicAdd(&dst[t]->steps, (unsigned long long)c_steps);
+                }
+                c_nodes = 0; c_prims = 0; c_steps = 0;
+            }
         }
         if (qpend && q.done) {
             leaf = q.bleaf;
@@ -851,7 +869,7 @@ walk_kernel(WalkArgs<T> a) {
         if (leaf < 0 || !(d2 >= T(0))) {
             // non-finite position (e.g. a NaN query point): end the walk with
             // a NaN result instead of touching primitive -1
-            c_invalid++;
+            count_rare(&Counters::invalid, 1ull);
             const T nanv = T(NAN);
             a.rec_u[wid] = nanv;
             if (MODE >= 1) {
@@ -870,7 +888,7 @@ walk_kernel(WalkArgs<T> a) {
         bool alive = false;        // ... in the shell or at the cap (not by roulette)
         T result = T(0);           // its value
         if (d < eps || cap) {
-            if (cap && !(d < eps)) c_trunc++;
+            if (cap && !(d < eps)) count_rare(&Counters::truncated, 1ull);
             // closest point, barycentrics, boundary value
             T P[9], bary[3];
             scene_prim<T, D>(a.s, sv, leaf, P);
@@ -915,8 +933,11 @@ walk_kernel(WalkArgs<T> a) {
                 term_code = orig * 2 + flip;
                 term_b1 = bary[1]; term_b2 = bary[2];
                 term_leaf = leaf;
+                {
+                    const T delta = a.inst[inst_tag >> 16].delta;
 #pragma unroll
-                for (int c = 0; c < D; ++c) xoff[c] = xbar[c] - delta * n[c];
+                    for (int c = 0; c < D; ++c) xoff[c] = xbar[c] - delta * n[c];
+                }
                 c_term++;
                 if (a.prim_dep && !a.prim_dep[orig]) {
                     a.rec_u[wid] = u_main;
@@ -954,6 +975,11 @@ walk_kernel(WalkArgs<T> a) {
                         continue;
                     }
                 }
+                // the walk's own records now (only the nested mean is left)
+                a.rec_u[wid] = u_main;
+                a.rec_prim[wid] = term_code;
+                a.rec_b[(size_t)wid * (D - 1)] = term_b1;
+                if constexpr (D == 3) a.rec_b[(size_t)wid * 2 + 1] = term_b2;
                 // start the first nested forward walk at the offset point
                 phase = 1;
                 cv_S = T(0); rho_sel = T(0); d_sel = T(0);
@@ -1062,11 +1088,7 @@ walk_kernel(WalkArgs<T> a) {
                 a.cv_alive[q] = alive ? 1 : 0;
             }
             if (phase >= a.prm.K) {
-                a.rec_u[wid] = u_main;
-                a.rec_prim[wid] = term_code;
-                a.rec_b[(size_t)wid * (D - 1)] = term_b1;
-                if constexpr (D == 3) a.rec_b[(size_t)wid * 2 + 1] = term_b2;
-                if constexpr (MODE == 2) a.rec_uoff[wid] = bvc_g - delta * (usum / T(a.prm.K));
+                if constexpr (MODE == 2) a.rec_uoff[wid] = bvc_g - a.inst[inst_tag >> 16].delta * (usum / T(a.prm.K));
                 else a.rec_uoff[wid] = usum / T(a.prm.K);
                 if (a.rec_steps) a.rec_steps[wid] = wsteps;
                 wid = -1;
@@ -1082,28 +1104,22 @@ walk_kernel(WalkArgs<T> a) {
         }
     }
     // ---- statistics: wave sums, then one atomic per counter per wave -------
-    c_walks = wave_sum_u64(c_walks);
-    c_nested = wave_sum_u64(c_nested);
-    c_steps = wave_sum_u64(c_steps);
-    c_term = wave_sum_u64(c_term);
-    c_nodes = wave_sum_u64(c_nodes);
-    c_prims = wave_sum_u64(c_prims);
-    c_trunc = wave_sum_u64(c_trunc);
-    c_ovf = wave_sum_u64(c_ovf);
-    c_invalid = wave_sum_u64(c_invalid);
+    const unsigned long long s_walks = wave_sum_u64(c_walks);
+    const unsigned long long s_nested = wave_sum_u64(c_nested);
+    const unsigned long long s_steps = wave_sum_u64(c_steps);
+    const unsigned long long s_term = wave_sum_u64(c_term);
+    const unsigned long long s_nodes = wave_sum_u64(c_nodes);
+    const unsigned long long s_prims = wave_sum_u64(c_prims);
     if (lane == 0) {
         Counters* dst[2] = {a.cnt, a.tot};
         for (int q = 0; q < 2; ++q) {
             Counters* c = dst[q];
-            atomicAdd(&c->walks, c_walks);
-            atomicAdd(&c->nested, c_nested);
-            atomicAdd(&c->steps, c_steps);
-            atomicAdd(&c->terminal, c_term);
-            atomicAdd(&c->nodes, c_nodes);
-            atomicAdd(&c->prims, c_prims);
-            if (c_trunc) atomicAdd(&c->truncated, c_trunc);
-            if (c_ovf) atomicAdd(&c->overflow, c_ovf);
-            if (c_invalid) atomicAdd(&c->invalid, c_invalid);
+            atomicAdd(&c->walks, s_walks);
+            atomicAdd(&c->nested, s_nested);
+            atomicAdd(&c->steps, s_steps);
+            atomicAdd(&c->terminal, s_term);
+            atomicAdd(&c->nodes, s_nodes);
+            atomicAdd(&c->prims, s_prims);
         }
     }
 }
