@@ -684,7 +684,7 @@ dwos_status ensure_totals(dwos_ctx* c) {
     return DWOS_OK;
 }
 
-template <class T, int D, int MODE, bool staged>
+template <class T, int D, int MODE, bool staged, bool cv>
 dwos_status launch_shape(dwos_ctx* c, dwos::WalkArgs<T>& a, bool timed);
 
 // Launch the persistent walk kernel over `total` walks.  FP32 uses the
@@ -697,20 +697,30 @@ dwos_status launch_walks(dwos_ctx* c, dwos::WalkArgs<T>& a, dwos::Counters* tot 
     hipStream_t s = c->stream;
     a.tot = tot ? tot : c->totals.as<dwos::Counters>() + (MODE ? 1 : 0);
     hipLaunchKernelGGL(dwos::fill_u64_kernel, dim3(1), dim3(64), 0, s, a.queue, (int64_t)1);
+    if constexpr (MODE >= 1) {
+        if (a.cv_run) {   // the build with the control variate's bookkeeping
+            if constexpr (sizeof(T) == 4) {
+                if (c->variant == 1) return launch_shape<T, D, MODE, false, true>(c, a, timed);
+                return launch_shape<T, D, MODE, true, true>(c, a, timed);
+            } else {
+                return launch_shape<T, D, MODE, false, true>(c, a, timed);
+            }
+        }
+    }
     if constexpr (sizeof(T) == 4) {
-        if (c->variant == 1) return launch_shape<T, D, MODE, false>(c, a, timed);
-        return launch_shape<T, D, MODE, true>(c, a, timed);
+        if (c->variant == 1) return launch_shape<T, D, MODE, false, false>(c, a, timed);
+        return launch_shape<T, D, MODE, true, false>(c, a, timed);
     } else {
-        return launch_shape<T, D, MODE, false>(c, a, timed);
+        return launch_shape<T, D, MODE, false, false>(c, a, timed);
     }
 }
 
-template <class T, int D, int MODE, bool staged>
+template <class T, int D, int MODE, bool staged, bool cv>
 dwos_status launch_shape(dwos_ctx* c, dwos::WalkArgs<T>& a, bool timed) {
     hipStream_t s = c->stream;
     constexpr int block = staged ? dwos::kBlockStaged : dwos::kBlock;
     const size_t smem = staged ? stage_bytes<T>(a.s, D) : 0;
-    auto kern = dwos::walk_kernel<T, D, MODE, staged>;
+    auto kern = dwos::walk_kernel<T, D, MODE, staged, cv>;
     // launch attributes and occupancy are computed once per kernel and LDS
     // size (no runtime queries on later, possibly captured, calls)
     static size_t attr_smem = 0;

@@ -683,7 +683,9 @@ __device__ __forceinline__ unsigned long long bcast64(unsigned long long v, int 
 template <class T, int D, bool STAGED>
 struct WalkWaves { static constexpr int v = (sizeof(T) == 4 && !STAGED && D == 3) ? 6 : 1; };
 
-template <class T, int D, int MODE, bool STAGED>
+// CV: the build with the control variate's bookkeeping (MODE >= 1 with
+// a.cv_run set); without it the kernel carries none of that state.
+template <class T, int D, int MODE, bool STAGED, bool CV = false>
 __global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) __attribute__((amdgpu_waves_per_eu(WalkWaves<T, D, STAGED>::v)))
 walk_kernel(WalkArgs<T> a) {
     const int lane = threadIdx.x & 63;
@@ -875,7 +877,7 @@ walk_kernel(WalkArgs<T> a) {
             if (MODE >= 1) {
                 a.rec_prim[wid] = -1;
                 a.rec_uoff[wid] = nanv;
-                if (a.cv_run) a.cv_run[wid] = -1;
+                if (CV && a.cv_run) a.cv_run[wid] = -1;
             }
             if (a.rec_steps) a.rec_steps[wid] = wsteps;
             wid = -1;
@@ -945,12 +947,12 @@ walk_kernel(WalkArgs<T> a) {
                     a.rec_b[(size_t)wid * (D - 1)] = term_b1;
                     if constexpr (D == 3) a.rec_b[(size_t)wid * 2 + 1] = term_b2;
                     a.rec_uoff[wid] = g;
-                    if (a.cv_run) a.cv_run[wid] = -1;
+                    if (CV && a.cv_run) a.cv_run[wid] = -1;
                     if (a.rec_steps) a.rec_steps[wid] = wsteps;
                     wid = -1;
                     continue;
                 }
-                if (a.cv_run) {
+                if (CV && a.cv_run) {
 #pragma unroll
                     for (int c = 0; c < D; ++c) {
                         a.cv_xoff[(size_t)wid * D + c] = xoff[c];
@@ -995,7 +997,7 @@ walk_kernel(WalkArgs<T> a) {
         } else {
             const uint32_t tag = inst_tag | (nested ? (1u | ((uint32_t)(phase - 1) << 8)) : 0u);
             const u4 r = philox10(u4{k, m, p, tag}, key0, key1);
-            if (MODE >= 1 && nested && a.cv_run) {
+            if (MODE >= 1 && CV && nested && a.cv_run) {
                 // weighted reservoir choice of one source step (probability
                 // proportional to its ball's Green's-function mass) with one
                 // uniform point of its ball
@@ -1069,13 +1071,13 @@ walk_kernel(WalkArgs<T> a) {
             a.rec_u[wid] = result;
             a.rec_prim[wid] = -1;
             a.rec_uoff[wid] = T(0);
-            if (a.cv_run) a.cv_run[wid] = -1;
+            if (CV && a.cv_run) a.cv_run[wid] = -1;
             if (a.rec_steps) a.rec_steps[wid] = wsteps;
             wid = -1;
         } else {
             if constexpr (MODE == 2) usum += bvc_w * (result - bvc_g);
             else usum += result;
-            if (a.cv_run) {
+            if (CV && a.cv_run) {
                 const size_t q = (size_t)wid * a.prm.K + (phase - 1);
 #pragma unroll
                 for (int c = 0; c < D; ++c) {
