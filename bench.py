@@ -437,7 +437,7 @@ def run_c4(args):
 
     kind, ms, n, tot = (1, ms1, n1, tot1) if ms1 >= ms0 else (0, ms0, n0, tot0)
     avg_s = ms / max(1, n) / 1e3
-    kname = f"walk_kernel<float,3,{kind},true>" if tuning["variant"] == 0 else f"walk_kernel<float,3,{kind},false>"
+    kname = f"walk_kernel<float,3,{kind},{'true' if tuning['variant'] == 0 else 'false'},false>"
     bytes_launch = (tot["nodes"] * BYTES_NODE_3D + tot["prims"] * BYTES_PRIM_3D) / max(1, n)
     ops_launch = (tot["nodes"] * OPS_NODE_3D + tot["prims"] * OPS_PRIM_3D + tot["steps"] * OPS_STEP_3D) / max(1, n)
     achieved = bytes_launch / avg_s
@@ -1129,7 +1129,7 @@ def run_c3(args):
     kind, ms, n, tot = (1, ms1, n1, tot1) if ms1 >= ms0 else (0, ms0, n0, tot0)
     avg_s = ms / max(1, n) / 1e3
     staged = model.solver.get_tuning()["variant"] == 0
-    kname = f"walk_kernel<float,3,{kind},{'true' if staged else 'false'}>"
+    kname = f"walk_kernel<float,3,{kind},{'true' if staged else 'false'},false>"
     bytes_launch = (tot["nodes"] * BYTES_NODE_3D + tot["prims"] * BYTES_PRIM_3D) / max(1, n)
     ops_launch = (tot["nodes"] * OPS_NODE_3D + tot["prims"] * OPS_PRIM_3D + tot["steps"] * OPS_STEP_3D) / max(1, n)
     achieved = bytes_launch / avg_s
@@ -1390,7 +1390,7 @@ def run_c2(args):
     ops = kernel_ops(tot) / max(1, n)
     achieved = ops / avg_s
     # the default launch shape: the LDS-staged 1024-thread walk kernel
-    kname = f"walk_kernel<float,2,{kind},true>"
+    kname = f"walk_kernel<float,2,{kind},true,false>"
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": measured_traffic(kname, args.nested, "c2"),
             "kernel": kname, "avg_launch_ms": ms / max(1, n),

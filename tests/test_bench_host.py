@@ -10,8 +10,8 @@ import pytest
 import bench
 
 
-@pytest.mark.parametrize("workload,kernel", [("c2", "walk_kernel<float,2,1,true>"),
-                                             ("c3", "walk_kernel<float,3,1,false>")])
+@pytest.mark.parametrize("workload,kernel", [("c2", "walk_kernel<float,2,1,true,false>"),
+                                             ("c3", "walk_kernel<float,3,1,false,false>")])
 def test_traffic_figure_matches_sources_and_workload(workload, kernel):
     path = bench.TRAFFIC_FILES[workload]
     if not os.path.exists(path):
@@ -31,7 +31,7 @@ def test_traffic_figure_matches_sources_and_workload(workload, kernel):
 
 def test_traffic_needs_the_summary(monkeypatch, tmp_path):
     monkeypatch.setitem(bench.TRAFFIC_FILES, "c2", os.path.join(tmp_path, "missing.txt"))
-    assert bench.measured_traffic("walk_kernel<float,2,1,true>", 8, "c2") is None
+    assert bench.measured_traffic("walk_kernel<float,2,1,true,false>", 8, "c2") is None
 
 
 class _FakeGrad:

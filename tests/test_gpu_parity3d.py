@@ -1,5 +1,5 @@
 """FP32 parity of the 3D walk kernel -- the shape-from-diffusion hot path,
-walk_kernel<float, 3, *, true> -- with the FP64 oracle, and the edge paths
+walk_kernel<float, 3, *, *> (either launch shape) -- with the FP64 oracle, and the edge paths
 of the mesh walk kernel in the FP64 walk-for-walk mode.
 
 * Forward mode per point and per parameter (Algorithm 2, eq. wos_deriv) on
