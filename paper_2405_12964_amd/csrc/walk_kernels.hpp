@@ -395,31 +395,37 @@ template <class T> struct TravStack<T, true> {
 // every lane holds a leaf or has finished, then test the held leaves
 // together, so that node and primitive work are not interleaved within one
 // iteration.
-// The traversal stack's kStackRegs most recent entries are kept in
-// registers (rn, rd; rn[0] the newest); a push moves the oldest of them to
-// the stack memory only when all are in use, and a pop reads memory only
-// when none is left.  Depth-first descent alternates pushes and pops, so
-// most entries never reach memory (the stack's order is unchanged).
-#ifndef DWOS_STACK_REGS
-#define DWOS_STACK_REGS 3
+// The traversal stack's R most recent entries are kept in registers (rn,
+// rd; rn[0] the newest); a push moves the oldest of them to the stack
+// memory only when all are in use, and a pop reads memory only when none is
+// left.  Depth-first descent alternates pushes and pops, so most entries
+// never reach memory (the stack's order is unchanged).  R = 8 in 2D: the
+// star's differential launch writes 0.56 GB of stack instead of 6.1 GB at
+// R = 3, for 4% more time; R = 5 in 3D, as fast as 3 on the icosphere (at
+// 8 the 3D kernel spills and slows by 6-8%).
+#ifndef DWOS_STACK_REGS_2D
+#define DWOS_STACK_REGS_2D 8
 #endif
-constexpr int kStackRegs = DWOS_STACK_REGS;
-template <class T>
+#ifndef DWOS_STACK_REGS_3D
+#define DWOS_STACK_REGS_3D 5
+#endif
+template <class T, int D>
 struct Query {
+    static constexpr int R = D == 2 ? DWOS_STACK_REGS_2D : DWOS_STACK_REGS_3D;
     T best;          // squared distance of the best primitive so far
     int32_t bleaf;   // its leaf position, -1 none
     int32_t node;    // internal node to expand next, or -1 (pop)
     int32_t leaf;    // held leaf reference
     int32_t sp;      // entries in stack memory
     int32_t rt;      // register-held entries in use
-    int32_t rn[kStackRegs];   // register-held entries: node reference
-    T rd[kStackRegs];         // ... and squared bound distance
+    int32_t rn[R];   // register-held entries: node reference
+    T rd[R];         // ... and squared bound distance
     bool has_leaf, done;
 };
 
 template <class T, int D>
 __device__ __forceinline__ void query_test_prim(const Scene<T>& s, const StageView& sv, const T* x,
-                                                int32_t i, Query<T>& q, QueryCount& qc) {
+                                                int32_t i, Query<T, D>& q, QueryCount& qc) {
     T P[9], bb[3];
     scene_prim<T, D>(s, sv, i, P);
     const T d2 = prim_closest<T, D>(P, x, bb);
@@ -434,7 +440,7 @@ __device__ __forceinline__ void query_test_prim(const Scene<T>& s, const StageVi
 
 template <class T, int D>
 __device__ __forceinline__ void query_begin(const Scene<T>& s, const StageView& sv, int32_t root,
-                                            const T* x, int32_t warm, Query<T>& q) {
+                                            const T* x, int32_t warm, Query<T, D>& q) {
     q.best = T(INFINITY);
     q.bleaf = -1;
     if (warm >= 0) {
@@ -469,7 +475,8 @@ __device__ __forceinline__ void query_begin(const Scene<T>& s, const StageView& 
 constexpr int kDescendTail = DWOS_DESCEND_TAIL;
 template <class T, int D, class Stack>
 __device__ __forceinline__ void query_round(const Scene<T>& s, const StageView& sv, const T* x, bool active,
-                                            Query<T>& q, QueryCount& qc, Stack& st) {
+                                            Query<T, D>& q, QueryCount& qc, Stack& st) {
+    using Q = Query<T, D>;
     constexpr T slack = Slack<T>::v;
     // phase 1: expand nodes until this lane holds a leaf or is finished
 #pragma unroll 1
@@ -490,7 +497,7 @@ __device__ __forceinline__ void query_round(const Scene<T>& s, const StageView& 
                 cur = q.rn[0];
                 dd = q.rd[0];
 #pragma unroll
-                for (int i = 0; i + 1 < kStackRegs; ++i) { q.rn[i] = q.rn[i + 1]; q.rd[i] = q.rd[i + 1]; }
+                for (int i = 0; i + 1 < Q::R; ++i) { q.rn[i] = q.rn[i + 1]; q.rd[i] = q.rd[i + 1]; }
                 --q.rt;
             } else {
                 if (q.sp == 0) { q.done = true; continue; }
@@ -512,15 +519,15 @@ __device__ __forceinline__ void query_round(const Scene<T>& s, const StageView& 
         int32_t next = -1;
         if (h0 && h1) {
             if (q.sp + q.rt < kStackSize) {
-                if (q.rt == kStackRegs) {
-                    st.put(q.sp, q.rn[kStackRegs - 1], q.rd[kStackRegs - 1]);
+                if (q.rt == Q::R) {
+                    st.put(q.sp, q.rn[Q::R - 1], q.rd[Q::R - 1]);
                     ++q.sp;
                 }
 #pragma unroll
-                for (int i = kStackRegs - 1; i > 0; --i) { q.rn[i] = q.rn[i - 1]; q.rd[i] = q.rd[i - 1]; }
+                for (int i = Q::R - 1; i > 0; --i) { q.rn[i] = q.rn[i - 1]; q.rd[i] = q.rd[i - 1]; }
                 q.rn[0] = near0 ? nd.c1 : nd.c0;
                 q.rd[0] = near0 ? d1 : d0;
-                q.rt = q.rt < kStackRegs ? q.rt + 1 : kStackRegs;
+                q.rt = q.rt < Q::R ? q.rt + 1 : Q::R;
             } else {
                 qc.overflow++;
             }
@@ -548,7 +555,7 @@ template <class T, int D, class Stack>
 __device__ __forceinline__ int32_t closest_leaf(const Scene<T>& s, const StageView& sv, int32_t root,
                                                 const T* x, int32_t warm, T& best, QueryCount& qc,
                                                 Stack& st) {
-    Query<T> q;
+    Query<T, D> q;
     query_begin<T, D>(s, sv, root, x, warm, q);
 #pragma unroll 1
     while (!q.done) query_round<T, D>(s, sv, x, true, q, qc, st);
@@ -564,7 +571,7 @@ template <class T, int D, class Stack>
 __device__ __forceinline__ int32_t closest_leaf_within(const Scene<T>& s, const StageView& sv, int32_t root,
                                                        const T* x, int32_t warm, T warm_d2, T bound2, T& best,
                                                        QueryCount& qc, Stack& st) {
-    Query<T> q;
+    Query<T, D> q;
     query_begin<T, D>(s, sv, root, x, -1, q);
     if (warm >= 0 && warm_d2 < bound2) {
         q.best = warm_d2;
@@ -736,7 +743,7 @@ walk_kernel(WalkArgs<T> a) {
 #pragma unroll
     for (int c = 0; c < D; ++c) bvc_n[c] = T(0);
     // closest-point query in progress (resumable across iterations)
-    Query<T> q;
+    Query<T, D> q;
     bool qpend = false;
     // control-variate trace of the current nested walk
     T cv_S = T(0);
