@@ -295,6 +295,39 @@ __device__ inline T green_mass(T kappa, T R) {
     }
 }
 
+// FP32 2D ball Green's function for b = kappa R <= 2 (returns 2 pi G for
+// a = rho b, given L = -ln rho).  With A = a^2/4, B = b^2/4, c_k = 1/(k!)^2,
+// the series I0 = sum c_k Z^k and F = sum H_k c_k Z^k (H_k the harmonic
+// numbers) of 2 pi G = I0(a) L + (F(a) I0(b) - F(b) I0(a)) / I0(b), and the
+// divided differences P_k = (B^k - A^k) / (B - A) = B P_{k-1} + A^(k-1):
+//   F(a) - F(b)   = -(B - A) sum H_k c_k P_k,
+//   I0(b) - I0(a) =  (B - A) sum c_k P_k,
+// so the second term is (B - A) [F(b)/I0(b) sum c_k P_k - sum H_k c_k P_k],
+// whose summands all have one sign (F(b)/I0(b) < 1 <= H_k for B <= 1):
+// no cancellation as a -> b, where the term vanishes.  Eight terms reach
+// FP32 resolution for B <= 1.
+__device__ __forceinline__ float green2_small_f32(float rho, float b, float L) {
+    const float a = rho * b;
+    const float A = 0.25f * a * a, B = 0.25f * b * b;
+    float ck = 1.0f, Ak = 1.0f, Bk = 1.0f, hk = 0.0f;
+    float i0a = 1.0f, i0b = 1.0f, fb = 0.0f, P = 1.0f, sc = 0.0f, sh = 0.0f;
+#pragma unroll
+    for (int k = 1; k <= 8; ++k) {
+        ck *= 1.0f / float(k * k);
+        hk += 1.0f / float(k);
+        if (k > 1) P = B * P + Ak;   // Ak still holds A^(k-1)
+        Ak *= A;
+        Bk *= B;
+        i0a += ck * Ak;
+        i0b += ck * Bk;
+        fb += hk * ck * Bk;
+        sc += ck * P;
+        sh += hk * ck * P;
+    }
+    const float ba = B * ((1.0f - rho) * (1.0f + rho));
+    return i0a * L + ba * (fb / i0b * sc - sh);
+}
+
 template <int D, class T>
 __device__ inline T green_ball_t(T kappa, T rho, T R) {
     if constexpr (D == 2) {
@@ -302,6 +335,7 @@ __device__ inline T green_ball_t(T kappa, T rho, T R) {
         if (kappa == T(0)) return T(0.5) * R * R * lnR_r;
         const T b = kappa * R, a = rho * b;
         if (b <= T(2)) {
+            if constexpr (sizeof(T) == 4) return T(0.5) * R * R * green2_small_f32(rho, b, lnR_r);
             double i0a, fa, i0b, fb;
             i0_f_small(double(a), i0a, fa);
             i0_f_small(double(b), i0b, fb);
