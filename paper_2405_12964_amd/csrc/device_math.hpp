@@ -254,6 +254,18 @@ __device__ __forceinline__ T poisson_scale(T kappa, T R) {
     if (kappa == T(0)) return T(1);
     const T a = kappa * R;
     if constexpr (D == 2) {
+        if constexpr (sizeof(T) == 4) {
+            if (a <= T(2)) {   // eight terms of the I0 series reach FP32 resolution
+                const float q = 0.25f * a * a;
+                float t = 1.0f, sum = 1.0f;
+#pragma unroll
+                for (int k = 1; k <= 8; ++k) {
+                    t *= q * (1.0f / float(k * k));
+                    sum += t;
+                }
+                return T(1) / sum;
+            }
+        }
         if (a <= T(20)) return T(1) / i0_series<T>(a);
         return exp(-a) / i0_scaled<T>(a);
     } else {
