@@ -257,13 +257,29 @@ __device__ __forceinline__ void edge_node3(const RefScene3<T>& r, int32_t i, Nod
     for (int k = 0; k < 2 * kEdgeCone; ++k) cq[k] = g[k];
 }
 
-// Closest silhouette edge as a resumable query (one node or leaf per
-// round), as sil_round in 2D; x lies on leaf triangle `on` (domain side
-// nin) or inside (-1).
+// Closest silhouette edge as a resumable query, as sil_round in 2D; x lies
+// on leaf triangle `on` (domain side nin) or inside (-1).  A round expands
+// nodes until the lane holds a leaf or is answered, then the lanes holding
+// leaves test them together; with tail > 0 the expansion stops once at most
+// `tail` lanes still descend while some lane holds a leaf (those go on in
+// the next round), as in the closest-point query.  Each lane visits the same
+// nodes and edges in the same order whatever the tail, so the answer and
+// the edge found do not depend on it.
 template <class T, class Stack>
 __device__ __forceinline__ void sil3_round(const RefScene3<T>& r, const T* x, int32_t on, const T* nin,
-                                           SilQuery<T>& q, QueryCount& qc, Stack& st) {
-    if (q.cur >= 0) {
+                                           SilQuery<T>& q, QueryCount& qc, Stack& st, int tail = 0) {
+    // phase 1: expand nodes
+#pragma unroll 1
+    while (true) {
+        const bool go = q.have && q.cur >= 0;
+        if (tail > 0) {
+            const unsigned long long gm = __ballot(go);
+            if (gm == 0ull) break;
+            if (__popcll(gm) <= tail && __ballot(q.have && q.cur < 0) != 0ull) break;
+            if (!go) continue;
+        } else if (!go) {
+            break;
+        }
         NodeData<T, 3> nd;
         T cq[2 * kEdgeCone];
         edge_node3<T>(r, q.cur, nd, cq);
@@ -286,27 +302,18 @@ __device__ __forceinline__ void sil3_round(const RefScene3<T>& r, const T* x, in
         } else if (h1) {
             q.cur = nd.c1;
         } else {
-            q.have = false;
+            sil_pop<T>(q, st);
         }
-    } else {
+    }
+    // phase 2: the lanes holding a leaf test its edges
+    if (q.have && q.cur < 0) {
         const int32_t v = -1 - q.cur;
         const int32_t start = v >> 3, n = (v & 7) + 1;
         for (int32_t i = start; i < start + n; ++i) {
             qc.prims++;
             if (sil3_edge_nearer<T>(r, i, x, on, nin, q.best)) q.bsil = i;
         }
-        q.have = false;
-    }
-    if (!q.have) {
-#pragma unroll 1
-        while (q.sp > 0) {
-            --q.sp;
-            if (st.get_d(q.sp) < q.best) {
-                q.cur = st.get_node(q.sp);
-                q.have = true;
-                break;
-            }
-        }
+        sil_pop<T>(q, st);
     }
 }
 
@@ -744,7 +751,7 @@ wost3_kernel(WalkArgs<T> a, RefScene3<T> ref, const int32_t* start_tri) {
                 const unsigned long long sm = __ballot(trav);
                 const unsigned long long present = __ballot(true);
                 if (sm == 0ull || __popcll(present & ~sm) >= a.park) break;
-                if (trav) sil3_round<T>(ref, x, on, nin, sq, qc, stack);
+                if (trav) sil3_round<T>(ref, x, on, nin, sq, qc, stack, a.s.tail);
             }
         }
         if (spend && sq.have) {

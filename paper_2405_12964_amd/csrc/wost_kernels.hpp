@@ -287,7 +287,7 @@ __device__ __forceinline__ bool sil_test(const T* v, const T* u, const T* w, int
 
 // Closest silhouette vertex as a resumable query: the traversal state of one
 // lane (node to visit next or a held leaf, stack depth, best squared
-// distance so far).  sil_round processes one node or one leaf; a lane keeps
+// distance so far).  sil_round expands nodes, then tests a leaf; a lane keeps
 // its state (and its entries in the traversal stack) across iterations of
 // the walk loop, so a wavefront can take its step once enough lanes are
 // answered (see wost_kernel).  x lies on leaf segment `on` (domain side nin)
@@ -310,10 +310,43 @@ __device__ __forceinline__ void sil_begin(SilQuery<T>& q, T best, int32_t bsil =
     q.bsil = bsil;
 }
 
+// Answer the next entry of the traversal stack still nearer than the best
+// distance, or end the query when none is left.
+template <class T, class Stack>
+__device__ __forceinline__ void sil_pop(SilQuery<T>& q, Stack& st) {
+    q.have = false;
+#pragma unroll 1
+    while (q.sp > 0) {
+        --q.sp;
+        if (st.get_d(q.sp) < q.best) {
+            q.cur = st.get_node(q.sp);
+            q.have = true;
+            break;
+        }
+    }
+}
+
+// One round of the query: expand nodes until the lane holds a leaf or is
+// answered, then the lanes holding leaves test them together; with tail > 0
+// the expansion stops once at most `tail` lanes still descend while some
+// lane holds a leaf (those go on in the next round), as in the closest-point
+// query.  Each lane visits the same nodes and vertices in the same order
+// whatever the tail, so the answer does not depend on it.
 template <class T, class Stack>
 __device__ __forceinline__ void sil_round(const RefScene<T>& r, const T* x, int32_t on, const T* nin,
-                                          SilQuery<T>& q, QueryCount& qc, Stack& st) {
-    if (q.cur >= 0) {
+                                          SilQuery<T>& q, QueryCount& qc, Stack& st, int tail = 0) {
+    // phase 1: expand nodes
+#pragma unroll 1
+    while (true) {
+        const bool go = q.have && q.cur >= 0;
+        if (tail > 0) {
+            const unsigned long long gm = __ballot(go);
+            if (gm == 0ull) break;
+            if (__popcll(gm) <= tail && __ballot(q.have && q.cur < 0) != 0ull) break;
+            if (!go) continue;
+        } else if (!go) {
+            break;
+        }
         NodeData<T, 2> nd;
         ref_node<T>(r, q.cur, nd);
         qc.nodes++;
@@ -337,9 +370,11 @@ __device__ __forceinline__ void sil_round(const RefScene<T>& r, const T* x, int3
         } else if (h1) {
             q.cur = nd.c1;
         } else {
-            q.have = false;
+            sil_pop<T>(q, st);
         }
-    } else {
+    }
+    // phase 2: the lanes holding a leaf test its vertices
+    if (q.have && q.cur < 0) {
         const int32_t v = -1 - q.cur;
         const int32_t start = v >> 3, n = (v & 7) + 1;
         for (int32_t i = start; i < start + n; ++i) {
@@ -363,18 +398,7 @@ __device__ __forceinline__ void sil_round(const RefScene<T>& r, const T* x, int3
                 }
             }
         }
-        q.have = false;
-    }
-    if (!q.have) {
-#pragma unroll 1
-        while (q.sp > 0) {
-            --q.sp;
-            if (st.get_d(q.sp) < q.best) {
-                q.cur = st.get_node(q.sp);
-                q.have = true;
-                break;
-            }
-        }
+        sil_pop<T>(q, st);
     }
 }
 
@@ -782,7 +806,7 @@ wost_kernel(WalkArgs<T> a, RefScene<T> ref, const int32_t* start_seg) {
                 const unsigned long long sm = __ballot(trav);
                 const unsigned long long present = __ballot(true);
                 if (sm == 0ull || __popcll(present & ~sm) >= a.park) break;
-                if (trav) sil_round<T>(ref, x, on, nin, sq, qc, stack);
+                if (trav) sil_round<T>(ref, x, on, nin, sq, qc, stack, a.s.tail);
             }
         }
         if (spend && sq.have) {
