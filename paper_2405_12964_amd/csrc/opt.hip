@@ -14,7 +14,10 @@
 // The solves are Jacobi-preconditioned conjugate gradients on the D
 // coordinate systems at once (block-diagonal M (x) I_D), warm-started from
 // the previous solution, with every scalar kept on the device; the host
-// reads a convergence flag every kCheckEvery iterations.
+// reads a convergence flag every kCheckEvery iterations.  An iteration is
+// three launches (M p with p . q, the update with r . z, the new direction),
+// each block adding the previous launch's per-block partials itself in one
+// fixed order, so no launch waits on a separate reduction.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,7 +39,9 @@ constexpr int kThreads = 256;
 constexpr int kRedBlocks = 512;      // partial sums of a reduction
 constexpr int kCheckEvery = 16;      // CG iterations between convergence reads
 // device scalars
-enum { S_RZ = 0, S_RZ0, S_ALPHA, S_BETA, S_PQ, S_VMAX, S_DONE, S_COUNT };
+// S_RZ, S_RZ1: r . z of the current iteration in alternating slots (iteration
+// k reads slot k & 1 and leaves the next one in the other)
+enum { S_RZ = 0, S_RZ1, S_RZ0, S_PQ, S_VMAX, S_DONE, S_COUNT };
 }  // namespace
 
 struct dwos_opt {
@@ -125,51 +130,104 @@ __global__ void cg_start(const double* red, double* scal, double tol2) {
     }
 }
 
-// alpha = rz / (p . q)
-__global__ void cg_alpha(const double* red, double* scal) {
-    if (scal[S_DONE] != 0.0) return;
-    const double pq = final_sum(red);
+// The sum of red[0..n) for every thread of the block, added in the same
+// order by every block.
+__device__ __forceinline__ double block_total(const double* red, int64_t n) {
+    __shared__ double sh[kThreads / 64];
+    __shared__ double tot;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += red[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        scal[S_PQ] = pq;
-        scal[S_ALPHA] = pq > 0.0 ? scal[S_RZ] / pq : 0.0;
-        if (!(pq > 0.0)) scal[S_DONE] = 1.0;
+        double t = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) t += sh[w];
+        tot = t;
     }
+    __syncthreads();
+    return tot;
 }
 
-// x += alpha p; r -= alpha q; z = r / diag
-__global__ void cg_update(double* x, double* r, double* z, const double* p, const double* q, const double* diag,
-                          int64_t nv, int D, const double* scal) {
-    if (scal[S_DONE] != 0.0) return;
+// The convergence flag as one value for the whole block (block 0 of a launch
+// may set it while other blocks start).
+__device__ __forceinline__ bool block_done(const double* scal) {
+    __shared__ int d;
+    if (threadIdx.x == 0) d = scal[S_DONE] != 0.0 ? 1 : 0;
+    __syncthreads();
+    return d != 0;
+}
+
+// One CG iteration takes three launches over blocks of kThreads rows, each
+// block leaving its partial of the next dot product in red:
+// q = M p with partials of p . q
+__global__ void cg_spmv_dot(const int64_t* rowptr, const int32_t* col, const double* val, const double* p,
+                            double* q, int64_t nv, int D, double* red_pq, const double* scal) {
+    if (block_done(scal)) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nv) return;
-    const double al = scal[S_ALPHA], di = 1.0 / diag[i];
-    for (int c = 0; c < D; ++c) {
-        const int64_t k = i * D + c;
-        x[k] += al * p[k];
-        const double rr = r[k] - al * q[k];
-        r[k] = rr;
-        z[k] = rr * di;
+    double s = 0.0;
+    if (i < nv) {
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            const double a = val[k];
+            const int64_t j = (int64_t)col[k] * D;
+            for (int c = 0; c < D; ++c) acc[c] += a * p[j + c];
+        }
+        for (int c = 0; c < D; ++c) {
+            q[i * D + c] = acc[c];
+            s += p[i * D + c] * acc[c];
+        }
     }
+    s = block_sum(s);
+    if (threadIdx.x == 0) red_pq[blockIdx.x] = s;
 }
 
-// beta = rz_new / rz; converged when rz_new <= tol^2 rz0
-__global__ void cg_beta(const double* red, double* scal, double tol2) {
-    if (scal[S_DONE] != 0.0) return;
-    const double rzn = final_sum(red);
-    if (threadIdx.x == 0) {
-        const double rz = scal[S_RZ];
-        scal[S_BETA] = rz > 0.0 ? rzn / rz : 0.0;
-        scal[S_RZ] = rzn;
+// alpha = rz / (p . q); x += alpha p; r -= alpha q; z = r / diag, with
+// partials of r . z (stops the solve if p . q is not positive)
+__global__ void cg_update_dot(double* x, double* r, double* z, const double* p, const double* q, const double* diag,
+                              int64_t nv, int D, const double* red_pq, int64_t nblk, double* red_rz, double* scal,
+                              int par) {
+    if (block_done(scal)) return;
+    const double pq = block_total(red_pq, nblk);
+    if (!(pq > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_DONE] = 1.0;
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_PQ] = pq;
+    const double al = scal[S_RZ + par] / pq;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (i < nv) {
+        const double di = 1.0 / diag[i];
+        for (int c = 0; c < D; ++c) {
+            const int64_t k = i * D + c;
+            x[k] += al * p[k];
+            const double rr = r[k] - al * q[k];
+            r[k] = rr;
+            const double zz = rr * di;
+            z[k] = zz;
+            s += rr * zz;
+        }
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) red_rz[blockIdx.x] = s;
+}
+
+// beta = rz_new / rz; p = z + beta p; converged when rz_new <= tol^2 rz0
+__global__ void cg_direction_beta(double* p, const double* z, int64_t nv, int D, const double* red_rz, int64_t nblk,
+                                  double* scal, int par, double tol2) {
+    if (block_done(scal)) return;
+    const double rzn = block_total(red_rz, nblk);
+    const double rz = scal[S_RZ + par];
+    const double beta = rz > 0.0 ? rzn / rz : 0.0;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        scal[S_RZ + (par ^ 1)] = rzn;
         if (rzn <= tol2 * scal[S_RZ0]) scal[S_DONE] = 1.0;
     }
-}
-
-// p = z + beta p
-__global__ void cg_direction(double* p, const double* z, int64_t n, const double* scal) {
-    if (scal[S_DONE] != 0.0) return;
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    p[k] = z[k] + scal[S_BETA] * p[k];
+    if (i >= nv) return;
+    for (int c = 0; c < D; ++c) p[i * D + c] = z[i * D + c] + beta * p[i * D + c];
 }
 
 // moments of the vector Adam step; partial maxima of v_hat over movable vertices
@@ -243,6 +301,9 @@ dwos_status cg_solve(dwos_opt* o, const double* b, double* x, int32_t max_iters,
     const int64_t nv = o->nv, n = nv * o->D;
     const int D = o->D;
     double* red = o->red.as<double>();
+    const int64_t nblk = blocks_for(nv, kThreads);
+    double* red_pq = red + kRedBlocks;   // per-block partials of the iteration's dot products
+    double* red_rz = red_pq + nblk;
     double* sc = o->scal.as<double>();
     const int64_t* rp = o->rowptr.as<int64_t>();
     const int32_t* cl = o->col.as<int32_t>();
@@ -263,14 +324,12 @@ dwos_status cg_solve(dwos_opt* o, const double* b, double* x, int32_t max_iters,
             HIP_OK(hipStreamSynchronize(s));
             if (done != 0.0) break;
         }
-        hipLaunchKernelGGL(opt_k::spmv, dim3(blocks_for(nv, kThreads)), dim3(kThreads), 0, s, rp, cl, va, p, q, nv, D);
-        hipLaunchKernelGGL(opt_k::dot_partial, dim3(kRedBlocks), dim3(kThreads), 0, s, p, q, n, red, sc);
-        hipLaunchKernelGGL(opt_k::cg_alpha, dim3(1), dim3(kThreads), 0, s, red, sc);
-        hipLaunchKernelGGL(opt_k::cg_update, dim3(blocks_for(nv, kThreads)), dim3(kThreads), 0, s, x, r, z, p, q, dg,
-                           nv, D, sc);
-        hipLaunchKernelGGL(opt_k::dot_partial, dim3(kRedBlocks), dim3(kThreads), 0, s, r, z, n, red, sc);
-        hipLaunchKernelGGL(opt_k::cg_beta, dim3(1), dim3(kThreads), 0, s, red, sc, tol2);
-        hipLaunchKernelGGL(opt_k::cg_direction, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, p, z, n, sc);
+        const int par = it & 1;
+        hipLaunchKernelGGL(opt_k::cg_spmv_dot, dim3(nblk), dim3(kThreads), 0, s, rp, cl, va, p, q, nv, D, red_pq, sc);
+        hipLaunchKernelGGL(opt_k::cg_update_dot, dim3(nblk), dim3(kThreads), 0, s, x, r, z, p, q, dg, nv, D, red_pq,
+                           nblk, red_rz, sc, par);
+        hipLaunchKernelGGL(opt_k::cg_direction_beta, dim3(nblk), dim3(kThreads), 0, s, p, z, nv, D, red_rz, nblk, sc,
+                           par, tol2);
     }
     HIP_OK(hipGetLastError());
     if (iters) *iters = it;
@@ -343,7 +402,7 @@ dwos_status dwos_opt_create(int32_t dim, int64_t nv, const int32_t* prims, int64
         const size_t vb = (size_t)nv * dim * sizeof(double);
         for (DevBuf* b : {&o->u, &o->m, &o->gu, &o->r, &o->z, &o->p, &o->q}) HIP_OK(b->reserve(vb));
         HIP_OK(o->v.reserve((size_t)nv * sizeof(double)));
-        HIP_OK(o->red.reserve(kRedBlocks * sizeof(double)));
+        HIP_OK(o->red.reserve((kRedBlocks + 2 * blocks_for(nv, kThreads)) * sizeof(double)));
         HIP_OK(o->scal.reserve(S_COUNT * sizeof(double)));
         return DWOS_OK;
     };
