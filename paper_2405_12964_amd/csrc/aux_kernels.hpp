@@ -437,10 +437,14 @@ __global__ void order_scatter_kernel(const int32_t* cell, int64_t P, uint32_t* c
 }
 
 // row r of X is global point x_base + r, which lies in the instance whose
-// point range contains it
+// point range contains it.  warm_in (or null): per row a primitive (leaf
+// position) to start the query from when it is one of the scene's (it may
+// be leaf_out itself); only a single-instance scene, whose tree holds every
+// primitive, may pass it.
 template <class T, int D>
 __global__ void first_query_kernel(Scene<T> s, const Instance<T>* inst, int32_t n_inst, const double* X,
-                                   int64_t x_base, int64_t P, int32_t* leaf_out, T* d2_out) {
+                                   int64_t x_base, int64_t P, const int32_t* warm_in, int32_t* leaf_out,
+                                   T* d2_out) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= P) return;
     const int64_t g = x_base + r;
@@ -456,7 +460,12 @@ __global__ void first_query_kernel(Scene<T> s, const Instance<T>* inst, int32_t 
     T d2;
     QueryCount qc{0, 0, 0};
     TravStack<T, false> stack;
-    leaf_out[r] = closest_leaf<T, D>(s, sv, inst[lo].root, x, -1, d2, qc, stack);
+    int32_t warm = -1;
+    if (warm_in) {
+        const int32_t w = warm_in[r];
+        if (w >= 0 && (int64_t)w < s.n_prims) warm = w;
+    }
+    leaf_out[r] = closest_leaf<T, D>(s, sv, inst[lo].root, x, warm, d2, qc, stack);
     d2_out[r] = d2;
 }
 

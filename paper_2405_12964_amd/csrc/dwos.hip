@@ -119,6 +119,9 @@ struct dwos_ctx {
     DevBuf rec_u, rec_prim, rec_b, rec_uoff, rec_steps, accA, accB, queue, counters, instbuf, export_u;
     DevBuf vtmp;   // V(pi) for dwos_apply_parameters
     DevBuf first_leaf, first_d2;   // shared first query of each start point
+    // first_leaf holds primitives of this context's own (single-instance)
+    // scene, so the next first queries may start from them
+    bool first_warm = false;
     DevBuf order_cell, order_perm, order_hist;   // spatial scheduling order of a chunk's points
     const uint64_t* seed_dev = nullptr;   // optional device seed offset
     int variant = 0;                      // walk-kernel launch shape (FP32; 3D contexts start at 1)
@@ -611,6 +614,7 @@ dwos_status upload_geometry(dwos_ctx* c, const std::vector<double>& V, const std
     std::vector<T> gv(gvert.size());
     for (size_t i = 0; i < gvert.size(); ++i) gv[i] = T(gvert[i]);
     hipStream_t s = c->stream;
+    c->first_warm = false;
     HIP_OK(upload(c->nodes, nodes.data(), nodes.size(), s));
     HIP_OK(upload(c->node_ranges, ranges.data(), ranges.size(), s));
     HIP_OK(upload(c->prims, pr.data(), pr.size(), s));
@@ -1181,12 +1185,19 @@ dwos_status run_op(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
         a.n_inst = 1;
         a.total = walks;
         a.wid_offset = 0;
-        // every walk of a point starts with the same closest-point query
+        // every walk of a point starts with the same closest-point query,
+        // started from the primitive the previous query of that row found
+        // (any primitive of the scene only bounds the search: the answer is
+        // the same; callers solve at the same points again and again)
+        const void* fl_old = c->first_leaf.ptr;
         HIP_OK(c->first_leaf.reserve(Pc * sizeof(int32_t)));
+        if (c->first_leaf.ptr != fl_old) c->first_warm = false;
         HIP_OK(c->first_d2.reserve(Pc * sizeof(T)));
         hipLaunchKernelGGL((dwos::first_query_kernel<T, D>), dim3(blocks_for(Pc, 64)), dim3(64), 0, s, scene,
                            c->instbuf.as<dwos::Instance<T>>(), 1, o.X + p0 * D, p0, Pc,
-                           c->first_leaf.as<int32_t>(), c->first_d2.as<T>());
+                           c->first_warm ? c->first_leaf.as<int32_t>() : nullptr, c->first_leaf.as<int32_t>(),
+                           c->first_d2.as<T>());
+        c->first_warm = true;
         a.first_leaf = c->first_leaf.as<int32_t>();
         a.first_d2 = c->first_d2.as<T>();
         a.x_base = p0;
@@ -1356,7 +1367,7 @@ dwos_status run_solve_noalloc(dwos_ctx* c, const double* X, int64_t P, int32_t W
     auto* leaf = reinterpret_cast<int32_t*>(base + L.leaf);
     auto* d2 = reinterpret_cast<T*>(base + L.d2);
     hipLaunchKernelGGL((dwos::first_query_kernel<T, D>), dim3(blocks_for(P, 64)), dim3(64), 0, s, scene, inst, 1, X,
-                       (int64_t)0, P, leaf, d2);
+                       (int64_t)0, P, nullptr, leaf, d2);
     dwos::WalkArgs<T> a = base_args<T>(c, X, W, seed);
     a.inst = inst;
     a.n_inst = 1;
@@ -2666,9 +2677,10 @@ dwos_status run_batch(dwos_ctx* c, const double* X, const int64_t* P, int32_t W,
     const dwos::Scene<T> scene = make_scene<T>(c);
     HIP_OK(c->first_leaf.reserve(std::max<int64_t>(1, pts) * sizeof(int32_t)));
     HIP_OK(c->first_d2.reserve(std::max<int64_t>(1, pts) * sizeof(T)));
+    c->first_warm = false;   // batch leaves are positions in the instances' trees
     hipLaunchKernelGGL((dwos::first_query_kernel<T, D>), dim3(blocks_for(pts, 64)), dim3(64), 0, s, scene,
-                       c->instbuf.as<dwos::Instance<T>>(), n, X, (int64_t)0, pts, c->first_leaf.as<int32_t>(),
-                       c->first_d2.as<T>());
+                       c->instbuf.as<dwos::Instance<T>>(), n, X, (int64_t)0, pts, nullptr,
+                       c->first_leaf.as<int32_t>(), c->first_d2.as<T>());
     dwos::WalkArgs<T> a = base_args<T>(c, X, W, seed);
     a.inst = c->instbuf.as<dwos::Instance<T>>();
     a.n_inst = n;
@@ -2723,9 +2735,10 @@ dwos_status run_batch_grad(dwos_ctx* c, const double* X, const int64_t* P, const
     if (pts > 0) {
         HIP_OK(c->first_leaf.reserve(pts * sizeof(int32_t)));
         HIP_OK(c->first_d2.reserve(pts * sizeof(T)));
+        c->first_warm = false;   // batch leaves are positions in the instances' trees
         hipLaunchKernelGGL((dwos::first_query_kernel<T, D>), dim3(blocks_for(pts, 64)), dim3(64), 0, s, scene,
-                           c->instbuf.as<dwos::Instance<T>>(), n, X, (int64_t)0, pts, c->first_leaf.as<int32_t>(),
-                           c->first_d2.as<T>());
+                           c->instbuf.as<dwos::Instance<T>>(), n, X, (int64_t)0, pts, nullptr,
+                           c->first_leaf.as<int32_t>(), c->first_d2.as<T>());
         dwos::WalkArgs<T> a = base_args<T>(c, X, W, seed);
         a.inst = c->instbuf.as<dwos::Instance<T>>();
         a.n_inst = n;
