@@ -438,13 +438,14 @@ __global__ void order_scatter_kernel(const int32_t* cell, int64_t P, uint32_t* c
 
 // row r of X is global point x_base + r, which lies in the instance whose
 // point range contains it.  warm_in (or null): per row a primitive (leaf
-// position) to start the query from when it is one of the scene's (it may
-// be leaf_out itself); only a single-instance scene, whose tree holds every
-// primitive, may pass it.
+// position) to start the query from (it may be leaf_out itself), used only
+// when it lies in the row's instance's leaf positions: prange[2 i] ..
+// prange[2 i + 1] for instance i, or (prange null, a single-instance scene
+// whose tree holds every primitive) 0 .. n_prims.
 template <class T, int D>
 __global__ void first_query_kernel(Scene<T> s, const Instance<T>* inst, int32_t n_inst, const double* X,
-                                   int64_t x_base, int64_t P, const int32_t* warm_in, int32_t* leaf_out,
-                                   T* d2_out) {
+                                   int64_t x_base, int64_t P, const int32_t* prange, const int32_t* warm_in,
+                                   int32_t* leaf_out, T* d2_out) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= P) return;
     const int64_t g = x_base + r;
@@ -463,7 +464,9 @@ __global__ void first_query_kernel(Scene<T> s, const Instance<T>* inst, int32_t 
     int32_t warm = -1;
     if (warm_in) {
         const int32_t w = warm_in[r];
-        if (w >= 0 && (int64_t)w < s.n_prims) warm = w;
+        const int64_t b = prange ? (int64_t)prange[2 * lo] : 0;
+        const int64_t e = prange ? (int64_t)prange[2 * lo + 1] : s.n_prims;
+        if ((int64_t)w >= b && (int64_t)w < e) warm = w;
     }
     leaf_out[r] = closest_leaf<T, D>(s, sv, inst[lo].root, x, warm, d2, qc, stack);
     d2_out[r] = d2;

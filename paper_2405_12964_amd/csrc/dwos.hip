@@ -122,6 +122,7 @@ struct dwos_ctx {
     // first_leaf holds primitives of this context's own (single-instance)
     // scene, so the next first queries may start from them
     bool first_warm = false;
+    DevBuf inst_prange;   // batch: per instance its leaf positions [begin, end)
     DevBuf order_cell, order_perm, order_hist;   // spatial scheduling order of a chunk's points
     const uint64_t* seed_dev = nullptr;   // optional device seed offset
     int variant = 0;                      // walk-kernel launch shape (FP32; 3D contexts start at 1)
@@ -1037,6 +1038,20 @@ dwos_status upload_instances(dwos_ctx* c, const dwos::Instance<T>* in, size_t n)
     return DWOS_OK;
 }
 
+// Per batch instance the leaf positions of its primitives, [begin, end), so
+// that a first query may start from the previous call's answer for its row
+// only when that primitive is the row's instance's.
+dwos_status upload_prange(dwos_ctx* c) {
+    const size_t n = c->instances.size();
+    std::vector<int32_t> pr(2 * std::max<size_t>(1, n), 0);
+    for (size_t i = 0; i < n; ++i) {
+        pr[2 * i] = (int32_t)c->instances[i].np_off;
+        pr[2 * i + 1] = (int32_t)(i + 1 < n ? c->instances[i + 1].np_off : (int64_t)c->hostOrder.size());
+    }
+    HIP_OK(upload(c->inst_prange, pr.data(), pr.size(), c->stream));
+    return DWOS_OK;
+}
+
 // single-instance table for points [p0, p0 + P) of a chunk
 template <class T>
 dwos_status set_single_instance(dwos_ctx* c, int64_t p0, int64_t P, int32_t W) {
@@ -1194,7 +1209,7 @@ dwos_status run_op(dwos_ctx* c, Op op, const OpArgs& o, dwos_stats* st) {
         if (c->first_leaf.ptr != fl_old) c->first_warm = false;
         HIP_OK(c->first_d2.reserve(Pc * sizeof(T)));
         hipLaunchKernelGGL((dwos::first_query_kernel<T, D>), dim3(blocks_for(Pc, 64)), dim3(64), 0, s, scene,
-                           c->instbuf.as<dwos::Instance<T>>(), 1, o.X + p0 * D, p0, Pc,
+                           c->instbuf.as<dwos::Instance<T>>(), 1, o.X + p0 * D, p0, Pc, nullptr,
                            c->first_warm ? c->first_leaf.as<int32_t>() : nullptr, c->first_leaf.as<int32_t>(),
                            c->first_d2.as<T>());
         c->first_warm = true;
@@ -1367,7 +1382,7 @@ dwos_status run_solve_noalloc(dwos_ctx* c, const double* X, int64_t P, int32_t W
     auto* leaf = reinterpret_cast<int32_t*>(base + L.leaf);
     auto* d2 = reinterpret_cast<T*>(base + L.d2);
     hipLaunchKernelGGL((dwos::first_query_kernel<T, D>), dim3(blocks_for(P, 64)), dim3(64), 0, s, scene, inst, 1, X,
-                       (int64_t)0, P, nullptr, leaf, d2);
+                       (int64_t)0, P, nullptr, nullptr, leaf, d2);
     dwos::WalkArgs<T> a = base_args<T>(c, X, W, seed);
     a.inst = inst;
     a.n_inst = 1;
@@ -2679,8 +2694,8 @@ dwos_status run_batch(dwos_ctx* c, const double* X, const int64_t* P, int32_t W,
     HIP_OK(c->first_d2.reserve(std::max<int64_t>(1, pts) * sizeof(T)));
     c->first_warm = false;   // batch leaves are positions in the instances' trees
     hipLaunchKernelGGL((dwos::first_query_kernel<T, D>), dim3(blocks_for(pts, 64)), dim3(64), 0, s, scene,
-                       c->instbuf.as<dwos::Instance<T>>(), n, X, (int64_t)0, pts, nullptr,
-                       c->first_leaf.as<int32_t>(), c->first_d2.as<T>());
+                       c->instbuf.as<dwos::Instance<T>>(), n, X, (int64_t)0, pts, c->inst_prange.as<int32_t>(),
+                       c->first_leaf.as<int32_t>(), c->first_leaf.as<int32_t>(), c->first_d2.as<T>());
     dwos::WalkArgs<T> a = base_args<T>(c, X, W, seed);
     a.inst = c->instbuf.as<dwos::Instance<T>>();
     a.n_inst = n;
@@ -2737,8 +2752,9 @@ dwos_status run_batch_grad(dwos_ctx* c, const double* X, const int64_t* P, const
         HIP_OK(c->first_d2.reserve(pts * sizeof(T)));
         c->first_warm = false;   // batch leaves are positions in the instances' trees
         hipLaunchKernelGGL((dwos::first_query_kernel<T, D>), dim3(blocks_for(pts, 64)), dim3(64), 0, s, scene,
-                           c->instbuf.as<dwos::Instance<T>>(), n, X, (int64_t)0, pts, nullptr,
-                           c->first_leaf.as<int32_t>(), c->first_d2.as<T>());
+                           c->instbuf.as<dwos::Instance<T>>(), n, X, (int64_t)0, pts,
+                           c->inst_prange.as<int32_t>(), c->first_leaf.as<int32_t>(), c->first_leaf.as<int32_t>(),
+                           c->first_d2.as<T>());
         dwos::WalkArgs<T> a = base_args<T>(c, X, W, seed);
         a.inst = c->instbuf.as<dwos::Instance<T>>();
         a.n_inst = n;
@@ -2842,6 +2858,8 @@ dwos_status dwos_batch_grad(dwos_ctx* c, const double* X_all, const int64_t* P, 
             ? upload_geometry<float>(c, c->hostV, c->hostP, c->hostL, c->hostG, c->hostNodes, c->hostOrder)
             : upload_geometry<double>(c, c->hostV, c->hostP, c->hostL, c->hostG, c->hostNodes, c->hostOrder);
         if (rc) return rc;
+        rc = upload_prange(c);
+        if (rc) return rc;
         c->batch_dirty = false;
         c->has_boundary = true;
         c->batch_params_dirty = true;
@@ -2900,6 +2918,8 @@ dwos_status dwos_batch_solve(dwos_ctx* c, const double* X_all, const int64_t* P,
         dwos_status rc = c->prec == DWOS_FP32
             ? upload_geometry<float>(c, c->hostV, c->hostP, c->hostL, c->hostG, c->hostNodes, c->hostOrder)
             : upload_geometry<double>(c, c->hostV, c->hostP, c->hostL, c->hostG, c->hostNodes, c->hostOrder);
+        if (rc) return rc;
+        rc = upload_prange(c);
         if (rc) return rc;
         c->batch_dirty = false;
         c->has_boundary = true;
