@@ -551,12 +551,14 @@ __device__ int32_t ref3_boundary_sample(const RefScene3<T>& r, const T* x, T R, 
 // none): walks of that point start on the triangle with the domain on its
 // left normal.
 // ---------------------------------------------------------------------------
-// FP32: five wavefronts per SIMD for the forward kernel, six for the
-// differential one (at most 96 / 80 registers per lane instead of the
-// compiler's 128 / 150): the queries wait on memory, and on the 3D thermal
-// stand-in (W = 32) the launches take 848 / 907 ms against 937 / 996 ms.
+// FP32: four wavefronts per SIMD (at most 128 registers per lane; the
+// compiler took 150 for the differential kernel, three wavefronts).  The
+// LDS staging of about 40 KB per 256-thread block admits four blocks per
+// CU, i.e. four wavefronts per SIMD, so asking for more only spills: on the
+// 3D thermal stand-in (W = 32, three runs each) 791 / 805 ms against 814 /
+// 824 ms at five / six wavefronts (937 / 996 ms at the compiler's choice).
 template <class T, int MODE>
-struct Wost3Waves { static constexpr int v = sizeof(T) == 4 ? (MODE == 1 ? 6 : 5) : 1; };
+struct Wost3Waves { static constexpr int v = sizeof(T) == 4 ? 4 : 1; };
 
 template <class T, int MODE>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Wost3Waves<T, MODE>::v)))
