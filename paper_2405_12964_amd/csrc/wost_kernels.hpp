@@ -570,13 +570,14 @@ __device__ __forceinline__ void keep_on_domain_side(const RefScene<T>& r, int32_
 // none): walks of that point start on the segment with the domain on its
 // left.
 // ---------------------------------------------------------------------------
-// FP32 differential kernel: five wavefronts per SIMD (at most 96 registers
-// per lane instead of the compiler's 130): on the 2D thermal workload
-// (W = 128) the differential launch takes 441 ms against 469 ms; the
-// forward kernel keeps the compiler's choice (four; five was slower, 362
-// against 337 ms).
+// FP32 differential kernel: four wavefronts per SIMD (at most 128 registers
+// per lane instead of the compiler's 130, which gave three).  On the 2D
+// thermal workload (W = 128, three runs each) the differential launch takes
+// 306 ms against 315 ms at five wavefronts (96 registers, more spilling) and
+// 333 ms at six; the forward kernel keeps the compiler's choice (four; five
+// was slower, 362 against 337 ms).
 template <class T, int MODE>
-struct WostWaves { static constexpr int v = (sizeof(T) == 4 && MODE == 1) ? 5 : 1; };
+struct WostWaves { static constexpr int v = (sizeof(T) == 4 && MODE == 1) ? 4 : 1; };
 
 template <class T, int MODE>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WostWaves<T, MODE>::v)))
