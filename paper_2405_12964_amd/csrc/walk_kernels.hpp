@@ -684,16 +684,21 @@ __device__ __forceinline__ unsigned long long bcast64(unsigned long long v, int 
 // and Infinity-Cache gathers, and the extra wavefronts hide that latency
 // (200,000-triangle icosphere: forward launch 117 -> 100 ms, differential
 // 162 -> 133 ms, against 106 / 136 ms at five and 107 / 156 ms at seven
-// wavefronts).  The staged kernel's 1024-thread block, the 2D scenes'
-// LDS-resident trees and the FP64 reference build keep the compiler's
-// choice.
-template <class T, int D, bool STAGED>
-struct WalkWaves { static constexpr int v = (sizeof(T) == 4 && !STAGED && D == 3) ? 6 : 1; };
+// wavefronts).  Since the registers were trimmed, the differential build
+// (MODE 1) is faster at five (at most 96 registers, fewer spills): 120.0 ->
+// 118.5 ms on the icosphere and 88.2 -> 86.9 ms on the 256-instance batch,
+// while the forward build loses 9-10% at five and stays at six.  The staged
+// kernel's 1024-thread block, the 2D scenes' LDS-resident trees and the FP64
+// reference build keep the compiler's choice.
+template <class T, int D, int MODE, bool STAGED>
+struct WalkWaves {
+    static constexpr int v = (sizeof(T) == 4 && !STAGED && D == 3) ? (MODE == 1 ? 5 : 6) : 1;
+};
 
 // CV: the build with the control variate's bookkeeping (MODE >= 1 with
 // a.cv_run set); without it the kernel carries none of that state.
 template <class T, int D, int MODE, bool STAGED, bool CV = false>
-__global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) __attribute__((amdgpu_waves_per_eu(WalkWaves<T, D, STAGED>::v)))
+__global__ void __launch_bounds__(STAGED ? kBlockStaged : kBlock) __attribute__((amdgpu_waves_per_eu(WalkWaves<T, D, MODE, STAGED>::v)))
 walk_kernel(WalkArgs<T> a) {
     const int lane = threadIdx.x & 63;
     TravStack<T, kLdsStack && !STAGED> stack;
