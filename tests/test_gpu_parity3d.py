@@ -196,10 +196,12 @@ def test_fp32_3d_autograd_gradient_against_central_differences(dev, dwos):
     """The autograd gradient of L(pi) = sum_p w_p u(x_p; pi) through
     DWoSFunction on the displaced icosphere (backward = differential walks,
     Algorithm 2 in reverse mode, Sec. 5.3) against central differences of the
-    forward solve along three directions v, with common random numbers: both
+    forward solve along three directions v, with common random numbers (the
+    comparison of Sec. 6.1): both
     sides of a difference reuse the Philox stream, so a walk moves
     continuously with the boundary and the difference keeps little noise.
-    Bias budget: the nested walk of the backward difference (Sec. 4.3) starts
+    Bias budget: the nested walk of the backward difference (Sec. 5.1, eq.
+    dudn_fd_estimate) starts
     delta inside the boundary and stops in the eps-shell about 0.6 eps short
     of it, so the difference quotient sees an offset of about delta - 0.6 eps
     and the differential walks fall short of the eps-shell solution's
