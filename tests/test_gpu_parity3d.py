@@ -11,7 +11,8 @@ of the mesh walk kernel in the FP64 walk-for-walk mode.
 * The ball's shape derivative du/dR against its closed form (Sec. 4):
   (sinh kr / (r sinh kR)) (1 - kR coth kR) for g = 1.
 * The autograd gradient (DWoSFunction's backward) against central
-  differences of the forward solve with common random numbers.
+  differences of the forward solve with common random numbers, and the
+  eps-shell bias of the backward difference growing as eps/delta.
 * Edge paths: the walk-length cap (the kmax-th query is terminal) and a
   query point with a NaN coordinate (its walks end with NaN and are counted
   as invalid, the other points' walks are unchanged).
@@ -242,3 +243,46 @@ def test_fp32_3d_autograd_gradient_against_central_differences(dev, dwos):
     print("autograd", ma, "central differences", mf, "SE", se, "tol", tol)
     assert np.abs(mf).max() > 5 * se.max(), "directional derivatives lost in noise"
     assert np.all(np.abs(ma - mf) <= tol), (ma, mf, tol)
+
+
+def test_fp32_3d_eps_shell_bias_of_the_differential_walks_scales_as_eps_over_delta(dev, dwos):
+    """The autograd gradient's shortfall against central differences (the
+    test above) grows as delta approaches eps, as the eps-shell offset of the
+    backward difference predicts: relative gap about -c eps/delta with c
+    between 0.3 and 1 at delta = 10 eps and at delta = 2.5 eps, and the gap at
+    2.5 eps two to six times that at 10 eps.  The gaps are pooled over three
+    directions (sum of signed gaps over sum of |central difference|)."""
+    eps = 1e-3
+    X = shell_points(32, 51)
+    Xt = T(X, dev)
+    w = T(np.random.default_rng(52).uniform(0.5, 1.5, len(X)), dev)
+    rng = np.random.default_rng(53)
+    V = rng.normal(size=(3, 64))
+    V /= np.linalg.norm(V, axis=1, keepdims=True)
+    h, W, R = 0.05, 65536, 16
+    fd, gaps = None, {}
+    for ratio in (10.0, 2.5):
+        sc = scenes.c3_icosphere(nu=12, n_basis=64, h=0.4, coef_seed=0, eps=eps, delta=ratio * eps)
+        model = dwos.ShapeModel(sc, "fp32")
+        pi0 = np.asarray(sc.pi0, float)
+        if fd is None:   # the forward walks do not depend on delta
+            def L(pi, seed):
+                model.apply(torch.tensor(pi, dtype=torch.float64, device=dev))
+                u, _ = model.solver.solve(Xt, W, seed, var=False)
+                return float((w * u).sum())
+            fd = np.array([[(L(pi0 + h * v, 1000 + r) - L(pi0 - h * v, 1000 + r)) / (2 * h) for v in V]
+                           for r in range(R)])
+        ad = []
+        for r in range(R):
+            pi = torch.tensor(pi0, dtype=torch.float64, device=dev, requires_grad=True)
+            u = dwos.DWoSFunction.apply(pi, Xt, model, 1024, 900 + r, W, 950 + r)
+            (w * u).sum().backward()
+            ad.append(V @ pi.grad.cpu().numpy())
+        ad = np.array(ad)
+        s = np.sign(fd.mean(0))
+        per_rep = (ad - fd) @ s / np.abs(fd.mean(0)).sum()
+        gap, se = per_rep.mean(), per_rep.std(ddof=1) / math.sqrt(R)
+        gaps[ratio] = gap
+        print(f"delta = {ratio:g} eps: pooled relative gap {gap:.4f} (SE {se:.4f})")
+        assert -1.0 / ratio - 4 * se <= gap <= -0.3 / ratio + 4 * se, (ratio, gap, se)
+    assert 2.0 <= gaps[2.5] / gaps[10.0] <= 6.0, gaps
